@@ -1,0 +1,28 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This package only builds workloads: hexahedral meshes stored as face lists,
+face coefficients, liquid-fraction fields and right-hand sides.  It holds
+none of the solver's arithmetic (no masking, assembly, aggregation or Krylov
+step); those live separately in the oracle and in the HIP library.
+"""
+from .mesh import HexMesh, box_mesh, plate_with_ribs_mesh, concat_meshes, face_coeff
+from .fields import (
+    fl_linear_x,
+    fl_planar_front,
+    fl_growing_front,
+    rhs_uniform,
+    batch_samples,
+)
+
+__all__ = [
+    "HexMesh",
+    "box_mesh",
+    "plate_with_ribs_mesh",
+    "concat_meshes",
+    "face_coeff",
+    "fl_linear_x",
+    "fl_planar_front",
+    "fl_growing_front",
+    "rhs_uniform",
+    "batch_samples",
+]

@@ -1,0 +1,59 @@
+"""Seeded liquid-fraction fields, right-hand sides and uncertainty samples.
+
+The liquid fraction f_l in [0, 1] is the solver's masking input: cells with
+f_l == 0 are fully solid (the paper's S tag, section 2.4) and drop out of the
+pressure system; every other cell (liquid or mushy, tag LM) is solved.  The
+fields here are synthetic stand-ins for the temperature-driven f_l of a real
+solidification run.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def fl_linear_x(centres, x0=0.3, width=0.4):
+    """f_l = clamp((x - x0) / width, 0, 1): solid for x <= x0."""
+    return np.clip((centres[:, 0] - x0) / width, 0.0, 1.0)
+
+
+def fl_planar_front(centres, seed=2, width=0.4, centre=(0.5, 0.5, 0.5), s_range=0.2):
+    """Planar front with a seeded normal uniform on the sphere and offset
+    s ~ U(-s_range, s_range): f_l = clamp((n.(x - centre) - s) / width, 0, 1)."""
+    rng = np.random.default_rng(seed)
+    n = rng.normal(size=3)
+    n /= np.linalg.norm(n)
+    s = rng.uniform(-s_range, s_range)
+    return np.clip(((centres - np.asarray(centre)) @ n - s) / width, 0.0, 1.0)
+
+
+def fl_growing_front(centres, t, t_end, s_max=0.6, delta=0.1, axis=0, length=1.0):
+    """Solid layer growing from the cold wall at x_axis = 0 as sqrt(t):
+    s(t) = s_max * length * sqrt(t / t_end); f_l = clamp((x - s) / (delta*length), 0, 1)."""
+    s = s_max * length * np.sqrt(max(t, 0.0) / t_end)
+    return np.clip((centres[:, axis] - s) / (delta * length), 0.0, 1.0)
+
+
+def rhs_uniform(n, seed=1, center_mask=None):
+    """b ~ U(-1, 1) i.i.d. (PCG64 stream ``seed``); if ``center_mask`` is
+    given, the mean over the masked entries is removed from those entries."""
+    rng = np.random.default_rng(seed)
+    b = rng.uniform(-1.0, 1.0, size=n)
+    if center_mask is not None:
+        m = np.asarray(center_mask, dtype=bool)
+        if m.any():
+            b[m] -= b[m].mean()
+    return b
+
+
+def batch_samples(n_samples=256, seed=3, param_seed=4, side_range=(24, 48)):
+    """Uncertainty-quantification samples: cube side m ~ U{side_range}
+    (inclusive), melt temperature ~ N(950, 10) K, mould wall temperature
+    ~ N(600, 20) K, liquidus shift ~ U(-5, 5) K."""
+    rng = np.random.default_rng(seed)
+    sides = rng.integers(side_range[0], side_range[1] + 1, size=n_samples)
+    prng = np.random.default_rng(param_seed)
+    t_melt = prng.normal(950.0, 10.0, size=n_samples)
+    t_wall = prng.normal(600.0, 20.0, size=n_samples)
+    d_liq = prng.uniform(-5.0, 5.0, size=n_samples)
+    return [dict(side=int(sides[s]), t_melt=float(t_melt[s]), t_wall=float(t_wall[s]),
+                 d_liq=float(d_liq[s])) for s in range(n_samples)]
