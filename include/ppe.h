@@ -1,0 +1,180 @@
+/*
+ * ppe.h - masked pressure-correction Poisson solve on unstructured hexahedral
+ * finite-volume meshes, smoothed-aggregation AMG preconditioned conjugate
+ * gradients, on AMD Instinct MI355X (gfx950).
+ *
+ * What is solved (arXiv:1810.08572, Shahane et al., "Finite Volume Simulation
+ * Framework for Die Casting with Uncertainty Quantification"):
+ *   - the pressure Poisson equation of the fractional-step method, Eq. 9,
+ *     discretised with the direct (two-point) term of the face-gradient split
+ *     of Eq. 11; face f between cells o and n contributes c_f (p_n - p_o) to
+ *     the balance of o, with c_f = |S_f| / (rho n.d) supplied by the caller;
+ *   - with the solidification modification of section 2.4.2: cells whose
+ *     liquid fraction is exactly 0 (tag S) are removed, every face with a
+ *     removed owner is blocked (zero flux, i.e. Neumann: its coefficient
+ *     leaves the diagonal too, case 3 and modification step 2), the rows of
+ *     the remaining liquid/mushy cells are re-assembled (step 3);
+ *   - every connected set of remaining cells (a liquid pocket, section 2.5)
+ *     is made non-singular by pinning its lowest-index cell: that cell's row
+ *     and column are zeroed except the diagonal (1 for an isolated cell), and
+ *     its right-hand side entry is replaced by 0;
+ *   - solved to ||b' - A p||_2 <= rtol ||b'||_2 (true residual, FP64) by
+ *     conjugate gradients (the Krylov solver of section 2.5) preconditioned
+ *     by one smoothed-aggregation AMG V-cycle (the multigrid of section 2.5).
+ *
+ * Conventions
+ *   - Every array argument is a DEVICE pointer (HIP device memory of the
+ *     device that was current at ppe_create) owned by the caller.  Inputs are
+ *     read in stream order on the solver's stream and must stay valid until
+ *     the call returns; outputs are complete when the call returns (each call
+ *     synchronises the solver's stream before returning).
+ *   - Indices are int32, cell numbering 0..n_cells-1; values are FP64.
+ *   - A solver is not thread-safe; use one solver per host thread.
+ *   - Every function returns a ppe_status; a negative value means the call
+ *     failed, its outputs are undefined, and ppe_last_error() describes why.
+ */
+#ifndef PPE_H
+#define PPE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ppe_solver ppe_solver; /* opaque: mesh topology, hierarchy, workspace */
+
+typedef enum {
+  PPE_OK = 0,
+  PPE_NOT_CONVERGED = 1,    /* max_iter reached; p holds the last iterate */
+  PPE_ERR_ARG = -1,         /* invalid argument or input data */
+  PPE_ERR_HIP = -2,         /* a HIP runtime call failed */
+  PPE_ERR_OOM = -3,         /* device allocation failed */
+  PPE_ERR_BREAKDOWN = -4,   /* p.Ap <= 0, r.z <= 0 or a non-finite scalar */
+  PPE_ERR_STATE = -5,       /* call out of order (e.g. solve before assemble) */
+  PPE_ERR_INTERNAL = -6     /* a bounded internal table overflowed */
+} ppe_status;
+
+typedef enum { PPE_FP64 = 0, PPE_MIXED = 1 } ppe_precision;
+
+typedef struct {
+  int precision;      /* ppe_precision; PPE_MIXED = FP32 hierarchy + FP64 outer PCG */
+  double rtol;        /* relative residual target, default 1e-10 */
+  int max_iter;       /* PCG iteration cap, default 500 */
+  int cheb_degree;    /* Chebyshev smoother degree per application, default 2 */
+  double cheb_ratio;  /* smoothing interval [rho/ratio, rho], default 30 */
+  int coarse_max;     /* stop coarsening at <= this many rows, default 256 */
+  int max_levels;     /* hierarchy depth cap, default 10 */
+  double theta;       /* strength threshold, default 0.08 */
+  int check_every;    /* PCG iterations between host convergence checks, default 1 */
+  void* stream;       /* hipStream_t used for every launch; NULL = default stream */
+} ppe_options;
+
+typedef struct {
+  int iterations;        /* PCG iterations of the last solve */
+  double rel_residual;   /* true ||b'-Ap||/||b'|| at exit (0 when b' = 0) */
+  double setup_ms;       /* last ppe_assemble wall time */
+  double solve_ms;       /* last ppe_solve wall time */
+  int n_active;          /* cells with f_l > 0 */
+  int n_components;      /* liquid pockets (= pinned cells) */
+  int levels;            /* AMG levels including the finest */
+  double op_complexity;  /* sum of level nnz / finest nnz */
+  double bytes_per_iter; /* algorithmic bytes one PCG iteration moves */
+} ppe_stats;
+
+/* Fill *opt with the defaults listed above. */
+void ppe_default_options(ppe_options* opt);
+
+/* Create a solver on the current HIP device.  opt may be NULL (defaults).
+ * Errors: PPE_ERR_ARG for out-of-range options, PPE_ERR_HIP. */
+ppe_status ppe_create(const ppe_options* opt, ppe_solver** out);
+
+/* Destroy a solver and free its device memory.  NULL is accepted. */
+void ppe_destroy(ppe_solver* s);
+
+/* Mesh topology, section 2.3: face f joins owner[f] and neigh[f]
+ * (neigh[f] = -1: wall face, which carries no flux).  Copies what it needs;
+ * the arrays may be freed after return.
+ * Errors (PPE_ERR_ARG): n_cells <= 0, n_faces < 0, an index out of range,
+ * owner == neigh, two faces joining the same pair of cells. */
+ppe_status ppe_set_mesh(ppe_solver* s, int32_t n_cells, int32_t n_faces,
+                        const int32_t* owner, const int32_t* neigh);
+
+/* Masked assembly and AMG setup (section 2.4.2 and section 2.5).
+ * face_coeff[n_faces]: c_f, finite and > 0 on interior faces (ignored on
+ * walls).  liquid_fraction[n_cells]: finite, in [0,1]; 0 removes the cell.
+ * Errors: PPE_ERR_STATE before ppe_set_mesh; PPE_ERR_ARG on invalid data;
+ * PPE_ERR_OOM; PPE_ERR_INTERNAL if a setup table overflows. */
+ppe_status ppe_assemble(ppe_solver* s, const double* face_coeff,
+                        const double* liquid_fraction);
+
+/* Solve A p = b' (Eq. 9 as modified in section 2.4.2).
+ * rhs[n_cells]: entries of removed cells are ignored, pins are replaced by 0.
+ * p[n_cells]: in: initial guess if use_x0 != 0; out: pressure, exactly 0 on
+ * removed cells and pins.  stats: host pointer, may be NULL.
+ * Returns PPE_OK, PPE_NOT_CONVERGED (p = last iterate, stats filled),
+ * PPE_ERR_STATE before ppe_assemble, PPE_ERR_BREAKDOWN, PPE_ERR_HIP.
+ * An empty active set or b' = 0 returns PPE_OK with p = 0 (or x0 masked)
+ * after 0 iterations. */
+ppe_status ppe_solve(ppe_solver* s, const double* rhs, double* p, int use_x0,
+                     ppe_stats* stats);
+
+/* Statistics of the last assemble/solve. */
+ppe_status ppe_get_stats(const ppe_solver* s, ppe_stats* stats);
+
+const char* ppe_status_string(ppe_status st);
+/* Detail of the last failure of this solver ("" if none).  NULL = global. */
+const char* ppe_last_error(const ppe_solver* s);
+
+/* ---- Inspection: used by the parity tests to compare each setup stage. ----
+ * All sizes are host ints; arrays are device pointers sized by the caller
+ * from ppe_level_info.  PPE_ERR_STATE before assemble, PPE_ERR_ARG for a bad
+ * level or a NULL array. */
+
+/* Level sizes: rows, stored entries of A_l, entries of P_l (0 on the
+ * coarsest level), aggregates (= rows of level l+1), and rho_l. */
+ppe_status ppe_level_info(const ppe_solver* s, int level, int32_t* n_rows,
+                          int64_t* nnz_a, int64_t* nnz_p, int32_t* n_agg,
+                          double* rho);
+
+/* Copy A_l in CSR (sorted columns, diagonal included): row_ptr[n+1],
+ * col[nnz], val[nnz]. */
+ppe_status ppe_copy_level_matrix(const ppe_solver* s, int level, int32_t* row_ptr,
+                                 int32_t* col, double* val);
+
+/* Copy P_l in CSR: row_ptr[n+1], col[nnz_p], val[nnz_p]. */
+ppe_status ppe_copy_prolongator(const ppe_solver* s, int level, int32_t* row_ptr,
+                                int32_t* col, double* val);
+
+/* Copy the aggregate id of every row of level l (-1: not aggregated). */
+ppe_status ppe_copy_aggregates(const ppe_solver* s, int level, int32_t* agg);
+
+/* Masking outputs on the finest level: compact id per cell (-1 removed) and
+ * the component label (its pin's cell index) per cell (-1 removed). */
+ppe_status ppe_copy_mask(const ppe_solver* s, int32_t* compact_id, int32_t* component);
+
+/* y = A_l x on level l (x, y of length n_rows(l)). */
+ppe_status ppe_apply_matrix(ppe_solver* s, int level, const double* x, double* y);
+
+/* z = M r: one V-cycle from level 0 with a zero initial guess (length n_active). */
+ppe_status ppe_apply_vcycle(ppe_solver* s, const double* r, double* z);
+
+/* ---- Measurement of the dominant kernel. ----
+ * While enabled, every launch of the finest-level fused Chebyshev smoothing
+ * kernel (the operator applied most often per PCG iteration) is bracketed by
+ * a pair of HIP events on the solver's stream, and the library adds up the
+ * kernel times and the algorithmic bytes each launch moves (every stored
+ * off-diagonal entry read once as 8-byte value + 4-byte column index, and
+ * 8 bytes per row for each vector the step reads or writes: diagonal,
+ * iterate in and out, right-hand side, search direction in (steps after the
+ * first) and out).  Enabling resets the totals.  PPE_ERR_ARG on NULL. */
+ppe_status ppe_profile_enable(ppe_solver* s, int enable);
+ppe_status ppe_profile_read(const ppe_solver* s, double* kernel_ms, double* bytes,
+                            int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PPE_H */

@@ -1,0 +1,338 @@
+"""Python binding of libppe: the masked pressure-correction Poisson solve
+(smoothed-aggregation AMG-preconditioned conjugate gradients) on MI355X.
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+PyTorch supplies device memory (tensors) and the stream.  The functions
+mirror the C ABI of include/ppe.h one to one (``ppe_create``,
+``ppe_set_mesh``, ``ppe_assemble``, ``ppe_solve``, ...); ``Solver`` wraps
+them with tensor checks.  If the library is not built this module raises on
+first use - there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libppe.so")
+
+PPE_OK = 0
+PPE_NOT_CONVERGED = 1
+PPE_ERR_ARG = -1
+PPE_ERR_HIP = -2
+PPE_ERR_OOM = -3
+PPE_ERR_BREAKDOWN = -4
+PPE_ERR_STATE = -5
+PPE_ERR_INTERNAL = -6
+PPE_FP64 = 0
+PPE_MIXED = 1
+
+
+class ppe_options(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int),
+        ("rtol", ctypes.c_double),
+        ("max_iter", ctypes.c_int),
+        ("cheb_degree", ctypes.c_int),
+        ("cheb_ratio", ctypes.c_double),
+        ("coarse_max", ctypes.c_int),
+        ("max_levels", ctypes.c_int),
+        ("theta", ctypes.c_double),
+        ("check_every", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class ppe_stats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int),
+        ("rel_residual", ctypes.c_double),
+        ("setup_ms", ctypes.c_double),
+        ("solve_ms", ctypes.c_double),
+        ("n_active", ctypes.c_int),
+        ("n_components", ctypes.c_int),
+        ("levels", ctypes.c_int),
+        ("op_complexity", ctypes.c_double),
+        ("bytes_per_iter", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+# symbol -> (restype, argtypes); the exported C ABI
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_SIGS = {
+    "ppe_default_options": (None, [ctypes.POINTER(ppe_options)]),
+    "ppe_create": (ctypes.c_int, [ctypes.POINTER(ppe_options), ctypes.POINTER(_P)]),
+    "ppe_destroy": (None, [_P]),
+    "ppe_set_mesh": (ctypes.c_int, [_P, _I32, _I32, _P, _P]),
+    "ppe_assemble": (ctypes.c_int, [_P, _P, _P]),
+    "ppe_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.POINTER(ppe_stats)]),
+    "ppe_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(ppe_stats)]),
+    "ppe_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "ppe_last_error": (ctypes.c_char_p, [_P]),
+    "ppe_level_info": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(_I32),
+                                      ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_I32),
+                                      ctypes.POINTER(ctypes.c_double)]),
+    "ppe_copy_level_matrix": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P]),
+    "ppe_copy_prolongator": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P]),
+    "ppe_copy_aggregates": (ctypes.c_int, [_P, ctypes.c_int, _P]),
+    "ppe_copy_mask": (ctypes.c_int, [_P, _P, _P]),
+    "ppe_apply_matrix": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
+    "ppe_apply_vcycle": (ctypes.c_int, [_P, _P, _P]),
+    "ppe_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
+    "ppe_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int64)]),
+}
+SYMBOLS = tuple(_SIGS)
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libppe.so (built in-tree by ``build()``); raises if missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libppe.so not built at {path}; run paper_1810_08572_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class PpeError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+def _check(status, handle=None, allow=(PPE_OK,)):
+    if status in allow:
+        return status
+    lib = load_library()
+    detail = lib.ppe_last_error(handle).decode() if handle is not None else ""
+    name = lib.ppe_status_string(status).decode()
+    raise PpeError(status, f"{name}: {detail}")
+
+
+# ---- one-to-one wrappers of the C ABI ---------------------------------------
+def ppe_default_options():
+    o = ppe_options()
+    load_library().ppe_default_options(ctypes.byref(o))
+    return o
+
+
+def ppe_create(options: ppe_options):
+    h = ctypes.c_void_p()
+    _check(load_library().ppe_create(ctypes.byref(options), ctypes.byref(h)))
+    return h
+
+
+def ppe_destroy(handle):
+    load_library().ppe_destroy(handle)
+
+
+def ppe_set_mesh(handle, n_cells, n_faces, owner_ptr, neigh_ptr):
+    return load_library().ppe_set_mesh(handle, n_cells, n_faces, owner_ptr, neigh_ptr)
+
+
+def ppe_assemble(handle, coeff_ptr, fl_ptr):
+    return load_library().ppe_assemble(handle, coeff_ptr, fl_ptr)
+
+
+def ppe_solve(handle, rhs_ptr, p_ptr, use_x0, stats: ppe_stats):
+    return load_library().ppe_solve(handle, rhs_ptr, p_ptr, int(use_x0), ctypes.byref(stats))
+
+
+def ppe_status_string(status):
+    return load_library().ppe_status_string(status).decode()
+
+
+def ppe_last_error(handle=None):
+    return load_library().ppe_last_error(handle).decode()
+
+
+# ---- tensor-level wrapper ----------------------------------------------------
+def _dev_ptr(t, dtype, n, name):
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on a GPU device")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class SolveResult:
+    p: "object"
+    status: int
+    stats: dict
+
+
+class Solver:
+    """Pressure solver bound to the current device and torch stream."""
+
+    def __init__(self, precision="fp64", rtol=1e-10, max_iter=500, cheb_degree=2,
+                 cheb_ratio=30.0, coarse_max=256, max_levels=10, theta=0.08, stream=None):
+        import torch
+
+        lib = load_library()
+        o = ppe_default_options()
+        o.precision = {"fp64": PPE_FP64, "mixed": PPE_MIXED}[precision]
+        o.rtol, o.max_iter, o.cheb_degree, o.cheb_ratio = rtol, max_iter, cheb_degree, cheb_ratio
+        o.coarse_max, o.max_levels, o.theta = coarse_max, max_levels, theta
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        o.stream = ctypes.c_void_p(stream.cuda_stream)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self._lib = lib
+        self._h = ppe_create(o)
+        self.n_cells = 0
+        self.n_faces = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ppe_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def _chk(self, st, allow=(PPE_OK,)):
+        return _check(st, self._h, allow)
+
+    def set_mesh(self, n_cells, owner, neigh):
+        import torch
+
+        nf = owner.numel()
+        self.n_cells, self.n_faces = 0, 0
+        self._chk(self._lib.ppe_set_mesh(self._h, int(n_cells), int(nf),
+                                         _dev_ptr(owner, torch.int32, nf, "owner"),
+                                         _dev_ptr(neigh, torch.int32, nf, "neigh")))
+        self.n_cells, self.n_faces = int(n_cells), int(nf)
+
+    def assemble(self, face_coeff, liquid_fraction):
+        import torch
+
+        # before set_mesh the sizes are unknown: the library reports the state error
+        nf = self.n_faces if self.n_cells else None
+        nc = self.n_cells if self.n_cells else None
+        self._chk(self._lib.ppe_assemble(
+            self._h, _dev_ptr(face_coeff, torch.float64, nf, "face_coeff"),
+            _dev_ptr(liquid_fraction, torch.float64, nc, "liquid_fraction")))
+
+    def solve(self, rhs, x0=None, out=None, allow_not_converged=False):
+        import torch
+
+        if out is None:
+            out = torch.empty(self.n_cells, dtype=torch.float64, device=rhs.device)
+        use_x0 = x0 is not None
+        if use_x0 and x0.data_ptr() != out.data_ptr():
+            out.copy_(x0)
+        st = ppe_stats()
+        allow = (PPE_OK, PPE_NOT_CONVERGED) if allow_not_converged else (PPE_OK,)
+        status = self._lib.ppe_solve(self._h, _dev_ptr(rhs, torch.float64, self.n_cells, "rhs"),
+                                     _dev_ptr(out, torch.float64, self.n_cells, "p"),
+                                     int(use_x0), ctypes.byref(st))
+        self._chk(status, allow)
+        return SolveResult(out, status, st.as_dict())
+
+    def stats(self):
+        st = ppe_stats()
+        self._chk(self._lib.ppe_get_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    # ---- dominant-kernel measurement ----
+    def profile(self, enable=True):
+        self._chk(self._lib.ppe_profile_enable(self._h, int(enable)))
+
+    def profile_read(self):
+        ms, by, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        self._chk(self._lib.ppe_profile_read(self._h, ctypes.byref(ms), ctypes.byref(by),
+                                             ctypes.byref(n)))
+        return dict(kernel_ms=ms.value, bytes=by.value, launches=n.value)
+
+    # ---- inspection (parity tests) ----
+    def n_levels(self):
+        return self.stats()["levels"]
+
+    def level_info(self, level):
+        n = ctypes.c_int32()
+        nnz = ctypes.c_int64()
+        nnzp = ctypes.c_int64()
+        na = ctypes.c_int32()
+        rho = ctypes.c_double()
+        self._chk(self._lib.ppe_level_info(self._h, level, ctypes.byref(n), ctypes.byref(nnz),
+                                           ctypes.byref(nnzp), ctypes.byref(na),
+                                           ctypes.byref(rho)))
+        return dict(n=n.value, nnz=nnz.value, nnz_p=nnzp.value, n_agg=na.value, rho=rho.value)
+
+    def _csr(self, fn, level, rows, nnz):
+        import torch
+
+        rp = torch.empty(rows + 1, dtype=torch.int32, device=self.device)
+        ci = torch.empty(max(nnz, 1), dtype=torch.int32, device=self.device)
+        v = torch.empty(max(nnz, 1), dtype=torch.float64, device=self.device)
+        self._chk(fn(self._h, level, ctypes.c_void_p(rp.data_ptr()), ctypes.c_void_p(ci.data_ptr()),
+                     ctypes.c_void_p(v.data_ptr())))
+        return rp, ci[:nnz], v[:nnz]
+
+    def level_matrix(self, level):
+        info = self.level_info(level)
+        return self._csr(self._lib.ppe_copy_level_matrix, level, info["n"], info["nnz"])
+
+    def prolongator(self, level):
+        info = self.level_info(level)
+        return self._csr(self._lib.ppe_copy_prolongator, level, info["n"], info["nnz_p"])
+
+    def aggregates(self, level):
+        import torch
+
+        info = self.level_info(level)
+        a = torch.empty(max(info["n"], 1), dtype=torch.int32, device=self.device)
+        self._chk(self._lib.ppe_copy_aggregates(self._h, level, ctypes.c_void_p(a.data_ptr())))
+        return a[:info["n"]]
+
+    def mask(self):
+        import torch
+
+        cid = torch.empty(self.n_cells, dtype=torch.int32, device=self.device)
+        comp = torch.empty(self.n_cells, dtype=torch.int32, device=self.device)
+        self._chk(self._lib.ppe_copy_mask(self._h, ctypes.c_void_p(cid.data_ptr()),
+                                          ctypes.c_void_p(comp.data_ptr())))
+        return cid, comp
+
+    def apply_matrix(self, level, x):
+        import torch
+
+        n = self.level_info(level)["n"]
+        y = torch.empty(n, dtype=torch.float64, device=self.device)
+        self._chk(self._lib.ppe_apply_matrix(self._h, level, _dev_ptr(x, torch.float64, n, "x"),
+                                             ctypes.c_void_p(y.data_ptr())))
+        return y
+
+    def apply_vcycle(self, r):
+        import torch
+
+        n = self.level_info(0)["n"]
+        z = torch.empty(n, dtype=torch.float64, device=self.device)
+        self._chk(self._lib.ppe_apply_vcycle(self._h, _dev_ptr(r, torch.float64, n, "r"),
+                                             ctypes.c_void_p(z.data_ptr())))
+        return z

@@ -1,0 +1,682 @@
+// Smoothed-aggregation AMG setup on the device (the multigrid of section 2.5
+// of the paper, which coarsens the matrix by heuristics without a physical
+// grid; the paper names no variant, this is smoothed aggregation):
+//
+//   strength   j strong for i  iff  a_ij^2 >= theta^2 (a_ii a_jj), j != i
+//   MIS-2      synchronous rounds over keys (state, fmix32(i ^ salt), -i):
+//              an undecided node that holds the maximum key of its
+//              distance-2 neighbourhood joins, one that sees a member there
+//              leaves; nodes without strong neighbours never take part
+//   aggregates member roots; strong neighbours of a root join it; leftovers
+//              join the first-pass neighbour with the largest |a_ij|
+//              (ties to the lowest index)
+//   P_tent     B restricted to each aggregate, normalised; coarse B = norms
+//   rho        Gershgorin bound on the finest level, 1.1 x a 15-step power
+//              estimate of lambda_max(D^-1 A) on coarse levels
+//   P          P_tent - (4 / (3 rho)) D^-1 A P_tent;  R = P^T;  A_c = R (A P)
+//   coarsest   at most coarse_max rows: dense Cholesky, explicit inverse
+//
+// Every product is formed row by row in a fixed order (Gustavson order: the
+// entries of the left factor's row in ascending column order), so the setup
+// is bitwise reproducible from run to run.
+#include "common.h"
+
+#include <cmath>
+
+namespace ppe {
+namespace {
+
+constexpr int kPowerIters = 15;
+constexpr double kPowerSafety = 1.1;
+constexpr int kDenseMax = 1024;
+constexpr int kCountHash = 1024;  // hash slots per row in the symbolic product
+
+enum : int { S_OUT = 0, S_UND = 1, S_IN = 2 };
+
+// ------------------------------------------------------------------ strength
+__global__ void k_strength(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                           const double* __restrict__ v, const double* __restrict__ diag,
+                           double theta2, unsigned char* __restrict__ strong,
+                           unsigned char* __restrict__ state) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double di = diag[i];
+  int deg = 0;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    int j = ci[k];
+    double a = v[k];
+    bool s = (j != i) && (a != 0.0) && (a * a >= theta2 * (di * diag[j]));
+    strong[k] = s ? 1 : 0;
+    deg += s ? 1 : 0;
+  }
+  state[i] = deg > 0 ? S_UND : S_OUT;
+}
+
+// ------------------------------------------------------------------ MIS-2
+__device__ __forceinline__ unsigned long long mis_key(unsigned char st, int j, uint32_t salt) {
+  return ((unsigned long long)st << 62) |
+         ((unsigned long long)fmix32((uint32_t)j ^ salt) << 30) |
+         (unsigned long long)((1u << 30) - 1u - (uint32_t)j);
+}
+
+__global__ void k_mis_max1(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                           const unsigned char* __restrict__ strong,
+                           const unsigned char* __restrict__ state, uint32_t salt,
+                           unsigned long long* __restrict__ m1) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  unsigned long long m = mis_key(state[i], i, salt);
+  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    if (!strong[k]) continue;
+    int j = ci[k];
+    unsigned long long kj = mis_key(state[j], j, salt);
+    m = kj > m ? kj : m;
+  }
+  m1[i] = m;
+}
+
+__global__ void k_mis_max2(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                           const unsigned char* __restrict__ strong,
+                           const unsigned char* __restrict__ state, uint32_t salt,
+                           const unsigned long long* __restrict__ m1,
+                           unsigned char* __restrict__ next, int* __restrict__ undecided) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  unsigned char st = state[i];
+  if (st != S_UND) {
+    next[i] = st;
+    return;
+  }
+  unsigned long long m = m1[i];
+  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    if (!strong[k]) continue;
+    unsigned long long mj = m1[ci[k]];
+    m = mj > m ? mj : m;
+  }
+  const unsigned long long own = mis_key(st, i, salt);
+  unsigned char ns = st;
+  if (m == own)
+    ns = S_IN;
+  else if ((m >> 62) == S_IN)
+    ns = S_OUT;
+  next[i] = ns;
+  if (ns == S_UND) atomicAdd(undecided, 1);
+}
+
+// ------------------------------------------------------------------ aggregation
+__global__ void k_is_root(int n, const unsigned char* __restrict__ state, int* __restrict__ root) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) root[i] = state[i] == S_IN ? 1 : 0;
+}
+
+__global__ void k_agg_first(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                            const unsigned char* __restrict__ strong,
+                            const unsigned char* __restrict__ state,
+                            const int* __restrict__ root_id, int* __restrict__ agg1) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int a = -1;
+  if (state[i] == S_IN) {
+    a = root_id[i];
+  } else {
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      if (!strong[k]) continue;
+      int j = ci[k];
+      if (state[j] == S_IN) { a = root_id[j]; break; }
+    }
+  }
+  agg1[i] = a;
+}
+
+__global__ void k_agg_second(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                             const double* __restrict__ v, const unsigned char* __restrict__ strong,
+                             const int* __restrict__ agg1, int* __restrict__ agg,
+                             int* __restrict__ flag) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int a = agg1[i];
+  if (a < 0) {
+    double best = -1.0;
+    int bestj = -1;
+    bool any_strong = false;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      if (!strong[k]) continue;
+      any_strong = true;
+      int j = ci[k];
+      if (agg1[j] < 0) continue;
+      double w = fabs(v[k]);
+      if (w > best || (w == best && j < bestj)) { best = w; bestj = j; }
+    }
+    if (bestj >= 0) a = agg1[bestj];
+    else if (any_strong) atomicOr(flag, 1);
+  }
+  agg[i] = a;
+}
+
+__global__ void k_agg_count(int n, const int* __restrict__ agg, int* __restrict__ cnt) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n && agg[i] >= 0) atomicAdd(&cnt[agg[i]], 1);
+}
+
+__global__ void k_agg_fill(int n, const int* __restrict__ agg, int* __restrict__ cursor,
+                           int* __restrict__ mem) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n && agg[i] >= 0) mem[atomicAdd(&cursor[agg[i]], 1)] = i;
+}
+
+// Sort each aggregate's members, then norm_J = sqrt(sum B_i^2) in ascending i.
+__global__ void k_agg_norm(int na, const int* __restrict__ ptr, int* __restrict__ mem,
+                           const double* __restrict__ B, double* __restrict__ Bc) {
+  int J = blockIdx.x * kBlock + threadIdx.x;
+  if (J >= na) return;
+  int b = ptr[J], e = ptr[J + 1];
+  for (int i = b + 1; i < e; ++i) {
+    int key = mem[i], j = i - 1;
+    while (j >= b && mem[j] > key) { mem[j + 1] = mem[j]; --j; }
+    mem[j + 1] = key;
+  }
+  double s = 0.0;
+  for (int i = b; i < e; ++i) s = s + B[mem[i]] * B[mem[i]];
+  Bc[J] = sqrt(s);
+}
+
+__global__ void k_tent(int n, const int* __restrict__ agg, const double* __restrict__ B,
+                       const double* __restrict__ Bc, int* __restrict__ cnt,
+                       double* __restrict__ pt) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int a = agg[i];
+  cnt[i] = a >= 0 ? 1 : 0;
+  pt[i] = a >= 0 ? B[i] / Bc[a] : 0.0;
+}
+
+__global__ void k_tent_csr(int n, const int* __restrict__ rp, const int* __restrict__ agg,
+                           const double* __restrict__ pt, int* __restrict__ ci,
+                           double* __restrict__ v) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  if (agg[i] >= 0) {
+    ci[rp[i]] = agg[i];
+    v[rp[i]] = pt[i];
+  }
+}
+
+// P = P_tent - omega D^-1 (A P_tent); the pattern of A P_tent contains P_tent's.
+__global__ void k_smooth_p(int n, const int* __restrict__ qrp, const int* __restrict__ qci,
+                           const double* __restrict__ qv, const double* __restrict__ diag,
+                           const int* __restrict__ agg, const double* __restrict__ pt,
+                           double omega, double* __restrict__ pv) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double dinv = 1.0 / diag[i];
+  const int ai = agg[i];
+  for (int k = qrp[i]; k < qrp[i + 1]; ++k) {
+    double t = (qci[k] == ai) ? pt[i] : 0.0;
+    pv[k] = t - omega * (qv[k] * dinv);
+  }
+}
+
+// ------------------------------------------------------------------ spectral bounds
+__global__ void k_gershgorin(int n, const int* __restrict__ rp, const double* __restrict__ v,
+                             const double* __restrict__ diag, unsigned long long* __restrict__ out) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  double r = 0.0;
+  if (i < n) {
+    for (int k = rp[i]; k < rp[i + 1]; ++k) r = r + fabs(v[k]);
+    r = r / diag[i];
+  }
+  r = block_max<kBlock>(r);
+  if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(r));
+}
+
+__global__ void k_power_init(int n, uint32_t salt, double* __restrict__ x, double* partials,
+                             unsigned int* counter, double* out) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  double v = 0.0;
+  if (i < n) {
+    v = 0.5 + (double)fmix32((uint32_t)i ^ salt) * (1.0 / 4294967296.0);
+    x[i] = v;
+  }
+  double sq[1] = {v * v};
+  grid_sum<kBlock, 1>(sq, partials, counter, out);
+}
+
+// y = (A x) / diag / sqrt(*prev), accumulating ||y||^2 into *out.
+__global__ void k_power_step(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                             const double* __restrict__ v, const double* __restrict__ diag,
+                             const double* __restrict__ x, const double* __restrict__ prev,
+                             double* __restrict__ y, double* partials, unsigned int* counter,
+                             double* out) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  double yi = 0.0;
+  if (i < n) {
+    double s = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) s = s + v[k] * x[ci[k]];
+    yi = (s / diag[i]) / sqrt(*prev);
+    y[i] = yi;
+  }
+  double sq[1] = {yi * yi};
+  grid_sum<kBlock, 1>(sq, partials, counter, out);
+}
+
+__global__ void k_diag(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                       const double* __restrict__ v, double* __restrict__ diag,
+                       int* __restrict__ flag) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double d = 0.0;
+  for (int k = rp[i]; k < rp[i + 1]; ++k)
+    if (ci[k] == i) d = v[k];
+  diag[i] = d;
+  if (!(d > 0.0)) atomicOr(flag, 1);
+}
+
+// ------------------------------------------------------------------ sparse products
+__device__ __forceinline__ uint32_t slot_hash(int key) { return fmix32((uint32_t)key); }
+
+// Symbolic C = A B: number of distinct columns in every row of C.
+// One 64-lane workgroup per row; open-addressing hash of column ids in LDS.
+__global__ void __launch_bounds__(kWave) k_spgemm_count(
+    const int* __restrict__ arp, const int* __restrict__ aci, const int* __restrict__ brp,
+    const int* __restrict__ bci, int* __restrict__ counts, int* __restrict__ flag) {
+  __shared__ int keys[kCountHash];
+  __shared__ int cnt;
+  const int i = blockIdx.x, t = threadIdx.x;
+  for (int s = t; s < kCountHash; s += kWave) keys[s] = -1;
+  if (t == 0) cnt = 0;
+  __syncthreads();
+  bool overflow = false;
+  for (int a = arp[i]; a < arp[i + 1]; ++a) {
+    const int j = aci[a];
+    for (int b = brp[j] + t; b < brp[j + 1]; b += kWave) {
+      const int key = bci[b];
+      uint32_t s = slot_hash(key) & (kCountHash - 1);
+      int probes = 0;
+      while (true) {
+        int prev = atomicCAS(&keys[s], -1, key);
+        if (prev == -1) { atomicAdd(&cnt, 1); break; }
+        if (prev == key) break;
+        s = (s + 1) & (kCountHash - 1);
+        if (++probes >= kCountHash) { overflow = true; break; }
+      }
+    }
+    __syncthreads();
+  }
+  if (overflow) atomicOr(flag, 1);
+  __syncthreads();
+  if (t == 0) {
+    counts[i] = cnt;
+    if (cnt > (kCountHash * 3) / 4) atomicOr(flag, 1);
+  }
+}
+
+// Numeric C = A B with the row structure from k_spgemm_count.  Products are
+// accumulated in ascending order of A's row entries (one barrier per entry;
+// within one entry every column of B's row is distinct, so lanes never share
+// a slot), then written out sorted by column.
+template <int H>
+__global__ void __launch_bounds__(kWave) k_spgemm_fill(
+    const int* __restrict__ arp, const int* __restrict__ aci, const double* __restrict__ av,
+    const int* __restrict__ brp, const int* __restrict__ bci, const double* __restrict__ bv,
+    const int* __restrict__ crp, int* __restrict__ cci, double* __restrict__ cv) {
+  __shared__ int keys[H];
+  __shared__ double vals[H];
+  __shared__ int list[H];
+  __shared__ int cnt;
+  const int i = blockIdx.x, t = threadIdx.x;
+  for (int s = t; s < H; s += kWave) { keys[s] = -1; vals[s] = 0.0; }
+  if (t == 0) cnt = 0;
+  __syncthreads();
+  for (int a = arp[i]; a < arp[i + 1]; ++a) {
+    const int j = aci[a];
+    const double x = av[a];
+    for (int b = brp[j] + t; b < brp[j + 1]; b += kWave) {
+      const int key = bci[b];
+      uint32_t s = slot_hash(key) & (H - 1);
+      for (int probes = 0; probes < H; ++probes) {
+        int prev = atomicCAS(&keys[s], -1, key);
+        if (prev == -1 || prev == key) break;
+        s = (s + 1) & (H - 1);
+      }
+      vals[s] = vals[s] + x * bv[b];
+    }
+    __syncthreads();
+  }
+  for (int s = t; s < H; s += kWave)
+    if (keys[s] != -1) list[atomicAdd(&cnt, 1)] = s;
+  __syncthreads();
+  const int u = cnt, base = crp[i];
+  for (int p = t; p < u; p += kWave) {
+    const int key = keys[list[p]];
+    int rank = 0;
+    for (int q = 0; q < u; ++q) rank += keys[list[q]] < key ? 1 : 0;
+    cci[base + rank] = key;
+    cv[base + rank] = vals[list[p]];
+  }
+}
+
+// ------------------------------------------------------------------ transpose
+__global__ void k_col_count(int64_t nnz, const int* __restrict__ ci, int* __restrict__ cnt) {
+  int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k < nnz) atomicAdd(&cnt[ci[k]], 1);
+}
+
+__global__ void k_transpose_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                 const double* __restrict__ v, int* __restrict__ cursor,
+                                 int* __restrict__ tci, double* __restrict__ tv) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    int p = atomicAdd(&cursor[ci[k]], 1);
+    tci[p] = i;
+    tv[p] = v[k];
+  }
+}
+
+__global__ void k_sort_rows(int n, const int* __restrict__ rp, int* __restrict__ ci,
+                            double* __restrict__ v) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int b = rp[i], e = rp[i + 1];
+  for (int k = b + 1; k < e; ++k) {
+    int key = ci[k];
+    double x = v[k];
+    int j = k - 1;
+    while (j >= b && ci[j] > key) { ci[j + 1] = ci[j]; v[j + 1] = v[j]; --j; }
+    ci[j + 1] = key;
+    v[j + 1] = x;
+  }
+}
+
+// ------------------------------------------------------------------ dense coarsest
+__global__ void k_densify(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                          const double* __restrict__ v, double* __restrict__ M) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) M[(size_t)i * n + ci[k]] = v[k];
+}
+
+// In-place Cholesky (lower) of the symmetric matrix M, then the explicit
+// inverse L^-T L^-1 into Ainv.  One workgroup; W scratch n*n.
+__global__ void __launch_bounds__(1024) k_dense_inverse(int n, double* __restrict__ M,
+                                                        double* __restrict__ W,
+                                                        double* __restrict__ Ainv,
+                                                        int* __restrict__ flag) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int k = 0; k < n; ++k) {
+    if (t == 0) {
+      double d = M[(size_t)k * n + k];
+      if (!(d > 0.0)) { atomicOr(flag, 2); d = 1.0; }
+      M[(size_t)k * n + k] = sqrt(d);
+    }
+    __syncthreads();
+    const double lkk = M[(size_t)k * n + k];
+    for (int i = k + 1 + t; i < n; i += nt) M[(size_t)i * n + k] = M[(size_t)i * n + k] / lkk;
+    __syncthreads();
+    const int m = n - k - 1;
+    for (int64_t p = t; p < (int64_t)m * m; p += nt) {
+      int i = k + 1 + (int)(p / m), j = k + 1 + (int)(p % m);
+      if (j <= i) M[(size_t)i * n + j] -= M[(size_t)i * n + k] * M[(size_t)j * n + k];
+    }
+    __syncthreads();
+  }
+  // W = L^-1 (lower), column c by forward substitution (one thread per column)
+  for (int c = t; c < n; c += nt) {
+    for (int i = 0; i < c; ++i) W[(size_t)i * n + c] = 0.0;
+    for (int i = c; i < n; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) s -= M[(size_t)i * n + k] * W[(size_t)k * n + c];
+      W[(size_t)i * n + c] = s / M[(size_t)i * n + i];
+    }
+  }
+  __syncthreads();
+  // Ainv = W^T W
+  for (int64_t p = t; p < (int64_t)n * n; p += nt) {
+    int i = (int)(p / n), j = (int)(p % n);
+    int k0 = i > j ? i : j;
+    double s = 0.0;
+    for (int k = k0; k < n; ++k) s += W[(size_t)k * n + i] * W[(size_t)k * n + j];
+    Ainv[p] = s;
+  }
+}
+
+// ------------------------------------------------------------------ host helpers
+void spgemm(ppe_solver* s, const Csr& A, const Csr& B, Csr& C) {
+  require(A.m == B.n, PPE_ERR_INTERNAL, "spgemm shape mismatch");
+  C.n = A.n;
+  C.m = B.m;
+  int* crp = C.rowptr.get<int>(C.n + 1);
+  if (C.n == 0) {
+    C.nnz = 0;
+    fill_int(s, crp, 0, 1);
+    return;
+  }
+  int* counts = s->tmp_i[0].get<int>(C.n + 1);
+  int* flag = s->flag.get<int>(1);
+  fill_int(s, flag, 0, 1);
+  hipLaunchKernelGGL(k_spgemm_count, dim3(C.n), dim3(kWave), 0, s->stream, A.rp(), A.ci(), B.rp(),
+                     B.ci(), counts, flag);
+  PPE_LAUNCH_CHECK();
+  require(read_scalar(s, flag) == 0, PPE_ERR_INTERNAL,
+          "sparse product row exceeds the hash table (more than 768 distinct columns)");
+  int mx = reduce_max_int(s, counts, C.n);
+  C.nnz = exclusive_scan(s, counts, crp, C.n);
+  int* cci = C.col.get<int>(C.nnz);
+  double* cv = C.val.get<double>(C.nnz);
+  int H = 64;
+  while (H < 2 * mx) H *= 2;
+#define PPE_FILL(HH)                                                                          \
+  hipLaunchKernelGGL(k_spgemm_fill<HH>, dim3(C.n), dim3(kWave), 0, s->stream, A.rp(), A.ci(),  \
+                     A.v(), B.rp(), B.ci(), B.v(), crp, cci, cv)
+  if (H <= 64) PPE_FILL(64);
+  else if (H <= 128) PPE_FILL(128);
+  else if (H <= 256) PPE_FILL(256);
+  else if (H <= 512) PPE_FILL(512);
+  else if (H <= 1024) PPE_FILL(1024);
+  else PPE_FILL(2048);
+#undef PPE_FILL
+  PPE_LAUNCH_CHECK();
+}
+
+void transpose(ppe_solver* s, const Csr& A, Csr& T) {
+  T.n = A.m;
+  T.m = A.n;
+  T.nnz = A.nnz;
+  int* cnt = s->tmp_i[0].get<int>(T.n + 1);
+  fill_int(s, cnt, 0, T.n + 1);
+  if (A.nnz) {
+    hipLaunchKernelGGL(k_col_count, dim3(grid_for(A.nnz)), dim3(kBlock), 0, s->stream, A.nnz, A.ci(),
+                       cnt);
+    PPE_LAUNCH_CHECK();
+  }
+  int* trp = T.rowptr.get<int>(T.n + 1);
+  exclusive_scan(s, cnt, trp, T.n);
+  int* cursor = s->tmp_i[1].get<int>(T.n + 1);
+  PPE_HIP(hipMemcpyAsync(cursor, trp, sizeof(int) * (T.n + 1), hipMemcpyDeviceToDevice, s->stream));
+  int* tci = T.col.get<int>(T.nnz);
+  double* tv = T.val.get<double>(T.nnz);
+  if (A.n) {
+    hipLaunchKernelGGL(k_transpose_fill, dim3(grid_for(A.n)), dim3(kBlock), 0, s->stream, A.n, A.rp(),
+                       A.ci(), A.v(), cursor, tci, tv);
+    PPE_LAUNCH_CHECK();
+  }
+  if (T.n) {
+    hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(T.n)), dim3(kBlock), 0, s->stream, T.n, trp, tci, tv);
+    PPE_LAUNCH_CHECK();
+  }
+}
+
+double spectral_bound(ppe_solver* s, Level& L, int lvl) {
+  const int n = L.n;
+  if (n == 0) return 1.0;
+  if (lvl == 0) {
+    unsigned long long* out = reinterpret_cast<unsigned long long*>(s->tmp_d[0].get<double>(1));
+    PPE_HIP(hipMemsetAsync(out, 0, sizeof(double), s->stream));
+    hipLaunchKernelGGL(k_gershgorin, dim3(grid_for(n)), dim3(kBlock), 0, s->stream, n, L.A.rp(),
+                       L.A.v(), L.diag.as<double>(), out);
+    PPE_LAUNCH_CHECK();
+    double r = read_scalar(s, reinterpret_cast<double*>(out));
+    return r;
+  }
+  const int g = grid_for(n);
+  double* x = L.x.get<double>(n);
+  double* y = L.r.get<double>(n);
+  double* sums = s->tmp_d[0].get<double>(kPowerIters + 1);
+  double* partials = s->partial.get<double>((size_t)g * 4);
+  unsigned int* counter = s->counter.get<unsigned int>(1);
+  hipLaunchKernelGGL(k_power_init, dim3(g), dim3(kBlock), 0, s->stream, n, level_salt(lvl), x,
+                     partials, counter, sums);
+  PPE_LAUNCH_CHECK();
+  for (int it = 0; it < kPowerIters; ++it) {
+    hipLaunchKernelGGL(k_power_step, dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(), L.A.ci(),
+                       L.A.v(), L.diag.as<double>(), x, sums + it, y, partials, counter,
+                       sums + it + 1);
+    PPE_LAUNCH_CHECK();
+    double* t = x;
+    x = y;
+    y = t;
+  }
+  double last = read_scalar(s, sums + kPowerIters);
+  return kPowerSafety * std::sqrt(last);
+}
+
+}  // namespace
+
+void build_hierarchy(ppe_solver* s) {
+  const double theta2 = s->opt.theta * s->opt.theta;
+  for (int lvl = 0;; ++lvl) {
+    Level& L = s->levels[lvl];
+    const int n = L.n;
+    int* flag = s->flag.get<int>(1);
+    if (lvl > 0 && n > 0) {
+      fill_int(s, flag, 0, 1);
+      hipLaunchKernelGGL(k_diag, dim3(grid_for(n)), dim3(kBlock), 0, s->stream, n, L.A.rp(), L.A.ci(),
+                         L.A.v(), L.diag.get<double>(n), flag);
+      PPE_LAUNCH_CHECK();
+      require(read_scalar(s, flag) == 0, PPE_ERR_INTERNAL, "coarse operator lost its diagonal");
+    }
+    L.rho = spectral_bound(s, L, lvl);
+    L.n_agg = 0;
+    L.dense = false;
+    L.mis_rounds = 0;
+    const bool last = n <= s->opt.coarse_max || lvl == s->opt.max_levels - 1;
+    if (!last) {
+      const int g = grid_for(n);
+      unsigned char* strong = L.strong.get<unsigned char>(L.A.nnz);
+      unsigned char* st = L.state.get<unsigned char>(n);
+      unsigned char* st2 = L.state2.get<unsigned char>(n);
+      unsigned long long* m1 = L.m1.get<unsigned long long>(n);
+      hipLaunchKernelGGL(k_strength, dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(), L.A.ci(),
+                         L.A.v(), L.diag.as<double>(), theta2, strong, st);
+      PPE_LAUNCH_CHECK();
+      const uint32_t salt = level_salt(lvl);
+      int* und = s->tmp_i[3].get<int>(1);
+      while (true) {
+        fill_int(s, und, 0, 1);
+        hipLaunchKernelGGL(k_mis_max1, dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(), L.A.ci(),
+                           strong, st, salt, m1);
+        PPE_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_mis_max2, dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(), L.A.ci(),
+                           strong, st, salt, m1, st2, und);
+        PPE_LAUNCH_CHECK();
+        std::swap(st, st2);
+        ++L.mis_rounds;
+        if (read_scalar(s, und) == 0) break;
+        require(L.mis_rounds < 10000, PPE_ERR_INTERNAL, "MIS-2 did not terminate");
+      }
+      int* root = s->tmp_i[2].get<int>(n + 1);
+      hipLaunchKernelGGL(k_is_root, dim3(g), dim3(kBlock), 0, s->stream, n, st, root);
+      PPE_LAUNCH_CHECK();
+      int* root_id = L.mis_root.get<int>(n + 1);
+      const int na = (int)exclusive_scan(s, root, root_id, n);
+      if (na > 0) {
+        int* agg1 = L.agg1.get<int>(n);
+        int* agg = L.agg.get<int>(n);
+        hipLaunchKernelGGL(k_agg_first, dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(), L.A.ci(),
+                           strong, st, root_id, agg1);
+        PPE_LAUNCH_CHECK();
+        fill_int(s, flag, 0, 1);
+        hipLaunchKernelGGL(k_agg_second, dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(), L.A.ci(),
+                           L.A.v(), strong, agg1, agg, flag);
+        PPE_LAUNCH_CHECK();
+        require(read_scalar(s, flag) == 0, PPE_ERR_INTERNAL, "aggregation left a node unassigned");
+        L.n_agg = na;
+        // aggregate members, coarse near-null vector, tentative prolongator
+        int* cnt = s->tmp_i[0].get<int>(na + 1);
+        fill_int(s, cnt, 0, na + 1);
+        hipLaunchKernelGGL(k_agg_count, dim3(g), dim3(kBlock), 0, s->stream, n, agg, cnt);
+        PPE_LAUNCH_CHECK();
+        int* aptr = L.agg_ptr.get<int>(na + 1);
+        int64_t nm = exclusive_scan(s, cnt, aptr, na);
+        int* cursor = s->tmp_i[1].get<int>(na + 1);
+        PPE_HIP(hipMemcpyAsync(cursor, aptr, sizeof(int) * (na + 1), hipMemcpyDeviceToDevice,
+                               s->stream));
+        int* mem = L.agg_mem.get<int>(nm);
+        hipLaunchKernelGGL(k_agg_fill, dim3(g), dim3(kBlock), 0, s->stream, n, agg, cursor, mem);
+        PPE_LAUNCH_CHECK();
+        if ((int)s->levels.size() < lvl + 2) s->levels.resize(lvl + 2);
+        Level& L0 = s->levels[lvl];  // re-fetch: resize may move levels
+        Level& C = s->levels[lvl + 1];
+        double* Bc = C.B.get<double>(na);
+        hipLaunchKernelGGL(k_agg_norm, dim3(grid_for(na)), dim3(kBlock), 0, s->stream, na, aptr, mem,
+                           L0.B.as<double>(), Bc);
+        PPE_LAUNCH_CHECK();
+        double* pt = L0.pt.get<double>(n);
+        int* pcnt = s->tmp_i[0].get<int>(n + 1);
+        hipLaunchKernelGGL(k_tent, dim3(g), dim3(kBlock), 0, s->stream, n, agg, L0.B.as<double>(), Bc,
+                           pcnt, pt);
+        PPE_LAUNCH_CHECK();
+        Csr& Pt = L0.Pt;
+        Pt.n = n;
+        Pt.m = na;
+        int* ptrp = Pt.rowptr.get<int>(n + 1);
+        Pt.nnz = exclusive_scan(s, pcnt, ptrp, n);
+        hipLaunchKernelGGL(k_tent_csr, dim3(g), dim3(kBlock), 0, s->stream, n, ptrp, agg, pt,
+                           Pt.col.get<int>(Pt.nnz), Pt.val.get<double>(Pt.nnz));
+        PPE_LAUNCH_CHECK();
+        // smoothed prolongator
+        spgemm(s, L0.A, Pt, L0.Q);
+        Csr& P = L0.P;
+        P.n = n;
+        P.m = na;
+        P.nnz = L0.Q.nnz;
+        int* prp = P.rowptr.get<int>(n + 1);
+        PPE_HIP(hipMemcpyAsync(prp, L0.Q.rp(), sizeof(int) * (n + 1), hipMemcpyDeviceToDevice,
+                               s->stream));
+        int* pci = P.col.get<int>(P.nnz);
+        PPE_HIP(hipMemcpyAsync(pci, L0.Q.ci(), sizeof(int) * P.nnz, hipMemcpyDeviceToDevice,
+                               s->stream));
+        const double omega = 4.0 / (3.0 * L0.rho);
+        hipLaunchKernelGGL(k_smooth_p, dim3(g), dim3(kBlock), 0, s->stream, n, L0.Q.rp(), L0.Q.ci(),
+                           L0.Q.v(), L0.diag.as<double>(), agg, pt, omega,
+                           P.val.get<double>(P.nnz));
+        PPE_LAUNCH_CHECK();
+        transpose(s, P, L0.R);
+        spgemm(s, L0.A, P, L0.AP);
+        spgemm(s, L0.R, L0.AP, C.A);
+        C.n = na;
+        s->nlev = lvl + 2;
+        continue;
+      }
+    }
+    // coarsest level
+    s->nlev = lvl + 1;
+    if (n > 0 && n <= kDenseMax) {
+      double* M = L.Ainv.get<double>((size_t)n * n);  // reused below as the result
+      double* Wk = s->tmp_d[1].get<double>((size_t)2 * n * n);
+      double* Mw = Wk + (size_t)n * n;
+      PPE_HIP(hipMemsetAsync(Mw, 0, sizeof(double) * n * n, s->stream));
+      hipLaunchKernelGGL(k_densify, dim3(grid_for(n)), dim3(kBlock), 0, s->stream, n, L.A.rp(),
+                         L.A.ci(), L.A.v(), Mw);
+      PPE_LAUNCH_CHECK();
+      fill_int(s, flag, 0, 1);
+      hipLaunchKernelGGL(k_dense_inverse, dim3(1), dim3(1024), 0, s->stream, n, Mw, Wk, M, flag);
+      PPE_LAUNCH_CHECK();
+      require(read_scalar(s, flag) == 0, PPE_ERR_INTERNAL, "coarsest operator is not positive definite");
+      L.dense = true;
+    }
+    break;
+  }
+}
+
+}  // namespace ppe

@@ -1,0 +1,361 @@
+// C ABI of the pressure-solve library (declared in include/ppe.h).
+#include "common.h"
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+namespace {
+
+thread_local std::string g_err;
+
+template <class F>
+ppe_status guarded(ppe_solver* s, F&& f) {
+  try {
+    if (s) s->err.clear();
+    return f();
+  } catch (const ppe::Error& e) {
+    if (s) s->err = e.what();
+    g_err = e.what();
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    if (s) s->err = "host allocation failed";
+    g_err = "host allocation failed";
+    return PPE_ERR_OOM;
+  } catch (const std::exception& e) {
+    if (s) s->err = e.what();
+    g_err = e.what();
+    return PPE_ERR_INTERNAL;
+  }
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+float elapsed_ms(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, a, b);
+  return ms;
+}
+
+double bytes_per_iteration(const ppe_solver* s) {
+  // Algorithmic bytes of one PCG iteration: every matrix entry read once
+  // (value + column index), every vector an operator touches read or written
+  // once.  v = 8 bytes per value.
+  const double v = 8.0;
+  double total = 0.0;
+  const ppe::Level& L0 = s->levels[0];
+  const double n0 = L0.n, off0 = (double)(L0.A.nnz - L0.n);
+  // outer SpMV with p.q (diag, p, q) + x,r update (x,p,r,q -> x,r) + r.z + p update
+  total += off0 * (v + 4) + 3 * v * n0 + 6 * v * n0 + 2 * v * n0 + 3 * v * n0;
+  const int deg = s->opt.cheb_degree;
+  for (int l = 0; l < s->nlev; ++l) {
+    const ppe::Level& L = s->levels[l];
+    const double n = L.n;
+    const double mat = (l == 0) ? off0 * (v + 4) + v * n : (double)L.A.nnz * (v + 4) + 4 * n;
+    if (l == s->nlev - 1) {
+      total += L.dense ? n * n * v + 2 * n * v : 2 * deg * (mat + 6 * v * n);
+      continue;
+    }
+    // pre: first step elementwise (b, diag -> d, x) + (deg-1) fused steps;
+    // residual; restriction; prolongation; post: deg fused steps
+    const double fused = mat + 5 * v * n;  // x_in, b, d -> d, x_out (+diag in mat)
+    total += 4 * v * n + (deg - 1) * fused;
+    total += mat + 3 * v * n;
+    const ppe::Csr& R = L.R;
+    const ppe::Csr& P = L.P;
+    total += (double)R.nnz * (v + 4) + 4.0 * R.n + v * n + v * R.n;
+    total += (double)P.nnz * (v + 4) + 4.0 * P.n + v * R.n + 2 * v * n;
+    total += deg * fused;
+  }
+  return total;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ppe_default_options(ppe_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = PPE_FP64;
+  o->rtol = 1e-10;
+  o->max_iter = 500;
+  o->cheb_degree = 2;
+  o->cheb_ratio = 30.0;
+  o->coarse_max = 256;
+  o->max_levels = 10;
+  o->theta = 0.08;
+  o->check_every = 1;
+  o->stream = nullptr;
+}
+
+ppe_status ppe_create(const ppe_options* opt, ppe_solver** out) {
+  return guarded(nullptr, [&]() -> ppe_status {
+    ppe::require(out != nullptr, PPE_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    ppe_options o;
+    ppe_default_options(&o);
+    if (opt) o = *opt;
+    ppe::require(o.precision == PPE_FP64 || o.precision == PPE_MIXED, PPE_ERR_ARG, "bad precision");
+    ppe::require(o.rtol > 0 && o.rtol < 1, PPE_ERR_ARG, "rtol must be in (0, 1)");
+    ppe::require(o.max_iter >= 1, PPE_ERR_ARG, "max_iter must be >= 1");
+    ppe::require(o.cheb_degree >= 1 && o.cheb_degree <= 8, PPE_ERR_ARG, "cheb_degree in [1, 8]");
+    ppe::require(o.cheb_ratio > 1, PPE_ERR_ARG, "cheb_ratio must be > 1");
+    ppe::require(o.coarse_max >= 1, PPE_ERR_ARG, "coarse_max must be >= 1");
+    ppe::require(o.max_levels >= 1 && o.max_levels <= 32, PPE_ERR_ARG, "max_levels in [1, 32]");
+    ppe::require(o.theta >= 0 && o.theta < 1, PPE_ERR_ARG, "theta in [0, 1)");
+    if (o.check_every < 1) o.check_every = 1;
+    auto* s = new ppe_solver();
+    s->opt = o;
+    s->stream = static_cast<hipStream_t>(o.stream);
+    try {
+      PPE_HIP(hipGetDevice(&s->device));
+      PPE_HIP(hipEventCreate(&s->ev0));
+      PPE_HIP(hipEventCreate(&s->ev1));
+      s->levels.reserve(o.max_levels + 1);
+      unsigned int* c = s->counter.get<unsigned int>(1);
+      PPE_HIP(hipMemsetAsync(c, 0, sizeof(unsigned int), s->stream));
+      PPE_HIP(hipStreamSynchronize(s->stream));
+    } catch (...) {
+      if (s->ev0) (void)hipEventDestroy(s->ev0);
+      if (s->ev1) (void)hipEventDestroy(s->ev1);
+      delete s;
+      throw;
+    }
+    *out = s;
+    return PPE_OK;
+  });
+}
+
+void ppe_destroy(ppe_solver* s) {
+  if (!s) return;
+  DeviceGuard g(s->device);
+  (void)hipStreamSynchronize(s->stream);
+  for (auto& e : s->prof_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (s->ev0) (void)hipEventDestroy(s->ev0);
+  if (s->ev1) (void)hipEventDestroy(s->ev1);
+  delete s;
+}
+
+ppe_status ppe_set_mesh(ppe_solver* s, int32_t n_cells, int32_t n_faces, const int32_t* owner,
+                        const int32_t* neigh) {
+  if (!s) return PPE_ERR_ARG;
+  return guarded(s, [&]() -> ppe_status {
+    DeviceGuard g(s->device);
+    ppe::require(n_cells > 0, PPE_ERR_ARG, "n_cells must be positive");
+    ppe::require(n_faces >= 0, PPE_ERR_ARG, "n_faces must be >= 0");
+    ppe::require(n_faces == 0 || (owner && neigh), PPE_ERR_ARG, "owner/neigh is NULL");
+    s->have_mesh = false;
+    s->assembled = false;
+    s->n_cells = n_cells;
+    s->n_faces = n_faces;
+    ppe::build_topology(s, owner, neigh);
+    s->have_mesh = true;
+    return PPE_OK;
+  });
+}
+
+ppe_status ppe_assemble(ppe_solver* s, const double* face_coeff, const double* fl) {
+  if (!s) return PPE_ERR_ARG;
+  return guarded(s, [&]() -> ppe_status {
+    DeviceGuard g(s->device);
+    ppe::require(s->have_mesh, PPE_ERR_STATE, "ppe_assemble before ppe_set_mesh");
+    ppe::require(fl && (face_coeff || s->n_faces == 0), PPE_ERR_ARG, "NULL input array");
+    s->assembled = false;
+    PPE_HIP(hipEventRecord(s->ev0, s->stream));
+    ppe::assemble_fine(s, face_coeff, fl);
+    if (s->n_active > 0) {
+      ppe::build_hierarchy(s);
+      ppe::prepare_solve_levels(s);
+    } else {
+      s->nlev = 1;
+    }
+    PPE_HIP(hipEventRecord(s->ev1, s->stream));
+    PPE_HIP(hipEventSynchronize(s->ev1));
+    s->stats.setup_ms = elapsed_ms(s->ev0, s->ev1);
+    s->stats.n_active = s->n_active;
+    s->stats.n_components = s->n_comp;
+    s->stats.levels = s->n_active > 0 ? s->nlev : 0;
+    double nnz0 = s->levels[0].A.nnz, tot = 0;
+    for (int l = 0; l < s->nlev; ++l) tot += s->levels[l].A.nnz;
+    s->stats.op_complexity = nnz0 > 0 ? tot / nnz0 : 1.0;
+    s->stats.bytes_per_iter = s->n_active > 0 ? bytes_per_iteration(s) : 0.0;
+    s->assembled = true;
+    return PPE_OK;
+  });
+}
+
+ppe_status ppe_solve(ppe_solver* s, const double* rhs, double* p, int use_x0, ppe_stats* stats) {
+  if (!s) return PPE_ERR_ARG;
+  return guarded(s, [&]() -> ppe_status {
+    DeviceGuard g(s->device);
+    ppe::require(s->assembled, PPE_ERR_STATE, "ppe_solve before ppe_assemble");
+    ppe::require(rhs && p, PPE_ERR_ARG, "NULL rhs or p");
+    PPE_HIP(hipEventRecord(s->ev0, s->stream));
+    ppe_status st = ppe::pcg_solve(s, rhs, p, use_x0);
+    PPE_HIP(hipEventRecord(s->ev1, s->stream));
+    PPE_HIP(hipEventSynchronize(s->ev1));
+    s->stats.solve_ms = elapsed_ms(s->ev0, s->ev1);
+    if (stats) *stats = s->stats;
+    if (st == PPE_ERR_BREAKDOWN) s->err = "PCG breakdown (p.Ap <= 0, r.z <= 0 or non-finite)";
+    return st;
+  });
+}
+
+ppe_status ppe_get_stats(const ppe_solver* s, ppe_stats* stats) {
+  if (!s || !stats) return PPE_ERR_ARG;
+  *stats = s->stats;
+  return PPE_OK;
+}
+
+const char* ppe_status_string(ppe_status st) {
+  switch (st) {
+    case PPE_OK: return "ok";
+    case PPE_NOT_CONVERGED: return "not converged";
+    case PPE_ERR_ARG: return "invalid argument";
+    case PPE_ERR_HIP: return "HIP runtime error";
+    case PPE_ERR_OOM: return "out of device memory";
+    case PPE_ERR_BREAKDOWN: return "Krylov breakdown";
+    case PPE_ERR_STATE: return "call out of order";
+    case PPE_ERR_INTERNAL: return "internal limit exceeded";
+  }
+  return "unknown status";
+}
+
+const char* ppe_last_error(const ppe_solver* s) { return s ? s->err.c_str() : g_err.c_str(); }
+
+// ------------------------------------------------------------------ inspection
+static ppe_status check_level(const ppe_solver* s, int level) {
+  if (!s) return PPE_ERR_ARG;
+  if (!s->assembled) return PPE_ERR_STATE;
+  if (level < 0 || level >= s->nlev || s->n_active == 0) return PPE_ERR_ARG;
+  return PPE_OK;
+}
+
+ppe_status ppe_level_info(const ppe_solver* s, int level, int32_t* n_rows, int64_t* nnz_a,
+                          int64_t* nnz_p, int32_t* n_agg, double* rho) {
+  ppe_status st = check_level(s, level);
+  if (st != PPE_OK) return st;
+  const ppe::Level& L = s->levels[level];
+  const bool coarsest = level == s->nlev - 1;
+  if (n_rows) *n_rows = L.n;
+  if (nnz_a) *nnz_a = L.A.nnz;
+  if (nnz_p) *nnz_p = coarsest ? 0 : L.P.nnz;
+  if (n_agg) *n_agg = coarsest ? 0 : L.n_agg;
+  if (rho) *rho = L.rho;
+  return PPE_OK;
+}
+
+static ppe_status copy_csr(ppe_solver* s, const ppe::Csr& A, int32_t* rp, int32_t* ci, double* v) {
+  if (!rp || !ci || !v) return PPE_ERR_ARG;
+  return guarded(s, [&]() -> ppe_status {
+    DeviceGuard g(s->device);
+    PPE_HIP(hipMemcpyAsync(rp, A.rp(), sizeof(int) * (A.n + 1), hipMemcpyDeviceToDevice, s->stream));
+    if (A.nnz) {
+      PPE_HIP(hipMemcpyAsync(ci, A.ci(), sizeof(int) * A.nnz, hipMemcpyDeviceToDevice, s->stream));
+      PPE_HIP(hipMemcpyAsync(v, A.v(), sizeof(double) * A.nnz, hipMemcpyDeviceToDevice, s->stream));
+    }
+    PPE_HIP(hipStreamSynchronize(s->stream));
+    return PPE_OK;
+  });
+}
+
+ppe_status ppe_copy_level_matrix(const ppe_solver* s, int level, int32_t* row_ptr, int32_t* col,
+                                 double* val) {
+  ppe_status st = check_level(s, level);
+  if (st != PPE_OK) return st;
+  return copy_csr(const_cast<ppe_solver*>(s), s->levels[level].A, row_ptr, col, val);
+}
+
+ppe_status ppe_copy_prolongator(const ppe_solver* s, int level, int32_t* row_ptr, int32_t* col,
+                                double* val) {
+  ppe_status st = check_level(s, level);
+  if (st != PPE_OK) return st;
+  if (level == s->nlev - 1) return PPE_ERR_ARG;
+  return copy_csr(const_cast<ppe_solver*>(s), s->levels[level].P, row_ptr, col, val);
+}
+
+ppe_status ppe_copy_aggregates(const ppe_solver* s, int level, int32_t* agg) {
+  ppe_status st = check_level(s, level);
+  if (st != PPE_OK) return st;
+  if (level == s->nlev - 1 || !agg) return PPE_ERR_ARG;
+  ppe_solver* m = const_cast<ppe_solver*>(s);
+  return guarded(m, [&]() -> ppe_status {
+    DeviceGuard g(s->device);
+    const ppe::Level& L = s->levels[level];
+    PPE_HIP(hipMemcpyAsync(agg, L.agg.as<int>(), sizeof(int) * L.n, hipMemcpyDeviceToDevice,
+                           s->stream));
+    PPE_HIP(hipStreamSynchronize(s->stream));
+    return PPE_OK;
+  });
+}
+
+ppe_status ppe_copy_mask(const ppe_solver* s, int32_t* compact_id, int32_t* component) {
+  if (!s) return PPE_ERR_ARG;
+  if (!s->assembled) return PPE_ERR_STATE;
+  if (!compact_id || !component) return PPE_ERR_ARG;
+  ppe_solver* m = const_cast<ppe_solver*>(s);
+  return guarded(m, [&]() -> ppe_status {
+    DeviceGuard g(s->device);
+    PPE_HIP(hipMemcpyAsync(compact_id, s->cid.as<int>(), sizeof(int) * s->n_cells,
+                           hipMemcpyDeviceToDevice, s->stream));
+    PPE_HIP(hipMemcpyAsync(component, s->comp_full.as<int>(), sizeof(int) * s->n_cells,
+                           hipMemcpyDeviceToDevice, s->stream));
+    PPE_HIP(hipStreamSynchronize(s->stream));
+    return PPE_OK;
+  });
+}
+
+ppe_status ppe_apply_matrix(ppe_solver* s, int level, const double* x, double* y) {
+  ppe_status st = check_level(s, level);
+  if (st != PPE_OK) return st;
+  if (!x || !y) return PPE_ERR_ARG;
+  return guarded(s, [&]() -> ppe_status {
+    DeviceGuard g(s->device);
+    ppe::spmv(s, s->levels[level], x, y);
+    PPE_HIP(hipStreamSynchronize(s->stream));
+    return PPE_OK;
+  });
+}
+
+ppe_status ppe_apply_vcycle(ppe_solver* s, const double* r, double* z) {
+  ppe_status st = check_level(s, 0);
+  if (st != PPE_OK) return st;
+  if (!r || !z) return PPE_ERR_ARG;
+  return guarded(s, [&]() -> ppe_status {
+    DeviceGuard g(s->device);
+    ppe::vcycle(s, 0, r, z);
+    PPE_HIP(hipStreamSynchronize(s->stream));
+    return PPE_OK;
+  });
+}
+
+ppe_status ppe_profile_enable(ppe_solver* s, int enable) {
+  if (!s) return PPE_ERR_ARG;
+  return guarded(s, [&]() -> ppe_status {
+    DeviceGuard g(s->device);
+    ppe::profile_enable(s, enable != 0);
+    return PPE_OK;
+  });
+}
+
+ppe_status ppe_profile_read(const ppe_solver* s, double* kernel_ms, double* bytes,
+                            int64_t* launches) {
+  if (!s || !kernel_ms || !bytes || !launches) return PPE_ERR_ARG;
+  *kernel_ms = s->prof_ms;
+  *bytes = s->prof_bytes;
+  *launches = s->prof_launches;
+  return PPE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,337 @@
+// Mesh topology and the masked assembly of the finest pressure operator.
+//
+// Topology (once per mesh): for every cell, the list of (neighbour, face)
+// over its interior faces, sorted by neighbour then face, in CSR form.
+//
+// Masked assembly (each time the liquid fraction changes), section 2.4.2:
+//   active cell     f_l > 0 (liquid or mushy, tag LM); compact ids by scan;
+//   open face       interior face whose two owners are active; a face with a
+//                   removed owner is blocked and adds nothing anywhere
+//                   (Neumann at the solid front, case 3, step 2);
+//   components      connected sets of active cells over open faces, found by
+//                   lock-free union-find that always hooks the larger root
+//                   under the smaller one, so the final root of each set is
+//                   its lowest cell index: that cell is the set's pin;
+//   rows            diagonal = sum of open-face coefficients taken in
+//                   ascending neighbour order; off-diagonal -c_f towards every
+//                   active neighbour that is not a pin; a pin keeps only its
+//                   diagonal (1 when it has no open face).
+#include "common.h"
+
+namespace ppe {
+namespace {
+
+__global__ void k_check_faces(const int* __restrict__ owner, const int* __restrict__ neigh,
+                              int n_faces, int n_cells, int* __restrict__ flag) {
+  int f = blockIdx.x * kBlock + threadIdx.x;
+  if (f >= n_faces) return;
+  int o = owner[f], nb = neigh[f];
+  if (o < 0 || o >= n_cells || nb < -1 || nb >= n_cells || o == nb) atomicOr(flag, 1);
+}
+
+__global__ void k_degree(const int* __restrict__ owner, const int* __restrict__ neigh,
+                         int n_faces, int* __restrict__ deg) {
+  int f = blockIdx.x * kBlock + threadIdx.x;
+  if (f >= n_faces) return;
+  int nb = neigh[f];
+  if (nb < 0) return;
+  atomicAdd(&deg[owner[f]], 1);
+  atomicAdd(&deg[nb], 1);
+}
+
+__global__ void k_adj_fill(const int* __restrict__ owner, const int* __restrict__ neigh,
+                           int n_faces, int* __restrict__ cursor, int* __restrict__ adj_nbr,
+                           int* __restrict__ adj_face) {
+  int f = blockIdx.x * kBlock + threadIdx.x;
+  if (f >= n_faces) return;
+  int o = owner[f], nb = neigh[f];
+  if (nb < 0) return;
+  int p = atomicAdd(&cursor[o], 1);
+  adj_nbr[p] = nb;
+  adj_face[p] = f;
+  p = atomicAdd(&cursor[nb], 1);
+  adj_nbr[p] = o;
+  adj_face[p] = f;
+}
+
+// Sort each cell's (neighbour, face) list; flag two faces joining one pair.
+__global__ void k_adj_sort(const int* __restrict__ ptr, int n_cells, int* __restrict__ nbr,
+                           int* __restrict__ face, int* __restrict__ flag) {
+  int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= n_cells) return;
+  int b = ptr[c], e = ptr[c + 1];
+  for (int i = b + 1; i < e; ++i) {
+    int kn = nbr[i], kf = face[i];
+    int j = i - 1;
+    while (j >= b && (nbr[j] > kn || (nbr[j] == kn && face[j] > kf))) {
+      nbr[j + 1] = nbr[j];
+      face[j + 1] = face[j];
+      --j;
+    }
+    nbr[j + 1] = kn;
+    face[j + 1] = kf;
+  }
+  for (int i = b + 1; i < e; ++i)
+    if (nbr[i] == nbr[i - 1]) atomicOr(flag, 2);
+}
+
+__global__ void k_check_fields(const double* __restrict__ coeff, const int* __restrict__ neigh,
+                               int n_faces, const double* __restrict__ fl, int n_cells,
+                               int* __restrict__ flag) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n_faces && neigh[i] >= 0) {
+    double c = coeff[i];
+    if (!(c > 0.0) || !(c <= 1.7976931348623157e308)) atomicOr(flag, 1);
+  }
+  if (i < n_cells) {
+    double v = fl[i];
+    if (!(v >= 0.0 && v <= 1.0)) atomicOr(flag, 2);
+  }
+}
+
+__global__ void k_active(const double* __restrict__ fl, int n, int* __restrict__ active,
+                         int* __restrict__ parent) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  active[i] = fl[i] > 0.0 ? 1 : 0;
+  parent[i] = i;
+}
+
+__global__ void k_compact(const int* __restrict__ active, int n, int* __restrict__ cid,
+                          int* __restrict__ perm) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  if (active[i]) {
+    perm[cid[i]] = i;
+  } else {
+    cid[i] = -1;
+  }
+}
+
+__device__ __forceinline__ int ld(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int find_root(int* parent, int x) {
+  int p = ld(&parent[x]);
+  while (p != x) {
+    int gp = ld(&parent[p]);
+    if (gp != p) __hip_atomic_store(&parent[x], gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    x = p;
+    p = gp;
+  }
+  return x;
+}
+
+__global__ void k_union(const int* __restrict__ owner, const int* __restrict__ neigh, int n_faces,
+                        const int* __restrict__ active, int* parent) {
+  int f = blockIdx.x * kBlock + threadIdx.x;
+  if (f >= n_faces) return;
+  int a = owner[f], b = neigh[f];
+  if (b < 0 || !active[a] || !active[b]) return;
+  while (true) {
+    a = find_root(parent, a);
+    b = find_root(parent, b);
+    if (a == b) return;
+    if (a > b) { int t = a; a = b; b = t; }
+    int old = atomicCAS(&parent[b], b, a);
+    if (old == b) return;
+    b = old;
+  }
+}
+
+__global__ void k_components(const int* __restrict__ active, int n, int* parent,
+                             int* __restrict__ comp, int* __restrict__ is_pin) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  if (!active[i]) {
+    comp[i] = -1;
+    is_pin[i] = 0;
+    return;
+  }
+  int r = find_root(parent, i);
+  comp[i] = r;
+  is_pin[i] = (r == i) ? 1 : 0;
+}
+
+__global__ void k_row_counts(const int* __restrict__ perm, int n_active,
+                             const int* __restrict__ adj_ptr, const int* __restrict__ adj_nbr,
+                             const int* __restrict__ active, const int* __restrict__ is_pin,
+                             int* __restrict__ counts) {
+  int r = blockIdx.x * kBlock + threadIdx.x;
+  if (r >= n_active) return;
+  int c = perm[r];
+  int cnt = 1;
+  if (!is_pin[c]) {
+    for (int k = adj_ptr[c]; k < adj_ptr[c + 1]; ++k) {
+      int j = adj_nbr[k];
+      if (active[j] && !is_pin[j]) ++cnt;
+    }
+  }
+  counts[r] = cnt;
+}
+
+__global__ void k_fill_rows(const int* __restrict__ perm, int n_active,
+                            const int* __restrict__ adj_ptr, const int* __restrict__ adj_nbr,
+                            const int* __restrict__ adj_face, const int* __restrict__ active,
+                            const int* __restrict__ is_pin, const int* __restrict__ cid,
+                            const double* __restrict__ coeff, const int* __restrict__ rowptr,
+                            int* __restrict__ col, double* __restrict__ val,
+                            double* __restrict__ diag, int W, int* __restrict__ ell_col,
+                            double* __restrict__ ell_val, double* __restrict__ B) {
+  int r = blockIdx.x * kBlock + threadIdx.x;
+  if (r >= n_active) return;
+  int c = perm[r];
+  const bool pin = is_pin[c] != 0;
+  double d = 0.0;
+  for (int k = adj_ptr[c]; k < adj_ptr[c + 1]; ++k) {
+    int j = adj_nbr[k];
+    if (active[j]) d = d + coeff[adj_face[k]];
+  }
+  if (pin && d == 0.0) d = 1.0;
+  diag[r] = d;
+  B[r] = 1.0;
+  int p = rowptr[r];
+  int slot = 0;
+  bool diag_done = false;
+  if (!pin) {
+    for (int k = adj_ptr[c]; k < adj_ptr[c + 1]; ++k) {
+      int j = adj_nbr[k];
+      if (!active[j] || is_pin[j]) continue;
+      int cj = cid[j];
+      double v = -coeff[adj_face[k]];
+      if (!diag_done && cj > r) {
+        col[p] = r;
+        val[p] = d;
+        ++p;
+        diag_done = true;
+      }
+      col[p] = cj;
+      val[p] = v;
+      ++p;
+      ell_col[(size_t)slot * n_active + r] = cj;
+      ell_val[(size_t)slot * n_active + r] = v;
+      ++slot;
+    }
+  }
+  if (!diag_done) {
+    col[p] = r;
+    val[p] = d;
+  }
+  for (; slot < W; ++slot) {
+    ell_col[(size_t)slot * n_active + r] = r;
+    ell_val[(size_t)slot * n_active + r] = 0.0;
+  }
+}
+
+}  // namespace
+
+void build_topology(ppe_solver* s, const int32_t* owner, const int32_t* neigh) {
+  const int nf = s->n_faces, nc = s->n_cells;
+  int* o = s->owner.get<int>(nf);
+  int* nb = s->neigh.get<int>(nf);
+  if (nf) {
+    PPE_HIP(hipMemcpyAsync(o, owner, sizeof(int) * nf, hipMemcpyDeviceToDevice, s->stream));
+    PPE_HIP(hipMemcpyAsync(nb, neigh, sizeof(int) * nf, hipMemcpyDeviceToDevice, s->stream));
+  }
+  int* flag = s->flag.get<int>(1);
+  fill_int(s, flag, 0, 1);
+  if (nf) {
+    hipLaunchKernelGGL(k_check_faces, dim3(grid_for(nf)), dim3(kBlock), 0, s->stream, o, nb, nf, nc,
+                       flag);
+    PPE_LAUNCH_CHECK();
+  }
+  require(read_scalar(s, flag) == 0, PPE_ERR_ARG,
+          "face owner/neighbour out of range or equal");
+  int* deg = s->tmp_i[0].get<int>(nc + 1);
+  fill_int(s, deg, 0, nc + 1);
+  if (nf) {
+    hipLaunchKernelGGL(k_degree, dim3(grid_for(nf)), dim3(kBlock), 0, s->stream, o, nb, nf, deg);
+    PPE_LAUNCH_CHECK();
+  }
+  s->max_deg = reduce_max_int(s, deg, nc);
+  int* ptr = s->adj_ptr.get<int>(nc + 1);
+  int64_t nh = exclusive_scan(s, deg, ptr, nc);
+  int* cursor = s->tmp_i[1].get<int>(nc + 1);
+  PPE_HIP(hipMemcpyAsync(cursor, ptr, sizeof(int) * (nc + 1), hipMemcpyDeviceToDevice, s->stream));
+  int* an = s->adj_nbr.get<int>(nh);
+  int* af = s->adj_face.get<int>(nh);
+  if (nf) {
+    hipLaunchKernelGGL(k_adj_fill, dim3(grid_for(nf)), dim3(kBlock), 0, s->stream, o, nb, nf, cursor,
+                       an, af);
+    PPE_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(k_adj_sort, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, ptr, nc, an, af,
+                     flag);
+  PPE_LAUNCH_CHECK();
+  require(read_scalar(s, flag) == 0, PPE_ERR_ARG, "two faces join the same pair of cells");
+}
+
+void assemble_fine(ppe_solver* s, const double* coeff, const double* fl) {
+  const int nc = s->n_cells, nf = s->n_faces;
+  int* flag = s->flag.get<int>(1);
+  fill_int(s, flag, 0, 1);
+  int g = grid_for(nf > nc ? nf : nc);
+  hipLaunchKernelGGL(k_check_fields, dim3(g), dim3(kBlock), 0, s->stream, coeff, s->neigh.as<int>(),
+                     nf, fl, nc, flag);
+  PPE_LAUNCH_CHECK();
+  int bad = read_scalar(s, flag);
+  require(!(bad & 1), PPE_ERR_ARG, "face coefficient must be finite and > 0 on interior faces");
+  require(!(bad & 2), PPE_ERR_ARG, "liquid fraction must be finite and in [0, 1]");
+
+  int* active = s->active.get<int>(nc);
+  int* parent = s->parent.get<int>(nc);
+  int* cid = s->cid.get<int>(nc + 1);
+  hipLaunchKernelGGL(k_active, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, fl, nc, active, parent);
+  PPE_LAUNCH_CHECK();
+  const int na = (int)exclusive_scan(s, active, cid, nc);
+  s->n_active = na;
+  int* perm = s->perm.get<int>(na);
+  hipLaunchKernelGGL(k_compact, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, active, nc, cid, perm);
+  PPE_LAUNCH_CHECK();
+
+  int* comp = s->comp_full.get<int>(nc);
+  int* is_pin = s->tmp_i[2].get<int>(nc);
+  if (nf) {
+    hipLaunchKernelGGL(k_union, dim3(grid_for(nf)), dim3(kBlock), 0, s->stream, s->owner.as<int>(),
+                       s->neigh.as<int>(), nf, active, parent);
+    PPE_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(k_components, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, active, nc,
+                     parent, comp, is_pin);
+  PPE_LAUNCH_CHECK();
+  {
+    int* tmp = s->tmp_i[1].get<int>(nc + 1);
+    s->n_comp = (int)exclusive_scan(s, is_pin, tmp, nc);
+  }
+
+  if (s->levels.empty()) s->levels.resize(1);
+  s->nlev = 1;
+  Level& L = s->levels[0];
+  L.n = na;
+  L.A.n = L.A.m = na;
+  L.W = s->max_deg;
+  if (na == 0) {
+    L.A.nnz = 0;
+    return;
+  }
+  int* counts = s->tmp_i[0].get<int>(na + 1);
+  hipLaunchKernelGGL(k_row_counts, dim3(grid_for(na)), dim3(kBlock), 0, s->stream, perm, na,
+                     s->adj_ptr.as<int>(), s->adj_nbr.as<int>(), active, is_pin, counts);
+  PPE_LAUNCH_CHECK();
+  int* rowptr = L.A.rowptr.get<int>(na + 1);
+  L.A.nnz = exclusive_scan(s, counts, rowptr, na);
+  int* col = L.A.col.get<int>(L.A.nnz);
+  double* val = L.A.val.get<double>(L.A.nnz);
+  double* diag = L.diag.get<double>(na);
+  const int W = L.W > 0 ? L.W : 1;
+  int* ecol = L.ell_col.get<int>((size_t)W * na);
+  double* evl = L.ell_val.get<double>((size_t)W * na);
+  double* B = L.B.get<double>(na);
+  hipLaunchKernelGGL(k_fill_rows, dim3(grid_for(na)), dim3(kBlock), 0, s->stream, perm, na,
+                     s->adj_ptr.as<int>(), s->adj_nbr.as<int>(), s->adj_face.as<int>(), active,
+                     is_pin, cid, coeff, rowptr, col, val, diag, L.W, ecol, evl, B);
+  PPE_LAUNCH_CHECK();
+}
+
+}  // namespace ppe

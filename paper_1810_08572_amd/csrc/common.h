@@ -1,0 +1,299 @@
+// Shared infrastructure of the pressure-solve library: error handling,
+// grow-only device buffers, the solver state, and device primitives
+// (wave64 reductions and scans, the MIS-2 priority hash).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/ppe.h"
+
+namespace ppe {
+
+constexpr int kBlock = 256;   // threads per workgroup for streaming kernels
+constexpr int kWave = 64;     // CDNA wavefront width
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+  ppe_status status;
+  Error(ppe_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+#define PPE_HIP(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      if (e_ == hipErrorOutOfMemory)                                               \
+        throw ::ppe::Error(PPE_ERR_OOM, std::string(#expr) + ": out of memory");   \
+      throw ::ppe::Error(PPE_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    }                                                                              \
+  } while (0)
+
+#define PPE_LAUNCH_CHECK() PPE_HIP(hipGetLastError())
+
+inline void require(bool ok, ppe_status st, const std::string& msg) {
+  if (!ok) throw Error(st, msg);
+}
+
+// ---------------------------------------------------------------- buffers
+// Grow-only device allocation: reassembling with a new mask reuses memory.
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), cap(o.cap) { o.p = nullptr; o.cap = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; cap = o.cap; o.p = nullptr; o.cap = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  template <class T>
+  T* get(size_t n) {
+    size_t bytes = (n ? n : 1) * sizeof(T);
+    if (bytes > cap) {
+      release();
+      size_t want = bytes + bytes / 8;  // slack so a slowly growing size does not realloc each time
+      PPE_HIP(hipMalloc(&p, want));
+      cap = want;
+    }
+    return static_cast<T*>(p);
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// CSR matrix on the device (sorted columns; square levels store their diagonal).
+struct Csr {
+  int n = 0, m = 0;   // rows, columns
+  int64_t nnz = 0;
+  DevBuf rowptr, col, val, valf;  // valf: FP32 copy of val (mixed precision)
+  int* rp() const { return rowptr.as<int>(); }
+  int* ci() const { return col.as<int>(); }
+  double* v() const { return val.as<double>(); }
+  float* vf() const { return valf.as<float>(); }
+};
+
+struct Level {
+  int n = 0;
+  Csr A;                 // the level operator
+  DevBuf diag, diagf;    // diagonal (FP64, FP32)
+  // finest level: slot-major ELL of the off-diagonal part, padding = (row, 0)
+  int W = 0;
+  DevBuf ell_col, ell_val, ell_valf;
+  // transfer operators to level+1
+  Csr P, R;
+  int n_agg = 0;
+  DevBuf agg;            // int[n], aggregate id or -1
+  DevBuf B;              // near-null vector
+  double rho = 1.0;      // spectral bound of D^-1 A
+  double inv_theta = 0.0;
+  std::vector<double> c1, c2;  // Chebyshev steps 2..degree
+  int mis_rounds = 0;
+  Csr Pt, Q, AP;         // setup scratch: tentative P, A*P_tent, A*P
+  DevBuf strong, state, state2, m1, mis_root, agg1, agg_ptr, agg_mem, pt;
+  // coarsest level
+  bool dense = false;
+  DevBuf Ainv, Ainvf;
+  // V-cycle work vectors (FP64 and FP32 variants)
+  DevBuf x, b, r, d, x2, d2, t;
+  DevBuf xf, bf, rf, df, x2f, d2f;
+};
+
+// Device-resident PCG scalars.
+struct Scalars {
+  double rz, pq, alpha, beta, rr, rz_old, rzo, bb, tmp0, tmp1;
+  int flag;
+  int pad;
+};
+
+}  // namespace ppe
+
+struct ppe_solver {
+  ppe_options opt{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+  ppe_stats stats{};
+
+  // mesh topology
+  int n_cells = 0, n_faces = 0, max_deg = 0;
+  bool have_mesh = false;
+  ppe::DevBuf owner, neigh, adj_ptr, adj_nbr, adj_face;
+
+  // masking
+  bool assembled = false;
+  int n_active = 0, n_comp = 0;
+  ppe::DevBuf active, cid, perm, parent, comp_full;
+
+  std::vector<ppe::Level> levels;  // never shrunk, so buffers are reused
+  int nlev = 0;                    // levels in use
+
+  // solve workspace
+  ppe::DevBuf vx, vr, vz, vp, vq, vzold, vb;
+  ppe::DevBuf scal, partial, counter, flag;
+  ppe::DevBuf tmp_i[4], tmp_d[2], tmp_l[2];
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+  // dominant-kernel measurement (event pairs around fine-level smoothing steps)
+  bool prof = false;
+  std::vector<hipEvent_t> prof_ev;
+  std::vector<double> prof_pending;  // bytes of each recorded pair
+  double prof_ms = 0.0, prof_bytes = 0.0;
+  int64_t prof_launches = 0;
+};
+
+namespace ppe {
+
+// ---------------------------------------------------------------- device helpers
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+  // MurmurHash3 32-bit finaliser (Appleby)
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+
+__host__ __device__ __forceinline__ uint32_t level_salt(int level) {
+  return static_cast<uint32_t>(level) * 0x9E3779B9u;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+  return v;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    T w = __shfl_down(v, o, kWave);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
+// Deterministic block sum (fixed tree).  Result valid in thread 0.
+template <int BS, class T>
+__device__ __forceinline__ T block_sum(T v) {
+  __shared__ T sh[BS / kWave];
+  v = wave_sum(v);
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  T s = 0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < BS / kWave; ++i) s += sh[i];
+  }
+  __syncthreads();
+  return s;
+}
+
+template <int BS, class T>
+__device__ __forceinline__ T block_max(T v) {
+  __shared__ T sh[BS / kWave];
+  v = wave_max(v);
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  T s = sh[0];
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 1; i < BS / kWave; ++i) s = sh[i] > s ? sh[i] : s;
+  }
+  __syncthreads();
+  return s;
+}
+
+// Grid-wide deterministic sum of one value per thread, finished by the last
+// block to arrive: partials are added in block order whatever the arrival
+// order, so the result is bitwise reproducible.  Returns true in thread 0 of
+// the last block, with *out written.  counter must start at 0 (it is reset).
+template <int BS, int NV>
+__device__ __forceinline__ bool grid_sum(const double (&v)[NV], double* partials,
+                                         unsigned int* counter, double* out) {
+  __shared__ bool last;
+  double s[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) s[k] = block_sum<BS>(v[k]);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) partials[(size_t)k * gridDim.x + blockIdx.x] = s[k];
+    __threadfence();
+    unsigned int t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double a = 0.0;
+    for (unsigned int b = threadIdx.x; b < gridDim.x; b += BS)
+      a += __hip_atomic_load(&partials[(size_t)k * gridDim.x + b], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    acc[k] = block_sum<BS>(a);
+  }
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) out[k] = acc[k];
+    *counter = 0u;
+  }
+  return threadIdx.x == 0;
+}
+
+inline int grid_for(int64_t n, int bs = kBlock) {
+  int64_t g = (n + bs - 1) / bs;
+  return static_cast<int>(g < 1 ? 1 : g);
+}
+
+// ---------------------------------------------------------------- host-side primitives (prims.hip)
+// Exclusive scan of int32 counts into out[0..n] (out[n] = total).  Returns
+// the total; throws PPE_ERR_INTERNAL if it does not fit int32.
+int64_t exclusive_scan(ppe_solver* s, const int* in, int* out, int n);
+// Max of an int array.
+int reduce_max_int(ppe_solver* s, const int* in, int n);
+// Copy one value from device to host on the solver stream (synchronises).
+template <class T>
+T read_scalar(ppe_solver* s, const T* dptr) {
+  T v{};
+  PPE_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, s->stream));
+  PPE_HIP(hipStreamSynchronize(s->stream));
+  return v;
+}
+void fill_int(ppe_solver* s, int* p, int v, int64_t n);
+void fill_double(ppe_solver* s, double* p, double v, int64_t n);
+
+// assemble.hip
+void build_topology(ppe_solver* s, const int32_t* owner, const int32_t* neigh);
+void assemble_fine(ppe_solver* s, const double* coeff, const double* fl);
+
+// amg.hip
+void build_hierarchy(ppe_solver* s);
+
+// solve.hip
+void spmv(ppe_solver* s, const Level& L, const double* x, double* y);
+void vcycle(ppe_solver* s, int level, const double* b, double* x);
+ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p, int use_x0);
+void prepare_solve_levels(ppe_solver* s);
+void profile_harvest(ppe_solver* s);
+void profile_enable(ppe_solver* s, bool on);
+
+}  // namespace ppe

@@ -1,0 +1,534 @@
+// Solve phase: sparse matrix-vector kernels with fused epilogues, the
+// Chebyshev smoother, the V-cycle and preconditioned conjugate gradients
+// (the multigrid-preconditioned Krylov solve of section 2.5).
+//
+// Layout: the finest operator is applied from a slot-major ELL copy of its
+// off-diagonal part (one thread per row, every slot load coalesced) plus the
+// diagonal; coarse operators, P and R are CSR, applied by groups of LPR
+// lanes per row with a shuffle reduction inside the group.  All reductions
+// are deterministic (fixed trees, partials summed in block order).
+#include "common.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace ppe {
+namespace {
+
+enum Epi : int {
+  E_SPMV = 0,   // y = A x
+  E_RESID = 1,  // y = b - A x
+  E_CHEB = 2,   // r = (b - A x)/diag; d = c1 d + c2 r; y = x + d
+  E_DOT = 3,    // y = A x and sum x.y
+};
+
+template <int EPI>
+__device__ __forceinline__ double epilogue(int i, double ax, const double* __restrict__ x,
+                                           const double* __restrict__ b,
+                                           const double* __restrict__ diag, double* __restrict__ d,
+                                           double c1, double c2, double* __restrict__ y) {
+  if (EPI == E_SPMV) {
+    y[i] = ax;
+    return 0.0;
+  } else if (EPI == E_RESID) {
+    y[i] = b[i] - ax;
+    return 0.0;
+  } else if (EPI == E_CHEB) {
+    const double r = (b[i] - ax) / diag[i];
+    const double dn = (c1 == 0.0 ? 0.0 : c1 * d[i]) + c2 * r;
+    d[i] = dn;
+    y[i] = x[i] + dn;
+    return 0.0;
+  } else {
+    y[i] = ax;
+    return x[i] * ax;
+  }
+}
+
+// ---- finest level: ELL, one thread per row
+template <int EPI>
+__global__ void __launch_bounds__(kBlock) k_ell(int n, int W, const int* __restrict__ ecol,
+                                                const double* __restrict__ eval,
+                                                const double* __restrict__ diag,
+                                                const double* __restrict__ x,
+                                                const double* __restrict__ b, double* __restrict__ d,
+                                                double c1, double c2, double* __restrict__ y,
+                                                double* partials, unsigned int* counter,
+                                                double* out) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  double dot = 0.0;
+  if (i < n) {
+    double s = diag[i] * x[i];
+    for (int k = 0; k < W; ++k) {
+      const size_t e = (size_t)k * n + i;
+      s = s + eval[e] * x[ecol[e]];
+    }
+    dot = epilogue<EPI>(i, s, x, b, diag, d, c1, c2, y);
+  }
+  if (EPI == E_DOT) {
+    double v[1] = {dot};
+    grid_sum<kBlock, 1>(v, partials, counter, out);
+  }
+}
+
+// ---- CSR, LPR lanes per row
+template <int EPI, int LPR>
+__global__ void __launch_bounds__(kBlock) k_csr(int n, const int* __restrict__ rp,
+                                                const int* __restrict__ ci,
+                                                const double* __restrict__ v,
+                                                const double* __restrict__ diag,
+                                                const double* __restrict__ x,
+                                                const double* __restrict__ b, double* __restrict__ d,
+                                                double c1, double c2, double* __restrict__ y,
+                                                double* partials, unsigned int* counter,
+                                                double* out) {
+  const int g = (blockIdx.x * kBlock + threadIdx.x) / LPR;
+  const int lane = threadIdx.x % LPR;
+  double s = 0.0;
+  if (g < n) {
+    for (int k = rp[g] + lane; k < rp[g + 1]; k += LPR) s = s + v[k] * x[ci[k]];
+  }
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_down(s, o, LPR);
+  double dot = 0.0;
+  if (g < n && lane == 0) dot = epilogue<EPI>(g, s, x, b, diag, d, c1, c2, y);
+  if (EPI == E_DOT) {
+    double vv[1] = {dot};
+    grid_sum<kBlock, 1>(vv, partials, counter, out);
+  }
+}
+
+// y (+)= P x for a rectangular CSR (prolongation adds into y).
+template <int LPR, bool ADD>
+__global__ void __launch_bounds__(kBlock) k_csr_rect(int n, const int* __restrict__ rp,
+                                                     const int* __restrict__ ci,
+                                                     const double* __restrict__ v,
+                                                     const double* __restrict__ x,
+                                                     double* __restrict__ y) {
+  const int g = (blockIdx.x * kBlock + threadIdx.x) / LPR;
+  const int lane = threadIdx.x % LPR;
+  double s = 0.0;
+  if (g < n) {
+    for (int k = rp[g] + lane; k < rp[g + 1]; k += LPR) s = s + v[k] * x[ci[k]];
+  }
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_down(s, o, LPR);
+  if (g < n && lane == 0) y[g] = ADD ? y[g] + s : s;
+}
+
+// First Chebyshev step from a zero guess: d = b / (theta diag); x = d.
+__global__ void k_cheb_first(int n, const double* __restrict__ b, const double* __restrict__ diag,
+                             double inv_theta, double* __restrict__ d, double* __restrict__ x) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double v = inv_theta * (b[i] / diag[i]);
+  d[i] = v;
+  x[i] = v;
+}
+
+// Dense coarsest solve x = Ainv b (Ainv symmetric, row i read as column i).
+__global__ void k_dense_gemv(int n, const double* __restrict__ Ainv, const double* __restrict__ b,
+                             double* __restrict__ x) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int j = 0; j < n; ++j) s = s + Ainv[(size_t)j * n + i] * b[j];
+  x[i] = s;
+}
+
+// ---- PCG vector kernels (device-resident scalars)
+__global__ void k_gather_rhs(int na, const int* __restrict__ perm, const int* __restrict__ comp,
+                             const double* __restrict__ rhs, double* __restrict__ b,
+                             double* partials, unsigned int* counter, double* out) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  double v = 0.0;
+  if (i < na) {
+    int c = perm[i];
+    v = comp[c] == c ? 0.0 : rhs[c];
+    b[i] = v;
+  }
+  double s[1] = {v * v};
+  grid_sum<kBlock, 1>(s, partials, counter, out);
+}
+
+__global__ void k_gather_x0(int na, const int* __restrict__ perm, const int* __restrict__ comp,
+                            const double* __restrict__ p, double* __restrict__ x) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= na) return;
+  int c = perm[i];
+  x[i] = comp[c] == c ? 0.0 : p[c];
+}
+
+__global__ void k_scatter(int nc, const int* __restrict__ cid, const int* __restrict__ comp,
+                          const double* __restrict__ x, double* __restrict__ p) {
+  int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= nc) return;
+  int k = cid[c];
+  p[c] = (k < 0 || comp[c] == c) ? 0.0 : x[k];
+}
+
+__global__ void k_norm2(int n, const double* __restrict__ a, double* partials,
+                        unsigned int* counter, double* out) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  double v = i < n ? a[i] : 0.0;
+  double s[1] = {v * v};
+  grid_sum<kBlock, 1>(s, partials, counter, out);
+}
+
+// sums r.z and r.z_old (the latter for the flexible beta).
+__global__ void k_dot2(int n, const double* __restrict__ r, const double* __restrict__ z,
+                       const double* __restrict__ zold, double* partials, unsigned int* counter,
+                       double* out) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  double s[2] = {0.0, 0.0};
+  if (i < n) {
+    s[0] = r[i] * z[i];
+    if (zold) s[1] = r[i] * zold[i];
+  }
+  grid_sum<kBlock, 2>(s, partials, counter, out);
+}
+
+// alpha = rz / pq; x += alpha p; r -= alpha q; sum r.r
+__global__ void k_update_xr(int n, const double* __restrict__ rz, const double* __restrict__ pq,
+                            const double* __restrict__ p, const double* __restrict__ q,
+                            double* __restrict__ x, double* __restrict__ r, double* partials,
+                            unsigned int* counter, double* out) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  const double alpha = *rz / *pq;
+  double v = 0.0;
+  if (i < n) {
+    x[i] = x[i] + alpha * p[i];
+    v = r[i] - alpha * q[i];
+    r[i] = v;
+  }
+  double s[1] = {v * v};
+  grid_sum<kBlock, 1>(s, partials, counter, out);
+}
+
+// beta = (rz_new - rzold_new) / rz_prev; p = z + beta p
+__global__ void k_update_p(int n, const double* __restrict__ rzn, const double* __restrict__ rzp,
+                           int flexible, const double* __restrict__ z, double* __restrict__ p) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double beta = (flexible ? (rzn[0] - rzn[1]) : rzn[0]) / rzp[0];
+  p[i] = z[i] + beta * p[i];
+}
+
+__global__ void k_copy(int n, const double* __restrict__ a, double* __restrict__ b) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+int lanes_for(const Csr& A) {
+  const double mean = A.n ? (double)A.nnz / A.n : 1.0;
+  int lpr = 4;
+  while (lpr < 64 && lpr < mean) lpr *= 2;
+  return lpr;
+}
+
+struct RedBuf {
+  double* partials;
+  unsigned int* counter;
+};
+
+RedBuf red(ppe_solver* s, int grid) {
+  return RedBuf{s->partial.get<double>((size_t)grid * 4), s->counter.get<unsigned int>(1)};
+}
+
+constexpr size_t kProfPairs = 256;
+
+template <int EPI>
+void apply_op(ppe_solver* s, const Level& L, const double* x, const double* b, double* d, double c1,
+              double c2, double* y, double* out) {
+  const int n = L.n;
+  if (n == 0) return;
+  if (&L == &s->levels[0]) {
+    const int g = grid_for(n);
+    RedBuf rb = red(s, g);
+    const bool prof = s->prof && EPI == E_CHEB;
+    if (prof) {
+      if (s->prof_pending.size() == kProfPairs) profile_harvest(s);
+      const size_t k = s->prof_pending.size();
+      PPE_HIP(hipEventRecord(s->prof_ev[2 * k], s->stream));
+    }
+    hipLaunchKernelGGL(k_ell<EPI>, dim3(g), dim3(kBlock), 0, s->stream, n, L.W,
+                       L.ell_col.as<int>(), L.ell_val.as<double>(), L.diag.as<double>(), x, b, d,
+                       c1, c2, y, rb.partials, rb.counter, out);
+    PPE_LAUNCH_CHECK();
+    if (prof) {
+      const size_t k = s->prof_pending.size();
+      PPE_HIP(hipEventRecord(s->prof_ev[2 * k + 1], s->stream));
+      const double off = (double)(L.A.nnz - n);
+      const double vecs = (c1 != 0.0) ? 6.0 : 5.0;  // diag, x_in, b, x_out, d out (+ d in)
+      s->prof_pending.push_back(off * 12.0 + vecs * 8.0 * n);
+    }
+    return;
+  }
+  const int lpr = lanes_for(L.A);
+  const int g = grid_for((int64_t)n * lpr);
+  RedBuf rb = red(s, g);
+#define PPE_CSR(LL)                                                                          \
+  hipLaunchKernelGGL((k_csr<EPI, LL>), dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(),     \
+                     L.A.ci(), L.A.v(), L.diag.as<double>(), x, b, d, c1, c2, y, rb.partials, \
+                     rb.counter, out)
+  switch (lpr) {
+    case 4: PPE_CSR(4); break;
+    case 8: PPE_CSR(8); break;
+    case 16: PPE_CSR(16); break;
+    case 32: PPE_CSR(32); break;
+    default: PPE_CSR(64); break;
+  }
+#undef PPE_CSR
+  PPE_LAUNCH_CHECK();
+}
+
+template <bool ADD>
+void apply_rect(ppe_solver* s, const Csr& M, const double* x, double* y) {
+  if (M.n == 0) return;
+  const int lpr = lanes_for(M);
+  const int g = grid_for((int64_t)M.n * lpr);
+#define PPE_RECT(LL)                                                                        \
+  hipLaunchKernelGGL((k_csr_rect<LL, ADD>), dim3(g), dim3(kBlock), 0, s->stream, M.n, M.rp(), \
+                     M.ci(), M.v(), x, y)
+  switch (lpr) {
+    case 4: PPE_RECT(4); break;
+    case 8: PPE_RECT(8); break;
+    case 16: PPE_RECT(16); break;
+    case 32: PPE_RECT(32); break;
+    default: PPE_RECT(64); break;
+  }
+#undef PPE_RECT
+  PPE_LAUNCH_CHECK();
+}
+
+// Chebyshev smoothing of A x = b.  x_in == nullptr: zero initial guess.
+// The result is written to x_out; xa/xb are ping-pong buffers distinct from
+// x_in and x_out.
+void smooth(ppe_solver* s, Level& L, const double* b, const double* x_in, double* x_out, double* xa,
+            double* xb) {
+  const int n = L.n;
+  const int deg = 1 + (int)L.c1.size();
+  double* d = L.d.as<double>();
+  const double* cur = x_in;
+  for (int step = 1; step <= deg; ++step) {
+    double* dst = step == deg ? x_out : ((step % 2) ? xa : xb);
+    if (step == 1 && cur == nullptr) {
+      hipLaunchKernelGGL(k_cheb_first, dim3(grid_for(n)), dim3(kBlock), 0, s->stream, n, b,
+                         L.diag.as<double>(), L.inv_theta, d, dst);
+      PPE_LAUNCH_CHECK();
+    } else if (step == 1) {
+      apply_op<E_CHEB>(s, L, cur, b, d, 0.0, L.inv_theta, dst, nullptr);
+    } else {
+      apply_op<E_CHEB>(s, L, cur, b, d, L.c1[step - 2], L.c2[step - 2], dst, nullptr);
+    }
+    cur = dst;
+  }
+}
+
+}  // namespace
+
+void profile_harvest(ppe_solver* s) {
+  const size_t k = s->prof_pending.size();
+  if (k == 0) return;
+  PPE_HIP(hipEventSynchronize(s->prof_ev[2 * k - 1]));
+  for (size_t i = 0; i < k; ++i) {
+    float ms = 0.f;
+    PPE_HIP(hipEventElapsedTime(&ms, s->prof_ev[2 * i], s->prof_ev[2 * i + 1]));
+    s->prof_ms += ms;
+    s->prof_bytes += s->prof_pending[i];
+  }
+  s->prof_launches += (int64_t)k;
+  s->prof_pending.clear();
+}
+
+void profile_enable(ppe_solver* s, bool on) {
+  if (on && s->prof_ev.empty()) {
+    s->prof_ev.resize(2 * kProfPairs, nullptr);
+    for (auto& e : s->prof_ev) PPE_HIP(hipEventCreate(&e));
+  }
+  profile_harvest(s);
+  s->prof = on;
+  if (on) {
+    s->prof_ms = 0.0;
+    s->prof_bytes = 0.0;
+    s->prof_launches = 0;
+  }
+}
+
+void spmv(ppe_solver* s, const Level& L, const double* x, double* y) {
+  apply_op<E_SPMV>(s, L, x, nullptr, nullptr, 0.0, 0.0, y, nullptr);
+}
+
+void prepare_solve_levels(ppe_solver* s) {
+  for (int l = 0; l < s->nlev; ++l) {
+    Level& L = s->levels[l];
+    const int n = L.n > 0 ? L.n : 1;
+    L.x.get<double>(n);
+    L.b.get<double>(n);
+    L.r.get<double>(n);
+    L.d.get<double>(n);
+    L.x2.get<double>(n);
+    L.d2.get<double>(n);
+    L.t.get<double>(n);
+    const double lmax = L.rho, lmin = L.rho / s->opt.cheb_ratio;
+    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+    const double sigma = theta / delta;
+    double rho_prev = 1.0 / sigma;
+    L.inv_theta = 1.0 / theta;
+    L.c1.clear();
+    L.c2.clear();
+    for (int j = 2; j <= s->opt.cheb_degree; ++j) {
+      const double rho_j = 1.0 / (2.0 * sigma - rho_prev);
+      L.c1.push_back(rho_j * rho_prev);
+      L.c2.push_back(2.0 * rho_j / delta);
+      rho_prev = rho_j;
+    }
+  }
+}
+
+// One V-cycle with zero initial guess: x = M b on level l.
+void vcycle(ppe_solver* s, int l, const double* b, double* x) {
+  Level& L = s->levels[l];
+  const int n = L.n;
+  if (n == 0) return;
+  double* xa = L.x2.as<double>();
+  double* xb = L.d2.as<double>();
+  if (l == s->nlev - 1) {
+    if (L.dense) {
+      hipLaunchKernelGGL(k_dense_gemv, dim3(grid_for(n)), dim3(kBlock), 0, s->stream, n,
+                         L.Ainv.as<double>(), b, x);
+      PPE_LAUNCH_CHECK();
+    } else {
+      double* t = L.r.as<double>();
+      smooth(s, L, b, nullptr, t, xa, xb);
+      smooth(s, L, b, t, x, xa, xb);
+    }
+    return;
+  }
+  Level& C = s->levels[l + 1];
+  double* x1 = L.t.as<double>();  // pre-smoothed iterate, corrected in place
+  double* r = L.r.as<double>();
+  smooth(s, L, b, nullptr, x1, xa, xb);
+  apply_op<E_RESID>(s, L, x1, b, nullptr, 0.0, 0.0, r, nullptr);
+  apply_rect<false>(s, L.R, r, C.b.as<double>());
+  vcycle(s, l + 1, C.b.as<double>(), C.x.as<double>());
+  apply_rect<true>(s, L.P, C.x.as<double>(), x1);
+  smooth(s, L, b, x1, x, xa, xb);
+}
+
+ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0) {
+  const int na = s->n_active, nc = s->n_cells;
+  ppe_stats& st = s->stats;
+  st.iterations = 0;
+  st.rel_residual = 0.0;
+  if (na == 0) {
+    fill_double(s, p_out, 0.0, nc);
+    PPE_HIP(hipStreamSynchronize(s->stream));
+    return PPE_OK;
+  }
+  Level& L0 = s->levels[0];
+  const int g = grid_for(na);
+  double* x = s->vx.get<double>(na);
+  double* r = s->vr.get<double>(na);
+  double* z = s->vz.get<double>(na);
+  double* p = s->vp.get<double>(na);
+  double* q = s->vq.get<double>(na);
+  double* b = s->vb.get<double>(na);
+  const bool flexible = s->opt.precision == PPE_MIXED;
+  double* zold = flexible ? s->vzold.get<double>(na) : nullptr;
+  // scalars: [0] bb, [1] rr, [2] pq, [3,4] rz even (rz, rzold), [5,6] rz odd, [7] rtrue
+  double* sc = s->scal.get<double>(16);
+  RedBuf rb = red(s, g);
+  const int* perm = s->perm.as<int>();
+  const int* comp = s->comp_full.as<int>();
+  hipLaunchKernelGGL(k_gather_rhs, dim3(g), dim3(kBlock), 0, s->stream, na, perm, comp, rhs, b,
+                     rb.partials, rb.counter, sc + 0);
+  PPE_LAUNCH_CHECK();
+  if (use_x0) {
+    hipLaunchKernelGGL(k_gather_x0, dim3(g), dim3(kBlock), 0, s->stream, na, perm, comp, p_out, x);
+    PPE_LAUNCH_CHECK();
+    apply_op<E_RESID>(s, L0, x, b, nullptr, 0.0, 0.0, r, nullptr);
+  } else {
+    fill_double(s, x, 0.0, na);
+    hipLaunchKernelGGL(k_copy, dim3(g), dim3(kBlock), 0, s->stream, na, b, r);
+    PPE_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(k_norm2, dim3(g), dim3(kBlock), 0, s->stream, na, r, rb.partials, rb.counter,
+                     sc + 1);
+  PPE_LAUNCH_CHECK();
+  double h[8];
+  PPE_HIP(hipMemcpyAsync(h, sc, sizeof(double) * 2, hipMemcpyDeviceToHost, s->stream));
+  PPE_HIP(hipStreamSynchronize(s->stream));
+  const double bb = h[0];
+  const double tol2 = s->opt.rtol * s->opt.rtol * bb;
+  auto finish = [&](ppe_status status, double rr_true) {
+    hipLaunchKernelGGL(k_scatter, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc,
+                       s->cid.as<int>(), comp, x, p_out);
+    PPE_LAUNCH_CHECK();
+    PPE_HIP(hipStreamSynchronize(s->stream));
+    profile_harvest(s);
+    st.rel_residual = bb > 0 ? std::sqrt(rr_true / bb) : std::sqrt(rr_true);
+    return status;
+  };
+  if (bb == 0.0) {
+    fill_double(s, x, 0.0, na);
+    return finish(PPE_OK, 0.0);
+  }
+  if (h[1] <= tol2) return finish(PPE_OK, h[1]);
+
+  vcycle(s, 0, r, z);
+  hipLaunchKernelGGL(k_dot2, dim3(g), dim3(kBlock), 0, s->stream, na, r, z, nullptr, rb.partials,
+                     rb.counter, sc + 3);
+  PPE_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_copy, dim3(g), dim3(kBlock), 0, s->stream, na, z, p);
+  PPE_LAUNCH_CHECK();
+  int slot = 0;  // rz of the current iteration at sc[3 + 2*slot]
+  const int max_iter = s->opt.max_iter;
+  for (int it = 1; it <= max_iter; ++it) {
+    double* rzc = sc + 3 + 2 * slot;
+    apply_op<E_DOT>(s, L0, p, nullptr, nullptr, 0.0, 0.0, q, sc + 2);
+    hipLaunchKernelGGL(k_update_xr, dim3(g), dim3(kBlock), 0, s->stream, na, rzc, sc + 2, p, q, x, r,
+                       rb.partials, rb.counter, sc + 1);
+    PPE_LAUNCH_CHECK();
+    PPE_HIP(hipMemcpyAsync(h, sc, sizeof(double) * 7, hipMemcpyDeviceToHost, s->stream));
+    PPE_HIP(hipStreamSynchronize(s->stream));
+    st.iterations = it;
+    const double pq = h[2], rr = h[1], rz = h[3 + 2 * slot];
+    if (!(pq > 0.0) || !std::isfinite(rr) || !(rz > 0.0)) {
+      finish(PPE_ERR_BREAKDOWN, rr);
+      return PPE_ERR_BREAKDOWN;
+    }
+    if (rr <= tol2) {
+      apply_op<E_RESID>(s, L0, x, b, nullptr, 0.0, 0.0, q, nullptr);
+      hipLaunchKernelGGL(k_norm2, dim3(g), dim3(kBlock), 0, s->stream, na, q, rb.partials, rb.counter,
+                         sc + 7);
+      PPE_LAUNCH_CHECK();
+      double rt = read_scalar(s, sc + 7);
+      if (rt <= tol2) return finish(PPE_OK, rt);
+      hipLaunchKernelGGL(k_copy, dim3(g), dim3(kBlock), 0, s->stream, na, q, r);
+      PPE_LAUNCH_CHECK();
+    }
+    if (it == max_iter) break;
+    if (flexible) {
+      hipLaunchKernelGGL(k_copy, dim3(g), dim3(kBlock), 0, s->stream, na, z, zold);
+      PPE_LAUNCH_CHECK();
+    }
+    vcycle(s, 0, r, z);
+    double* rzn = sc + 3 + 2 * (1 - slot);
+    hipLaunchKernelGGL(k_dot2, dim3(g), dim3(kBlock), 0, s->stream, na, r, z, zold, rb.partials,
+                       rb.counter, rzn);
+    PPE_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_update_p, dim3(g), dim3(kBlock), 0, s->stream, na, rzn, rzc,
+                       flexible ? 1 : 0, z, p);
+    PPE_LAUNCH_CHECK();
+    slot = 1 - slot;
+  }
+  apply_op<E_RESID>(s, L0, x, b, nullptr, 0.0, 0.0, q, nullptr);
+  hipLaunchKernelGGL(k_norm2, dim3(g), dim3(kBlock), 0, s->stream, na, q, rb.partials, rb.counter,
+                     sc + 7);
+  PPE_LAUNCH_CHECK();
+  double rt = read_scalar(s, sc + 7);
+  return finish(PPE_NOT_CONVERGED, rt);
+}
+
+}  // namespace ppe

@@ -1,0 +1,69 @@
+"""CPU checks of the C-ABI boundary: the library is built, loads, and
+exports every function include/ppe.h declares; the binding mirrors them."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1810_08572_amd as ppe
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "ppe.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ppe_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding():
+    assert set(_declared()) == set(ppe.SYMBOLS)
+
+
+def test_library_exports_every_symbol():
+    lib = ppe.load_library()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_host_only_calls():
+    lib = ppe.load_library()
+    o = ppe.ppe_default_options()
+    assert o.rtol == 1e-10 and o.max_iter == 500 and o.cheb_degree == 2
+    assert o.coarse_max == 256 and o.theta == 0.08
+    assert ppe.ppe_status_string(ppe.PPE_ERR_STATE) == "call out of order"
+    assert ppe.ppe_status_string(ppe.PPE_NOT_CONVERGED) == "not converged"
+    # NULL solver handles are rejected without touching a device
+    assert lib.ppe_assemble(None, None, None) == ppe.PPE_ERR_ARG
+    assert lib.ppe_solve(None, None, None, 0, None) == ppe.PPE_ERR_ARG
+    st = ppe.ppe_stats()
+    assert lib.ppe_get_stats(None, ctypes.byref(st)) == ppe.PPE_ERR_ARG
+    lib.ppe_destroy(None)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Sizes and field offsets of the binding's structs equal what a C
+    compiler makes of the header."""
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = []
+    for cname, cls in (("ppe_options", ppe.ppe_options), ("ppe_stats", ppe.ppe_stats)):
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ppe.h"\nint main(void){'
+                   + "".join(lines) + "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = dict(line.rsplit(" ", 1) for line in out if line)
+    for cname, cls in (("ppe_options", ppe.ppe_options), ("ppe_stats", ppe.ppe_stats)):
+        assert int(got[f"{cname} size"]) == ctypes.sizeof(cls)
+        for f, _ in cls._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(cls, f).offset, (cname, f)

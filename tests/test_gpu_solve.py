@@ -1,0 +1,87 @@
+"""End-to-end GPU parity of the pressure solve: relative residual <= 1e-10
+(recomputed in FP64 by the oracle from the GPU's pressure) and relative L2
+error <= 1e-9 against an exact reference (dense Cholesky / SuperLU)."""
+import numpy as np
+import pytest
+
+from oracle import amg, assembly, direct, pcg
+from synth import box_mesh, face_coeff
+from tests.gpu_util import case, gpu_solver, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _solve(m, f, c, b, x0=None, **opts):
+    import torch
+
+    s = gpu_solver(m, f, c, **opts)
+    res = s.solve(to_dev(b, torch.float64),
+                  x0=None if x0 is None else to_dev(x0, torch.float64))
+    return s, res
+
+
+@pytest.mark.parametrize("x0kind", ["zero", "random", "exact"])
+def test_c1_against_dense(x0kind):
+    m, f, c, b = case()
+    sy = assembly.masked_system(m.n_cells, m.owner, m.neigh, c, f)
+    pref = direct.solve_dense(sy, b)
+    x0 = {"zero": None, "random": np.random.default_rng(5).normal(size=m.n_cells) * 1e3,
+          "exact": pref}[x0kind]
+    s, res = _solve(m, f, c, b, x0)
+    p = res.p.cpu().numpy()
+    assert res.status == 0
+    assert assembly.relative_residual(sy, b, p) <= 1e-10
+    assert abs(res.stats["rel_residual"] - assembly.relative_residual(sy, b, p)) <= 1e-11
+    assert np.linalg.norm(p - pref) <= 1e-9 * np.linalg.norm(pref)
+    assert np.all(p[~sy.active] == 0) and np.all(p[sy.pins] == 0)
+    if x0kind == "zero":
+        H = amg.build_hierarchy(sy.A)
+        ref = pcg.pcg(sy.A, assembly.pinned_rhs(sy, b), M=lambda r: amg.vcycle(H, r), rtol=1e-10)
+        assert abs(res.stats["iterations"] - ref.iterations) <= 1
+
+
+@pytest.mark.parametrize("shape,fl,seed", [((32, 32, 32), "front", 2), ((29, 17, 23), "front", 9),
+                                           ((24, 24, 24), "ones", 0)])
+def test_ragged_against_superlu(shape, fl, seed):
+    m, f, c, b = case(shape=shape, fl=fl, fl_seed=seed, seed=seed)
+    sy = assembly.masked_system(m.n_cells, m.owner, m.neigh, c, f)
+    pref = direct.solve_sparse(sy, b)
+    s, res = _solve(m, f, c, b)
+    p = res.p.cpu().numpy()
+    assert assembly.relative_residual(sy, b, p) <= 1e-10
+    assert np.linalg.norm(p - pref) <= 1e-9 * np.linalg.norm(pref)
+
+
+def test_pockets_and_uncentred_rhs():
+    """Several pockets, b not balanced: each pin absorbs its pocket's
+    imbalance; the result is still the unique pinned solution."""
+    m = box_mesh((18, 14, 10), jitter=0.1, seed=1)
+    x = m.cell_centre
+    f = np.where((np.abs(x[:, 0] - 0.5) < 0.08) | (np.abs(x[:, 1] - 0.4) < 0.06), 0.0, 0.7)
+    c = face_coeff(m, 2400.0)
+    b = np.random.default_rng(2).uniform(-1, 1, m.n_cells)
+    sy = assembly.masked_system(m.n_cells, m.owner, m.neigh, c, f)
+    assert len(sy.pins) == 4
+    pref = direct.solve_sparse(sy, b)
+    s, res = _solve(m, f, c, b)
+    p = res.p.cpu().numpy()
+    assert assembly.relative_residual(sy, b, p) <= 1e-10
+    assert np.linalg.norm(p - pref) <= 1e-9 * np.linalg.norm(pref)
+
+
+def test_not_converged_and_determinism():
+    import torch
+
+    import paper_1810_08572_amd as ppe
+
+    m, f, c, b = case(shape=(20, 20, 20), fl="front")
+    s = gpu_solver(m, f, c, max_iter=2)
+    with pytest.raises(ppe.PpeError) as e:
+        s.solve(to_dev(b, torch.float64))
+    assert e.value.status == ppe.PPE_NOT_CONVERGED
+    r = s.solve(to_dev(b, torch.float64), allow_not_converged=True)
+    assert r.status == ppe.PPE_NOT_CONVERGED and r.stats["iterations"] == 2
+    s2 = gpu_solver(m, f, c)
+    p1 = s2.solve(to_dev(b, torch.float64)).p.cpu().numpy()
+    p2 = s2.solve(to_dev(b, torch.float64)).p.cpu().numpy()
+    assert np.array_equal(p1, p2)
