@@ -14,7 +14,7 @@
 //   rho        Gershgorin bound on the finest level, 1.1 x a 15-step power
 //              estimate of lambda_max(D^-1 A) on coarse levels
 //   P          P_tent - (4 / (3 rho)) D^-1 A P_tent;  R = P^T;  A_c = R (A P)
-//   coarsest   at most coarse_max rows: dense Cholesky, explicit inverse
+//   coarsest   at most coarse_max rows: explicit inverse (Gauss-Jordan)
 //
 // Every product is formed row by row in a fixed order (Gustavson order: the
 // entries of the left factor's row in ascending column order), so the setup
@@ -229,36 +229,6 @@ __global__ void k_gershgorin(int n, const int* __restrict__ rp, const double* __
   if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(r));
 }
 
-__global__ void k_power_init(int n, uint32_t salt, double* __restrict__ x, double* partials,
-                             unsigned int* counter, double* out) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
-  double v = 0.0;
-  if (i < n) {
-    v = 0.5 + (double)fmix32((uint32_t)i ^ salt) * (1.0 / 4294967296.0);
-    x[i] = v;
-  }
-  double sq[1] = {v * v};
-  grid_sum<kBlock, 1>(sq, partials, counter, out);
-}
-
-// y = (A x) / diag / sqrt(*prev), accumulating ||y||^2 into *out.
-__global__ void k_power_step(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                             const double* __restrict__ v, const double* __restrict__ diag,
-                             const double* __restrict__ x, const double* __restrict__ prev,
-                             double* __restrict__ y, double* partials, unsigned int* counter,
-                             double* out) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
-  double yi = 0.0;
-  if (i < n) {
-    double s = 0.0;
-    for (int k = rp[i]; k < rp[i + 1]; ++k) s = s + v[k] * x[ci[k]];
-    yi = (s / diag[i]) / sqrt(*prev);
-    y[i] = yi;
-  }
-  double sq[1] = {yi * yi};
-  grid_sum<kBlock, 1>(sq, partials, counter, out);
-}
-
 __global__ void k_diag(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                        const double* __restrict__ v, double* __restrict__ diag,
                        int* __restrict__ flag) {
@@ -274,15 +244,28 @@ __global__ void k_diag(int n, const int* __restrict__ rp, const int* __restrict_
 // ------------------------------------------------------------------ sparse products
 __device__ __forceinline__ uint32_t slot_hash(int key) { return fmix32((uint32_t)key); }
 
+// Upper bound of the entries of every row of C = A B: the number of products.
+__global__ void k_spgemm_bound(int n, const int* __restrict__ arp, const int* __restrict__ aci,
+                               const int* __restrict__ brp, int* __restrict__ ub) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  long long s = 0;
+  for (int a = arp[i]; a < arp[i + 1]; ++a) s += brp[aci[a] + 1] - brp[aci[a]];
+  ub[i] = s > (1 << 30) ? (1 << 30) : (int)s;
+}
+
 // Symbolic C = A B: number of distinct columns in every row of C.
-// One 64-lane workgroup per row; open-addressing hash of column ids in LDS.
+// One 64-lane workgroup per row; open-addressing hash of column ids in LDS
+// with H slots (H >= 2 x the row's product bound whenever that bound is at
+// most 1024; otherwise a full table is reported through the flag).
+template <int H>
 __global__ void __launch_bounds__(kWave) k_spgemm_count(
     const int* __restrict__ arp, const int* __restrict__ aci, const int* __restrict__ brp,
     const int* __restrict__ bci, int* __restrict__ counts, int* __restrict__ flag) {
-  __shared__ int keys[kCountHash];
+  __shared__ int keys[H];
   __shared__ int cnt;
   const int i = blockIdx.x, t = threadIdx.x;
-  for (int s = t; s < kCountHash; s += kWave) keys[s] = -1;
+  for (int s = t; s < H; s += kWave) keys[s] = -1;
   if (t == 0) cnt = 0;
   __syncthreads();
   bool overflow = false;
@@ -290,14 +273,14 @@ __global__ void __launch_bounds__(kWave) k_spgemm_count(
     const int j = aci[a];
     for (int b = brp[j] + t; b < brp[j + 1]; b += kWave) {
       const int key = bci[b];
-      uint32_t s = slot_hash(key) & (kCountHash - 1);
+      uint32_t s = slot_hash(key) & (H - 1);
       int probes = 0;
       while (true) {
         int prev = atomicCAS(&keys[s], -1, key);
         if (prev == -1) { atomicAdd(&cnt, 1); break; }
         if (prev == key) break;
-        s = (s + 1) & (kCountHash - 1);
-        if (++probes >= kCountHash) { overflow = true; break; }
+        s = (s + 1) & (H - 1);
+        if (++probes >= H) { overflow = true; break; }
       }
     }
     __syncthreads();
@@ -306,7 +289,7 @@ __global__ void __launch_bounds__(kWave) k_spgemm_count(
   __syncthreads();
   if (t == 0) {
     counts[i] = cnt;
-    if (cnt > (kCountHash * 3) / 4) atomicOr(flag, 1);
+    if (cnt > H / 2) atomicOr(flag, 1);
   }
 }
 
@@ -373,71 +356,67 @@ __global__ void k_transpose_fill(int n, const int* __restrict__ rp, const int* _
   }
 }
 
-__global__ void k_sort_rows(int n, const int* __restrict__ rp, int* __restrict__ ci,
-                            double* __restrict__ v) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  int b = rp[i], e = rp[i + 1];
-  for (int k = b + 1; k < e; ++k) {
-    int key = ci[k];
-    double x = v[k];
-    int j = k - 1;
-    while (j >= b && ci[j] > key) { ci[j + 1] = ci[j]; v[j + 1] = v[j]; --j; }
-    ci[j + 1] = key;
-    v[j + 1] = x;
+// Sort every row of an unsorted CSR by column into (ci, v): one 64-lane
+// workgroup per row; each entry's destination is the number of smaller keys
+// in its row (keys are distinct within a row).
+__global__ void __launch_bounds__(kWave) k_rank_rows(const int* __restrict__ rp,
+                                                     const int* __restrict__ uci,
+                                                     const double* __restrict__ uv,
+                                                     int* __restrict__ ci, double* __restrict__ v) {
+  const int i = blockIdx.x;
+  const int b = rp[i], e = rp[i + 1];
+  for (int p = b + threadIdx.x; p < e; p += kWave) {
+    const int key = uci[p];
+    int rank = 0;
+    for (int q = b; q < e; ++q) rank += uci[q] < key ? 1 : 0;
+    ci[b + rank] = key;
+    v[b + rank] = uv[p];
   }
 }
 
 // ------------------------------------------------------------------ dense coarsest
-__global__ void k_densify(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                          const double* __restrict__ v, double* __restrict__ M) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  for (int k = rp[i]; k < rp[i + 1]; ++k) M[(size_t)i * n + ci[k]] = v[k];
-}
-
-// In-place Cholesky (lower) of the symmetric matrix M, then the explicit
-// inverse L^-T L^-1 into Ainv.  One workgroup; W scratch n*n.
-__global__ void __launch_bounds__(1024) k_dense_inverse(int n, double* __restrict__ M,
-                                                        double* __restrict__ W,
+// Explicit inverse of the SPD matrix in the left half of the n x 2n
+// row-major array G = [A | I] by Gauss-Jordan elimination without pivoting
+// (pivots of an SPD matrix are positive).  One workgroup; at step k only the
+// columns k..n+k can change.  The inverse is left in the right half and
+// copied to Ainv.
+__global__ void __launch_bounds__(1024) k_dense_inverse(int n, double* __restrict__ G,
                                                         double* __restrict__ Ainv,
                                                         int* __restrict__ flag) {
+  __shared__ double f[kDenseMax];
+  __shared__ double piv;
   const int t = threadIdx.x, nt = blockDim.x;
+  const int w = 2 * n;
   for (int k = 0; k < n; ++k) {
     if (t == 0) {
-      double d = M[(size_t)k * n + k];
+      double d = G[(size_t)k * w + k];
       if (!(d > 0.0)) { atomicOr(flag, 2); d = 1.0; }
-      M[(size_t)k * n + k] = sqrt(d);
+      piv = d;
     }
+    for (int i = t; i < n; i += nt) f[i] = G[(size_t)i * w + k];
     __syncthreads();
-    const double lkk = M[(size_t)k * n + k];
-    for (int i = k + 1 + t; i < n; i += nt) M[(size_t)i * n + k] = M[(size_t)i * n + k] / lkk;
+    const double inv = 1.0 / piv;
+    const int ncol = n + 1;  // columns k .. n+k
+    for (int j = t; j < ncol; j += nt) G[(size_t)k * w + k + j] *= inv;
     __syncthreads();
-    const int m = n - k - 1;
-    for (int64_t p = t; p < (int64_t)m * m; p += nt) {
-      int i = k + 1 + (int)(p / m), j = k + 1 + (int)(p % m);
-      if (j <= i) M[(size_t)i * n + j] -= M[(size_t)i * n + k] * M[(size_t)j * n + k];
+    for (int64_t p = t; p < (int64_t)n * ncol; p += nt) {
+      const int i = (int)(p / ncol), j = k + (int)(p % ncol);
+      if (i != k) G[(size_t)i * w + j] -= f[i] * G[(size_t)k * w + j];
     }
     __syncthreads();
   }
-  // W = L^-1 (lower), column c by forward substitution (one thread per column)
-  for (int c = t; c < n; c += nt) {
-    for (int i = 0; i < c; ++i) W[(size_t)i * n + c] = 0.0;
-    for (int i = c; i < n; ++i) {
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int k = c; k < i; ++k) s -= M[(size_t)i * n + k] * W[(size_t)k * n + c];
-      W[(size_t)i * n + c] = s / M[(size_t)i * n + i];
-    }
-  }
-  __syncthreads();
-  // Ainv = W^T W
   for (int64_t p = t; p < (int64_t)n * n; p += nt) {
-    int i = (int)(p / n), j = (int)(p % n);
-    int k0 = i > j ? i : j;
-    double s = 0.0;
-    for (int k = k0; k < n; ++k) s += W[(size_t)k * n + i] * W[(size_t)k * n + j];
-    Ainv[p] = s;
+    const int i = (int)(p / n), j = (int)(p % n);
+    Ainv[p] = G[(size_t)i * w + n + j];
   }
+}
+
+__global__ void k_densify(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                          const double* __restrict__ v, double* __restrict__ G) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) G[(size_t)i * 2 * n + ci[k]] = v[k];
+  G[(size_t)i * 2 * n + n + i] = 1.0;
 }
 
 // ------------------------------------------------------------------ host helpers
@@ -453,12 +432,26 @@ void spgemm(ppe_solver* s, const Csr& A, const Csr& B, Csr& C) {
   }
   int* counts = s->tmp_i[0].get<int>(C.n + 1);
   int* flag = s->flag.get<int>(1);
+  hipLaunchKernelGGL(k_spgemm_bound, dim3(grid_for(C.n)), dim3(kBlock), 0, s->stream, C.n, A.rp(),
+                     A.ci(), B.rp(), counts);
+  PPE_LAUNCH_CHECK();
+  const int ub = reduce_max_int(s, counts, C.n);
+  int Hc = 64;
+  while (Hc < 2 * ub && Hc < 2048) Hc *= 2;
   fill_int(s, flag, 0, 1);
-  hipLaunchKernelGGL(k_spgemm_count, dim3(C.n), dim3(kWave), 0, s->stream, A.rp(), A.ci(), B.rp(),
-                     B.ci(), counts, flag);
+#define PPE_COUNT(HH)                                                                        \
+  hipLaunchKernelGGL(k_spgemm_count<HH>, dim3(C.n), dim3(kWave), 0, s->stream, A.rp(), A.ci(), \
+                     B.rp(), B.ci(), counts, flag)
+  if (Hc <= 64) PPE_COUNT(64);
+  else if (Hc <= 128) PPE_COUNT(128);
+  else if (Hc <= 256) PPE_COUNT(256);
+  else if (Hc <= 512) PPE_COUNT(512);
+  else if (Hc <= 1024) PPE_COUNT(1024);
+  else PPE_COUNT(2048);
+#undef PPE_COUNT
   PPE_LAUNCH_CHECK();
   require(read_scalar(s, flag) == 0, PPE_ERR_INTERNAL,
-          "sparse product row exceeds the hash table (more than 768 distinct columns)");
+          "sparse product row exceeds the hash table (more than 1024 distinct columns)");
   int mx = reduce_max_int(s, counts, C.n);
   C.nnz = exclusive_scan(s, counts, crp, C.n);
   int* cci = C.col.get<int>(C.nnz);
@@ -495,13 +488,15 @@ void transpose(ppe_solver* s, const Csr& A, Csr& T) {
   PPE_HIP(hipMemcpyAsync(cursor, trp, sizeof(int) * (T.n + 1), hipMemcpyDeviceToDevice, s->stream));
   int* tci = T.col.get<int>(T.nnz);
   double* tv = T.val.get<double>(T.nnz);
+  int* uci = s->tmp_i[2].get<int>(T.nnz);
+  double* uv = s->tmp_d[1].get<double>(T.nnz);
   if (A.n) {
     hipLaunchKernelGGL(k_transpose_fill, dim3(grid_for(A.n)), dim3(kBlock), 0, s->stream, A.n, A.rp(),
-                       A.ci(), A.v(), cursor, tci, tv);
+                       A.ci(), A.v(), cursor, uci, uv);
     PPE_LAUNCH_CHECK();
   }
   if (T.n) {
-    hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(T.n)), dim3(kBlock), 0, s->stream, T.n, trp, tci, tv);
+    hipLaunchKernelGGL(k_rank_rows, dim3(T.n), dim3(kWave), 0, s->stream, trp, uci, uv, tci, tv);
     PPE_LAUNCH_CHECK();
   }
 }
@@ -518,26 +513,10 @@ double spectral_bound(ppe_solver* s, Level& L, int lvl) {
     double r = read_scalar(s, reinterpret_cast<double*>(out));
     return r;
   }
-  const int g = grid_for(n);
-  double* x = L.x.get<double>(n);
-  double* y = L.r.get<double>(n);
-  double* sums = s->tmp_d[0].get<double>(kPowerIters + 1);
-  double* partials = s->partial.get<double>((size_t)g * 4);
-  unsigned int* counter = s->counter.get<unsigned int>(1);
-  hipLaunchKernelGGL(k_power_init, dim3(g), dim3(kBlock), 0, s->stream, n, level_salt(lvl), x,
-                     partials, counter, sums);
-  PPE_LAUNCH_CHECK();
-  for (int it = 0; it < kPowerIters; ++it) {
-    hipLaunchKernelGGL(k_power_step, dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(), L.A.ci(),
-                       L.A.v(), L.diag.as<double>(), x, sums + it, y, partials, counter,
-                       sums + it + 1);
-    PPE_LAUNCH_CHECK();
-    double* t = x;
-    x = y;
-    y = t;
-  }
-  double last = read_scalar(s, sums + kPowerIters);
-  return kPowerSafety * std::sqrt(last);
+  L.x.get<double>(n);
+  L.r.get<double>(n);
+  const double lam = power_estimate(s, L, level_salt(lvl), kPowerIters);
+  return kPowerSafety * lam;
 }
 
 }  // namespace
@@ -570,18 +549,22 @@ void build_hierarchy(ppe_solver* s) {
                          L.A.v(), L.diag.as<double>(), theta2, strong, st);
       PPE_LAUNCH_CHECK();
       const uint32_t salt = level_salt(lvl);
-      int* und = s->tmp_i[3].get<int>(1);
+      // rounds run in pairs between host checks; a round after the set is
+      // complete changes nothing, so only the second count is read
+      int* und = s->tmp_i[3].get<int>(2);
       while (true) {
-        fill_int(s, und, 0, 1);
-        hipLaunchKernelGGL(k_mis_max1, dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(), L.A.ci(),
-                           strong, st, salt, m1);
-        PPE_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_mis_max2, dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(), L.A.ci(),
-                           strong, st, salt, m1, st2, und);
-        PPE_LAUNCH_CHECK();
-        std::swap(st, st2);
-        ++L.mis_rounds;
-        if (read_scalar(s, und) == 0) break;
+        fill_int(s, und, 0, 2);
+        for (int k = 0; k < 2; ++k) {
+          hipLaunchKernelGGL(k_mis_max1, dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(),
+                             L.A.ci(), strong, st, salt, m1);
+          PPE_LAUNCH_CHECK();
+          hipLaunchKernelGGL(k_mis_max2, dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(),
+                             L.A.ci(), strong, st, salt, m1, st2, und + k);
+          PPE_LAUNCH_CHECK();
+          std::swap(st, st2);
+          ++L.mis_rounds;
+        }
+        if (read_scalar(s, und + 1) == 0) break;
         require(L.mis_rounds < 10000, PPE_ERR_INTERNAL, "MIS-2 did not terminate");
       }
       int* root = s->tmp_i[2].get<int>(n + 1);
@@ -662,15 +645,14 @@ void build_hierarchy(ppe_solver* s) {
     // coarsest level
     s->nlev = lvl + 1;
     if (n > 0 && n <= kDenseMax) {
-      double* M = L.Ainv.get<double>((size_t)n * n);  // reused below as the result
-      double* Wk = s->tmp_d[1].get<double>((size_t)2 * n * n);
-      double* Mw = Wk + (size_t)n * n;
-      PPE_HIP(hipMemsetAsync(Mw, 0, sizeof(double) * n * n, s->stream));
+      double* Ainv = L.Ainv.get<double>((size_t)n * n);
+      double* G = s->tmp_d[1].get<double>((size_t)2 * n * n);
+      fill_double(s, G, 0.0, (int64_t)2 * n * n);
       hipLaunchKernelGGL(k_densify, dim3(grid_for(n)), dim3(kBlock), 0, s->stream, n, L.A.rp(),
-                         L.A.ci(), L.A.v(), Mw);
+                         L.A.ci(), L.A.v(), G);
       PPE_LAUNCH_CHECK();
       fill_int(s, flag, 0, 1);
-      hipLaunchKernelGGL(k_dense_inverse, dim3(1), dim3(1024), 0, s->stream, n, Mw, Wk, M, flag);
+      hipLaunchKernelGGL(k_dense_inverse, dim3(1), dim3(1024), 0, s->stream, n, G, Ainv, flag);
       PPE_LAUNCH_CHECK();
       require(read_scalar(s, flag) == 0, PPE_ERR_INTERNAL, "coarsest operator is not positive definite");
       L.dense = true;

@@ -221,6 +221,41 @@ __device__ __forceinline__ T block_max(T v) {
   return s;
 }
 
+// Deterministic grid reductions without fences: a producer kernel (grid of
+// at most kRedBlocks blocks, grid-stride loops) writes one partial per block
+// and value; a consumer kernel sums those partials in a fixed order at the
+// start of every block, so all blocks see the same bitwise result.
+constexpr int kRedBlocks = 1024;
+
+template <int BS, int NV>
+__device__ __forceinline__ void write_partials(const double (&v)[NV], double* partials) {
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = block_sum<BS>(v[k]);
+    if (threadIdx.x == 0) partials[(size_t)k * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// Sum of partials[0..G) (fixed order); result broadcast to every thread.
+template <int BS>
+__device__ __forceinline__ double sum_partials(const double* __restrict__ partials, int G) {
+  __shared__ double bc;
+  double a = 0.0;
+  for (int b = threadIdx.x; b < G; b += BS) a += partials[b];
+  a = block_sum<BS>(a);
+  if (threadIdx.x == 0) bc = a;
+  __syncthreads();
+  const double r = bc;
+  __syncthreads();
+  return r;
+}
+
+inline int red_grid(int64_t work_items, int bs = kBlock) {
+  int64_t g = (work_items + bs - 1) / bs;
+  if (g < 1) g = 1;
+  return static_cast<int>(g > kRedBlocks ? kRedBlocks : g);
+}
+
 // Grid-wide deterministic sum of one value per thread, finished by the last
 // block to arrive: partials are added in block order whatever the arrival
 // order, so the result is bitwise reproducible.  Returns true in thread 0 of
@@ -290,6 +325,9 @@ void build_hierarchy(ppe_solver* s);
 
 // solve.hip
 void spmv(ppe_solver* s, const Level& L, const double* x, double* y);
+// Power iteration for lambda_max(D^-1 A) on a CSR level from the hashed
+// start vector 1/2 + fmix32(i ^ salt) / 2^32; uses L.x and L.r as work.
+double power_estimate(ppe_solver* s, Level& L, uint32_t salt, int iters);
 void vcycle(ppe_solver* s, int level, const double* b, double* x);
 ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p, int use_x0);
 void prepare_solve_levels(ppe_solver* s);

@@ -5,8 +5,9 @@
 // Layout: the finest operator is applied from a slot-major ELL copy of its
 // off-diagonal part (one thread per row, every slot load coalesced) plus the
 // diagonal; coarse operators, P and R are CSR, applied by groups of LPR
-// lanes per row with a shuffle reduction inside the group.  All reductions
-// are deterministic (fixed trees, partials summed in block order).
+// lanes per row with a shuffle reduction inside the group.  Reductions are
+// deterministic and fence-free: producers write one partial per block,
+// consumers add the partials in a fixed order.
 #include "common.h"
 
 #include <algorithm>
@@ -19,14 +20,22 @@ enum Epi : int {
   E_SPMV = 0,   // y = A x
   E_RESID = 1,  // y = b - A x
   E_CHEB = 2,   // r = (b - A x)/diag; d = c1 d + c2 r; y = x + d
-  E_DOT = 3,    // y = A x and sum x.y
+  E_DOT = 3,    // y = A x, partial sums of x.y
+  E_POWER = 4,  // y = (A x)/diag / ||x||, partial sums of y.y
 };
+
+// partial-sum slots (each kRedBlocks doubles) in s->partial
+enum Slot : int { P_BB = 0, P_RR = 1, P_PQ = 2, P_RZ = 3 /* and 4 */, P_RT = 5, P_POW = 6 /* 6, 7 */,
+                  P_NSLOTS = 8 };
+// device scalars in s->scal
+enum Scal : int { S_BB = 0, S_RR = 1, S_PQ = 2, S_RZ = 3 /* 3, 4 */, S_RT = 5, S_POW = 6, S_N = 8 };
 
 template <int EPI>
 __device__ __forceinline__ double epilogue(int i, double ax, const double* __restrict__ x,
                                            const double* __restrict__ b,
                                            const double* __restrict__ diag, double* __restrict__ d,
-                                           double c1, double c2, double* __restrict__ y) {
+                                           double c1, double c2, double scale,
+                                           double* __restrict__ y) {
   if (EPI == E_SPMV) {
     y[i] = ax;
     return 0.0;
@@ -39,13 +48,17 @@ __device__ __forceinline__ double epilogue(int i, double ax, const double* __res
     d[i] = dn;
     y[i] = x[i] + dn;
     return 0.0;
-  } else {
+  } else if (EPI == E_DOT) {
     y[i] = ax;
     return x[i] * ax;
+  } else {
+    const double v = (ax / diag[i]) * scale;
+    y[i] = v;
+    return v * v;
   }
 }
 
-// ---- finest level: ELL, one thread per row
+// ---- finest level: ELL, one thread per row (grid-stride)
 template <int EPI>
 __global__ void __launch_bounds__(kBlock) k_ell(int n, int W, const int* __restrict__ ecol,
                                                 const double* __restrict__ eval,
@@ -53,25 +66,24 @@ __global__ void __launch_bounds__(kBlock) k_ell(int n, int W, const int* __restr
                                                 const double* __restrict__ x,
                                                 const double* __restrict__ b, double* __restrict__ d,
                                                 double c1, double c2, double* __restrict__ y,
-                                                double* partials, unsigned int* counter,
-                                                double* out) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+                                                double* __restrict__ partials) {
   double dot = 0.0;
-  if (i < n) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     double s = diag[i] * x[i];
     for (int k = 0; k < W; ++k) {
       const size_t e = (size_t)k * n + i;
       s = s + eval[e] * x[ecol[e]];
     }
-    dot = epilogue<EPI>(i, s, x, b, diag, d, c1, c2, y);
+    dot += epilogue<EPI>(i, s, x, b, diag, d, c1, c2, 1.0, y);
   }
   if (EPI == E_DOT) {
     double v[1] = {dot};
-    grid_sum<kBlock, 1>(v, partials, counter, out);
+    write_partials<kBlock, 1>(v, partials);
   }
 }
 
-// ---- CSR, LPR lanes per row
+// ---- CSR, LPR lanes per row; every lane runs the same trip count so the
+// group shuffles always see all lanes.
 template <int EPI, int LPR>
 __global__ void __launch_bounds__(kBlock) k_csr(int n, const int* __restrict__ rp,
                                                 const int* __restrict__ ci,
@@ -80,25 +92,32 @@ __global__ void __launch_bounds__(kBlock) k_csr(int n, const int* __restrict__ r
                                                 const double* __restrict__ x,
                                                 const double* __restrict__ b, double* __restrict__ d,
                                                 double c1, double c2, double* __restrict__ y,
-                                                double* partials, unsigned int* counter,
-                                                double* out) {
-  const int g = (blockIdx.x * kBlock + threadIdx.x) / LPR;
+                                                const double* __restrict__ prevp, int gprev,
+                                                double* __restrict__ partials) {
+  double scale = 1.0;
+  if (EPI == E_POWER) scale = 1.0 / sqrt(sum_partials<kBlock>(prevp, gprev));
   const int lane = threadIdx.x % LPR;
-  double s = 0.0;
-  if (g < n) {
-    for (int k = rp[g] + lane; k < rp[g + 1]; k += LPR) s = s + v[k] * x[ci[k]];
-  }
-#pragma unroll
-  for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_down(s, o, LPR);
+  const int groups = gridDim.x * (kBlock / LPR);
+  const int my = (blockIdx.x * kBlock + threadIdx.x) / LPR;
+  const int trips = (n + groups - 1) / groups;
   double dot = 0.0;
-  if (g < n && lane == 0) dot = epilogue<EPI>(g, s, x, b, diag, d, c1, c2, y);
-  if (EPI == E_DOT) {
+  for (int t = 0; t < trips; ++t) {
+    const int g = t * groups + my;
+    double s = 0.0;
+    if (g < n) {
+      for (int k = rp[g] + lane; k < rp[g + 1]; k += LPR) s = s + v[k] * x[ci[k]];
+    }
+#pragma unroll
+    for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_down(s, o, LPR);
+    if (g < n && lane == 0) dot += epilogue<EPI>(g, s, x, b, diag, d, c1, c2, scale, y);
+  }
+  if (EPI == E_DOT || EPI == E_POWER) {
     double vv[1] = {dot};
-    grid_sum<kBlock, 1>(vv, partials, counter, out);
+    write_partials<kBlock, 1>(vv, partials);
   }
 }
 
-// y (+)= P x for a rectangular CSR (prolongation adds into y).
+// y (+)= M x for a rectangular CSR (prolongation adds into y).
 template <int LPR, bool ADD>
 __global__ void __launch_bounds__(kBlock) k_csr_rect(int n, const int* __restrict__ rp,
                                                      const int* __restrict__ ci,
@@ -126,29 +145,44 @@ __global__ void k_cheb_first(int n, const double* __restrict__ b, const double* 
   x[i] = v;
 }
 
-// Dense coarsest solve x = Ainv b (Ainv symmetric, row i read as column i).
-__global__ void k_dense_gemv(int n, const double* __restrict__ Ainv, const double* __restrict__ b,
-                             double* __restrict__ x) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
+// Dense coarsest solve x = Ainv b: one wave per row, lanes over columns.
+__global__ void __launch_bounds__(kBlock) k_dense_gemv(int n, const double* __restrict__ Ainv,
+                                                       const double* __restrict__ b,
+                                                       double* __restrict__ x) {
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int lane = threadIdx.x % kWave;
   double s = 0.0;
-  for (int j = 0; j < n; ++j) s = s + Ainv[(size_t)j * n + i] * b[j];
-  x[i] = s;
+  if (i < n)
+    for (int j = lane; j < n; j += kWave) s = s + Ainv[(size_t)i * n + j] * b[j];
+  s = wave_sum(s);
+  if (i < n && lane == 0) x[i] = s;
 }
 
-// ---- PCG vector kernels (device-resident scalars)
+__global__ void k_power_init(int n, uint32_t salt, double* __restrict__ x,
+                             double* __restrict__ partials) {
+  double acc = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const double v = 0.5 + (double)fmix32((uint32_t)i ^ salt) * (1.0 / 4294967296.0);
+    x[i] = v;
+    acc += v * v;
+  }
+  double sq[1] = {acc};
+  write_partials<kBlock, 1>(sq, partials);
+}
+
+// ---- PCG vector kernels
 __global__ void k_gather_rhs(int na, const int* __restrict__ perm, const int* __restrict__ comp,
                              const double* __restrict__ rhs, double* __restrict__ b,
-                             double* partials, unsigned int* counter, double* out) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
-  double v = 0.0;
-  if (i < na) {
-    int c = perm[i];
-    v = comp[c] == c ? 0.0 : rhs[c];
+                             double* __restrict__ partials) {
+  double acc = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < na; i += gridDim.x * kBlock) {
+    const int c = perm[i];
+    const double v = comp[c] == c ? 0.0 : rhs[c];
     b[i] = v;
+    acc += v * v;
   }
-  double s[1] = {v * v};
-  grid_sum<kBlock, 1>(s, partials, counter, out);
+  double s[1] = {acc};
+  write_partials<kBlock, 1>(s, partials);
 }
 
 __global__ void k_gather_x0(int na, const int* __restrict__ perm, const int* __restrict__ comp,
@@ -167,51 +201,72 @@ __global__ void k_scatter(int nc, const int* __restrict__ cid, const int* __rest
   p[c] = (k < 0 || comp[c] == c) ? 0.0 : x[k];
 }
 
-__global__ void k_norm2(int n, const double* __restrict__ a, double* partials,
-                        unsigned int* counter, double* out) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
-  double v = i < n ? a[i] : 0.0;
-  double s[1] = {v * v};
-  grid_sum<kBlock, 1>(s, partials, counter, out);
+__global__ void k_norm2(int n, const double* __restrict__ a, double* __restrict__ partials) {
+  double acc = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) acc += a[i] * a[i];
+  double s[1] = {acc};
+  write_partials<kBlock, 1>(s, partials);
 }
 
-// sums r.z and r.z_old (the latter for the flexible beta).
+// Partial sums of r.z and (flexible variant) r.z_old.
 __global__ void k_dot2(int n, const double* __restrict__ r, const double* __restrict__ z,
-                       const double* __restrict__ zold, double* partials, unsigned int* counter,
-                       double* out) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
+                       const double* __restrict__ zold, double* __restrict__ partials) {
   double s[2] = {0.0, 0.0};
-  if (i < n) {
-    s[0] = r[i] * z[i];
-    if (zold) s[1] = r[i] * zold[i];
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    s[0] += r[i] * z[i];
+    if (zold) s[1] += r[i] * zold[i];
   }
-  grid_sum<kBlock, 2>(s, partials, counter, out);
+  write_partials<kBlock, 2>(s, partials);
 }
 
-// alpha = rz / pq; x += alpha p; r -= alpha q; sum r.r
-__global__ void k_update_xr(int n, const double* __restrict__ rz, const double* __restrict__ pq,
-                            const double* __restrict__ p, const double* __restrict__ q,
-                            double* __restrict__ x, double* __restrict__ r, double* partials,
-                            unsigned int* counter, double* out) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
-  const double alpha = *rz / *pq;
-  double v = 0.0;
-  if (i < n) {
+// p = z; block 0 stores rz = sum of the r.z partials.
+__global__ void k_init_p(int n, const double* __restrict__ z, double* __restrict__ p,
+                         const double* __restrict__ rz_parts, int g, double* __restrict__ rz_out) {
+  const double rz = sum_partials<kBlock>(rz_parts, g);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *rz_out = rz;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = z[i];
+}
+
+// alpha = rz / p.q (partials); x += alpha p; r -= alpha q; partial sums of r.r
+__global__ void k_update_xr(int n, const double* __restrict__ rz, const double* __restrict__ pq_parts,
+                            int g, const double* __restrict__ p, const double* __restrict__ q,
+                            double* __restrict__ x, double* __restrict__ r,
+                            double* __restrict__ partials) {
+  const double alpha = *rz / sum_partials<kBlock>(pq_parts, g);
+  double acc = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     x[i] = x[i] + alpha * p[i];
-    v = r[i] - alpha * q[i];
+    const double v = r[i] - alpha * q[i];
     r[i] = v;
+    acc += v * v;
   }
-  double s[1] = {v * v};
-  grid_sum<kBlock, 1>(s, partials, counter, out);
+  double s[1] = {acc};
+  write_partials<kBlock, 1>(s, partials);
 }
 
-// beta = (rz_new - rzold_new) / rz_prev; p = z + beta p
-__global__ void k_update_p(int n, const double* __restrict__ rzn, const double* __restrict__ rzp,
+// beta = (rz_new [- r.z_old]) / rz_prev; p = z + beta p; block 0 stores rz_new.
+__global__ void k_update_p(int n, const double* __restrict__ rz_parts, int g,
+                           const double* __restrict__ rz_prev, double* __restrict__ rz_next,
                            int flexible, const double* __restrict__ z, double* __restrict__ p) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const double beta = (flexible ? (rzn[0] - rzn[1]) : rzn[0]) / rzp[0];
-  p[i] = z[i] + beta * p[i];
+  const double rzn = sum_partials<kBlock>(rz_parts, g);
+  const double rzo = flexible ? sum_partials<kBlock>(rz_parts + g, g) : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *rz_next = rzn;
+  const double beta = (rzn - rzo) / *rz_prev;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+    p[i] = z[i] + beta * p[i];
+}
+
+// Host-facing scalars: *o0 = sum of p0, *o1 = sum of p1 (p1 may be null).
+__global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ p0,
+                                                     const double* __restrict__ p1, int g,
+                                                     double* __restrict__ o0,
+                                                     double* __restrict__ o1) {
+  const double a = sum_partials<kBlock>(p0, g);
+  const double b = p1 ? sum_partials<kBlock>(p1, g) : 0.0;
+  if (threadIdx.x == 0) {
+    *o0 = a;
+    if (p1) *o1 = b;
+  }
 }
 
 __global__ void k_copy(int n, const double* __restrict__ a, double* __restrict__ b) {
@@ -226,25 +281,22 @@ int lanes_for(const Csr& A) {
   return lpr;
 }
 
-struct RedBuf {
-  double* partials;
-  unsigned int* counter;
-};
-
-RedBuf red(ppe_solver* s, int grid) {
-  return RedBuf{s->partial.get<double>((size_t)grid * 4), s->counter.get<unsigned int>(1)};
+double* part(ppe_solver* s, int slot) {
+  return s->partial.as<double>() + (size_t)slot * kRedBlocks;
 }
 
 constexpr size_t kProfPairs = 256;
 
+// Apply the level operator with epilogue EPI.  Dot/power epilogues run on a
+// capped grid and write partials to `partials`; returns that grid size.
 template <int EPI>
-void apply_op(ppe_solver* s, const Level& L, const double* x, const double* b, double* d, double c1,
-              double c2, double* y, double* out) {
+int apply_op(ppe_solver* s, const Level& L, const double* x, const double* b, double* d, double c1,
+             double c2, double* y, double* partials, const double* prevp = nullptr, int gprev = 0) {
   const int n = L.n;
-  if (n == 0) return;
-  if (&L == &s->levels[0]) {
-    const int g = grid_for(n);
-    RedBuf rb = red(s, g);
+  if (n == 0) return 1;
+  const bool reduce = EPI == E_DOT || EPI == E_POWER;
+  if (&L == &s->levels[0] && EPI != E_POWER) {
+    const int g = reduce ? red_grid(n) : grid_for(n);
     const bool prof = s->prof && EPI == E_CHEB;
     if (prof) {
       if (s->prof_pending.size() == kProfPairs) profile_harvest(s);
@@ -253,7 +305,7 @@ void apply_op(ppe_solver* s, const Level& L, const double* x, const double* b, d
     }
     hipLaunchKernelGGL(k_ell<EPI>, dim3(g), dim3(kBlock), 0, s->stream, n, L.W,
                        L.ell_col.as<int>(), L.ell_val.as<double>(), L.diag.as<double>(), x, b, d,
-                       c1, c2, y, rb.partials, rb.counter, out);
+                       c1, c2, y, partials);
     PPE_LAUNCH_CHECK();
     if (prof) {
       const size_t k = s->prof_pending.size();
@@ -262,15 +314,14 @@ void apply_op(ppe_solver* s, const Level& L, const double* x, const double* b, d
       const double vecs = (c1 != 0.0) ? 6.0 : 5.0;  // diag, x_in, b, x_out, d out (+ d in)
       s->prof_pending.push_back(off * 12.0 + vecs * 8.0 * n);
     }
-    return;
+    return g;
   }
   const int lpr = lanes_for(L.A);
-  const int g = grid_for((int64_t)n * lpr);
-  RedBuf rb = red(s, g);
-#define PPE_CSR(LL)                                                                          \
-  hipLaunchKernelGGL((k_csr<EPI, LL>), dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(),     \
-                     L.A.ci(), L.A.v(), L.diag.as<double>(), x, b, d, c1, c2, y, rb.partials, \
-                     rb.counter, out)
+  const int g = reduce ? red_grid((int64_t)n * lpr) : grid_for((int64_t)n * lpr);
+#define PPE_CSR(LL)                                                                           \
+  hipLaunchKernelGGL((k_csr<EPI, LL>), dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(),      \
+                     L.A.ci(), L.A.v(), L.diag.as<double>(), x, b, d, c1, c2, y, prevp, gprev, \
+                     partials)
   switch (lpr) {
     case 4: PPE_CSR(4); break;
     case 8: PPE_CSR(8); break;
@@ -280,6 +331,7 @@ void apply_op(ppe_solver* s, const Level& L, const double* x, const double* b, d
   }
 #undef PPE_CSR
   PPE_LAUNCH_CHECK();
+  return g;
 }
 
 template <bool ADD>
@@ -359,6 +411,28 @@ void spmv(ppe_solver* s, const Level& L, const double* x, double* y) {
   apply_op<E_SPMV>(s, L, x, nullptr, nullptr, 0.0, 0.0, y, nullptr);
 }
 
+double power_estimate(ppe_solver* s, Level& L, uint32_t salt, int iters) {
+  const int n = L.n;
+  s->partial.get<double>((size_t)P_NSLOTS * kRedBlocks);
+  double* sc = s->scal.get<double>(S_N);
+  double* x = L.x.as<double>();
+  double* y = L.r.as<double>();
+  double* pa = part(s, P_POW);
+  double* pb = part(s, P_POW + 1);
+  int g = red_grid(n);
+  hipLaunchKernelGGL(k_power_init, dim3(g), dim3(kBlock), 0, s->stream, n, salt, x, pa);
+  PPE_LAUNCH_CHECK();
+  for (int it = 0; it < iters; ++it) {
+    g = apply_op<E_POWER>(s, L, x, nullptr, nullptr, 0.0, 0.0, y, pb, pa, g);
+    std::swap(x, y);
+    std::swap(pa, pb);
+  }
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s->stream, pa, nullptr, g, sc + S_POW,
+                     nullptr);
+  PPE_LAUNCH_CHECK();
+  return std::sqrt(read_scalar(s, sc + S_POW));
+}
+
 void prepare_solve_levels(ppe_solver* s) {
   for (int l = 0; l < s->nlev; ++l) {
     Level& L = s->levels[l];
@@ -395,8 +469,8 @@ void vcycle(ppe_solver* s, int l, const double* b, double* x) {
   double* xb = L.d2.as<double>();
   if (l == s->nlev - 1) {
     if (L.dense) {
-      hipLaunchKernelGGL(k_dense_gemv, dim3(grid_for(n)), dim3(kBlock), 0, s->stream, n,
-                         L.Ainv.as<double>(), b, x);
+      hipLaunchKernelGGL(k_dense_gemv, dim3(grid_for((int64_t)n * kWave)), dim3(kBlock), 0,
+                         s->stream, n, L.Ainv.as<double>(), b, x);
       PPE_LAUNCH_CHECK();
     } else {
       double* t = L.r.as<double>();
@@ -427,7 +501,7 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
     return PPE_OK;
   }
   Level& L0 = s->levels[0];
-  const int g = grid_for(na);
+  const int gv = red_grid(na);
   double* x = s->vx.get<double>(na);
   double* r = s->vr.get<double>(na);
   double* z = s->vz.get<double>(na);
@@ -436,30 +510,33 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
   double* b = s->vb.get<double>(na);
   const bool flexible = s->opt.precision == PPE_MIXED;
   double* zold = flexible ? s->vzold.get<double>(na) : nullptr;
-  // scalars: [0] bb, [1] rr, [2] pq, [3,4] rz even (rz, rzold), [5,6] rz odd, [7] rtrue
-  double* sc = s->scal.get<double>(16);
-  RedBuf rb = red(s, g);
+  double* sc = s->scal.get<double>(S_N);
+  s->partial.get<double>((size_t)P_NSLOTS * kRedBlocks);
   const int* perm = s->perm.as<int>();
   const int* comp = s->comp_full.as<int>();
-  hipLaunchKernelGGL(k_gather_rhs, dim3(g), dim3(kBlock), 0, s->stream, na, perm, comp, rhs, b,
-                     rb.partials, rb.counter, sc + 0);
+  const int ge = grid_for(na);
+
+  hipLaunchKernelGGL(k_gather_rhs, dim3(gv), dim3(kBlock), 0, s->stream, na, perm, comp, rhs, b,
+                     part(s, P_BB));
   PPE_LAUNCH_CHECK();
   if (use_x0) {
-    hipLaunchKernelGGL(k_gather_x0, dim3(g), dim3(kBlock), 0, s->stream, na, perm, comp, p_out, x);
+    hipLaunchKernelGGL(k_gather_x0, dim3(ge), dim3(kBlock), 0, s->stream, na, perm, comp, p_out, x);
     PPE_LAUNCH_CHECK();
     apply_op<E_RESID>(s, L0, x, b, nullptr, 0.0, 0.0, r, nullptr);
   } else {
     fill_double(s, x, 0.0, na);
-    hipLaunchKernelGGL(k_copy, dim3(g), dim3(kBlock), 0, s->stream, na, b, r);
+    hipLaunchKernelGGL(k_copy, dim3(ge), dim3(kBlock), 0, s->stream, na, b, r);
     PPE_LAUNCH_CHECK();
   }
-  hipLaunchKernelGGL(k_norm2, dim3(g), dim3(kBlock), 0, s->stream, na, r, rb.partials, rb.counter,
-                     sc + 1);
+  hipLaunchKernelGGL(k_norm2, dim3(gv), dim3(kBlock), 0, s->stream, na, r, part(s, P_RR));
   PPE_LAUNCH_CHECK();
-  double h[8];
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s->stream, part(s, P_BB), part(s, P_RR),
+                     gv, sc + S_BB, sc + S_RR);
+  PPE_LAUNCH_CHECK();
+  double h[S_N];
   PPE_HIP(hipMemcpyAsync(h, sc, sizeof(double) * 2, hipMemcpyDeviceToHost, s->stream));
   PPE_HIP(hipStreamSynchronize(s->stream));
-  const double bb = h[0];
+  const double bb = h[S_BB];
   const double tol2 = s->opt.rtol * s->opt.rtol * bb;
   auto finish = [&](ppe_status status, double rr_true) {
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc,
@@ -470,65 +547,66 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
     st.rel_residual = bb > 0 ? std::sqrt(rr_true / bb) : std::sqrt(rr_true);
     return status;
   };
+  auto true_residual = [&]() {
+    apply_op<E_RESID>(s, L0, x, b, nullptr, 0.0, 0.0, q, nullptr);
+    hipLaunchKernelGGL(k_norm2, dim3(gv), dim3(kBlock), 0, s->stream, na, q, part(s, P_RT));
+    PPE_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s->stream, part(s, P_RT), nullptr, gv,
+                       sc + S_RT, nullptr);
+    PPE_LAUNCH_CHECK();
+    return read_scalar(s, sc + S_RT);
+  };
   if (bb == 0.0) {
     fill_double(s, x, 0.0, na);
     return finish(PPE_OK, 0.0);
   }
-  if (h[1] <= tol2) return finish(PPE_OK, h[1]);
+  if (h[S_RR] <= tol2) return finish(PPE_OK, h[S_RR]);
 
   vcycle(s, 0, r, z);
-  hipLaunchKernelGGL(k_dot2, dim3(g), dim3(kBlock), 0, s->stream, na, r, z, nullptr, rb.partials,
-                     rb.counter, sc + 3);
+  hipLaunchKernelGGL(k_dot2, dim3(gv), dim3(kBlock), 0, s->stream, na, r, z, nullptr, part(s, P_RZ));
   PPE_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_copy, dim3(g), dim3(kBlock), 0, s->stream, na, z, p);
+  hipLaunchKernelGGL(k_init_p, dim3(gv), dim3(kBlock), 0, s->stream, na, z, p, part(s, P_RZ), gv,
+                     sc + S_RZ);
   PPE_LAUNCH_CHECK();
-  int slot = 0;  // rz of the current iteration at sc[3 + 2*slot]
+  int slot = 0;  // rz of the current iteration at sc[S_RZ + slot]
   const int max_iter = s->opt.max_iter;
   for (int it = 1; it <= max_iter; ++it) {
-    double* rzc = sc + 3 + 2 * slot;
-    apply_op<E_DOT>(s, L0, p, nullptr, nullptr, 0.0, 0.0, q, sc + 2);
-    hipLaunchKernelGGL(k_update_xr, dim3(g), dim3(kBlock), 0, s->stream, na, rzc, sc + 2, p, q, x, r,
-                       rb.partials, rb.counter, sc + 1);
+    double* rzc = sc + S_RZ + slot;
+    const int gq = apply_op<E_DOT>(s, L0, p, nullptr, nullptr, 0.0, 0.0, q, part(s, P_PQ));
+    hipLaunchKernelGGL(k_update_xr, dim3(gv), dim3(kBlock), 0, s->stream, na, rzc, part(s, P_PQ), gq,
+                       p, q, x, r, part(s, P_RR));
     PPE_LAUNCH_CHECK();
-    PPE_HIP(hipMemcpyAsync(h, sc, sizeof(double) * 7, hipMemcpyDeviceToHost, s->stream));
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s->stream, part(s, P_RR), part(s, P_PQ),
+                       gv, sc + S_RR, sc + S_PQ);
+    PPE_LAUNCH_CHECK();
+    PPE_HIP(hipMemcpyAsync(h, sc, sizeof(double) * S_N, hipMemcpyDeviceToHost, s->stream));
     PPE_HIP(hipStreamSynchronize(s->stream));
     st.iterations = it;
-    const double pq = h[2], rr = h[1], rz = h[3 + 2 * slot];
+    const double pq = h[S_PQ], rr = h[S_RR], rz = h[S_RZ + slot];
     if (!(pq > 0.0) || !std::isfinite(rr) || !(rz > 0.0)) {
       finish(PPE_ERR_BREAKDOWN, rr);
       return PPE_ERR_BREAKDOWN;
     }
     if (rr <= tol2) {
-      apply_op<E_RESID>(s, L0, x, b, nullptr, 0.0, 0.0, q, nullptr);
-      hipLaunchKernelGGL(k_norm2, dim3(g), dim3(kBlock), 0, s->stream, na, q, rb.partials, rb.counter,
-                         sc + 7);
-      PPE_LAUNCH_CHECK();
-      double rt = read_scalar(s, sc + 7);
+      const double rt = true_residual();
       if (rt <= tol2) return finish(PPE_OK, rt);
-      hipLaunchKernelGGL(k_copy, dim3(g), dim3(kBlock), 0, s->stream, na, q, r);
+      hipLaunchKernelGGL(k_copy, dim3(ge), dim3(kBlock), 0, s->stream, na, q, r);
       PPE_LAUNCH_CHECK();
     }
     if (it == max_iter) break;
     if (flexible) {
-      hipLaunchKernelGGL(k_copy, dim3(g), dim3(kBlock), 0, s->stream, na, z, zold);
+      hipLaunchKernelGGL(k_copy, dim3(ge), dim3(kBlock), 0, s->stream, na, z, zold);
       PPE_LAUNCH_CHECK();
     }
     vcycle(s, 0, r, z);
-    double* rzn = sc + 3 + 2 * (1 - slot);
-    hipLaunchKernelGGL(k_dot2, dim3(g), dim3(kBlock), 0, s->stream, na, r, z, zold, rb.partials,
-                       rb.counter, rzn);
+    hipLaunchKernelGGL(k_dot2, dim3(gv), dim3(kBlock), 0, s->stream, na, r, z, zold, part(s, P_RZ));
     PPE_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_update_p, dim3(g), dim3(kBlock), 0, s->stream, na, rzn, rzc,
-                       flexible ? 1 : 0, z, p);
+    hipLaunchKernelGGL(k_update_p, dim3(gv), dim3(kBlock), 0, s->stream, na, part(s, P_RZ), gv, rzc,
+                       sc + S_RZ + (1 - slot), flexible ? 1 : 0, z, p);
     PPE_LAUNCH_CHECK();
     slot = 1 - slot;
   }
-  apply_op<E_RESID>(s, L0, x, b, nullptr, 0.0, 0.0, q, nullptr);
-  hipLaunchKernelGGL(k_norm2, dim3(g), dim3(kBlock), 0, s->stream, na, q, rb.partials, rb.counter,
-                     sc + 7);
-  PPE_LAUNCH_CHECK();
-  double rt = read_scalar(s, sc + 7);
-  return finish(PPE_NOT_CONVERGED, rt);
+  return finish(PPE_NOT_CONVERGED, true_residual());
 }
 
 }  // namespace ppe
