@@ -33,23 +33,48 @@ constexpr int kCountHash = 1024;  // hash slots per row in the symbolic product
 
 enum : int { S_OUT = 0, S_UND = 1, S_IN = 2 };
 
-// ------------------------------------------------------------------ strength
-__global__ void k_strength(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                           const double* __restrict__ v, const double* __restrict__ diag,
-                           double theta2, unsigned char* __restrict__ strong,
-                           unsigned char* __restrict__ state) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const double di = diag[i];
-  int deg = 0;
-  for (int k = rp[i]; k < rp[i + 1]; ++k) {
-    int j = ci[k];
-    double a = v[k];
-    bool s = (j != i) && (a != 0.0) && (a * a >= theta2 * (di * diag[j]));
-    strong[k] = s ? 1 : 0;
-    deg += s ? 1 : 0;
+// Row kernels below give each row a group of LPR lanes (LPR = power of two
+// near the mean row length); lanes stride over the row's entries and the
+// group combines its results with shuffles, in a fixed order.
+template <int LPR, class T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) v += __shfl_down(v, o, LPR);
+  return v;
+}
+
+template <int LPR, class T>
+__device__ __forceinline__ T group_max(T v) {
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) {
+    T w = __shfl_down(v, o, LPR);
+    v = w > v ? w : v;
   }
-  state[i] = deg > 0 ? S_UND : S_OUT;
+  return v;
+}
+
+// ------------------------------------------------------------------ strength
+template <int LPR>
+__global__ void __launch_bounds__(kBlock) k_strength(int n, const int* __restrict__ rp,
+                                                     const int* __restrict__ ci,
+                                                     const double* __restrict__ v,
+                                                     const double* __restrict__ diag, double theta2,
+                                                     unsigned char* __restrict__ strong,
+                                                     unsigned char* __restrict__ state) {
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / LPR, lane = threadIdx.x % LPR;
+  int deg = 0;
+  if (i < n) {
+    const double di = diag[i];
+    for (int k = rp[i] + lane; k < rp[i + 1]; k += LPR) {
+      const int j = ci[k];
+      const double a = v[k];
+      const bool st = (j != i) && (a != 0.0) && (a * a >= theta2 * (di * diag[j]));
+      strong[k] = st ? 1 : 0;
+      deg += st ? 1 : 0;
+    }
+  }
+  deg = group_sum<LPR>(deg);
+  if (i < n && lane == 0) state[i] = deg > 0 ? S_UND : S_OUT;
 }
 
 // ------------------------------------------------------------------ MIS-2
@@ -59,48 +84,69 @@ __device__ __forceinline__ unsigned long long mis_key(unsigned char st, int j, u
          (unsigned long long)((1u << 30) - 1u - (uint32_t)j);
 }
 
-__global__ void k_mis_max1(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                           const unsigned char* __restrict__ strong,
-                           const unsigned char* __restrict__ state, uint32_t salt,
-                           unsigned long long* __restrict__ m1) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  unsigned long long m = mis_key(state[i], i, salt);
-  for (int k = rp[i]; k < rp[i + 1]; ++k) {
-    if (!strong[k]) continue;
-    int j = ci[k];
-    unsigned long long kj = mis_key(state[j], j, salt);
-    m = kj > m ? kj : m;
+// m1_i = max key over i and its strong neighbours
+template <int LPR>
+__global__ void __launch_bounds__(kBlock) k_mis_max1(int n, const int* __restrict__ rp,
+                                                     const int* __restrict__ ci,
+                                                     const unsigned char* __restrict__ strong,
+                                                     const unsigned char* __restrict__ state,
+                                                     uint32_t salt,
+                                                     unsigned long long* __restrict__ m1) {
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / LPR, lane = threadIdx.x % LPR;
+  unsigned long long m = 0;
+  if (i < n) {
+    for (int k = rp[i] + lane; k < rp[i + 1]; k += LPR) {
+      if (!strong[k]) continue;
+      const int j = ci[k];
+      const unsigned long long kj = mis_key(state[j], j, salt);
+      m = kj > m ? kj : m;
+    }
   }
-  m1[i] = m;
+  m = group_max<LPR>(m);
+  if (i < n && lane == 0) {
+    const unsigned long long own = mis_key(state[i], i, salt);
+    m1[i] = own > m ? own : m;
+  }
 }
 
-__global__ void k_mis_max2(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                           const unsigned char* __restrict__ strong,
-                           const unsigned char* __restrict__ state, uint32_t salt,
-                           const unsigned long long* __restrict__ m1,
-                           unsigned char* __restrict__ next, int* __restrict__ undecided) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  unsigned char st = state[i];
-  if (st != S_UND) {
-    next[i] = st;
-    return;
+// m2_i = max m1 over i and its strong neighbours; an undecided node joins if
+// m2 is its own key, leaves if m2 belongs to a member.
+template <int LPR>
+__global__ void __launch_bounds__(kBlock) k_mis_max2(int n, const int* __restrict__ rp,
+                                                     const int* __restrict__ ci,
+                                                     const unsigned char* __restrict__ strong,
+                                                     const unsigned char* __restrict__ state,
+                                                     uint32_t salt,
+                                                     const unsigned long long* __restrict__ m1,
+                                                     unsigned char* __restrict__ next,
+                                                     int* __restrict__ undecided) {
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / LPR, lane = threadIdx.x % LPR;
+  const unsigned char st = i < n ? state[i] : (unsigned char)S_OUT;
+  unsigned long long m = 0;
+  int und = 0;
+  if (i < n && st == S_UND) {
+    for (int k = rp[i] + lane; k < rp[i + 1]; k += LPR) {
+      if (!strong[k]) continue;
+      const unsigned long long mj = m1[ci[k]];
+      m = mj > m ? mj : m;
+    }
   }
-  unsigned long long m = m1[i];
-  for (int k = rp[i]; k < rp[i + 1]; ++k) {
-    if (!strong[k]) continue;
-    unsigned long long mj = m1[ci[k]];
-    m = mj > m ? mj : m;
+  m = group_max<LPR>(m);
+  if (i < n && lane == 0) {
+    unsigned char ns = st;
+    if (st == S_UND) {
+      const unsigned long long own = mis_key(st, i, salt);
+      const unsigned long long mm = m1[i] > m ? m1[i] : m;
+      if (mm == own)
+        ns = S_IN;
+      else if ((mm >> 62) == S_IN)
+        ns = S_OUT;
+    }
+    next[i] = ns;
+    und = ns == S_UND ? 1 : 0;
   }
-  const unsigned long long own = mis_key(st, i, salt);
-  unsigned char ns = st;
-  if (m == own)
-    ns = S_IN;
-  else if ((m >> 62) == S_IN)
-    ns = S_OUT;
-  next[i] = ns;
-  if (ns == S_UND) atomicAdd(undecided, 1);
+  und = block_sum<kBlock>(und);
+  if (threadIdx.x == 0 && und) atomicAdd(undecided, und);
 }
 
 // ------------------------------------------------------------------ aggregation
@@ -109,48 +155,67 @@ __global__ void k_is_root(int n, const unsigned char* __restrict__ state, int* _
   if (i < n) root[i] = state[i] == S_IN ? 1 : 0;
 }
 
-__global__ void k_agg_first(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                            const unsigned char* __restrict__ strong,
-                            const unsigned char* __restrict__ state,
-                            const int* __restrict__ root_id, int* __restrict__ agg1) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
+// A root's id; a node with a strong root neighbour takes that root's id (the
+// root is unique: roots are at least three edges apart); others -1.
+template <int LPR>
+__global__ void __launch_bounds__(kBlock) k_agg_first(int n, const int* __restrict__ rp,
+                                                      const int* __restrict__ ci,
+                                                      const unsigned char* __restrict__ strong,
+                                                      const unsigned char* __restrict__ state,
+                                                      const int* __restrict__ root_id,
+                                                      int* __restrict__ agg1) {
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / LPR, lane = threadIdx.x % LPR;
   int a = -1;
-  if (state[i] == S_IN) {
-    a = root_id[i];
-  } else {
-    for (int k = rp[i]; k < rp[i + 1]; ++k) {
-      if (!strong[k]) continue;
-      int j = ci[k];
-      if (state[j] == S_IN) { a = root_id[j]; break; }
+  const bool root = i < n && state[i] == S_IN;
+  if (i < n && !root) {
+    for (int k = rp[i] + lane; k < rp[i + 1]; k += LPR) {
+      const int j = ci[k];
+      if (strong[k] && state[j] == S_IN) a = root_id[j];
     }
   }
-  agg1[i] = a;
+  a = group_max<LPR>(a);
+  if (i < n && lane == 0) agg1[i] = root ? root_id[i] : a;
 }
 
-__global__ void k_agg_second(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                             const double* __restrict__ v, const unsigned char* __restrict__ strong,
-                             const int* __restrict__ agg1, int* __restrict__ agg,
-                             int* __restrict__ flag) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  int a = agg1[i];
-  if (a < 0) {
-    double best = -1.0;
-    int bestj = -1;
-    bool any_strong = false;
-    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+// Leftover nodes join the first-pass neighbour with the largest |a_ij|, ties
+// to the lowest j.
+template <int LPR>
+__global__ void __launch_bounds__(kBlock) k_agg_second(int n, const int* __restrict__ rp,
+                                                       const int* __restrict__ ci,
+                                                       const double* __restrict__ v,
+                                                       const unsigned char* __restrict__ strong,
+                                                       const int* __restrict__ agg1,
+                                                       int* __restrict__ agg, int* __restrict__ flag) {
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / LPR, lane = threadIdx.x % LPR;
+  const int a1 = i < n ? agg1[i] : 0;
+  double best = -1.0;
+  int bestj = INT32_MAX;
+  int any = 0;
+  if (i < n && a1 < 0) {
+    for (int k = rp[i] + lane; k < rp[i + 1]; k += LPR) {
       if (!strong[k]) continue;
-      any_strong = true;
-      int j = ci[k];
+      any = 1;
+      const int j = ci[k];
       if (agg1[j] < 0) continue;
-      double w = fabs(v[k]);
+      const double w = fabs(v[k]);
       if (w > best || (w == best && j < bestj)) { best = w; bestj = j; }
     }
-    if (bestj >= 0) a = agg1[bestj];
-    else if (any_strong) atomicOr(flag, 1);
   }
-  agg[i] = a;
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) {
+    const double wb = __shfl_down(best, o, LPR);
+    const int jb = __shfl_down(bestj, o, LPR);
+    if (wb > best || (wb == best && jb < bestj)) { best = wb; bestj = jb; }
+  }
+  any = group_max<LPR>(any);
+  if (i < n && lane == 0) {
+    int a = a1;
+    if (a < 0) {
+      if (best >= 0.0) a = agg1[bestj];
+      else if (any) atomicOr(flag, 1);
+    }
+    agg[i] = a;
+  }
 }
 
 __global__ void k_agg_count(int n, const int* __restrict__ agg, int* __restrict__ cnt) {
@@ -229,29 +294,66 @@ __global__ void k_gershgorin(int n, const int* __restrict__ rp, const double* __
   if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(r));
 }
 
-__global__ void k_diag(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                       const double* __restrict__ v, double* __restrict__ diag,
-                       int* __restrict__ flag) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  double d = 0.0;
-  for (int k = rp[i]; k < rp[i + 1]; ++k)
-    if (ci[k] == i) d = v[k];
-  diag[i] = d;
-  if (!(d > 0.0)) atomicOr(flag, 1);
+template <int LPR>
+__global__ void __launch_bounds__(kBlock) k_diag(int n, const int* __restrict__ rp,
+                                                 const int* __restrict__ ci,
+                                                 const double* __restrict__ v,
+                                                 double* __restrict__ diag, int* __restrict__ flag) {
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / LPR, lane = threadIdx.x % LPR;
+  double d = 0.0;  // only the lane holding the diagonal adds a nonzero term
+  if (i < n)
+    for (int k = rp[i] + lane; k < rp[i + 1]; k += LPR)
+      if (ci[k] == i) d = v[k];
+  d = group_sum<LPR>(d);
+  if (i < n && lane == 0) {
+    diag[i] = d;
+    if (!(d > 0.0)) atomicOr(flag, 1);
+  }
 }
 
 // ------------------------------------------------------------------ sparse products
 __device__ __forceinline__ uint32_t slot_hash(int key) { return fmix32((uint32_t)key); }
 
 // Upper bound of the entries of every row of C = A B: the number of products.
-__global__ void k_spgemm_bound(int n, const int* __restrict__ arp, const int* __restrict__ aci,
-                               const int* __restrict__ brp, int* __restrict__ ub) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
+template <int LPR>
+__global__ void __launch_bounds__(kBlock) k_spgemm_bound(int n, const int* __restrict__ arp,
+                                                         const int* __restrict__ aci,
+                                                         const int* __restrict__ brp,
+                                                         int* __restrict__ ub) {
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / LPR, lane = threadIdx.x % LPR;
   long long s = 0;
-  for (int a = arp[i]; a < arp[i + 1]; ++a) s += brp[aci[a] + 1] - brp[aci[a]];
-  ub[i] = s > (1 << 30) ? (1 << 30) : (int)s;
+  if (i < n)
+    for (int a = arp[i] + lane; a < arp[i + 1]; a += LPR) s += brp[aci[a] + 1] - brp[aci[a]];
+  s = group_sum<LPR>(s);
+  if (i < n && lane == 0) ub[i] = s > (1 << 30) ? (1 << 30) : (int)s;
+}
+
+// Rows of A up to kStageA entries have their columns, values and the
+// extents of the matching rows of B staged in LDS before the product loop,
+// so each step of the loop waits on a single global load.
+constexpr int kStageA = 256;
+
+struct RowStage {
+  int j[kStageA];
+  int b0[kStageA];
+  int b1[kStageA];
+  double av[kStageA];
+};
+
+// Stage row i of A (if short enough); returns whether it was staged.
+__device__ __forceinline__ bool stage_row(RowStage& st, int a0, int len, const int* __restrict__ aci,
+                                          const double* __restrict__ av,
+                                          const int* __restrict__ brp) {
+  if (len > kStageA) return false;
+  for (int a = threadIdx.x; a < len; a += kWave) {
+    const int j = aci[a0 + a];
+    st.j[a] = j;
+    st.b0[a] = brp[j];
+    st.b1[a] = brp[j + 1];
+    if (av) st.av[a] = av[a0 + a];
+  }
+  __syncthreads();
+  return true;
 }
 
 // Symbolic C = A B: number of distinct columns in every row of C.
@@ -264,14 +366,25 @@ __global__ void __launch_bounds__(kWave) k_spgemm_count(
     const int* __restrict__ bci, int* __restrict__ counts, int* __restrict__ flag) {
   __shared__ int keys[H];
   __shared__ int cnt;
+  __shared__ RowStage st;
   const int i = blockIdx.x, t = threadIdx.x;
   for (int s = t; s < H; s += kWave) keys[s] = -1;
   if (t == 0) cnt = 0;
+  const int a0 = arp[i], len = arp[i + 1] - a0;
+  const bool staged = stage_row(st, a0, len, aci, nullptr, brp);
   __syncthreads();
   bool overflow = false;
-  for (int a = arp[i]; a < arp[i + 1]; ++a) {
-    const int j = aci[a];
-    for (int b = brp[j] + t; b < brp[j + 1]; b += kWave) {
+  for (int a = 0; a < len; ++a) {
+    int b0, b1;
+    if (staged) {
+      b0 = st.b0[a];
+      b1 = st.b1[a];
+    } else {
+      const int j = aci[a0 + a];
+      b0 = brp[j];
+      b1 = brp[j + 1];
+    }
+    for (int b = b0 + t; b < b1; b += kWave) {
       const int key = bci[b];
       uint32_t s = slot_hash(key) & (H - 1);
       int probes = 0;
@@ -283,7 +396,6 @@ __global__ void __launch_bounds__(kWave) k_spgemm_count(
         if (++probes >= H) { overflow = true; break; }
       }
     }
-    __syncthreads();
   }
   if (overflow) atomicOr(flag, 1);
   __syncthreads();
@@ -306,14 +418,27 @@ __global__ void __launch_bounds__(kWave) k_spgemm_fill(
   __shared__ double vals[H];
   __shared__ int list[H];
   __shared__ int cnt;
+  __shared__ RowStage st;
   const int i = blockIdx.x, t = threadIdx.x;
   for (int s = t; s < H; s += kWave) { keys[s] = -1; vals[s] = 0.0; }
   if (t == 0) cnt = 0;
+  const int a0 = arp[i], len = arp[i + 1] - a0;
+  const bool staged = stage_row(st, a0, len, aci, av, brp);
   __syncthreads();
-  for (int a = arp[i]; a < arp[i + 1]; ++a) {
-    const int j = aci[a];
-    const double x = av[a];
-    for (int b = brp[j] + t; b < brp[j + 1]; b += kWave) {
+  for (int a = 0; a < len; ++a) {
+    int b0, b1;
+    double x;
+    if (staged) {
+      b0 = st.b0[a];
+      b1 = st.b1[a];
+      x = st.av[a];
+    } else {
+      const int j = aci[a0 + a];
+      b0 = brp[j];
+      b1 = brp[j + 1];
+      x = av[a0 + a];
+    }
+    for (int b = b0 + t; b < b1; b += kWave) {
       const int key = bci[b];
       uint32_t s = slot_hash(key) & (H - 1);
       for (int probes = 0; probes < H; ++probes) {
@@ -411,6 +536,106 @@ __global__ void __launch_bounds__(1024) k_dense_inverse(int n, double* __restric
   }
 }
 
+// The same elimination done in place in LDS (the identity half implicit):
+// at step k the pivot row is divided by the pivot with a_kk replaced by 1,
+// and every other row i gets a_ij -= f_i a_kj with a_ik replaced by 0.
+// G holds the n x 2n array [A | I]; only its left half is read.
+__global__ void __launch_bounds__(1024) k_dense_inverse_lds(int n, const double* __restrict__ G,
+                                                            double* __restrict__ Ainv,
+                                                            int* __restrict__ flag) {
+  extern __shared__ double M[];
+  __shared__ double f[kDenseMax];
+  __shared__ double piv;
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int p = t; p < n * n; p += nt) M[p] = G[(size_t)(p / n) * 2 * n + (p % n)];
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (t == 0) {
+      double d = M[k * n + k];
+      if (!(d > 0.0)) { atomicOr(flag, 2); d = 1.0; }
+      piv = d;
+    }
+    for (int i = t; i < n; i += nt) f[i] = M[i * n + k];
+    __syncthreads();
+    const double inv = 1.0 / piv;
+    for (int j = t; j < n; j += nt) M[k * n + j] = (j == k ? 1.0 : M[k * n + j]) * inv;
+    __syncthreads();
+    for (int p = t; p < n * n; p += nt) {
+      const int i = p / n, j = p % n;
+      if (i != k) M[p] = (j == k ? 0.0 : M[p]) - f[i] * M[k * n + j];
+    }
+    __syncthreads();
+  }
+  for (int p = t; p < n * n; p += nt) Ainv[p] = M[p];
+}
+
+// The same in-place elimination with the matrix held in registers.  With
+// G = 1024 / n row groups, thread t < G n owns column j = t mod n and rows
+// i = g, g + G, g + 2G, ... (g = t / n), at most E of them; the pivot column
+// and the scaled pivot row are exchanged through LDS.
+template <int E>
+__global__ void __launch_bounds__(1024) k_dense_inverse_reg(int n, const double* __restrict__ Gm,
+                                                            double* __restrict__ Ainv,
+                                                            int* __restrict__ flag) {
+  __shared__ double colk[kDenseMax];
+  __shared__ double rowk[kDenseMax];
+  __shared__ double piv;
+  const int t = threadIdx.x;
+  const int G = 1024 / n;
+  const bool owner = t < G * n;
+  const int j = owner ? t % n : 0, g = owner ? t / n : 0;
+  double a[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int i = g + G * m;
+    a[m] = (owner && i < n) ? Gm[(size_t)i * 2 * n + j] : 0.0;
+  }
+  for (int k = 0; k < n; ++k) {
+    if (owner && j == k) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int i = g + G * m;
+        if (i < n) colk[i] = a[m];
+      }
+    }
+    __syncthreads();
+    if (t == 0) {
+      double d = colk[k];
+      if (!(d > 0.0)) { atomicOr(flag, 2); d = 1.0; }
+      piv = d;
+    }
+    __syncthreads();
+    const double inv = 1.0 / piv;
+    const int mk = k / G;  // slot of row k in the owning row group k % G
+    if (owner && g == k % G) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        if (m == mk) {
+          a[m] = (j == k ? 1.0 : a[m]) * inv;
+          rowk[j] = a[m];
+        }
+      }
+    }
+    __syncthreads();
+    if (owner) {
+      const double rj = rowk[j];
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int i = g + G * m;
+        if (i < n && i != k) a[m] = (j == k ? 0.0 : a[m]) - colk[i] * rj;
+      }
+    }
+    __syncthreads();
+  }
+  if (owner) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int i = g + G * m;
+      if (i < n) Ainv[(size_t)i * n + j] = a[m];
+    }
+  }
+}
+
 __global__ void k_densify(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                           const double* __restrict__ v, double* __restrict__ G) {
   int i = blockIdx.x * kBlock + threadIdx.x;
@@ -420,6 +645,20 @@ __global__ void k_densify(int n, const int* __restrict__ rp, const int* __restri
 }
 
 // ------------------------------------------------------------------ host helpers
+// Launch a lane-grouped row kernel K<LPR> over `rows` rows.
+#define PPE_ROWS(LPR_, K, rows, ...)                                                         \
+  do {                                                                                       \
+    const int lpr_ = (LPR_);                                                                 \
+    const int g_ = grid_for((int64_t)(rows) * lpr_);                                         \
+    switch (lpr_) {                                                                          \
+      case 4: hipLaunchKernelGGL(K<4>, dim3(g_), dim3(kBlock), 0, s->stream, __VA_ARGS__); break;   \
+      case 8: hipLaunchKernelGGL(K<8>, dim3(g_), dim3(kBlock), 0, s->stream, __VA_ARGS__); break;   \
+      case 16: hipLaunchKernelGGL(K<16>, dim3(g_), dim3(kBlock), 0, s->stream, __VA_ARGS__); break; \
+      case 32: hipLaunchKernelGGL(K<32>, dim3(g_), dim3(kBlock), 0, s->stream, __VA_ARGS__); break; \
+      default: hipLaunchKernelGGL(K<64>, dim3(g_), dim3(kBlock), 0, s->stream, __VA_ARGS__); break; \
+    }                                                                                        \
+    PPE_LAUNCH_CHECK();                                                                      \
+  } while (0)
 void spgemm(ppe_solver* s, const Csr& A, const Csr& B, Csr& C) {
   require(A.m == B.n, PPE_ERR_INTERNAL, "spgemm shape mismatch");
   C.n = A.n;
@@ -432,9 +671,7 @@ void spgemm(ppe_solver* s, const Csr& A, const Csr& B, Csr& C) {
   }
   int* counts = s->tmp_i[0].get<int>(C.n + 1);
   int* flag = s->flag.get<int>(1);
-  hipLaunchKernelGGL(k_spgemm_bound, dim3(grid_for(C.n)), dim3(kBlock), 0, s->stream, C.n, A.rp(),
-                     A.ci(), B.rp(), counts);
-  PPE_LAUNCH_CHECK();
+  PPE_ROWS(lanes_for(A), k_spgemm_bound, C.n, C.n, A.rp(), A.ci(), B.rp(), counts);
   const int ub = reduce_max_int(s, counts, C.n);
   int Hc = 64;
   while (Hc < 2 * ub && Hc < 2048) Hc *= 2;
@@ -529,9 +766,8 @@ void build_hierarchy(ppe_solver* s) {
     int* flag = s->flag.get<int>(1);
     if (lvl > 0 && n > 0) {
       fill_int(s, flag, 0, 1);
-      hipLaunchKernelGGL(k_diag, dim3(grid_for(n)), dim3(kBlock), 0, s->stream, n, L.A.rp(), L.A.ci(),
-                         L.A.v(), L.diag.get<double>(n), flag);
-      PPE_LAUNCH_CHECK();
+      PPE_ROWS(lanes_for(L.A), k_diag, n, n, L.A.rp(), L.A.ci(), L.A.v(), L.diag.get<double>(n),
+               flag);
       require(read_scalar(s, flag) == 0, PPE_ERR_INTERNAL, "coarse operator lost its diagonal");
     }
     L.rho = spectral_bound(s, L, lvl);
@@ -545,9 +781,9 @@ void build_hierarchy(ppe_solver* s) {
       unsigned char* st = L.state.get<unsigned char>(n);
       unsigned char* st2 = L.state2.get<unsigned char>(n);
       unsigned long long* m1 = L.m1.get<unsigned long long>(n);
-      hipLaunchKernelGGL(k_strength, dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(), L.A.ci(),
-                         L.A.v(), L.diag.as<double>(), theta2, strong, st);
-      PPE_LAUNCH_CHECK();
+      const int lpr = lanes_for(L.A);
+      PPE_ROWS(lpr, k_strength, n, n, L.A.rp(), L.A.ci(), L.A.v(), L.diag.as<double>(), theta2,
+               strong, st);
       const uint32_t salt = level_salt(lvl);
       // rounds run in pairs between host checks; a round after the set is
       // complete changes nothing, so only the second count is read
@@ -555,12 +791,8 @@ void build_hierarchy(ppe_solver* s) {
       while (true) {
         fill_int(s, und, 0, 2);
         for (int k = 0; k < 2; ++k) {
-          hipLaunchKernelGGL(k_mis_max1, dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(),
-                             L.A.ci(), strong, st, salt, m1);
-          PPE_LAUNCH_CHECK();
-          hipLaunchKernelGGL(k_mis_max2, dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(),
-                             L.A.ci(), strong, st, salt, m1, st2, und + k);
-          PPE_LAUNCH_CHECK();
+          PPE_ROWS(lpr, k_mis_max1, n, n, L.A.rp(), L.A.ci(), strong, st, salt, m1);
+          PPE_ROWS(lpr, k_mis_max2, n, n, L.A.rp(), L.A.ci(), strong, st, salt, m1, st2, und + k);
           std::swap(st, st2);
           ++L.mis_rounds;
         }
@@ -575,13 +807,9 @@ void build_hierarchy(ppe_solver* s) {
       if (na > 0) {
         int* agg1 = L.agg1.get<int>(n);
         int* agg = L.agg.get<int>(n);
-        hipLaunchKernelGGL(k_agg_first, dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(), L.A.ci(),
-                           strong, st, root_id, agg1);
-        PPE_LAUNCH_CHECK();
+        PPE_ROWS(lpr, k_agg_first, n, n, L.A.rp(), L.A.ci(), strong, st, root_id, agg1);
         fill_int(s, flag, 0, 1);
-        hipLaunchKernelGGL(k_agg_second, dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(), L.A.ci(),
-                           L.A.v(), strong, agg1, agg, flag);
-        PPE_LAUNCH_CHECK();
+        PPE_ROWS(lpr, k_agg_second, n, n, L.A.rp(), L.A.ci(), L.A.v(), strong, agg1, agg, flag);
         require(read_scalar(s, flag) == 0, PPE_ERR_INTERNAL, "aggregation left a node unassigned");
         L.n_agg = na;
         // aggregate members, coarse near-null vector, tentative prolongator
@@ -652,7 +880,24 @@ void build_hierarchy(ppe_solver* s) {
                          L.A.ci(), L.A.v(), G);
       PPE_LAUNCH_CHECK();
       fill_int(s, flag, 0, 1);
-      hipLaunchKernelGGL(k_dense_inverse, dim3(1), dim3(1024), 0, s->stream, n, G, Ainv, flag);
+      const size_t lds = sizeof(double) * (size_t)n * n;
+      if (lds + sizeof(double) * (kDenseMax + 1) <= s->lds_max) {
+        hipLaunchKernelGGL(k_dense_inverse_lds, dim3(1), dim3(1024), lds, s->stream, n, G, Ainv,
+                           flag);
+      } else if (n <= 256) {
+        const int rows_per = (n + (1024 / n) - 1) / (1024 / n);  // rows one thread owns
+        if (rows_per <= 24)
+          hipLaunchKernelGGL(k_dense_inverse_reg<24>, dim3(1), dim3(1024), 0, s->stream, n, G,
+                             Ainv, flag);
+        else if (rows_per <= 40)
+          hipLaunchKernelGGL(k_dense_inverse_reg<40>, dim3(1), dim3(1024), 0, s->stream, n, G,
+                             Ainv, flag);
+        else
+          hipLaunchKernelGGL(k_dense_inverse_reg<64>, dim3(1), dim3(1024), 0, s->stream, n, G,
+                             Ainv, flag);
+      } else {
+        hipLaunchKernelGGL(k_dense_inverse, dim3(1), dim3(1024), 0, s->stream, n, G, Ainv, flag);
+      }
       PPE_LAUNCH_CHECK();
       require(read_scalar(s, flag) == 0, PPE_ERR_INTERNAL, "coarsest operator is not positive definite");
       L.dense = true;

@@ -119,6 +119,9 @@ ppe_status ppe_create(const ppe_options* opt, ppe_solver** out) {
     s->stream = static_cast<hipStream_t>(o.stream);
     try {
       PPE_HIP(hipGetDevice(&s->device));
+      int lds = 0;
+      PPE_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, s->device));
+      s->lds_max = (size_t)lds;
       PPE_HIP(hipEventCreate(&s->ev0));
       PPE_HIP(hipEventCreate(&s->ev1));
       s->levels.reserve(o.max_levels + 1);
@@ -177,6 +180,7 @@ ppe_status ppe_assemble(ppe_solver* s, const double* face_coeff, const double* f
     if (s->n_active > 0) {
       ppe::build_hierarchy(s);
       ppe::prepare_solve_levels(s);
+      if (s->opt.precision == PPE_MIXED) ppe::make_fp32_hierarchy(s);
     } else {
       s->nlev = 1;
     }

@@ -129,6 +129,7 @@ struct ppe_solver {
 
   // mesh topology
   int n_cells = 0, n_faces = 0, max_deg = 0;
+  size_t lds_max = 65536;  // LDS bytes one workgroup may use
   bool have_mesh = false;
   ppe::DevBuf owner, neigh, adj_ptr, adj_nbr, adj_face;
 
@@ -294,6 +295,15 @@ __device__ __forceinline__ bool grid_sum(const double (&v)[NV], double* partials
   return threadIdx.x == 0;
 }
 
+// Lanes per row for row-parallel CSR kernels: the power of two (4..64) at or
+// above the mean row length.
+inline int lanes_for(const Csr& A) {
+  const double mean = A.n ? (double)A.nnz / A.n : 1.0;
+  int lpr = 4;
+  while (lpr < 64 && lpr < mean) lpr *= 2;
+  return lpr;
+}
+
 inline int grid_for(int64_t n, int bs = kBlock) {
   int64_t g = (n + bs - 1) / bs;
   return static_cast<int>(g < 1 ? 1 : g);
@@ -331,6 +341,7 @@ double power_estimate(ppe_solver* s, Level& L, uint32_t salt, int iters);
 void vcycle(ppe_solver* s, int level, const double* b, double* x);
 ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p, int use_x0);
 void prepare_solve_levels(ppe_solver* s);
+void make_fp32_hierarchy(ppe_solver* s);
 void profile_harvest(ppe_solver* s);
 void profile_enable(ppe_solver* s, bool on);
 

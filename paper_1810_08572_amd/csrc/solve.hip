@@ -30,12 +30,11 @@ enum Slot : int { P_BB = 0, P_RR = 1, P_PQ = 2, P_RZ = 3 /* and 4 */, P_RT = 5, 
 // device scalars in s->scal
 enum Scal : int { S_BB = 0, S_RR = 1, S_PQ = 2, S_RZ = 3 /* 3, 4 */, S_RT = 5, S_POW = 6, S_N = 8 };
 
-template <int EPI>
-__device__ __forceinline__ double epilogue(int i, double ax, const double* __restrict__ x,
-                                           const double* __restrict__ b,
-                                           const double* __restrict__ diag, double* __restrict__ d,
-                                           double c1, double c2, double scale,
-                                           double* __restrict__ y) {
+template <int EPI, class T>
+__device__ __forceinline__ double epilogue(int i, T ax, const T* __restrict__ x,
+                                           const T* __restrict__ b, const T* __restrict__ diag,
+                                           T* __restrict__ d, T c1, T c2, T scale,
+                                           T* __restrict__ y) {
   if (EPI == E_SPMV) {
     y[i] = ax;
     return 0.0;
@@ -43,38 +42,37 @@ __device__ __forceinline__ double epilogue(int i, double ax, const double* __res
     y[i] = b[i] - ax;
     return 0.0;
   } else if (EPI == E_CHEB) {
-    const double r = (b[i] - ax) / diag[i];
-    const double dn = (c1 == 0.0 ? 0.0 : c1 * d[i]) + c2 * r;
+    const T r = (b[i] - ax) / diag[i];
+    const T dn = (c1 == T(0) ? T(0) : c1 * d[i]) + c2 * r;
     d[i] = dn;
     y[i] = x[i] + dn;
     return 0.0;
   } else if (EPI == E_DOT) {
     y[i] = ax;
-    return x[i] * ax;
+    return (double)x[i] * (double)ax;
   } else {
-    const double v = (ax / diag[i]) * scale;
+    const T v = (ax / diag[i]) * scale;
     y[i] = v;
-    return v * v;
+    return (double)v * (double)v;
   }
 }
 
 // ---- finest level: ELL, one thread per row (grid-stride)
-template <int EPI>
+template <int EPI, class T>
 __global__ void __launch_bounds__(kBlock) k_ell(int n, int W, const int* __restrict__ ecol,
-                                                const double* __restrict__ eval,
-                                                const double* __restrict__ diag,
-                                                const double* __restrict__ x,
-                                                const double* __restrict__ b, double* __restrict__ d,
-                                                double c1, double c2, double* __restrict__ y,
+                                                const T* __restrict__ eval,
+                                                const T* __restrict__ diag, const T* __restrict__ x,
+                                                const T* __restrict__ b, T* __restrict__ d, T c1,
+                                                T c2, T* __restrict__ y,
                                                 double* __restrict__ partials) {
   double dot = 0.0;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    double s = diag[i] * x[i];
+    T s = diag[i] * x[i];
     for (int k = 0; k < W; ++k) {
       const size_t e = (size_t)k * n + i;
       s = s + eval[e] * x[ecol[e]];
     }
-    dot += epilogue<EPI>(i, s, x, b, diag, d, c1, c2, 1.0, y);
+    dot += epilogue<EPI, T>(i, s, x, b, diag, d, c1, c2, T(1), y);
   }
   if (EPI == E_DOT) {
     double v[1] = {dot};
@@ -84,18 +82,16 @@ __global__ void __launch_bounds__(kBlock) k_ell(int n, int W, const int* __restr
 
 // ---- CSR, LPR lanes per row; every lane runs the same trip count so the
 // group shuffles always see all lanes.
-template <int EPI, int LPR>
+template <int EPI, int LPR, class T>
 __global__ void __launch_bounds__(kBlock) k_csr(int n, const int* __restrict__ rp,
                                                 const int* __restrict__ ci,
-                                                const double* __restrict__ v,
-                                                const double* __restrict__ diag,
-                                                const double* __restrict__ x,
-                                                const double* __restrict__ b, double* __restrict__ d,
-                                                double c1, double c2, double* __restrict__ y,
+                                                const T* __restrict__ v, const T* __restrict__ diag,
+                                                const T* __restrict__ x, const T* __restrict__ b,
+                                                T* __restrict__ d, T c1, T c2, T* __restrict__ y,
                                                 const double* __restrict__ prevp, int gprev,
                                                 double* __restrict__ partials) {
-  double scale = 1.0;
-  if (EPI == E_POWER) scale = 1.0 / sqrt(sum_partials<kBlock>(prevp, gprev));
+  T scale = T(1);
+  if (EPI == E_POWER) scale = T(1.0 / sqrt(sum_partials<kBlock>(prevp, gprev)));
   const int lane = threadIdx.x % LPR;
   const int groups = gridDim.x * (kBlock / LPR);
   const int my = (blockIdx.x * kBlock + threadIdx.x) / LPR;
@@ -103,13 +99,13 @@ __global__ void __launch_bounds__(kBlock) k_csr(int n, const int* __restrict__ r
   double dot = 0.0;
   for (int t = 0; t < trips; ++t) {
     const int g = t * groups + my;
-    double s = 0.0;
+    T s = T(0);
     if (g < n) {
       for (int k = rp[g] + lane; k < rp[g + 1]; k += LPR) s = s + v[k] * x[ci[k]];
     }
 #pragma unroll
     for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_down(s, o, LPR);
-    if (g < n && lane == 0) dot += epilogue<EPI>(g, s, x, b, diag, d, c1, c2, scale, y);
+    if (g < n && lane == 0) dot += epilogue<EPI, T>(g, s, x, b, diag, d, c1, c2, scale, y);
   }
   if (EPI == E_DOT || EPI == E_POWER) {
     double vv[1] = {dot};
@@ -118,15 +114,14 @@ __global__ void __launch_bounds__(kBlock) k_csr(int n, const int* __restrict__ r
 }
 
 // y (+)= M x for a rectangular CSR (prolongation adds into y).
-template <int LPR, bool ADD>
+template <int LPR, bool ADD, class T>
 __global__ void __launch_bounds__(kBlock) k_csr_rect(int n, const int* __restrict__ rp,
                                                      const int* __restrict__ ci,
-                                                     const double* __restrict__ v,
-                                                     const double* __restrict__ x,
-                                                     double* __restrict__ y) {
+                                                     const T* __restrict__ v,
+                                                     const T* __restrict__ x, T* __restrict__ y) {
   const int g = (blockIdx.x * kBlock + threadIdx.x) / LPR;
   const int lane = threadIdx.x % LPR;
-  double s = 0.0;
+  T s = T(0);
   if (g < n) {
     for (int k = rp[g] + lane; k < rp[g + 1]; k += LPR) s = s + v[k] * x[ci[k]];
   }
@@ -136,22 +131,24 @@ __global__ void __launch_bounds__(kBlock) k_csr_rect(int n, const int* __restric
 }
 
 // First Chebyshev step from a zero guess: d = b / (theta diag); x = d.
-__global__ void k_cheb_first(int n, const double* __restrict__ b, const double* __restrict__ diag,
-                             double inv_theta, double* __restrict__ d, double* __restrict__ x) {
+template <class T>
+__global__ void k_cheb_first(int n, const T* __restrict__ b, const T* __restrict__ diag,
+                             T inv_theta, T* __restrict__ d, T* __restrict__ x) {
   int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  double v = inv_theta * (b[i] / diag[i]);
+  T v = inv_theta * (b[i] / diag[i]);
   d[i] = v;
   x[i] = v;
 }
 
 // Dense coarsest solve x = Ainv b: one wave per row, lanes over columns.
-__global__ void __launch_bounds__(kBlock) k_dense_gemv(int n, const double* __restrict__ Ainv,
-                                                       const double* __restrict__ b,
-                                                       double* __restrict__ x) {
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_dense_gemv(int n, const T* __restrict__ Ainv,
+                                                       const T* __restrict__ b,
+                                                       T* __restrict__ x) {
   const int i = (blockIdx.x * kBlock + threadIdx.x) / kWave;
   const int lane = threadIdx.x % kWave;
-  double s = 0.0;
+  T s = T(0);
   if (i < n)
     for (int j = lane; j < n; j += kWave) s = s + Ainv[(size_t)i * n + j] * b[j];
   s = wave_sum(s);
@@ -269,16 +266,16 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ 
   }
 }
 
+template <class S, class D>
+__global__ void k_cast(int64_t n, const S* __restrict__ a, D* __restrict__ b) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock)
+    b[i] = (D)a[i];
+}
+
 __global__ void k_copy(int n, const double* __restrict__ a, double* __restrict__ b) {
   int i = blockIdx.x * kBlock + threadIdx.x;
   if (i < n) b[i] = a[i];
-}
-
-int lanes_for(const Csr& A) {
-  const double mean = A.n ? (double)A.nnz / A.n : 1.0;
-  int lpr = 4;
-  while (lpr < 64 && lpr < mean) lpr *= 2;
-  return lpr;
 }
 
 double* part(ppe_solver* s, int slot) {
@@ -287,11 +284,28 @@ double* part(ppe_solver* s, int slot) {
 
 constexpr size_t kProfPairs = 256;
 
-// Apply the level operator with epilogue EPI.  Dot/power epilogues run on a
-// capped grid and write partials to `partials`; returns that grid size.
-template <int EPI>
-int apply_op(ppe_solver* s, const Level& L, const double* x, const double* b, double* d, double c1,
-             double c2, double* y, double* partials, const double* prevp = nullptr, int gprev = 0) {
+// Matrix and diagonal arrays of a level in value type T (FP32 copies exist
+// when the solver runs the mixed-precision V-cycle).
+template <class T> struct LevelData;
+template <> struct LevelData<double> {
+  static const double* ell(const Level& L) { return L.ell_val.as<double>(); }
+  static const double* diag(const Level& L) { return L.diag.as<double>(); }
+  static const double* val(const Csr& A) { return A.v(); }
+  static const double* ainv(const Level& L) { return L.Ainv.as<double>(); }
+};
+template <> struct LevelData<float> {
+  static const float* ell(const Level& L) { return L.ell_valf.as<float>(); }
+  static const float* diag(const Level& L) { return L.diagf.as<float>(); }
+  static const float* val(const Csr& A) { return A.vf(); }
+  static const float* ainv(const Level& L) { return L.Ainvf.as<float>(); }
+};
+
+// Apply the level operator with epilogue EPI in value type T.  Dot/power
+// epilogues run on a capped grid and write partials to `partials`; returns
+// that grid size.
+template <int EPI, class T = double>
+int apply_op(ppe_solver* s, const Level& L, const T* x, const T* b, T* d, double c1, double c2,
+             T* y, double* partials, const double* prevp = nullptr, int gprev = 0) {
   const int n = L.n;
   if (n == 0) return 1;
   const bool reduce = EPI == E_DOT || EPI == E_POWER;
@@ -303,25 +317,25 @@ int apply_op(ppe_solver* s, const Level& L, const double* x, const double* b, do
       const size_t k = s->prof_pending.size();
       PPE_HIP(hipEventRecord(s->prof_ev[2 * k], s->stream));
     }
-    hipLaunchKernelGGL(k_ell<EPI>, dim3(g), dim3(kBlock), 0, s->stream, n, L.W,
-                       L.ell_col.as<int>(), L.ell_val.as<double>(), L.diag.as<double>(), x, b, d,
-                       c1, c2, y, partials);
+    hipLaunchKernelGGL((k_ell<EPI, T>), dim3(g), dim3(kBlock), 0, s->stream, n, L.W,
+                       L.ell_col.as<int>(), LevelData<T>::ell(L), LevelData<T>::diag(L), x, b, d,
+                       (T)c1, (T)c2, y, partials);
     PPE_LAUNCH_CHECK();
     if (prof) {
       const size_t k = s->prof_pending.size();
       PPE_HIP(hipEventRecord(s->prof_ev[2 * k + 1], s->stream));
       const double off = (double)(L.A.nnz - n);
       const double vecs = (c1 != 0.0) ? 6.0 : 5.0;  // diag, x_in, b, x_out, d out (+ d in)
-      s->prof_pending.push_back(off * 12.0 + vecs * 8.0 * n);
+      s->prof_pending.push_back(off * (sizeof(T) + 4.0) + vecs * sizeof(T) * n);
     }
     return g;
   }
   const int lpr = lanes_for(L.A);
   const int g = reduce ? red_grid((int64_t)n * lpr) : grid_for((int64_t)n * lpr);
-#define PPE_CSR(LL)                                                                           \
-  hipLaunchKernelGGL((k_csr<EPI, LL>), dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(),      \
-                     L.A.ci(), L.A.v(), L.diag.as<double>(), x, b, d, c1, c2, y, prevp, gprev, \
-                     partials)
+#define PPE_CSR(LL)                                                                            \
+  hipLaunchKernelGGL((k_csr<EPI, LL, T>), dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(),    \
+                     L.A.ci(), LevelData<T>::val(L.A), LevelData<T>::diag(L), x, b, d, (T)c1,   \
+                     (T)c2, y, prevp, gprev, partials)
   switch (lpr) {
     case 4: PPE_CSR(4); break;
     case 8: PPE_CSR(8); break;
@@ -334,14 +348,14 @@ int apply_op(ppe_solver* s, const Level& L, const double* x, const double* b, do
   return g;
 }
 
-template <bool ADD>
-void apply_rect(ppe_solver* s, const Csr& M, const double* x, double* y) {
+template <bool ADD, class T>
+void apply_rect(ppe_solver* s, const Csr& M, const T* x, T* y) {
   if (M.n == 0) return;
   const int lpr = lanes_for(M);
   const int g = grid_for((int64_t)M.n * lpr);
-#define PPE_RECT(LL)                                                                        \
-  hipLaunchKernelGGL((k_csr_rect<LL, ADD>), dim3(g), dim3(kBlock), 0, s->stream, M.n, M.rp(), \
-                     M.ci(), M.v(), x, y)
+#define PPE_RECT(LL)                                                                           \
+  hipLaunchKernelGGL((k_csr_rect<LL, ADD, T>), dim3(g), dim3(kBlock), 0, s->stream, M.n, M.rp(), \
+                     M.ci(), LevelData<T>::val(M), x, y)
   switch (lpr) {
     case 4: PPE_RECT(4); break;
     case 8: PPE_RECT(8); break;
@@ -356,25 +370,65 @@ void apply_rect(ppe_solver* s, const Csr& M, const double* x, double* y) {
 // Chebyshev smoothing of A x = b.  x_in == nullptr: zero initial guess.
 // The result is written to x_out; xa/xb are ping-pong buffers distinct from
 // x_in and x_out.
-void smooth(ppe_solver* s, Level& L, const double* b, const double* x_in, double* x_out, double* xa,
-            double* xb) {
+template <class T>
+void smooth(ppe_solver* s, Level& L, const T* b, const T* x_in, T* x_out, T* xa, T* xb) {
   const int n = L.n;
   const int deg = 1 + (int)L.c1.size();
-  double* d = L.d.as<double>();
-  const double* cur = x_in;
+  T* d = L.d.as<T>();
+  const T* cur = x_in;
   for (int step = 1; step <= deg; ++step) {
-    double* dst = step == deg ? x_out : ((step % 2) ? xa : xb);
+    T* dst = step == deg ? x_out : ((step % 2) ? xa : xb);
     if (step == 1 && cur == nullptr) {
-      hipLaunchKernelGGL(k_cheb_first, dim3(grid_for(n)), dim3(kBlock), 0, s->stream, n, b,
-                         L.diag.as<double>(), L.inv_theta, d, dst);
+      hipLaunchKernelGGL(k_cheb_first<T>, dim3(grid_for(n)), dim3(kBlock), 0, s->stream, n, b,
+                         LevelData<T>::diag(L), (T)L.inv_theta, d, dst);
       PPE_LAUNCH_CHECK();
     } else if (step == 1) {
-      apply_op<E_CHEB>(s, L, cur, b, d, 0.0, L.inv_theta, dst, nullptr);
+      apply_op<E_CHEB, T>(s, L, cur, b, d, 0.0, L.inv_theta, dst, nullptr);
     } else {
-      apply_op<E_CHEB>(s, L, cur, b, d, L.c1[step - 2], L.c2[step - 2], dst, nullptr);
+      apply_op<E_CHEB, T>(s, L, cur, b, d, L.c1[step - 2], L.c2[step - 2], dst, nullptr);
     }
     cur = dst;
   }
+}
+
+// One V-cycle with zero initial guess, x = M b on level l, in value type T.
+template <class T>
+void vcycle_t(ppe_solver* s, int l, const T* b, T* x) {
+  Level& L = s->levels[l];
+  const int n = L.n;
+  if (n == 0) return;
+  T* xa = L.x2.as<T>();
+  T* xb = L.d2.as<T>();
+  if (l == s->nlev - 1) {
+    if (L.dense) {
+      hipLaunchKernelGGL(k_dense_gemv<T>, dim3(grid_for((int64_t)n * kWave)), dim3(kBlock), 0,
+                         s->stream, n, LevelData<T>::ainv(L), b, x);
+      PPE_LAUNCH_CHECK();
+    } else {
+      T* t = L.r.as<T>();
+      smooth<T>(s, L, b, nullptr, t, xa, xb);
+      smooth<T>(s, L, b, t, x, xa, xb);
+    }
+    return;
+  }
+  Level& C = s->levels[l + 1];
+  T* x1 = L.t.as<T>();  // pre-smoothed iterate, corrected in place
+  T* r = L.r.as<T>();
+  smooth<T>(s, L, b, nullptr, x1, xa, xb);
+  apply_op<E_RESID, T>(s, L, x1, b, nullptr, 0.0, 0.0, r, nullptr);
+  apply_rect<false, T>(s, L.R, r, C.b.as<T>());
+  vcycle_t<T>(s, l + 1, C.b.as<T>(), C.x.as<T>());
+  apply_rect<true, T>(s, L.P, C.x.as<T>(), x1);
+  smooth<T>(s, L, b, x1, x, xa, xb);
+}
+
+template <class S, class D>
+void cast(ppe_solver* s, const S* a, D* b, int64_t n) {
+  if (n <= 0) return;
+  int g = grid_for(n);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL((k_cast<S, D>), dim3(g), dim3(kBlock), 0, s->stream, n, a, b);
+  PPE_LAUNCH_CHECK();
 }
 
 }  // namespace
@@ -408,7 +462,7 @@ void profile_enable(ppe_solver* s, bool on) {
 }
 
 void spmv(ppe_solver* s, const Level& L, const double* x, double* y) {
-  apply_op<E_SPMV>(s, L, x, nullptr, nullptr, 0.0, 0.0, y, nullptr);
+  apply_op<E_SPMV, double>(s, L, x, nullptr, nullptr, 0.0, 0.0, y, nullptr);
 }
 
 double power_estimate(ppe_solver* s, Level& L, uint32_t salt, int iters) {
@@ -423,7 +477,7 @@ double power_estimate(ppe_solver* s, Level& L, uint32_t salt, int iters) {
   hipLaunchKernelGGL(k_power_init, dim3(g), dim3(kBlock), 0, s->stream, n, salt, x, pa);
   PPE_LAUNCH_CHECK();
   for (int it = 0; it < iters; ++it) {
-    g = apply_op<E_POWER>(s, L, x, nullptr, nullptr, 0.0, 0.0, y, pb, pa, g);
+    g = apply_op<E_POWER, double>(s, L, x, nullptr, nullptr, 0.0, 0.0, y, pb, pa, g);
     std::swap(x, y);
     std::swap(pa, pb);
   }
@@ -460,34 +514,39 @@ void prepare_solve_levels(ppe_solver* s) {
   }
 }
 
-// One V-cycle with zero initial guess: x = M b on level l.
+// z = M r with the V-cycle in the solver's precision: FP64 throughout, or
+// (mixed) r rounded to FP32 on entry, an FP32 V-cycle, z widened on exit.
 void vcycle(ppe_solver* s, int l, const double* b, double* x) {
-  Level& L = s->levels[l];
-  const int n = L.n;
-  if (n == 0) return;
-  double* xa = L.x2.as<double>();
-  double* xb = L.d2.as<double>();
-  if (l == s->nlev - 1) {
-    if (L.dense) {
-      hipLaunchKernelGGL(k_dense_gemv, dim3(grid_for((int64_t)n * kWave)), dim3(kBlock), 0,
-                         s->stream, n, L.Ainv.as<double>(), b, x);
-      PPE_LAUNCH_CHECK();
-    } else {
-      double* t = L.r.as<double>();
-      smooth(s, L, b, nullptr, t, xa, xb);
-      smooth(s, L, b, t, x, xa, xb);
-    }
+  if (s->opt.precision != PPE_MIXED) {
+    vcycle_t<double>(s, l, b, x);
     return;
   }
-  Level& C = s->levels[l + 1];
-  double* x1 = L.t.as<double>();  // pre-smoothed iterate, corrected in place
-  double* r = L.r.as<double>();
-  smooth(s, L, b, nullptr, x1, xa, xb);
-  apply_op<E_RESID>(s, L, x1, b, nullptr, 0.0, 0.0, r, nullptr);
-  apply_rect<false>(s, L.R, r, C.b.as<double>());
-  vcycle(s, l + 1, C.b.as<double>(), C.x.as<double>());
-  apply_rect<true>(s, L.P, C.x.as<double>(), x1);
-  smooth(s, L, b, x1, x, xa, xb);
+  Level& L = s->levels[l];
+  cast<double, float>(s, b, L.b.as<float>(), L.n);
+  vcycle_t<float>(s, l, L.b.as<float>(), L.x.as<float>());
+  cast<float, double>(s, L.x.as<float>(), x, L.n);
+}
+
+// FP32 copies of the hierarchy for the mixed-precision V-cycle.
+void make_fp32_hierarchy(ppe_solver* s) {
+  for (int l = 0; l < s->nlev; ++l) {
+    Level& L = s->levels[l];
+    if (L.n == 0) continue;
+    cast<double, float>(s, L.diag.as<double>(), L.diagf.get<float>(L.n), L.n);
+    if (l == 0) {
+      const int64_t e = (int64_t)(L.W > 0 ? L.W : 1) * L.n;
+      cast<double, float>(s, L.ell_val.as<double>(), L.ell_valf.get<float>(e), e);
+    } else {
+      cast<double, float>(s, L.A.v(), L.A.valf.get<float>(L.A.nnz), L.A.nnz);
+    }
+    if (l < s->nlev - 1) {
+      cast<double, float>(s, L.P.v(), L.P.valf.get<float>(L.P.nnz), L.P.nnz);
+      cast<double, float>(s, L.R.v(), L.R.valf.get<float>(L.R.nnz), L.R.nnz);
+    } else if (L.dense) {
+      const int64_t nn = (int64_t)L.n * L.n;
+      cast<double, float>(s, L.Ainv.as<double>(), L.Ainvf.get<float>(nn), nn);
+    }
+  }
 }
 
 ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0) {
@@ -522,7 +581,7 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
   if (use_x0) {
     hipLaunchKernelGGL(k_gather_x0, dim3(ge), dim3(kBlock), 0, s->stream, na, perm, comp, p_out, x);
     PPE_LAUNCH_CHECK();
-    apply_op<E_RESID>(s, L0, x, b, nullptr, 0.0, 0.0, r, nullptr);
+    apply_op<E_RESID, double>(s, L0, x, b, nullptr, 0.0, 0.0, r, nullptr);
   } else {
     fill_double(s, x, 0.0, na);
     hipLaunchKernelGGL(k_copy, dim3(ge), dim3(kBlock), 0, s->stream, na, b, r);
@@ -548,7 +607,7 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
     return status;
   };
   auto true_residual = [&]() {
-    apply_op<E_RESID>(s, L0, x, b, nullptr, 0.0, 0.0, q, nullptr);
+    apply_op<E_RESID, double>(s, L0, x, b, nullptr, 0.0, 0.0, q, nullptr);
     hipLaunchKernelGGL(k_norm2, dim3(gv), dim3(kBlock), 0, s->stream, na, q, part(s, P_RT));
     PPE_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s->stream, part(s, P_RT), nullptr, gv,
@@ -572,7 +631,7 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
   const int max_iter = s->opt.max_iter;
   for (int it = 1; it <= max_iter; ++it) {
     double* rzc = sc + S_RZ + slot;
-    const int gq = apply_op<E_DOT>(s, L0, p, nullptr, nullptr, 0.0, 0.0, q, part(s, P_PQ));
+    const int gq = apply_op<E_DOT, double>(s, L0, p, nullptr, nullptr, 0.0, 0.0, q, part(s, P_PQ));
     hipLaunchKernelGGL(k_update_xr, dim3(gv), dim3(kBlock), 0, s->stream, na, rzc, part(s, P_PQ), gq,
                        p, q, x, r, part(s, P_RR));
     PPE_LAUNCH_CHECK();
