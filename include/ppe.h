@@ -64,7 +64,7 @@ typedef struct {
   int max_iter;       /* PCG iteration cap, default 500 */
   int cheb_degree;    /* Chebyshev smoother degree per application, default 2 */
   double cheb_ratio;  /* smoothing interval [rho/ratio, rho], default 30 */
-  int coarse_max;     /* stop coarsening at <= this many rows, default 256 */
+  int coarse_max;     /* stop coarsening at <= this many rows, default 128 */
   int max_levels;     /* hierarchy depth cap, default 10 */
   double theta;       /* strength threshold, default 0.08 */
   int check_every;    /* PCG iterations between host convergence checks, default 1 */
@@ -120,7 +120,27 @@ ppe_status ppe_assemble(ppe_solver* s, const double* face_coeff,
 ppe_status ppe_solve(ppe_solver* s, const double* rhs, double* p, int use_x0,
                      ppe_stats* stats);
 
-/* Statistics of the last assemble/solve. */
+/* Independent samples (uncertainty-quantification batches, section 3 of the
+ * paper runs one deterministic simulation per collocation sample): cells
+ * [cell_offsets[k], cell_offsets[k+1]) form sample k.  offsets is a HOST
+ * array of n_samples + 1 ascending ints from 0 to n_cells; no interior face
+ * may join two samples.  Each sample then gets its own conjugate-gradient
+ * scalars and its own stopping test ||b'_k - A_k p_k|| <= rtol ||b'_k||, so
+ * one call solves every sample as if it were solved alone; the AMG
+ * hierarchy is shared (it never couples samples).  Setting one sample that
+ * covers all cells restores the default.  Call after ppe_set_mesh; takes
+ * effect at the next ppe_assemble.
+ * Errors: PPE_ERR_STATE before ppe_set_mesh; PPE_ERR_ARG for bad offsets or
+ * a face joining two samples. */
+ppe_status ppe_set_segments(ppe_solver* s, int32_t n_samples, const int32_t* cell_offsets);
+
+/* Per-sample results of the last solve: PCG iterations until that sample
+ * met its tolerance, and its true relative residual.  Host arrays of
+ * n_samples (from ppe_set_segments; 1 by default). */
+ppe_status ppe_get_segment_stats(const ppe_solver* s, int32_t* iterations, double* rel_residual);
+
+/* Statistics of the last assemble/solve.  With several samples, iterations
+ * and rel_residual are the maxima over the samples. */
 ppe_status ppe_get_stats(const ppe_solver* s, ppe_stats* stats);
 
 const char* ppe_status_string(ppe_status st);

@@ -35,7 +35,7 @@ parameter.  This project's reading is smoothed aggregation:
              [rho / 30, rho];
   cycle      V-cycle with the same smoother before and after the coarse
              correction (so the preconditioner is symmetric); the coarsest
-             level (at most coarse_max rows, default 256) is solved with a
+             level (at most coarse_max rows, default 128) is solved with a
              dense inverse.
 """
 from __future__ import annotations
@@ -256,7 +256,7 @@ class Hierarchy:
         return sum(l.A.nnz for l in self.levels) / nnz0 if nnz0 else 1.0
 
 
-def build_hierarchy(A0: sp.csr_matrix, theta=0.08, coarse_max=256, max_levels=10,
+def build_hierarchy(A0: sp.csr_matrix, theta=0.08, coarse_max=128, max_levels=10,
                     degree=2, ratio=30.0, dense_max=4096) -> Hierarchy:
     H = Hierarchy(degree=degree, ratio=ratio)
     A = A0.tocsr()

@@ -84,6 +84,9 @@ _SIGS = {
     "ppe_copy_mask": (ctypes.c_int, [_P, _P, _P]),
     "ppe_apply_matrix": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
     "ppe_apply_vcycle": (ctypes.c_int, [_P, _P, _P]),
+    "ppe_set_segments": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_I32)]),
+    "ppe_get_segment_stats": (ctypes.c_int, [_P, ctypes.POINTER(_I32),
+                                             ctypes.POINTER(ctypes.c_double)]),
     "ppe_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "ppe_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double),
@@ -190,7 +193,7 @@ class Solver:
     """Pressure solver bound to the current device and torch stream."""
 
     def __init__(self, precision="fp64", rtol=1e-10, max_iter=500, cheb_degree=2,
-                 cheb_ratio=30.0, coarse_max=256, max_levels=10, theta=0.08, stream=None):
+                 cheb_ratio=30.0, coarse_max=128, max_levels=10, theta=0.08, stream=None):
         import torch
 
         lib = load_library()
@@ -227,6 +230,21 @@ class Solver:
                                          _dev_ptr(owner, torch.int32, nf, "owner"),
                                          _dev_ptr(neigh, torch.int32, nf, "neigh")))
         self.n_cells, self.n_faces = int(n_cells), int(nf)
+        self.n_seg = 1
+
+    def set_segments(self, cell_offsets):
+        """Declare independent samples: cells [off[k], off[k+1]) form sample k."""
+        off = [int(v) for v in cell_offsets]
+        arr = (_I32 * len(off))(*off)
+        self._chk(self._lib.ppe_set_segments(self._h, len(off) - 1, arr))
+        self.n_seg = len(off) - 1
+
+    def segment_stats(self):
+        n = getattr(self, "n_seg", 1)
+        it = (_I32 * n)()
+        rr = (ctypes.c_double * n)()
+        self._chk(self._lib.ppe_get_segment_stats(self._h, it, rr))
+        return list(it), list(rr)
 
     def assemble(self, face_coeff, liquid_fraction):
         import torch

@@ -91,7 +91,7 @@ void ppe_default_options(ppe_options* o) {
   o->max_iter = 500;
   o->cheb_degree = 2;
   o->cheb_ratio = 30.0;
-  o->coarse_max = 256;
+  o->coarse_max = 128;
   o->max_levels = 10;
   o->theta = 0.08;
   o->check_every = 1;
@@ -163,6 +163,8 @@ ppe_status ppe_set_mesh(ppe_solver* s, int32_t n_cells, int32_t n_faces, const i
     s->n_cells = n_cells;
     s->n_faces = n_faces;
     ppe::build_topology(s, owner, neigh);
+    s->n_seg = 1;
+    s->seg_cell_off = {0, n_cells};
     s->have_mesh = true;
     return PPE_OK;
   });
@@ -214,6 +216,35 @@ ppe_status ppe_solve(ppe_solver* s, const double* rhs, double* p, int use_x0, pp
     if (st == PPE_ERR_BREAKDOWN) s->err = "PCG breakdown (p.Ap <= 0, r.z <= 0 or non-finite)";
     return st;
   });
+}
+
+ppe_status ppe_set_segments(ppe_solver* s, int32_t n_samples, const int32_t* off) {
+  if (!s) return PPE_ERR_ARG;
+  return guarded(s, [&]() -> ppe_status {
+    DeviceGuard g(s->device);
+    ppe::require(s->have_mesh, PPE_ERR_STATE, "ppe_set_segments before ppe_set_mesh");
+    ppe::require(n_samples >= 1 && off != nullptr, PPE_ERR_ARG, "need n_samples >= 1 and offsets");
+    ppe::require(off[0] == 0 && off[n_samples] == s->n_cells, PPE_ERR_ARG,
+                 "offsets must run from 0 to n_cells");
+    for (int k = 0; k < n_samples; ++k)
+      ppe::require(off[k] < off[k + 1], PPE_ERR_ARG, "offsets must be strictly ascending");
+    std::vector<int> o(off, off + n_samples + 1);
+    ppe::check_segments(s, o);
+    s->n_seg = n_samples;
+    s->seg_cell_off = o;
+    s->assembled = false;
+    return PPE_OK;
+  });
+}
+
+ppe_status ppe_get_segment_stats(const ppe_solver* s, int32_t* iterations, double* rel_residual) {
+  if (!s || !iterations || !rel_residual) return PPE_ERR_ARG;
+  if ((int)s->seg_iters_h.size() != s->n_seg) return PPE_ERR_STATE;
+  for (int k = 0; k < s->n_seg; ++k) {
+    iterations[k] = s->seg_iters_h[k];
+    rel_residual[k] = s->seg_res_h[k];
+  }
+  return PPE_OK;
 }
 
 ppe_status ppe_get_stats(const ppe_solver* s, ppe_stats* stats) {

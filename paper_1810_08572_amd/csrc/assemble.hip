@@ -18,6 +18,8 @@
 //                   diagonal (1 when it has no open face).
 #include "common.h"
 
+#include <algorithm>
+
 namespace ppe {
 namespace {
 
@@ -97,12 +99,15 @@ __global__ void k_active(const double* __restrict__ fl, int n, int* __restrict__
   parent[i] = i;
 }
 
-__global__ void k_compact(const int* __restrict__ active, int n, int* __restrict__ cid,
-                          int* __restrict__ perm) {
+// rowpos = exclusive scan of active (kept: segment row offsets read it);
+// cid = rowpos on active cells, -1 elsewhere; perm inverts cid.
+__global__ void k_compact(const int* __restrict__ active, int n, const int* __restrict__ rowpos,
+                          int* __restrict__ cid, int* __restrict__ perm) {
   int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   if (active[i]) {
-    perm[cid[i]] = i;
+    cid[i] = rowpos[i];
+    perm[rowpos[i]] = i;
   } else {
     cid[i] = -1;
   }
@@ -224,7 +229,86 @@ __global__ void k_fill_rows(const int* __restrict__ perm, int n_active,
   }
 }
 
+__global__ void k_gather_int(int n, const int* __restrict__ idx, const int* __restrict__ src,
+                             int* __restrict__ dst) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) dst[i] = src[idx[i]];
+}
+
+// Reduction tiles: runs of at most kTileRows compact rows that never cross a
+// segment boundary; tile t covers rows [r0[t], r1[t]) of segment seg[t], and
+// segment s owns tiles [seg_tile_ptr[s], seg_tile_ptr[s+1]).
+void build_tiles(ppe_solver* s) {
+  const int ns = s->n_seg;
+  int* d_off = s->tmp_i[0].get<int>(ns + 1);
+  int* d_row = s->tmp_i[1].get<int>(ns + 1);
+  PPE_HIP(hipMemcpyAsync(d_off, s->seg_cell_off.data(), sizeof(int) * (ns + 1),
+                         hipMemcpyHostToDevice, s->stream));
+  hipLaunchKernelGGL(k_gather_int, dim3(grid_for(ns + 1)), dim3(kBlock), 0, s->stream, ns + 1, d_off,
+                     s->rowpos.as<int>(), d_row);
+  PPE_LAUNCH_CHECK();
+  s->seg_row_off.assign(ns + 1, 0);
+  PPE_HIP(hipMemcpyAsync(s->seg_row_off.data(), d_row, sizeof(int) * (ns + 1),
+                         hipMemcpyDeviceToHost, s->stream));
+  PPE_HIP(hipStreamSynchronize(s->stream));
+  std::vector<int> r0, r1, sg, tp(ns + 1, 0);
+  for (int q = 0; q < ns; ++q) {
+    tp[q] = (int)r0.size();
+    for (int a = s->seg_row_off[q]; a < s->seg_row_off[q + 1]; a += kTileRows) {
+      r0.push_back(a);
+      r1.push_back(std::min(a + kTileRows, s->seg_row_off[q + 1]));
+      sg.push_back(q);
+    }
+  }
+  tp[ns] = (int)r0.size();
+  s->n_tiles = (int)r0.size();
+  const size_t nt = r0.size() ? r0.size() : 1;
+  int* a = s->tile_r0.get<int>(nt);
+  int* b = s->tile_r1.get<int>(nt);
+  int* c = s->tile_seg.get<int>(nt);
+  int* d = s->seg_tile_ptr.get<int>(ns + 1);
+  if (!r0.empty()) {
+    PPE_HIP(hipMemcpyAsync(a, r0.data(), sizeof(int) * r0.size(), hipMemcpyHostToDevice, s->stream));
+    PPE_HIP(hipMemcpyAsync(b, r1.data(), sizeof(int) * r1.size(), hipMemcpyHostToDevice, s->stream));
+    PPE_HIP(hipMemcpyAsync(c, sg.data(), sizeof(int) * sg.size(), hipMemcpyHostToDevice, s->stream));
+  }
+  PPE_HIP(hipMemcpyAsync(d, tp.data(), sizeof(int) * (ns + 1), hipMemcpyHostToDevice, s->stream));
+  PPE_HIP(hipStreamSynchronize(s->stream));  // host vectors above go out of scope
+}
+
+// flag faces whose two owners lie in different samples
+__global__ void k_check_segments(const int* __restrict__ owner, const int* __restrict__ neigh,
+                                 int n_faces, const int* __restrict__ off, int ns,
+                                 int* __restrict__ flag) {
+  int f = blockIdx.x * kBlock + threadIdx.x;
+  if (f >= n_faces || neigh[f] < 0) return;
+  auto seg_of = [&](int c) {
+    int lo = 0, hi = ns;  // off[lo] <= c < off[hi]
+    while (hi - lo > 1) {
+      int mid = (lo + hi) / 2;
+      if (off[mid] <= c) lo = mid; else hi = mid;
+    }
+    return lo;
+  };
+  if (seg_of(owner[f]) != seg_of(neigh[f])) atomicOr(flag, 1);
+}
+
 }  // namespace
+
+void check_segments(ppe_solver* s, const std::vector<int>& off) {
+  const int ns = (int)off.size() - 1;
+  int* d_off = s->tmp_i[0].get<int>(ns + 1);
+  PPE_HIP(hipMemcpyAsync(d_off, off.data(), sizeof(int) * (ns + 1), hipMemcpyHostToDevice,
+                         s->stream));
+  int* flag = s->flag.get<int>(4);
+  fill_int(s, flag, 0, 1);
+  if (s->n_faces) {
+    hipLaunchKernelGGL(k_check_segments, dim3(grid_for(s->n_faces)), dim3(kBlock), 0, s->stream,
+                       s->owner.as<int>(), s->neigh.as<int>(), s->n_faces, d_off, ns, flag);
+    PPE_LAUNCH_CHECK();
+  }
+  require(read_scalar(s, flag) == 0, PPE_ERR_ARG, "an interior face joins two samples");
+}
 
 void build_topology(ppe_solver* s, const int32_t* owner, const int32_t* neigh) {
   const int nf = s->n_faces, nc = s->n_cells;
@@ -282,13 +366,17 @@ void assemble_fine(ppe_solver* s, const double* coeff, const double* fl) {
   int* active = s->active.get<int>(nc);
   int* parent = s->parent.get<int>(nc);
   int* cid = s->cid.get<int>(nc + 1);
+  int* rowpos = s->rowpos.get<int>(nc + 1);
   hipLaunchKernelGGL(k_active, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, fl, nc, active, parent);
   PPE_LAUNCH_CHECK();
-  const int na = (int)exclusive_scan(s, active, cid, nc);
+  const int na = (int)exclusive_scan(s, active, rowpos, nc);
   s->n_active = na;
   int* perm = s->perm.get<int>(na);
-  hipLaunchKernelGGL(k_compact, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, active, nc, cid, perm);
+  hipLaunchKernelGGL(k_compact, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, active, nc, rowpos,
+                     cid, perm);
   PPE_LAUNCH_CHECK();
+
+  build_tiles(s);
 
   int* comp = s->comp_full.get<int>(nc);
   int* is_pin = s->tmp_i[2].get<int>(nc);

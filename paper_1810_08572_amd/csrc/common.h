@@ -136,7 +136,17 @@ struct ppe_solver {
   // masking
   bool assembled = false;
   int n_active = 0, n_comp = 0;
-  ppe::DevBuf active, cid, perm, parent, comp_full;
+  ppe::DevBuf active, cid, rowpos, perm, parent, comp_full;
+
+  // samples (segments): contiguous cell ranges solved as independent systems
+  int n_seg = 1;
+  std::vector<int> seg_cell_off{0, 0};  // host, n_seg + 1
+  std::vector<int> seg_row_off;         // host, compact rows, n_seg + 1
+  int n_tiles = 0;
+  ppe::DevBuf tile_r0, tile_r1, tile_seg, seg_tile_ptr;  // reduction tiles
+  ppe::DevBuf seg_sc, seg_done, tpart;                   // per-segment scalars, tile partials
+  std::vector<int> seg_iters_h;
+  std::vector<double> seg_res_h;
 
   std::vector<ppe::Level> levels;  // never shrunk, so buffers are reused
   int nlev = 0;                    // levels in use
@@ -227,6 +237,7 @@ __device__ __forceinline__ T block_max(T v) {
 // and value; a consumer kernel sums those partials in a fixed order at the
 // start of every block, so all blocks see the same bitwise result.
 constexpr int kRedBlocks = 1024;
+constexpr int kTileRows = 2048;  // rows per reduction tile of the segmented PCG
 
 template <int BS, int NV>
 __device__ __forceinline__ void write_partials(const double (&v)[NV], double* partials) {
@@ -328,6 +339,7 @@ void fill_double(ppe_solver* s, double* p, double v, int64_t n);
 
 // assemble.hip
 void build_topology(ppe_solver* s, const int32_t* owner, const int32_t* neigh);
+void check_segments(ppe_solver* s, const std::vector<int>& off);
 void assemble_fine(ppe_solver* s, const double* coeff, const double* fl);
 
 // amg.hip

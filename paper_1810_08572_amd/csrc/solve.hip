@@ -24,11 +24,10 @@ enum Epi : int {
   E_POWER = 4,  // y = (A x)/diag / ||x||, partial sums of y.y
 };
 
-// partial-sum slots (each kRedBlocks doubles) in s->partial
-enum Slot : int { P_BB = 0, P_RR = 1, P_PQ = 2, P_RZ = 3 /* and 4 */, P_RT = 5, P_POW = 6 /* 6, 7 */,
-                  P_NSLOTS = 8 };
+// partial-sum slots (each kRedBlocks doubles) in s->partial: power iteration
+enum Slot : int { P_POW = 0 /* 0, 1 */, P_NSLOTS = 2 };
 // device scalars in s->scal
-enum Scal : int { S_BB = 0, S_RR = 1, S_PQ = 2, S_RZ = 3 /* 3, 4 */, S_RT = 5, S_POW = 6, S_N = 8 };
+enum Scal : int { S_POW = 0, S_N = 2 };
 
 template <int EPI, class T>
 __device__ __forceinline__ double epilogue(int i, T ax, const T* __restrict__ x,
@@ -167,19 +166,237 @@ __global__ void k_power_init(int n, uint32_t salt, double* __restrict__ x,
   write_partials<kBlock, 1>(sq, partials);
 }
 
-// ---- PCG vector kernels
-__global__ void k_gather_rhs(int na, const int* __restrict__ perm, const int* __restrict__ comp,
-                             const double* __restrict__ rhs, double* __restrict__ b,
-                             double* __restrict__ partials) {
+// ---- segmented PCG kernels.  Compact rows are cut into reduction tiles
+// that never cross a sample (segment); a producer writes one partial per
+// tile, and every consumer block of segment q adds that segment's tile
+// partials in tile order, so per-segment scalars are bitwise reproducible.
+struct Tiles {
+  const int* r0;
+  const int* r1;
+  const int* seg;
+  const int* tp;  // segment q owns tiles [tp[q], tp[q+1])
+};
+
+__device__ __forceinline__ double seg_sum(const double* __restrict__ part, const Tiles& T, int q) {
+  return sum_partials<kBlock>(part + T.tp[q], T.tp[q + 1] - T.tp[q]);
+}
+
+// per-segment scalar arrays (each n_seg doubles) in s->seg_sc
+enum SegScal : int { SS_BB = 0, SS_TOL2 = 1, SS_RZ0 = 2, SS_RZ1 = 3, SS_RES = 4, SS_N = 5 };
+// tile-partial arrays (each n_tiles doubles) in s->tpart
+enum TilePart : int { T_BB = 0, T_RR = 1, T_PQ = 2, T_RZ = 3 /* and 4 */, T_RT = 5, T_N = 6 };
+
+__global__ void __launch_bounds__(kBlock) k_gather_rhs_t(Tiles T, const int* __restrict__ perm,
+                                                         const int* __restrict__ comp,
+                                                         const double* __restrict__ rhs,
+                                                         double* __restrict__ b,
+                                                         double* __restrict__ part) {
+  const int t = blockIdx.x;
   double acc = 0.0;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < na; i += gridDim.x * kBlock) {
+  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) {
     const int c = perm[i];
     const double v = comp[c] == c ? 0.0 : rhs[c];
     b[i] = v;
     acc += v * v;
   }
-  double s[1] = {acc};
-  write_partials<kBlock, 1>(s, partials);
+  double sv[1] = {acc};
+  write_partials<kBlock, 1>(sv, part);
+}
+
+__global__ void __launch_bounds__(kBlock) k_norm2_t(Tiles T, const double* __restrict__ a,
+                                                    double* __restrict__ part) {
+  const int t = blockIdx.x;
+  double acc = 0.0;
+  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) acc += a[i] * a[i];
+  double sv[1] = {acc};
+  write_partials<kBlock, 1>(sv, part);
+}
+
+// tile partials of r.z and (flexible) r.z_old
+__global__ void __launch_bounds__(kBlock) k_dot2_t(Tiles T, const double* __restrict__ r,
+                                                   const double* __restrict__ z,
+                                                   const double* __restrict__ zold,
+                                                   double* __restrict__ part) {
+  const int t = blockIdx.x;
+  double sv[2] = {0.0, 0.0};
+  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) {
+    sv[0] += r[i] * z[i];
+    if (zold) sv[1] += r[i] * zold[i];
+  }
+  write_partials<kBlock, 2>(sv, part);
+}
+
+// q = A p on the finest (ELL) level over the tile's rows; tile partial of p.q
+__global__ void __launch_bounds__(kBlock) k_ell_dot_t(Tiles T, int n, int W,
+                                                      const int* __restrict__ ecol,
+                                                      const double* __restrict__ eval,
+                                                      const double* __restrict__ diag,
+                                                      const int* __restrict__ done,
+                                                      const double* __restrict__ p,
+                                                      double* __restrict__ q,
+                                                      double* __restrict__ part) {
+  const int t = blockIdx.x;
+  double acc = 0.0;
+  if (!done[T.seg[t]]) {
+    for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) {
+      double s = diag[i] * p[i];
+      for (int k = 0; k < W; ++k) {
+        const size_t e = (size_t)k * n + i;
+        s = s + eval[e] * p[ecol[e]];
+      }
+      q[i] = s;
+      acc += p[i] * s;
+    }
+  }
+  double sv[1] = {acc};
+  write_partials<kBlock, 1>(sv, part);
+}
+
+// Per segment: bb, tolerance, initial convergence; counts active segments.
+__global__ void k_seg_init(int ns, Tiles T, const double* __restrict__ part_bb,
+                           const double* __restrict__ part_rr, double rtol2,
+                           double* __restrict__ sc, int* __restrict__ done,
+                           int* __restrict__ iters, int* __restrict__ restart,
+                           int* __restrict__ active) {
+  const int q = blockIdx.x * kBlock + threadIdx.x;
+  if (q >= ns) return;
+  double bb = 0.0, rr = 0.0;
+  for (int t = T.tp[q]; t < T.tp[q + 1]; ++t) {
+    bb += part_bb[t];
+    rr += part_rr[t];
+  }
+  const double tol2 = rtol2 * bb;
+  sc[SS_BB * ns + q] = bb;
+  sc[SS_TOL2 * ns + q] = tol2;
+  const int d = (bb == 0.0 || rr <= tol2) ? 1 : 0;
+  done[q] = d;
+  iters[q] = 0;
+  restart[q] = 0;
+  if (!d) atomicAdd(active, 1);
+}
+
+// zero the iterate of segments whose right-hand side is zero
+__global__ void __launch_bounds__(kBlock) k_zero_empty_t(Tiles T, int ns,
+                                                         const double* __restrict__ sc,
+                                                         double* __restrict__ x) {
+  const int t = blockIdx.x;
+  if (sc[SS_BB * ns + T.seg[t]] != 0.0) return;
+  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) x[i] = 0.0;
+}
+
+// p = z on active segments; the first tile of a segment stores its r.z
+__global__ void __launch_bounds__(kBlock) k_init_p_t(Tiles T, int ns, const int* __restrict__ done,
+                                                     const double* __restrict__ part_rz,
+                                                     const double* __restrict__ z,
+                                                     double* __restrict__ p,
+                                                     double* __restrict__ rz_out) {
+  const int t = blockIdx.x, q = T.seg[t];
+  if (done[q]) return;
+  const double rz = seg_sum(part_rz, T, q);
+  if (t == T.tp[q] && threadIdx.x == 0) rz_out[q] = rz;
+  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) p[i] = z[i];
+}
+
+// alpha_q = rz_q / (p.q)_q; x += alpha p; r -= alpha q; tile partial of r.r
+__global__ void __launch_bounds__(kBlock) k_update_xr_t(Tiles T, const int* __restrict__ done,
+                                                        const double* __restrict__ rz,
+                                                        const double* __restrict__ part_pq,
+                                                        const double* __restrict__ p,
+                                                        const double* __restrict__ qv,
+                                                        double* __restrict__ x,
+                                                        double* __restrict__ r,
+                                                        double* __restrict__ part,
+                                                        int* __restrict__ err) {
+  const int t = blockIdx.x, q = T.seg[t];
+  double acc = 0.0;
+  if (!done[q]) {
+    const double pq = seg_sum(part_pq, T, q);
+    if (!(pq > 0.0) || !(rz[q] > 0.0)) {
+      if (threadIdx.x == 0) atomicOr(err, 1);
+    } else {
+      const double alpha = rz[q] / pq;
+      for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) {
+        x[i] = x[i] + alpha * p[i];
+        const double v = r[i] - alpha * qv[i];
+        r[i] = v;
+        acc += v * v;
+      }
+    }
+  }
+  double sv[1] = {acc};
+  write_partials<kBlock, 1>(sv, part);
+}
+
+// Per active segment: count the iteration, test ||r||^2 against the
+// tolerance; counts segments still running.
+__global__ void k_seg_step(int ns, Tiles T, const double* __restrict__ part_rr,
+                           const double* __restrict__ sc, int* __restrict__ done,
+                           int* __restrict__ iters, int* __restrict__ restart,
+                           int* __restrict__ active, int* __restrict__ err) {
+  const int q = blockIdx.x * kBlock + threadIdx.x;
+  if (q >= ns || done[q]) return;
+  double rr = 0.0;
+  for (int t = T.tp[q]; t < T.tp[q + 1]; ++t) rr += part_rr[t];
+  iters[q] += 1;
+  restart[q] = 0;
+  if (!(rr == rr) || rr > 1.7976931348623157e308) {
+    atomicOr(err, 2);
+    done[q] = 1;
+    return;
+  }
+  if (rr <= sc[SS_TOL2 * ns + q])
+    done[q] = 1;
+  else
+    atomicAdd(active, 1);
+}
+
+// beta_q = (r.z - [r.z_old]) / rz_prev (0 right after a restart); p = z + beta p
+__global__ void __launch_bounds__(kBlock) k_update_p_t(Tiles T, int nt, const int* __restrict__ done,
+                                                       const int* __restrict__ restart,
+                                                       const double* __restrict__ part_rz,
+                                                       int flexible,
+                                                       const double* __restrict__ rz_prev,
+                                                       double* __restrict__ rz_next,
+                                                       const double* __restrict__ z,
+                                                       double* __restrict__ p,
+                                                       int* __restrict__ err) {
+  const int t = blockIdx.x, q = T.seg[t];
+  if (done[q]) return;
+  const double rzn = seg_sum(part_rz, T, q);
+  const double rzo = flexible ? seg_sum(part_rz + nt, T, q) : 0.0;
+  if (t == T.tp[q] && threadIdx.x == 0) {
+    rz_next[q] = rzn;
+    if (!(rzn > 0.0)) atomicOr(err, 4);
+  }
+  const double beta = restart[q] ? 0.0 : (rzn - rzo) / rz_prev[q];
+  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) p[i] = z[i] + beta * p[i];
+}
+
+// After the recurred residuals all met the tolerance: per segment, the true
+// residual; a segment that misses it restarts from the true residual.
+__global__ void k_seg_check(int ns, Tiles T, const double* __restrict__ part_rt,
+                            double* __restrict__ sc, int* __restrict__ done,
+                            int* __restrict__ restart, int* __restrict__ active) {
+  const int q = blockIdx.x * kBlock + threadIdx.x;
+  if (q >= ns) return;
+  double rt = 0.0;
+  for (int t = T.tp[q]; t < T.tp[q + 1]; ++t) rt += part_rt[t];
+  sc[SS_RES * ns + q] = rt;
+  const double bb = sc[SS_BB * ns + q];
+  if (bb != 0.0 && rt > sc[SS_TOL2 * ns + q]) {
+    done[q] = 0;
+    restart[q] = 1;
+    atomicAdd(active, 1);
+  }
+}
+
+// r = r_true on segments that restart
+__global__ void __launch_bounds__(kBlock) k_copy_restart_t(Tiles T, const int* __restrict__ restart,
+                                                           const double* __restrict__ rt,
+                                                           double* __restrict__ r) {
+  const int t = blockIdx.x;
+  if (!restart[T.seg[t]]) return;
+  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) r[i] = rt[i];
 }
 
 __global__ void k_gather_x0(int na, const int* __restrict__ perm, const int* __restrict__ comp,
@@ -198,72 +415,11 @@ __global__ void k_scatter(int nc, const int* __restrict__ cid, const int* __rest
   p[c] = (k < 0 || comp[c] == c) ? 0.0 : x[k];
 }
 
-__global__ void k_norm2(int n, const double* __restrict__ a, double* __restrict__ partials) {
-  double acc = 0.0;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) acc += a[i] * a[i];
-  double s[1] = {acc};
-  write_partials<kBlock, 1>(s, partials);
-}
-
-// Partial sums of r.z and (flexible variant) r.z_old.
-__global__ void k_dot2(int n, const double* __restrict__ r, const double* __restrict__ z,
-                       const double* __restrict__ zold, double* __restrict__ partials) {
-  double s[2] = {0.0, 0.0};
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    s[0] += r[i] * z[i];
-    if (zold) s[1] += r[i] * zold[i];
-  }
-  write_partials<kBlock, 2>(s, partials);
-}
-
-// p = z; block 0 stores rz = sum of the r.z partials.
-__global__ void k_init_p(int n, const double* __restrict__ z, double* __restrict__ p,
-                         const double* __restrict__ rz_parts, int g, double* __restrict__ rz_out) {
-  const double rz = sum_partials<kBlock>(rz_parts, g);
-  if (blockIdx.x == 0 && threadIdx.x == 0) *rz_out = rz;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = z[i];
-}
-
-// alpha = rz / p.q (partials); x += alpha p; r -= alpha q; partial sums of r.r
-__global__ void k_update_xr(int n, const double* __restrict__ rz, const double* __restrict__ pq_parts,
-                            int g, const double* __restrict__ p, const double* __restrict__ q,
-                            double* __restrict__ x, double* __restrict__ r,
-                            double* __restrict__ partials) {
-  const double alpha = *rz / sum_partials<kBlock>(pq_parts, g);
-  double acc = 0.0;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    x[i] = x[i] + alpha * p[i];
-    const double v = r[i] - alpha * q[i];
-    r[i] = v;
-    acc += v * v;
-  }
-  double s[1] = {acc};
-  write_partials<kBlock, 1>(s, partials);
-}
-
-// beta = (rz_new [- r.z_old]) / rz_prev; p = z + beta p; block 0 stores rz_new.
-__global__ void k_update_p(int n, const double* __restrict__ rz_parts, int g,
-                           const double* __restrict__ rz_prev, double* __restrict__ rz_next,
-                           int flexible, const double* __restrict__ z, double* __restrict__ p) {
-  const double rzn = sum_partials<kBlock>(rz_parts, g);
-  const double rzo = flexible ? sum_partials<kBlock>(rz_parts + g, g) : 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *rz_next = rzn;
-  const double beta = (rzn - rzo) / *rz_prev;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
-    p[i] = z[i] + beta * p[i];
-}
-
-// Host-facing scalars: *o0 = sum of p0, *o1 = sum of p1 (p1 may be null).
-__global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ p0,
-                                                     const double* __restrict__ p1, int g,
-                                                     double* __restrict__ o0,
-                                                     double* __restrict__ o1) {
+// Host-facing scalar: *o0 = sum of p0[0..g).
+__global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ p0, int g,
+                                                     double* __restrict__ o0) {
   const double a = sum_partials<kBlock>(p0, g);
-  const double b = p1 ? sum_partials<kBlock>(p1, g) : 0.0;
-  if (threadIdx.x == 0) {
-    *o0 = a;
-    if (p1) *o1 = b;
-  }
+  if (threadIdx.x == 0) *o0 = a;
 }
 
 template <class S, class D>
@@ -481,8 +637,7 @@ double power_estimate(ppe_solver* s, Level& L, uint32_t salt, int iters) {
     std::swap(x, y);
     std::swap(pa, pb);
   }
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s->stream, pa, nullptr, g, sc + S_POW,
-                     nullptr);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s->stream, pa, g, sc + S_POW);
   PPE_LAUNCH_CHECK();
   return std::sqrt(read_scalar(s, sc + S_POW));
 }
@@ -550,17 +705,18 @@ void make_fp32_hierarchy(ppe_solver* s) {
 }
 
 ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0) {
-  const int na = s->n_active, nc = s->n_cells;
+  const int na = s->n_active, nc = s->n_cells, ns = s->n_seg, nt = s->n_tiles;
   ppe_stats& st = s->stats;
   st.iterations = 0;
   st.rel_residual = 0.0;
+  s->seg_iters_h.assign(ns, 0);
+  s->seg_res_h.assign(ns, 0.0);
   if (na == 0) {
     fill_double(s, p_out, 0.0, nc);
     PPE_HIP(hipStreamSynchronize(s->stream));
     return PPE_OK;
   }
   Level& L0 = s->levels[0];
-  const int gv = red_grid(na);
   double* x = s->vx.get<double>(na);
   double* r = s->vr.get<double>(na);
   double* z = s->vz.get<double>(na);
@@ -569,14 +725,27 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
   double* b = s->vb.get<double>(na);
   const bool flexible = s->opt.precision == PPE_MIXED;
   double* zold = flexible ? s->vzold.get<double>(na) : nullptr;
-  double* sc = s->scal.get<double>(S_N);
-  s->partial.get<double>((size_t)P_NSLOTS * kRedBlocks);
+  double* tp = s->tpart.get<double>((size_t)T_N * nt);
+  double* sc = s->seg_sc.get<double>((size_t)SS_N * ns);
+  int* done = s->seg_done.get<int>(3 * (size_t)ns);
+  int* iters = done + ns;
+  int* restart = done + 2 * ns;
+  int* cnt = s->flag.get<int>(4);  // [0] active segments, [1] error bits
+  const Tiles T{s->tile_r0.as<int>(), s->tile_r1.as<int>(), s->tile_seg.as<int>(),
+                s->seg_tile_ptr.as<int>()};
+  auto tpart = [&](int k) { return tp + (size_t)k * nt; };
   const int* perm = s->perm.as<int>();
   const int* comp = s->comp_full.as<int>();
-  const int ge = grid_for(na);
+  const int ge = grid_for(na), gs = grid_for(ns);
+  double* rz[2] = {sc + (size_t)SS_RZ0 * ns, sc + (size_t)SS_RZ1 * ns};
+  int h[2];
+  auto read_counts = [&]() {
+    PPE_HIP(hipMemcpyAsync(h, cnt, sizeof(int) * 2, hipMemcpyDeviceToHost, s->stream));
+    PPE_HIP(hipStreamSynchronize(s->stream));
+  };
 
-  hipLaunchKernelGGL(k_gather_rhs, dim3(gv), dim3(kBlock), 0, s->stream, na, perm, comp, rhs, b,
-                     part(s, P_BB));
+  hipLaunchKernelGGL(k_gather_rhs_t, dim3(nt), dim3(kBlock), 0, s->stream, T, perm, comp, rhs, b,
+                     tpart(T_BB));
   PPE_LAUNCH_CHECK();
   if (use_x0) {
     hipLaunchKernelGGL(k_gather_x0, dim3(ge), dim3(kBlock), 0, s->stream, na, perm, comp, p_out, x);
@@ -587,70 +756,85 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
     hipLaunchKernelGGL(k_copy, dim3(ge), dim3(kBlock), 0, s->stream, na, b, r);
     PPE_LAUNCH_CHECK();
   }
-  hipLaunchKernelGGL(k_norm2, dim3(gv), dim3(kBlock), 0, s->stream, na, r, part(s, P_RR));
+  hipLaunchKernelGGL(k_norm2_t, dim3(nt), dim3(kBlock), 0, s->stream, T, r, tpart(T_RR));
   PPE_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s->stream, part(s, P_BB), part(s, P_RR),
-                     gv, sc + S_BB, sc + S_RR);
+  fill_int(s, cnt, 0, 2);
+  hipLaunchKernelGGL(k_seg_init, dim3(gs), dim3(kBlock), 0, s->stream, ns, T, tpart(T_BB),
+                     tpart(T_RR), s->opt.rtol * s->opt.rtol, sc, done, iters, restart, cnt);
   PPE_LAUNCH_CHECK();
-  double h[S_N];
-  PPE_HIP(hipMemcpyAsync(h, sc, sizeof(double) * 2, hipMemcpyDeviceToHost, s->stream));
-  PPE_HIP(hipStreamSynchronize(s->stream));
-  const double bb = h[S_BB];
-  const double tol2 = s->opt.rtol * s->opt.rtol * bb;
-  auto finish = [&](ppe_status status, double rr_true) {
+  if (use_x0) {
+    hipLaunchKernelGGL(k_zero_empty_t, dim3(nt), dim3(kBlock), 0, s->stream, T, ns, sc, x);
+    PPE_LAUNCH_CHECK();
+  }
+  // true residual of every segment, then restart those that miss the tolerance
+  auto check_true = [&]() {
+    apply_op<E_RESID, double>(s, L0, x, b, nullptr, 0.0, 0.0, q, nullptr);
+    hipLaunchKernelGGL(k_norm2_t, dim3(nt), dim3(kBlock), 0, s->stream, T, q, tpart(T_RT));
+    PPE_LAUNCH_CHECK();
+    fill_int(s, cnt, 0, 1);
+    hipLaunchKernelGGL(k_seg_check, dim3(gs), dim3(kBlock), 0, s->stream, ns, T, tpart(T_RT), sc,
+                       done, restart, cnt);
+    PPE_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_copy_restart_t, dim3(nt), dim3(kBlock), 0, s->stream, T, restart, q, r);
+    PPE_LAUNCH_CHECK();
+    read_counts();
+    return h[0];
+  };
+  auto finish = [&](ppe_status status) {
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc,
                        s->cid.as<int>(), comp, x, p_out);
     PPE_LAUNCH_CHECK();
+    std::vector<double> bbh(ns), rth(ns);
+    PPE_HIP(hipMemcpyAsync(bbh.data(), sc + (size_t)SS_BB * ns, sizeof(double) * ns,
+                           hipMemcpyDeviceToHost, s->stream));
+    PPE_HIP(hipMemcpyAsync(rth.data(), sc + (size_t)SS_RES * ns, sizeof(double) * ns,
+                           hipMemcpyDeviceToHost, s->stream));
+    PPE_HIP(hipMemcpyAsync(s->seg_iters_h.data(), iters, sizeof(int) * ns, hipMemcpyDeviceToHost,
+                           s->stream));
     PPE_HIP(hipStreamSynchronize(s->stream));
     profile_harvest(s);
-    st.rel_residual = bb > 0 ? std::sqrt(rr_true / bb) : std::sqrt(rr_true);
+    double worst = 0.0;
+    int itmax = 0;
+    for (int k = 0; k < ns; ++k) {
+      s->seg_res_h[k] = bbh[k] > 0 ? std::sqrt(rth[k] / bbh[k]) : 0.0;
+      worst = std::max(worst, s->seg_res_h[k]);
+      itmax = std::max(itmax, s->seg_iters_h[k]);
+    }
+    st.rel_residual = worst;
+    st.iterations = itmax;
     return status;
   };
-  auto true_residual = [&]() {
-    apply_op<E_RESID, double>(s, L0, x, b, nullptr, 0.0, 0.0, q, nullptr);
-    hipLaunchKernelGGL(k_norm2, dim3(gv), dim3(kBlock), 0, s->stream, na, q, part(s, P_RT));
-    PPE_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s->stream, part(s, P_RT), nullptr, gv,
-                       sc + S_RT, nullptr);
-    PPE_LAUNCH_CHECK();
-    return read_scalar(s, sc + S_RT);
-  };
-  if (bb == 0.0) {
-    fill_double(s, x, 0.0, na);
-    return finish(PPE_OK, 0.0);
-  }
-  if (h[S_RR] <= tol2) return finish(PPE_OK, h[S_RR]);
+
+  read_counts();
+  if (h[0] == 0 && check_true() == 0) return finish(PPE_OK);
 
   vcycle(s, 0, r, z);
-  hipLaunchKernelGGL(k_dot2, dim3(gv), dim3(kBlock), 0, s->stream, na, r, z, nullptr, part(s, P_RZ));
+  hipLaunchKernelGGL(k_dot2_t, dim3(nt), dim3(kBlock), 0, s->stream, T, r, z, nullptr, tpart(T_RZ));
   PPE_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_init_p, dim3(gv), dim3(kBlock), 0, s->stream, na, z, p, part(s, P_RZ), gv,
-                     sc + S_RZ);
+  hipLaunchKernelGGL(k_init_p_t, dim3(nt), dim3(kBlock), 0, s->stream, T, ns, done, tpart(T_RZ), z,
+                     p, rz[0]);
   PPE_LAUNCH_CHECK();
-  int slot = 0;  // rz of the current iteration at sc[S_RZ + slot]
-  const int max_iter = s->opt.max_iter;
+  int slot = 0;
+  const int max_iter = s->opt.max_iter, every = s->opt.check_every;
   for (int it = 1; it <= max_iter; ++it) {
-    double* rzc = sc + S_RZ + slot;
-    const int gq = apply_op<E_DOT, double>(s, L0, p, nullptr, nullptr, 0.0, 0.0, q, part(s, P_PQ));
-    hipLaunchKernelGGL(k_update_xr, dim3(gv), dim3(kBlock), 0, s->stream, na, rzc, part(s, P_PQ), gq,
-                       p, q, x, r, part(s, P_RR));
+    hipLaunchKernelGGL(k_ell_dot_t, dim3(nt), dim3(kBlock), 0, s->stream, T, na, L0.W,
+                       L0.ell_col.as<int>(), L0.ell_val.as<double>(), L0.diag.as<double>(), done,
+                       p, q, tpart(T_PQ));
     PPE_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s->stream, part(s, P_RR), part(s, P_PQ),
-                       gv, sc + S_RR, sc + S_PQ);
+    hipLaunchKernelGGL(k_update_xr_t, dim3(nt), dim3(kBlock), 0, s->stream, T, done, rz[slot],
+                       tpart(T_PQ), p, q, x, r, tpart(T_RR), cnt + 1);
     PPE_LAUNCH_CHECK();
-    PPE_HIP(hipMemcpyAsync(h, sc, sizeof(double) * S_N, hipMemcpyDeviceToHost, s->stream));
-    PPE_HIP(hipStreamSynchronize(s->stream));
-    st.iterations = it;
-    const double pq = h[S_PQ], rr = h[S_RR], rz = h[S_RZ + slot];
-    if (!(pq > 0.0) || !std::isfinite(rr) || !(rz > 0.0)) {
-      finish(PPE_ERR_BREAKDOWN, rr);
-      return PPE_ERR_BREAKDOWN;
-    }
-    if (rr <= tol2) {
-      const double rt = true_residual();
-      if (rt <= tol2) return finish(PPE_OK, rt);
-      hipLaunchKernelGGL(k_copy, dim3(ge), dim3(kBlock), 0, s->stream, na, q, r);
-      PPE_LAUNCH_CHECK();
+    fill_int(s, cnt, 0, 1);
+    hipLaunchKernelGGL(k_seg_step, dim3(gs), dim3(kBlock), 0, s->stream, ns, T, tpart(T_RR), sc, done,
+                       iters, restart, cnt, cnt + 1);
+    PPE_LAUNCH_CHECK();
+    if (it % every == 0 || it == max_iter) {
+      read_counts();
+      if (h[1]) {
+        finish(PPE_ERR_BREAKDOWN);
+        return PPE_ERR_BREAKDOWN;
+      }
+      if (h[0] == 0 && check_true() == 0) return finish(PPE_OK);
     }
     if (it == max_iter) break;
     if (flexible) {
@@ -658,14 +842,22 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
       PPE_LAUNCH_CHECK();
     }
     vcycle(s, 0, r, z);
-    hipLaunchKernelGGL(k_dot2, dim3(gv), dim3(kBlock), 0, s->stream, na, r, z, zold, part(s, P_RZ));
+    hipLaunchKernelGGL(k_dot2_t, dim3(nt), dim3(kBlock), 0, s->stream, T, r, z, zold, tpart(T_RZ));
     PPE_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_update_p, dim3(gv), dim3(kBlock), 0, s->stream, na, part(s, P_RZ), gv, rzc,
-                       sc + S_RZ + (1 - slot), flexible ? 1 : 0, z, p);
+    hipLaunchKernelGGL(k_update_p_t, dim3(nt), dim3(kBlock), 0, s->stream, T, nt, done, restart,
+                       tpart(T_RZ), flexible ? 1 : 0, rz[slot], rz[1 - slot], z, p, cnt + 1);
     PPE_LAUNCH_CHECK();
     slot = 1 - slot;
   }
-  return finish(PPE_NOT_CONVERGED, true_residual());
+  // out of iterations: record the true residuals
+  apply_op<E_RESID, double>(s, L0, x, b, nullptr, 0.0, 0.0, q, nullptr);
+  hipLaunchKernelGGL(k_norm2_t, dim3(nt), dim3(kBlock), 0, s->stream, T, q, tpart(T_RT));
+  PPE_LAUNCH_CHECK();
+  fill_int(s, cnt, 0, 1);
+  hipLaunchKernelGGL(k_seg_check, dim3(gs), dim3(kBlock), 0, s->stream, ns, T, tpart(T_RT), sc, done,
+                     restart, cnt);
+  PPE_LAUNCH_CHECK();
+  return finish(PPE_NOT_CONVERGED);
 }
 
 }  // namespace ppe

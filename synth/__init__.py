@@ -12,6 +12,7 @@ from .fields import (
     fl_growing_front,
     rhs_uniform,
     batch_samples,
+    uq_front_fl,
 )
 
 __all__ = [
@@ -25,4 +26,5 @@ __all__ = [
     "fl_growing_front",
     "rhs_uniform",
     "batch_samples",
+    "uq_front_fl",
 ]

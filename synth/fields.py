@@ -57,3 +57,13 @@ def batch_samples(n_samples=256, seed=3, param_seed=4, side_range=(24, 48)):
     d_liq = prng.uniform(-5.0, 5.0, size=n_samples)
     return [dict(side=int(sides[s]), t_melt=float(t_melt[s]), t_wall=float(t_wall[s]),
                  d_liq=float(d_liq[s])) for s in range(n_samples)]
+
+
+def uq_front_fl(centres, sample, t, t_end, length=1.0, delta=0.1, t_liquidus=913.0):
+    """Surrogate solid front of one uncertainty sample: a layer growing from
+    the cold wall x = 0 as sqrt(t), its final depth set by how far the wall
+    sits below the (shifted) liquidus relative to the melt superheat:
+    s_max = 0.7 (T_liq + dT_liq - T_wall) / (T_melt - T_wall)."""
+    t_liq = t_liquidus + sample["d_liq"]
+    s_max = 0.7 * (t_liq - sample["t_wall"]) / (sample["t_melt"] - sample["t_wall"])
+    return fl_growing_front(centres, t, t_end, s_max=s_max, delta=delta, axis=0, length=length)

@@ -31,7 +31,7 @@ def test_host_only_calls():
     lib = ppe.load_library()
     o = ppe.ppe_default_options()
     assert o.rtol == 1e-10 and o.max_iter == 500 and o.cheb_degree == 2
-    assert o.coarse_max == 256 and o.theta == 0.08
+    assert o.coarse_max == 128 and o.theta == 0.08
     assert ppe.ppe_status_string(ppe.PPE_ERR_STATE) == "call out of order"
     assert ppe.ppe_status_string(ppe.PPE_NOT_CONVERGED) == "not converged"
     # NULL solver handles are rejected without touching a device
