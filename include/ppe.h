@@ -67,8 +67,11 @@ typedef struct {
   int coarse_max;     /* stop coarsening at <= this many rows, default 128 */
   int max_levels;     /* hierarchy depth cap, default 10 */
   double theta;       /* strength threshold, default 0.08 */
-  int check_every;    /* PCG iterations between host convergence checks, default 1 */
+  int check_every;    /* PCG iterations between host convergence checks when not
+                         replaying graphs (a graph replay of two iterations is
+                         followed by one check), default 1 */
   void* stream;       /* hipStream_t used for every launch; NULL = default stream */
+  int use_graph;      /* replay PCG iterations from a captured HIP graph, default 1 */
 } ppe_options;
 
 typedef struct {

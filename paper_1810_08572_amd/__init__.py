@@ -41,6 +41,7 @@ class ppe_options(ctypes.Structure):
         ("theta", ctypes.c_double),
         ("check_every", ctypes.c_int),
         ("stream", ctypes.c_void_p),
+        ("use_graph", ctypes.c_int),
     ]
 
 
@@ -193,7 +194,8 @@ class Solver:
     """Pressure solver bound to the current device and torch stream."""
 
     def __init__(self, precision="fp64", rtol=1e-10, max_iter=500, cheb_degree=2,
-                 cheb_ratio=30.0, coarse_max=128, max_levels=10, theta=0.08, stream=None):
+                 cheb_ratio=30.0, coarse_max=128, max_levels=10, theta=0.08, stream=None,
+                 use_graph=True, check_every=1):
         import torch
 
         lib = load_library()
@@ -201,6 +203,7 @@ class Solver:
         o.precision = {"fp64": PPE_FP64, "mixed": PPE_MIXED}[precision]
         o.rtol, o.max_iter, o.cheb_degree, o.cheb_ratio = rtol, max_iter, cheb_degree, cheb_ratio
         o.coarse_max, o.max_levels, o.theta = coarse_max, max_levels, theta
+        o.use_graph, o.check_every = int(bool(use_graph)), int(check_every)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

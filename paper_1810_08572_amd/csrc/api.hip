@@ -96,6 +96,7 @@ void ppe_default_options(ppe_options* o) {
   o->theta = 0.08;
   o->check_every = 1;
   o->stream = nullptr;
+  o->use_graph = 1;
 }
 
 ppe_status ppe_create(const ppe_options* opt, ppe_solver** out) {
@@ -124,6 +125,7 @@ ppe_status ppe_create(const ppe_options* opt, ppe_solver** out) {
       s->lds_max = (size_t)lds;
       PPE_HIP(hipEventCreate(&s->ev0));
       PPE_HIP(hipEventCreate(&s->ev1));
+      PPE_HIP(hipStreamCreateWithFlags(&s->gstream, hipStreamNonBlocking));
       s->levels.reserve(o.max_levels + 1);
       unsigned int* c = s->counter.get<unsigned int>(1);
       PPE_HIP(hipMemsetAsync(c, 0, sizeof(unsigned int), s->stream));
@@ -131,6 +133,7 @@ ppe_status ppe_create(const ppe_options* opt, ppe_solver** out) {
     } catch (...) {
       if (s->ev0) (void)hipEventDestroy(s->ev0);
       if (s->ev1) (void)hipEventDestroy(s->ev1);
+      if (s->gstream) (void)hipStreamDestroy(s->gstream);
       delete s;
       throw;
     }
@@ -145,6 +148,8 @@ void ppe_destroy(ppe_solver* s) {
   (void)hipStreamSynchronize(s->stream);
   for (auto& e : s->prof_ev)
     if (e) (void)hipEventDestroy(e);
+  ppe::drop_graph(s);
+  if (s->gstream) (void)hipStreamDestroy(s->gstream);
   if (s->ev0) (void)hipEventDestroy(s->ev0);
   if (s->ev1) (void)hipEventDestroy(s->ev1);
   delete s;
@@ -177,6 +182,8 @@ ppe_status ppe_assemble(ppe_solver* s, const double* face_coeff, const double* f
     ppe::require(s->have_mesh, PPE_ERR_STATE, "ppe_assemble before ppe_set_mesh");
     ppe::require(fl && (face_coeff || s->n_faces == 0), PPE_ERR_ARG, "NULL input array");
     s->assembled = false;
+    s->solves_since_assemble = 0;
+    ppe::drop_graph(s);
     PPE_HIP(hipEventRecord(s->ev0, s->stream));
     ppe::assemble_fine(s, face_coeff, fl);
     if (s->n_active > 0) {
@@ -209,6 +216,7 @@ ppe_status ppe_solve(ppe_solver* s, const double* rhs, double* p, int use_x0, pp
     ppe::require(rhs && p, PPE_ERR_ARG, "NULL rhs or p");
     PPE_HIP(hipEventRecord(s->ev0, s->stream));
     ppe_status st = ppe::pcg_solve(s, rhs, p, use_x0);
+    s->solves_since_assemble += 1;
     PPE_HIP(hipEventRecord(s->ev1, s->stream));
     PPE_HIP(hipEventSynchronize(s->ev1));
     s->stats.solve_ms = elapsed_ms(s->ev0, s->ev1);

@@ -235,7 +235,7 @@ __global__ void k_gather_int(int n, const int* __restrict__ idx, const int* __re
   if (i < n) dst[i] = src[idx[i]];
 }
 
-// Reduction tiles: runs of at most kTileRows compact rows that never cross a
+// Reduction tiles: runs of at most 4096 compact rows that never cross a
 // segment boundary; tile t covers rows [r0[t], r1[t]) of segment seg[t], and
 // segment s owns tiles [seg_tile_ptr[s], seg_tile_ptr[s+1]).
 void build_tiles(ppe_solver* s) {
@@ -251,12 +251,16 @@ void build_tiles(ppe_solver* s) {
   PPE_HIP(hipMemcpyAsync(s->seg_row_off.data(), d_row, sizeof(int) * (ns + 1),
                          hipMemcpyDeviceToHost, s->stream));
   PPE_HIP(hipStreamSynchronize(s->stream));
+  // about kRedBlocks tiles over the whole system, 256..4096 rows each
+  const int na = s->seg_row_off[ns];
+  int rows = ((na / kRedBlocks + 255) / 256) * 256;
+  rows = std::min(std::max(rows, 256), 4096);
   std::vector<int> r0, r1, sg, tp(ns + 1, 0);
   for (int q = 0; q < ns; ++q) {
     tp[q] = (int)r0.size();
-    for (int a = s->seg_row_off[q]; a < s->seg_row_off[q + 1]; a += kTileRows) {
+    for (int a = s->seg_row_off[q]; a < s->seg_row_off[q + 1]; a += rows) {
       r0.push_back(a);
-      r1.push_back(std::min(a + kTileRows, s->seg_row_off[q + 1]));
+      r1.push_back(std::min(a + rows, s->seg_row_off[q + 1]));
       sg.push_back(q);
     }
   }

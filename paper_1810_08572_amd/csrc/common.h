@@ -157,6 +157,12 @@ struct ppe_solver {
   ppe::DevBuf tmp_i[4], tmp_d[2], tmp_l[2];
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
+  // HIP graph of two PCG iterations, captured once per hierarchy
+  hipStream_t gstream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  bool graph_ok = false;
+  int solves_since_assemble = 0;
+
   // dominant-kernel measurement (event pairs around fine-level smoothing steps)
   bool prof = false;
   std::vector<hipEvent_t> prof_ev;
@@ -237,7 +243,6 @@ __device__ __forceinline__ T block_max(T v) {
 // and value; a consumer kernel sums those partials in a fixed order at the
 // start of every block, so all blocks see the same bitwise result.
 constexpr int kRedBlocks = 1024;
-constexpr int kTileRows = 2048;  // rows per reduction tile of the segmented PCG
 
 template <int BS, int NV>
 __device__ __forceinline__ void write_partials(const double (&v)[NV], double* partials) {
@@ -355,6 +360,7 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p, int use_x0);
 void prepare_solve_levels(ppe_solver* s);
 void make_fp32_hierarchy(ppe_solver* s);
 void profile_harvest(ppe_solver* s);
+void drop_graph(ppe_solver* s);
 void profile_enable(ppe_solver* s, bool on);
 
 }  // namespace ppe

@@ -589,6 +589,12 @@ void cast(ppe_solver* s, const S* a, D* b, int64_t n) {
 
 }  // namespace
 
+void drop_graph(ppe_solver* s) {
+  if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+  s->gexec = nullptr;
+  s->graph_ok = false;
+}
+
 void profile_harvest(ppe_solver* s) {
   const size_t k = s->prof_pending.size();
   if (k == 0) return;
@@ -704,6 +710,32 @@ void make_fp32_hierarchy(ppe_solver* s) {
   }
 }
 
+// Record the launches `issue` makes into a HIP graph on the solver's capture
+// stream and instantiate it (the launches see that stream as s->stream).
+template <class F>
+void capture_iterations(ppe_solver* s, F&& issue) {
+  drop_graph(s);
+  hipStream_t user = s->stream;
+  s->stream = s->gstream;
+  hipGraph_t g = nullptr;
+  try {
+    PPE_HIP(hipStreamBeginCapture(s->gstream, hipStreamCaptureModeRelaxed));
+    issue();
+    PPE_HIP(hipStreamEndCapture(s->gstream, &g));
+  } catch (...) {
+    hipGraph_t junk = nullptr;
+    (void)hipStreamEndCapture(s->gstream, &junk);
+    if (junk) (void)hipGraphDestroy(junk);
+    s->stream = user;
+    throw;
+  }
+  s->stream = user;
+  hipError_t e = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  PPE_HIP(e);
+  s->graph_ok = true;
+}
+
 ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0) {
   const int na = s->n_active, nc = s->n_cells, ns = s->n_seg, nt = s->n_tiles;
   ppe_stats& st = s->stats;
@@ -814,29 +846,21 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
   hipLaunchKernelGGL(k_init_p_t, dim3(nt), dim3(kBlock), 0, s->stream, T, ns, done, tpart(T_RZ), z,
                      p, rz[0]);
   PPE_LAUNCH_CHECK();
-  int slot = 0;
-  const int max_iter = s->opt.max_iter, every = s->opt.check_every;
-  for (int it = 1; it <= max_iter; ++it) {
+  // One PCG iteration of every sample still running: q = A p; x, r update;
+  // the convergence test; z = M r; beta; p.  Samples already converged are
+  // left untouched by every kernel, so extra iterations change nothing.
+  auto body = [&](int sl) {
     hipLaunchKernelGGL(k_ell_dot_t, dim3(nt), dim3(kBlock), 0, s->stream, T, na, L0.W,
                        L0.ell_col.as<int>(), L0.ell_val.as<double>(), L0.diag.as<double>(), done,
                        p, q, tpart(T_PQ));
     PPE_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_update_xr_t, dim3(nt), dim3(kBlock), 0, s->stream, T, done, rz[slot],
+    hipLaunchKernelGGL(k_update_xr_t, dim3(nt), dim3(kBlock), 0, s->stream, T, done, rz[sl],
                        tpart(T_PQ), p, q, x, r, tpart(T_RR), cnt + 1);
     PPE_LAUNCH_CHECK();
     fill_int(s, cnt, 0, 1);
     hipLaunchKernelGGL(k_seg_step, dim3(gs), dim3(kBlock), 0, s->stream, ns, T, tpart(T_RR), sc, done,
                        iters, restart, cnt, cnt + 1);
     PPE_LAUNCH_CHECK();
-    if (it % every == 0 || it == max_iter) {
-      read_counts();
-      if (h[1]) {
-        finish(PPE_ERR_BREAKDOWN);
-        return PPE_ERR_BREAKDOWN;
-      }
-      if (h[0] == 0 && check_true() == 0) return finish(PPE_OK);
-    }
-    if (it == max_iter) break;
     if (flexible) {
       hipLaunchKernelGGL(k_copy, dim3(ge), dim3(kBlock), 0, s->stream, na, z, zold);
       PPE_LAUNCH_CHECK();
@@ -845,9 +869,50 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
     hipLaunchKernelGGL(k_dot2_t, dim3(nt), dim3(kBlock), 0, s->stream, T, r, z, zold, tpart(T_RZ));
     PPE_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_update_p_t, dim3(nt), dim3(kBlock), 0, s->stream, T, nt, done, restart,
-                       tpart(T_RZ), flexible ? 1 : 0, rz[slot], rz[1 - slot], z, p, cnt + 1);
+                       tpart(T_RZ), flexible ? 1 : 0, rz[sl], rz[1 - sl], z, p, cnt + 1);
     PPE_LAUNCH_CHECK();
-    slot = 1 - slot;
+  };
+  // Two iterations (both rz slots) captured into a HIP graph on the second
+  // solve with one hierarchy (a single solve per assembly would pay the
+  // capture without reuse), replayed while at least two iterations remain.
+  const bool graph = s->opt.use_graph && !s->prof && s->solves_since_assemble > 0;
+  if (graph && !s->graph_ok) capture_iterations(s, [&]() { body(0); body(1); });
+  int it = 0, slot = 0;
+  const int max_iter = s->opt.max_iter, every = s->opt.check_every;
+  while (it < max_iter) {
+    bool check;
+    if (graph && slot == 0 && it + 2 <= max_iter) {
+      PPE_HIP(hipGraphLaunch(s->gexec, s->stream));
+      it += 2;
+      check = true;
+    } else {
+      body(slot);
+      slot = 1 - slot;
+      it += 1;
+      check = it % every == 0 || it == max_iter;
+    }
+    if (!check) continue;
+    read_counts();
+    if (h[1]) {
+      finish(PPE_ERR_BREAKDOWN);
+      return PPE_ERR_BREAKDOWN;
+    }
+    if (h[0] == 0) {
+      if (check_true() == 0) return finish(PPE_OK);
+      // restarted samples: z = M r_true, p = z (beta is 0 after a restart)
+      if (flexible) {
+        hipLaunchKernelGGL(k_copy, dim3(ge), dim3(kBlock), 0, s->stream, na, z, zold);
+        PPE_LAUNCH_CHECK();
+      }
+      vcycle(s, 0, r, z);
+      hipLaunchKernelGGL(k_dot2_t, dim3(nt), dim3(kBlock), 0, s->stream, T, r, z, zold,
+                         tpart(T_RZ));
+      PPE_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_update_p_t, dim3(nt), dim3(kBlock), 0, s->stream, T, nt, done, restart,
+                         tpart(T_RZ), flexible ? 1 : 0, rz[slot], rz[1 - slot], z, p, cnt + 1);
+      PPE_LAUNCH_CHECK();
+      slot = 1 - slot;
+    }
   }
   // out of iterations: record the true residuals
   apply_op<E_RESID, double>(s, L0, x, b, nullptr, 0.0, 0.0, q, nullptr);
