@@ -670,12 +670,12 @@ void spgemm(ppe_solver* s, const Csr& A, const Csr& B, Csr& C) {
     return;
   }
   int* counts = s->tmp_i[0].get<int>(C.n + 1);
-  int* flag = s->flag.get<int>(1);
+  int* flag = s->flag.get<int>(4);
   PPE_ROWS(lanes_for(A), k_spgemm_bound, C.n, C.n, A.rp(), A.ci(), B.rp(), counts);
   const int ub = reduce_max_int(s, counts, C.n);
   int Hc = 64;
   while (Hc < 2 * ub && Hc < 2048) Hc *= 2;
-  fill_int(s, flag, 0, 1);
+  fill_int(s, flag, 0, 2);
 #define PPE_COUNT(HH)                                                                        \
   hipLaunchKernelGGL(k_spgemm_count<HH>, dim3(C.n), dim3(kWave), 0, s->stream, A.rp(), A.ci(), \
                      B.rp(), B.ci(), counts, flag)
@@ -687,10 +687,20 @@ void spgemm(ppe_solver* s, const Csr& A, const Csr& B, Csr& C) {
   else PPE_COUNT(2048);
 #undef PPE_COUNT
   PPE_LAUNCH_CHECK();
-  require(read_scalar(s, flag) == 0, PPE_ERR_INTERNAL,
+  max_int_async(s, counts, C.n, flag + 1);
+  // one host round trip for the scan total, the overflow flag and the max
+  long long total = 0;
+  int fm[2] = {0, 0};
+  exclusive_scan_async(s, counts, crp, C.n);
+  PPE_HIP(hipMemcpyAsync(&total, s->tmp_l[0].as<long long>() + scan_blocks(C.n), sizeof(long long),
+                         hipMemcpyDeviceToHost, s->stream));
+  PPE_HIP(hipMemcpyAsync(fm, flag, sizeof(int) * 2, hipMemcpyDeviceToHost, s->stream));
+  PPE_HIP(hipStreamSynchronize(s->stream));
+  require(fm[0] == 0, PPE_ERR_INTERNAL,
           "sparse product row exceeds the hash table (more than 1024 distinct columns)");
-  int mx = reduce_max_int(s, counts, C.n);
-  C.nnz = exclusive_scan(s, counts, crp, C.n);
+  require(total <= INT32_MAX, PPE_ERR_INTERNAL, "sparse product too large for int32 indices");
+  C.nnz = total;
+  const int mx = fm[1];
   int* cci = C.col.get<int>(C.nnz);
   double* cv = C.val.get<double>(C.nnz);
   int H = 64;
@@ -785,18 +795,18 @@ void build_hierarchy(ppe_solver* s) {
       PPE_ROWS(lpr, k_strength, n, n, L.A.rp(), L.A.ci(), L.A.v(), L.diag.as<double>(), theta2,
                strong, st);
       const uint32_t salt = level_salt(lvl);
-      // rounds run in pairs between host checks; a round after the set is
-      // complete changes nothing, so only the second count is read
-      int* und = s->tmp_i[3].get<int>(2);
+      // rounds run in triples between host checks; a round after the set is
+      // complete changes nothing, so only the last count is read
+      int* und = s->tmp_i[3].get<int>(3);
       while (true) {
-        fill_int(s, und, 0, 2);
-        for (int k = 0; k < 2; ++k) {
+        fill_int(s, und, 0, 3);
+        for (int k = 0; k < 3; ++k) {
           PPE_ROWS(lpr, k_mis_max1, n, n, L.A.rp(), L.A.ci(), strong, st, salt, m1);
           PPE_ROWS(lpr, k_mis_max2, n, n, L.A.rp(), L.A.ci(), strong, st, salt, m1, st2, und + k);
           std::swap(st, st2);
           ++L.mis_rounds;
         }
-        if (read_scalar(s, und + 1) == 0) break;
+        if (read_scalar(s, und + 2) == 0) break;
         require(L.mis_rounds < 10000, PPE_ERR_INTERNAL, "MIS-2 did not terminate");
       }
       int* root = s->tmp_i[2].get<int>(n + 1);

@@ -329,6 +329,12 @@ inline int grid_for(int64_t n, int bs = kBlock) {
 // Exclusive scan of int32 counts into out[0..n] (out[n] = total).  Returns
 // the total; throws PPE_ERR_INTERNAL if it does not fit int32.
 int64_t exclusive_scan(ppe_solver* s, const int* in, int* out, int n);
+// The same without reading the total back: the total stays at
+// tmp_l[0] + scan_blocks(n) (a long long) for the caller to fetch.
+void exclusive_scan_async(ppe_solver* s, const int* in, int* out, int n);
+int scan_blocks(int n);
+// *out = max of in[0..n) on the device (no host read)
+void max_int_async(ppe_solver* s, const int* in, int n, int* out);
 // Max of an int array.
 int reduce_max_int(ppe_solver* s, const int* in, int n);
 // Copy one value from device to host on the solver stream (synchronises).

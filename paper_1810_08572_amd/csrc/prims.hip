@@ -105,6 +105,24 @@ __global__ void __launch_bounds__(kBlock) k_fill(T* __restrict__ p, T v, long lo
 
 }  // namespace
 
+int scan_blocks(int n) {
+  int nb = (int)((n + (int64_t)kScanTile - 1) / kScanTile);
+  return nb < 1 ? 1 : nb;
+}
+
+void exclusive_scan_async(ppe_solver* s, const int* in, int* out, int n) {
+  if (n < 0) throw Error(PPE_ERR_INTERNAL, "negative scan length");
+  const int nb = scan_blocks(n);
+  long long* bsum = s->tmp_l[0].get<long long>(nb + 1);
+  long long* total = bsum + nb;
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s->stream, in, n, bsum);
+  PPE_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s->stream, bsum, nb, total);
+  PPE_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kBlock), 0, s->stream, in, n, bsum, total, out);
+  PPE_LAUNCH_CHECK();
+}
+
 int64_t exclusive_scan(ppe_solver* s, const int* in, int* out, int n) {
   if (n < 0) throw Error(PPE_ERR_INTERNAL, "negative scan length");
   int nb = (int)((n + (int64_t)kScanTile - 1) / kScanTile);
@@ -120,6 +138,14 @@ int64_t exclusive_scan(ppe_solver* s, const int* in, int* out, int n) {
   long long t = read_scalar(s, total);
   if (t > INT32_MAX) throw Error(PPE_ERR_INTERNAL, "scan total exceeds int32 range");
   return t;
+}
+
+void max_int_async(ppe_solver* s, const int* in, int n, int* out) {
+  fill_int(s, out, INT32_MIN, 1);
+  int g = grid_for(n);
+  if (g > 1024) g = 1024;
+  hipLaunchKernelGGL(k_max_int, dim3(g), dim3(kBlock), 0, s->stream, in, n, out);
+  PPE_LAUNCH_CHECK();
 }
 
 int reduce_max_int(ppe_solver* s, const int* in, int n) {

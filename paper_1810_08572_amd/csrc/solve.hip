@@ -252,19 +252,19 @@ __global__ void __launch_bounds__(kBlock) k_ell_dot_t(Tiles T, int n, int W,
   write_partials<kBlock, 1>(sv, part);
 }
 
-// Per segment: bb, tolerance, initial convergence; counts active segments.
-__global__ void k_seg_init(int ns, Tiles T, const double* __restrict__ part_bb,
-                           const double* __restrict__ part_rr, double rtol2,
-                           double* __restrict__ sc, int* __restrict__ done,
-                           int* __restrict__ iters, int* __restrict__ restart,
-                           int* __restrict__ active) {
-  const int q = blockIdx.x * kBlock + threadIdx.x;
-  if (q >= ns) return;
-  double bb = 0.0, rr = 0.0;
-  for (int t = T.tp[q]; t < T.tp[q + 1]; ++t) {
-    bb += part_bb[t];
-    rr += part_rr[t];
-  }
+// Per segment (one block each): bb, tolerance, initial convergence; counts
+// active segments.
+__global__ void __launch_bounds__(kBlock) k_seg_init(int ns, Tiles T,
+                                                     const double* __restrict__ part_bb,
+                                                     const double* __restrict__ part_rr,
+                                                     double rtol2, double* __restrict__ sc,
+                                                     int* __restrict__ done, int* __restrict__ iters,
+                                                     int* __restrict__ restart,
+                                                     int* __restrict__ active) {
+  const int q = blockIdx.x;
+  const double bb = seg_sum(part_bb, T, q);
+  const double rr = seg_sum(part_rr, T, q);
+  if (threadIdx.x != 0) return;
   const double tol2 = rtol2 * bb;
   sc[SS_BB * ns + q] = bb;
   sc[SS_TOL2 * ns + q] = tol2;
@@ -327,16 +327,20 @@ __global__ void __launch_bounds__(kBlock) k_update_xr_t(Tiles T, const int* __re
   write_partials<kBlock, 1>(sv, part);
 }
 
-// Per active segment: count the iteration, test ||r||^2 against the
-// tolerance; counts segments still running.
-__global__ void k_seg_step(int ns, Tiles T, const double* __restrict__ part_rr,
-                           const double* __restrict__ sc, int* __restrict__ done,
-                           int* __restrict__ iters, int* __restrict__ restart,
-                           int* __restrict__ active, int* __restrict__ err) {
-  const int q = blockIdx.x * kBlock + threadIdx.x;
-  if (q >= ns || done[q]) return;
-  double rr = 0.0;
-  for (int t = T.tp[q]; t < T.tp[q + 1]; ++t) rr += part_rr[t];
+// Per active segment (one block each): count the iteration, test ||r||^2
+// against the tolerance; counts segments still running.
+__global__ void __launch_bounds__(kBlock) k_seg_step(int ns, Tiles T,
+                                                     const double* __restrict__ part_rr,
+                                                     const double* __restrict__ sc,
+                                                     int* __restrict__ done,
+                                                     int* __restrict__ iters,
+                                                     int* __restrict__ restart,
+                                                     int* __restrict__ active,
+                                                     int* __restrict__ err) {
+  const int q = blockIdx.x;
+  if (done[q]) return;
+  const double rr = seg_sum(part_rr, T, q);
+  if (threadIdx.x != 0) return;
   iters[q] += 1;
   restart[q] = 0;
   if (!(rr == rr) || rr > 1.7976931348623157e308) {
@@ -372,15 +376,17 @@ __global__ void __launch_bounds__(kBlock) k_update_p_t(Tiles T, int nt, const in
   for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) p[i] = z[i] + beta * p[i];
 }
 
-// After the recurred residuals all met the tolerance: per segment, the true
-// residual; a segment that misses it restarts from the true residual.
-__global__ void k_seg_check(int ns, Tiles T, const double* __restrict__ part_rt,
-                            double* __restrict__ sc, int* __restrict__ done,
-                            int* __restrict__ restart, int* __restrict__ active) {
-  const int q = blockIdx.x * kBlock + threadIdx.x;
-  if (q >= ns) return;
-  double rt = 0.0;
-  for (int t = T.tp[q]; t < T.tp[q + 1]; ++t) rt += part_rt[t];
+// After the recurred residuals all met the tolerance: per segment (one
+// block each), the true residual; a segment that misses it restarts.
+__global__ void __launch_bounds__(kBlock) k_seg_check(int ns, Tiles T,
+                                                      const double* __restrict__ part_rt,
+                                                      double* __restrict__ sc,
+                                                      int* __restrict__ done,
+                                                      int* __restrict__ restart,
+                                                      int* __restrict__ active) {
+  const int q = blockIdx.x;
+  const double rt = seg_sum(part_rt, T, q);
+  if (threadIdx.x != 0) return;
   sc[SS_RES * ns + q] = rt;
   const double bb = sc[SS_BB * ns + q];
   if (bb != 0.0 && rt > sc[SS_TOL2 * ns + q]) {
@@ -791,7 +797,7 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
   hipLaunchKernelGGL(k_norm2_t, dim3(nt), dim3(kBlock), 0, s->stream, T, r, tpart(T_RR));
   PPE_LAUNCH_CHECK();
   fill_int(s, cnt, 0, 2);
-  hipLaunchKernelGGL(k_seg_init, dim3(gs), dim3(kBlock), 0, s->stream, ns, T, tpart(T_BB),
+  hipLaunchKernelGGL(k_seg_init, dim3(ns), dim3(kBlock), 0, s->stream, ns, T, tpart(T_BB),
                      tpart(T_RR), s->opt.rtol * s->opt.rtol, sc, done, iters, restart, cnt);
   PPE_LAUNCH_CHECK();
   if (use_x0) {
@@ -804,7 +810,7 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
     hipLaunchKernelGGL(k_norm2_t, dim3(nt), dim3(kBlock), 0, s->stream, T, q, tpart(T_RT));
     PPE_LAUNCH_CHECK();
     fill_int(s, cnt, 0, 1);
-    hipLaunchKernelGGL(k_seg_check, dim3(gs), dim3(kBlock), 0, s->stream, ns, T, tpart(T_RT), sc,
+    hipLaunchKernelGGL(k_seg_check, dim3(ns), dim3(kBlock), 0, s->stream, ns, T, tpart(T_RT), sc,
                        done, restart, cnt);
     PPE_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_copy_restart_t, dim3(nt), dim3(kBlock), 0, s->stream, T, restart, q, r);
@@ -858,7 +864,7 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
                        tpart(T_PQ), p, q, x, r, tpart(T_RR), cnt + 1);
     PPE_LAUNCH_CHECK();
     fill_int(s, cnt, 0, 1);
-    hipLaunchKernelGGL(k_seg_step, dim3(gs), dim3(kBlock), 0, s->stream, ns, T, tpart(T_RR), sc, done,
+    hipLaunchKernelGGL(k_seg_step, dim3(ns), dim3(kBlock), 0, s->stream, ns, T, tpart(T_RR), sc, done,
                        iters, restart, cnt, cnt + 1);
     PPE_LAUNCH_CHECK();
     if (flexible) {
@@ -919,7 +925,7 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
   hipLaunchKernelGGL(k_norm2_t, dim3(nt), dim3(kBlock), 0, s->stream, T, q, tpart(T_RT));
   PPE_LAUNCH_CHECK();
   fill_int(s, cnt, 0, 1);
-  hipLaunchKernelGGL(k_seg_check, dim3(gs), dim3(kBlock), 0, s->stream, ns, T, tpart(T_RT), sc, done,
+  hipLaunchKernelGGL(k_seg_check, dim3(ns), dim3(kBlock), 0, s->stream, ns, T, tpart(T_RT), sc, done,
                      restart, cnt);
   PPE_LAUNCH_CHECK();
   return finish(PPE_NOT_CONVERGED);
