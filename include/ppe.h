@@ -183,6 +183,59 @@ ppe_status ppe_apply_matrix(ppe_solver* s, int level, const double* x, double* y
 /* z = M r: one V-cycle from level 0 with a zero initial guess (length n_active). */
 ppe_status ppe_apply_vcycle(ppe_solver* s, const double* r, double* z);
 
+/* ---- Learned warm start (not part of the paper's method). ----
+ * A dense network n_in -> width (n_hidden SiLU layers) -> 1 (linear)
+ * predicts each active cell's next pressure increment from local features;
+ * the solve then starts from x0 = p_prev + dp_scale * y and conjugate
+ * gradients still finishes it to rtol, so the network only changes the
+ * iteration count.  Parameters are FP32, packed layer by layer as W
+ * ([out][in], row-major) followed by b.  Every array is a device pointer;
+ * the network runs on the stream given at creation. */
+typedef struct ppe_mlp ppe_mlp;
+
+/* Errors: PPE_ERR_ARG for sizes < 1 or > 4096. Parameters start at 0. */
+ppe_status ppe_mlp_create(int32_t n_in, int32_t width, int32_t n_hidden, void* stream,
+                          ppe_mlp** out);
+void ppe_mlp_destroy(ppe_mlp* m);
+int64_t ppe_mlp_num_params(const ppe_mlp* m);
+const char* ppe_mlp_last_error(const ppe_mlp* m);
+/* Copy parameters in (also resets the Adam moments) or out. */
+ppe_status ppe_mlp_set_params(ppe_mlp* m, const float* params);
+ppe_status ppe_mlp_get_params(const ppe_mlp* m, float* params);
+/* y[n] = network(x[n][n_in]).  bf16 = 0: FP32 throughout; bf16 = 1: the
+ * width x width layers on BF16 matrix cores with FP32 accumulation (needs
+ * n_in = 10, width = 128, n_hidden >= 2). */
+ppe_status ppe_mlp_forward(ppe_mlp* m, int32_t n, const float* x, float* y, int bf16);
+/* Mean squared error of network(x) against t over n rows (*loss, host) and
+ * its gradient with respect to the packed parameters (grad, device). */
+ppe_status ppe_mlp_loss_grad(ppe_mlp* m, int32_t n, const float* x, const float* t, float* grad,
+                             double* loss);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on that loss; *loss (host,
+ * nullable) receives the loss before the step. */
+ppe_status ppe_mlp_train_step(ppe_mlp* m, int32_t n, const float* x, const float* t, float lr,
+                              double* loss);
+
+/* Previous fields are re-referenced to the current pins: a field q becomes
+ * q_c - q_pin(c), pin(c) = the pin of cell c's pocket, which removes the
+ * constant jump a pocket's pressure takes when its pin moves.
+ * Features of the assembled solver's active cells, row r = compact id:
+ * previous increment / its RMS, rhs / its RMS, liquid fraction, volume /
+ * mean volume, and the six largest open-face coefficients of the cell
+ * divided by their sum (descending); then (f - mu) / sigma per feature.
+ * features: [n_active][10] FP32.  *dp_scale (host) = RMS of dp_prev over
+ * the active cells.  Arrays of length n_cells / n_faces are FP64. */
+ppe_status ppe_warm_start_features(ppe_solver* s, const double* dp_prev, const double* rhs,
+                                   const double* face_coeff, const double* liquid_fraction,
+                                   const double* cell_volume, const float* mu, const float* sigma,
+                                   float* features, double* dp_scale);
+/* x0 = p_prev (re-referenced) + dp_scale * y on active non-pin cells, 0
+ * elsewhere (y per compact row, x0 per cell). */
+ppe_status ppe_warm_start_apply(ppe_solver* s, const double* p_prev, const float* y,
+                                double dp_scale, double* x0);
+/* Training targets per compact row: (p_new - p_prev re-referenced) / dp_scale. */
+ppe_status ppe_warm_start_targets(ppe_solver* s, const double* p_new, const double* p_prev,
+                                  double dp_scale, float* targets);
+
 /* ---- Measurement of the dominant kernel. ----
  * While enabled, every launch of the finest-level fused Chebyshev smoothing
  * kernel (the operator applied most often per PCG iteration) is bracketed by

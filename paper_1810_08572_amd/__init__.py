@@ -88,6 +88,20 @@ _SIGS = {
     "ppe_set_segments": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_I32)]),
     "ppe_get_segment_stats": (ctypes.c_int, [_P, ctypes.POINTER(_I32),
                                              ctypes.POINTER(ctypes.c_double)]),
+    "ppe_mlp_create": (ctypes.c_int, [_I32, _I32, _I32, _P, ctypes.POINTER(_P)]),
+    "ppe_mlp_destroy": (None, [_P]),
+    "ppe_mlp_num_params": (ctypes.c_int64, [_P]),
+    "ppe_mlp_last_error": (ctypes.c_char_p, [_P]),
+    "ppe_mlp_set_params": (ctypes.c_int, [_P, _P]),
+    "ppe_mlp_get_params": (ctypes.c_int, [_P, _P]),
+    "ppe_mlp_forward": (ctypes.c_int, [_P, _I32, _P, _P, ctypes.c_int]),
+    "ppe_mlp_loss_grad": (ctypes.c_int, [_P, _I32, _P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
+    "ppe_mlp_train_step": (ctypes.c_int, [_P, _I32, _P, _P, ctypes.c_float,
+                                          ctypes.POINTER(ctypes.c_double)]),
+    "ppe_warm_start_features": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                               ctypes.POINTER(ctypes.c_double)]),
+    "ppe_warm_start_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, _P]),
+    "ppe_warm_start_targets": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, _P]),
     "ppe_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "ppe_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double),
@@ -357,3 +371,118 @@ class Solver:
         self._chk(self._lib.ppe_apply_vcycle(self._h, _dev_ptr(r, torch.float64, n, "r"),
                                              ctypes.c_void_p(z.data_ptr())))
         return z
+
+
+class WarmStartNet:
+    """The warm-start network (FP32 parameters on the device)."""
+
+    def __init__(self, n_in=10, width=128, n_hidden=3, stream=None):
+        import torch
+
+        self._lib = load_library()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = self._lib.ppe_mlp_create(n_in, width, n_hidden, ctypes.c_void_p(stream.cuda_stream),
+                                      ctypes.byref(h))
+        _check(st)
+        self._h = h
+        self.n_in, self.width, self.n_hidden = n_in, width, n_hidden
+        self.n_params = int(self._lib.ppe_mlp_num_params(h))
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ppe_mlp_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def _chk(self, st):
+        if st != PPE_OK:
+            raise PpeError(st, f"{ppe_status_string(st)}: "
+                               f"{self._lib.ppe_mlp_last_error(self._h).decode()}")
+
+    def set_params(self, theta):
+        import torch
+
+        self._chk(self._lib.ppe_mlp_set_params(
+            self._h, _dev_ptr(theta, torch.float32, self.n_params, "params")))
+
+    def get_params(self):
+        import torch
+
+        out = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        self._chk(self._lib.ppe_mlp_get_params(self._h, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def forward(self, x, bf16=False):
+        import torch
+
+        n = x.shape[0]
+        y = torch.empty(n, dtype=torch.float32, device=self.device)
+        self._chk(self._lib.ppe_mlp_forward(self._h, n, _dev_ptr(x, torch.float32, n * self.n_in, "x"),
+                                            ctypes.c_void_p(y.data_ptr()), int(bool(bf16))))
+        return y
+
+    def loss_grad(self, x, t):
+        import torch
+
+        n = x.shape[0]
+        g = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        loss = ctypes.c_double()
+        self._chk(self._lib.ppe_mlp_loss_grad(self._h, n, _dev_ptr(x, torch.float32, n * self.n_in, "x"),
+                                              _dev_ptr(t, torch.float32, n, "t"),
+                                              ctypes.c_void_p(g.data_ptr()), ctypes.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, x, t, lr):
+        import torch
+
+        n = x.shape[0]
+        loss = ctypes.c_double()
+        self._chk(self._lib.ppe_mlp_train_step(
+            self._h, n, _dev_ptr(x, torch.float32, n * self.n_in, "x"),
+            _dev_ptr(t, torch.float32, n, "t"), ctypes.c_float(lr), ctypes.byref(loss)))
+        return loss.value
+
+
+def warm_start_features(solver, dp_prev, rhs, face_coeff, fl, cell_volume, mu, sigma):
+    """Features [n_active, 10] (FP32) and the increment scale of the
+    assembled solver."""
+    import torch
+
+    na = solver.stats()["n_active"]
+    feats = torch.empty((max(na, 1), 10), dtype=torch.float32, device=solver.device)
+    scale = ctypes.c_double()
+    nc, nf = solver.n_cells, solver.n_faces
+    solver._chk(load_library().ppe_warm_start_features(
+        solver._h, _dev_ptr(dp_prev, torch.float64, nc, "dp_prev"),
+        _dev_ptr(rhs, torch.float64, nc, "rhs"), _dev_ptr(face_coeff, torch.float64, nf, "coeff"),
+        _dev_ptr(fl, torch.float64, nc, "fl"), _dev_ptr(cell_volume, torch.float64, nc, "volume"),
+        _dev_ptr(mu, torch.float32, 10, "mu"), _dev_ptr(sigma, torch.float32, 10, "sigma"),
+        ctypes.c_void_p(feats.data_ptr()), ctypes.byref(scale)))
+    return feats[:na], scale.value
+
+
+def warm_start_apply(solver, p_prev, y, scale):
+    import torch
+
+    x0 = torch.empty(solver.n_cells, dtype=torch.float64, device=solver.device)
+    solver._chk(load_library().ppe_warm_start_apply(
+        solver._h, _dev_ptr(p_prev, torch.float64, solver.n_cells, "p_prev"),
+        ctypes.c_void_p(y.data_ptr()), ctypes.c_double(scale), ctypes.c_void_p(x0.data_ptr())))
+    return x0
+
+
+def warm_start_targets(solver, p_new, p_prev, scale):
+    import torch
+
+    na = solver.stats()["n_active"]
+    t = torch.empty(max(na, 1), dtype=torch.float32, device=solver.device)
+    solver._chk(load_library().ppe_warm_start_targets(
+        solver._h, _dev_ptr(p_new, torch.float64, solver.n_cells, "p_new"),
+        _dev_ptr(p_prev, torch.float64, solver.n_cells, "p_prev"), ctypes.c_double(scale),
+        ctypes.c_void_p(t.data_ptr())))
+    return t[:na]

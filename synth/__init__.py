@@ -13,6 +13,7 @@ from .fields import (
     rhs_uniform,
     batch_samples,
     uq_front_fl,
+    rhs_smooth_series,
 )
 
 __all__ = [
@@ -27,4 +28,5 @@ __all__ = [
     "rhs_uniform",
     "batch_samples",
     "uq_front_fl",
+    "rhs_smooth_series",
 ]

@@ -67,3 +67,28 @@ def uq_front_fl(centres, sample, t, t_end, length=1.0, delta=0.1, t_liquidus=913
     t_liq = t_liquidus + sample["d_liq"]
     s_max = 0.7 * (t_liq - sample["t_wall"]) / (sample["t_melt"] - sample["t_wall"])
     return fl_growing_front(centres, t, t_end, s_max=s_max, delta=delta, axis=0, length=length)
+
+
+def rhs_smooth_series(centres, t, seed=5, n_modes=6, noise=0.05, center_mask=None):
+    """Right-hand side that changes smoothly in time, standing in for the
+    velocity divergence of successive timesteps: a sum of n_modes products of
+    low-order cosines, each with a seeded amplitude, frequency and phase in
+    time, plus a small fixed noise field.  Centred over center_mask."""
+    rng = np.random.default_rng(seed)
+    x = np.asarray(centres)
+    lo = x.min(axis=0)
+    span = np.maximum(x.max(axis=0) - lo, 1e-30)
+    u = (x - lo) / span
+    b = np.zeros(x.shape[0])
+    for _ in range(n_modes):
+        k = rng.integers(0, 4, size=3)
+        amp = rng.uniform(0.5, 1.5)
+        omega = rng.uniform(5.0, 20.0)
+        phase = rng.uniform(0, 2 * np.pi)
+        b += amp * np.cos(omega * t + phase) * np.prod(np.cos(np.pi * k * u + rng.uniform(0, 1, 3)), axis=1)
+    b += noise * rng.uniform(-1.0, 1.0, size=x.shape[0])
+    if center_mask is not None:
+        m = np.asarray(center_mask, dtype=bool)
+        if m.any():
+            b[m] -= b[m].mean()
+    return b

@@ -1,0 +1,190 @@
+"""Learned warm start: the GPU network's FP32 loss and gradients match the
+FP64 oracle; BF16 matrix-core inference matches the FP32 forward pass to
+BF16 rounding; one Adam step matches the oracle's; the features match the
+oracle's definition; and a network trained on snapshots the solver itself
+produced reduces the iterations of held-out solves (the solve always ends at
+the FP64 tolerance, whatever the initial guess)."""
+import numpy as np
+import pytest
+
+from oracle import assembly, mlp as omlp
+from synth import box_mesh, face_coeff, fl_growing_front, rhs_smooth_series
+from tests.gpu_util import to_dev, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+# FP32 forward/backward against FP64: the gradient of a mean over n rows of
+# products of FP32-rounded layers agrees to ~sqrt(n) * 6e-8 * depth relative
+BWD_RTOL = 1e-4
+# BF16 activations/weights (8-bit mantissa, 4e-3 relative rounding) through
+# three rounded layers
+BF16_RTOL = 3e-2
+
+
+def _net(seed=0, width=128, hidden=3):
+    import paper_1810_08572_amd as ppe
+    import torch
+
+    torch_dev()
+    shapes = omlp.layer_shapes(10, width, hidden)
+    theta = omlp.init_params(shapes, seed=seed)
+    net = ppe.WarmStartNet(10, width, hidden)
+    net.set_params(to_dev(theta.astype(np.float32), torch.float32))
+    return net, shapes, theta.astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("n", [1, 77, 5000])
+def test_fp32_loss_and_gradient_match_oracle(n):
+    import torch
+
+    net, shapes, theta = _net()
+    rng = np.random.default_rng(n)
+    X = rng.normal(size=(n, 10)).astype(np.float32)
+    T = rng.normal(size=n).astype(np.float32)
+    loss, g = net.loss_grad(to_dev(X, torch.float32), to_dev(T, torch.float32))
+    l_ref, g_ref = omlp.loss_and_grad(theta, shapes, X.astype(np.float64), T.astype(np.float64))
+    assert abs(loss - l_ref) <= BWD_RTOL * l_ref
+    g = g.cpu().numpy()
+    assert np.linalg.norm(g - g_ref) <= BWD_RTOL * np.linalg.norm(g_ref)
+    y = net.forward(to_dev(X, torch.float32)).cpu().numpy()
+    y_ref, _, _ = omlp.forward(theta, shapes, X.astype(np.float64))
+    assert np.abs(y - y_ref).max() <= 1e-5 * max(1.0, np.abs(y_ref).max())
+
+
+@pytest.mark.parametrize("n", [32, 1000, 12345])
+def test_bf16_inference_matches_fp32(n):
+    import torch
+
+    net, shapes, theta = _net(seed=3)
+    X = to_dev(np.random.default_rng(1).normal(size=(n, 10)).astype(np.float32), torch.float32)
+    y32 = net.forward(X).cpu().numpy()
+    y16 = net.forward(X, bf16=True).cpu().numpy()
+    assert np.linalg.norm(y16 - y32) <= BF16_RTOL * np.linalg.norm(y32)
+    assert not np.array_equal(y16, y32)       # the BF16 path really ran
+
+
+def test_adam_step_matches_oracle():
+    import torch
+
+    net, shapes, theta = _net(seed=5, width=32, hidden=2)
+    rng = np.random.default_rng(0)
+    X = rng.normal(size=(500, 10)).astype(np.float32)
+    T = np.tanh(X[:, 0]).astype(np.float32)
+    lr = 1e-3
+    net.train_step(to_dev(X, torch.float32), to_dev(T, torch.float32), lr)
+    new = net.get_params().cpu().numpy()
+    _, g = omlp.loss_and_grad(theta, shapes, X.astype(np.float64), T.astype(np.float64))
+    ref, _, _ = omlp.adam_step(theta, g, np.zeros_like(g), np.zeros_like(g), 1, lr)
+    big = np.abs(g) > 1e-3 * np.abs(g).max()   # first Adam step ~ lr*sign(g): skip g ~ 0
+    assert np.abs(new - ref)[big].max() <= 1e-2 * lr
+
+
+def _series(m, c, steps, t0, seed, solver):
+    """Run the solver through a smooth series; yields per-step tensors."""
+    import torch
+
+    dev = torch.device("cuda", 0)
+    p_prev = torch.zeros(m.n_cells, dtype=torch.float64, device=dev)
+    dp_prev = torch.zeros_like(p_prev)
+    for k in range(steps):
+        t = t0 + 1e-3 * k
+        fl = fl_growing_front(m.cell_centre, t, 0.2, s_max=0.5)
+        b = rhs_smooth_series(m.cell_centre, t, seed=seed, center_mask=fl > 0)
+        yield k, fl, b, p_prev, dp_prev
+        solver.assemble(to_dev(c, torch.float64), to_dev(fl, torch.float64))
+        p = solver.solve(to_dev(b, torch.float64)).p.clone()
+        dp_prev = p - p_prev
+        p_prev = p
+
+
+def test_features_match_oracle_definition():
+    import torch
+
+    import paper_1810_08572_amd as ppe
+
+    torch_dev()
+    m = box_mesh((11, 9, 7), jitter=0.1, seed=2)
+    c = face_coeff(m, 2400.0)
+    s = ppe.Solver()
+    s.set_mesh(m.n_cells, to_dev(m.owner, torch.int32), to_dev(m.neigh, torch.int32))
+    fl = fl_growing_front(m.cell_centre, 0.05, 0.2)
+    s.assemble(to_dev(c, torch.float64), to_dev(fl, torch.float64))
+    rng = np.random.default_rng(4)
+    dp, b = rng.normal(size=m.n_cells), rng.normal(size=m.n_cells)
+    mu = np.zeros(10, np.float32)
+    sg = np.ones(10, np.float32)
+    F, scale = ppe.warm_start_features(s, to_dev(dp, torch.float64), to_dev(b, torch.float64),
+                                       to_dev(c, torch.float64), to_dev(fl, torch.float64),
+                                       to_dev(m.cell_volume, torch.float64),
+                                       to_dev(mu, torch.float32), to_dev(sg, torch.float32))
+    sy = assembly.masked_system(m.n_cells, m.owner, m.neigh, c, fl)
+    pin_of = np.zeros(m.n_cells, dtype=np.int64)
+    pin_of[sy.perm] = sy.comp
+    Fr, sr = omlp.warm_start_features(m.n_cells, m.owner, m.neigh, c, fl, m.cell_volume, dp, b,
+                                      pin_of)
+    assert abs(scale - sr) <= 1e-14 * sr
+    assert np.abs(F.cpu().numpy() - Fr).max() <= 1e-6
+
+
+def test_trained_network_reduces_iterations():
+    import torch
+
+    import paper_1810_08572_amd as ppe
+
+    torch_dev()
+    m = box_mesh((24, 24, 24), jitter=0.1, seed=0)
+    c = face_coeff(m, 2400.0)
+    c_d = to_dev(c, torch.float64)
+    vol = to_dev(m.cell_volume, torch.float64)
+    s = ppe.Solver()
+    s.set_mesh(m.n_cells, to_dev(m.owner, torch.int32), to_dev(m.neigh, torch.int32))
+    zero10 = torch.zeros(10, dtype=torch.float32, device="cuda")
+    one10 = torch.ones(10, dtype=torch.float32, device="cuda")
+    # training snapshots produced by the solver itself
+    # Snapshots right after the front crosses a cell layer (the mask changed
+    # within the last two steps) carry a jump no local feature predicts; they
+    # are left out of training (the network is still applied to them below).
+    feats, targs, masks = [], [], []
+    for k, fl, b, p_prev, dp_prev in _series(m, c, 40, 0.01, seed=5, solver=s):
+        masks.append(fl > 0)
+        if k < 2 or not (np.array_equal(masks[-1], masks[-2]) and
+                         np.array_equal(masks[-2], masks[-3])):
+            continue
+        s.assemble(c_d, to_dev(fl, torch.float64))
+        F, scale = ppe.warm_start_features(s, dp_prev, to_dev(b, torch.float64), c_d,
+                                           to_dev(fl, torch.float64), vol, zero10, one10)
+        p_new = s.solve(to_dev(b, torch.float64)).p
+        feats.append(F.clone())
+        targs.append(ppe.warm_start_targets(s, p_new, p_prev, scale).clone())
+    X = torch.cat(feats)
+    T = torch.cat(targs)
+    mu, sigma = X.mean(0), X.std(0).clamp_min(1e-6)
+    Xs = ((X - mu) / sigma).contiguous()
+    shapes = omlp.layer_shapes()
+    net = ppe.WarmStartNet()
+    net.set_params(to_dev(omlp.init_params(shapes, seed=0).astype(np.float32), torch.float32))
+    g = torch.Generator(device="cuda").manual_seed(0)
+    losses = []
+    for it in range(400):
+        idx = torch.randint(0, Xs.shape[0], (8192,), device="cuda", generator=g)
+        losses.append(net.train_step(Xs[idx].contiguous(), T[idx].contiguous(), 1e-3))
+    assert np.mean(losses[-20:]) < 0.1 * np.mean(losses[:20])
+    # held-out run (different right-hand-side series and times)
+    its = {"zero": [], "prev": [], "mlp": []}
+    for k, fl, b, p_prev, dp_prev in _series(m, c, 16, 0.05, seed=9, solver=s):
+        if k < 2:
+            continue
+        fl_d, b_d = to_dev(fl, torch.float64), to_dev(b, torch.float64)
+        s.assemble(c_d, fl_d)
+        F, scale = ppe.warm_start_features(s, dp_prev, b_d, c_d, fl_d, vol, mu.contiguous(),
+                                           sigma.contiguous())
+        y = net.forward(F.contiguous(), bf16=True)
+        x0 = ppe.warm_start_apply(s, p_prev, y, scale)
+        for name, guess in (("zero", None), ("prev", p_prev), ("mlp", x0)):
+            r = s.solve(b_d, x0=guess)
+            assert r.stats["rel_residual"] <= 1e-10
+            its[name].append(r.stats["iterations"])
+    mean = {k: float(np.mean(v)) for k, v in its.items()}
+    print("mean PCG iterations:", mean)
+    assert mean["mlp"] < mean["zero"]
+    assert mean["mlp"] <= mean["prev"]
