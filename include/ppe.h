@@ -69,7 +69,9 @@ typedef struct {
   double theta;       /* strength threshold, default 0.08 */
   int check_every;    /* PCG iterations between host convergence checks when not
                          replaying graphs (a graph replay of two iterations is
-                         followed by one check), default 1 */
+                         followed by one check), default 2; iterations past
+                         convergence leave a converged system untouched, so
+                         the result and iteration count do not depend on it */
   void* stream;       /* hipStream_t used for every launch; NULL = default stream */
   int use_graph;      /* replay PCG iterations from a captured HIP graph, default 1 */
 } ppe_options;

@@ -209,7 +209,7 @@ class Solver:
 
     def __init__(self, precision="fp64", rtol=1e-10, max_iter=500, cheb_degree=2,
                  cheb_ratio=30.0, coarse_max=128, max_levels=10, theta=0.08, stream=None,
-                 use_graph=True, check_every=1):
+                 use_graph=True, check_every=2):
         import torch
 
         lib = load_library()

@@ -110,7 +110,8 @@ __global__ void __launch_bounds__(kBlock) k_mis_max1(int n, const int* __restric
 }
 
 // m2_i = max m1 over i and its strong neighbours; an undecided node joins if
-// m2 is its own key, leaves if m2 belongs to a member.
+// m2 is its own key, leaves if m2 belongs to a member.  *undecided is set to
+// 1 if any node stays undecided.
 template <int LPR>
 __global__ void __launch_bounds__(kBlock) k_mis_max2(int n, const int* __restrict__ rp,
                                                      const int* __restrict__ ci,
@@ -145,8 +146,11 @@ __global__ void __launch_bounds__(kBlock) k_mis_max2(int n, const int* __restric
     next[i] = ns;
     und = ns == S_UND ? 1 : 0;
   }
+  // the host only asks whether any node is still undecided: a plain store of
+  // the same value from every such block (same-address atomics from every
+  // block serialise across the chip)
   und = block_sum<kBlock>(und);
-  if (threadIdx.x == 0 && und) atomicAdd(undecided, und);
+  if (threadIdx.x == 0 && und) *undecided = 1;
 }
 
 // ------------------------------------------------------------------ aggregation
@@ -314,152 +318,215 @@ __global__ void __launch_bounds__(kBlock) k_diag(int n, const int* __restrict__ 
 // ------------------------------------------------------------------ sparse products
 __device__ __forceinline__ uint32_t slot_hash(int key) { return fmix32((uint32_t)key); }
 
-// Upper bound of the entries of every row of C = A B: the number of products.
+// Products per row of C = A B: the summed lengths of the rows of B that row
+// i of A selects (clipped at 2^30).
 template <int LPR>
 __global__ void __launch_bounds__(kBlock) k_spgemm_bound(int n, const int* __restrict__ arp,
                                                          const int* __restrict__ aci,
                                                          const int* __restrict__ brp,
-                                                         int* __restrict__ ub) {
+                                                         int* __restrict__ prod) {
   const int i = (blockIdx.x * kBlock + threadIdx.x) / LPR, lane = threadIdx.x % LPR;
   long long s = 0;
   if (i < n)
     for (int a = arp[i] + lane; a < arp[i + 1]; a += LPR) s += brp[aci[a] + 1] - brp[aci[a]];
   s = group_sum<LPR>(s);
-  if (i < n && lane == 0) ub[i] = s > (1 << 30) ? (1 << 30) : (int)s;
+  if (i < n && lane == 0) prod[i] = s > (1 << 30) ? (1 << 30) : (int)s;
 }
 
-// Rows of A up to kStageA entries have their columns, values and the
-// extents of the matching rows of B staged in LDS before the product loop,
-// so each step of the loop waits on a single global load.
-constexpr int kStageA = 256;
+enum SpMode { SP_COUNT = 0, SP_FILL = 1, SP_DENSE = 2 };
+constexpr int kSpBatch = 4;        // entries of A whose loads are issued together
+constexpr int kSpDenseWidth = 512; // widest C accumulated with one slot per column
 
-struct RowStage {
-  int j[kStageA];
-  int b0[kStageA];
-  int b1[kStageA];
-  double av[kStageA];
-};
-
-// Stage row i of A (if short enough); returns whether it was staged.
-__device__ __forceinline__ bool stage_row(RowStage& st, int a0, int len, const int* __restrict__ aci,
-                                          const double* __restrict__ av,
-                                          const int* __restrict__ brp) {
-  if (len > kStageA) return false;
-  for (int a = threadIdx.x; a < len; a += kWave) {
-    const int j = aci[a0 + a];
-    st.j[a] = j;
-    st.b0[a] = brp[j];
-    st.b1[a] = brp[j + 1];
-    if (av) st.av[a] = av[a0 + a];
+// Row-parallel C = A B.  Row i of C belongs to W sub-groups of LPR lanes;
+// sub-group w walks its contiguous run of row i of A in ascending order and
+// scatters the products with each selected row of B into its own value
+// array.  The lanes of a sub-group hold distinct columns of that row of B
+// and a wavefront's LDS operations complete in issue order, so the products
+// reaching one slot from one sub-group are added in entry order with no
+// barrier; the sub-groups' arrays are then added in the order w = 0..W-1.
+// The result therefore depends only on W, never on timing.  Column slots are
+// shared by the row's sub-groups:
+//   SP_COUNT  open-addressing hash of column ids (H slots, a power of two);
+//             counts[i] = distinct columns of the row;
+//   SP_FILL   the same hash; the row is written to C at off[i], sorted by
+//             column (rank among the row's columns);
+//   SP_DENSE  slot = column (H >= width); the row is written in column order
+//             to the scratch row at off[i]; counts[i] = entries written.
+// The block holds blockDim / (LPR W) rows; LDS is sized by the host.
+template <int LPR, int MODE>
+__global__ void __launch_bounds__(1024) k_spgemm_rows(
+    int n, int W, int H, const int* __restrict__ arp, const int* __restrict__ aci,
+    const double* __restrict__ av, const int* __restrict__ brp, const int* __restrict__ bci,
+    const double* __restrict__ bv, const int* __restrict__ off, int* __restrict__ counts,
+    int* __restrict__ cci, double* __restrict__ cv, int* __restrict__ flag) {
+  extern __shared__ double smem[];
+  const int per_row = LPR * W;
+  const int rpb = blockDim.x / per_row;
+  const int rl = threadIdx.x / per_row, tr = threadIdx.x % per_row;
+  const int w = tr / LPR, lane = tr % LPR;
+  const int i = blockIdx.x * rpb + rl;
+  const bool numeric = MODE != SP_COUNT;
+  double* vals = smem + (size_t)rl * W * H;  // [W][H] of this row
+  int* ibase = reinterpret_cast<int*>(smem + (numeric ? (size_t)rpb * W * H : 0));
+  int* keys = ibase + (size_t)rl * H;
+  // SP_FILL: the row's occupied slots and their columns, at most H / 2 each
+  int* list = ibase + (size_t)rpb * H + (size_t)rl * H;
+  int* ckey = list + H / 2;
+  int* cnt = ibase + (size_t)(MODE == SP_FILL ? 2 : 1) * rpb * H;
+  for (int q = tr; q < H; q += per_row) {
+    keys[q] = -1;
+    if (numeric)
+      for (int v = 0; v < W; ++v) vals[(size_t)v * H + q] = 0.0;
+  }
+  if (MODE == SP_DENSE) {
+    for (int q = tr; q < per_row / kWave + 1; q += per_row) cnt[rl * (per_row / kWave + 1) + q] = 0;
+  } else if (tr == 0) {
+    cnt[rl] = 0;
   }
   __syncthreads();
-  return true;
-}
 
-// Symbolic C = A B: number of distinct columns in every row of C.
-// One 64-lane workgroup per row; open-addressing hash of column ids in LDS
-// with H slots (H >= 2 x the row's product bound whenever that bound is at
-// most 1024; otherwise a full table is reported through the flag).
-template <int H>
-__global__ void __launch_bounds__(kWave) k_spgemm_count(
-    const int* __restrict__ arp, const int* __restrict__ aci, const int* __restrict__ brp,
-    const int* __restrict__ bci, int* __restrict__ counts, int* __restrict__ flag) {
-  __shared__ int keys[H];
-  __shared__ int cnt;
-  __shared__ RowStage st;
-  const int i = blockIdx.x, t = threadIdx.x;
-  for (int s = t; s < H; s += kWave) keys[s] = -1;
-  if (t == 0) cnt = 0;
-  const int a0 = arp[i], len = arp[i + 1] - a0;
-  const bool staged = stage_row(st, a0, len, aci, nullptr, brp);
-  __syncthreads();
   bool overflow = false;
-  for (int a = 0; a < len; ++a) {
-    int b0, b1;
-    if (staged) {
-      b0 = st.b0[a];
-      b1 = st.b1[a];
+  auto insert = [&](int key, double y) {
+    int q;
+    if (MODE == SP_DENSE) {
+      q = key;
+      keys[q] = key;
     } else {
-      const int j = aci[a0 + a];
-      b0 = brp[j];
-      b1 = brp[j + 1];
-    }
-    for (int b = b0 + t; b < b1; b += kWave) {
-      const int key = bci[b];
-      uint32_t s = slot_hash(key) & (H - 1);
+      q = (int)(slot_hash(key) & (uint32_t)(H - 1));
       int probes = 0;
       while (true) {
-        int prev = atomicCAS(&keys[s], -1, key);
-        if (prev == -1) { atomicAdd(&cnt, 1); break; }
+        const int prev = atomicCAS(&keys[q], -1, key);
+        if (prev == -1) {
+          if (MODE == SP_COUNT) atomicAdd(&cnt[rl], 1);
+          break;
+        }
         if (prev == key) break;
-        s = (s + 1) & (H - 1);
-        if (++probes >= H) { overflow = true; break; }
+        q = (q + 1) & (H - 1);
+        if (++probes >= H) { overflow = true; return; }
+      }
+    }
+    if (numeric) vals[(size_t)w * H + q] += y;
+  };
+
+  if (i < n) {
+    const int a0 = arp[i], a1 = arp[i + 1];
+    const int chunk = (a1 - a0 + W - 1) / W;
+    const int lo = a0 + w * chunk, hi = min(a1, lo + chunk);
+    for (int e = lo; e < hi; e += kSpBatch) {
+      int kk[kSpBatch], bb[kSpBatch], be[kSpBatch];
+      double xa[kSpBatch], yy[kSpBatch];
+#pragma unroll
+      for (int u = 0; u < kSpBatch; ++u) {
+        kk[u] = -1;
+        bb[u] = 0;
+        be[u] = 0;
+        xa[u] = 0.0;
+        yy[u] = 0.0;
+        if (e + u < hi) {
+          const int j = aci[e + u];
+          bb[u] = brp[j];
+          be[u] = brp[j + 1];
+          if (numeric) xa[u] = av[e + u];
+          const int b = bb[u] + lane;
+          if (b < be[u]) {
+            kk[u] = bci[b];
+            if (numeric) yy[u] = xa[u] * bv[b];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kSpBatch; ++u) {
+        if (kk[u] >= 0) insert(kk[u], yy[u]);
+        for (int b = bb[u] + lane + LPR; b < be[u]; b += LPR)
+          insert(bci[b], numeric ? xa[u] * bv[b] : 0.0);
       }
     }
   }
   if (overflow) atomicOr(flag, 1);
   __syncthreads();
-  if (t == 0) {
-    counts[i] = cnt;
-    if (cnt > H / 2) atomicOr(flag, 1);
-  }
-}
 
-// Numeric C = A B with the row structure from k_spgemm_count.  Products are
-// accumulated in ascending order of A's row entries (one barrier per entry;
-// within one entry every column of B's row is distinct, so lanes never share
-// a slot), then written out sorted by column.
-template <int H>
-__global__ void __launch_bounds__(kWave) k_spgemm_fill(
-    const int* __restrict__ arp, const int* __restrict__ aci, const double* __restrict__ av,
-    const int* __restrict__ brp, const int* __restrict__ bci, const double* __restrict__ bv,
-    const int* __restrict__ crp, int* __restrict__ cci, double* __restrict__ cv) {
-  __shared__ int keys[H];
-  __shared__ double vals[H];
-  __shared__ int list[H];
-  __shared__ int cnt;
-  __shared__ RowStage st;
-  const int i = blockIdx.x, t = threadIdx.x;
-  for (int s = t; s < H; s += kWave) { keys[s] = -1; vals[s] = 0.0; }
-  if (t == 0) cnt = 0;
-  const int a0 = arp[i], len = arp[i + 1] - a0;
-  const bool staged = stage_row(st, a0, len, aci, av, brp);
-  __syncthreads();
-  for (int a = 0; a < len; ++a) {
-    int b0, b1;
-    double x;
-    if (staged) {
-      b0 = st.b0[a];
-      b1 = st.b1[a];
-      x = st.av[a];
-    } else {
-      const int j = aci[a0 + a];
-      b0 = brp[j];
-      b1 = brp[j + 1];
-      x = av[a0 + a];
-    }
-    for (int b = b0 + t; b < b1; b += kWave) {
-      const int key = bci[b];
-      uint32_t s = slot_hash(key) & (H - 1);
-      for (int probes = 0; probes < H; ++probes) {
-        int prev = atomicCAS(&keys[s], -1, key);
-        if (prev == -1 || prev == key) break;
-        s = (s + 1) & (H - 1);
+  if (MODE == SP_COUNT) {
+    if (i < n && tr == 0) counts[i] = cnt[rl];
+    return;
+  }
+  if (MODE == SP_FILL) {
+    for (int q = tr; q < H; q += per_row) {
+      const int key = keys[q];
+      if (key != -1) {
+        double v = vals[q];
+        for (int u = 1; u < W; ++u) v += vals[(size_t)u * H + q];
+        vals[q] = v;
+        const int p = atomicAdd(&cnt[rl], 1);
+        list[p] = q;
+        ckey[p] = key;
       }
-      vals[s] = vals[s] + x * bv[b];
     }
     __syncthreads();
+    if (i >= n) return;
+    const int u = cnt[rl], base = off[i];
+    for (int p = tr; p < u; p += per_row) {
+      const int key = ckey[p];
+      int rank = 0;
+      for (int q = 0; q < u; ++q) rank += ckey[q] < key ? 1 : 0;
+      cci[base + rank] = key;
+      cv[base + rank] = vals[list[p]];
+    }
+    return;
   }
-  for (int s = t; s < H; s += kWave)
-    if (keys[s] != -1) list[atomicAdd(&cnt, 1)] = s;
-  __syncthreads();
-  const int u = cnt, base = crp[i];
-  for (int p = t; p < u; p += kWave) {
-    const int key = keys[list[p]];
-    int rank = 0;
-    for (int q = 0; q < u; ++q) rank += keys[list[q]] < key ? 1 : 0;
-    cci[base + rank] = key;
-    cv[base + rank] = vals[list[p]];
+  // SP_DENSE: thread tr owns the contiguous slots [s0, s1); an exclusive scan
+  // of the owned counts over the row's threads gives each its output offset.
+  const int per = (H + per_row - 1) / per_row;
+  const int s0 = min(H, tr * per), s1 = min(H, s0 + per);
+  int c = 0;
+  for (int q = s0; q < s1; ++q) c += keys[q] != -1 ? 1 : 0;
+  const int width = per_row < kWave ? per_row : kWave;
+  int inc = c;
+  const int wl = tr % width;
+  for (int o = 1; o < width; o <<= 1) {
+    const int t = __shfl_up(inc, o, width);
+    if (wl >= o) inc += t;
+  }
+  int* wtot = cnt + rl * (per_row / kWave + 1);
+  if (per_row > kWave) {
+    if (wl == width - 1) wtot[tr / kWave] = inc;
+    __syncthreads();
+    int before = 0;
+    for (int q = 0; q < tr / kWave; ++q) before += wtot[q];
+    inc += before;
+  }
+  if (i >= n) return;
+  int pos = off[i] + inc - c;
+  for (int q = s0; q < s1; ++q) {
+    if (keys[q] != -1) {
+      double v = vals[q];
+      for (int u = 1; u < W; ++u) v += vals[(size_t)u * H + q];
+      cci[pos] = q;
+      cv[pos] = v;
+      ++pos;
+    }
+  }
+  if (tr == per_row - 1) counts[i] = inc;
+}
+
+__global__ void k_stride_offsets(int n, int stride, int* __restrict__ off) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) off[i] = i * stride;
+}
+
+// Copy the rows of a product from scratch rows (at off[i]) into C.
+template <int LPR>
+__global__ void __launch_bounds__(kBlock) k_spgemm_compact(int n, const int* __restrict__ off,
+                                                           const int* __restrict__ crp,
+                                                           const int* __restrict__ sci,
+                                                           const double* __restrict__ sv,
+                                                           int* __restrict__ cci,
+                                                           double* __restrict__ cv) {
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / LPR, lane = threadIdx.x % LPR;
+  if (i >= n) return;
+  const int src = off[i], dst = crp[i], len = crp[i + 1] - dst;
+  for (int k = lane; k < len; k += LPR) {
+    cci[dst + k] = sci[src + k];
+    cv[dst + k] = sv[src + k];
   }
 }
 
@@ -483,19 +550,29 @@ __global__ void k_transpose_fill(int n, const int* __restrict__ rp, const int* _
 
 // Sort every row of an unsorted CSR by column into (ci, v): one 64-lane
 // workgroup per row; each entry's destination is the number of smaller keys
-// in its row (keys are distinct within a row).
+// in its row (keys are distinct within a row).  Rows up to kRankStage
+// entries are compared from LDS.
+constexpr int kRankStage = 2048;
 __global__ void __launch_bounds__(kWave) k_rank_rows(const int* __restrict__ rp,
                                                      const int* __restrict__ uci,
                                                      const double* __restrict__ uv,
                                                      int* __restrict__ ci, double* __restrict__ v) {
+  __shared__ int sk[kRankStage];
   const int i = blockIdx.x;
-  const int b = rp[i], e = rp[i + 1];
-  for (int p = b + threadIdx.x; p < e; p += kWave) {
-    const int key = uci[p];
+  const int b = rp[i], e = rp[i + 1], len = e - b;
+  const bool staged = len <= kRankStage;
+  if (staged)
+    for (int p = threadIdx.x; p < len; p += kWave) sk[p] = uci[b + p];
+  __syncthreads();
+  for (int p = threadIdx.x; p < len; p += kWave) {
+    const int key = staged ? sk[p] : uci[b + p];
     int rank = 0;
-    for (int q = b; q < e; ++q) rank += uci[q] < key ? 1 : 0;
+    if (staged)
+      for (int q = 0; q < len; ++q) rank += sk[q] < key ? 1 : 0;
+    else
+      for (int q = b; q < e; ++q) rank += uci[q] < key ? 1 : 0;
     ci[b + rank] = key;
-    v[b + rank] = uv[p];
+    v[b + rank] = uv[b + p];
   }
 }
 
@@ -536,41 +613,10 @@ __global__ void __launch_bounds__(1024) k_dense_inverse(int n, double* __restric
   }
 }
 
-// The same elimination done in place in LDS (the identity half implicit):
-// at step k the pivot row is divided by the pivot with a_kk replaced by 1,
-// and every other row i gets a_ij -= f_i a_kj with a_ik replaced by 0.
-// G holds the n x 2n array [A | I]; only its left half is read.
-__global__ void __launch_bounds__(1024) k_dense_inverse_lds(int n, const double* __restrict__ G,
-                                                            double* __restrict__ Ainv,
-                                                            int* __restrict__ flag) {
-  extern __shared__ double M[];
-  __shared__ double f[kDenseMax];
-  __shared__ double piv;
-  const int t = threadIdx.x, nt = blockDim.x;
-  for (int p = t; p < n * n; p += nt) M[p] = G[(size_t)(p / n) * 2 * n + (p % n)];
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    if (t == 0) {
-      double d = M[k * n + k];
-      if (!(d > 0.0)) { atomicOr(flag, 2); d = 1.0; }
-      piv = d;
-    }
-    for (int i = t; i < n; i += nt) f[i] = M[i * n + k];
-    __syncthreads();
-    const double inv = 1.0 / piv;
-    for (int j = t; j < n; j += nt) M[k * n + j] = (j == k ? 1.0 : M[k * n + j]) * inv;
-    __syncthreads();
-    for (int p = t; p < n * n; p += nt) {
-      const int i = p / n, j = p % n;
-      if (i != k) M[p] = (j == k ? 0.0 : M[p]) - f[i] * M[k * n + j];
-    }
-    __syncthreads();
-  }
-  for (int p = t; p < n * n; p += nt) Ainv[p] = M[p];
-}
-
-// The same in-place elimination with the matrix held in registers.  With
-// G = 1024 / n row groups, thread t < G n owns column j = t mod n and rows
+// The same elimination done in place with the matrix held in registers (the
+// identity half implicit): at step k the pivot row is divided by the pivot
+// with a_kk replaced by 1, and every other row i gets a_ij -= f_i a_kj with
+// a_ik replaced by 0.  With G = 1024 / n row groups, thread t < G n owns column j = t mod n and rows
 // i = g, g + G, g + 2G, ... (g = t / n), at most E of them; the pivot column
 // and the scaled pivot row are exchanged through LDS.
 template <int E>
@@ -659,6 +705,67 @@ __global__ void k_densify(int n, const int* __restrict__ rp, const int* __restri
     }                                                                                        \
     PPE_LAUNCH_CHECK();                                                                      \
   } while (0)
+// Launch configuration of k_spgemm_rows for one product.
+struct SpConfig {
+  int lpr, W, H, rpb, threads;
+  size_t lds;
+};
+
+static size_t spgemm_lds(int mode, int rpb, int W, int H, int per_row) {
+  const size_t r = (size_t)rpb, h = (size_t)H;
+  if (mode == SP_COUNT) return r * h * 4 + r * 4;
+  if (mode == SP_FILL) return r * W * h * 8 + 2 * r * h * 4 + r * 4;
+  return r * W * h * 8 + r * h * 4 + r * (per_row / kWave + 1) * 4;
+}
+
+// Lanes per sub-group from the mean row length of B; sub-groups per row so
+// that each walks about eight entries of A; rows per block to fill 256
+// threads.  W is halved until the block's LDS fits.
+static SpConfig spgemm_config(ppe_solver* s, const Csr& A, const Csr& B, int mode, int H) {
+  SpConfig c{};
+  c.lpr = lanes_for(B);
+  const double mean_a = A.n ? (double)A.nnz / A.n : 1.0;
+  c.W = 1;
+  while (c.W * c.lpr < 1024 && c.W < 16 && c.W * 8 < mean_a) c.W *= 2;
+  c.H = H;
+  while (true) {
+    const int per_row = c.lpr * c.W;
+    c.rpb = per_row >= kBlock ? 1 : kBlock / per_row;
+    c.threads = c.rpb * per_row;
+    c.lds = spgemm_lds(mode, c.rpb, c.W, H, per_row);
+    if (c.lds <= s->lds_max || (c.W == 1 && c.rpb == 1)) break;
+    if (c.W > 1) c.W /= 2;
+    else c.lpr *= 2;  // fewer rows per block
+  }
+  require(c.lds <= s->lds_max, PPE_ERR_INTERNAL, "sparse product row does not fit in LDS");
+  return c;
+}
+
+template <int MODE>
+static void spgemm_launch(ppe_solver* s, const SpConfig& c, const Csr& A, const Csr& B,
+                          const int* off, int* counts, int* cci, double* cv, int* flag) {
+  const int g = (A.n + c.rpb - 1) / c.rpb;
+  const double* av = MODE == SP_COUNT ? nullptr : A.v();
+  const double* bv = MODE == SP_COUNT ? nullptr : B.v();
+#define PPE_SPR(L_)                                                                            \
+  hipLaunchKernelGGL((k_spgemm_rows<L_, MODE>), dim3(g), dim3(c.threads), c.lds, s->stream, A.n, \
+                     c.W, c.H, A.rp(), A.ci(), av, B.rp(), B.ci(), bv, off, counts, cci, cv, flag)
+  switch (c.lpr) {
+    case 4: PPE_SPR(4); break;
+    case 8: PPE_SPR(8); break;
+    case 16: PPE_SPR(16); break;
+    case 32: PPE_SPR(32); break;
+    default: PPE_SPR(64); break;
+  }
+#undef PPE_SPR
+  PPE_LAUNCH_CHECK();
+}
+
+// C = A B.  Narrow products (C at most kSpDenseWidth columns, rows expected
+// to fill a quarter of them) take one pass with a slot per column into
+// fixed-stride scratch rows and a compaction;
+// wider ones count each row's distinct columns with a hash sized from the
+// product bound, then fill C with a hash sized from the largest count.
 void spgemm(ppe_solver* s, const Csr& A, const Csr& B, Csr& C) {
   require(A.m == B.n, PPE_ERR_INTERNAL, "spgemm shape mismatch");
   C.n = A.n;
@@ -669,53 +776,61 @@ void spgemm(ppe_solver* s, const Csr& A, const Csr& B, Csr& C) {
     fill_int(s, crp, 0, 1);
     return;
   }
-  int* counts = s->tmp_i[0].get<int>(C.n + 1);
   int* flag = s->flag.get<int>(4);
-  PPE_ROWS(lanes_for(A), k_spgemm_bound, C.n, C.n, A.rp(), A.ci(), B.rp(), counts);
-  const int ub = reduce_max_int(s, counts, C.n);
-  int Hc = 64;
-  while (Hc < 2 * ub && Hc < 2048) Hc *= 2;
-  fill_int(s, flag, 0, 2);
-#define PPE_COUNT(HH)                                                                        \
-  hipLaunchKernelGGL(k_spgemm_count<HH>, dim3(C.n), dim3(kWave), 0, s->stream, A.rp(), A.ci(), \
-                     B.rp(), B.ci(), counts, flag)
-  if (Hc <= 64) PPE_COUNT(64);
-  else if (Hc <= 128) PPE_COUNT(128);
-  else if (Hc <= 256) PPE_COUNT(256);
-  else if (Hc <= 512) PPE_COUNT(512);
-  else if (Hc <= 1024) PPE_COUNT(1024);
-  else PPE_COUNT(2048);
-#undef PPE_COUNT
-  PPE_LAUNCH_CHECK();
-  max_int_async(s, counts, C.n, flag + 1);
-  // one host round trip for the scan total, the overflow flag and the max
+  int* counts = s->sp_cnt.get<int>(C.n + 1);
   long long total = 0;
   int fm[2] = {0, 0};
-  exclusive_scan_async(s, counts, crp, C.n);
-  PPE_HIP(hipMemcpyAsync(&total, s->tmp_l[0].as<long long>() + scan_blocks(C.n), sizeof(long long),
-                         hipMemcpyDeviceToHost, s->stream));
+  auto fetch_scan = [&](bool with_max) {
+    exclusive_scan_async(s, counts, crp, C.n);
+    if (with_max) max_int_async(s, counts, C.n, flag + 1);
+    PPE_HIP(hipMemcpyAsync(&total, s->tmp_l[0].as<long long>() + scan_blocks(C.n),
+                           sizeof(long long), hipMemcpyDeviceToHost, s->stream));
+    PPE_HIP(hipMemcpyAsync(fm, flag, sizeof(int) * 2, hipMemcpyDeviceToHost, s->stream));
+    PPE_HIP(hipStreamSynchronize(s->stream));
+    require(fm[0] == 0, PPE_ERR_INTERNAL, "sparse product row overflowed its hash table");
+    require(total <= INT32_MAX, PPE_ERR_INTERNAL, "sparse product too large for int32 indices");
+    C.nnz = total;
+  };
+  fill_int(s, flag, 0, 2);
+
+  const double mean_a = (double)A.nnz / A.n, mean_b = B.n ? (double)B.nnz / B.n : 0.0;
+  if (C.m <= kSpDenseWidth && 4.0 * mean_a * mean_b >= C.m) {
+    int H = 64;
+    while (H < C.m) H += 64;
+    const SpConfig c = spgemm_config(s, A, B, SP_DENSE, H);
+    const size_t cap = (size_t)C.n * C.m;
+    require(cap <= INT32_MAX, PPE_ERR_INTERNAL, "sparse product scratch too large");
+    int* off = s->sp_off.get<int>(C.n + 1);
+    hipLaunchKernelGGL(k_stride_offsets, dim3(grid_for(C.n + 1)), dim3(kBlock), 0, s->stream,
+                       C.n + 1, C.m, off);
+    PPE_LAUNCH_CHECK();
+    int* sci = s->sp_ci.get<int>(cap);
+    double* sv = s->sp_v.get<double>(cap);
+    spgemm_launch<SP_DENSE>(s, c, A, B, off, counts, sci, sv, flag);
+    fetch_scan(false);
+    int* cci = C.col.get<int>(C.nnz);
+    double* cv = C.val.get<double>(C.nnz);
+    PPE_ROWS(lanes_for(B), k_spgemm_compact, C.n, C.n, off, crp, sci, sv, cci, cv);
+    return;
+  }
+
+  int* prod = s->sp_prod.get<int>(C.n + 1);
+  PPE_ROWS(lanes_for(A), k_spgemm_bound, C.n, C.n, A.rp(), A.ci(), B.rp(), prod);
+  max_int_async(s, prod, C.n, flag + 1);
   PPE_HIP(hipMemcpyAsync(fm, flag, sizeof(int) * 2, hipMemcpyDeviceToHost, s->stream));
   PPE_HIP(hipStreamSynchronize(s->stream));
-  require(fm[0] == 0, PPE_ERR_INTERNAL,
-          "sparse product row exceeds the hash table (more than 1024 distinct columns)");
-  require(total <= INT32_MAX, PPE_ERR_INTERNAL, "sparse product too large for int32 indices");
-  C.nnz = total;
-  const int mx = fm[1];
+  const int ub = std::min(fm[1], C.m);
+  int Hc = 32;
+  while (Hc < 2 * ub && Hc < 8192) Hc *= 2;
+  const SpConfig cc = spgemm_config(s, A, B, SP_COUNT, Hc);
+  spgemm_launch<SP_COUNT>(s, cc, A, B, nullptr, counts, nullptr, nullptr, flag);
+  fetch_scan(true);
+  int H = 16;  // at least twice the longest row: list and ckey hold H / 2
+  while (H < 2 * fm[1]) H *= 2;
+  const SpConfig cf = spgemm_config(s, A, B, SP_FILL, H);
   int* cci = C.col.get<int>(C.nnz);
   double* cv = C.val.get<double>(C.nnz);
-  int H = 64;
-  while (H < 2 * mx) H *= 2;
-#define PPE_FILL(HH)                                                                          \
-  hipLaunchKernelGGL(k_spgemm_fill<HH>, dim3(C.n), dim3(kWave), 0, s->stream, A.rp(), A.ci(),  \
-                     A.v(), B.rp(), B.ci(), B.v(), crp, cci, cv)
-  if (H <= 64) PPE_FILL(64);
-  else if (H <= 128) PPE_FILL(128);
-  else if (H <= 256) PPE_FILL(256);
-  else if (H <= 512) PPE_FILL(512);
-  else if (H <= 1024) PPE_FILL(1024);
-  else PPE_FILL(2048);
-#undef PPE_FILL
-  PPE_LAUNCH_CHECK();
+  spgemm_launch<SP_FILL>(s, cf, A, B, crp, nullptr, cci, cv, flag);
 }
 
 void transpose(ppe_solver* s, const Csr& A, Csr& T) {
@@ -730,7 +845,7 @@ void transpose(ppe_solver* s, const Csr& A, Csr& T) {
     PPE_LAUNCH_CHECK();
   }
   int* trp = T.rowptr.get<int>(T.n + 1);
-  exclusive_scan(s, cnt, trp, T.n);
+  exclusive_scan_async(s, cnt, trp, T.n);  // the total is A.nnz
   int* cursor = s->tmp_i[1].get<int>(T.n + 1);
   PPE_HIP(hipMemcpyAsync(cursor, trp, sizeof(int) * (T.n + 1), hipMemcpyDeviceToDevice, s->stream));
   int* tci = T.col.get<int>(T.nnz);
@@ -890,21 +1005,18 @@ void build_hierarchy(ppe_solver* s) {
                          L.A.ci(), L.A.v(), G);
       PPE_LAUNCH_CHECK();
       fill_int(s, flag, 0, 1);
-      const size_t lds = sizeof(double) * (size_t)n * n;
-      if (lds + sizeof(double) * (kDenseMax + 1) <= s->lds_max) {
-        hipLaunchKernelGGL(k_dense_inverse_lds, dim3(1), dim3(1024), lds, s->stream, n, G, Ainv,
-                           flag);
-      } else if (n <= 256) {
-        const int rows_per = (n + (1024 / n) - 1) / (1024 / n);  // rows one thread owns
-        if (rows_per <= 24)
-          hipLaunchKernelGGL(k_dense_inverse_reg<24>, dim3(1), dim3(1024), 0, s->stream, n, G,
-                             Ainv, flag);
-        else if (rows_per <= 40)
-          hipLaunchKernelGGL(k_dense_inverse_reg<40>, dim3(1), dim3(1024), 0, s->stream, n, G,
-                             Ainv, flag);
-        else
-          hipLaunchKernelGGL(k_dense_inverse_reg<64>, dim3(1), dim3(1024), 0, s->stream, n, G,
-                             Ainv, flag);
+      if (n <= 256) {
+        // rows one thread owns; every FMA of the elimination stays in registers
+        const int rows_per = (n + (1024 / n) - 1) / (1024 / n);
+#define PPE_DINV(E_)                                                                           \
+  hipLaunchKernelGGL(k_dense_inverse_reg<E_>, dim3(1), dim3(1024), 0, s->stream, n, G, Ainv, flag)
+        if (rows_per <= 4) PPE_DINV(4);
+        else if (rows_per <= 8) PPE_DINV(8);
+        else if (rows_per <= 16) PPE_DINV(16);
+        else if (rows_per <= 24) PPE_DINV(24);
+        else if (rows_per <= 40) PPE_DINV(40);
+        else PPE_DINV(64);
+#undef PPE_DINV
       } else {
         hipLaunchKernelGGL(k_dense_inverse, dim3(1), dim3(1024), 0, s->stream, n, G, Ainv, flag);
       }

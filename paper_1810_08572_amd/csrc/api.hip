@@ -94,7 +94,7 @@ void ppe_default_options(ppe_options* o) {
   o->coarse_max = 128;
   o->max_levels = 10;
   o->theta = 0.08;
-  o->check_every = 1;
+  o->check_every = 2;
   o->stream = nullptr;
   o->use_graph = 1;
 }

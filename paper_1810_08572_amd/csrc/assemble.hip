@@ -128,6 +128,35 @@ __device__ __forceinline__ int find_root(int* parent, int x) {
   return x;
 }
 
+// Connected components start from a forest built without atomics: every
+// active cell hooks to its smallest active neighbour (or itself), which
+// already joins most of a component; the forest is then flattened (each cell
+// to its tree's root) and the face pass below only links the remaining trees.
+// Every link points to a smaller index, so each component's root is its
+// smallest cell.
+__global__ void k_cc_init(int n, const int* __restrict__ adj_ptr, const int* __restrict__ adj_nbr,
+                          const int* __restrict__ active, int* __restrict__ forest) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int m = i;
+  if (active[i])
+    for (int k = adj_ptr[i]; k < adj_ptr[i + 1]; ++k) {
+      const int j = adj_nbr[k];
+      if (j < m && active[j]) m = j;
+    }
+  forest[i] = m;
+}
+
+// parent_i = root of i in the forest (indices strictly decrease along a path,
+// so the walk ends).
+__global__ void k_cc_flatten(int n, const int* __restrict__ forest, int* __restrict__ parent) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int p = forest[i];
+  while (forest[p] != p) p = forest[p];
+  parent[i] = p;
+}
+
 __global__ void k_union(const int* __restrict__ owner, const int* __restrict__ neigh, int n_faces,
                         const int* __restrict__ active, int* parent) {
   int f = blockIdx.x * kBlock + threadIdx.x;
@@ -385,6 +414,13 @@ void assemble_fine(ppe_solver* s, const double* coeff, const double* fl) {
   int* comp = s->comp_full.get<int>(nc);
   int* is_pin = s->tmp_i[2].get<int>(nc);
   if (nf) {
+    int* forest = s->tmp_i[1].get<int>(nc);
+    hipLaunchKernelGGL(k_cc_init, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc,
+                       s->adj_ptr.as<int>(), s->adj_nbr.as<int>(), active, forest);
+    PPE_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_cc_flatten, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc, forest,
+                       parent);
+    PPE_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_union, dim3(grid_for(nf)), dim3(kBlock), 0, s->stream, s->owner.as<int>(),
                        s->neigh.as<int>(), nf, active, parent);
     PPE_LAUNCH_CHECK();

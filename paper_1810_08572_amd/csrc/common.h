@@ -155,6 +155,7 @@ struct ppe_solver {
   ppe::DevBuf vx, vr, vz, vp, vq, vzold, vb;
   ppe::DevBuf scal, partial, counter, flag;
   ppe::DevBuf tmp_i[4], tmp_d[2], tmp_l[2];
+  ppe::DevBuf sp_prod, sp_off, sp_cnt, sp_ci, sp_v;  // sparse-product scratch
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
   // HIP graph of two PCG iterations, captured once per hierarchy

@@ -8,10 +8,13 @@
 // lanes per row with a shuffle reduction inside the group.  Reductions are
 // deterministic and fence-free: producers write one partial per block,
 // consumers add the partials in a fixed order.
+#include <hip/hip_ext.h>
+
 #include "common.h"
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 namespace ppe {
 namespace {
@@ -22,6 +25,9 @@ enum Epi : int {
   E_CHEB = 2,   // r = (b - A x)/diag; d = c1 d + c2 r; y = x + d
   E_DOT = 3,    // y = A x, partial sums of x.y
   E_POWER = 4,  // y = (A x)/diag / ||x||, partial sums of y.y
+  E_CHEB0 = 5,  // the first two Chebyshev steps from a zero guess in one
+                // pass: x = c0 b/diag is formed on the fly (for the row and
+                // its neighbours), then the E_CHEB step from d = x
 };
 
 // partial-sum slots (each kRedBlocks doubles) in s->partial: power iteration
@@ -29,12 +35,28 @@ enum Slot : int { P_POW = 0 /* 0, 1 */, P_NSLOTS = 2 };
 // device scalars in s->scal
 enum Scal : int { S_POW = 0, S_N = 2 };
 
+// Operand of the matrix product: x_j, or for E_CHEB0 the first Chebyshev
+// iterate c0 b_j / diag_j (the same expression the unfused first step stores).
+template <int EPI, class T>
+__device__ __forceinline__ T operand(int j, const T* __restrict__ x, const T* __restrict__ b,
+                                     const T* __restrict__ diag, T c0) {
+  if (EPI == E_CHEB0) return c0 * (b[j] / diag[j]);
+  return x[j];
+}
+
 template <int EPI, class T>
 __device__ __forceinline__ double epilogue(int i, T ax, const T* __restrict__ x,
                                            const T* __restrict__ b, const T* __restrict__ diag,
                                            T* __restrict__ d, T c1, T c2, T scale,
-                                           T* __restrict__ y) {
-  if (EPI == E_SPMV) {
+                                           T* __restrict__ y, T c0 = T(0)) {
+  if (EPI == E_CHEB0) {
+    const T x1 = c0 * (b[i] / diag[i]);
+    const T r = (b[i] - ax) / diag[i];
+    const T dn = c1 * x1 + c2 * r;
+    d[i] = dn;
+    y[i] = x1 + dn;
+    return 0.0;
+  } else if (EPI == E_SPMV) {
     y[i] = ax;
     return 0.0;
   } else if (EPI == E_RESID) {
@@ -56,22 +78,51 @@ __device__ __forceinline__ double epilogue(int i, T ax, const T* __restrict__ x,
   }
 }
 
+// Off-diagonal part of row i of an ELL matrix (slot-major, n rows) added to
+// s in slot order.  With WM > 0 (W <= WM) the slot loop is unrolled, so every
+// column index, and then every gathered operand, is requested before the
+// first one is used.
+template <int EPI, int WM, class T>
+__device__ __forceinline__ T ell_row(T s, int i, int n, int W, const int* __restrict__ ecol,
+                                     const T* __restrict__ eval, const T* __restrict__ x,
+                                     const T* __restrict__ b, const T* __restrict__ diag, T c0) {
+  if (WM > 0) {
+    int col[WM > 0 ? WM : 1];
+    T v[WM > 0 ? WM : 1];
+#pragma unroll
+    for (int k = 0; k < WM; ++k) {
+      const size_t e = (size_t)k * n + i;
+      col[k] = k < W ? ecol[e] : i;
+      v[k] = k < W ? eval[e] : T(0);
+    }
+    T g[WM > 0 ? WM : 1];
+#pragma unroll
+    for (int k = 0; k < WM; ++k) g[k] = operand<EPI, T>(col[k], x, b, diag, c0);
+#pragma unroll
+    for (int k = 0; k < WM; ++k)
+      if (k < W) s = s + v[k] * g[k];
+    return s;
+  }
+  for (int k = 0; k < W; ++k) {
+    const size_t e = (size_t)k * n + i;
+    s = s + eval[e] * operand<EPI, T>(ecol[e], x, b, diag, c0);
+  }
+  return s;
+}
+
 // ---- finest level: ELL, one thread per row (grid-stride)
-template <int EPI, class T>
+template <int EPI, class T, int WM>
 __global__ void __launch_bounds__(kBlock) k_ell(int n, int W, const int* __restrict__ ecol,
                                                 const T* __restrict__ eval,
                                                 const T* __restrict__ diag, const T* __restrict__ x,
                                                 const T* __restrict__ b, T* __restrict__ d, T c1,
                                                 T c2, T* __restrict__ y,
-                                                double* __restrict__ partials) {
+                                                double* __restrict__ partials, T c0) {
   double dot = 0.0;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    T s = diag[i] * x[i];
-    for (int k = 0; k < W; ++k) {
-      const size_t e = (size_t)k * n + i;
-      s = s + eval[e] * x[ecol[e]];
-    }
-    dot += epilogue<EPI, T>(i, s, x, b, diag, d, c1, c2, T(1), y);
+    T s = diag[i] * operand<EPI, T>(i, x, b, diag, c0);
+    s = ell_row<EPI, WM, T>(s, i, n, W, ecol, eval, x, b, diag, c0);
+    dot += epilogue<EPI, T>(i, s, x, b, diag, d, c1, c2, T(1), y, c0);
   }
   if (EPI == E_DOT) {
     double v[1] = {dot};
@@ -88,7 +139,7 @@ __global__ void __launch_bounds__(kBlock) k_csr(int n, const int* __restrict__ r
                                                 const T* __restrict__ x, const T* __restrict__ b,
                                                 T* __restrict__ d, T c1, T c2, T* __restrict__ y,
                                                 const double* __restrict__ prevp, int gprev,
-                                                double* __restrict__ partials) {
+                                                double* __restrict__ partials, T c0) {
   T scale = T(1);
   if (EPI == E_POWER) scale = T(1.0 / sqrt(sum_partials<kBlock>(prevp, gprev)));
   const int lane = threadIdx.x % LPR;
@@ -100,11 +151,12 @@ __global__ void __launch_bounds__(kBlock) k_csr(int n, const int* __restrict__ r
     const int g = t * groups + my;
     T s = T(0);
     if (g < n) {
-      for (int k = rp[g] + lane; k < rp[g + 1]; k += LPR) s = s + v[k] * x[ci[k]];
+      for (int k = rp[g] + lane; k < rp[g + 1]; k += LPR)
+        s = s + v[k] * operand<EPI, T>(ci[k], x, b, diag, c0);
     }
 #pragma unroll
     for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_down(s, o, LPR);
-    if (g < n && lane == 0) dot += epilogue<EPI, T>(g, s, x, b, diag, d, c1, c2, scale, y);
+    if (g < n && lane == 0) dot += epilogue<EPI, T>(g, s, x, b, diag, d, c1, c2, scale, y, c0);
   }
   if (EPI == E_DOT || EPI == E_POWER) {
     double vv[1] = {dot};
@@ -226,7 +278,52 @@ __global__ void __launch_bounds__(kBlock) k_dot2_t(Tiles T, const double* __rest
   write_partials<kBlock, 2>(sv, part);
 }
 
+// The last smoothing step of a level-0 V-cycle fused with the PCG dots that
+// follow it: the E_CHEB step y = x + d over the tile's rows, then tile
+// partials of b.y and (flexible) b.zold, where b is the PCG residual the
+// V-cycle was applied to.  Same arithmetic and order as the separate kernels.
+template <int WM>
+__global__ void __launch_bounds__(kBlock) k_ell_cheb_dot_t(
+    Tiles T, int n, int W, const int* __restrict__ ecol, const double* __restrict__ eval,
+    const double* __restrict__ diag, const double* __restrict__ x, const double* __restrict__ b,
+    double* __restrict__ d, double c1, double c2, double* __restrict__ y,
+    const double* __restrict__ zold, double* __restrict__ part) {
+  const int t = blockIdx.x;
+  double sv[2] = {0.0, 0.0};
+  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) {
+    double s = diag[i] * x[i];
+    s = ell_row<E_CHEB, WM, double>(s, i, n, W, ecol, eval, x, b, diag, 0.0);
+    const double r = (b[i] - s) / diag[i];
+    const double dn = (c1 == 0.0 ? 0.0 : c1 * d[i]) + c2 * r;
+    d[i] = dn;
+    const double yi = x[i] + dn;
+    y[i] = yi;
+    sv[0] += b[i] * yi;
+    if (zold) sv[1] += b[i] * zold[i];
+  }
+  write_partials<kBlock, 2>(sv, part);
+}
+
+// Mixed precision: z = (double) z32 over the tile's rows with the PCG dots
+// r.z and (flexible) r.zold as tile partials.
+__global__ void __launch_bounds__(kBlock) k_cast_dot_t(Tiles T, const float* __restrict__ zf,
+                                                       const double* __restrict__ r,
+                                                       const double* __restrict__ zold,
+                                                       double* __restrict__ z,
+                                                       double* __restrict__ part) {
+  const int t = blockIdx.x;
+  double sv[2] = {0.0, 0.0};
+  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) {
+    const double v = (double)zf[i];
+    z[i] = v;
+    sv[0] += r[i] * v;
+    if (zold) sv[1] += r[i] * zold[i];
+  }
+  write_partials<kBlock, 2>(sv, part);
+}
+
 // q = A p on the finest (ELL) level over the tile's rows; tile partial of p.q
+template <int WM>
 __global__ void __launch_bounds__(kBlock) k_ell_dot_t(Tiles T, int n, int W,
                                                       const int* __restrict__ ecol,
                                                       const double* __restrict__ eval,
@@ -240,10 +337,7 @@ __global__ void __launch_bounds__(kBlock) k_ell_dot_t(Tiles T, int n, int W,
   if (!done[T.seg[t]]) {
     for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) {
       double s = diag[i] * p[i];
-      for (int k = 0; k < W; ++k) {
-        const size_t e = (size_t)k * n + i;
-        s = s + eval[e] * p[ecol[e]];
-      }
+      s = ell_row<E_SPMV, WM, double>(s, i, n, W, ecol, eval, p, nullptr, diag, 0.0);
       q[i] = s;
       acc += p[i] * s;
     }
@@ -306,8 +400,10 @@ __global__ void __launch_bounds__(kBlock) k_update_xr_t(Tiles T, const int* __re
                                                         double* __restrict__ x,
                                                         double* __restrict__ r,
                                                         double* __restrict__ part,
+                                                        int* __restrict__ active,
                                                         int* __restrict__ err) {
   const int t = blockIdx.x, q = T.seg[t];
+  if (t == 0 && threadIdx.x == 0) *active = 0;  // counted again by k_update_p_t
   double acc = 0.0;
   if (!done[q]) {
     const double pq = seg_sum(part_pq, T, q);
@@ -327,52 +423,42 @@ __global__ void __launch_bounds__(kBlock) k_update_xr_t(Tiles T, const int* __re
   write_partials<kBlock, 1>(sv, part);
 }
 
-// Per active segment (one block each): count the iteration, test ||r||^2
-// against the tolerance; counts segments still running.
-__global__ void __launch_bounds__(kBlock) k_seg_step(int ns, Tiles T,
-                                                     const double* __restrict__ part_rr,
-                                                     const double* __restrict__ sc,
-                                                     int* __restrict__ done,
-                                                     int* __restrict__ iters,
-                                                     int* __restrict__ restart,
-                                                     int* __restrict__ active,
-                                                     int* __restrict__ err) {
-  const int q = blockIdx.x;
-  if (done[q]) return;
-  const double rr = seg_sum(part_rr, T, q);
-  if (threadIdx.x != 0) return;
-  iters[q] += 1;
-  restart[q] = 0;
-  if (!(rr == rr) || rr > 1.7976931348623157e308) {
-    atomicOr(err, 2);
-    done[q] = 1;
-    return;
-  }
-  if (rr <= sc[SS_TOL2 * ns + q])
-    done[q] = 1;
-  else
-    atomicAdd(active, 1);
-}
-
-// beta_q = (r.z - [r.z_old]) / rz_prev (0 right after a restart); p = z + beta p
-__global__ void __launch_bounds__(kBlock) k_update_p_t(Tiles T, int nt, const int* __restrict__ done,
-                                                       const int* __restrict__ restart,
-                                                       const double* __restrict__ part_rz,
-                                                       int flexible,
-                                                       const double* __restrict__ rz_prev,
-                                                       double* __restrict__ rz_next,
-                                                       const double* __restrict__ z,
-                                                       double* __restrict__ p,
-                                                       int* __restrict__ err) {
+// With test set (every PCG iteration): count the iteration of each running
+// segment and test its recurred ||r||^2 against the tolerance; every tile
+// of a segment adds the same partials in the same order, so all of them take
+// the same decision, and a segment that converged (or broke down) keeps its
+// p.  Otherwise (first direction after a restart) restart[q] forces beta 0.
+// Then beta_q = (r.z - [r.z_old]) / rz_prev and p = z + beta p; counts the
+// segments still running.
+__global__ void __launch_bounds__(kBlock) k_update_p_t(
+    Tiles T, int nt, int ns, int test, int* __restrict__ done, int* __restrict__ restart,
+    const double* __restrict__ part_rr, const double* __restrict__ sc, int* __restrict__ iters,
+    int* __restrict__ active, const double* __restrict__ part_rz, int flexible,
+    const double* __restrict__ rz_prev, double* __restrict__ rz_next,
+    const double* __restrict__ z, double* __restrict__ p, int* __restrict__ err) {
   const int t = blockIdx.x, q = T.seg[t];
   if (done[q]) return;
+  const bool lead = t == T.tp[q] && threadIdx.x == 0;
+  if (test) {
+    const double rr = seg_sum(part_rr, T, q);
+    const bool bad = !(rr == rr) || rr > 1.7976931348623157e308;
+    const bool conv = bad || rr <= sc[SS_TOL2 * ns + q];
+    if (lead) {
+      iters[q] += 1;
+      restart[q] = 0;
+      if (bad) atomicOr(err, 2);
+      if (conv) done[q] = 1;
+      else atomicAdd(active, 1);
+    }
+    if (conv) return;
+  }
   const double rzn = seg_sum(part_rz, T, q);
   const double rzo = flexible ? seg_sum(part_rz + nt, T, q) : 0.0;
-  if (t == T.tp[q] && threadIdx.x == 0) {
+  if (lead) {
     rz_next[q] = rzn;
     if (!(rzn > 0.0)) atomicOr(err, 4);
   }
-  const double beta = restart[q] ? 0.0 : (rzn - rzo) / rz_prev[q];
+  const double beta = (!test && restart[q]) ? 0.0 : (rzn - rzo) / rz_prev[q];
   for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) p[i] = z[i] + beta * p[i];
 }
 
@@ -446,6 +532,18 @@ double* part(ppe_solver* s, int slot) {
 
 constexpr size_t kProfPairs = 256;
 
+// Launch an ELL kernel template K<WM> with the smallest unrolled width that
+// covers W (a generic slot loop beyond 12).
+#define PPE_ELL_WIDTH(W_, LAUNCH)                \
+  do {                                           \
+    const int w_ = (W_);                         \
+    if (w_ <= 4) { LAUNCH(4); }                  \
+    else if (w_ <= 6) { LAUNCH(6); }             \
+    else if (w_ <= 8) { LAUNCH(8); }             \
+    else if (w_ <= 12) { LAUNCH(12); }           \
+    else { LAUNCH(0); }                          \
+  } while (0)
+
 // Matrix and diagonal arrays of a level in value type T (FP32 copies exist
 // when the solver runs the mixed-precision V-cycle).
 template <class T> struct LevelData;
@@ -467,7 +565,8 @@ template <> struct LevelData<float> {
 // that grid size.
 template <int EPI, class T = double>
 int apply_op(ppe_solver* s, const Level& L, const T* x, const T* b, T* d, double c1, double c2,
-             T* y, double* partials, const double* prevp = nullptr, int gprev = 0) {
+             T* y, double* partials, const double* prevp = nullptr, int gprev = 0,
+             double c0 = 0.0) {
   const int n = L.n;
   if (n == 0) return 1;
   const bool reduce = EPI == E_DOT || EPI == E_POWER;
@@ -475,17 +574,26 @@ int apply_op(ppe_solver* s, const Level& L, const T* x, const T* b, T* d, double
     const int g = reduce ? red_grid(n) : grid_for(n);
     const bool prof = s->prof && EPI == E_CHEB;
     if (prof) {
+      // the event pair takes the dispatch's own start and end timestamps
       if (s->prof_pending.size() == kProfPairs) profile_harvest(s);
       const size_t k = s->prof_pending.size();
-      PPE_HIP(hipEventRecord(s->prof_ev[2 * k], s->stream));
+#define PPE_ELL_PROF(WM_)                                                                     \
+  hipExtLaunchKernelGGL((k_ell<EPI, T, WM_>), dim3(g), dim3(kBlock), 0, s->stream,             \
+                        s->prof_ev[2 * k], s->prof_ev[2 * k + 1], 0, n, L.W,                   \
+                        L.ell_col.as<int>(), LevelData<T>::ell(L), LevelData<T>::diag(L), x, b, \
+                        d, (T)c1, (T)c2, y, partials, (T)c0)
+      PPE_ELL_WIDTH(L.W, PPE_ELL_PROF);
+#undef PPE_ELL_PROF
+    } else {
+#define PPE_ELL(WM_)                                                                           \
+  hipLaunchKernelGGL((k_ell<EPI, T, WM_>), dim3(g), dim3(kBlock), 0, s->stream, n, L.W,         \
+                     L.ell_col.as<int>(), LevelData<T>::ell(L), LevelData<T>::diag(L), x, b, d,  \
+                     (T)c1, (T)c2, y, partials, (T)c0)
+      PPE_ELL_WIDTH(L.W, PPE_ELL);
+#undef PPE_ELL
     }
-    hipLaunchKernelGGL((k_ell<EPI, T>), dim3(g), dim3(kBlock), 0, s->stream, n, L.W,
-                       L.ell_col.as<int>(), LevelData<T>::ell(L), LevelData<T>::diag(L), x, b, d,
-                       (T)c1, (T)c2, y, partials);
     PPE_LAUNCH_CHECK();
     if (prof) {
-      const size_t k = s->prof_pending.size();
-      PPE_HIP(hipEventRecord(s->prof_ev[2 * k + 1], s->stream));
       const double off = (double)(L.A.nnz - n);
       const double vecs = (c1 != 0.0) ? 6.0 : 5.0;  // diag, x_in, b, x_out, d out (+ d in)
       s->prof_pending.push_back(off * (sizeof(T) + 4.0) + vecs * sizeof(T) * n);
@@ -497,7 +605,7 @@ int apply_op(ppe_solver* s, const Level& L, const T* x, const T* b, T* d, double
 #define PPE_CSR(LL)                                                                            \
   hipLaunchKernelGGL((k_csr<EPI, LL, T>), dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(),    \
                      L.A.ci(), LevelData<T>::val(L.A), LevelData<T>::diag(L), x, b, d, (T)c1,   \
-                     (T)c2, y, prevp, gprev, partials)
+                     (T)c2, y, prevp, gprev, partials, (T)c0)
   switch (lpr) {
     case 4: PPE_CSR(4); break;
     case 8: PPE_CSR(8); break;
@@ -529,36 +637,77 @@ void apply_rect(ppe_solver* s, const Csr& M, const T* x, T* y) {
   PPE_LAUNCH_CHECK();
 }
 
-// Chebyshev smoothing of A x = b.  x_in == nullptr: zero initial guess.
-// The result is written to x_out; xa/xb are ping-pong buffers distinct from
-// x_in and x_out.
+// PCG dots fused into the last level-0 step of the V-cycle: tile partials of
+// r.z and (flexible) r.z_old into part (2 x n_tiles).
+struct PcgDot {
+  Tiles T;
+  int nt;
+  const double* zold;
+  double* part;
+};
+
+// Chebyshev smoothing of A x = b.  x_in == nullptr: zero initial guess, and
+// the first two steps run as one pass.  The result is written to x_out;
+// xa/xb are ping-pong buffers distinct from x_in and x_out.  With dot (FP64,
+// level 0 only) the last step also produces the PCG dots; returns whether it
+// did.
 template <class T>
-void smooth(ppe_solver* s, Level& L, const T* b, const T* x_in, T* x_out, T* xa, T* xb) {
+bool smooth(ppe_solver* s, Level& L, const T* b, const T* x_in, T* x_out, T* xa, T* xb,
+            const PcgDot* dot = nullptr) {
   const int n = L.n;
   const int deg = 1 + (int)L.c1.size();
   T* d = L.d.as<T>();
+  auto dst_of = [&](int k) { return k == deg ? x_out : ((k % 2) ? xa : xb); };
   const T* cur = x_in;
-  for (int step = 1; step <= deg; ++step) {
-    T* dst = step == deg ? x_out : ((step % 2) ? xa : xb);
-    if (step == 1 && cur == nullptr) {
+  int step = 1;
+  if (cur == nullptr) {
+    if (deg >= 2) {
+      T* dst = dst_of(2);
+      apply_op<E_CHEB0, T>(s, L, nullptr, b, d, L.c1[0], L.c2[0], dst, nullptr, nullptr, 0,
+                           L.inv_theta);
+      cur = dst;
+      step = 3;
+    } else {
+      T* dst = dst_of(1);
       hipLaunchKernelGGL(k_cheb_first<T>, dim3(grid_for(n)), dim3(kBlock), 0, s->stream, n, b,
                          LevelData<T>::diag(L), (T)L.inv_theta, d, dst);
       PPE_LAUNCH_CHECK();
-    } else if (step == 1) {
-      apply_op<E_CHEB, T>(s, L, cur, b, d, 0.0, L.inv_theta, dst, nullptr);
-    } else {
-      apply_op<E_CHEB, T>(s, L, cur, b, d, L.c1[step - 2], L.c2[step - 2], dst, nullptr);
+      cur = dst;
+      step = 2;
     }
+  }
+  bool dotted = false;
+  for (; step <= deg; ++step) {
+    T* dst = dst_of(step);
+    const double c1 = step == 1 ? 0.0 : L.c1[step - 2];
+    const double c2 = step == 1 ? L.inv_theta : L.c2[step - 2];
+    if constexpr (std::is_same<T, double>::value) {
+      if (dot && step == deg && &L == &s->levels[0]) {
+#define PPE_CHEB_DOT(WM_)                                                                     \
+  hipLaunchKernelGGL(k_ell_cheb_dot_t<WM_>, dim3(dot->nt), dim3(kBlock), 0, s->stream, dot->T, n, \
+                     L.W, L.ell_col.as<int>(), L.ell_val.as<double>(), L.diag.as<double>(), cur, \
+                     b, d, c1, c2, dst, dot->zold, dot->part)
+        PPE_ELL_WIDTH(L.W, PPE_CHEB_DOT);
+#undef PPE_CHEB_DOT
+        PPE_LAUNCH_CHECK();
+        dotted = true;
+        cur = dst;
+        continue;
+      }
+    }
+    apply_op<E_CHEB, T>(s, L, cur, b, d, c1, c2, dst, nullptr);
     cur = dst;
   }
+  return dotted;
 }
 
 // One V-cycle with zero initial guess, x = M b on level l, in value type T.
+// dot: see smooth (consumed by the last level-0 smoothing step, if any).
 template <class T>
-void vcycle_t(ppe_solver* s, int l, const T* b, T* x) {
+bool vcycle_t(ppe_solver* s, int l, const T* b, T* x, const PcgDot* dot = nullptr) {
   Level& L = s->levels[l];
   const int n = L.n;
-  if (n == 0) return;
+  if (n == 0) return false;
   T* xa = L.x2.as<T>();
   T* xb = L.d2.as<T>();
   if (l == s->nlev - 1) {
@@ -566,12 +715,11 @@ void vcycle_t(ppe_solver* s, int l, const T* b, T* x) {
       hipLaunchKernelGGL(k_dense_gemv<T>, dim3(grid_for((int64_t)n * kWave)), dim3(kBlock), 0,
                          s->stream, n, LevelData<T>::ainv(L), b, x);
       PPE_LAUNCH_CHECK();
-    } else {
-      T* t = L.r.as<T>();
-      smooth<T>(s, L, b, nullptr, t, xa, xb);
-      smooth<T>(s, L, b, t, x, xa, xb);
+      return false;
     }
-    return;
+    T* t = L.r.as<T>();
+    smooth<T>(s, L, b, nullptr, t, xa, xb);
+    return smooth<T>(s, L, b, t, x, xa, xb, dot);
   }
   Level& C = s->levels[l + 1];
   T* x1 = L.t.as<T>();  // pre-smoothed iterate, corrected in place
@@ -581,7 +729,7 @@ void vcycle_t(ppe_solver* s, int l, const T* b, T* x) {
   apply_rect<false, T>(s, L.R, r, C.b.as<T>());
   vcycle_t<T>(s, l + 1, C.b.as<T>(), C.x.as<T>());
   apply_rect<true, T>(s, L.P, C.x.as<T>(), x1);
-  smooth<T>(s, L, b, x1, x, xa, xb);
+  return smooth<T>(s, L, b, x1, x, xa, xb, dot);
 }
 
 template <class S, class D>
@@ -694,6 +842,29 @@ void vcycle(ppe_solver* s, int l, const double* b, double* x) {
   cast<float, double>(s, L.x.as<float>(), x, L.n);
 }
 
+// z = M r for PCG, with the dots r.z and (flexible) r.z_old left as tile
+// partials: fused into the last level-0 smoothing step (FP64) or into the
+// cast back to FP64 (mixed), else a separate pass.
+static void vcycle_pcg(ppe_solver* s, const double* r, double* z, const PcgDot& dot) {
+  bool dotted;
+  if (s->opt.precision != PPE_MIXED) {
+    dotted = vcycle_t<double>(s, 0, r, z, &dot);
+  } else {
+    Level& L = s->levels[0];
+    cast<double, float>(s, r, L.b.as<float>(), L.n);
+    vcycle_t<float>(s, 0, L.b.as<float>(), L.x.as<float>());
+    hipLaunchKernelGGL(k_cast_dot_t, dim3(dot.nt), dim3(kBlock), 0, s->stream, dot.T,
+                       L.x.as<float>(), r, dot.zold, z, dot.part);
+    PPE_LAUNCH_CHECK();
+    dotted = true;
+  }
+  if (!dotted) {
+    hipLaunchKernelGGL(k_dot2_t, dim3(dot.nt), dim3(kBlock), 0, s->stream, dot.T, r, z, dot.zold,
+                       dot.part);
+    PPE_LAUNCH_CHECK();
+  }
+}
+
 // FP32 copies of the hierarchy for the mixed-precision V-cycle.
 void make_fp32_hierarchy(ppe_solver* s) {
   for (int l = 0; l < s->nlev; ++l) {
@@ -757,12 +928,13 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
   Level& L0 = s->levels[0];
   double* x = s->vx.get<double>(na);
   double* r = s->vr.get<double>(na);
-  double* z = s->vz.get<double>(na);
+  // z alternates between two buffers, so the previous z (flexible beta) is
+  // the other one
+  double* zb[2] = {s->vz.get<double>(na), s->vzold.get<double>(na)};
   double* p = s->vp.get<double>(na);
   double* q = s->vq.get<double>(na);
   double* b = s->vb.get<double>(na);
   const bool flexible = s->opt.precision == PPE_MIXED;
-  double* zold = flexible ? s->vzold.get<double>(na) : nullptr;
   double* tp = s->tpart.get<double>((size_t)T_N * nt);
   double* sc = s->seg_sc.get<double>((size_t)SS_N * ns);
   int* done = s->seg_done.get<int>(3 * (size_t)ns);
@@ -846,36 +1018,32 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
   read_counts();
   if (h[0] == 0 && check_true() == 0) return finish(PPE_OK);
 
-  vcycle(s, 0, r, z);
-  hipLaunchKernelGGL(k_dot2_t, dim3(nt), dim3(kBlock), 0, s->stream, T, r, z, nullptr, tpart(T_RZ));
-  PPE_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_init_p_t, dim3(nt), dim3(kBlock), 0, s->stream, T, ns, done, tpart(T_RZ), z,
-                     p, rz[0]);
+  auto precondition = [&](int sl, bool with_old) {
+    vcycle_pcg(s, r, zb[sl],
+               PcgDot{T, nt, flexible && with_old ? zb[1 - sl] : nullptr, tpart(T_RZ)});
+  };
+  precondition(1, false);  // the first iteration (slot 0) takes this z as z_old
+  hipLaunchKernelGGL(k_init_p_t, dim3(nt), dim3(kBlock), 0, s->stream, T, ns, done, tpart(T_RZ),
+                     zb[1], p, rz[0]);
   PPE_LAUNCH_CHECK();
   // One PCG iteration of every sample still running: q = A p; x, r update;
   // the convergence test; z = M r; beta; p.  Samples already converged are
   // left untouched by every kernel, so extra iterations change nothing.
   auto body = [&](int sl) {
-    hipLaunchKernelGGL(k_ell_dot_t, dim3(nt), dim3(kBlock), 0, s->stream, T, na, L0.W,
-                       L0.ell_col.as<int>(), L0.ell_val.as<double>(), L0.diag.as<double>(), done,
-                       p, q, tpart(T_PQ));
+#define PPE_ELL_DOT(WM_)                                                                      \
+  hipLaunchKernelGGL(k_ell_dot_t<WM_>, dim3(nt), dim3(kBlock), 0, s->stream, T, na, L0.W,         \
+                     L0.ell_col.as<int>(), L0.ell_val.as<double>(), L0.diag.as<double>(), done,  \
+                     p, q, tpart(T_PQ))
+    PPE_ELL_WIDTH(L0.W, PPE_ELL_DOT);
+#undef PPE_ELL_DOT
     PPE_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_update_xr_t, dim3(nt), dim3(kBlock), 0, s->stream, T, done, rz[sl],
-                       tpart(T_PQ), p, q, x, r, tpart(T_RR), cnt + 1);
+                       tpart(T_PQ), p, q, x, r, tpart(T_RR), cnt, cnt + 1);
     PPE_LAUNCH_CHECK();
-    fill_int(s, cnt, 0, 1);
-    hipLaunchKernelGGL(k_seg_step, dim3(ns), dim3(kBlock), 0, s->stream, ns, T, tpart(T_RR), sc, done,
-                       iters, restart, cnt, cnt + 1);
-    PPE_LAUNCH_CHECK();
-    if (flexible) {
-      hipLaunchKernelGGL(k_copy, dim3(ge), dim3(kBlock), 0, s->stream, na, z, zold);
-      PPE_LAUNCH_CHECK();
-    }
-    vcycle(s, 0, r, z);
-    hipLaunchKernelGGL(k_dot2_t, dim3(nt), dim3(kBlock), 0, s->stream, T, r, z, zold, tpart(T_RZ));
-    PPE_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_update_p_t, dim3(nt), dim3(kBlock), 0, s->stream, T, nt, done, restart,
-                       tpart(T_RZ), flexible ? 1 : 0, rz[sl], rz[1 - sl], z, p, cnt + 1);
+    precondition(sl, true);
+    hipLaunchKernelGGL(k_update_p_t, dim3(nt), dim3(kBlock), 0, s->stream, T, nt, ns, 1, done,
+                       restart, tpart(T_RR), sc, iters, cnt, tpart(T_RZ), flexible ? 1 : 0, rz[sl],
+                       rz[1 - sl], zb[sl], p, cnt + 1);
     PPE_LAUNCH_CHECK();
   };
   // Two iterations (both rz slots) captured into a HIP graph on the second
@@ -906,16 +1074,10 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
     if (h[0] == 0) {
       if (check_true() == 0) return finish(PPE_OK);
       // restarted samples: z = M r_true, p = z (beta is 0 after a restart)
-      if (flexible) {
-        hipLaunchKernelGGL(k_copy, dim3(ge), dim3(kBlock), 0, s->stream, na, z, zold);
-        PPE_LAUNCH_CHECK();
-      }
-      vcycle(s, 0, r, z);
-      hipLaunchKernelGGL(k_dot2_t, dim3(nt), dim3(kBlock), 0, s->stream, T, r, z, zold,
-                         tpart(T_RZ));
-      PPE_LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_update_p_t, dim3(nt), dim3(kBlock), 0, s->stream, T, nt, done, restart,
-                         tpart(T_RZ), flexible ? 1 : 0, rz[slot], rz[1 - slot], z, p, cnt + 1);
+      precondition(slot, false);  // beta is 0: z_old is not needed
+      hipLaunchKernelGGL(k_update_p_t, dim3(nt), dim3(kBlock), 0, s->stream, T, nt, ns, 0, done,
+                         restart, tpart(T_RR), sc, iters, cnt, tpart(T_RZ), flexible ? 1 : 0,
+                         rz[slot], rz[1 - slot], zb[slot], p, cnt + 1);
       PPE_LAUNCH_CHECK();
       slot = 1 - slot;
     }

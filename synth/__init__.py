@@ -14,6 +14,7 @@ from .fields import (
     batch_samples,
     uq_front_fl,
     rhs_smooth_series,
+    mlp_initial_weights,
 )
 
 __all__ = [
@@ -29,4 +30,5 @@ __all__ = [
     "batch_samples",
     "uq_front_fl",
     "rhs_smooth_series",
+    "mlp_initial_weights",
 ]

@@ -92,3 +92,19 @@ def rhs_smooth_series(centres, t, seed=5, n_modes=6, noise=0.05, center_mask=Non
         if m.any():
             b[m] -= b[m].mean()
     return b
+
+
+def mlp_initial_weights(n_in=10, width=128, n_hidden=3, seed=0):
+    """Initial weights of the warm-start network, drawn outside the method:
+    for each layer (fan_out x fan_in), a row-major weight matrix followed by
+    its bias, all U(-1/sqrt(fan_in), 1/sqrt(fan_in)) from PCG64 stream seed,
+    concatenated in layer order (the library's parameter layout)."""
+    rng = np.random.default_rng(seed)
+    dims = [n_in] + [width] * n_hidden + [1]
+    parts = []
+    for k in range(len(dims) - 1):
+        fan_in, fan_out = dims[k], dims[k + 1]
+        lim = 1.0 / np.sqrt(fan_in)
+        parts.append(rng.uniform(-lim, lim, size=fan_out * fan_in))
+        parts.append(rng.uniform(-lim, lim, size=fan_out))
+    return np.concatenate(parts)

@@ -53,9 +53,17 @@ def csr(rp, ci, v, shape):
     return sp.csr_matrix((v.cpu().numpy(), ci.cpu().numpy(), rp.cpu().numpy()), shape=shape)
 
 
+def _absmax(M):
+    """max |entry| without densifying a sparse operand (0 for an empty one)."""
+    if sp.issparse(M):
+        M = sp.csr_matrix(M)
+        return float(np.abs(M.data).max()) if M.nnz else 0.0
+    M = np.asarray(M)
+    return float(np.abs(M).max()) if M.size else 0.0
+
+
 def rel_max(A, B):
     """max |A - B| / max |B| for sparse or dense operands."""
-    D = A - B
-    D = np.abs(D.toarray() if sp.issparse(D) else D).max() if D.shape[0] else 0.0
-    s = np.abs(B.toarray() if sp.issparse(B) else B).max() if B.shape[0] else 1.0
+    D = _absmax(A - B)
+    s = _absmax(B)
     return D / s if s else D

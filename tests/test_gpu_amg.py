@@ -65,3 +65,61 @@ def test_setup_is_deterministic():
     for lvl in range(s1.n_levels()):
         for a, b in zip(s1.level_matrix(lvl), s2.level_matrix(lvl)):
             assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+def _vcycle_case(name):
+    if name.startswith("c1"):
+        return case()
+    if name == "ragged_front":
+        m = box_mesh((23, 19, 17), jitter=0.1, seed=4)
+        return m, fl_planar_front(m.cell_centre, seed=7), face_coeff(m, 2400.0), None
+    raise ValueError(name)
+
+
+# The coarsest operator is inverted by register-resident Gauss-Jordan for
+# n <= 256 (one template per rows-per-thread bound) and by the global-memory
+# variant above; coarse_max picks which one a hierarchy ends in.
+@pytest.mark.parametrize("name,coarse_max,n_coarsest", [
+    ("c1", 16, 2), ("c1", 128, 45), ("c1", 400, 279), ("ragged_front", 128, None)])
+def test_coarsest_inverse_variants(name, coarse_max, n_coarsest):
+    import torch
+
+    m, f, c, _ = _vcycle_case(name)
+    sy = assembly.masked_system(m.n_cells, m.owner, m.neigh, c, f)
+    H = amg.build_hierarchy(sy.A, coarse_max=coarse_max)
+    if n_coarsest is not None:
+        assert H.levels[-1].A.shape[0] == n_coarsest
+    s = gpu_solver(m, f, c, coarse_max=coarse_max)
+    assert s.n_levels() == len(H.levels)
+    r = np.random.default_rng(5).normal(size=sy.n_active)
+    z = s.apply_vcycle(to_dev(r, torch.float64)).cpu().numpy()
+    zr = amg.vcycle(H, r)
+    assert np.linalg.norm(z - zr) <= 1e-12 * np.linalg.norm(zr)
+
+
+def test_full_size_64cube_hierarchy():
+    """The 64^3 timestep the benchmark times first: every level's aggregates
+    exactly, operators and prolongators to rounding, and one V-cycle."""
+    import torch
+
+    from synth import fl_growing_front
+
+    m = box_mesh((64, 64, 64), lengths=(0.01,) * 3, jitter=0.1, seed=0)
+    c = face_coeff(m, 2400.0)
+    f = fl_growing_front(m.cell_centre, t=0.101, t_end=0.2, s_max=0.6, delta=0.1, axis=0,
+                         length=0.01)
+    sy = assembly.masked_system(m.n_cells, m.owner, m.neigh, c, f)
+    H = amg.build_hierarchy(sy.A)
+    s = gpu_solver(m, f, c)
+    assert s.n_levels() == len(H.levels)
+    for lvl, lev in enumerate(H.levels):
+        n = lev.A.shape[0]
+        A = csr(*s.level_matrix(lvl), (n, n))
+        assert rel_max(A, lev.A) <= 1e-13, lvl
+        if lvl < len(H.levels) - 1:
+            assert np.array_equal(s.aggregates(lvl).cpu().numpy(), lev.agg), lvl
+            P = csr(*s.prolongator(lvl), lev.P.shape)
+            assert rel_max(P, lev.P) <= 1e-13, lvl
+    r = np.random.default_rng(6).normal(size=sy.n_active)
+    z = s.apply_vcycle(to_dev(r, torch.float64)).cpu().numpy()
+    assert np.linalg.norm(z - amg.vcycle(H, r)) <= 1e-12 * np.linalg.norm(z)
