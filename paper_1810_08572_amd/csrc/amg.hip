@@ -21,7 +21,9 @@
 // is bitwise reproducible from run to run.
 #include "common.h"
 
+#include <algorithm>
 #include <cmath>
+#include <cstring>
 
 namespace ppe {
 namespace {
@@ -29,7 +31,12 @@ namespace {
 constexpr int kPowerIters = 15;
 constexpr double kPowerSafety = 1.1;
 constexpr int kDenseMax = 1024;
-constexpr int kCountHash = 1024;  // hash slots per row in the symbolic product
+
+// Deferred setup checks: bits of an error word read back with the spectral
+// bounds once the hierarchy is built.  Kernels between a failed check and the
+// read stay in bounds (an unassigned node only leaves its prolongator row
+// empty; a lost diagonal or a non-positive pivot only spoils values).
+enum SetupErr : int { SE_DIAG = 1, SE_DENSE = 2, SE_AGG = 4 };
 
 enum : int { S_OUT = 0, S_UND = 1, S_IN = 2 };
 
@@ -216,7 +223,7 @@ __global__ void __launch_bounds__(kBlock) k_agg_second(int n, const int* __restr
     int a = a1;
     if (a < 0) {
       if (best >= 0.0) a = agg1[bestj];
-      else if (any) atomicOr(flag, 1);
+      else if (any) atomicOr(flag, SE_AGG);
     }
     agg[i] = a;
   }
@@ -233,12 +240,36 @@ __global__ void k_agg_fill(int n, const int* __restrict__ agg, int* __restrict__
   if (i < n && agg[i] >= 0) mem[atomicAdd(&cursor[agg[i]], 1)] = i;
 }
 
-// Sort each aggregate's members, then norm_J = sqrt(sum B_i^2) in ascending i.
-__global__ void k_agg_norm(int na, const int* __restrict__ ptr, int* __restrict__ mem,
-                           const double* __restrict__ B, double* __restrict__ Bc) {
-  int J = blockIdx.x * kBlock + threadIdx.x;
-  if (J >= na) return;
-  int b = ptr[J], e = ptr[J + 1];
+// Sort each aggregate's members, then norm_J = sqrt(sum B_i^2) in ascending
+// i.  One wavefront per aggregate: up to 64 members are ranked in registers
+// and their squares summed in rank order by one lane; a larger aggregate is
+// sorted and summed by one lane.
+__global__ void __launch_bounds__(kBlock) k_agg_norm(int na, const int* __restrict__ ptr,
+                                                     int* __restrict__ mem,
+                                                     const double* __restrict__ B,
+                                                     double* __restrict__ Bc) {
+  __shared__ double sq[kBlock];
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int J = blockIdx.x * (kBlock / kWave) + w;
+  const int b = J < na ? ptr[J] : 0, e = J < na ? ptr[J + 1] : 0, m = e - b;
+  double* wsq = sq + w * kWave;
+  if (J < na && m <= kWave) {
+    const int key = lane < m ? mem[b + lane] : INT32_MAX;
+    int rank = 0;
+    for (int q = 0; q < m; ++q) rank += __shfl(key, q, kWave) < key ? 1 : 0;
+    if (lane < m) {
+      mem[b + rank] = key;
+      wsq[rank] = B[key] * B[key];
+    }
+  }
+  __syncthreads();
+  if (J >= na || lane != 0) return;
+  if (m <= kWave) {
+    double s = 0.0;
+    for (int q = 0; q < m; ++q) s = s + wsq[q];
+    Bc[J] = sqrt(s);
+    return;
+  }
   for (int i = b + 1; i < e; ++i) {
     int key = mem[i], j = i - 1;
     while (j >= b && mem[j] > key) { mem[j + 1] = mem[j]; --j; }
@@ -271,12 +302,14 @@ __global__ void k_tent_csr(int n, const int* __restrict__ rp, const int* __restr
 }
 
 // P = P_tent - omega D^-1 (A P_tent); the pattern of A P_tent contains P_tent's.
+// omega = 4 / (3 rho) with rho the level's spectral bound (device value).
 __global__ void k_smooth_p(int n, const int* __restrict__ qrp, const int* __restrict__ qci,
                            const double* __restrict__ qv, const double* __restrict__ diag,
                            const int* __restrict__ agg, const double* __restrict__ pt,
-                           double omega, double* __restrict__ pv) {
+                           const double* __restrict__ rho, double* __restrict__ pv) {
   int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
+  const double omega = 4.0 / (3.0 * *rho);
   const double dinv = 1.0 / diag[i];
   const int ai = agg[i];
   for (int k = qrp[i]; k < qrp[i + 1]; ++k) {
@@ -286,8 +319,9 @@ __global__ void k_smooth_p(int n, const int* __restrict__ qrp, const int* __rest
 }
 
 // ------------------------------------------------------------------ spectral bounds
+// Gershgorin bound of D^-1 A: block maxima of sum_j |a_ij| / a_ii
 __global__ void k_gershgorin(int n, const int* __restrict__ rp, const double* __restrict__ v,
-                             const double* __restrict__ diag, unsigned long long* __restrict__ out) {
+                             const double* __restrict__ diag, double* __restrict__ part) {
   int i = blockIdx.x * kBlock + threadIdx.x;
   double r = 0.0;
   if (i < n) {
@@ -295,7 +329,15 @@ __global__ void k_gershgorin(int n, const int* __restrict__ rp, const double* __
     r = r / diag[i];
   }
   r = block_max<kBlock>(r);
-  if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(r));
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+__global__ void __launch_bounds__(kBlock) k_max_partials(const double* __restrict__ part, int g,
+                                                         double* __restrict__ out) {
+  double m = 0.0;
+  for (int b = threadIdx.x; b < g; b += kBlock) m = fmax(m, part[b]);
+  m = block_max<kBlock>(m);
+  if (threadIdx.x == 0) *out = m;
 }
 
 template <int LPR>
@@ -311,7 +353,7 @@ __global__ void __launch_bounds__(kBlock) k_diag(int n, const int* __restrict__ 
   d = group_sum<LPR>(d);
   if (i < n && lane == 0) {
     diag[i] = d;
-    if (!(d > 0.0)) atomicOr(flag, 1);
+    if (!(d > 0.0)) atomicOr(flag, SE_DIAG);
   }
 }
 
@@ -592,7 +634,7 @@ __global__ void __launch_bounds__(1024) k_dense_inverse(int n, double* __restric
   for (int k = 0; k < n; ++k) {
     if (t == 0) {
       double d = G[(size_t)k * w + k];
-      if (!(d > 0.0)) { atomicOr(flag, 2); d = 1.0; }
+      if (!(d > 0.0)) { atomicOr(flag, SE_DENSE); d = 1.0; }
       piv = d;
     }
     for (int i = t; i < n; i += nt) f[i] = G[(size_t)i * w + k];
@@ -616,59 +658,71 @@ __global__ void __launch_bounds__(1024) k_dense_inverse(int n, double* __restric
 // The same elimination done in place with the matrix held in registers (the
 // identity half implicit): at step k the pivot row is divided by the pivot
 // with a_kk replaced by 1, and every other row i gets a_ij -= f_i a_kj with
-// a_ik replaced by 0.  With G = 1024 / n row groups, thread t < G n owns column j = t mod n and rows
-// i = g, g + G, g + 2G, ... (g = t / n), at most E of them; the pivot column
-// and the scaled pivot row are exchanged through LDS.
+// a_ik replaced by 0.  With G = ceil(n / E) row groups, thread t < G n owns
+// column j = t mod n and the E consecutive rows g E .. g E + E - 1 (g = t / n)
+// (rows past n are carried as throw-away values).  The pivot column and the (unscaled) pivot row of step k are
+// published in LDS by their owners at the end of step k - 1, into the buffer
+// step k - 1 did not read, so one barrier per step suffices; every thread
+// scales its own entry of the pivot row.  The update of an owned entry is a
+// load from LDS at a fixed offset, a multiply and a subtract; column k and
+// row k are fixed up by their owners only.
+constexpr int kDenseReg = 256;
 template <int E>
 __global__ void __launch_bounds__(1024) k_dense_inverse_reg(int n, const double* __restrict__ Gm,
                                                             double* __restrict__ Ainv,
                                                             int* __restrict__ flag) {
-  __shared__ double colk[kDenseMax];
-  __shared__ double rowk[kDenseMax];
-  __shared__ double piv;
+  __shared__ double colk[2][kDenseReg + E];  // + E: the last group's rows past n
+  __shared__ double rowk[2][kDenseReg];
   const int t = threadIdx.x;
-  const int G = 1024 / n;
+  const int G = (n + E - 1) / E;  // groups needed (G n <= 1024: the host picks E >= n / (1024 / n))
   const bool owner = t < G * n;
   const int j = owner ? t % n : 0, g = owner ? t / n : 0;
+  const int r0 = g * E;  // first owned row; r0 + E <= n - 1 + E
   double a[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
-    const int i = g + G * m;
+    const int i = r0 + m;
     a[m] = (owner && i < n) ? Gm[(size_t)i * 2 * n + j] : 0.0;
   }
+  // publish column 0 and row 0 (group 0, slot 0)
+  if (owner && j == 0) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) colk[0][r0 + m] = a[m];
+  }
+  if (owner && g == 0) rowk[0][j] = a[0];
+  __syncthreads();
   for (int k = 0; k < n; ++k) {
-    if (owner && j == k) {
-#pragma unroll
-      for (int m = 0; m < E; ++m) {
-        const int i = g + G * m;
-        if (i < n) colk[i] = a[m];
-      }
+    const int cb = k & 1, nb = cb ^ 1;
+    double piv = colk[cb][k];
+    if (!(piv > 0.0)) {
+      if (t == 0) atomicOr(flag, SE_DENSE);
+      piv = 1.0;
     }
-    __syncthreads();
-    if (t == 0) {
-      double d = colk[k];
-      if (!(d > 0.0)) { atomicOr(flag, 2); d = 1.0; }
-      piv = d;
-    }
-    __syncthreads();
     const double inv = 1.0 / piv;
-    const int mk = k / G;  // slot of row k in the owning row group k % G
-    if (owner && g == k % G) {
+    const double rk = (j == k ? 1.0 : rowk[cb][j]) * inv;  // scaled pivot row, column j
+    if (j == k) {  // a_ik is replaced by 0 before the update
 #pragma unroll
-      for (int m = 0; m < E; ++m) {
-        if (m == mk) {
-          a[m] = (j == k ? 1.0 : a[m]) * inv;
-          rowk[j] = a[m];
-        }
-      }
+      for (int m = 0; m < E; ++m) a[m] = 0.0;
     }
-    __syncthreads();
-    if (owner) {
-      const double rj = rowk[j];
+    const double* f = &colk[cb][r0];
 #pragma unroll
-      for (int m = 0; m < E; ++m) {
-        const int i = g + G * m;
-        if (i < n && i != k) a[m] = (j == k ? 0.0 : a[m]) - colk[i] * rj;
+    for (int m = 0; m < E; ++m) a[m] = a[m] - f[m] * rk;
+    if (g == k / E) {  // the pivot row becomes the scaled row
+      const int mk = k - r0;
+#pragma unroll
+      for (int m = 0; m < E; ++m) a[m] = m == mk ? rk : a[m];
+    }
+    if (owner && k + 1 < n) {
+      if (j == k + 1) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) colk[nb][r0 + m] = a[m];
+      }
+      if (g == (k + 1) / E) {
+        const int mk = k + 1 - r0;
+        double v = a[0];
+#pragma unroll
+        for (int m = 1; m < E; ++m) v = m == mk ? a[m] : v;
+        rowk[nb][j] = v;
       }
     }
     __syncthreads();
@@ -676,7 +730,7 @@ __global__ void __launch_bounds__(1024) k_dense_inverse_reg(int n, const double*
   if (owner) {
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const int i = g + G * m;
+      const int i = r0 + m;
       if (i < n) Ainv[(size_t)i * n + j] = a[m];
     }
   }
@@ -863,39 +917,46 @@ void transpose(ppe_solver* s, const Csr& A, Csr& T) {
   }
 }
 
-double spectral_bound(ppe_solver* s, Level& L, int lvl) {
+// The level's spectral bound of D^-1 A into *rho_dev (read back with the
+// rest of the setup results): Gershgorin on the finest level, the safety
+// factor times a power estimate on coarse ones.
+void spectral_bound(ppe_solver* s, Level& L, int lvl, double* rho_dev) {
   const int n = L.n;
-  if (n == 0) return 1.0;
+  if (n == 0) {
+    fill_double(s, rho_dev, 1.0, 1);
+    return;
+  }
   if (lvl == 0) {
-    unsigned long long* out = reinterpret_cast<unsigned long long*>(s->tmp_d[0].get<double>(1));
-    PPE_HIP(hipMemsetAsync(out, 0, sizeof(double), s->stream));
-    hipLaunchKernelGGL(k_gershgorin, dim3(grid_for(n)), dim3(kBlock), 0, s->stream, n, L.A.rp(),
-                       L.A.v(), L.diag.as<double>(), out);
+    const int g = grid_for(n);
+    double* part = s->tmp_d[0].get<double>(g);
+    hipLaunchKernelGGL(k_gershgorin, dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(), L.A.v(),
+                       L.diag.as<double>(), part);
     PPE_LAUNCH_CHECK();
-    double r = read_scalar(s, reinterpret_cast<double*>(out));
-    return r;
+    hipLaunchKernelGGL(k_max_partials, dim3(1), dim3(kBlock), 0, s->stream, part, g, rho_dev);
+    PPE_LAUNCH_CHECK();
+    return;
   }
   L.x.get<double>(n);
   L.r.get<double>(n);
-  const double lam = power_estimate(s, L, level_salt(lvl), kPowerIters);
-  return kPowerSafety * lam;
+  power_estimate(s, L, level_salt(lvl), kPowerIters, kPowerSafety, rho_dev);
 }
 
 }  // namespace
 
 void build_hierarchy(ppe_solver* s) {
   const double theta2 = s->opt.theta * s->opt.theta;
+  const int maxlev = std::max(1, s->opt.max_levels);
+  double* rho_dev = s->setup_out.get<double>((size_t)maxlev + 1);
+  int* err = reinterpret_cast<int*>(rho_dev + maxlev);
+  fill_int(s, err, 0, 1);
   for (int lvl = 0;; ++lvl) {
     Level& L = s->levels[lvl];
     const int n = L.n;
-    int* flag = s->flag.get<int>(1);
     if (lvl > 0 && n > 0) {
-      fill_int(s, flag, 0, 1);
       PPE_ROWS(lanes_for(L.A), k_diag, n, n, L.A.rp(), L.A.ci(), L.A.v(), L.diag.get<double>(n),
-               flag);
-      require(read_scalar(s, flag) == 0, PPE_ERR_INTERNAL, "coarse operator lost its diagonal");
+               err);  // sets SE_DIAG
     }
-    L.rho = spectral_bound(s, L, lvl);
+    spectral_bound(s, L, lvl, rho_dev + lvl);
     L.n_agg = 0;
     L.dense = false;
     L.mis_rounds = 0;
@@ -912,16 +973,16 @@ void build_hierarchy(ppe_solver* s) {
       const uint32_t salt = level_salt(lvl);
       // rounds run in triples between host checks; a round after the set is
       // complete changes nothing, so only the last count is read
-      int* und = s->tmp_i[3].get<int>(3);
-      while (true) {
-        fill_int(s, und, 0, 3);
-        for (int k = 0; k < 3; ++k) {
+      int* und = s->tmp_i[3].get<int>(1);
+      for (int batch = 6;; batch = 3) {  // six rounds before the first check
+        for (int k = 0; k < batch; ++k) {
+          if (k == batch - 1) fill_int(s, und, 0, 1);
           PPE_ROWS(lpr, k_mis_max1, n, n, L.A.rp(), L.A.ci(), strong, st, salt, m1);
-          PPE_ROWS(lpr, k_mis_max2, n, n, L.A.rp(), L.A.ci(), strong, st, salt, m1, st2, und + k);
+          PPE_ROWS(lpr, k_mis_max2, n, n, L.A.rp(), L.A.ci(), strong, st, salt, m1, st2, und);
           std::swap(st, st2);
           ++L.mis_rounds;
         }
-        if (read_scalar(s, und + 2) == 0) break;
+        if (read_scalar(s, und) == 0) break;
         require(L.mis_rounds < 10000, PPE_ERR_INTERNAL, "MIS-2 did not terminate");
       }
       int* root = s->tmp_i[2].get<int>(n + 1);
@@ -933,29 +994,31 @@ void build_hierarchy(ppe_solver* s) {
         int* agg1 = L.agg1.get<int>(n);
         int* agg = L.agg.get<int>(n);
         PPE_ROWS(lpr, k_agg_first, n, n, L.A.rp(), L.A.ci(), strong, st, root_id, agg1);
-        fill_int(s, flag, 0, 1);
-        PPE_ROWS(lpr, k_agg_second, n, n, L.A.rp(), L.A.ci(), L.A.v(), strong, agg1, agg, flag);
-        require(read_scalar(s, flag) == 0, PPE_ERR_INTERNAL, "aggregation left a node unassigned");
+        PPE_ROWS(lpr, k_agg_second, n, n, L.A.rp(), L.A.ci(), L.A.v(), strong, agg1, agg,
+                 err);  // sets SE_AGG
         L.n_agg = na;
         // aggregate members, coarse near-null vector, tentative prolongator
+        // (nodes with no strong connection stay outside every aggregate, so
+        // members and prolongator entries number at most n; only the device
+        // row pointers are exact)
         int* cnt = s->tmp_i[0].get<int>(na + 1);
         fill_int(s, cnt, 0, na + 1);
         hipLaunchKernelGGL(k_agg_count, dim3(g), dim3(kBlock), 0, s->stream, n, agg, cnt);
         PPE_LAUNCH_CHECK();
         int* aptr = L.agg_ptr.get<int>(na + 1);
-        int64_t nm = exclusive_scan(s, cnt, aptr, na);
+        exclusive_scan_async(s, cnt, aptr, na);
         int* cursor = s->tmp_i[1].get<int>(na + 1);
         PPE_HIP(hipMemcpyAsync(cursor, aptr, sizeof(int) * (na + 1), hipMemcpyDeviceToDevice,
                                s->stream));
-        int* mem = L.agg_mem.get<int>(nm);
+        int* mem = L.agg_mem.get<int>(n);
         hipLaunchKernelGGL(k_agg_fill, dim3(g), dim3(kBlock), 0, s->stream, n, agg, cursor, mem);
         PPE_LAUNCH_CHECK();
         if ((int)s->levels.size() < lvl + 2) s->levels.resize(lvl + 2);
         Level& L0 = s->levels[lvl];  // re-fetch: resize may move levels
         Level& C = s->levels[lvl + 1];
         double* Bc = C.B.get<double>(na);
-        hipLaunchKernelGGL(k_agg_norm, dim3(grid_for(na)), dim3(kBlock), 0, s->stream, na, aptr, mem,
-                           L0.B.as<double>(), Bc);
+        hipLaunchKernelGGL(k_agg_norm, dim3(grid_for((int64_t)na * kWave)), dim3(kBlock), 0,
+                           s->stream, na, aptr, mem, L0.B.as<double>(), Bc);
         PPE_LAUNCH_CHECK();
         double* pt = L0.pt.get<double>(n);
         int* pcnt = s->tmp_i[0].get<int>(n + 1);
@@ -966,7 +1029,8 @@ void build_hierarchy(ppe_solver* s) {
         Pt.n = n;
         Pt.m = na;
         int* ptrp = Pt.rowptr.get<int>(n + 1);
-        Pt.nnz = exclusive_scan(s, pcnt, ptrp, n);
+        exclusive_scan_async(s, pcnt, ptrp, n);
+        Pt.nnz = n;  // capacity (an upper bound): only the row pointers are read
         hipLaunchKernelGGL(k_tent_csr, dim3(g), dim3(kBlock), 0, s->stream, n, ptrp, agg, pt,
                            Pt.col.get<int>(Pt.nnz), Pt.val.get<double>(Pt.nnz));
         PPE_LAUNCH_CHECK();
@@ -976,17 +1040,13 @@ void build_hierarchy(ppe_solver* s) {
         P.n = n;
         P.m = na;
         P.nnz = L0.Q.nnz;
-        int* prp = P.rowptr.get<int>(n + 1);
-        PPE_HIP(hipMemcpyAsync(prp, L0.Q.rp(), sizeof(int) * (n + 1), hipMemcpyDeviceToDevice,
-                               s->stream));
-        int* pci = P.col.get<int>(P.nnz);
-        PPE_HIP(hipMemcpyAsync(pci, L0.Q.ci(), sizeof(int) * P.nnz, hipMemcpyDeviceToDevice,
-                               s->stream));
-        const double omega = 4.0 / (3.0 * L0.rho);
         hipLaunchKernelGGL(k_smooth_p, dim3(g), dim3(kBlock), 0, s->stream, n, L0.Q.rp(), L0.Q.ci(),
-                           L0.Q.v(), L0.diag.as<double>(), agg, pt, omega,
+                           L0.Q.v(), L0.diag.as<double>(), agg, pt, rho_dev + lvl,
                            P.val.get<double>(P.nnz));
         PPE_LAUNCH_CHECK();
+        // P has the pattern of A P_tent: take its arrays instead of copying
+        std::swap(P.rowptr, L0.Q.rowptr);
+        std::swap(P.col, L0.Q.col);
         transpose(s, P, L0.R);
         spgemm(s, L0.A, P, L0.AP);
         spgemm(s, L0.R, L0.AP, C.A);
@@ -1004,12 +1064,11 @@ void build_hierarchy(ppe_solver* s) {
       hipLaunchKernelGGL(k_densify, dim3(grid_for(n)), dim3(kBlock), 0, s->stream, n, L.A.rp(),
                          L.A.ci(), L.A.v(), G);
       PPE_LAUNCH_CHECK();
-      fill_int(s, flag, 0, 1);
       if (n <= 256) {
         // rows one thread owns; every FMA of the elimination stays in registers
         const int rows_per = (n + (1024 / n) - 1) / (1024 / n);
 #define PPE_DINV(E_)                                                                           \
-  hipLaunchKernelGGL(k_dense_inverse_reg<E_>, dim3(1), dim3(1024), 0, s->stream, n, G, Ainv, flag)
+  hipLaunchKernelGGL(k_dense_inverse_reg<E_>, dim3(1), dim3(1024), 0, s->stream, n, G, Ainv, err)
         if (rows_per <= 4) PPE_DINV(4);
         else if (rows_per <= 8) PPE_DINV(8);
         else if (rows_per <= 16) PPE_DINV(16);
@@ -1018,14 +1077,24 @@ void build_hierarchy(ppe_solver* s) {
         else PPE_DINV(64);
 #undef PPE_DINV
       } else {
-        hipLaunchKernelGGL(k_dense_inverse, dim3(1), dim3(1024), 0, s->stream, n, G, Ainv, flag);
+        hipLaunchKernelGGL(k_dense_inverse, dim3(1), dim3(1024), 0, s->stream, n, G, Ainv, err);
       }
       PPE_LAUNCH_CHECK();
-      require(read_scalar(s, flag) == 0, PPE_ERR_INTERNAL, "coarsest operator is not positive definite");
       L.dense = true;
     }
     break;
   }
+  // one read-back for the whole hierarchy: spectral bounds and error bits
+  std::vector<double> out((size_t)maxlev + 1);
+  PPE_HIP(hipMemcpyAsync(out.data(), rho_dev, sizeof(double) * (maxlev + 1), hipMemcpyDeviceToHost,
+                         s->stream));
+  PPE_HIP(hipStreamSynchronize(s->stream));
+  int bits = 0;
+  std::memcpy(&bits, &out[maxlev], sizeof(int));
+  require(!(bits & SE_DIAG), PPE_ERR_INTERNAL, "coarse operator lost its diagonal");
+  require(!(bits & SE_AGG), PPE_ERR_INTERNAL, "aggregation left a node unassigned");
+  require(!(bits & SE_DENSE), PPE_ERR_INTERNAL, "coarsest operator is not positive definite");
+  for (int l = 0; l < s->nlev; ++l) s->levels[l].rho = out[l];
 }
 
 }  // namespace ppe

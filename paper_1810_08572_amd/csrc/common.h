@@ -156,6 +156,9 @@ struct ppe_solver {
   ppe::DevBuf scal, partial, counter, flag;
   ppe::DevBuf tmp_i[4], tmp_d[2], tmp_l[2];
   ppe::DevBuf sp_prod, sp_off, sp_cnt, sp_ci, sp_v;  // sparse-product scratch
+  // setup results read back once per hierarchy: the spectral bound of every
+  // level (doubles [0, max_levels)), then the deferred setup error bits (int)
+  ppe::DevBuf setup_out;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
   // HIP graph of two PCG iterations, captured once per hierarchy
@@ -361,7 +364,9 @@ void build_hierarchy(ppe_solver* s);
 void spmv(ppe_solver* s, const Level& L, const double* x, double* y);
 // Power iteration for lambda_max(D^-1 A) on a CSR level from the hashed
 // start vector 1/2 + fmix32(i ^ salt) / 2^32; uses L.x and L.r as work.
-double power_estimate(ppe_solver* s, Level& L, uint32_t salt, int iters);
+// *out = scale x (power estimate of the largest eigenvalue of D^-1 A on level
+// L after iters steps from the seeded start vector); stays on the device.
+void power_estimate(ppe_solver* s, Level& L, uint32_t salt, int iters, double scale, double* out);
 void vcycle(ppe_solver* s, int level, const double* b, double* x);
 ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p, int use_x0);
 void prepare_solve_levels(ppe_solver* s);

@@ -507,12 +507,13 @@ __global__ void k_scatter(int nc, const int* __restrict__ cid, const int* __rest
   p[c] = (k < 0 || comp[c] == c) ? 0.0 : x[k];
 }
 
-// Host-facing scalar: *o0 = sum of p0[0..g).
-__global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ p0, int g,
-                                                     double* __restrict__ o0) {
+// *out = scale sqrt(sum of p0[0..g)).
+__global__ void __launch_bounds__(kBlock) k_finalize_norm(const double* __restrict__ p0, int g,
+                                                          double scale, double* __restrict__ out) {
   const double a = sum_partials<kBlock>(p0, g);
-  if (threadIdx.x == 0) *o0 = a;
+  if (threadIdx.x == 0) *out = scale * sqrt(a);
 }
+
 
 template <class S, class D>
 __global__ void k_cast(int64_t n, const S* __restrict__ a, D* __restrict__ b) {
@@ -781,10 +782,10 @@ void spmv(ppe_solver* s, const Level& L, const double* x, double* y) {
   apply_op<E_SPMV, double>(s, L, x, nullptr, nullptr, 0.0, 0.0, y, nullptr);
 }
 
-double power_estimate(ppe_solver* s, Level& L, uint32_t salt, int iters) {
+void power_estimate(ppe_solver* s, Level& L, uint32_t salt, int iters, double scale,
+                    double* out) {
   const int n = L.n;
   s->partial.get<double>((size_t)P_NSLOTS * kRedBlocks);
-  double* sc = s->scal.get<double>(S_N);
   double* x = L.x.as<double>();
   double* y = L.r.as<double>();
   double* pa = part(s, P_POW);
@@ -797,9 +798,8 @@ double power_estimate(ppe_solver* s, Level& L, uint32_t salt, int iters) {
     std::swap(x, y);
     std::swap(pa, pb);
   }
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s->stream, pa, g, sc + S_POW);
+  hipLaunchKernelGGL(k_finalize_norm, dim3(1), dim3(kBlock), 0, s->stream, pa, g, scale, out);
   PPE_LAUNCH_CHECK();
-  return std::sqrt(read_scalar(s, sc + S_POW));
 }
 
 void prepare_solve_levels(ppe_solver* s) {
@@ -946,7 +946,7 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
   auto tpart = [&](int k) { return tp + (size_t)k * nt; };
   const int* perm = s->perm.as<int>();
   const int* comp = s->comp_full.as<int>();
-  const int ge = grid_for(na), gs = grid_for(ns);
+  const int ge = grid_for(na);
   double* rz[2] = {sc + (size_t)SS_RZ0 * ns, sc + (size_t)SS_RZ1 * ns};
   int h[2];
   auto read_counts = [&]() {
