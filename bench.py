@@ -1,18 +1,17 @@
 """Benchmark: masked pressure-correction Poisson solves per second on one GPU.
 
-Workload: 64^3 = 262,144-cell jittered (+-10 %) hex cube stored as an
-unstructured face list, a 10 mm cavity, aluminium density rho = 2400.
+Headline workload: timesteps on a 64^3 cube.
+- Mesh: 64^3 = 262,144-cell jittered (+-10 %) hex cube stored as an
+  unstructured face list; 10 mm cavity; aluminium density rho = 2400.
 - Solid front: grows from the cold wall x = 0 as sqrt(t) over a 200-step
   schedule of 1e-3 s (mushy band 10 % of the cube).
-- RHS: varies smoothly from step to step, standing in for the velocity
-  divergence of a flow solve; it is centred over the liquid cells.
-- Each timestep does one masked SA-AMG-PCG solve to 1e-10 relative
-  residual.
+- Right-hand side: varies smoothly from step to step, standing in for the
+  velocity divergence of a flow solve; centred over the liquid cells.
+- Each timestep does one masked SA-AMG-PCG solve to 1e-10 relative residual.
 
-One bench step = one timestep's whole hot path: masked assembly, AMG setup,
+One bench step is one timestep's whole hot path: masked assembly, AMG setup,
 then PCG.  K consecutive timesteps are timed from the middle of the
-schedule, after W warmup steps, and all inputs are resident in device
-memory first.
+schedule, after W warmup steps, with all inputs already in device memory.
 
 Reported:
 - value: FP64 AMG-PCG from a zero guess (the plain method).
@@ -21,10 +20,19 @@ Reported:
   by the warm-start network from the previous step.  The network is trained
   beforehand, untimed, on snapshots the solver produced for earlier
   timesteps of the same run.
-- roofline: the dominant kernel's achieved HBM bandwidth.
+- variants.c3_128cube (unless --no-c3): repeated solves of one 128^3 system
+  (2.1 M cells, random planar front) in FP64 and mixed precision, each with
+  its finest-level roofline; at this size the hierarchy outgrows the
+  256 MB Infinity Cache.
+- variants.c5_plate_ribs (unless --no-c5): timesteps on the 1.5 M-cell plate
+  with four ribs, with the front rising from the bottom face.  Compares zero
+  and previous-solution guesses in FP64 and mixed precision with the guess
+  of the network trained on the cube (a geometry it never saw).
+- variants.uq_batched (--uq): 256 uneven uncertainty samples solved as one
+  batch.
+- roofline: the dominant kernel's achieved HBM bandwidth on the headline
+  workload.
 - cpu_baseline: the FP64 oracle on host cores.
-- variants.uq_batched: optional (--uq), 256 uneven uncertainty samples
-  solved as one batch.
 """
 from __future__ import annotations
 
@@ -41,7 +49,6 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 N_TIMESTEPS = 200
 DT = 1e-3
-SIDE = 64
 RHO = 2400.0
 CAVITY = 0.01  # m
 FIRST_TIMED = 100
@@ -53,28 +60,51 @@ def note(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def step_inputs(m, k):
-    from synth import fl_growing_front, rhs_smooth_series
+class Timesteps:
+    """A mesh with a growing solid front and a smooth right-hand side per
+    timestep k (time (k + 1) dt of a 200-step schedule)."""
 
-    t = (k + 1) * DT
-    fl = fl_growing_front(m.cell_centre, t=t, t_end=N_TIMESTEPS * DT, s_max=0.6, delta=0.1,
-                          axis=0, length=CAVITY)
-    b = rhs_smooth_series(m.cell_centre, t, seed=RHS_SEED, center_mask=fl > 0)
-    return fl, b
+    def __init__(self, mesh, axis, length, s_max=0.6):
+        from synth import face_coeff
+
+        self.m = mesh
+        self.c = face_coeff(mesh, RHO)
+        self.axis, self.length, self.s_max = axis, length, s_max
+
+    def inputs(self, k):
+        from synth import fl_growing_front, rhs_smooth_series
+
+        t = (k + 1) * DT
+        fl = fl_growing_front(self.m.cell_centre, t=t, t_end=N_TIMESTEPS * DT, s_max=self.s_max,
+                              delta=0.1, axis=self.axis, length=self.length)
+        b = rhs_smooth_series(self.m.cell_centre, t, seed=RHS_SEED, center_mask=fl > 0)
+        return fl, b
+
+    def to_device(self, torch, dev, steps):
+        m = self.m
+        host = {k: self.inputs(k) for k in sorted(set(steps))}
+        self.host = host
+        return dict(owner=torch.as_tensor(m.owner, device=dev),
+                    neigh=torch.as_tensor(m.neigh, device=dev),
+                    coeff=torch.as_tensor(self.c, device=dev),
+                    vol=torch.as_tensor(m.cell_volume, device=dev),
+                    fl={k: torch.as_tensor(v[0], device=dev) for k, v in host.items()},
+                    b={k: torch.as_tensor(v[1], device=dev) for k, v in host.items()})
 
 
-def cpu_baseline(m, c, inputs, steps, budget_s=20.0):
+def cpu_baseline(wl, steps, budget_s=20.0):
     """The FP64 oracle (assembly + SA setup + PCG from zero, unmodified) on
     host cores, single-threaded, over as many timed steps as fit the budget."""
     from threadpoolctl import threadpool_limits
 
     from oracle import amg, assembly, pcg
 
+    m = wl.m
     done, iters, t0 = 0, 0, time.perf_counter()
     with threadpool_limits(limits=1):
         for k in steps:
-            fl, b = inputs[k]
-            sy = assembly.masked_system(m.n_cells, m.owner, m.neigh, c, fl)
+            fl, b = wl.host[k]
+            sy = assembly.masked_system(m.n_cells, m.owner, m.neigh, wl.c, fl)
             H = amg.build_hierarchy(sy.A)
             res = pcg.pcg(sy.A, assembly.pinned_rhs(sy, b), M=lambda r: amg.vcycle(H, r),
                           rtol=1e-10)
@@ -89,9 +119,11 @@ def cpu_baseline(m, c, inputs, steps, budget_s=20.0):
                        f"{dt:.1f} s on one host thread")
 
 
-def run_leg(ppe, torch, m, dev, d_in, steps, warm, precision, learned=None):
-    """Solve warm + steps timesteps; time the last len(steps).  learned =
-    (net, mu, sigma) uses the warm-start network from the previous step."""
+def run_leg(ppe, torch, wl, d_in, steps, warm, precision, guess="zero", net=None):
+    """Solve warm + steps timesteps; time the last len(steps).  guess: "zero",
+    "prev" (the previous step's pressure) or "learned" (net = (network, mu,
+    sigma) predicts the increment from the previous step)."""
+    m, dev = wl.m, d_in["coeff"].device
     s = ppe.Solver(precision=precision)
     s.set_mesh(m.n_cells, d_in["owner"], d_in["neigh"])
     p_prev = torch.zeros(m.n_cells, dtype=torch.float64, device=dev)
@@ -104,14 +136,17 @@ def run_leg(ppe, torch, m, dev, d_in, steps, warm, precision, learned=None):
         fl, b = d_in["fl"][k], d_in["b"][k]
         s.assemble(d_in["coeff"], fl)
         x0 = None
-        if learned is not None:
-            net, mu, sigma = learned
+        if guess == "learned":
+            network, mu, sigma = net
             F, scale = ppe.warm_start_features(s, dp_prev, b, d_in["coeff"], fl, d_in["vol"], mu,
                                                sigma)
-            y = net.forward(F, bf16=True)
+            y = network.forward(F, bf16=True)
             x0 = ppe.warm_start_apply(s, p_prev, y, scale)
+        elif guess == "prev":  # the previous pressure re-referenced to the current pins
+            zero = torch.zeros(max(s.stats()["n_active"], 1), dtype=torch.float32, device=dev)
+            x0 = ppe.warm_start_apply(s, p_prev, zero, 0.0)
         r = s.solve(b, x0=x0, out=out)
-        if learned is not None:
+        if guess != "zero":
             dp_prev = out - p_prev
             p_prev, out = out, p_prev
         if timed:
@@ -131,16 +166,53 @@ def run_leg(ppe, torch, m, dev, d_in, steps, warm, precision, learned=None):
     torch.cuda.synchronize()
     rec["elapsed"] = time.perf_counter() - t0
     rec["solver"] = s
+    assert rec["worst"] <= 1e-10, f"a timed solve missed the tolerance: {rec['worst']}"
     return rec
 
 
-def train_network(ppe, torch, m, dev, d_in, n_adam=400, batch=8192):
+def leg_summary(rec, K, base=None):
+    import numpy as np
+
+    out = dict(value=K / rec["elapsed"], unit="solves/s",
+               ms_per_step=1e3 * rec["elapsed"] / K,
+               pcg_iterations_per_solve=rec["iters"] / K,
+               setup_ms_per_step=rec["setup_ms"] / K,
+               solve_ms_per_step=rec["solve_ms"] / K,
+               mean_active_cells=float(np.mean(rec["n_act"])),
+               worst_rel_residual=rec["worst"])
+    if base is not None:
+        out["wall_time_ratio_vs_fp64"] = base["elapsed"] / rec["elapsed"]
+        out["solve_time_ratio_vs_fp64"] = base["solve_ms"] / max(rec["solve_ms"], 1e-12)
+    return out
+
+
+def roofline(s, run):
+    """Live measurement of the finest-level Chebyshev step over run(): mean
+    dispatch duration from the library's event pairs, algorithmic bytes."""
+    s.profile(True)
+    run()
+    prof = s.profile_read()
+    s.profile(False)
+    launches = max(prof["launches"], 1)
+    avg_ms = prof["kernel_ms"] / launches
+    per_launch = prof["bytes"] / launches
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm",
+            "kernel": "finest-level Chebyshev step (ELL SpMV + smoother update)",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": per_launch,
+            "launches": prof["launches"]}
+
+
+def train_network(ppe, torch, wl, d_in, n_adam=400, batch=8192):
     """Snapshots produced by the solver on earlier timesteps -> trained
     network and feature standardisation (untimed)."""
     import numpy as np
 
     from synth import mlp_initial_weights
 
+    m, dev = wl.m, d_in["coeff"].device
     s = ppe.Solver(precision="mixed")
     s.set_mesh(m.n_cells, d_in["owner"], d_in["neigh"])
     zero10 = torch.zeros(10, dtype=torch.float32, device=dev)
@@ -179,6 +251,67 @@ def train_network(ppe, torch, m, dev, d_in, n_adam=400, batch=8192):
                                 loss_last=float(np.mean(losses[-10:])))
 
 
+def c3_leg(ppe, torch, dev, reps=4):
+    """One 128^3 system (random planar front), solved repeatedly."""
+    from synth import box_mesh, face_coeff, fl_planar_front, rhs_uniform
+
+    m = box_mesh((128, 128, 128), jitter=0.1, seed=0)
+    fh = fl_planar_front(m.cell_centre, seed=2)
+    c = torch.as_tensor(face_coeff(m, RHO), device=dev)
+    f = torch.as_tensor(fh, device=dev)
+    b = torch.as_tensor(rhs_uniform(m.n_cells, seed=1, center_mask=fh > 0), device=dev)
+    owner = torch.as_tensor(m.owner, device=dev)
+    neigh = torch.as_tensor(m.neigh, device=dev)
+    out = {"workload": "128^3 jittered cube, planar front (normal seed 2), uniform RHS; "
+                       f"{reps} timed solves of one assembled system after one untimed"}
+    for prec in ("fp64", "mixed"):
+        s = ppe.Solver(precision=prec)
+        s.set_mesh(m.n_cells, owner, neigh)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.assemble(c, f)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        p = torch.zeros(m.n_cells, dtype=torch.float64, device=dev)
+        r = s.solve(b, out=p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = s.solve(b, out=p)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        assert r.stats["rel_residual"] <= 1e-10
+        out[prec] = dict(solves_per_s=1.0 / dt, solve_ms=1e3 * dt, setup_ms=1e3 * t_setup,
+                         pcg_iterations=r.stats["iterations"], active_cells=r.stats["n_active"],
+                         levels=r.stats["levels"], rel_residual=r.stats["rel_residual"],
+                         roofline=roofline(s, lambda: s.solve(b, out=p)))
+    return out
+
+
+def c5_leg(ppe, torch, dev, net, steps=10, warm=3, first=40):
+    """Timesteps on the plate with ribs, front rising from the bottom face."""
+    from synth import plate_with_ribs_mesh
+
+    m = plate_with_ribs_mesh()
+    height = float(m.cell_centre[:, 2].max() - m.cell_centre[:, 2].min()) + 2.0e-3 / 3.0
+    wl = Timesteps(m, axis=2, length=height)
+    K = list(range(first, first + steps))
+    W = list(range(first - warm, first))
+    d_in = wl.to_device(torch, dev, W + K)
+    base = run_leg(ppe, torch, wl, d_in, K, W, "fp64")
+    out = {"workload": f"plate with ribs, {m.n_cells} cells (+-5 % jitter), front rising from "
+                       f"the bottom face, timesteps {K[0]}..{K[-1]} of 200 x 1e-3 s; network "
+                       "trained on the 64^3 cube run only",
+           "fp64_zero_guess": leg_summary(base, steps)}
+    for name, prec, guess in (("fp64_previous_guess", "fp64", "prev"),
+                              ("mixed_zero_guess", "mixed", "zero"),
+                              ("mixed_previous_guess", "mixed", "prev"),
+                              ("mixed_learned", "mixed", "learned")):
+        rec = run_leg(ppe, torch, wl, d_in, K, W, prec, guess=guess, net=net)
+        out[name] = leg_summary(rec, steps, base)
+    return out
+
+
 def uq_batched(ppe, torch, dev, n_samples=256, steps=3, warm=1):
     """Batched uncertainty samples (sides U{24..48}, 50-step schedule):
     per step, one assembly and one segmented solve of all samples."""
@@ -211,7 +344,7 @@ def uq_batched(ppe, torch, dev, n_samples=256, steps=3, warm=1):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
         s.assemble(c, data[k][0])
-        r = s.solve(data[k][1], out=out)
+        s.solve(data[k][1], out=out)
         if i >= warm:
             it, rr = s.segment_stats()
             its.append(float(np.mean(it)))
@@ -232,6 +365,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="time the FP64 leg only")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 128^3 leg")
+    ap.add_argument("--no-c5", action="store_true", help="skip the plate-with-ribs leg")
     ap.add_argument("--uq", action="store_true", help="add the batched-UQ measurement")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -243,25 +378,20 @@ def main():
     import torch
 
     import paper_1810_08572_amd as ppe
-    from synth import box_mesh, face_coeff
+    from synth import box_mesh
 
     dev = torch.device("cuda", 0)
     K, W = args.steps, args.warmup
     steps = list(range(FIRST_TIMED, FIRST_TIMED + K))
     warm = list(range(FIRST_TIMED - W, FIRST_TIMED))
-    m = box_mesh((SIDE,) * 3, lengths=(CAVITY,) * 3, jitter=0.1, seed=0)
-    c = face_coeff(m, RHO)
-    need = sorted(set(warm + steps + ([] if args.no_variants else list(TRAIN_STEPS))))
-    inputs = {k: step_inputs(m, k) for k in need}
-    d_in = dict(owner=torch.as_tensor(m.owner, device=dev), neigh=torch.as_tensor(m.neigh, device=dev),
-                coeff=torch.as_tensor(c, device=dev), vol=torch.as_tensor(m.cell_volume, device=dev),
-                fl={k: torch.as_tensor(v[0], device=dev) for k, v in inputs.items()},
-                b={k: torch.as_tensor(v[1], device=dev) for k, v in inputs.items()})
+    wl = Timesteps(box_mesh((64, 64, 64), lengths=(CAVITY,) * 3, jitter=0.1, seed=0), axis=0,
+                   length=CAVITY)
+    need = warm + steps + ([] if args.no_variants else list(TRAIN_STEPS))
+    d_in = wl.to_device(torch, dev, need)
+    note(f"inputs ready: {len(set(need))} timesteps of {wl.m.n_cells} cells")
 
-    note(f"inputs ready: {len(need)} timesteps of {m.n_cells} cells")
-    base = run_leg(ppe, torch, m, dev, d_in, steps, warm, "fp64")
+    base = run_leg(ppe, torch, wl, d_in, steps, warm, "fp64")
     note(f"fp64 leg: {K / base['elapsed']:.1f} solves/s")
-    assert base["worst"] <= 1e-10, f"a timed solve missed the tolerance: {base['worst']}"
     n_act = base["n_act"]
     out = {
         "metric": "pressure solves/s at 1e-10 rel. residual",
@@ -280,7 +410,7 @@ def main():
             "workload": "64^3 jittered hex cube, sqrt(t) solid front, smooth-in-time RHS, "
                         f"timesteps {steps[0]}..{steps[-1]} of 200 x 1e-3 s; one masked SA-AMG-PCG "
                         "pressure solve per step (assembly + setup + solve), FP64, zero guess",
-            "cells": m.n_cells,
+            "cells": wl.m.n_cells,
             "mean_active_cells": float(np.mean(n_act)),
             "pcg_iterations_per_solve": base["iters"] / K,
             "dof_iterations_per_s": float(np.sum(n_act)) * (base["iters"] / K) / base["elapsed"],
@@ -292,55 +422,39 @@ def main():
 
     if not args.no_profile:
         s = base["solver"]
-        s.profile(True)
-        for k in steps:
-            s.assemble(d_in["coeff"], d_in["fl"][k])
-            s.solve(d_in["b"][k])
-        prof = s.profile_read()
-        s.profile(False)
-        avg_ms = prof["kernel_ms"] / max(prof["launches"], 1)
-        per_launch = prof["bytes"] / max(prof["launches"], 1)
-        achieved = per_launch / (avg_ms * 1e-3) / 1e9
-        out["roofline"] = {
-            "bound": "hbm",
-            "kernel": "finest-level fused Chebyshev step (ELL SpMV + smoother update), FP64",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "avg_launch_us": avg_ms * 1e3,
-            "bytes_per_launch": per_launch,
-            "launches": prof["launches"],
-        }
+
+        def rerun():
+            for k in steps:
+                s.assemble(d_in["coeff"], d_in["fl"][k])
+                s.solve(d_in["b"][k])
+
+        out["roofline"] = roofline(s, rerun)
+        out["roofline"]["kernel"] += ", FP64"
 
     if not args.no_variants:
         variants = {}
-        mixed = run_leg(ppe, torch, m, dev, d_in, steps, warm, "mixed")
-        variants["mixed"] = dict(value=K / mixed["elapsed"], unit="solves/s",
-                                 pcg_iterations_per_solve=mixed["iters"] / K,
-                                 setup_ms_per_step=mixed["setup_ms"] / K,
-                                 solve_ms_per_step=mixed["solve_ms"] / K,
-                                 worst_rel_residual=mixed["worst"])
+        mixed = run_leg(ppe, torch, wl, d_in, steps, warm, "mixed")
+        variants["mixed"] = leg_summary(mixed, K, base)
         note(f"mixed leg: {K / mixed['elapsed']:.1f} solves/s")
-        net, mu, sigma, tr = train_network(ppe, torch, m, dev, d_in)
+        net, mu, sigma, tr = train_network(ppe, torch, wl, d_in)
         note(f"network trained: {tr}")
-        ml = run_leg(ppe, torch, m, dev, d_in, steps, warm, "mixed", learned=(net, mu, sigma))
-        assert ml["worst"] <= 1e-10
-        variants["mixed_learned"] = dict(
-            value=K / ml["elapsed"], unit="solves/s",
-            pcg_iterations_per_solve=ml["iters"] / K,
-            setup_ms_per_step=ml["setup_ms"] / K, solve_ms_per_step=ml["solve_ms"] / K,
-            worst_rel_residual=ml["worst"],
-            solve_time_ratio_vs_fp64=base["solve_ms"] / max(ml["solve_ms"], 1e-12),
-            training=tr)
+        ml = run_leg(ppe, torch, wl, d_in, steps, warm, "mixed", guess="learned",
+                     net=(net, mu, sigma))
+        variants["mixed_learned"] = dict(leg_summary(ml, K, base), training=tr)
         note(f"mixed+learned leg: {K / ml['elapsed']:.1f} solves/s")
+        if not args.no_c3:
+            variants["c3_128cube"] = c3_leg(ppe, torch, dev)
+            note("128^3 leg done")
+        if not args.no_c5:
+            variants["c5_plate_ribs"] = c5_leg(ppe, torch, dev, (net, mu, sigma))
+            note("plate-with-ribs leg done")
         out["variants"] = variants
     if args.uq:
         out.setdefault("variants", {})["uq_batched"] = uq_batched(ppe, torch, dev)
+        note("batched UQ leg done")
     if not args.no_cpu_baseline:
         note("timing the oracle on the host")
-        out["cpu_baseline"] = cpu_baseline(m, c, inputs, steps)
+        out["cpu_baseline"] = cpu_baseline(wl, steps)
     print(json.dumps(out), flush=True)
 
 

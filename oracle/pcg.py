@@ -7,9 +7,13 @@ naming it; the pinned pressure matrix is symmetric positive definite and the
 V-cycle preconditioner is symmetric, so conjugate gradients applies.  The
 stopping rule is ||b - A x||_2 <= rtol ||b||_2; when the recurred residual
 meets it the true residual is recomputed, and the iteration goes on from the
-true residual if that one does not.  ``flexible`` selects the Polak-Ribiere
-form of beta, r_new.(z_new - z_old) / (r_old.z_old), for preconditioners
-that are only approximately fixed (a lower-precision V-cycle).
+true residual if that one does not.  ``flexible`` selects the flexible form
+for preconditioners that are only approximately fixed (a lower-precision
+V-cycle): alpha = (r.p) / (p.Ap), the exact line search along p, and
+beta = -(z_new.Ap) / (p.Ap), which makes the new direction A-orthogonal to
+the previous one whatever the preconditioner did (flexible CG with one
+stored direction, Notay 2000).  For a fixed SPD preconditioner both forms
+equal the standard ones in exact arithmetic.
 """
 from __future__ import annotations
 
@@ -53,7 +57,7 @@ def pcg(A, b, M: Optional[Callable] = None, x0=None, rtol=1e-10, max_iter=500,
         pq = float(p @ q)
         if not pq > 0.0:
             return PcgResult(x, k - 1, BREAKDOWN, hist[-1], hist)
-        alpha = rz / pq
+        alpha = float(r @ p) / pq if flexible else rz / pq
         x = x + alpha * p
         r = r - alpha * q
         rn = float(np.linalg.norm(r))
@@ -65,12 +69,11 @@ def pcg(A, b, M: Optional[Callable] = None, x0=None, rtol=1e-10, max_iter=500,
                 hist[-1] = rtn / bnorm
                 return PcgResult(x, k, OK, rtn / bnorm, hist)
             r = rt
-        z_old = z
         z = M(r)
         rz_new = float(r @ z)
         if not rz_new > 0.0:
             return PcgResult(x, k, BREAKDOWN, hist[-1], hist)
-        beta = (rz_new - float(r @ z_old)) / rz if flexible else rz_new / rz
+        beta = -float(z @ q) / pq if flexible else rz_new / rz
         p = z + beta * p
         rz = rz_new
     rt = b - A @ x

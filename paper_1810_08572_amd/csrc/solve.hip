@@ -236,7 +236,8 @@ __device__ __forceinline__ double seg_sum(const double* __restrict__ part, const
 // per-segment scalar arrays (each n_seg doubles) in s->seg_sc
 enum SegScal : int { SS_BB = 0, SS_TOL2 = 1, SS_RZ0 = 2, SS_RZ1 = 3, SS_RES = 4, SS_N = 5 };
 // tile-partial arrays (each n_tiles doubles) in s->tpart
-enum TilePart : int { T_BB = 0, T_RR = 1, T_PQ = 2, T_RZ = 3 /* and 4 */, T_RT = 5, T_N = 6 };
+// (pairs written by one kernel are adjacent: T_PQ/T_RP and T_RZ/T_ZQ)
+enum TilePart : int { T_BB = 0, T_RR = 1, T_PQ = 2, T_RP = 3, T_RZ = 4, T_ZQ = 5, T_RT = 6, T_N = 7 };
 
 __global__ void __launch_bounds__(kBlock) k_gather_rhs_t(Tiles T, const int* __restrict__ perm,
                                                          const int* __restrict__ comp,
@@ -264,30 +265,31 @@ __global__ void __launch_bounds__(kBlock) k_norm2_t(Tiles T, const double* __res
   write_partials<kBlock, 1>(sv, part);
 }
 
-// tile partials of r.z and (flexible) r.z_old
+// tile partials of r.z and (flexible) z.q
 __global__ void __launch_bounds__(kBlock) k_dot2_t(Tiles T, const double* __restrict__ r,
                                                    const double* __restrict__ z,
-                                                   const double* __restrict__ zold,
+                                                   const double* __restrict__ q,
                                                    double* __restrict__ part) {
   const int t = blockIdx.x;
   double sv[2] = {0.0, 0.0};
   for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) {
     sv[0] += r[i] * z[i];
-    if (zold) sv[1] += r[i] * zold[i];
+    if (q) sv[1] += z[i] * q[i];
   }
   write_partials<kBlock, 2>(sv, part);
 }
 
 // The last smoothing step of a level-0 V-cycle fused with the PCG dots that
 // follow it: the E_CHEB step y = x + d over the tile's rows, then tile
-// partials of b.y and (flexible) b.zold, where b is the PCG residual the
-// V-cycle was applied to.  Same arithmetic and order as the separate kernels.
+// partials of b.y and (flexible) y.q, where b is the PCG residual the V-cycle
+// was applied to and y the preconditioned residual.  Same arithmetic and
+// order as the separate kernels.
 template <int WM>
 __global__ void __launch_bounds__(kBlock) k_ell_cheb_dot_t(
     Tiles T, int n, int W, const int* __restrict__ ecol, const double* __restrict__ eval,
     const double* __restrict__ diag, const double* __restrict__ x, const double* __restrict__ b,
     double* __restrict__ d, double c1, double c2, double* __restrict__ y,
-    const double* __restrict__ zold, double* __restrict__ part) {
+    const double* __restrict__ qv, double* __restrict__ part) {
   const int t = blockIdx.x;
   double sv[2] = {0.0, 0.0};
   for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) {
@@ -299,16 +301,16 @@ __global__ void __launch_bounds__(kBlock) k_ell_cheb_dot_t(
     const double yi = x[i] + dn;
     y[i] = yi;
     sv[0] += b[i] * yi;
-    if (zold) sv[1] += b[i] * zold[i];
+    if (qv) sv[1] += yi * qv[i];
   }
   write_partials<kBlock, 2>(sv, part);
 }
 
 // Mixed precision: z = (double) z32 over the tile's rows with the PCG dots
-// r.z and (flexible) r.zold as tile partials.
+// r.z and (flexible) z.q as tile partials.
 __global__ void __launch_bounds__(kBlock) k_cast_dot_t(Tiles T, const float* __restrict__ zf,
                                                        const double* __restrict__ r,
-                                                       const double* __restrict__ zold,
+                                                       const double* __restrict__ qv,
                                                        double* __restrict__ z,
                                                        double* __restrict__ part) {
   const int t = blockIdx.x;
@@ -317,13 +319,14 @@ __global__ void __launch_bounds__(kBlock) k_cast_dot_t(Tiles T, const float* __r
     const double v = (double)zf[i];
     z[i] = v;
     sv[0] += r[i] * v;
-    if (zold) sv[1] += r[i] * zold[i];
+    if (qv) sv[1] += v * qv[i];
   }
   write_partials<kBlock, 2>(sv, part);
 }
 
-// q = A p on the finest (ELL) level over the tile's rows; tile partial of p.q
-template <int WM>
+// q = A p on the finest (ELL) level over the tile's rows; tile partials of
+// p.q and (RP: flexible iteration) r.p
+template <int WM, bool RP>
 __global__ void __launch_bounds__(kBlock) k_ell_dot_t(Tiles T, int n, int W,
                                                       const int* __restrict__ ecol,
                                                       const double* __restrict__ eval,
@@ -331,19 +334,26 @@ __global__ void __launch_bounds__(kBlock) k_ell_dot_t(Tiles T, int n, int W,
                                                       const int* __restrict__ done,
                                                       const double* __restrict__ p,
                                                       double* __restrict__ q,
+                                                      const double* __restrict__ r,
                                                       double* __restrict__ part) {
   const int t = blockIdx.x;
-  double acc = 0.0;
+  double acc = 0.0, arp = 0.0;
   if (!done[T.seg[t]]) {
     for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) {
       double s = diag[i] * p[i];
       s = ell_row<E_SPMV, WM, double>(s, i, n, W, ecol, eval, p, nullptr, diag, 0.0);
       q[i] = s;
       acc += p[i] * s;
+      if (RP) arp += r[i] * p[i];
     }
   }
-  double sv[1] = {acc};
-  write_partials<kBlock, 1>(sv, part);
+  if (RP) {
+    double sv[2] = {acc, arp};
+    write_partials<kBlock, 2>(sv, part);
+  } else {
+    double sv[1] = {acc};
+    write_partials<kBlock, 1>(sv, part);
+  }
 }
 
 // Per segment (one block each): bb, tolerance, initial convergence; counts
@@ -391,7 +401,9 @@ __global__ void __launch_bounds__(kBlock) k_init_p_t(Tiles T, int ns, const int*
   for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) p[i] = z[i];
 }
 
-// alpha_q = rz_q / (p.q)_q; x += alpha p; r -= alpha q; tile partial of r.r
+// alpha_q = rz_q / (p.q)_q, or (flexible) (r.p)_q / (p.q)_q, the exact line
+// search whatever the preconditioner; x += alpha p; r -= alpha q; tile
+// partial of r.r
 __global__ void __launch_bounds__(kBlock) k_update_xr_t(Tiles T, const int* __restrict__ done,
                                                         const double* __restrict__ rz,
                                                         const double* __restrict__ part_pq,
@@ -401,16 +413,18 @@ __global__ void __launch_bounds__(kBlock) k_update_xr_t(Tiles T, const int* __re
                                                         double* __restrict__ r,
                                                         double* __restrict__ part,
                                                         int* __restrict__ active,
-                                                        int* __restrict__ err) {
+                                                        int* __restrict__ err, int nt,
+                                                        int flexible) {
   const int t = blockIdx.x, q = T.seg[t];
   if (t == 0 && threadIdx.x == 0) *active = 0;  // counted again by k_update_p_t
   double acc = 0.0;
   if (!done[q]) {
     const double pq = seg_sum(part_pq, T, q);
-    if (!(pq > 0.0) || !(rz[q] > 0.0)) {
+    const double num = flexible ? seg_sum(part_pq + nt, T, q) : rz[q];
+    if (!(pq > 0.0) || !(num > 0.0)) {
       if (threadIdx.x == 0) atomicOr(err, 1);
     } else {
-      const double alpha = rz[q] / pq;
+      const double alpha = num / pq;
       for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) {
         x[i] = x[i] + alpha * p[i];
         const double v = r[i] - alpha * qv[i];
@@ -428,13 +442,15 @@ __global__ void __launch_bounds__(kBlock) k_update_xr_t(Tiles T, const int* __re
 // of a segment adds the same partials in the same order, so all of them take
 // the same decision, and a segment that converged (or broke down) keeps its
 // p.  Otherwise (first direction after a restart) restart[q] forces beta 0.
-// Then beta_q = (r.z - [r.z_old]) / rz_prev and p = z + beta p; counts the
-// segments still running.
+// Then beta_q = r.z / rz_prev, or (flexible) -(z.q) / (p.q), which makes the
+// new direction A-orthogonal to the previous one whatever the preconditioner;
+// p = z + beta p; counts the segments still running.
 __global__ void __launch_bounds__(kBlock) k_update_p_t(
     Tiles T, int nt, int ns, int test, int* __restrict__ done, int* __restrict__ restart,
     const double* __restrict__ part_rr, const double* __restrict__ sc, int* __restrict__ iters,
-    int* __restrict__ active, const double* __restrict__ part_rz, int flexible,
-    const double* __restrict__ rz_prev, double* __restrict__ rz_next,
+    int* __restrict__ active, const double* __restrict__ part_rz,
+    const double* __restrict__ part_pq, int flexible, const double* __restrict__ rz_prev,
+    double* __restrict__ rz_next,
     const double* __restrict__ z, double* __restrict__ p, int* __restrict__ err) {
   const int t = blockIdx.x, q = T.seg[t];
   if (done[q]) return;
@@ -453,12 +469,17 @@ __global__ void __launch_bounds__(kBlock) k_update_p_t(
     if (conv) return;
   }
   const double rzn = seg_sum(part_rz, T, q);
-  const double rzo = flexible ? seg_sum(part_rz + nt, T, q) : 0.0;
+  double beta = 0.0;
+  if (!(!test && restart[q])) {
+    if (flexible)
+      beta = -seg_sum(part_rz + nt, T, q) / seg_sum(part_pq, T, q);
+    else
+      beta = rzn / rz_prev[q];
+  }
   if (lead) {
     rz_next[q] = rzn;
     if (!(rzn > 0.0)) atomicOr(err, 4);
   }
-  const double beta = (!test && restart[q]) ? 0.0 : (rzn - rzo) / rz_prev[q];
   for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) p[i] = z[i] + beta * p[i];
 }
 
@@ -639,11 +660,11 @@ void apply_rect(ppe_solver* s, const Csr& M, const T* x, T* y) {
 }
 
 // PCG dots fused into the last level-0 step of the V-cycle: tile partials of
-// r.z and (flexible) r.z_old into part (2 x n_tiles).
+// r.z and (flexible) z.q into part (2 x n_tiles).
 struct PcgDot {
   Tiles T;
   int nt;
-  const double* zold;
+  const double* q;  // flexible: also z.q (q = A p of the iteration)
   double* part;
 };
 
@@ -687,7 +708,7 @@ bool smooth(ppe_solver* s, Level& L, const T* b, const T* x_in, T* x_out, T* xa,
 #define PPE_CHEB_DOT(WM_)                                                                     \
   hipLaunchKernelGGL(k_ell_cheb_dot_t<WM_>, dim3(dot->nt), dim3(kBlock), 0, s->stream, dot->T, n, \
                      L.W, L.ell_col.as<int>(), L.ell_val.as<double>(), L.diag.as<double>(), cur, \
-                     b, d, c1, c2, dst, dot->zold, dot->part)
+                     b, d, c1, c2, dst, dot->q, dot->part)
         PPE_ELL_WIDTH(L.W, PPE_CHEB_DOT);
 #undef PPE_CHEB_DOT
         PPE_LAUNCH_CHECK();
@@ -842,7 +863,7 @@ void vcycle(ppe_solver* s, int l, const double* b, double* x) {
   cast<float, double>(s, L.x.as<float>(), x, L.n);
 }
 
-// z = M r for PCG, with the dots r.z and (flexible) r.z_old left as tile
+// z = M r for PCG, with the dots r.z and (flexible) z.q left as tile
 // partials: fused into the last level-0 smoothing step (FP64) or into the
 // cast back to FP64 (mixed), else a separate pass.
 static void vcycle_pcg(ppe_solver* s, const double* r, double* z, const PcgDot& dot) {
@@ -854,12 +875,12 @@ static void vcycle_pcg(ppe_solver* s, const double* r, double* z, const PcgDot& 
     cast<double, float>(s, r, L.b.as<float>(), L.n);
     vcycle_t<float>(s, 0, L.b.as<float>(), L.x.as<float>());
     hipLaunchKernelGGL(k_cast_dot_t, dim3(dot.nt), dim3(kBlock), 0, s->stream, dot.T,
-                       L.x.as<float>(), r, dot.zold, z, dot.part);
+                       L.x.as<float>(), r, dot.q, z, dot.part);
     PPE_LAUNCH_CHECK();
     dotted = true;
   }
   if (!dotted) {
-    hipLaunchKernelGGL(k_dot2_t, dim3(dot.nt), dim3(kBlock), 0, s->stream, dot.T, r, z, dot.zold,
+    hipLaunchKernelGGL(k_dot2_t, dim3(dot.nt), dim3(kBlock), 0, s->stream, dot.T, r, z, dot.q,
                        dot.part);
     PPE_LAUNCH_CHECK();
   }
@@ -928,8 +949,7 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
   Level& L0 = s->levels[0];
   double* x = s->vx.get<double>(na);
   double* r = s->vr.get<double>(na);
-  // z alternates between two buffers, so the previous z (flexible beta) is
-  // the other one
+  // z alternates between two buffers (one captured graph holds both)
   double* zb[2] = {s->vz.get<double>(na), s->vzold.get<double>(na)};
   double* p = s->vp.get<double>(na);
   double* q = s->vq.get<double>(na);
@@ -1018,11 +1038,10 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
   read_counts();
   if (h[0] == 0 && check_true() == 0) return finish(PPE_OK);
 
-  auto precondition = [&](int sl, bool with_old) {
-    vcycle_pcg(s, r, zb[sl],
-               PcgDot{T, nt, flexible && with_old ? zb[1 - sl] : nullptr, tpart(T_RZ)});
+  auto precondition = [&](int sl, bool with_q) {
+    vcycle_pcg(s, r, zb[sl], PcgDot{T, nt, flexible && with_q ? q : nullptr, tpart(T_RZ)});
   };
-  precondition(1, false);  // the first iteration (slot 0) takes this z as z_old
+  precondition(1, false);
   hipLaunchKernelGGL(k_init_p_t, dim3(nt), dim3(kBlock), 0, s->stream, T, ns, done, tpart(T_RZ),
                      zb[1], p, rz[0]);
   PPE_LAUNCH_CHECK();
@@ -1031,19 +1050,24 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
   // left untouched by every kernel, so extra iterations change nothing.
   auto body = [&](int sl) {
 #define PPE_ELL_DOT(WM_)                                                                      \
-  hipLaunchKernelGGL(k_ell_dot_t<WM_>, dim3(nt), dim3(kBlock), 0, s->stream, T, na, L0.W,         \
-                     L0.ell_col.as<int>(), L0.ell_val.as<double>(), L0.diag.as<double>(), done,  \
-                     p, q, tpart(T_PQ))
+  if (flexible)                                                                                 \
+    hipLaunchKernelGGL((k_ell_dot_t<WM_, true>), dim3(nt), dim3(kBlock), 0, s->stream, T, na,     \
+                       L0.W, L0.ell_col.as<int>(), L0.ell_val.as<double>(), L0.diag.as<double>(), \
+                       done, p, q, r, tpart(T_PQ));                                             \
+  else                                                                                          \
+    hipLaunchKernelGGL((k_ell_dot_t<WM_, false>), dim3(nt), dim3(kBlock), 0, s->stream, T, na,    \
+                       L0.W, L0.ell_col.as<int>(), L0.ell_val.as<double>(), L0.diag.as<double>(), \
+                       done, p, q, nullptr, tpart(T_PQ))
     PPE_ELL_WIDTH(L0.W, PPE_ELL_DOT);
 #undef PPE_ELL_DOT
     PPE_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_update_xr_t, dim3(nt), dim3(kBlock), 0, s->stream, T, done, rz[sl],
-                       tpart(T_PQ), p, q, x, r, tpart(T_RR), cnt, cnt + 1);
+                       tpart(T_PQ), p, q, x, r, tpart(T_RR), cnt, cnt + 1, nt, flexible ? 1 : 0);
     PPE_LAUNCH_CHECK();
     precondition(sl, true);
     hipLaunchKernelGGL(k_update_p_t, dim3(nt), dim3(kBlock), 0, s->stream, T, nt, ns, 1, done,
-                       restart, tpart(T_RR), sc, iters, cnt, tpart(T_RZ), flexible ? 1 : 0, rz[sl],
-                       rz[1 - sl], zb[sl], p, cnt + 1);
+                       restart, tpart(T_RR), sc, iters, cnt, tpart(T_RZ), tpart(T_PQ),
+                       flexible ? 1 : 0, rz[sl], rz[1 - sl], zb[sl], p, cnt + 1);
     PPE_LAUNCH_CHECK();
   };
   // Two iterations (both rz slots) captured into a HIP graph on the second
@@ -1074,10 +1098,10 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
     if (h[0] == 0) {
       if (check_true() == 0) return finish(PPE_OK);
       // restarted samples: z = M r_true, p = z (beta is 0 after a restart)
-      precondition(slot, false);  // beta is 0: z_old is not needed
+      precondition(slot, false);  // beta is 0: z.q is not needed
       hipLaunchKernelGGL(k_update_p_t, dim3(nt), dim3(kBlock), 0, s->stream, T, nt, ns, 0, done,
-                         restart, tpart(T_RR), sc, iters, cnt, tpart(T_RZ), flexible ? 1 : 0,
-                         rz[slot], rz[1 - slot], zb[slot], p, cnt + 1);
+                         restart, tpart(T_RR), sc, iters, cnt, tpart(T_RZ), tpart(T_PQ),
+                         flexible ? 1 : 0, rz[slot], rz[1 - slot], zb[slot], p, cnt + 1);
       PPE_LAUNCH_CHECK();
       slot = 1 - slot;
     }
