@@ -186,9 +186,26 @@ def leg_summary(rec, K, base=None):
     return out
 
 
-def roofline(s, run):
+def counter_traffic(workload):
+    """Bytes per launch of the roofline kernel from the committed memory
+    counter summary, or None when the kernel source changed since."""
+    import hashlib
+
+    try:
+        with open(os.path.join(ROOT, "profiles", "roofline_traffic.json")) as f:
+            data = json.load(f)
+        with open(os.path.join(ROOT, data["source_file"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != data["source_sha256"]:
+                return None
+        return data[workload]["bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def roofline(s, run, workload=None):
     """Live measurement of the finest-level Chebyshev step over run(): mean
-    dispatch duration from the library's event pairs, algorithmic bytes."""
+    dispatch duration from the library's event pairs, algorithmic bytes;
+    traffic from the committed counter summary of that workload."""
     s.profile(True)
     run()
     prof = s.profile_read()
@@ -200,7 +217,8 @@ def roofline(s, run):
     return {"bound": "hbm",
             "kernel": "finest-level Chebyshev step (ELL SpMV + smoother update)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": counter_traffic(workload) if workload else None,
             "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": per_launch,
             "launches": prof["launches"]}
 
@@ -284,7 +302,8 @@ def c3_leg(ppe, torch, dev, reps=4):
         out[prec] = dict(solves_per_s=1.0 / dt, solve_ms=1e3 * dt, setup_ms=1e3 * t_setup,
                          pcg_iterations=r.stats["iterations"], active_cells=r.stats["n_active"],
                          levels=r.stats["levels"], rel_residual=r.stats["rel_residual"],
-                         roofline=roofline(s, lambda: s.solve(b, out=p)))
+                         roofline=roofline(s, lambda: s.solve(b, out=p),
+                                           "128cube_planar_front" if prec == "fp64" else None))
     return out
 
 
@@ -368,6 +387,11 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the 128^3 leg")
     ap.add_argument("--no-c5", action="store_true", help="skip the plate-with-ribs leg")
     ap.add_argument("--uq", action="store_true", help="add the batched-UQ measurement")
+    ap.add_argument("--c3-only", action="store_true",
+                    help="run only the 128^3 leg and print its JSON (for profiling it alone)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy a 512 MiB buffer three times (a kernel of known traffic, "
+                         "for scaling memory counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -381,6 +405,16 @@ def main():
     from synth import box_mesh
 
     dev = torch.device("cuda", 0)
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.c3_only:
+        print(json.dumps(c3_leg(ppe, torch, dev)), flush=True)
+        return
     K, W = args.steps, args.warmup
     steps = list(range(FIRST_TIMED, FIRST_TIMED + K))
     warm = list(range(FIRST_TIMED - W, FIRST_TIMED))
@@ -428,7 +462,7 @@ def main():
                 s.assemble(d_in["coeff"], d_in["fl"][k])
                 s.solve(d_in["b"][k])
 
-        out["roofline"] = roofline(s, rerun)
+        out["roofline"] = roofline(s, rerun, "64cube_timesteps")
         out["roofline"]["kernel"] += ", FP64"
 
     if not args.no_variants:
