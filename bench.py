@@ -119,12 +119,15 @@ def cpu_baseline(wl, steps, budget_s=20.0):
                        f"{dt:.1f} s on one host thread")
 
 
-def run_leg(ppe, torch, wl, d_in, steps, warm, precision, guess="zero", net=None):
+def run_leg(ppe, torch, wl, d_in, steps, warm, precision, guess="zero", net=None,
+            autotune=False):
     """Solve warm + steps timesteps; time the last len(steps).  guess: "zero",
     "prev" (the previous step's pressure) or "learned" (net = (network, mu,
-    sigma) predicts the increment from the previous step)."""
+    sigma) predicts the increment from the previous step).  autotune: the
+    library times its per-level launch choices at assembly (cached by level
+    shape; the warmup steps take the first tunings)."""
     m, dev = wl.m, d_in["coeff"].device
-    s = ppe.Solver(precision=precision)
+    s = ppe.Solver(precision=precision, autotune=autotune)
     s.set_mesh(m.n_cells, d_in["owner"], d_in["neigh"])
     p_prev = torch.zeros(m.n_cells, dtype=torch.float64, device=dev)
     dp_prev = torch.zeros_like(p_prev)
@@ -281,9 +284,10 @@ def c3_leg(ppe, torch, dev, reps=4):
     owner = torch.as_tensor(m.owner, device=dev)
     neigh = torch.as_tensor(m.neigh, device=dev)
     out = {"workload": "128^3 jittered cube, planar front (normal seed 2), uniform RHS; "
-                       f"{reps} timed solves of one assembled system after one untimed"}
+                       f"{reps} timed solves of one assembled system after one untimed; "
+                       "launch choices autotuned at assembly (setup_ms includes the tuning)"}
     for prec in ("fp64", "mixed"):
-        s = ppe.Solver(precision=prec)
+        s = ppe.Solver(precision=prec, autotune=True)
         s.set_mesh(m.n_cells, owner, neigh)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -317,16 +321,16 @@ def c5_leg(ppe, torch, dev, net, steps=10, warm=3, first=40):
     K = list(range(first, first + steps))
     W = list(range(first - warm, first))
     d_in = wl.to_device(torch, dev, W + K)
-    base = run_leg(ppe, torch, wl, d_in, K, W, "fp64")
+    base = run_leg(ppe, torch, wl, d_in, K, W, "fp64", autotune=True)
     out = {"workload": f"plate with ribs, {m.n_cells} cells (+-5 % jitter), front rising from "
                        f"the bottom face, timesteps {K[0]}..{K[-1]} of 200 x 1e-3 s; network "
-                       "trained on the 64^3 cube run only",
+                       "trained on the 64^3 cube run only; launch choices autotuned",
            "fp64_zero_guess": leg_summary(base, steps)}
     for name, prec, guess in (("fp64_previous_guess", "fp64", "prev"),
                               ("mixed_zero_guess", "mixed", "zero"),
                               ("mixed_previous_guess", "mixed", "prev"),
                               ("mixed_learned", "mixed", "learned")):
-        rec = run_leg(ppe, torch, wl, d_in, K, W, prec, guess=guess, net=net)
+        rec = run_leg(ppe, torch, wl, d_in, K, W, prec, guess=guess, net=net, autotune=True)
         out[name] = leg_summary(rec, steps, base)
     return out
 

@@ -74,6 +74,13 @@ typedef struct {
                          the result and iteration count do not depend on it */
   void* stream;       /* hipStream_t used for every launch; NULL = default stream */
   int use_graph;      /* replay PCG iterations from a captured HIP graph, default 1 */
+  int autotune;       /* 1: at assembly, time the candidate launch choices of each
+                         level's solve kernels (lanes per row of the smoother,
+                         restriction and prolongation; fused or split first
+                         smoothing steps) and keep the fastest, cached per level
+                         shape.  Lanes per row change the order of the row sums,
+                         so results then depend on the choices (to rounding).
+                         Default 0: fixed rules, bitwise reproducible. */
 } ppe_options;
 
 typedef struct {

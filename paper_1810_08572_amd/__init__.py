@@ -42,6 +42,7 @@ class ppe_options(ctypes.Structure):
         ("check_every", ctypes.c_int),
         ("stream", ctypes.c_void_p),
         ("use_graph", ctypes.c_int),
+        ("autotune", ctypes.c_int),
     ]
 
 
@@ -209,7 +210,7 @@ class Solver:
 
     def __init__(self, precision="fp64", rtol=1e-10, max_iter=500, cheb_degree=2,
                  cheb_ratio=30.0, coarse_max=128, max_levels=10, theta=0.08, stream=None,
-                 use_graph=True, check_every=2):
+                 use_graph=True, check_every=2, autotune=False):
         import torch
 
         lib = load_library()
@@ -218,6 +219,7 @@ class Solver:
         o.rtol, o.max_iter, o.cheb_degree, o.cheb_ratio = rtol, max_iter, cheb_degree, cheb_ratio
         o.coarse_max, o.max_levels, o.theta = coarse_max, max_levels, theta
         o.use_graph, o.check_every = int(bool(use_graph)), int(check_every)
+        o.autotune = int(bool(autotune))
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

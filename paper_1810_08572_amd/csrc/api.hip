@@ -97,6 +97,7 @@ void ppe_default_options(ppe_options* o) {
   o->check_every = 2;
   o->stream = nullptr;
   o->use_graph = 1;
+  o->autotune = 0;
 }
 
 ppe_status ppe_create(const ppe_options* opt, ppe_solver** out) {
@@ -152,6 +153,8 @@ void ppe_destroy(ppe_solver* s) {
   if (s->gstream) (void)hipStreamDestroy(s->gstream);
   if (s->ev0) (void)hipEventDestroy(s->ev0);
   if (s->ev1) (void)hipEventDestroy(s->ev1);
+  if (s->tev0) (void)hipEventDestroy(s->tev0);
+  if (s->tev1) (void)hipEventDestroy(s->tev1);
   delete s;
 }
 
@@ -190,6 +193,12 @@ ppe_status ppe_assemble(ppe_solver* s, const double* face_coeff, const double* f
       ppe::build_hierarchy(s);
       ppe::prepare_solve_levels(s);
       if (s->opt.precision == PPE_MIXED) ppe::make_fp32_hierarchy(s);
+      if (s->opt.autotune) {
+        const bool prof = s->prof;  // tuning launches are not measurements
+        s->prof = false;
+        ppe::autotune_levels(s);
+        s->prof = prof;
+      }
     } else {
       s->nlev = 1;
     }

@@ -9,6 +9,8 @@
 #include <cstdio>
 #include <stdexcept>
 #include <string>
+#include <array>
+#include <map>
 #include <vector>
 
 #include "../../include/ppe.h"
@@ -98,6 +100,12 @@ struct Level {
   DevBuf agg;            // int[n], aggregate id or -1
   DevBuf B;              // near-null vector
   double rho = 1.0;      // spectral bound of D^-1 A
+  // launch choices of the solve kernels (0 / true: the fixed rules; set by
+  // the autotuner when enabled): lanes per row of the smoother's CSR
+  // kernel, of the restriction and of the prolongation; whether the first
+  // two Chebyshev steps from a zero guess run as one fused pass
+  int lpr_a = 0, lpr_r = 0, lpr_p = 0;
+  bool fuse0 = true;
   double inv_theta = 0.0;
   std::vector<double> c1, c2;  // Chebyshev steps 2..degree
   int mis_rounds = 0;
@@ -160,6 +168,10 @@ struct ppe_solver {
   // level (doubles [0, max_levels)), then the deferred setup error bits (int)
   ppe::DevBuf setup_out;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t tev0 = nullptr, tev1 = nullptr;  // autotuner timing
+  // autotuner choices per (level, FP32, quarter-octave bins of rows and of
+  // entries): {lpr_a, fuse0, lpr_r, lpr_p}
+  std::map<std::array<int, 4>, std::array<int, 4>> tune_cache;
 
   // HIP graph of two PCG iterations, captured once per hierarchy
   hipStream_t gstream = nullptr;
@@ -371,6 +383,9 @@ void vcycle(ppe_solver* s, int level, const double* b, double* x);
 ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p, int use_x0);
 void prepare_solve_levels(ppe_solver* s);
 void make_fp32_hierarchy(ppe_solver* s);
+// Time the candidate launch choices of every level's solve kernels and keep
+// the fastest (cached by level shape).
+void autotune_levels(ppe_solver* s);
 void profile_harvest(ppe_solver* s);
 void drop_graph(ppe_solver* s);
 void profile_enable(ppe_solver* s, bool on);

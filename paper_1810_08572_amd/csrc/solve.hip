@@ -622,7 +622,7 @@ int apply_op(ppe_solver* s, const Level& L, const T* x, const T* b, T* d, double
     }
     return g;
   }
-  const int lpr = lanes_for(L.A);
+  const int lpr = L.lpr_a > 0 ? L.lpr_a : lanes_for(L.A);
   const int g = reduce ? red_grid((int64_t)n * lpr) : grid_for((int64_t)n * lpr);
 #define PPE_CSR(LL)                                                                            \
   hipLaunchKernelGGL((k_csr<EPI, LL, T>), dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(),    \
@@ -641,9 +641,9 @@ int apply_op(ppe_solver* s, const Level& L, const T* x, const T* b, T* d, double
 }
 
 template <bool ADD, class T>
-void apply_rect(ppe_solver* s, const Csr& M, const T* x, T* y) {
+void apply_rect(ppe_solver* s, const Csr& M, const T* x, T* y, int lpr_choice = 0) {
   if (M.n == 0) return;
-  const int lpr = lanes_for(M);
+  const int lpr = lpr_choice > 0 ? lpr_choice : lanes_for(M);
   const int g = grid_for((int64_t)M.n * lpr);
 #define PPE_RECT(LL)                                                                           \
   hipLaunchKernelGGL((k_csr_rect<LL, ADD, T>), dim3(g), dim3(kBlock), 0, s->stream, M.n, M.rp(), \
@@ -683,7 +683,7 @@ bool smooth(ppe_solver* s, Level& L, const T* b, const T* x_in, T* x_out, T* xa,
   const T* cur = x_in;
   int step = 1;
   if (cur == nullptr) {
-    if (deg >= 2) {
+    if (deg >= 2 && L.fuse0) {
       T* dst = dst_of(2);
       apply_op<E_CHEB0, T>(s, L, nullptr, b, d, L.c1[0], L.c2[0], dst, nullptr, nullptr, 0,
                            L.inv_theta);
@@ -748,9 +748,9 @@ bool vcycle_t(ppe_solver* s, int l, const T* b, T* x, const PcgDot* dot = nullpt
   T* r = L.r.as<T>();
   smooth<T>(s, L, b, nullptr, x1, xa, xb);
   apply_op<E_RESID, T>(s, L, x1, b, nullptr, 0.0, 0.0, r, nullptr);
-  apply_rect<false, T>(s, L.R, r, C.b.as<T>());
+  apply_rect<false, T>(s, L.R, r, C.b.as<T>(), L.lpr_r);
   vcycle_t<T>(s, l + 1, C.b.as<T>(), C.x.as<T>());
-  apply_rect<true, T>(s, L.P, C.x.as<T>(), x1);
+  apply_rect<true, T>(s, L.P, C.x.as<T>(), x1, L.lpr_p);
   return smooth<T>(s, L, b, x1, x, xa, xb, dot);
 }
 
@@ -826,6 +826,8 @@ void power_estimate(ppe_solver* s, Level& L, uint32_t salt, int iters, double sc
 void prepare_solve_levels(ppe_solver* s) {
   for (int l = 0; l < s->nlev; ++l) {
     Level& L = s->levels[l];
+    L.lpr_a = L.lpr_r = L.lpr_p = 0;
+    L.fuse0 = true;
     const int n = L.n > 0 ? L.n : 1;
     L.x.get<double>(n);
     L.b.get<double>(n);
@@ -1115,6 +1117,108 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
                      restart, cnt);
   PPE_LAUNCH_CHECK();
   return finish(PPE_NOT_CONVERGED);
+}
+
+
+namespace {
+
+// Mean duration of launch() over reps dispatches on the solver stream, after
+// one untimed dispatch.
+template <class F>
+float time_launches(ppe_solver* s, F&& launch, int reps = 3) {
+  if (!s->tev0) {
+    PPE_HIP(hipEventCreate(&s->tev0));
+    PPE_HIP(hipEventCreate(&s->tev1));
+  }
+  launch();
+  PPE_HIP(hipEventRecord(s->tev0, s->stream));
+  for (int k = 0; k < reps; ++k) launch();
+  PPE_HIP(hipEventRecord(s->tev1, s->stream));
+  PPE_HIP(hipEventSynchronize(s->tev1));
+  float ms = 0.f;
+  PPE_HIP(hipEventElapsedTime(&ms, s->tev0, s->tev1));
+  return ms / reps;
+}
+
+constexpr int kLprs[] = {4, 8, 16, 32, 64};
+
+// The fastest lanes-per-row choice for a CSR operator of mean row length
+// mean (candidates from a quarter of the rule's choice up to 64).
+template <class F>
+int best_lpr(ppe_solver* s, const Csr& M, F&& run) {
+  const int rule = lanes_for(M);
+  int best = rule;
+  float tbest = 1e30f;
+  for (int c : kLprs) {
+    if (c * 4 < rule) continue;
+    const float t = time_launches(s, [&]() { run(c); });
+    if (t < tbest) { tbest = t; best = c; }
+  }
+  return best;
+}
+
+// Tune one level's choices in value type T (the V-cycle's type).  Operands
+// are the level's work vectors; their contents do not affect the timings.
+template <class T>
+void tune_level(ppe_solver* s, int l) {
+  Level& L = s->levels[l];
+  const bool coarsest = l == s->nlev - 1;
+  if (L.n == 0 || (coarsest && L.dense)) return;
+  T* x = L.x.as<T>();
+  T* b = L.b.as<T>();
+  T* d = L.d.as<T>();
+  T* y = L.x2.as<T>();
+  const double c1 = L.c1.empty() ? 0.0 : L.c1[0], c2 = L.c1.empty() ? L.inv_theta : L.c2[0];
+  if (l > 0)
+    L.lpr_a = best_lpr(s, L.A, [&](int c) {
+      L.lpr_a = c;
+      apply_op<E_CHEB, T>(s, L, x, b, d, c1, c2, y, nullptr);
+    });
+  if (!L.c1.empty()) {
+    const float fused = time_launches(s, [&]() {
+      apply_op<E_CHEB0, T>(s, L, nullptr, b, d, c1, c2, y, nullptr, nullptr, 0, L.inv_theta);
+    });
+    const float split = time_launches(s, [&]() {
+      hipLaunchKernelGGL(k_cheb_first<T>, dim3(grid_for(L.n)), dim3(kBlock), 0, s->stream, L.n, b,
+                         LevelData<T>::diag(L), (T)L.inv_theta, d, x);
+      apply_op<E_CHEB, T>(s, L, x, b, d, c1, c2, y, nullptr);
+    });
+    L.fuse0 = fused <= split;
+  }
+  if (coarsest) return;
+  Level& C = s->levels[l + 1];
+  L.lpr_r = best_lpr(s, L.R, [&](int c) {
+    apply_rect<false, T>(s, L.R, L.r.as<T>(), C.b.as<T>(), c);
+  });
+  L.lpr_p = best_lpr(s, L.P, [&](int c) {
+    apply_rect<true, T>(s, L.P, C.x.as<T>(), L.t.as<T>(), c);
+  });
+}
+
+}  // namespace
+
+void autotune_levels(ppe_solver* s) {
+  const bool f32 = s->opt.precision == PPE_MIXED;
+  for (int l = 0; l < s->nlev; ++l) {
+    Level& L = s->levels[l];
+    // shapes within a quarter octave of rows and of entries share choices, so
+    // a slowly changing active set rarely triggers a new tuning
+    auto bin = [](double v) { return (int)std::lround(4.0 * std::log2(v > 1.0 ? v : 1.0)); };
+    const std::array<int, 4> key{l, f32 ? 1 : 0, bin(L.n), bin((double)L.A.nnz)};
+    auto it = s->tune_cache.find(key);
+    if (it != s->tune_cache.end()) {
+      L.lpr_a = it->second[0];
+      L.fuse0 = it->second[1] != 0;
+      L.lpr_r = it->second[2];
+      L.lpr_p = it->second[3];
+      continue;
+    }
+    if (f32)
+      tune_level<float>(s, l);
+    else
+      tune_level<double>(s, l);
+    s->tune_cache[key] = {L.lpr_a, L.fuse0 ? 1 : 0, L.lpr_r, L.lpr_p};
+  }
 }
 
 }  // namespace ppe
