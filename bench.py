@@ -191,15 +191,19 @@ def leg_summary(rec, K, base=None):
 
 def counter_traffic(workload):
     """Bytes per launch of the roofline kernel from the committed memory
-    counter summary, or None when the kernel source changed since."""
+    counter summary, or None when the kernel's source region (its operand,
+    epilogue and row helpers and the kernel) changed since."""
     import hashlib
 
     try:
         with open(os.path.join(ROOT, "profiles", "roofline_traffic.json")) as f:
             data = json.load(f)
-        with open(os.path.join(ROOT, data["source_file"]), "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest() != data["source_sha256"]:
-                return None
+        with open(os.path.join(ROOT, data["source_file"])) as f:
+            text = f.read()
+        begin, end = data["source_region"]
+        region = text[text.index(begin):text.index(end)]
+        if hashlib.sha256(region.encode()).hexdigest() != data["source_sha256"]:
+            return None
         return data[workload]["bytes_per_launch"]
     except (OSError, KeyError, ValueError):
         return None
