@@ -121,7 +121,11 @@ ppe_status ppe_set_mesh(ppe_solver* s, int32_t n_cells, int32_t n_faces,
 ppe_status ppe_assemble(ppe_solver* s, const double* face_coeff,
                         const double* liquid_fraction);
 
-/* Solve A p = b' (Eq. 9 as modified in section 2.4.2).
+/* Solve A p = b' (Eq. 9 as modified in section 2.4.2) by conjugate gradients
+ * preconditioned with one V-cycle per iteration (section 2.5), until the
+ * recomputed true residual meets rtol ||b'||.  With PPE_MIXED the V-cycle
+ * runs on the FP32 hierarchy and the iteration is flexible CG with one stored
+ * direction (alpha = r.p / p.Ap, beta = -z.Ap / p.Ap), all in FP64.
  * rhs[n_cells]: entries of removed cells are ignored, pins are replaced by 0.
  * p[n_cells]: in: initial guess if use_x0 != 0; out: pressure, exactly 0 on
  * removed cells and pins.  stats: host pointer, may be NULL.
