@@ -819,8 +819,12 @@ static void spgemm_launch(ppe_solver* s, const SpConfig& c, const Csr& A, const 
 // to fill a quarter of them) take one pass with a slot per column into
 // fixed-stride scratch rows and a compaction;
 // wider ones count each row's distinct columns with a hash sized from the
-// product bound, then fill C with a hash sized from the largest count.
-void spgemm(ppe_solver* s, const Csr& A, const Csr& B, Csr& C) {
+// product bound, then fill C with a hash sized from the largest count.  The
+// product bound is maxrow(A) maxrow(B) when both are known on the host, else
+// a bound pass reads it back.  C.maxrow is set to C's longest row.  extra: a
+// device int read back in the same round trip as C's size (extra_host).
+void spgemm(ppe_solver* s, const Csr& A, const Csr& B, Csr& C, const int* extra,
+            int* extra_host) {
   require(A.m == B.n, PPE_ERR_INTERNAL, "spgemm shape mismatch");
   C.n = A.n;
   C.m = B.m;
@@ -835,15 +839,17 @@ void spgemm(ppe_solver* s, const Csr& A, const Csr& B, Csr& C) {
   long long total = 0;
   int fm[2] = {0, 0};
   auto fetch_scan = [&](bool with_max) {
-    exclusive_scan_async(s, counts, crp, C.n);
+    const long long* dtotal = exclusive_scan_async(s, counts, crp, C.n);
     if (with_max) max_int_async(s, counts, C.n, flag + 1);
-    PPE_HIP(hipMemcpyAsync(&total, s->tmp_l[0].as<long long>() + scan_blocks(C.n),
-                           sizeof(long long), hipMemcpyDeviceToHost, s->stream));
+    PPE_HIP(hipMemcpyAsync(&total, dtotal, sizeof(long long), hipMemcpyDeviceToHost, s->stream));
     PPE_HIP(hipMemcpyAsync(fm, flag, sizeof(int) * 2, hipMemcpyDeviceToHost, s->stream));
+    if (extra)
+      PPE_HIP(hipMemcpyAsync(extra_host, extra, sizeof(int), hipMemcpyDeviceToHost, s->stream));
     PPE_HIP(hipStreamSynchronize(s->stream));
     require(fm[0] == 0, PPE_ERR_INTERNAL, "sparse product row overflowed its hash table");
     require(total <= INT32_MAX, PPE_ERR_INTERNAL, "sparse product too large for int32 indices");
     C.nnz = total;
+    C.maxrow = fm[1];
   };
   fill_int(s, flag, 0, 2);
 
@@ -861,19 +867,24 @@ void spgemm(ppe_solver* s, const Csr& A, const Csr& B, Csr& C) {
     int* sci = s->sp_ci.get<int>(cap);
     double* sv = s->sp_v.get<double>(cap);
     spgemm_launch<SP_DENSE>(s, c, A, B, off, counts, sci, sv, flag);
-    fetch_scan(false);
+    fetch_scan(true);
     int* cci = C.col.get<int>(C.nnz);
     double* cv = C.val.get<double>(C.nnz);
     PPE_ROWS(lanes_for(B), k_spgemm_compact, C.n, C.n, off, crp, sci, sv, cci, cv);
     return;
   }
 
-  int* prod = s->sp_prod.get<int>(C.n + 1);
-  PPE_ROWS(lanes_for(A), k_spgemm_bound, C.n, C.n, A.rp(), A.ci(), B.rp(), prod);
-  max_int_async(s, prod, C.n, flag + 1);
-  PPE_HIP(hipMemcpyAsync(fm, flag, sizeof(int) * 2, hipMemcpyDeviceToHost, s->stream));
-  PPE_HIP(hipStreamSynchronize(s->stream));
-  const int ub = std::min(fm[1], C.m);
+  int ub;
+  if (A.maxrow > 0 && B.maxrow > 0) {
+    ub = (int)std::min<int64_t>((int64_t)A.maxrow * B.maxrow, C.m);
+  } else {
+    int* prod = s->sp_prod.get<int>(C.n + 1);
+    PPE_ROWS(lanes_for(A), k_spgemm_bound, C.n, C.n, A.rp(), A.ci(), B.rp(), prod);
+    max_int_async(s, prod, C.n, flag + 1);
+    PPE_HIP(hipMemcpyAsync(fm, flag, sizeof(int) * 2, hipMemcpyDeviceToHost, s->stream));
+    PPE_HIP(hipStreamSynchronize(s->stream));
+    ub = std::min(fm[1], C.m);
+  }
   int Hc = 32;
   while (Hc < 2 * ub && Hc < 8192) Hc *= 2;
   const SpConfig cc = spgemm_config(s, A, B, SP_COUNT, Hc);
@@ -887,10 +898,12 @@ void spgemm(ppe_solver* s, const Csr& A, const Csr& B, Csr& C) {
   spgemm_launch<SP_FILL>(s, cf, A, B, crp, nullptr, cci, cv, flag);
 }
 
+// T = A^T with sorted rows; *s->rmax receives T's longest row (device int).
 void transpose(ppe_solver* s, const Csr& A, Csr& T) {
   T.n = A.m;
   T.m = A.n;
   T.nnz = A.nnz;
+  T.maxrow = 0;
   int* cnt = s->tmp_i[0].get<int>(T.n + 1);
   fill_int(s, cnt, 0, T.n + 1);
   if (A.nnz) {
@@ -899,6 +912,7 @@ void transpose(ppe_solver* s, const Csr& A, Csr& T) {
     PPE_LAUNCH_CHECK();
   }
   int* trp = T.rowptr.get<int>(T.n + 1);
+  max_int_async(s, cnt, T.n, s->rmax.get<int>(1));
   exclusive_scan_async(s, cnt, trp, T.n);  // the total is A.nnz
   int* cursor = s->tmp_i[1].get<int>(T.n + 1);
   PPE_HIP(hipMemcpyAsync(cursor, trp, sizeof(int) * (T.n + 1), hipMemcpyDeviceToDevice, s->stream));
@@ -974,7 +988,8 @@ void build_hierarchy(ppe_solver* s) {
       // rounds run in triples between host checks; a round after the set is
       // complete changes nothing, so only the last count is read
       int* und = s->tmp_i[3].get<int>(1);
-      for (int batch = 6;; batch = 3) {  // six rounds before the first check
+      // as many rounds before the first check as this level needed last time
+      for (int batch = std::max(3, L.mis_batch);; batch = 3) {
         for (int k = 0; k < batch; ++k) {
           if (k == batch - 1) fill_int(s, und, 0, 1);
           PPE_ROWS(lpr, k_mis_max1, n, n, L.A.rp(), L.A.ci(), strong, st, salt, m1);
@@ -985,6 +1000,7 @@ void build_hierarchy(ppe_solver* s) {
         if (read_scalar(s, und) == 0) break;
         require(L.mis_rounds < 10000, PPE_ERR_INTERNAL, "MIS-2 did not terminate");
       }
+      L.mis_batch = L.mis_rounds;
       int* root = s->tmp_i[2].get<int>(n + 1);
       hipLaunchKernelGGL(k_is_root, dim3(g), dim3(kBlock), 0, s->stream, n, st, root);
       PPE_LAUNCH_CHECK();
@@ -1028,6 +1044,7 @@ void build_hierarchy(ppe_solver* s) {
         Csr& Pt = L0.Pt;
         Pt.n = n;
         Pt.m = na;
+        Pt.maxrow = 1;
         int* ptrp = Pt.rowptr.get<int>(n + 1);
         exclusive_scan_async(s, pcnt, ptrp, n);
         Pt.nnz = n;  // capacity (an upper bound): only the row pointers are read
@@ -1035,11 +1052,12 @@ void build_hierarchy(ppe_solver* s) {
                            Pt.col.get<int>(Pt.nnz), Pt.val.get<double>(Pt.nnz));
         PPE_LAUNCH_CHECK();
         // smoothed prolongator
-        spgemm(s, L0.A, Pt, L0.Q);
+        spgemm(s, L0.A, Pt, L0.Q, nullptr, nullptr);
         Csr& P = L0.P;
         P.n = n;
         P.m = na;
         P.nnz = L0.Q.nnz;
+        P.maxrow = L0.Q.maxrow;
         hipLaunchKernelGGL(k_smooth_p, dim3(g), dim3(kBlock), 0, s->stream, n, L0.Q.rp(), L0.Q.ci(),
                            L0.Q.v(), L0.diag.as<double>(), agg, pt, rho_dev + lvl,
                            P.val.get<double>(P.nnz));
@@ -1048,8 +1066,8 @@ void build_hierarchy(ppe_solver* s) {
         std::swap(P.rowptr, L0.Q.rowptr);
         std::swap(P.col, L0.Q.col);
         transpose(s, P, L0.R);
-        spgemm(s, L0.A, P, L0.AP);
-        spgemm(s, L0.R, L0.AP, C.A);
+        spgemm(s, L0.A, P, L0.AP, s->rmax.as<int>(), &L0.R.maxrow);
+        spgemm(s, L0.R, L0.AP, C.A, nullptr, nullptr);
         C.n = na;
         s->nlev = lvl + 2;
         continue;

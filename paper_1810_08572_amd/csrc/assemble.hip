@@ -267,24 +267,23 @@ __global__ void k_gather_int(int n, const int* __restrict__ idx, const int* __re
 // Reduction tiles: runs of at most 4096 compact rows that never cross a
 // segment boundary; tile t covers rows [r0[t], r1[t]) of segment seg[t], and
 // segment s owns tiles [seg_tile_ptr[s], seg_tile_ptr[s+1]).
+// Reduction tiles over the compact rows of every segment (s->seg_row_off
+// must hold the segments' compact row offsets): about kRedBlocks tiles over
+// the whole system, 256..4096 rows each, none crossing a segment.  The host
+// tables are kept in the solver, so their uploads need no synchronisation.
 void build_tiles(ppe_solver* s) {
   const int ns = s->n_seg;
-  int* d_off = s->tmp_i[0].get<int>(ns + 1);
-  int* d_row = s->tmp_i[1].get<int>(ns + 1);
-  PPE_HIP(hipMemcpyAsync(d_off, s->seg_cell_off.data(), sizeof(int) * (ns + 1),
-                         hipMemcpyHostToDevice, s->stream));
-  hipLaunchKernelGGL(k_gather_int, dim3(grid_for(ns + 1)), dim3(kBlock), 0, s->stream, ns + 1, d_off,
-                     s->rowpos.as<int>(), d_row);
-  PPE_LAUNCH_CHECK();
-  s->seg_row_off.assign(ns + 1, 0);
-  PPE_HIP(hipMemcpyAsync(s->seg_row_off.data(), d_row, sizeof(int) * (ns + 1),
-                         hipMemcpyDeviceToHost, s->stream));
-  PPE_HIP(hipStreamSynchronize(s->stream));
-  // about kRedBlocks tiles over the whole system, 256..4096 rows each
   const int na = s->seg_row_off[ns];
   int rows = ((na / kRedBlocks + 255) / 256) * 256;
   rows = std::min(std::max(rows, 256), 4096);
-  std::vector<int> r0, r1, sg, tp(ns + 1, 0);
+  std::vector<int>& r0 = s->tile_h[0];
+  std::vector<int>& r1 = s->tile_h[1];
+  std::vector<int>& sg = s->tile_h[2];
+  std::vector<int>& tp = s->tile_h[3];
+  r0.clear();
+  r1.clear();
+  sg.clear();
+  tp.assign(ns + 1, 0);
   for (int q = 0; q < ns; ++q) {
     tp[q] = (int)r0.size();
     for (int a = s->seg_row_off[q]; a < s->seg_row_off[q + 1]; a += rows) {
@@ -306,7 +305,6 @@ void build_tiles(ppe_solver* s) {
     PPE_HIP(hipMemcpyAsync(c, sg.data(), sizeof(int) * sg.size(), hipMemcpyHostToDevice, s->stream));
   }
   PPE_HIP(hipMemcpyAsync(d, tp.data(), sizeof(int) * (ns + 1), hipMemcpyHostToDevice, s->stream));
-  PPE_HIP(hipStreamSynchronize(s->stream));  // host vectors above go out of scope
 }
 
 // flag faces whose two owners lie in different samples
@@ -385,16 +383,13 @@ void build_topology(ppe_solver* s, const int32_t* owner, const int32_t* neigh) {
 }
 
 void assemble_fine(ppe_solver* s, const double* coeff, const double* fl) {
-  const int nc = s->n_cells, nf = s->n_faces;
+  const int nc = s->n_cells, nf = s->n_faces, ns = s->n_seg;
   int* flag = s->flag.get<int>(1);
   fill_int(s, flag, 0, 1);
   int g = grid_for(nf > nc ? nf : nc);
   hipLaunchKernelGGL(k_check_fields, dim3(g), dim3(kBlock), 0, s->stream, coeff, s->neigh.as<int>(),
                      nf, fl, nc, flag);
   PPE_LAUNCH_CHECK();
-  int bad = read_scalar(s, flag);
-  require(!(bad & 1), PPE_ERR_ARG, "face coefficient must be finite and > 0 on interior faces");
-  require(!(bad & 2), PPE_ERR_ARG, "liquid fraction must be finite and in [0, 1]");
 
   int* active = s->active.get<int>(nc);
   int* parent = s->parent.get<int>(nc);
@@ -402,7 +397,25 @@ void assemble_fine(ppe_solver* s, const double* coeff, const double* fl) {
   int* rowpos = s->rowpos.get<int>(nc + 1);
   hipLaunchKernelGGL(k_active, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, fl, nc, active, parent);
   PPE_LAUNCH_CHECK();
-  const int na = (int)exclusive_scan(s, active, rowpos, nc);
+  exclusive_scan_async(s, active, rowpos, nc);  // rowpos[nc] = number of active cells
+  // compact row offsets of the segments: rowpos at their first cells
+  int* d_off = s->tmp_i[0].get<int>(ns + 1);
+  int* d_row = s->tmp_i[1].get<int>(ns + 1);
+  PPE_HIP(hipMemcpyAsync(d_off, s->seg_cell_off.data(), sizeof(int) * (ns + 1),
+                         hipMemcpyHostToDevice, s->stream));
+  hipLaunchKernelGGL(k_gather_int, dim3(grid_for(ns + 1)), dim3(kBlock), 0, s->stream, ns + 1, d_off,
+                     rowpos, d_row);
+  PPE_LAUNCH_CHECK();
+  // one read-back: the field checks and the segments' row offsets
+  int bad = 0;
+  s->seg_row_off.assign(ns + 1, 0);
+  PPE_HIP(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+  PPE_HIP(hipMemcpyAsync(s->seg_row_off.data(), d_row, sizeof(int) * (ns + 1),
+                         hipMemcpyDeviceToHost, s->stream));
+  PPE_HIP(hipStreamSynchronize(s->stream));
+  require(!(bad & 1), PPE_ERR_ARG, "face coefficient must be finite and > 0 on interior faces");
+  require(!(bad & 2), PPE_ERR_ARG, "liquid fraction must be finite and in [0, 1]");
+  const int na = s->seg_row_off[ns];
   s->n_active = na;
   int* perm = s->perm.get<int>(na);
   hipLaunchKernelGGL(k_compact, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, active, nc, rowpos,
@@ -428,19 +441,23 @@ void assemble_fine(ppe_solver* s, const double* coeff, const double* fl) {
   hipLaunchKernelGGL(k_components, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, active, nc,
                      parent, comp, is_pin);
   PPE_LAUNCH_CHECK();
-  {
-    int* tmp = s->tmp_i[1].get<int>(nc + 1);
-    s->n_comp = (int)exclusive_scan(s, is_pin, tmp, nc);
-  }
+  // the pocket count is read back with the matrix size below
+  const long long* d_ncomp =
+      exclusive_scan_async(s, is_pin, s->tmp_i[3].get<int>(nc + 1), nc, 1);
 
   if (s->levels.empty()) s->levels.resize(1);
   s->nlev = 1;
   Level& L = s->levels[0];
   L.n = na;
   L.A.n = L.A.m = na;
+  L.A.maxrow = s->max_deg + 1;  // a row holds its open faces and the diagonal
   L.W = s->max_deg;
+  long long tot[2] = {0, 0};
   if (na == 0) {
     L.A.nnz = 0;
+    PPE_HIP(hipMemcpyAsync(&tot[1], d_ncomp, sizeof(long long), hipMemcpyDeviceToHost, s->stream));
+    PPE_HIP(hipStreamSynchronize(s->stream));
+    s->n_comp = (int)tot[1];
     return;
   }
   int* counts = s->tmp_i[0].get<int>(na + 1);
@@ -448,7 +465,12 @@ void assemble_fine(ppe_solver* s, const double* coeff, const double* fl) {
                      s->adj_ptr.as<int>(), s->adj_nbr.as<int>(), active, is_pin, counts);
   PPE_LAUNCH_CHECK();
   int* rowptr = L.A.rowptr.get<int>(na + 1);
-  L.A.nnz = exclusive_scan(s, counts, rowptr, na);
+  const long long* d_nnz = exclusive_scan_async(s, counts, rowptr, na, 0);
+  PPE_HIP(hipMemcpyAsync(&tot[0], d_nnz, sizeof(long long), hipMemcpyDeviceToHost, s->stream));
+  PPE_HIP(hipMemcpyAsync(&tot[1], d_ncomp, sizeof(long long), hipMemcpyDeviceToHost, s->stream));
+  PPE_HIP(hipStreamSynchronize(s->stream));
+  L.A.nnz = tot[0];
+  s->n_comp = (int)tot[1];
   int* col = L.A.col.get<int>(L.A.nnz);
   double* val = L.A.val.get<double>(L.A.nnz);
   double* diag = L.diag.get<double>(na);

@@ -80,6 +80,7 @@ struct DevBuf {
 struct Csr {
   int n = 0, m = 0;   // rows, columns
   int64_t nnz = 0;
+  int maxrow = 0;     // host-known bound on a row's length (0: unknown)
   DevBuf rowptr, col, val, valf;  // valf: FP32 copy of val (mixed precision)
   int* rp() const { return rowptr.as<int>(); }
   int* ci() const { return col.as<int>(); }
@@ -109,6 +110,7 @@ struct Level {
   double inv_theta = 0.0;
   std::vector<double> c1, c2;  // Chebyshev steps 2..degree
   int mis_rounds = 0;
+  int mis_batch = 6;     // MIS-2 rounds before the first check (last assembly's count)
   Csr Pt, Q, AP;         // setup scratch: tentative P, A*P_tent, A*P
   DevBuf strong, state, state2, m1, mis_root, agg1, agg_ptr, agg_mem, pt;
   // coarsest level
@@ -150,6 +152,7 @@ struct ppe_solver {
   int n_seg = 1;
   std::vector<int> seg_cell_off{0, 0};  // host, n_seg + 1
   std::vector<int> seg_row_off;         // host, compact rows, n_seg + 1
+  std::vector<int> tile_h[4];           // host copies of the tile tables (kept for async uploads)
   int n_tiles = 0;
   ppe::DevBuf tile_r0, tile_r1, tile_seg, seg_tile_ptr;  // reduction tiles
   ppe::DevBuf seg_sc, seg_done, tpart;                   // per-segment scalars, tile partials
@@ -167,6 +170,7 @@ struct ppe_solver {
   // setup results read back once per hierarchy: the spectral bound of every
   // level (doubles [0, max_levels)), then the deferred setup error bits (int)
   ppe::DevBuf setup_out;
+  ppe::DevBuf rmax;  // max column count of the last transposed operator (device int)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t tev0 = nullptr, tev1 = nullptr;  // autotuner timing
   // autotuner choices per (level, FP32, quarter-octave bins of rows and of
@@ -347,7 +351,9 @@ inline int grid_for(int64_t n, int bs = kBlock) {
 int64_t exclusive_scan(ppe_solver* s, const int* in, int* out, int n);
 // The same without reading the total back: the total stays at
 // tmp_l[0] + scan_blocks(n) (a long long) for the caller to fetch.
-void exclusive_scan_async(ppe_solver* s, const int* in, int* out, int n);
+// Returns the device address of the total (a long long in tmp_l[slot], slot
+// 0 or 1, valid until the next scan through that slot).
+long long* exclusive_scan_async(ppe_solver* s, const int* in, int* out, int n, int slot = 0);
 int scan_blocks(int n);
 // *out = max of in[0..n) on the device (no host read)
 void max_int_async(ppe_solver* s, const int* in, int n, int* out);

@@ -110,10 +110,10 @@ int scan_blocks(int n) {
   return nb < 1 ? 1 : nb;
 }
 
-void exclusive_scan_async(ppe_solver* s, const int* in, int* out, int n) {
+long long* exclusive_scan_async(ppe_solver* s, const int* in, int* out, int n, int slot) {
   if (n < 0) throw Error(PPE_ERR_INTERNAL, "negative scan length");
   const int nb = scan_blocks(n);
-  long long* bsum = s->tmp_l[0].get<long long>(nb + 1);
+  long long* bsum = s->tmp_l[slot].get<long long>(nb + 1);
   long long* total = bsum + nb;
   hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s->stream, in, n, bsum);
   PPE_LAUNCH_CHECK();
@@ -121,6 +121,7 @@ void exclusive_scan_async(ppe_solver* s, const int* in, int* out, int n) {
   PPE_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kBlock), 0, s->stream, in, n, bsum, total, out);
   PPE_LAUNCH_CHECK();
+  return total;
 }
 
 int64_t exclusive_scan(ppe_solver* s, const int* in, int* out, int n) {
