@@ -76,7 +76,7 @@ def _face_nodes(cells_ijk, axis, plane_offset, nshape, reverse):
 
 
 def box_mesh(shape, lengths=(1.0, 1.0, 1.0), jitter=0.1, seed=0, mode="node",
-             keep=None, origin=(0.0, 0.0, 0.0)) -> HexMesh:
+             keep=None, origin=(0.0, 0.0, 0.0), affine=None) -> HexMesh:
     """Hex mesh of a logical block, stored as an unstructured face list.
 
     shape   : (mx, my, mz) cells of the logical block.
@@ -89,6 +89,9 @@ def box_mesh(shape, lengths=(1.0, 1.0, 1.0), jitter=0.1, seed=0, mode="node",
               None    - no jitter.
     keep    : optional bool [mx, my, mz]; cells left out are not meshed and
               their faces towards kept cells become walls.
+    affine  : optional 3x3 matrix applied to every node after the jitter
+              (x -> affine @ x), e.g. a shear that makes a uniform mesh
+              non-orthogonal while keeping its cells affine images of cubes.
     Cells are numbered in the order c = i + mx*(j + my*k) among kept cells.
     """
     mx, my, mz = (int(s) for s in shape)
@@ -113,6 +116,8 @@ def box_mesh(shape, lengths=(1.0, 1.0, 1.0), jitter=0.1, seed=0, mode="node",
     elif mode not in ("node", "plane", None):
         raise ValueError(f"unknown jitter mode {mode!r}")
     nodes = P.reshape(-1, 3, order="F")  # node id = i + nx*(j + ny*k)
+    if affine is not None:
+        nodes = nodes @ np.asarray(affine, dtype=np.float64).T
 
     if keep is None:
         keep = np.ones((mx, my, mz), dtype=bool)
@@ -177,10 +182,15 @@ def box_mesh(shape, lengths=(1.0, 1.0, 1.0), jitter=0.1, seed=0, mode="node",
     inner = neigh >= 0
     vol -= np.bincount(neigh[inner], weights=flux[inner], minlength=n_cells)
 
-    return HexMesh(n_cells=n_cells, owner=owner, neigh=neigh, face_area=face_area,
-                   face_centre=face_centre, cell_centre=cell_centre, cell_volume=vol,
-                   nodes=nodes, grid_index=cells_ijk.astype(np.int32),
-                   shape=(mx, my, mz), spacing=tuple(h.tolist()))
+    out = HexMesh(n_cells=n_cells, owner=owner, neigh=neigh, face_area=face_area,
+                  face_centre=face_centre, cell_centre=cell_centre, cell_volume=vol,
+                  nodes=nodes, grid_index=cells_ijk.astype(np.int32),
+                  shape=(mx, my, mz), spacing=tuple(h.tolist()))
+    # vertex lists: a face's V1..V4 (V1->V3 and V2->V4 are its diagonals) and
+    # a cell's eight corners
+    out.extra["face_nodes"] = fn.astype(np.int32)
+    out.extra["cell_nodes"] = cn.astype(np.int32)
+    return out
 
 
 def plate_with_ribs_mesh(h=2.0e-3 / 3.0, plate=(240, 144, 36), rib_cells=8,
@@ -208,6 +218,7 @@ def concat_meshes(meshes):
     face_off = np.zeros(len(meshes) + 1, dtype=np.int64)
     node_off = 0
     owners, neighs, fa, fc, cc, cv, nodes, gi = [], [], [], [], [], [], [], []
+    fnodes, cnodes = [], []
     for s, m in enumerate(meshes):
         c0 = cell_off[s]
         owners.append(m.owner.astype(np.int64) + c0)
@@ -219,6 +230,9 @@ def concat_meshes(meshes):
         cv.append(m.cell_volume)
         nodes.append(m.nodes)
         gi.append(m.grid_index)
+        if "face_nodes" in m.extra:
+            fnodes.append(m.extra["face_nodes"].astype(np.int64) + node_off)
+            cnodes.append(m.extra["cell_nodes"].astype(np.int64) + node_off)
         node_off += m.nodes.shape[0]
         cell_off[s + 1] = c0 + m.n_cells
         face_off[s + 1] = face_off[s] + m.n_faces
@@ -233,6 +247,9 @@ def concat_meshes(meshes):
                   shape=None, spacing=None)
     out.extra["cell_offsets"] = cell_off
     out.extra["face_offsets"] = face_off
+    if len(fnodes) == len(meshes):
+        out.extra["face_nodes"] = np.concatenate(fnodes).astype(np.int32)
+        out.extra["cell_nodes"] = np.concatenate(cnodes).astype(np.int32)
     return out
 
 
