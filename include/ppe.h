@@ -159,6 +159,63 @@ ppe_status ppe_get_segment_stats(const ppe_solver* s, int32_t* iterations, doubl
  * and rel_residual are the maxima over the samples. */
 ppe_status ppe_get_stats(const ppe_solver* s, ppe_stats* stats);
 
+/* ---- Pressure-correction step with cross diffusion (sections 2.3, 2.4.2,
+ * 2.4.3). ----
+ * The full discretisation of the face normal gradient (Eq. 11): the direct
+ * term c_f (p_C2 - p_C1) of the solved matrix plus the cross term
+ * t_f . grad(p)_f, t_f = S_f / rho - c_f d_f, with grad(p)_f reconstructed in
+ * the local frame C1C2, V1V3, V2V4 from vertex means of the cells around
+ * each vertex (Eq. 12).  Solid cells leave each face stencil with their
+ * coefficients spread equally over the remaining cells (case 2, Eq. 15-16);
+ * faces with a solid owner carry nothing (case 3). */
+
+/* Geometry of the mesh set by ppe_set_mesh (device arrays, copied):
+ * nodes[3 n_nodes] (x, y, z interleaved); face_nodes[4 n_faces] = V1..V4 of
+ * each face, ordered so that (V3 - V1) x (V4 - V2) / 2 = face_area, the area
+ * vector pointing from owner to neighbour (walls' entries must be valid
+ * indices but are not used); cell_nodes[8 n_cells], a cell's corners;
+ * cell_centre[3 n_cells]; face_area[3 n_faces].  Builds each interior face's
+ * gradient stencil over the cells sharing one of its vertices.
+ * Errors: PPE_ERR_STATE before ppe_set_mesh; PPE_ERR_ARG for an index out of
+ * range, a vertex repeated within a cell or shared by more than 16 cells, a
+ * face whose vertices are not corners of both its cells, or a degenerate
+ * local frame. */
+ppe_status ppe_set_geometry(ppe_solver* s, int32_t n_nodes, const double* nodes,
+                            const int32_t* face_nodes, const int32_t* cell_nodes,
+                            const double* cell_centre, const double* face_area);
+
+typedef struct {
+  int outer;             /* deferred-correction passes (one AMG-PCG solve each) */
+  int pcg_iterations;    /* PCG iterations summed over the passes */
+  double rel_residual;   /* ||b' + X p - L p|| / ||b'|| at exit, FP64 */
+  double ms;             /* wall time of the call */
+} ppe_project_stats;
+
+/* One pressure-correction step on the assembled system (Eq. 9 with both
+ * terms of Eq. 11, then Eq. 17 and Eq. 8):
+ *   F*_f = (u*_C1 + u*_C2)/2 . S_f on open faces, b'_i = -(1/dt) sum s_if F*_f;
+ *   (L - X) p = b' on the active cells, pinned as ppe_solve pins, solved by
+ *   deferred correction around the AMG-PCG solve of L (each pass solves
+ *   L delta = b' + X p - L p to a loose tolerance) until
+ *   ||b' + X p - L p|| <= rtol ||b'||;
+ *   flux[f] = F*_f - dt (c_f (p_C2 - p_C1) + t_f . grad(p)_f) on open faces,
+ *   0 on blocked and wall faces;
+ *   u[3 n_cells] = u* - (dt/rho) * (mean of the open faces' gradients) on
+ *   active cells (u* where a cell has no open face), 0 on removed cells.
+ * face_coeff must be the array given to ppe_assemble (c_f = |S_f|^2/(rho
+ * S_f.d) with the same rho).  ustar[3 n_cells]; p[n_cells] out (0 on
+ * removed cells and pins).  One sample only (ppe_set_segments with one
+ * sample).  Returns PPE_NOT_CONVERGED after 50 passes, PPE_ERR_STATE before
+ * ppe_assemble or ppe_set_geometry or with several samples, PPE_ERR_ARG. */
+ppe_status ppe_project(ppe_solver* s, const double* face_coeff, const double* ustar, double rho,
+                       double dt, double* p, double* flux, double* u, ppe_project_stats* stats);
+
+/* grad[3 n_faces] = masked face gradient of p[n_cells] (0 on blocked and
+ * wall faces) and cross[n_faces] = t_f . grad_f, as ppe_project uses them.
+ * Errors: PPE_ERR_STATE before ppe_assemble and ppe_set_geometry. */
+ppe_status ppe_face_gradient(ppe_solver* s, const double* face_coeff, double rho, const double* p,
+                             double* grad, double* cross);
+
 const char* ppe_status_string(ppe_status st);
 /* Detail of the last failure of this solver ("" if none).  NULL = global. */
 const char* ppe_last_error(const ppe_solver* s);
@@ -169,7 +226,9 @@ const char* ppe_last_error(const ppe_solver* s);
  * level or a NULL array. */
 
 /* Level sizes: rows, stored entries of A_l, entries of P_l (0 on the
- * coarsest level), aggregates (= rows of level l+1), and rho_l. */
+ * coarsest level), aggregates (= rows of level l+1), and rho_l, the spectral
+ * bound of D^-1 A_l used by the smoother and the prolongator smoothing (0 on
+ * a coarsest level solved through its explicit inverse, where neither runs). */
 ppe_status ppe_level_info(const ppe_solver* s, int level, int32_t* n_rows,
                           int64_t* nnz_a, int64_t* nnz_p, int32_t* n_agg,
                           double* rho);
@@ -195,6 +254,16 @@ ppe_status ppe_apply_matrix(ppe_solver* s, int level, const double* x, double* y
 
 /* z = M r: one V-cycle from level 0 with a zero initial guess (length n_active). */
 ppe_status ppe_apply_vcycle(ppe_solver* s, const double* r, double* z);
+
+/* Launch choices of level l's solve kernels, choice[4] (host): lanes per row
+ * of the coarse smoother, of the restriction and of the prolongation (0 = the
+ * fixed rule, else 4, 8, 16, 32 or 64), and 1 if the first two smoothing
+ * steps from a zero guess run fused, 0 if split.  The autotuner sets them at
+ * assembly; setting them by hand (until the next assembly) lets a test run
+ * every variant.  They never affect the hierarchy, only the solve's order of
+ * summation.  PPE_ERR_ARG for a value outside those sets. */
+ppe_status ppe_get_level_launch(const ppe_solver* s, int level, int32_t* choice);
+ppe_status ppe_set_level_launch(ppe_solver* s, int level, const int32_t* choice);
 
 /* ---- Learned warm start (not part of the paper's method). ----
  * A dense network n_in -> width (n_hidden SiLU layers) -> 1 (linear)

@@ -63,6 +63,18 @@ class ppe_stats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class ppe_project_stats(ctypes.Structure):
+    _fields_ = [
+        ("outer", ctypes.c_int),
+        ("pcg_iterations", ctypes.c_int),
+        ("rel_residual", ctypes.c_double),
+        ("ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 # symbol -> (restype, argtypes); the exported C ABI
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
@@ -87,6 +99,8 @@ _SIGS = {
     "ppe_apply_matrix": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
     "ppe_apply_vcycle": (ctypes.c_int, [_P, _P, _P]),
     "ppe_set_segments": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_I32)]),
+    "ppe_get_level_launch": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(_I32)]),
+    "ppe_set_level_launch": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(_I32)]),
     "ppe_get_segment_stats": (ctypes.c_int, [_P, ctypes.POINTER(_I32),
                                              ctypes.POINTER(ctypes.c_double)]),
     "ppe_mlp_create": (ctypes.c_int, [_I32, _I32, _I32, _P, ctypes.POINTER(_P)]),
@@ -103,6 +117,10 @@ _SIGS = {
                                                ctypes.POINTER(ctypes.c_double)]),
     "ppe_warm_start_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, _P]),
     "ppe_warm_start_targets": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, _P]),
+    "ppe_set_geometry": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P]),
+    "ppe_project": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_double, _P, _P, _P,
+                                   ctypes.POINTER(ppe_project_stats)]),
+    "ppe_face_gradient": (ctypes.c_int, [_P, _P, ctypes.c_double, _P, _P, _P]),
     "ppe_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "ppe_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double),
@@ -296,6 +314,51 @@ class Solver:
         self._chk(self._lib.ppe_get_stats(self._h, ctypes.byref(st)))
         return st.as_dict()
 
+    # ---- pressure-correction step with cross diffusion ----
+    def set_geometry(self, nodes, face_nodes, cell_nodes, cell_centre, face_area):
+        """nodes [n_nodes, 3] f64, face_nodes [n_faces, 4] i32 (V1..V4),
+        cell_nodes [n_cells, 8] i32, cell_centre [n_cells, 3] f64,
+        face_area [n_faces, 3] f64 (owner -> neighbour); device tensors."""
+        import torch
+
+        nn = nodes.numel() // 3
+        self._chk(self._lib.ppe_set_geometry(
+            self._h, int(nn), _dev_ptr(nodes, torch.float64, 3 * nn, "nodes"),
+            _dev_ptr(face_nodes, torch.int32, 4 * self.n_faces, "face_nodes"),
+            _dev_ptr(cell_nodes, torch.int32, 8 * self.n_cells, "cell_nodes"),
+            _dev_ptr(cell_centre, torch.float64, 3 * self.n_cells, "cell_centre"),
+            _dev_ptr(face_area, torch.float64, 3 * self.n_faces, "face_area")))
+
+    def project(self, face_coeff, ustar, rho, dt, allow_not_converged=False):
+        """One pressure-correction step; returns (p, flux, u, stats)."""
+        import torch
+
+        dev = ustar.device
+        p = torch.empty(self.n_cells, dtype=torch.float64, device=dev)
+        flux = torch.empty(max(self.n_faces, 1), dtype=torch.float64, device=dev)
+        u = torch.empty((self.n_cells, 3), dtype=torch.float64, device=dev)
+        st = ppe_project_stats()
+        allow = (PPE_OK, PPE_NOT_CONVERGED) if allow_not_converged else (PPE_OK,)
+        status = self._lib.ppe_project(
+            self._h, _dev_ptr(face_coeff, torch.float64, self.n_faces, "face_coeff"),
+            _dev_ptr(ustar, torch.float64, 3 * self.n_cells, "ustar"), float(rho), float(dt),
+            ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(flux.data_ptr()),
+            ctypes.c_void_p(u.data_ptr()), ctypes.byref(st))
+        self._chk(status, allow)
+        return p, flux[: self.n_faces], u, st.as_dict()
+
+    def face_gradient(self, face_coeff, rho, p):
+        """Masked face gradients [n_faces, 3] of p and the cross fluxes t_f.grad_f."""
+        import torch
+
+        g = torch.empty((max(self.n_faces, 1), 3), dtype=torch.float64, device=p.device)
+        x = torch.empty(max(self.n_faces, 1), dtype=torch.float64, device=p.device)
+        self._chk(self._lib.ppe_face_gradient(
+            self._h, _dev_ptr(face_coeff, torch.float64, self.n_faces, "face_coeff"), float(rho),
+            _dev_ptr(p, torch.float64, self.n_cells, "p"), ctypes.c_void_p(g.data_ptr()),
+            ctypes.c_void_p(x.data_ptr())))
+        return g[: self.n_faces], x[: self.n_faces]
+
     # ---- dominant-kernel measurement ----
     def profile(self, enable=True):
         self._chk(self._lib.ppe_profile_enable(self._h, int(enable)))
@@ -364,6 +427,16 @@ class Solver:
         self._chk(self._lib.ppe_apply_matrix(self._h, level, _dev_ptr(x, torch.float64, n, "x"),
                                              ctypes.c_void_p(y.data_ptr())))
         return y
+
+    def level_launch(self, level):
+        """(lanes smoother, lanes restriction, lanes prolongation, fused first step)."""
+        c = (_I32 * 4)()
+        self._chk(self._lib.ppe_get_level_launch(self._h, level, c))
+        return tuple(c)
+
+    def set_level_launch(self, level, choice):
+        c = (_I32 * 4)(*[int(v) for v in choice])
+        self._chk(self._lib.ppe_set_level_launch(self._h, level, c))
 
     def apply_vcycle(self, r):
         import torch

@@ -736,6 +736,100 @@ __global__ void __launch_bounds__(1024) k_dense_inverse_reg(int n, const double*
   }
 }
 
+// The same elimination for n <= 128 with a 2-D ownership: thread t owns the
+// 4 x 4 block of rows 4 (t / 32) .. +3 and columns 4 (t mod 32) .. +3 (the
+// 128 x 128 cover; entries past n are carried as throw-away values).  Per
+// step a thread reads four pivot-column and four pivot-row values from LDS
+// (double-buffered as above) and updates its block with 16 multiply-adds.
+__global__ void __launch_bounds__(1024) k_dense_inverse_blk(int n, const double* __restrict__ Gm,
+                                                            double* __restrict__ Ainv,
+                                                            int* __restrict__ flag) {
+  constexpr int B = 4;
+  __shared__ double colk[2][32 * B];
+  __shared__ double rowk[2][32 * B];
+  const int t = threadIdx.x;
+  const int i0 = (t / 32) * B, j0 = (t % 32) * B;
+  double a[B][B];
+#pragma unroll
+  for (int r = 0; r < B; ++r)
+#pragma unroll
+    for (int c = 0; c < B; ++c)
+      a[r][c] = (i0 + r < n && j0 + c < n) ? Gm[(size_t)(i0 + r) * 2 * n + j0 + c] : 0.0;
+  // publish column 0 and row 0
+  if (j0 == 0) {
+#pragma unroll
+    for (int r = 0; r < B; ++r) colk[0][i0 + r] = a[r][0];
+  }
+  if (i0 == 0) {
+#pragma unroll
+    for (int c = 0; c < B; ++c) rowk[0][j0 + c] = a[0][c];
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const int cb = k & 1, nb = cb ^ 1;
+    double piv = colk[cb][k];
+    if (!(piv > 0.0)) {
+      if (t == 0) atomicOr(flag, SE_DENSE);
+      piv = 1.0;
+    }
+    const double inv = 1.0 / piv;
+    double f[B], rk[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) f[r] = colk[cb][i0 + r];
+#pragma unroll
+    for (int c = 0; c < B; ++c) rk[c] = (j0 + c == k ? 1.0 : rowk[cb][j0 + c]) * inv;
+    if (j0 <= k && k < j0 + B) {  // a_ik is replaced by 0 before the update
+      const int ck = k - j0;
+#pragma unroll
+      for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int c = 0; c < B; ++c)
+          if (c == ck) a[r][c] = 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+      for (int c = 0; c < B; ++c) a[r][c] = fma(-f[r], rk[c], a[r][c]);
+    if (i0 <= k && k < i0 + B) {  // the pivot row becomes the scaled row
+      const int rk_ = k - i0;
+#pragma unroll
+      for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int c = 0; c < B; ++c)
+          if (r == rk_) a[r][c] = rk[c];
+    }
+    if (k + 1 < n) {
+      const int k1 = k + 1;
+      if (j0 <= k1 && k1 < j0 + B) {
+        const int c1 = k1 - j0;
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+          double v = a[r][0];
+#pragma unroll
+          for (int c = 1; c < B; ++c) v = c == c1 ? a[r][c] : v;
+          colk[nb][i0 + r] = v;
+        }
+      }
+      if (i0 <= k1 && k1 < i0 + B) {
+        const int r1 = k1 - i0;
+#pragma unroll
+        for (int c = 0; c < B; ++c) {
+          double v = a[0][c];
+#pragma unroll
+          for (int r = 1; r < B; ++r) v = r == r1 ? a[r][c] : v;
+          rowk[nb][j0 + c] = v;
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < B; ++r)
+#pragma unroll
+    for (int c = 0; c < B; ++c)
+      if (i0 + r < n && j0 + c < n) Ainv[(size_t)(i0 + r) * n + j0 + c] = a[r][c];
+}
+
 __global__ void k_densify(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                           const double* __restrict__ v, double* __restrict__ G) {
   int i = blockIdx.x * kBlock + threadIdx.x;
@@ -841,11 +935,12 @@ void spgemm(ppe_solver* s, const Csr& A, const Csr& B, Csr& C, const int* extra,
   auto fetch_scan = [&](bool with_max) {
     const long long* dtotal = exclusive_scan_async(s, counts, crp, C.n);
     if (with_max) max_int_async(s, counts, C.n, flag + 1);
-    PPE_HIP(hipMemcpyAsync(&total, dtotal, sizeof(long long), hipMemcpyDeviceToHost, s->stream));
-    PPE_HIP(hipMemcpyAsync(fm, flag, sizeof(int) * 2, hipMemcpyDeviceToHost, s->stream));
     if (extra)
-      PPE_HIP(hipMemcpyAsync(extra_host, extra, sizeof(int), hipMemcpyDeviceToHost, s->stream));
-    PPE_HIP(hipStreamSynchronize(s->stream));
+      read_back(s, {ReadItem{dtotal, sizeof(long long), &total},
+                    ReadItem{flag, sizeof(int) * 2, fm}, ReadItem{extra, sizeof(int), extra_host}});
+    else
+      read_back(s, {ReadItem{dtotal, sizeof(long long), &total},
+                    ReadItem{flag, sizeof(int) * 2, fm}});
     require(fm[0] == 0, PPE_ERR_INTERNAL, "sparse product row overflowed its hash table");
     require(total <= INT32_MAX, PPE_ERR_INTERNAL, "sparse product too large for int32 indices");
     C.nnz = total;
@@ -881,8 +976,7 @@ void spgemm(ppe_solver* s, const Csr& A, const Csr& B, Csr& C, const int* extra,
     int* prod = s->sp_prod.get<int>(C.n + 1);
     PPE_ROWS(lanes_for(A), k_spgemm_bound, C.n, C.n, A.rp(), A.ci(), B.rp(), prod);
     max_int_async(s, prod, C.n, flag + 1);
-    PPE_HIP(hipMemcpyAsync(fm, flag, sizeof(int) * 2, hipMemcpyDeviceToHost, s->stream));
-    PPE_HIP(hipStreamSynchronize(s->stream));
+    read_back(s, {ReadItem{flag, sizeof(int) * 2, fm}});
     ub = std::min(fm[1], C.m);
   }
   int Hc = 32;
@@ -966,15 +1060,23 @@ void build_hierarchy(ppe_solver* s) {
   for (int lvl = 0;; ++lvl) {
     Level& L = s->levels[lvl];
     const int n = L.n;
+    // setup kernels use the fixed launch rules: choices the autotuner made
+    // for the previous hierarchy would change the order of the power
+    // iteration's sums, and with it the spectral bound
+    L.lpr_a = L.lpr_r = L.lpr_p = 0;
+    L.fuse0 = true;
     if (lvl > 0 && n > 0) {
       PPE_ROWS(lanes_for(L.A), k_diag, n, n, L.A.rp(), L.A.ci(), L.A.v(), L.diag.get<double>(n),
                err);  // sets SE_DIAG
     }
-    spectral_bound(s, L, lvl, rho_dev + lvl);
     L.n_agg = 0;
     L.dense = false;
     L.mis_rounds = 0;
     const bool last = n <= s->opt.coarse_max || lvl == s->opt.max_levels - 1;
+    // a coarsest level solved by its explicit inverse runs no smoother and
+    // has no prolongator to smooth: its spectral bound is never used
+    if (last && n > 0 && n <= kDenseMax) fill_double(s, rho_dev + lvl, 0.0, 1);
+    else spectral_bound(s, L, lvl, rho_dev + lvl);
     if (!last) {
       const int g = grid_for(n);
       unsigned char* strong = L.strong.get<unsigned char>(L.A.nnz);
@@ -986,8 +1088,13 @@ void build_hierarchy(ppe_solver* s) {
                strong, st);
       const uint32_t salt = level_salt(lvl);
       // rounds run in triples between host checks; a round after the set is
-      // complete changes nothing, so only the last count is read
+      // complete changes nothing, so only the last count is read.  The roots
+      // are numbered before each check and their count read with it: the
+      // numbering is kept once no node is left undecided.
       int* und = s->tmp_i[3].get<int>(1);
+      int* root = s->tmp_i[2].get<int>(n + 1);
+      int* root_id = L.mis_root.get<int>(n + 1);
+      long long n_roots = 0;
       // as many rounds before the first check as this level needed last time
       for (int batch = std::max(3, L.mis_batch);; batch = 3) {
         for (int k = 0; k < batch; ++k) {
@@ -997,15 +1104,17 @@ void build_hierarchy(ppe_solver* s) {
           std::swap(st, st2);
           ++L.mis_rounds;
         }
-        if (read_scalar(s, und) == 0) break;
+        hipLaunchKernelGGL(k_is_root, dim3(g), dim3(kBlock), 0, s->stream, n, st, root);
+        PPE_LAUNCH_CHECK();
+        const long long* total = exclusive_scan_async(s, root, root_id, n);
+        int left = 0;
+        read_back(s, {ReadItem{und, sizeof(int), &left},
+                      ReadItem{total, sizeof(long long), &n_roots}});
+        if (left == 0) break;
         require(L.mis_rounds < 10000, PPE_ERR_INTERNAL, "MIS-2 did not terminate");
       }
       L.mis_batch = L.mis_rounds;
-      int* root = s->tmp_i[2].get<int>(n + 1);
-      hipLaunchKernelGGL(k_is_root, dim3(g), dim3(kBlock), 0, s->stream, n, st, root);
-      PPE_LAUNCH_CHECK();
-      int* root_id = L.mis_root.get<int>(n + 1);
-      const int na = (int)exclusive_scan(s, root, root_id, n);
+      const int na = (int)n_roots;
       if (na > 0) {
         int* agg1 = L.agg1.get<int>(n);
         int* agg = L.agg.get<int>(n);
@@ -1082,7 +1191,9 @@ void build_hierarchy(ppe_solver* s) {
       hipLaunchKernelGGL(k_densify, dim3(grid_for(n)), dim3(kBlock), 0, s->stream, n, L.A.rp(),
                          L.A.ci(), L.A.v(), G);
       PPE_LAUNCH_CHECK();
-      if (n <= 256) {
+      if (n <= 128) {
+        hipLaunchKernelGGL(k_dense_inverse_blk, dim3(1), dim3(1024), 0, s->stream, n, G, Ainv, err);
+      } else if (n <= 256) {
         // rows one thread owns; every FMA of the elimination stays in registers
         const int rows_per = (n + (1024 / n) - 1) / (1024 / n);
 #define PPE_DINV(E_)                                                                           \
@@ -1104,9 +1215,7 @@ void build_hierarchy(ppe_solver* s) {
   }
   // one read-back for the whole hierarchy: spectral bounds and error bits
   std::vector<double> out((size_t)maxlev + 1);
-  PPE_HIP(hipMemcpyAsync(out.data(), rho_dev, sizeof(double) * (maxlev + 1), hipMemcpyDeviceToHost,
-                         s->stream));
-  PPE_HIP(hipStreamSynchronize(s->stream));
+  read_back(s, {ReadItem{rho_dev, sizeof(double) * (maxlev + 1), out.data()}});
   int bits = 0;
   std::memcpy(&bits, &out[maxlev], sizeof(int));
   require(!(bits & SE_DIAG), PPE_ERR_INTERNAL, "coarse operator lost its diagonal");

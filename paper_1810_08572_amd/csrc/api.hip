@@ -155,6 +155,9 @@ void ppe_destroy(ppe_solver* s) {
   if (s->ev1) (void)hipEventDestroy(s->ev1);
   if (s->tev0) (void)hipEventDestroy(s->tev0);
   if (s->tev1) (void)hipEventDestroy(s->tev1);
+  for (auto& e : s->chk_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (s->box_h) (void)hipHostFree(s->box_h);
   delete s;
 }
 
@@ -167,6 +170,7 @@ ppe_status ppe_set_mesh(ppe_solver* s, int32_t n_cells, int32_t n_faces, const i
     ppe::require(n_faces >= 0, PPE_ERR_ARG, "n_faces must be >= 0");
     ppe::require(n_faces == 0 || (owner && neigh), PPE_ERR_ARG, "owner/neigh is NULL");
     s->have_mesh = false;
+    s->geom_ok = false;
     s->assembled = false;
     s->n_cells = n_cells;
     s->n_faces = n_faces;
@@ -232,6 +236,61 @@ ppe_status ppe_solve(ppe_solver* s, const double* rhs, double* p, int use_x0, pp
     if (stats) *stats = s->stats;
     if (st == PPE_ERR_BREAKDOWN) s->err = "PCG breakdown (p.Ap <= 0, r.z <= 0 or non-finite)";
     return st;
+  });
+}
+
+ppe_status ppe_set_geometry(ppe_solver* s, int32_t n_nodes, const double* nodes,
+                            const int32_t* face_nodes, const int32_t* cell_nodes,
+                            const double* cell_centre, const double* face_area) {
+  if (!s) return PPE_ERR_ARG;
+  return guarded(s, [&]() -> ppe_status {
+    DeviceGuard g(s->device);
+    ppe::require(s->have_mesh, PPE_ERR_STATE, "ppe_set_geometry before ppe_set_mesh");
+    ppe::require(n_nodes > 0, PPE_ERR_ARG, "n_nodes must be positive");
+    ppe::require(nodes && cell_nodes && cell_centre && (s->n_faces == 0 || (face_nodes && face_area)),
+                 PPE_ERR_ARG, "NULL geometry array");
+    ppe::set_geometry(s, n_nodes, nodes, face_nodes, cell_nodes, cell_centre, face_area);
+    return PPE_OK;
+  });
+}
+
+ppe_status ppe_project(ppe_solver* s, const double* face_coeff, const double* ustar, double rho,
+                       double dt, double* p, double* flux, double* u, ppe_project_stats* stats) {
+  if (!s) return PPE_ERR_ARG;
+  return guarded(s, [&]() -> ppe_status {
+    DeviceGuard g(s->device);
+    ppe::require(s->assembled, PPE_ERR_STATE, "ppe_project before ppe_assemble");
+    ppe::require(s->geom_ok, PPE_ERR_STATE, "ppe_project before ppe_set_geometry");
+    ppe::require(s->n_seg == 1, PPE_ERR_STATE, "ppe_project solves one sample at a time");
+    ppe::require(face_coeff && ustar && p && u && (flux || s->n_faces == 0), PPE_ERR_ARG,
+                 "NULL array");
+    ppe::require(std::isfinite(rho) && rho > 0 && std::isfinite(dt) && dt > 0, PPE_ERR_ARG,
+                 "rho and dt must be finite and > 0");
+    PPE_HIP(hipEventRecord(s->ev0, s->stream));
+    ppe_project_stats st{};
+    const ppe_status r = ppe::project(s, face_coeff, ustar, rho, dt, p, flux, u, &st);
+    PPE_HIP(hipEventRecord(s->ev1, s->stream));
+    PPE_HIP(hipEventSynchronize(s->ev1));
+    st.ms = elapsed_ms(s->ev0, s->ev1);
+    if (stats) *stats = st;
+    return r;
+  });
+}
+
+ppe_status ppe_face_gradient(ppe_solver* s, const double* face_coeff, double rho, const double* p,
+                             double* grad, double* cross) {
+  if (!s) return PPE_ERR_ARG;
+  return guarded(s, [&]() -> ppe_status {
+    DeviceGuard g(s->device);
+    ppe::require(s->assembled && s->geom_ok, PPE_ERR_STATE,
+                 "ppe_face_gradient needs ppe_assemble and ppe_set_geometry");
+    ppe::require(face_coeff && p && grad && cross, PPE_ERR_ARG, "NULL array");
+    ppe::require(std::isfinite(rho) && rho > 0, PPE_ERR_ARG, "rho must be finite and > 0");
+    double* t = s->pj_t.get<double>(3 * (size_t)(s->n_faces > 0 ? s->n_faces : 1));
+    ppe::cross_vectors(s, face_coeff, rho, t);
+    ppe::face_gradient(s, p, t, grad, cross);
+    PPE_HIP(hipStreamSynchronize(s->stream));
+    return PPE_OK;
   });
 }
 
@@ -305,6 +364,34 @@ ppe_status ppe_level_info(const ppe_solver* s, int level, int32_t* n_rows, int64
   if (nnz_p) *nnz_p = coarsest ? 0 : L.P.nnz;
   if (n_agg) *n_agg = coarsest ? 0 : L.n_agg;
   if (rho) *rho = L.rho;
+  return PPE_OK;
+}
+
+ppe_status ppe_get_level_launch(const ppe_solver* s, int level, int32_t* choice) {
+  ppe_status st = check_level(s, level);
+  if (st != PPE_OK) return st;
+  if (!choice) return PPE_ERR_ARG;
+  const ppe::Level& L = s->levels[level];
+  choice[0] = L.lpr_a;
+  choice[1] = L.lpr_r;
+  choice[2] = L.lpr_p;
+  choice[3] = L.fuse0 ? 1 : 0;
+  return PPE_OK;
+}
+
+ppe_status ppe_set_level_launch(ppe_solver* s, int level, const int32_t* choice) {
+  ppe_status st = check_level(s, level);
+  if (st != PPE_OK) return st;
+  if (!choice) return PPE_ERR_ARG;
+  auto ok = [](int v) { return v == 0 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64; };
+  if (!ok(choice[0]) || !ok(choice[1]) || !ok(choice[2]) || (choice[3] != 0 && choice[3] != 1))
+    return PPE_ERR_ARG;
+  ppe::Level& L = s->levels[level];
+  L.lpr_a = choice[0];
+  L.lpr_r = choice[1];
+  L.lpr_p = choice[2];
+  L.fuse0 = choice[3] != 0;
+  ppe::drop_graph(s);  // a captured graph holds the old launches
   return PPE_OK;
 }
 

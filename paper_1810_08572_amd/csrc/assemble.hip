@@ -188,12 +188,18 @@ __global__ void k_components(const int* __restrict__ active, int n, int* parent,
   is_pin[i] = (r == i) ? 1 : 0;
 }
 
-__global__ void k_row_counts(const int* __restrict__ perm, int n_active,
-                             const int* __restrict__ adj_ptr, const int* __restrict__ adj_nbr,
-                             const int* __restrict__ active, const int* __restrict__ is_pin,
-                             int* __restrict__ counts) {
+// Entries of every compact row r < *n_active; rows from there to n_max get 0
+// so that a scan over n_max rows ends at the matrix size.
+__global__ void k_row_counts(const int* __restrict__ perm, const int* __restrict__ n_active,
+                             int n_max, const int* __restrict__ adj_ptr,
+                             const int* __restrict__ adj_nbr, const int* __restrict__ active,
+                             const int* __restrict__ is_pin, int* __restrict__ counts) {
   int r = blockIdx.x * kBlock + threadIdx.x;
-  if (r >= n_active) return;
+  if (r >= n_max) return;
+  if (r >= *n_active) {
+    counts[r] = 0;
+    return;
+  }
   int c = perm[r];
   int cnt = 1;
   if (!is_pin[c]) {
@@ -406,28 +412,18 @@ void assemble_fine(ppe_solver* s, const double* coeff, const double* fl) {
   hipLaunchKernelGGL(k_gather_int, dim3(grid_for(ns + 1)), dim3(kBlock), 0, s->stream, ns + 1, d_off,
                      rowpos, d_row);
   PPE_LAUNCH_CHECK();
-  // one read-back: the field checks and the segments' row offsets
-  int bad = 0;
-  s->seg_row_off.assign(ns + 1, 0);
-  PPE_HIP(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s->stream));
-  PPE_HIP(hipMemcpyAsync(s->seg_row_off.data(), d_row, sizeof(int) * (ns + 1),
-                         hipMemcpyDeviceToHost, s->stream));
-  PPE_HIP(hipStreamSynchronize(s->stream));
-  require(!(bad & 1), PPE_ERR_ARG, "face coefficient must be finite and > 0 on interior faces");
-  require(!(bad & 2), PPE_ERR_ARG, "liquid fraction must be finite and in [0, 1]");
-  const int na = s->seg_row_off[ns];
-  s->n_active = na;
-  int* perm = s->perm.get<int>(na);
+  // Everything up to the row pointers is queued before the host learns the
+  // number of active cells (rowpos[nc] on the device): arrays indexed by
+  // compact row are sized for all cells.
+  int* perm = s->perm.get<int>(nc);
   hipLaunchKernelGGL(k_compact, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, active, nc, rowpos,
                      cid, perm);
   PPE_LAUNCH_CHECK();
 
-  build_tiles(s);
-
   int* comp = s->comp_full.get<int>(nc);
   int* is_pin = s->tmp_i[2].get<int>(nc);
   if (nf) {
-    int* forest = s->tmp_i[1].get<int>(nc);
+    int* forest = s->tmp_i[3].get<int>(nc + 1);
     hipLaunchKernelGGL(k_cc_init, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc,
                        s->adj_ptr.as<int>(), s->adj_nbr.as<int>(), active, forest);
     PPE_LAUNCH_CHECK();
@@ -441,36 +437,40 @@ void assemble_fine(ppe_solver* s, const double* coeff, const double* fl) {
   hipLaunchKernelGGL(k_components, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, active, nc,
                      parent, comp, is_pin);
   PPE_LAUNCH_CHECK();
-  // the pocket count is read back with the matrix size below
   const long long* d_ncomp =
       exclusive_scan_async(s, is_pin, s->tmp_i[3].get<int>(nc + 1), nc, 1);
 
   if (s->levels.empty()) s->levels.resize(1);
   s->nlev = 1;
   Level& L = s->levels[0];
+  int* counts = s->tmp_i[0].get<int>(nc + 1);
+  hipLaunchKernelGGL(k_row_counts, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, perm, rowpos + nc,
+                     nc, s->adj_ptr.as<int>(), s->adj_nbr.as<int>(), active, is_pin, counts);
+  PPE_LAUNCH_CHECK();
+  int* rowptr = L.A.rowptr.get<int>(nc + 1);
+  const long long* d_nnz = exclusive_scan_async(s, counts, rowptr, nc, 0);
+  // one read-back: the field checks, the segments' row offsets, the matrix
+  // size and the pocket count
+  int bad = 0;
+  long long tot[2] = {0, 0};
+  s->seg_row_off.assign(ns + 1, 0);
+  read_back(s, {ReadItem{flag, sizeof(int), &bad},
+                ReadItem{d_row, sizeof(int) * (ns + 1), s->seg_row_off.data()},
+                ReadItem{d_nnz, sizeof(long long), &tot[0]},
+                ReadItem{d_ncomp, sizeof(long long), &tot[1]}});
+  require(!(bad & 1), PPE_ERR_ARG, "face coefficient must be finite and > 0 on interior faces");
+  require(!(bad & 2), PPE_ERR_ARG, "liquid fraction must be finite and in [0, 1]");
+  const int na = s->seg_row_off[ns];
+  s->n_active = na;
+  s->n_comp = (int)tot[1];
+  build_tiles(s);
+
   L.n = na;
   L.A.n = L.A.m = na;
   L.A.maxrow = s->max_deg + 1;  // a row holds its open faces and the diagonal
   L.W = s->max_deg;
-  long long tot[2] = {0, 0};
-  if (na == 0) {
-    L.A.nnz = 0;
-    PPE_HIP(hipMemcpyAsync(&tot[1], d_ncomp, sizeof(long long), hipMemcpyDeviceToHost, s->stream));
-    PPE_HIP(hipStreamSynchronize(s->stream));
-    s->n_comp = (int)tot[1];
-    return;
-  }
-  int* counts = s->tmp_i[0].get<int>(na + 1);
-  hipLaunchKernelGGL(k_row_counts, dim3(grid_for(na)), dim3(kBlock), 0, s->stream, perm, na,
-                     s->adj_ptr.as<int>(), s->adj_nbr.as<int>(), active, is_pin, counts);
-  PPE_LAUNCH_CHECK();
-  int* rowptr = L.A.rowptr.get<int>(na + 1);
-  const long long* d_nnz = exclusive_scan_async(s, counts, rowptr, na, 0);
-  PPE_HIP(hipMemcpyAsync(&tot[0], d_nnz, sizeof(long long), hipMemcpyDeviceToHost, s->stream));
-  PPE_HIP(hipMemcpyAsync(&tot[1], d_ncomp, sizeof(long long), hipMemcpyDeviceToHost, s->stream));
-  PPE_HIP(hipStreamSynchronize(s->stream));
   L.A.nnz = tot[0];
-  s->n_comp = (int)tot[1];
+  if (na == 0) return;
   int* col = L.A.col.get<int>(L.A.nnz);
   double* val = L.A.val.get<double>(L.A.nnz);
   double* diag = L.diag.get<double>(na);

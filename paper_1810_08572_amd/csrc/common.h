@@ -128,6 +128,14 @@ struct Scalars {
   int pad;
 };
 
+// A device value the host needs: `bytes` (a multiple of 4) at `dev`, to be
+// copied to `host`.
+struct ReadItem {
+  const void* dev;
+  size_t bytes;
+  void* host;
+};
+
 }  // namespace ppe
 
 struct ppe_solver {
@@ -173,6 +181,12 @@ struct ppe_solver {
   ppe::DevBuf rmax;  // max column count of the last transposed operator (device int)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t tev0 = nullptr, tev1 = nullptr;  // autotuner timing
+  // pinned host memory that k_publish writes read-back values into
+  uint32_t* box_h = nullptr;
+  uint32_t* box_d = nullptr;
+  size_t box_words = 0;
+  uint32_t box_tag = 0;
+  hipEvent_t chk_ev[2] = {nullptr, nullptr};  // PCG convergence checks in flight
   // autotuner choices per (level, FP32, quarter-octave bins of rows and of
   // entries): {lpr_a, fuse0, lpr_r, lpr_p}
   std::map<std::array<int, 4>, std::array<int, 4>> tune_cache;
@@ -182,6 +196,14 @@ struct ppe_solver {
   hipGraphExec_t gexec = nullptr;
   bool graph_ok = false;
   int solves_since_assemble = 0;
+
+  // geometry of the pressure-correction step: nodes, cell centres, face area
+  // vectors, face vertices, vertex -> cells (sorted), local frames
+  bool geom_ok = false;
+  int n_nodes = 0;
+  ppe::DevBuf g_nodes, g_cc, g_S, g_fnodes, g_vptr, g_vcell;
+  ppe::DevBuf g_inv;  // J^-1 per face, nine arrays of n_faces
+  ppe::DevBuf pj_fs, pj_b, pj_r, pj_d, pj_grad, pj_xf, pj_part, pj_t, pj_vm;  // projection workspace
 
   // dominant-kernel measurement (event pairs around fine-level smoothing steps)
   bool prof = false;
@@ -359,12 +381,37 @@ int scan_blocks(int n);
 void max_int_async(ppe_solver* s, const int* in, int n, int* out);
 // Max of an int array.
 int reduce_max_int(ppe_solver* s, const int* in, int n);
-// Copy one value from device to host on the solver stream (synchronises).
+// ---- read-backs through pinned host memory
+// Box layout in words: [kBoxChecks, kBoxRead) for the PCG's convergence
+// checks (two in flight, three words each with the tag), read_back from
+// kBoxRead on.
+constexpr size_t kBoxChecks = 0, kBoxRead = 8;
+// Makes the solver's pinned box hold at least `words` 4-byte words; a box
+// that must grow is replaced only after the stream has drained.
+void ensure_box(ppe_solver* s, size_t words);
+// Values copied into the box by one publish call: n_words words at `words`,
+// followed by the call's tag.
+struct Published {
+  const uint32_t* words;
+  uint32_t n_words;
+  uint32_t tag;
+};
+// One small kernel on the solver stream copies the items (at most 16), in
+// order, into the box from word `at` on, then a fresh tag behind them.  No
+// host copies are made; read the values with published_words once the stream
+// (or an event recorded after the call) has completed.
+Published publish(ppe_solver* s, const ReadItem* items, int n, size_t at);
+// The published words after checking their tag; throws PPE_ERR_INTERNAL if
+// they are still not visible once the stream has drained.
+const uint32_t* published_words(ppe_solver* s, const Published& p);
+// Publishes the items at kBoxRead, waits for the stream and copies each item
+// to its host address: one round trip for any number of values.
+void read_back(ppe_solver* s, std::initializer_list<ReadItem> items);
+// One value from device to host on the solver stream (synchronises).
 template <class T>
 T read_scalar(ppe_solver* s, const T* dptr) {
   T v{};
-  PPE_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, s->stream));
-  PPE_HIP(hipStreamSynchronize(s->stream));
+  read_back(s, {ReadItem{dptr, sizeof(T), &v}});
   return v;
 }
 void fill_int(ppe_solver* s, int* p, int v, int64_t n);
@@ -392,6 +439,18 @@ void make_fp32_hierarchy(ppe_solver* s);
 // Time the candidate launch choices of every level's solve kernels and keep
 // the fastest (cached by level shape).
 void autotune_levels(ppe_solver* s);
+
+// project.hip
+// Copies the geometry and builds the Eq. 12 face-gradient stencils.
+void set_geometry(ppe_solver* s, int n_nodes, const double* nodes, const int32_t* face_nodes,
+                  const int32_t* cell_nodes, const double* cell_centre, const double* face_area);
+// t[3 n_faces] (three arrays) = S_f / rho - c_f d_f on interior faces
+void cross_vectors(ppe_solver* s, const double* coeff, double rho, double* t);
+// xf[n_faces] = t_f . grad_f with grad_f the masked face gradient of
+// p[n_cells]; grad[3 n_faces] receives the gradients unless NULL
+void face_gradient(ppe_solver* s, const double* p, const double* t, double* grad, double* xf);
+ppe_status project(ppe_solver* s, const double* coeff, const double* ustar, double rho, double dt,
+                   double* p, double* flux, double* u, ppe_project_stats* out);
 void profile_harvest(ppe_solver* s);
 void drop_graph(ppe_solver* s);
 void profile_enable(ppe_solver* s, bool on);

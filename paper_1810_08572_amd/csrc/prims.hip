@@ -1,5 +1,8 @@
 // Device primitives: exclusive scan of int32 counts (three-pass, int64
 // carries), integer max reduction and fills.
+#include <algorithm>
+#include <cstring>
+
 #include "common.h"
 
 namespace ppe {
@@ -96,6 +99,31 @@ __global__ void __launch_bounds__(kBlock) k_max_int(const int* __restrict__ in, 
   if (threadIdx.x == 0) atomicMax(out, m);
 }
 
+// Read-back staging: item k (kPubMax at most) is off[k+1] - off[k] words at
+// src[k], copied to dst[off[k]..] in the pinned host box.
+constexpr int kPubMax = 16;
+struct PubArgs {
+  const uint32_t* src[kPubMax];
+  uint32_t off[kPubMax + 1];
+  int n;
+};
+
+// After the items, dst[off[n]] receives `tag`, stored only once every word is
+// visible at system scope: a host that reads the tag it expects, then the
+// words, reads this call's values.
+__global__ void __launch_bounds__(kBlock) k_publish(PubArgs a, uint32_t tag,
+                                                    uint32_t* __restrict__ dst) {
+  for (int k = 0; k < a.n; ++k) {
+    const uint32_t* src = a.src[k];
+    const uint32_t o = a.off[k], len = a.off[k + 1] - o;
+    for (uint32_t w = threadIdx.x; w < len; w += kBlock) dst[o + w] = src[w];
+  }
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_store(dst + a.off[a.n], tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_fill(T* __restrict__ p, T v, long long n) {
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
@@ -157,6 +185,69 @@ int reduce_max_int(ppe_solver* s, const int* in, int n) {
   hipLaunchKernelGGL(k_max_int, dim3(g), dim3(kBlock), 0, s->stream, in, n, out);
   PPE_LAUNCH_CHECK();
   return read_scalar(s, out);
+}
+
+void ensure_box(ppe_solver* s, size_t words) {
+  if (words <= s->box_words) return;
+  size_t cap = s->box_words ? s->box_words : 4096;
+  while (cap < words) cap *= 2;
+  if (s->box_h) {
+    // kernels in flight may still write the old box
+    PPE_HIP(hipStreamSynchronize(s->stream));
+    PPE_HIP(hipHostFree(s->box_h));
+    s->box_h = s->box_d = nullptr;
+    s->box_words = 0;
+  }
+  void* h = nullptr;
+  PPE_HIP(hipHostMalloc(&h, cap * sizeof(uint32_t), hipHostMallocMapped | hipHostMallocCoherent));
+  void* d = nullptr;
+  PPE_HIP(hipHostGetDevicePointer(&d, h, 0));
+  s->box_h = static_cast<uint32_t*>(h);
+  s->box_d = static_cast<uint32_t*>(d);
+  s->box_words = cap;
+}
+
+Published publish(ppe_solver* s, const ReadItem* items, int n, size_t at) {
+  if (n > kPubMax) throw Error(PPE_ERR_INTERNAL, "too many read-back items in one call");
+  PubArgs a{};
+  a.n = n;
+  uint32_t off = 0;
+  for (int k = 0; k < n; ++k) {
+    if (items[k].bytes % 4 != 0) throw Error(PPE_ERR_INTERNAL, "read-back size not a word multiple");
+    a.src[k] = static_cast<const uint32_t*>(items[k].dev);
+    a.off[k] = off;
+    off += (uint32_t)(items[k].bytes / 4);
+  }
+  a.off[n] = off;
+  ensure_box(s, at + off + 1);
+  const uint32_t tag = ++s->box_tag;
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(kBlock), 0, s->stream, a, tag, s->box_d + at);
+  PPE_LAUNCH_CHECK();
+  return Published{s->box_h + at, off, tag};
+}
+
+const uint32_t* published_words(ppe_solver* s, const Published& p) {
+  auto tag_now = [&]() {
+    return __atomic_load_n(p.words + p.n_words, __ATOMIC_ACQUIRE);
+  };
+  if (tag_now() != p.tag) {
+    // the wait that preceded this call covered the kernel: drain the stream
+    // and look once more before giving up
+    PPE_HIP(hipStreamSynchronize(s->stream));
+    if (tag_now() != p.tag) throw Error(PPE_ERR_INTERNAL, "read-back values not visible to the host");
+  }
+  return p.words;
+}
+
+void read_back(ppe_solver* s, std::initializer_list<ReadItem> items) {
+  const std::vector<ReadItem> all(items);
+  const Published pub = publish(s, all.data(), (int)all.size(), kBoxRead);
+  PPE_HIP(hipStreamSynchronize(s->stream));
+  const uint32_t* h = published_words(s, pub);
+  for (const auto& it : all) {
+    std::memcpy(it.host, h, it.bytes);
+    h += it.bytes / 4;
+  }
 }
 
 void fill_int(ppe_solver* s, int* p, int v, int64_t n) {

@@ -836,13 +836,15 @@ void prepare_solve_levels(ppe_solver* s) {
     L.x2.get<double>(n);
     L.d2.get<double>(n);
     L.t.get<double>(n);
+    L.c1.clear();
+    L.c2.clear();
+    L.inv_theta = 0.0;
+    if (!(L.rho > 0.0)) continue;  // a coarsest level solved directly: no smoother
     const double lmax = L.rho, lmin = L.rho / s->opt.cheb_ratio;
     const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
     const double sigma = theta / delta;
     double rho_prev = 1.0 / sigma;
     L.inv_theta = 1.0 / theta;
-    L.c1.clear();
-    L.c2.clear();
     for (int j = 2; j <= s->opt.cheb_degree; ++j) {
       const double rho_j = 1.0 / (2.0 * sigma - rho_prev);
       L.c1.push_back(rho_j * rho_prev);
@@ -970,12 +972,9 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
   const int* comp = s->comp_full.as<int>();
   const int ge = grid_for(na);
   double* rz[2] = {sc + (size_t)SS_RZ0 * ns, sc + (size_t)SS_RZ1 * ns};
-  int h[2];
-  auto read_counts = [&]() {
-    PPE_HIP(hipMemcpyAsync(h, cnt, sizeof(int) * 2, hipMemcpyDeviceToHost, s->stream));
-    PPE_HIP(hipStreamSynchronize(s->stream));
-  };
-
+  // the box holds the final statistics (read_back) beside the two check slots
+  ensure_box(s, kBoxRead + 1 + 5 * (size_t)ns);
+  std::vector<double> bbh(ns), rth(ns);
   hipLaunchKernelGGL(k_gather_rhs_t, dim3(nt), dim3(kBlock), 0, s->stream, T, perm, comp, rhs, b,
                      tpart(T_BB));
   PPE_LAUNCH_CHECK();
@@ -998,7 +997,10 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
     hipLaunchKernelGGL(k_zero_empty_t, dim3(nt), dim3(kBlock), 0, s->stream, T, ns, sc, x);
     PPE_LAUNCH_CHECK();
   }
-  // true residual of every segment, then restart those that miss the tolerance
+  // true residual of every segment, then restart those that miss the
+  // tolerance.  The scatter and the statistics ride along in the same round
+  // trip: when nothing restarts they are the final ones.
+  bool fetched = false;
   auto check_true = [&]() {
     apply_op<E_RESID, double>(s, L0, x, b, nullptr, 0.0, 0.0, q, nullptr);
     hipLaunchKernelGGL(k_norm2_t, dim3(nt), dim3(kBlock), 0, s->stream, T, q, tpart(T_RT));
@@ -1009,21 +1011,26 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
     PPE_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_copy_restart_t, dim3(nt), dim3(kBlock), 0, s->stream, T, restart, q, r);
     PPE_LAUNCH_CHECK();
-    read_counts();
-    return h[0];
-  };
-  auto finish = [&](ppe_status status) {
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc,
                        s->cid.as<int>(), comp, x, p_out);
     PPE_LAUNCH_CHECK();
-    std::vector<double> bbh(ns), rth(ns);
-    PPE_HIP(hipMemcpyAsync(bbh.data(), sc + (size_t)SS_BB * ns, sizeof(double) * ns,
-                           hipMemcpyDeviceToHost, s->stream));
-    PPE_HIP(hipMemcpyAsync(rth.data(), sc + (size_t)SS_RES * ns, sizeof(double) * ns,
-                           hipMemcpyDeviceToHost, s->stream));
-    PPE_HIP(hipMemcpyAsync(s->seg_iters_h.data(), iters, sizeof(int) * ns, hipMemcpyDeviceToHost,
-                           s->stream));
-    PPE_HIP(hipStreamSynchronize(s->stream));
+    int left = 0;
+    read_back(s, {ReadItem{cnt, sizeof(int), &left},
+                  ReadItem{sc + (size_t)SS_BB * ns, sizeof(double) * ns, bbh.data()},
+                  ReadItem{sc + (size_t)SS_RES * ns, sizeof(double) * ns, rth.data()},
+                  ReadItem{iters, sizeof(int) * ns, s->seg_iters_h.data()}});
+    fetched = left == 0;
+    return left;
+  };
+  auto finish = [&](ppe_status status) {
+    if (!fetched) {
+      hipLaunchKernelGGL(k_scatter, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc,
+                         s->cid.as<int>(), comp, x, p_out);
+      PPE_LAUNCH_CHECK();
+      read_back(s, {ReadItem{sc + (size_t)SS_BB * ns, sizeof(double) * ns, bbh.data()},
+                    ReadItem{sc + (size_t)SS_RES * ns, sizeof(double) * ns, rth.data()},
+                    ReadItem{iters, sizeof(int) * ns, s->seg_iters_h.data()}});
+    }
     profile_harvest(s);
     double worst = 0.0;
     int itmax = 0;
@@ -1037,9 +1044,8 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
     return status;
   };
 
-  read_counts();
-  if (h[0] == 0 && check_true() == 0) return finish(PPE_OK);
-
+  // Samples converged from the start (zero right-hand side, exact guess) are
+  // left alone by every iteration, so the first check below finds them.
   auto precondition = [&](int sl, bool with_q) {
     vcycle_pcg(s, r, zb[sl], PcgDot{T, nt, flexible && with_q ? q : nullptr, tpart(T_RZ)});
   };
@@ -1079,25 +1085,52 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
   if (graph && !s->graph_ok) capture_iterations(s, [&]() { body(0); body(1); });
   int it = 0, slot = 0;
   const int max_iter = s->opt.max_iter, every = s->opt.check_every;
-  while (it < max_iter) {
-    bool check;
-    if (graph && slot == 0 && it + 2 <= max_iter) {
-      PPE_HIP(hipGraphLaunch(s->gexec, s->stream));
-      it += 2;
-      check = true;
-    } else {
+  // Convergence checks run one chunk behind: chunk c+1 is queued before the
+  // host waits for the counts of chunk c, so the device does not idle during
+  // the round trip.  A chunk queued after convergence changes nothing.
+  for (auto& e : s->chk_ev)
+    if (!e) PPE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  struct Check {
+    Published h;  // (active segments, error bits) once the event has passed
+    int ev;
+    int it;  // iterations launched up to this check
+  };
+  Check pend[2];
+  int npend = 0, next_ev = 0;
+  auto launch_chunk = [&]() {
+    do {
+      if (graph && slot == 0 && it + 2 <= max_iter) {
+        PPE_HIP(hipGraphLaunch(s->gexec, s->stream));
+        it += 2;
+        break;
+      }
       body(slot);
       slot = 1 - slot;
       it += 1;
-      check = it % every == 0 || it == max_iter;
-    }
-    if (!check) continue;
-    read_counts();
-    if (h[1]) {
+    } while (it % every != 0 && it < max_iter);
+    const ReadItem item{cnt, 2 * sizeof(int), nullptr};
+    const Published h = publish(s, &item, 1, kBoxChecks + 3 * next_ev);
+    PPE_HIP(hipEventRecord(s->chk_ev[next_ev], s->stream));
+    pend[npend++] = Check{h, next_ev, it};
+    next_ev = 1 - next_ev;
+  };
+  for (;;) {
+    while (npend < 2 && it < max_iter) launch_chunk();
+    if (npend == 0) break;
+    const Check c = pend[0];
+    pend[0] = pend[1];
+    --npend;
+    PPE_HIP(hipEventSynchronize(s->chk_ev[c.ev]));
+    const uint32_t* w = published_words(s, c.h);
+    const int active = (int)w[0], bad = (int)w[1];
+    if (bad) {
       finish(PPE_ERR_BREAKDOWN);
       return PPE_ERR_BREAKDOWN;
     }
-    if (h[0] == 0) {
+    if (active == 0) {
+      // everything converged at this check: the chunk behind it was a no-op
+      npend = 0;
+      it = c.it;
       if (check_true() == 0) return finish(PPE_OK);
       // restarted samples: z = M r_true, p = z (beta is 0 after a restart)
       precondition(slot, false);  // beta is 0: z.q is not needed

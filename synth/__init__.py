@@ -1,7 +1,8 @@
 """Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
 
 This package only builds workloads: hexahedral meshes stored as face lists,
-face coefficients, liquid-fraction fields and right-hand sides.  It holds
+face coefficients, liquid-fraction fields, right-hand sides and intermediate
+velocities.  It holds
 none of the solver's arithmetic (no masking, assembly, aggregation or Krylov
 step); those live separately in the oracle and in the HIP library.
 """
@@ -14,6 +15,7 @@ from .fields import (
     batch_samples,
     uq_front_fl,
     rhs_smooth_series,
+    ustar_smooth_series,
     mlp_initial_weights,
 )
 
@@ -30,5 +32,6 @@ __all__ = [
     "batch_samples",
     "uq_front_fl",
     "rhs_smooth_series",
+    "ustar_smooth_series",
     "mlp_initial_weights",
 ]

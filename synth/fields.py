@@ -94,6 +94,29 @@ def rhs_smooth_series(centres, t, seed=5, n_modes=6, noise=0.05, center_mask=Non
     return b
 
 
+def ustar_smooth_series(centres, t, seed=7, n_modes=6, scale=0.01, noise=0.05):
+    """Intermediate velocity u* [n, 3] that changes smoothly in time (the
+    predictor's output the pressure step corrects): per component, a sum of
+    n_modes seeded products of low-order cosines with a time phase, times
+    `scale`, plus a small fixed noise field."""
+    rng = np.random.default_rng(seed)
+    x = np.asarray(centres)
+    lo = x.min(axis=0)
+    span = np.maximum(x.max(axis=0) - lo, 1e-30)
+    v = (x - lo) / span
+    u = np.zeros((x.shape[0], 3))
+    for d in range(3):
+        for _ in range(n_modes):
+            k = rng.integers(0, 4, size=3)
+            amp = rng.uniform(0.5, 1.5)
+            omega = rng.uniform(5.0, 20.0)
+            phase = rng.uniform(0, 2 * np.pi)
+            u[:, d] += amp * np.cos(omega * t + phase) * np.prod(
+                np.cos(np.pi * k * v + rng.uniform(0, 1, 3)), axis=1)
+    u += noise * rng.uniform(-1.0, 1.0, size=u.shape)
+    return scale * u
+
+
 def mlp_initial_weights(n_in=10, width=128, n_hidden=3, seed=0):
     """Initial weights of the warm-start network, drawn outside the method:
     for each layer (fan_out x fan_in), a row-major weight matrix followed by
