@@ -455,6 +455,8 @@ def main():
     ap.add_argument("--no-c5", action="store_true", help="skip the plate-with-ribs leg")
     ap.add_argument("--no-projection", action="store_true",
                     help="skip the cross-diffusion pressure-correction leg")
+    ap.add_argument("--projection-only", action="store_true",
+                    help="time the FP64 leg and the pressure-correction leg only (for profiling)")
     ap.add_argument("--uq", action="store_true", help="add the batched-UQ measurement")
     ap.add_argument("--c3-only", action="store_true",
                     help="run only the 128^3 leg and print its JSON (for profiling it alone)")
@@ -489,7 +491,7 @@ def main():
     warm = list(range(FIRST_TIMED - W, FIRST_TIMED))
     wl = Timesteps(box_mesh((64, 64, 64), lengths=(CAVITY,) * 3, jitter=0.1, seed=0), axis=0,
                    length=CAVITY)
-    need = warm + steps + ([] if args.no_variants else list(TRAIN_STEPS))
+    need = warm + steps + ([] if args.no_variants or args.projection_only else list(TRAIN_STEPS))
     d_in = wl.to_device(torch, dev, need)
     note(f"inputs ready: {len(set(need))} timesteps of {wl.m.n_cells} cells")
 
@@ -534,6 +536,11 @@ def main():
         out["roofline"] = roofline(s, rerun, "64cube_timesteps")
         out["roofline"]["kernel"] += ", FP64"
 
+    if args.projection_only:
+        out["variants"] = {"projection_cross_diffusion": projection_leg(ppe, torch, wl, d_in, steps,
+                                                                         warm, dev, base)}
+        print(json.dumps(out), flush=True)
+        return
     if not args.no_variants:
         variants = {}
         mixed = run_leg(ppe, torch, wl, d_in, steps, warm, "mixed")

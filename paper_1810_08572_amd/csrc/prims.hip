@@ -90,6 +90,47 @@ __global__ void __launch_bounds__(kBlock) k_scan_down(const int* __restrict__ in
   if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = (int)*total;
 }
 
+// Exclusive scan of n <= kSmallScan counts by one block of kSmallBlock
+// threads, each owning a run of consecutive items: out[0..n], *total.
+constexpr int kSmallBlock = 1024;
+constexpr int kSmallItems = 16;
+constexpr int kSmallScan = kSmallBlock * kSmallItems;
+
+__global__ void __launch_bounds__(kSmallBlock) k_scan_small(const int* __restrict__ in, int n,
+                                                            int* __restrict__ out,
+                                                            long long* __restrict__ total) {
+  __shared__ long long wsum[kSmallBlock / kWave];
+  const int per = (n + kSmallBlock - 1) / kSmallBlock;  // <= kSmallItems
+  const int base = threadIdx.x * per;
+  long long run = 0;
+  for (int k = 0; k < per; ++k) {
+    const int i = base + k;
+    if (i < n) run += in[i];
+  }
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const long long inc = wave_incl_scan(run);
+  if (lane == kWave - 1) wsum[w] = inc;
+  __syncthreads();
+  long long off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kSmallBlock / kWave; ++i) {
+    if (i < w) off += wsum[i];
+    tot += wsum[i];
+  }
+  long long pos = off + inc - run;
+  for (int k = 0; k < per; ++k) {
+    const int i = base + k;
+    if (i < n) {
+      out[i] = (int)pos;
+      pos += in[i];
+    }
+  }
+  if (threadIdx.x == 0) {
+    out[n] = (int)tot;
+    *total = tot;
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) k_max_int(const int* __restrict__ in, int n,
                                                     int* __restrict__ out) {
   int m = INT32_MIN;
@@ -140,6 +181,12 @@ int scan_blocks(int n) {
 
 long long* exclusive_scan_async(ppe_solver* s, const int* in, int* out, int n, int slot) {
   if (n < 0) throw Error(PPE_ERR_INTERNAL, "negative scan length");
+  if (n <= kSmallScan) {
+    long long* total = s->tmp_l[slot].get<long long>(2) + 1;
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kSmallBlock), 0, s->stream, in, n, out, total);
+    PPE_LAUNCH_CHECK();
+    return total;
+  }
   const int nb = scan_blocks(n);
   long long* bsum = s->tmp_l[slot].get<long long>(nb + 1);
   long long* total = bsum + nb;
@@ -153,17 +200,7 @@ long long* exclusive_scan_async(ppe_solver* s, const int* in, int* out, int n, i
 }
 
 int64_t exclusive_scan(ppe_solver* s, const int* in, int* out, int n) {
-  if (n < 0) throw Error(PPE_ERR_INTERNAL, "negative scan length");
-  int nb = (int)((n + (int64_t)kScanTile - 1) / kScanTile);
-  if (nb < 1) nb = 1;
-  long long* bsum = s->tmp_l[0].get<long long>(nb + 1);
-  long long* total = bsum + nb;
-  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s->stream, in, n, bsum);
-  PPE_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s->stream, bsum, nb, total);
-  PPE_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kBlock), 0, s->stream, in, n, bsum, total, out);
-  PPE_LAUNCH_CHECK();
+  const long long* total = exclusive_scan_async(s, in, out, n, 0);
   long long t = read_scalar(s, total);
   if (t > INT32_MAX) throw Error(PPE_ERR_INTERNAL, "scan total exceeds int32 range");
   return t;

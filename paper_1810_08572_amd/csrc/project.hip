@@ -535,7 +535,11 @@ ppe_status project(ppe_solver* s, const double* coeff, const double* ustar, doub
   };
   const double bn = residual(0);
   double rn = bn;
-  const double target = s->opt.rtol * bn;
+  // one decade below rtol: loose inner solves leave the last residual in
+  // smooth modes, which the condition number amplifies in the pressure; the
+  // margin keeps p near the exact solution of the full system at the price
+  // of about one pass
+  const double target = 0.1 * s->opt.rtol * bn;
   ppe_status status = PPE_OK;
   const int max_outer = 50;
   while (rn > target) {
