@@ -228,7 +228,7 @@ ppe_status ppe_solve(ppe_solver* s, const double* rhs, double* p, int use_x0, pp
     ppe::require(s->assembled, PPE_ERR_STATE, "ppe_solve before ppe_assemble");
     ppe::require(rhs && p, PPE_ERR_ARG, "NULL rhs or p");
     PPE_HIP(hipEventRecord(s->ev0, s->stream));
-    ppe_status st = ppe::pcg_solve(s, rhs, p, use_x0);
+    ppe_status st = ppe::pcg_solve(s, rhs, p, use_x0, &s->pred_solve);
     s->solves_since_assemble += 1;
     PPE_HIP(hipEventRecord(s->ev1, s->stream));
     PPE_HIP(hipEventSynchronize(s->ev1));

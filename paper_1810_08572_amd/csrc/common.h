@@ -187,6 +187,7 @@ struct ppe_solver {
   size_t box_words = 0;
   uint32_t box_tag = 0;
   hipEvent_t chk_ev[2] = {nullptr, nullptr};  // PCG convergence checks in flight
+  int pred_solve = 0, pred_inner = 0;  // iterations of the last solve / projection inner solve
   // autotuner choices per (level, FP32, quarter-octave bins of rows and of
   // entries): {lpr_a, fuse0, lpr_r, lpr_p}
   std::map<std::array<int, 4>, std::array<int, 4>> tune_cache;
@@ -433,7 +434,10 @@ void spmv(ppe_solver* s, const Level& L, const double* x, double* y);
 // L after iters steps from the seeded start vector); stays on the device.
 void power_estimate(ppe_solver* s, Level& L, uint32_t salt, int iters, double scale, double* out);
 void vcycle(ppe_solver* s, int level, const double* b, double* x);
-ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p, int use_x0);
+// pred: iterations the previous solve of this kind took (0: unknown), updated
+// on return; the convergence checks run ahead of the device only while the
+// queued work stays short of it.  NULL: always run ahead.
+ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p, int use_x0, int* pred = nullptr);
 void prepare_solve_levels(ppe_solver* s);
 void make_fp32_hierarchy(ppe_solver* s);
 // Time the candidate launch choices of every level's solve kernels and keep

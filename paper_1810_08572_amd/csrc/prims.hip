@@ -91,21 +91,26 @@ __global__ void __launch_bounds__(kBlock) k_scan_down(const int* __restrict__ in
 }
 
 // Exclusive scan of n <= kSmallScan counts by one block of kSmallBlock
-// threads, each owning a run of consecutive items: out[0..n], *total.
+// threads: the counts are staged in LDS with coalesced loads, each thread
+// scans a run of consecutive items there, and the offsets leave through LDS
+// with coalesced stores.  out[0..n], *total.
 constexpr int kSmallBlock = 1024;
-constexpr int kSmallItems = 16;
+constexpr int kSmallItems = 15;  // staging buffer + wave sums stay under 64 KiB of LDS
 constexpr int kSmallScan = kSmallBlock * kSmallItems;
 
 __global__ void __launch_bounds__(kSmallBlock) k_scan_small(const int* __restrict__ in, int n,
                                                             int* __restrict__ out,
                                                             long long* __restrict__ total) {
+  __shared__ int buf[kSmallScan];
   __shared__ long long wsum[kSmallBlock / kWave];
+  for (int i = threadIdx.x; i < n; i += kSmallBlock) buf[i] = in[i];
+  __syncthreads();
   const int per = (n + kSmallBlock - 1) / kSmallBlock;  // <= kSmallItems
   const int base = threadIdx.x * per;
   long long run = 0;
   for (int k = 0; k < per; ++k) {
     const int i = base + k;
-    if (i < n) run += in[i];
+    if (i < n) run += buf[i];
   }
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const long long inc = wave_incl_scan(run);
@@ -121,10 +126,13 @@ __global__ void __launch_bounds__(kSmallBlock) k_scan_small(const int* __restric
   for (int k = 0; k < per; ++k) {
     const int i = base + k;
     if (i < n) {
-      out[i] = (int)pos;
-      pos += in[i];
+      const int v = buf[i];
+      buf[i] = (int)pos;  // this thread's own items only: no other thread reads them now
+      pos += v;
     }
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kSmallBlock) out[i] = buf[i];
   if (threadIdx.x == 0) {
     out[n] = (int)tot;
     *total = tot;

@@ -554,7 +554,7 @@ ppe_status project(ppe_solver* s, const double* coeff, const double* ustar, doub
     ppe_status ist;
     {
       RtolGuard g(s, inner);
-      ist = pcg_solve(s, r, delta, 0);
+      ist = pcg_solve(s, r, delta, 0, &s->pred_inner);
     }
     s->solves_since_assemble += 1;
     st.pcg_iterations += s->stats.iterations;

@@ -938,7 +938,7 @@ void capture_iterations(ppe_solver* s, F&& issue) {
   s->graph_ok = true;
 }
 
-ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0) {
+ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0, int* pred) {
   const int na = s->n_active, nc = s->n_cells, ns = s->n_seg, nt = s->n_tiles;
   ppe_stats& st = s->stats;
   st.iterations = 0;
@@ -1041,6 +1041,7 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
     }
     st.rel_residual = worst;
     st.iterations = itmax;
+    if (pred) *pred = itmax;
     return status;
   };
 
@@ -1087,7 +1088,11 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
   const int max_iter = s->opt.max_iter, every = s->opt.check_every;
   // Convergence checks run one chunk behind: chunk c+1 is queued before the
   // host waits for the counts of chunk c, so the device does not idle during
-  // the round trip.  A chunk queued after convergence changes nothing.
+  // the round trip.  A chunk queued after convergence changes nothing, but
+  // its V-cycles still run: with a prediction of the iteration count (the
+  // previous solve's), work is queued ahead only while it stays two
+  // iterations short of it, and each chunk after that is checked before the
+  // next is queued.
   for (auto& e : s->chk_ev)
     if (!e) PPE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   struct Check {
@@ -1114,8 +1119,10 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
     pend[npend++] = Check{h, next_ev, it};
     next_ev = 1 - next_ev;
   };
+  const int expect = pred ? *pred : 0;
+  auto run_ahead = [&]() { return expect <= 0 || it + 2 <= expect - 2; };
   for (;;) {
-    while (npend < 2 && it < max_iter) launch_chunk();
+    while (it < max_iter && (npend == 0 || (npend < 2 && run_ahead()))) launch_chunk();
     if (npend == 0) break;
     const Check c = pend[0];
     pend[0] = pend[1];
