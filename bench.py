@@ -443,6 +443,88 @@ def uq_batched(ppe, torch, dev, n_samples=256, steps=3, warm=1):
                 precision="mixed")
 
 
+def uq_collocation(ppe, torch, dev, side=32, level=6, degree=5, n_test=60):
+    """The paper's uncertainty wrapper on the batched solver: three inputs
+    (melt and wall temperature normal, liquidus shift uniform), the full
+    tensor grid of `level` Gauss points per input (216 samples at level 6,
+    the paper's three-input size), one batched assembly and solve of all
+    samples on identical side^3 meshes, a total-degree polynomial-chaos fit
+    of the whole pressure field, its statistics, and the paper's check on
+    Latin-hypercube test points (RMS of expansion minus simulation over the
+    largest pressure magnitude)."""
+    import numpy as np
+
+    from synth import box_mesh, concat_meshes, face_coeff, latin_hypercube, rhs_smooth_series, \
+        uq_front_fl
+
+    kinds = ["normal", "normal", "uniform"]
+    q = ppe.PolynomialChaos(kinds, degree)
+    m = box_mesh((side,) * 3, lengths=(CAVITY,) * 3, jitter=0.1, seed=0)
+    t, t_end = 30 * DT, 50 * DT
+
+    def fields(X):
+        fls, bs = [], []
+        for x in X:
+            sm = dict(t_melt=950.0 + 10.0 * x[0], t_wall=600.0 + 20.0 * x[1], d_liq=5.0 * x[2])
+            f = uq_front_fl(m.cell_centre, sm, t, t_end, length=CAVITY)
+            fls.append(f)
+            bs.append(rhs_smooth_series(m.cell_centre, t, seed=RHS_SEED, center_mask=f > 0))
+        return np.concatenate(fls), np.concatenate(bs)
+
+    def batch(X):
+        u = concat_meshes([m] * X.shape[0])
+        s = ppe.Solver(precision="mixed")
+        s.set_mesh(u.n_cells, torch.as_tensor(u.owner, device=dev), torch.as_tensor(u.neigh, device=dev))
+        s.set_segments(u.extra["cell_offsets"])
+        fl, b = fields(X)
+        return s, torch.as_tensor(face_coeff(u, RHO), device=dev), torch.as_tensor(fl, device=dev), \
+            torch.as_tensor(b, device=dev)
+
+    X, _ = q.nodes("tensor", level)
+    s, c, fl, b = batch(X)
+    s.assemble(c, fl)  # warm-up assembly and solve
+    s.solve(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.assemble(c, fl)
+    res = s.solve(b)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    its, rr = s.segment_stats()
+    Y = res.p.reshape(X.shape[0], m.n_cells)
+    q.fit(X, Y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    W = q.fit(X, Y)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t0
+    mean, var, first, total = q.stats(W)
+    T, _ = latin_hypercube(kinds, n_test, seed=17)
+    s2, c2, fl2, b2 = batch(T)
+    s2.assemble(c2, fl2)
+    Yt = s2.solve(b2).p.reshape(n_test, m.n_cells)
+    Ye = q.eval(T, W)
+    rms = float(torch.sqrt(((Ye - Yt) ** 2).mean()) / Yt.abs().max())
+    varying = var > 1e-6 * var.max()
+    return {
+        "workload": f"3 inputs (T_melt ~ N(950,10), T_wall ~ N(600,20), dT_liq ~ U(-5,5)), tensor grid of "
+                    f"{level} Gauss points per input ({X.shape[0]} samples) on {side}^3 cubes, one "
+                    f"batched assembly + solve (mixed precision), total-degree-{degree} expansion "
+                    f"({q.n_terms} terms) of every cell's pressure",
+        "samples": int(X.shape[0]),
+        "cells": int(X.shape[0] * m.n_cells),
+        "sample_solves_per_s": X.shape[0] / t_solve,
+        "batch_ms": 1e3 * t_solve,
+        "mean_sample_iterations": float(np.mean(its)),
+        "worst_rel_residual": float(max(rr)),
+        "fit_ms": 1e3 * t_fit,
+        "fit_gb_per_s": X.shape[0] * m.n_cells * 8 / t_fit / 1e9,
+        "lhs_test_points": n_test,
+        "lhs_rms_error_rel_to_max": rms,
+        "mean_total_sobol_of_varying_cells": [float(total[j][varying].mean()) for j in range(3)],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -455,6 +537,8 @@ def main():
     ap.add_argument("--no-c5", action="store_true", help="skip the plate-with-ribs leg")
     ap.add_argument("--no-projection", action="store_true",
                     help="skip the cross-diffusion pressure-correction leg")
+    ap.add_argument("--no-uq-collocation", action="store_true",
+                    help="skip the polynomial-chaos collocation leg")
     ap.add_argument("--projection-only", action="store_true",
                     help="time the FP64 leg and the pressure-correction leg only (for profiling)")
     ap.add_argument("--uq", action="store_true", help="add the batched-UQ measurement")
@@ -556,6 +640,9 @@ def main():
             variants["projection_cross_diffusion"] = projection_leg(ppe, torch, wl, d_in, steps,
                                                                     warm, dev, base)
             note("projection leg done")
+        if not args.no_uq_collocation:
+            variants["uq_collocation"] = uq_collocation(ppe, torch, dev)
+            note("collocation leg done")
         if not args.no_c3:
             variants["c3_128cube"] = c3_leg(ppe, torch, dev)
             note("128^3 leg done")

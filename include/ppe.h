@@ -320,6 +320,52 @@ ppe_status ppe_warm_start_apply(ppe_solver* s, const double* p_prev, const float
 ppe_status ppe_warm_start_targets(ppe_solver* s, const double* p_new, const double* p_prev,
                                   double dp_scale, float* targets);
 
+/* ---- Polynomial chaos by stochastic collocation (section 3, Eq. 27-28). ----
+ * The wrapper the paper puts around its deterministic simulations: an
+ * expansion w(x, xi) ~ sum_i w_i(x) Psi_i(xi) in products of polynomials
+ * orthonormal under each input's distribution (probabilists' Hermite for a
+ * standard normal input, Legendre for a uniform input on [-1, 1]) over all
+ * multi-indices of total degree <= degree, fitted by least squares to
+ * outputs at M sample points (the Vandermonde system of Eq. 28), for every
+ * output (e.g. every cell of a field) at once.  Sample points: the full
+ * tensor product of l-point Gauss rules, or Smolyak's sparse combination of
+ * Gauss rules of accuracy level l (exact for total degree 2l - 1).  Standard
+ * inputs xi are mapped to physical ones by the caller (e.g. T = mu + sigma
+ * xi).  Host arrays are marked; everything else is device memory. */
+typedef struct ppe_pce ppe_pce;
+enum { PPE_INPUT_NORMAL = 0, PPE_INPUT_UNIFORM = 1 };
+enum { PPE_GRID_TENSOR = 0, PPE_GRID_SMOLYAK = 1 };
+
+/* d inputs (1..16) of the given kinds (host array); degree 0..30.  stream:
+ * hipStream_t for the device work (NULL = default). */
+ppe_status ppe_pce_create(int32_t d, const int32_t* kinds, int32_t degree, void* stream,
+                          ppe_pce** out);
+void ppe_pce_destroy(ppe_pce* q);
+int32_t ppe_pce_num_terms(const ppe_pce* q);
+const char* ppe_pce_last_error(const ppe_pce* q);
+/* Multi-indices of the basis, graded order (host, [n_terms x d]). */
+ppe_status ppe_pce_terms(const ppe_pce* q, int32_t* alpha);
+/* Sample points of accuracy level 1..20 (host arrays): with nodes == NULL,
+ * *n_nodes receives the count; otherwise *n_nodes is the capacity and
+ * nodes[n x d] and weights[n] (probability weights, may be NULL) are
+ * filled.  Coincident nodes of the Smolyak combination are merged. */
+ppe_status ppe_pce_nodes(ppe_pce* q, int32_t grid, int32_t level, int32_t* n_nodes, double* nodes,
+                         double* weights);
+/* W[n_terms x n_out] = least-squares solution of V W = Y, with V the
+ * Vandermonde matrix of the M >= n_terms points xi (host, [M x d]) and
+ * Y[M x n_out] the outputs (row m = the simulation at point m).
+ * PPE_ERR_ARG if V is rank deficient. */
+ppe_status ppe_pce_fit(ppe_pce* q, int32_t M, const double* xi, int64_t n_out, const double* Y,
+                       double* W);
+/* Y[T x n_out] = the expansion W evaluated at T points xi (host, [T x d]). */
+ppe_status ppe_pce_eval(ppe_pce* q, int32_t T, const double* xi, int64_t n_out, const double* W,
+                        double* Y);
+/* Per output: mean = W_0, variance = sum_{i>0} W_i^2, and per input j the
+ * first-order Sobol index (terms in input j alone) and the total index
+ * (terms involving j) as shares of the variance: first, total [d x n_out]. */
+ppe_status ppe_pce_stats(ppe_pce* q, int64_t n_out, const double* W, double* mean, double* var,
+                         double* first, double* total);
+
 /* ---- Measurement of the dominant kernel. ----
  * While enabled, every launch of the finest-level fused Chebyshev smoothing
  * kernel (the operator applied most often per PCG iteration) is bracketed by

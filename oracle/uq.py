@@ -19,8 +19,6 @@ uncertainty wrapper (test infrastructure only; the product path never uses it).
 * Statistics of the expansion: mean w_0, variance sum_{i>0} w_i^2; Sobol
   indices (first order: terms in that input alone; total: every term that
   involves it) as shares of the variance.
-* Latin hypercube test points: one sample in each of the m equal-probability
-  strata of every input, strata paired by independent permutations.
 """
 from __future__ import annotations
 
@@ -30,7 +28,6 @@ from math import comb, factorial, sqrt
 import numpy as np
 from numpy.polynomial.hermite_e import hermegauss, hermeval
 from numpy.polynomial.legendre import leggauss, legval
-from scipy.special import ndtri
 
 NORMAL, UNIFORM = "normal", "uniform"
 
@@ -154,17 +151,3 @@ def statistics(alphas, W):
         first = np.where(var > 0, first / var, 0.0)
         total = np.where(var > 0, total / var, 0.0)
     return mean, var, first, total
-
-
-def latin_hypercube(kinds, m, seed):
-    """m points, one per equal-probability stratum of every input, mapped to
-    the standard input through its inverse distribution function."""
-    rng = np.random.default_rng(seed)
-    d = len(kinds)
-    U = np.empty((m, d))
-    for j in range(d):
-        U[:, j] = (rng.permutation(m) + rng.uniform(size=m)) / m
-    X = np.empty_like(U)
-    for j, kind in enumerate(kinds):
-        X[:, j] = ndtri(U[:, j]) if kind == NORMAL else 2.0 * U[:, j] - 1.0
-    return X, U

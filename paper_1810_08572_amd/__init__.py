@@ -121,6 +121,15 @@ _SIGS = {
     "ppe_project": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_double, _P, _P, _P,
                                    ctypes.POINTER(ppe_project_stats)]),
     "ppe_face_gradient": (ctypes.c_int, [_P, _P, ctypes.c_double, _P, _P, _P]),
+    "ppe_pce_create": (ctypes.c_int, [_I32, ctypes.POINTER(_I32), _I32, _P, ctypes.POINTER(_P)]),
+    "ppe_pce_destroy": (None, [_P]),
+    "ppe_pce_num_terms": (_I32, [_P]),
+    "ppe_pce_last_error": (ctypes.c_char_p, [_P]),
+    "ppe_pce_terms": (ctypes.c_int, [_P, ctypes.POINTER(_I32)]),
+    "ppe_pce_nodes": (ctypes.c_int, [_P, _I32, _I32, ctypes.POINTER(_I32), _P, _P]),
+    "ppe_pce_fit": (ctypes.c_int, [_P, _I32, _P, ctypes.c_int64, _P, _P]),
+    "ppe_pce_eval": (ctypes.c_int, [_P, _I32, _P, ctypes.c_int64, _P, _P]),
+    "ppe_pce_stats": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, _P, _P, _P]),
     "ppe_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "ppe_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double),
@@ -521,6 +530,100 @@ class WarmStartNet:
             self._h, n, _dev_ptr(x, torch.float32, n * self.n_in, "x"),
             _dev_ptr(t, torch.float32, n, "t"), ctypes.c_float(lr), ctypes.byref(loss)))
         return loss.value
+
+
+PPE_INPUT_NORMAL, PPE_INPUT_UNIFORM = 0, 1
+PPE_GRID_TENSOR, PPE_GRID_SMOLYAK = 0, 1
+
+
+class PolynomialChaos:
+    """Polynomial chaos by stochastic collocation (section 3): inputs
+    "normal" (standard normal) or "uniform" (on [-1, 1]), total degree."""
+
+    def __init__(self, kinds, degree, stream=None):
+        import numpy as np
+
+        self._lib = load_library()
+        k = [PPE_INPUT_NORMAL if x == "normal" else PPE_INPUT_UNIFORM for x in kinds]
+        arr = (_I32 * len(k))(*k)
+        h = _P()
+        st = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+        _check(self._lib.ppe_pce_create(len(k), arr, int(degree), st, ctypes.byref(h)))
+        self._h = h
+        self.d = len(k)
+        self.n_terms = int(self._lib.ppe_pce_num_terms(h))
+        a = np.zeros(self.n_terms * self.d, dtype=np.int32)
+        self._chk(self._lib.ppe_pce_terms(h, a.ctypes.data_as(ctypes.POINTER(_I32))))
+        self.terms = a.reshape(self.n_terms, self.d)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ppe_pce_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def _chk(self, st):
+        if st != PPE_OK:
+            raise PpeError(st, f"{self._lib.ppe_status_string(st).decode()}: "
+                               f"{self._lib.ppe_pce_last_error(self._h).decode()}")
+
+    def nodes(self, grid, level):
+        """(nodes [n, d], probability weights [n]) as numpy arrays; grid
+        "tensor" or "smolyak"."""
+        import numpy as np
+
+        g = PPE_GRID_TENSOR if grid == "tensor" else PPE_GRID_SMOLYAK
+        n = _I32(0)
+        self._chk(self._lib.ppe_pce_nodes(self._h, g, int(level), ctypes.byref(n), None, None))
+        X = np.zeros((n.value, self.d))
+        w = np.zeros(n.value)
+        self._chk(self._lib.ppe_pce_nodes(self._h, g, int(level), ctypes.byref(n),
+                                          X.ctypes.data_as(_P), w.ctypes.data_as(_P)))
+        return X, w
+
+    def fit(self, xi, Y):
+        """W [n_terms, n_out] from outputs Y [M, n_out] (device) at points xi [M, d] (host)."""
+        import numpy as np
+        import torch
+
+        xi = np.ascontiguousarray(xi, dtype=np.float64)
+        M, n_out = Y.shape
+        W = torch.empty((self.n_terms, n_out), dtype=torch.float64, device=Y.device)
+        self._chk(self._lib.ppe_pce_fit(self._h, M, xi.ctypes.data_as(_P), n_out,
+                                        _dev_ptr(Y, torch.float64, M * n_out, "Y"),
+                                        ctypes.c_void_p(W.data_ptr())))
+        return W
+
+    def eval(self, xi, W):
+        import numpy as np
+        import torch
+
+        xi = np.ascontiguousarray(xi, dtype=np.float64)
+        T = xi.shape[0]
+        n_out = W.shape[1]
+        Y = torch.empty((T, n_out), dtype=torch.float64, device=W.device)
+        self._chk(self._lib.ppe_pce_eval(self._h, T, xi.ctypes.data_as(_P), n_out,
+                                         _dev_ptr(W, torch.float64, self.n_terms * n_out, "W"),
+                                         ctypes.c_void_p(Y.data_ptr())))
+        return Y
+
+    def stats(self, W):
+        """(mean, variance, first-order Sobol [d, n_out], total Sobol [d, n_out])."""
+        import torch
+
+        n_out = W.shape[1]
+        dev = W.device
+        mean = torch.empty(n_out, dtype=torch.float64, device=dev)
+        var = torch.empty(n_out, dtype=torch.float64, device=dev)
+        first = torch.empty((self.d, n_out), dtype=torch.float64, device=dev)
+        total = torch.empty((self.d, n_out), dtype=torch.float64, device=dev)
+        self._chk(self._lib.ppe_pce_stats(self._h, n_out,
+                                          _dev_ptr(W, torch.float64, self.n_terms * n_out, "W"),
+                                          ctypes.c_void_p(mean.data_ptr()), ctypes.c_void_p(var.data_ptr()),
+                                          ctypes.c_void_p(first.data_ptr()),
+                                          ctypes.c_void_p(total.data_ptr())))
+        return mean, var, first, total
 
 
 def warm_start_features(solver, dp_prev, rhs, face_coeff, fl, cell_volume, mu, sigma):

@@ -16,6 +16,7 @@ from .fields import (
     uq_front_fl,
     rhs_smooth_series,
     ustar_smooth_series,
+    latin_hypercube,
     mlp_initial_weights,
 )
 
@@ -33,5 +34,6 @@ __all__ = [
     "uq_front_fl",
     "rhs_smooth_series",
     "ustar_smooth_series",
+    "latin_hypercube",
     "mlp_initial_weights",
 ]

@@ -131,3 +131,23 @@ def mlp_initial_weights(n_in=10, width=128, n_hidden=3, seed=0):
         parts.append(rng.uniform(-lim, lim, size=fan_out * fan_in))
         parts.append(rng.uniform(-lim, lim, size=fan_out))
     return np.concatenate(parts)
+
+
+def latin_hypercube(kinds, m, seed):
+    """Latin-hypercube test points of the uncertainty wrapper: m points, one
+    in each of the m equal-probability strata of every input (strata paired
+    by independent seeded permutations), mapped to the standard input
+    ("normal": standard normal, through the inverse distribution function;
+    "uniform": on [-1, 1]).  Returns the points [m, d] and the underlying
+    uniforms [m, d]."""
+    from scipy.special import ndtri
+
+    rng = np.random.default_rng(seed)
+    d = len(kinds)
+    U = np.empty((m, d))
+    for j in range(d):
+        U[:, j] = (rng.permutation(m) + rng.uniform(size=m)) / m
+    X = np.empty_like(U)
+    for j, kind in enumerate(kinds):
+        X[:, j] = ndtri(U[:, j]) if kind == "normal" else 2.0 * U[:, j] - 1.0
+    return X, U
