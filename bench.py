@@ -121,14 +121,15 @@ def cpu_baseline(wl, steps, budget_s=20.0):
 
 
 def run_leg(ppe, torch, wl, d_in, steps, warm, precision, guess="zero", net=None,
-            autotune=False):
+            autotune=False, reuse=False):
     """Solve warm + steps timesteps; time the last len(steps).  guess: "zero",
     "prev" (the previous step's pressure) or "learned" (net = (network, mu,
     sigma) predicts the increment from the previous step).  autotune: the
     library times its per-level launch choices at assembly (cached by level
-    shape; the warmup steps take the first tunings)."""
+    shape; the warmup steps take the first tunings).  reuse: assemblies that
+    find the mask and coefficients unchanged keep the system and hierarchy."""
     m, dev = wl.m, d_in["coeff"].device
-    s = ppe.Solver(precision=precision, autotune=autotune)
+    s = ppe.Solver(precision=precision, autotune=autotune, reuse_unchanged=reuse)
     s.set_mesh(m.n_cells, d_in["owner"], d_in["neigh"])
     p_prev = torch.zeros(m.n_cells, dtype=torch.float64, device=dev)
     dp_prev = torch.zeros_like(p_prev)
@@ -636,6 +637,13 @@ def main():
                      net=(net, mu, sigma))
         variants["mixed_learned"] = dict(leg_summary(ml, K, base), training=tr)
         note(f"mixed+learned leg: {K / ml['elapsed']:.1f} solves/s")
+        ru = run_leg(ppe, torch, wl, d_in, steps, warm, "fp64", reuse=True)
+        variants["fp64_reuse_unchanged"] = dict(
+            leg_summary(ru, K, base),
+            reused_assemblies=int(ru["solver"].stats()["reused_setup"]),
+            note="the same timesteps (reused_assemblies counts warmup and timed steps); an assembly whose mask and coefficients equal the previous "
+                 "one's keeps the system and hierarchy (the matrix depends on nothing else)")
+        note(f"fp64 reuse leg: {K / ru['elapsed']:.1f} solves/s")
         if not args.no_projection:
             variants["projection_cross_diffusion"] = projection_leg(ppe, torch, wl, d_in, steps,
                                                                     warm, dev, base)

@@ -81,6 +81,12 @@ typedef struct {
                          shape.  Lanes per row change the order of the row sums,
                          so results then depend on the choices (to rounding).
                          Default 0: fixed rules, bitwise reproducible. */
+  int reuse_unchanged; /* 1: ppe_assemble first compares the face coefficients and
+                         the removed-cell mask (liquid fraction > 0 or not; the
+                         matrix depends on nothing else) with the previous
+                         successful assembly's, and keeps the masked system, the
+                         AMG hierarchy and captured graphs when both are
+                         unchanged.  Default 0: every assembly rebuilds. */
 } ppe_options;
 
 typedef struct {
@@ -93,6 +99,7 @@ typedef struct {
   int levels;            /* AMG levels including the finest */
   double op_complexity;  /* sum of level nnz / finest nnz */
   double bytes_per_iter; /* algorithmic bytes one PCG iteration moves */
+  int reused_setup;      /* assemblies that kept an unchanged system (reuse_unchanged) */
 } ppe_stats;
 
 /* Fill *opt with the defaults listed above. */

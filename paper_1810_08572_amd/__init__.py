@@ -43,6 +43,7 @@ class ppe_options(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("use_graph", ctypes.c_int),
         ("autotune", ctypes.c_int),
+        ("reuse_unchanged", ctypes.c_int),
     ]
 
 
@@ -57,6 +58,7 @@ class ppe_stats(ctypes.Structure):
         ("levels", ctypes.c_int),
         ("op_complexity", ctypes.c_double),
         ("bytes_per_iter", ctypes.c_double),
+        ("reused_setup", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -237,7 +239,7 @@ class Solver:
 
     def __init__(self, precision="fp64", rtol=1e-10, max_iter=500, cheb_degree=2,
                  cheb_ratio=30.0, coarse_max=128, max_levels=10, theta=0.08, stream=None,
-                 use_graph=True, check_every=2, autotune=False):
+                 use_graph=True, check_every=2, autotune=False, reuse_unchanged=False):
         import torch
 
         lib = load_library()
@@ -247,6 +249,7 @@ class Solver:
         o.coarse_max, o.max_levels, o.theta = coarse_max, max_levels, theta
         o.use_graph, o.check_every = int(bool(use_graph)), int(check_every)
         o.autotune = int(bool(autotune))
+        o.reuse_unchanged = int(bool(reuse_unchanged))
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

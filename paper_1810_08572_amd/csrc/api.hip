@@ -98,6 +98,7 @@ void ppe_default_options(ppe_options* o) {
   o->stream = nullptr;
   o->use_graph = 1;
   o->autotune = 0;
+  o->reuse_unchanged = 0;
 }
 
 ppe_status ppe_create(const ppe_options* opt, ppe_solver** out) {
@@ -171,6 +172,7 @@ ppe_status ppe_set_mesh(ppe_solver* s, int32_t n_cells, int32_t n_faces, const i
     ppe::require(n_faces == 0 || (owner && neigh), PPE_ERR_ARG, "owner/neigh is NULL");
     s->have_mesh = false;
     s->geom_ok = false;
+    s->have_prev = false;
     s->assembled = false;
     s->n_cells = n_cells;
     s->n_faces = n_faces;
@@ -188,10 +190,20 @@ ppe_status ppe_assemble(ppe_solver* s, const double* face_coeff, const double* f
     DeviceGuard g(s->device);
     ppe::require(s->have_mesh, PPE_ERR_STATE, "ppe_assemble before ppe_set_mesh");
     ppe::require(fl && (face_coeff || s->n_faces == 0), PPE_ERR_ARG, "NULL input array");
+    PPE_HIP(hipEventRecord(s->ev0, s->stream));
+    if (s->opt.reuse_unchanged && s->have_prev && ppe::same_system(s, face_coeff, fl)) {
+      // the masked system, its hierarchy and captured graphs stay valid
+      s->assembled = true;
+      s->stats.reused_setup += 1;
+      PPE_HIP(hipEventRecord(s->ev1, s->stream));
+      PPE_HIP(hipEventSynchronize(s->ev1));
+      s->stats.setup_ms = elapsed_ms(s->ev0, s->ev1);
+      return PPE_OK;
+    }
     s->assembled = false;
+    s->have_prev = false;
     s->solves_since_assemble = 0;
     ppe::drop_graph(s);
-    PPE_HIP(hipEventRecord(s->ev0, s->stream));
     ppe::assemble_fine(s, face_coeff, fl);
     if (s->n_active > 0) {
       ppe::build_hierarchy(s);
@@ -216,6 +228,15 @@ ppe_status ppe_assemble(ppe_solver* s, const double* face_coeff, const double* f
     for (int l = 0; l < s->nlev; ++l) tot += s->levels[l].A.nnz;
     s->stats.op_complexity = nnz0 > 0 ? tot / nnz0 : 1.0;
     s->stats.bytes_per_iter = s->n_active > 0 ? bytes_per_iteration(s) : 0.0;
+    if (s->opt.reuse_unchanged) {
+      // the coefficients this system was built from, for the next comparison
+      double* pc = s->prev_coeff.get<double>(s->n_faces > 0 ? s->n_faces : 1);
+      if (s->n_faces)
+        PPE_HIP(hipMemcpyAsync(pc, face_coeff, sizeof(double) * s->n_faces, hipMemcpyDeviceToDevice,
+                               s->stream));
+      PPE_HIP(hipStreamSynchronize(s->stream));
+      s->have_prev = true;
+    }
     s->assembled = true;
     return PPE_OK;
   });
@@ -309,6 +330,7 @@ ppe_status ppe_set_segments(ppe_solver* s, int32_t n_samples, const int32_t* off
     s->n_seg = n_samples;
     s->seg_cell_off = o;
     s->assembled = false;
+    s->have_prev = false;
     return PPE_OK;
   });
 }

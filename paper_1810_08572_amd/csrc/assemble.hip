@@ -388,6 +388,38 @@ void build_topology(ppe_solver* s, const int32_t* owner, const int32_t* neigh) {
   require(read_scalar(s, flag) == 0, PPE_ERR_ARG, "two faces join the same pair of cells");
 }
 
+namespace {
+// bit 4 of *flag: a coefficient of an interior face or a cell's mask differs
+// from the stored ones
+__global__ void k_same_system(const double* __restrict__ coeff, const double* __restrict__ prev,
+                              const int* __restrict__ neigh, int nf, const double* __restrict__ fl,
+                              const int* __restrict__ active, int nc, int* __restrict__ flag) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  bool diff = false;
+  if (i < nf && neigh[i] >= 0 && coeff[i] != prev[i]) diff = true;
+  if (i < nc && ((fl[i] > 0.0 ? 1 : 0) != active[i])) diff = true;
+  if (diff) atomicOr(flag, 4);
+}
+}  // namespace
+
+bool same_system(ppe_solver* s, const double* coeff, const double* fl) {
+  const int nc = s->n_cells, nf = s->n_faces;
+  int* flag = s->flag.get<int>(1);
+  fill_int(s, flag, 0, 1);
+  const int g = grid_for(nf > nc ? nf : nc);
+  hipLaunchKernelGGL(k_check_fields, dim3(g), dim3(kBlock), 0, s->stream, coeff, s->neigh.as<int>(),
+                     nf, fl, nc, flag);
+  PPE_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_same_system, dim3(g), dim3(kBlock), 0, s->stream, coeff,
+                     s->prev_coeff.as<double>(), s->neigh.as<int>(), nf, fl, s->active.as<int>(), nc,
+                     flag);
+  PPE_LAUNCH_CHECK();
+  const int bad = read_scalar(s, flag);
+  require(!(bad & 1), PPE_ERR_ARG, "face coefficient must be finite and > 0 on interior faces");
+  require(!(bad & 2), PPE_ERR_ARG, "liquid fraction must be finite and in [0, 1]");
+  return !(bad & 4);
+}
+
 void assemble_fine(ppe_solver* s, const double* coeff, const double* fl) {
   const int nc = s->n_cells, nf = s->n_faces, ns = s->n_seg;
   int* flag = s->flag.get<int>(1);

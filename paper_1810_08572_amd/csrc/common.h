@@ -188,6 +188,10 @@ struct ppe_solver {
   uint32_t box_tag = 0;
   hipEvent_t chk_ev[2] = {nullptr, nullptr};  // PCG convergence checks in flight
   int pred_solve = 0, pred_inner = 0;  // iterations of the last solve / projection inner solve
+  // reuse of an unchanged system: the coefficients of the last successful
+  // assembly (its mask is `active`)
+  bool have_prev = false;
+  ppe::DevBuf prev_coeff;
   // autotuner choices per (level, FP32, quarter-octave bins of rows and of
   // entries): {lpr_a, fuse0, lpr_r, lpr_p}
   std::map<std::array<int, 4>, std::array<int, 4>> tune_cache;
@@ -422,6 +426,9 @@ void fill_double(ppe_solver* s, double* p, double v, int64_t n);
 void build_topology(ppe_solver* s, const int32_t* owner, const int32_t* neigh);
 void check_segments(ppe_solver* s, const std::vector<int>& off);
 void assemble_fine(ppe_solver* s, const double* coeff, const double* fl);
+// Checks the fields (raising PPE_ERR_ARG as the assembly does) and returns
+// whether the coefficients and the mask equal those of the last assembly.
+bool same_system(ppe_solver* s, const double* coeff, const double* fl);
 
 // amg.hip
 void build_hierarchy(ppe_solver* s);

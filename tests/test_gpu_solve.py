@@ -143,3 +143,45 @@ def test_every_launch_choice_meets_bars_and_repeats_after_reassembly():
         assert assembly.relative_residual(sy, b, outs[0]) <= 1e-10, (lvl, ch)
         assert np.linalg.norm(outs[0] - pref) <= 1e-9 * np.linalg.norm(pref), (lvl, ch)
         assert np.array_equal(outs[0], outs[1]), (lvl, ch)
+
+
+def test_reuse_of_an_unchanged_system():
+    """reuse_unchanged: an assembly whose coefficients and mask equal the
+    last one's keeps the system (liquid-fraction values may change); any
+    change of the mask or of a coefficient rebuilds.  Every result equals a
+    fresh solver's bitwise."""
+    import torch
+
+    import paper_1810_08572_amd as ppe
+
+    m, f, c, b = case(shape=(20, 18, 16), fl="front", fl_seed=3, seed=1)
+    bd = to_dev(b, torch.float64)
+
+    def fresh(cc, ff):
+        return gpu_solver(m, ff, cc).solve(bd).p.cpu().numpy()
+
+    s = gpu_solver(m, f, c, reuse_unchanged=True)
+    p0 = s.solve(bd).p.cpu().numpy()
+    assert s.stats()["reused_setup"] == 0
+    f2 = np.where(f > 0, 0.5 * f + 0.25, 0.0)  # same mask, other values
+    s.assemble(to_dev(c, torch.float64), to_dev(f2, torch.float64))
+    assert s.stats()["reused_setup"] == 1
+    assert np.array_equal(s.solve(bd).p.cpu().numpy(), p0)
+    assert np.array_equal(p0, fresh(c, f))
+    f3 = f.copy()
+    f3[np.nonzero(f > 0)[0][7]] = 0.0  # one more cell removed
+    s.assemble(to_dev(c, torch.float64), to_dev(f3, torch.float64))
+    assert s.stats()["reused_setup"] == 1
+    assert np.array_equal(s.solve(bd).p.cpu().numpy(), fresh(c, f3))
+    c4 = c.copy()
+    c4[np.nonzero(m.neigh >= 0)[0][11]] *= 1.5
+    s.assemble(to_dev(c4, torch.float64), to_dev(f3, torch.float64))
+    assert s.stats()["reused_setup"] == 1
+    assert np.array_equal(s.solve(bd).p.cpu().numpy(), fresh(c4, f3))
+    s.assemble(to_dev(c4, torch.float64), to_dev(f3, torch.float64))
+    assert s.stats()["reused_setup"] == 2
+    bad = f3.copy()
+    bad[0] = 2.0
+    with pytest.raises(ppe.PpeError) as e:
+        s.assemble(to_dev(c4, torch.float64), to_dev(bad, torch.float64))
+    assert e.value.status == ppe.PPE_ERR_ARG
