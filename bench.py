@@ -114,7 +114,14 @@ def cpu_baseline(wl, steps, budget_s=20.0):
             if time.perf_counter() - t0 > budget_s:
                 break
     dt = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return dict(value=done / dt, unit="solves/s", cores=1, kind="oracle",
+                host_cpu=model, host_logical_cpus=os.cpu_count(),
                 sample=f"{done} consecutive timed timesteps from step {steps[0]} of the 64^3 run: "
                        f"assembly + SA setup + PCG to 1e-10 from zero ({iters} PCG iterations), "
                        f"{dt:.1f} s on one host thread")

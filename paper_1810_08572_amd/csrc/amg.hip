@@ -593,7 +593,8 @@ __global__ void k_transpose_fill(int n, const int* __restrict__ rp, const int* _
 // Sort every row of an unsorted CSR by column into (ci, v): one 64-lane
 // workgroup per row; each entry's destination is the number of smaller keys
 // in its row (keys are distinct within a row).  Rows up to kRankStage
-// entries are compared from LDS.
+// entries are compared from LDS.  (Four rows per workgroup was slower: the
+// barrier waits for the block's longest row.)
 constexpr int kRankStage = 2048;
 __global__ void __launch_bounds__(kWave) k_rank_rows(const int* __restrict__ rp,
                                                      const int* __restrict__ uci,
@@ -932,9 +933,12 @@ void spgemm(ppe_solver* s, const Csr& A, const Csr& B, Csr& C, const int* extra,
   int* counts = s->sp_cnt.get<int>(C.n + 1);
   long long total = 0;
   int fm[2] = {0, 0};
+  // flag[1] starts at 0 (zeroed below): counts are >= 0, so the max needs
+  // no fill of its own unless a bound pass used the slot before
+  bool max_slot_used = false;
   auto fetch_scan = [&](bool with_max) {
     const long long* dtotal = exclusive_scan_async(s, counts, crp, C.n);
-    if (with_max) max_int_async(s, counts, C.n, flag + 1);
+    if (with_max) max_int_async(s, counts, C.n, flag + 1, max_slot_used);
     if (extra)
       read_back(s, {ReadItem{dtotal, sizeof(long long), &total},
                     ReadItem{flag, sizeof(int) * 2, fm}, ReadItem{extra, sizeof(int), extra_host}});
@@ -975,7 +979,8 @@ void spgemm(ppe_solver* s, const Csr& A, const Csr& B, Csr& C, const int* extra,
   } else {
     int* prod = s->sp_prod.get<int>(C.n + 1);
     PPE_ROWS(lanes_for(A), k_spgemm_bound, C.n, C.n, A.rp(), A.ci(), B.rp(), prod);
-    max_int_async(s, prod, C.n, flag + 1);
+    max_int_async(s, prod, C.n, flag + 1, false);
+    max_slot_used = true;
     read_back(s, {ReadItem{flag, sizeof(int) * 2, fm}});
     ub = std::min(fm[1], C.m);
   }

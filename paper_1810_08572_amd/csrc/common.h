@@ -383,7 +383,8 @@ int64_t exclusive_scan(ppe_solver* s, const int* in, int* out, int n);
 long long* exclusive_scan_async(ppe_solver* s, const int* in, int* out, int n, int slot = 0);
 int scan_blocks(int n);
 // *out = max of in[0..n) on the device (no host read)
-void max_int_async(ppe_solver* s, const int* in, int n, int* out);
+// init = false: *out already holds a lower bound (e.g. 0 for counts)
+void max_int_async(ppe_solver* s, const int* in, int n, int* out, bool init = true);
 // Max of an int array.
 int reduce_max_int(ppe_solver* s, const int* in, int n);
 // ---- read-backs through pinned host memory

@@ -214,8 +214,8 @@ int64_t exclusive_scan(ppe_solver* s, const int* in, int* out, int n) {
   return t;
 }
 
-void max_int_async(ppe_solver* s, const int* in, int n, int* out) {
-  fill_int(s, out, INT32_MIN, 1);
+void max_int_async(ppe_solver* s, const int* in, int n, int* out, bool init) {
+  if (init) fill_int(s, out, INT32_MIN, 1);
   int g = grid_for(n);
   if (g > 1024) g = 1024;
   hipLaunchKernelGGL(k_max_int, dim3(g), dim3(kBlock), 0, s->stream, in, n, out);
