@@ -151,3 +151,26 @@ def test_projection_errors():
                    to_dev(m.cell_centre, torch.float64), to_dev(m.face_area, torch.float64))
     p, F, u, st = s.project(to_dev(c, torch.float64), us, RHO, DT)
     assert st["outer"] == 0 and float(p.abs().max()) == 0 and float(F.abs().max()) == 0
+
+
+def test_projection_degenerate_masks():
+    """Every cell solid: p = 0, F = 0, u = 0 without a pass.  Isolated single
+    cells (every active cell its own pocket, hence a pin): no open face, so
+    F = 0 and u = u* on them, p = 0."""
+    import torch
+
+    m = box_mesh((6, 5, 4), jitter=0.1, seed=2)
+    c = face_coeff(m, RHO)
+    us = ustar_smooth_series(m.cell_centre, 0.05, seed=3)
+    s = _solver(m, c, np.zeros(m.n_cells))
+    p, F, u, st = s.project(to_dev(c, torch.float64), to_dev(us, torch.float64), RHO, DT)
+    assert st["outer"] == 0 and float(p.abs().max()) == 0 and float(F.abs().max()) == 0
+    assert float(u.abs().max()) == 0
+    ijk = m.grid_index
+    f = ((ijk.sum(axis=1) % 2) == 0).astype(float)  # checkerboard: no two active cells touch
+    s = _solver(m, c, f)
+    p, F, u, st = s.project(to_dev(c, torch.float64), to_dev(us, torch.float64), RHO, DT)
+    u = u.cpu().numpy()
+    act = f > 0
+    assert float(p.abs().max()) == 0 and float(F.abs().max()) == 0
+    assert np.array_equal(u[act], us[act]) and np.all(u[~act] == 0)

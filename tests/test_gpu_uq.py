@@ -103,3 +103,28 @@ def test_rejects_too_few_or_repeated_points():
     with pytest.raises(ppe.PpeError) as e:
         q.fit(X, to_dev(np.ones((12, 4)), torch.float64))
     assert e.value.status == ppe.PPE_ERR_ARG
+
+
+def test_smallest_expansions():
+    """Degree 0 (the mean only) from one node; one input; the smallest
+    Smolyak grid; a single output column."""
+    import torch
+
+    import paper_1810_08572_amd as ppe
+
+    q = ppe.PolynomialChaos(["normal"], 0)
+    X, w = q.nodes("smolyak", 1)
+    assert X.shape == (1, 1) and X[0, 0] == 0.0 and w[0] == 1.0
+    Y = to_dev(np.array([[3.5, -1.0]]), torch.float64)
+    W = q.fit(X, Y).cpu().numpy()
+    assert np.array_equal(W, np.array([[3.5, -1.0]]))
+    mean, var, first, total = [t.cpu().numpy() for t in q.stats(to_dev(W, torch.float64))]
+    assert np.array_equal(mean, [3.5, -1.0]) and np.all(var == 0) and np.all(total == 0)
+    q = ppe.PolynomialChaos(["uniform"], 4)
+    X, _ = q.nodes("tensor", 5)
+    x = X[:, 0]
+    y = 1.0 + 2.0 * x - 0.5 * x ** 4  # in the span of the basis
+    W = q.fit(X, to_dev(y[:, None], torch.float64))
+    T = np.linspace(-1, 1, 7)[:, None]
+    Ye = q.eval(T, W).cpu().numpy()[:, 0]
+    assert np.abs(Ye - (1.0 + 2.0 * T[:, 0] - 0.5 * T[:, 0] ** 4)).max() <= 1e-13
