@@ -1054,6 +1054,21 @@ void spectral_bound(ppe_solver* s, Level& L, int lvl, double* rho_dev) {
   power_estimate(s, L, level_salt(lvl), kPowerIters, kPowerSafety, rho_dev);
 }
 
+// Launches inside the scope go to another stream of the solver.
+struct OnStream {
+  ppe_solver* s;
+  hipStream_t saved;
+  OnStream(ppe_solver* s_, hipStream_t st) : s(s_), saved(s_->stream) { s->stream = st; }
+  ~OnStream() { s->stream = saved; }
+};
+
+void ensure_side_stream(ppe_solver* s) {
+  if (s->side) return;
+  PPE_HIP(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));
+  PPE_HIP(hipEventCreateWithFlags(&s->fork_ev, hipEventDisableTiming));
+  PPE_HIP(hipEventCreateWithFlags(&s->join_ev, hipEventDisableTiming));
+}
+
 }  // namespace
 
 void build_hierarchy(ppe_solver* s) {
@@ -1079,9 +1094,32 @@ void build_hierarchy(ppe_solver* s) {
     L.mis_rounds = 0;
     const bool last = n <= s->opt.coarse_max || lvl == s->opt.max_levels - 1;
     // a coarsest level solved by its explicit inverse runs no smoother and
-    // has no prolongator to smooth: its spectral bound is never used
-    if (last && n > 0 && n <= kDenseMax) fill_double(s, rho_dev + lvl, 0.0, 1);
-    else spectral_bound(s, L, lvl, rho_dev + lvl);
+    // has no prolongator to smooth: its spectral bound is never used.  A
+    // coarse level's power estimate (a chain of small launches) runs on the
+    // side stream beside the strength, MIS-2 and aggregation launches,
+    // which do not need it; the prolongator smoothing waits for it.
+    bool joined = true;
+    auto join = [&]() {
+      if (!joined) {
+        PPE_HIP(hipStreamWaitEvent(s->stream, s->join_ev, 0));
+        joined = true;
+      }
+    };
+    if (last && n > 0 && n <= kDenseMax) {
+      fill_double(s, rho_dev + lvl, 0.0, 1);
+    } else if (lvl > 0 && n > 0) {
+      ensure_side_stream(s);
+      PPE_HIP(hipEventRecord(s->fork_ev, s->stream));
+      PPE_HIP(hipStreamWaitEvent(s->side, s->fork_ev, 0));
+      {
+        OnStream on(s, s->side);
+        spectral_bound(s, L, lvl, rho_dev + lvl);
+      }
+      PPE_HIP(hipEventRecord(s->join_ev, s->side));
+      joined = false;
+    } else {
+      spectral_bound(s, L, lvl, rho_dev + lvl);
+    }
     if (!last) {
       const int g = grid_for(n);
       unsigned char* strong = L.strong.get<unsigned char>(L.A.nnz);
@@ -1172,6 +1210,7 @@ void build_hierarchy(ppe_solver* s) {
         P.m = na;
         P.nnz = L0.Q.nnz;
         P.maxrow = L0.Q.maxrow;
+        join();  // the smoothing uses this level's spectral bound
         hipLaunchKernelGGL(k_smooth_p, dim3(g), dim3(kBlock), 0, s->stream, n, L0.Q.rp(), L0.Q.ci(),
                            L0.Q.v(), L0.diag.as<double>(), agg, pt, rho_dev + lvl,
                            P.val.get<double>(P.nnz));
@@ -1188,6 +1227,7 @@ void build_hierarchy(ppe_solver* s) {
       }
     }
     // coarsest level
+    join();
     s->nlev = lvl + 1;
     if (n > 0 && n <= kDenseMax) {
       double* Ainv = L.Ainv.get<double>((size_t)n * n);

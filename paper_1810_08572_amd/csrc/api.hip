@@ -158,6 +158,12 @@ void ppe_destroy(ppe_solver* s) {
   if (s->tev1) (void)hipEventDestroy(s->tev1);
   for (auto& e : s->chk_ev)
     if (e) (void)hipEventDestroy(e);
+  if (s->fork_ev) (void)hipEventDestroy(s->fork_ev);
+  if (s->join_ev) (void)hipEventDestroy(s->join_ev);
+  if (s->side) {
+    (void)hipStreamSynchronize(s->side);
+    (void)hipStreamDestroy(s->side);
+  }
   if (s->box_h) (void)hipHostFree(s->box_h);
   delete s;
 }

@@ -187,6 +187,10 @@ struct ppe_solver {
   size_t box_words = 0;
   uint32_t box_tag = 0;
   hipEvent_t chk_ev[2] = {nullptr, nullptr};  // PCG convergence checks in flight
+  // setup's second stream (default priority): coarse power estimates run on
+  // it beside the aggregation of the same level
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   int pred_solve = 0, pred_inner = 0;  // iterations of the last solve / projection inner solve
   // reuse of an unchanged system: the coefficients of the last successful
   // assembly (its mask is `active`)
