@@ -17,6 +17,13 @@ silent, the stated reading:
                  operators, Chebyshev smoother, V-cycle (section 2.5)
   pcg          - preconditioned conjugate gradients (section 2.5)
   mlp          - the warm-start network's forward and backward pass
+  projection   - the pressure-correction step with cross diffusion, the
+                 smeared face gradients and the flux and velocity correction
+                 (section 2.3-2.4, Eq. 11-17)
+  uq           - polynomial chaos by stochastic collocation (section 3)
+  flow         - one fractional step: momentum predictor, projection,
+                 energy with the latent-heat Picard loop (section 2.2, Eq.
+                 2-9, 18-21)
 
 Nothing here is blocked, fused or reordered beyond what each definition
 states, so every function can be checked against its definition by eye.

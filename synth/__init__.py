@@ -1,11 +1,12 @@
 """Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
 
 This package only builds workloads: hexahedral meshes stored as face lists,
-face coefficients, liquid-fraction fields, right-hand sides and intermediate
-velocities.  It holds
+face coefficients, liquid-fraction fields, right-hand sides, intermediate
+velocities and material properties.  It holds
 none of the solver's arithmetic (no masking, assembly, aggregation or Krylov
 step); those live separately in the oracle and in the HIP library.
 """
+from .alloy import al_si_alloy
 from .mesh import HexMesh, box_mesh, plate_with_ribs_mesh, concat_meshes, face_coeff
 from .fields import (
     fl_linear_x,
@@ -18,9 +19,11 @@ from .fields import (
     ustar_smooth_series,
     latin_hypercube,
     mlp_initial_weights,
+    t_wall_layer,
 )
 
 __all__ = [
+    "al_si_alloy",
     "HexMesh",
     "box_mesh",
     "plate_with_ribs_mesh",
@@ -36,4 +39,5 @@ __all__ = [
     "ustar_smooth_series",
     "latin_hypercube",
     "mlp_initial_weights",
+    "t_wall_layer",
 ]

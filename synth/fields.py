@@ -151,3 +151,18 @@ def latin_hypercube(kinds, m, seed):
     for j, kind in enumerate(kinds):
         X[:, j] = ndtri(U[:, j]) if kind == "normal" else 2.0 * U[:, j] - 1.0
     return X, U
+
+
+def t_wall_layer(mesh, T_wall, T_melt, delta):
+    """Temperature of a melt at T_melt that has cooled for a while against
+    box walls held at T_wall: T = T_wall + (T_melt - T_wall) erf(d / delta),
+    d the distance of the cell centre to the nearest face of the mesh's
+    bounding box (a developed thermal boundary layer, so that a mushy zone
+    and a solid rim exist from the first step)."""
+    from scipy.special import erf
+
+    x = mesh.nodes
+    lo, hi = x.min(axis=0), x.max(axis=0)
+    c = mesh.cell_centre
+    d = np.minimum(c - lo, hi - c).min(axis=1)
+    return T_wall + (T_melt - T_wall) * erf(d / delta)
