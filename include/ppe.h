@@ -95,7 +95,7 @@ typedef struct {
   double setup_ms;       /* last ppe_assemble wall time */
   double solve_ms;       /* last ppe_solve wall time */
   int n_active;          /* cells with f_l > 0 */
-  int n_components;      /* liquid pockets (= pinned cells) */
+  int n_components;      /* liquid pockets (= pinned cells); 0 for a shifted system */
   int levels;            /* AMG levels including the finest */
   double op_complexity;  /* sum of level nnz / finest nnz */
   double bytes_per_iter; /* algorithmic bytes one PCG iteration moves */
@@ -127,6 +127,22 @@ ppe_status ppe_set_mesh(ppe_solver* s, int32_t n_cells, int32_t n_faces,
  * PPE_ERR_OOM; PPE_ERR_INTERNAL if a setup table overflows. */
 ppe_status ppe_assemble(ppe_solver* s, const double* face_coeff,
                         const double* liquid_fraction);
+
+/* Shifted assembly for the implicit parts of the momentum and energy
+ * equations (section 2.2, Eq. 6 and the energy step): the same AMG-PCG
+ * solves A = diag(diag_shift) + L, L the face-coefficient operator over the
+ * open faces (both cells kept), with no pins (A is non-singular when every
+ * kept row has a positive shift).  diag_shift[n_cells]: finite and > 0 on
+ * kept cells (ignored elsewhere).  liquid_fraction may be NULL (every cell
+ * kept); otherwise cells with 0 are removed as in ppe_assemble (a removed
+ * neighbour's coupling must then be folded into the shift by the caller).
+ * ppe_solve then returns the solution on kept cells and 0 elsewhere; no
+ * right-hand-side entry is replaced.  ppe_project, ppe_face_gradient and
+ * the warm-start calls need a pressure system and return PPE_ERR_STATE
+ * after this call; the reuse_unchanged option does not apply.  Errors as
+ * ppe_assemble, and PPE_ERR_ARG on a bad or NULL shift. */
+ppe_status ppe_assemble_shifted(ppe_solver* s, const double* face_coeff,
+                                const double* liquid_fraction, const double* diag_shift);
 
 /* Solve A p = b' (Eq. 9 as modified in section 2.4.2) by conjugate gradients
  * preconditioned with one V-cycle per iteration (section 2.5), until the

@@ -77,6 +77,35 @@ class ppe_project_stats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class ppe_alloy(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("rho", "cp", "k", "mu", "beta", "lam", "Lf",
+                                               "T_f", "T_liq", "T_sol", "T_eps", "k_p", "T_ref")] + [
+        ("g", ctypes.c_double * 3),
+        ("fixed_wall_T", ctypes.c_int),
+        ("T_wall", ctypes.c_double),
+    ]
+
+
+class ppe_step_params(ctypes.Structure):
+    _fields_ = [
+        ("dt", ctypes.c_double),
+        ("picard_tol", ctypes.c_double),
+        ("max_picard", ctypes.c_int),
+        ("relax", ctypes.c_double),
+        ("have_history", ctypes.c_int),
+    ]
+
+
+class ppe_flow_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int) for n in ("picard", "momentum_iterations", "pressure_outer",
+                                            "pressure_iterations", "energy_iterations", "n_fluid",
+                                            "n_solid")] + [
+        (n, ctypes.c_double) for n in ("momentum_ms", "pressure_ms", "energy_ms", "ms")]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 # symbol -> (restype, argtypes); the exported C ABI
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
@@ -86,6 +115,7 @@ _SIGS = {
     "ppe_destroy": (None, [_P]),
     "ppe_set_mesh": (ctypes.c_int, [_P, _I32, _I32, _P, _P]),
     "ppe_assemble": (ctypes.c_int, [_P, _P, _P]),
+    "ppe_assemble_shifted": (ctypes.c_int, [_P, _P, _P, _P]),
     "ppe_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.POINTER(ppe_stats)]),
     "ppe_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(ppe_stats)]),
     "ppe_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -132,6 +162,15 @@ _SIGS = {
     "ppe_pce_fit": (ctypes.c_int, [_P, _I32, _P, ctypes.c_int64, _P, _P]),
     "ppe_pce_eval": (ctypes.c_int, [_P, _I32, _P, ctypes.c_int64, _P, _P]),
     "ppe_pce_stats": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, _P, _P, _P]),
+    "ppe_flow_create": (ctypes.c_int, [ctypes.POINTER(ppe_options), ctypes.c_double,
+                                       ctypes.POINTER(_P)]),
+    "ppe_flow_destroy": (None, [_P]),
+    "ppe_flow_set_mesh": (ctypes.c_int, [_P, _I32, _I32, _P, _P, _I32, _P, _P, _P, _P, _P, _P,
+                                         _P]),
+    "ppe_flow_step": (ctypes.c_int, [_P, ctypes.POINTER(ppe_alloy),
+                                     ctypes.POINTER(ppe_step_params), _P, _P, _P, _P, _P, _P, _P,
+                                     ctypes.POINTER(ppe_flow_stats)]),
+    "ppe_flow_last_error": (ctypes.c_char_p, [_P]),
     "ppe_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "ppe_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double),
@@ -304,6 +343,19 @@ class Solver:
         self._chk(self._lib.ppe_assemble(
             self._h, _dev_ptr(face_coeff, torch.float64, nf, "face_coeff"),
             _dev_ptr(liquid_fraction, torch.float64, nc, "liquid_fraction")))
+
+    def assemble_shifted(self, face_coeff, diag_shift, liquid_fraction=None):
+        """diag(diag_shift) + L over the open faces, no pins
+        (liquid_fraction None: every cell kept)."""
+        import torch
+
+        nf = self.n_faces if self.n_cells else None
+        nc = self.n_cells if self.n_cells else None
+        fl = (ctypes.c_void_p(None) if liquid_fraction is None
+              else _dev_ptr(liquid_fraction, torch.float64, nc, "liquid_fraction"))
+        self._chk(self._lib.ppe_assemble_shifted(
+            self._h, _dev_ptr(face_coeff, torch.float64, nf, "face_coeff"), fl,
+            _dev_ptr(diag_shift, torch.float64, nc, "diag_shift")))
 
     def solve(self, rhs, x0=None, out=None, allow_not_converged=False):
         import torch
@@ -537,6 +589,125 @@ class WarmStartNet:
 
 PPE_INPUT_NORMAL, PPE_INPUT_UNIFORM = 0, 1
 PPE_GRID_TENSOR, PPE_GRID_SMOLYAK = 0, 1
+
+
+def _alloy(props):
+    """ppe_alloy from a property mapping (rho, cp, k, mu, beta, lam, Lf, T_f,
+    T_liq, T_sol, T_eps, k_p, T_ref, g, T_wall; T_wall None = insulated)."""
+    a = ppe_alloy()
+    for n in ("rho", "cp", "k", "mu", "beta", "lam", "Lf", "T_f", "T_liq", "T_sol", "T_eps",
+              "k_p", "T_ref"):
+        setattr(a, n, float(props[n]))
+    for i, v in enumerate(props["g"]):
+        a.g[i] = float(v)
+    a.fixed_wall_T = 0 if props["T_wall"] is None else 1
+    a.T_wall = 0.0 if props["T_wall"] is None else float(props["T_wall"])
+    return a
+
+
+@dataclass
+class FlowState:
+    """Device state of the time-step driver (float64 tensors)."""
+    u: "object"        # [n, 3]
+    T: "object"        # [n]
+    fs: "object"       # [n]
+    flux: "object"     # [n_faces]
+    p: "object"        # [n]
+    conv_u: "object"   # [n, 3]
+    conv_T: "object"   # [n]
+    have_history: bool = False
+
+
+class Flow:
+    """One fractional step per call (section 2.2): momentum predictor,
+    masked projection, energy with the latent-heat Picard loop.  The
+    pressure solver takes the Solver options; momentum and energy solve in
+    FP64 to transport_rtol."""
+
+    def __init__(self, precision="fp64", rtol=1e-10, transport_rtol=1e-12, stream=None,
+                 use_graph=True, autotune=False):
+        import torch
+
+        self._lib = load_library()
+        o = ppe_default_options()
+        o.precision = {"fp64": PPE_FP64, "mixed": PPE_MIXED}[precision]
+        o.rtol = rtol
+        o.use_graph = int(bool(use_graph))
+        o.autotune = int(bool(autotune))
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        o.stream = ctypes.c_void_p(stream.cuda_stream)
+        h = _P()
+        _check(self._lib.ppe_flow_create(ctypes.byref(o), float(transport_rtol), ctypes.byref(h)))
+        self._h = h
+        self.n_cells = self.n_faces = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ppe_flow_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def _chk(self, st, allow=(PPE_OK,)):
+        if st in allow:
+            return st
+        detail = self._lib.ppe_flow_last_error(self._h).decode()
+        raise PpeError(st, f"{self._lib.ppe_status_string(st).decode()}: {detail}")
+
+    def set_mesh(self, owner, neigh, nodes, face_nodes, cell_nodes, cell_centre, face_area,
+                 face_centre, cell_volume):
+        import torch
+
+        nc = cell_volume.numel()
+        nf = owner.numel()
+        nn = nodes.numel() // 3
+        self._chk(self._lib.ppe_flow_set_mesh(
+            self._h, int(nc), int(nf), _dev_ptr(owner, torch.int32, nf, "owner"),
+            _dev_ptr(neigh, torch.int32, nf, "neigh"), int(nn),
+            _dev_ptr(nodes, torch.float64, 3 * nn, "nodes"),
+            _dev_ptr(face_nodes, torch.int32, 4 * nf, "face_nodes"),
+            _dev_ptr(cell_nodes, torch.int32, 8 * nc, "cell_nodes"),
+            _dev_ptr(cell_centre, torch.float64, 3 * nc, "cell_centre"),
+            _dev_ptr(face_area, torch.float64, 3 * nf, "face_area"),
+            _dev_ptr(face_centre, torch.float64, 3 * nf, "face_centre"),
+            _dev_ptr(cell_volume, torch.float64, nc, "cell_volume")))
+        self.n_cells, self.n_faces = int(nc), int(nf)
+
+    def new_state(self, T, fs, u=None):
+        """State at rest (or with velocity u), no convection history."""
+        import torch
+
+        dev = T.device
+        n, nf = self.n_cells, self.n_faces
+        z = lambda *shape: torch.zeros(*shape, dtype=torch.float64, device=dev)
+        u = z(n, 3) if u is None else u.clone()
+        return FlowState(u.contiguous(), T.clone().contiguous(), fs.clone().contiguous(),
+                         z(max(nf, 1)), z(n), z(n, 3), z(n))
+
+    def step(self, props, state: FlowState, dt, picard_tol=1e-10, max_picard=50, relax=1.0,
+             allow_not_converged=False):
+        """Advance `state` in place by one step; returns (status, stats)."""
+        import torch
+
+        a = _alloy(props)
+        prm = ppe_step_params(float(dt), float(picard_tol), int(max_picard), float(relax),
+                              int(bool(state.have_history)))
+        st = ppe_flow_stats()
+        n, nf = self.n_cells, self.n_faces
+        allow = (PPE_OK, PPE_NOT_CONVERGED) if allow_not_converged else (PPE_OK,)
+        status = self._lib.ppe_flow_step(
+            self._h, ctypes.byref(a), ctypes.byref(prm),
+            _dev_ptr(state.u, torch.float64, 3 * n, "u"), _dev_ptr(state.T, torch.float64, n, "T"),
+            _dev_ptr(state.fs, torch.float64, n, "fs"),
+            _dev_ptr(state.flux, torch.float64, max(nf, 1), "flux"),
+            _dev_ptr(state.p, torch.float64, n, "p"),
+            _dev_ptr(state.conv_u, torch.float64, 3 * n, "conv_u"),
+            _dev_ptr(state.conv_T, torch.float64, n, "conv_T"), ctypes.byref(st))
+        self._chk(status, allow)
+        state.have_history = True
+        return status, st.as_dict()
 
 
 class PolynomialChaos:

@@ -190,14 +190,21 @@ ppe_status ppe_set_mesh(ppe_solver* s, int32_t n_cells, int32_t n_faces, const i
   });
 }
 
-ppe_status ppe_assemble(ppe_solver* s, const double* face_coeff, const double* fl) {
+namespace {
+
+// Shared body of ppe_assemble (shift NULL) and ppe_assemble_shifted.
+ppe_status assemble_impl(ppe_solver* s, const double* face_coeff, const double* fl,
+                         const double* shift) {
   if (!s) return PPE_ERR_ARG;
   return guarded(s, [&]() -> ppe_status {
     DeviceGuard g(s->device);
     ppe::require(s->have_mesh, PPE_ERR_STATE, "ppe_assemble before ppe_set_mesh");
-    ppe::require(fl && (face_coeff || s->n_faces == 0), PPE_ERR_ARG, "NULL input array");
+    ppe::require((fl || shift) && (face_coeff || s->n_faces == 0), PPE_ERR_ARG,
+                 "NULL input array");
     PPE_HIP(hipEventRecord(s->ev0, s->stream));
-    if (s->opt.reuse_unchanged && s->have_prev && ppe::same_system(s, face_coeff, fl)) {
+    // an unchanged system is recognised for pressure systems only
+    if (!shift && !s->shifted && s->opt.reuse_unchanged && s->have_prev &&
+        ppe::same_system(s, face_coeff, fl)) {
       // the masked system, its hierarchy and captured graphs stay valid
       s->assembled = true;
       s->stats.reused_setup += 1;
@@ -210,7 +217,7 @@ ppe_status ppe_assemble(ppe_solver* s, const double* face_coeff, const double* f
     s->have_prev = false;
     s->solves_since_assemble = 0;
     ppe::drop_graph(s);
-    ppe::assemble_fine(s, face_coeff, fl);
+    ppe::assemble_fine(s, face_coeff, fl, shift);
     if (s->n_active > 0) {
       ppe::build_hierarchy(s);
       ppe::prepare_solve_levels(s);
@@ -234,7 +241,7 @@ ppe_status ppe_assemble(ppe_solver* s, const double* face_coeff, const double* f
     for (int l = 0; l < s->nlev; ++l) tot += s->levels[l].A.nnz;
     s->stats.op_complexity = nnz0 > 0 ? tot / nnz0 : 1.0;
     s->stats.bytes_per_iter = s->n_active > 0 ? bytes_per_iteration(s) : 0.0;
-    if (s->opt.reuse_unchanged) {
+    if (s->opt.reuse_unchanged && !shift) {
       // the coefficients this system was built from, for the next comparison
       double* pc = s->prev_coeff.get<double>(s->n_faces > 0 ? s->n_faces : 1);
       if (s->n_faces)
@@ -246,6 +253,25 @@ ppe_status ppe_assemble(ppe_solver* s, const double* face_coeff, const double* f
     s->assembled = true;
     return PPE_OK;
   });
+}
+
+}  // namespace
+
+ppe_status ppe_assemble(ppe_solver* s, const double* face_coeff, const double* fl) {
+  if (s && !fl) {
+    s->err = "NULL input array";
+    return PPE_ERR_ARG;
+  }
+  return assemble_impl(s, face_coeff, fl, nullptr);
+}
+
+ppe_status ppe_assemble_shifted(ppe_solver* s, const double* face_coeff, const double* fl,
+                                const double* diag_shift) {
+  if (s && !diag_shift) {
+    s->err = "NULL diagonal shift";
+    return PPE_ERR_ARG;
+  }
+  return assemble_impl(s, face_coeff, fl, diag_shift);
 }
 
 ppe_status ppe_solve(ppe_solver* s, const double* rhs, double* p, int use_x0, ppe_stats* stats) {
@@ -286,7 +312,8 @@ ppe_status ppe_project(ppe_solver* s, const double* face_coeff, const double* us
   if (!s) return PPE_ERR_ARG;
   return guarded(s, [&]() -> ppe_status {
     DeviceGuard g(s->device);
-    ppe::require(s->assembled, PPE_ERR_STATE, "ppe_project before ppe_assemble");
+    ppe::require(s->assembled && !s->shifted, PPE_ERR_STATE,
+                 "ppe_project needs a pressure system (ppe_assemble)");
     ppe::require(s->geom_ok, PPE_ERR_STATE, "ppe_project before ppe_set_geometry");
     ppe::require(s->n_seg == 1, PPE_ERR_STATE, "ppe_project solves one sample at a time");
     ppe::require(face_coeff && ustar && p && u && (flux || s->n_faces == 0), PPE_ERR_ARG,
@@ -309,7 +336,7 @@ ppe_status ppe_face_gradient(ppe_solver* s, const double* face_coeff, double rho
   if (!s) return PPE_ERR_ARG;
   return guarded(s, [&]() -> ppe_status {
     DeviceGuard g(s->device);
-    ppe::require(s->assembled && s->geom_ok, PPE_ERR_STATE,
+    ppe::require(s->assembled && s->geom_ok && !s->shifted, PPE_ERR_STATE,
                  "ppe_face_gradient needs ppe_assemble and ppe_set_geometry");
     ppe::require(face_coeff && p && grad && cross, PPE_ERR_ARG, "NULL array");
     ppe::require(std::isfinite(rho) && rho > 0, PPE_ERR_ARG, "rho must be finite and > 0");

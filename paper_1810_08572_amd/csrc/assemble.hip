@@ -77,17 +77,24 @@ __global__ void k_adj_sort(const int* __restrict__ ptr, int n_cells, int* __rest
     if (nbr[i] == nbr[i - 1]) atomicOr(flag, 2);
 }
 
+// Bit 1: a bad face coefficient; bit 2: a bad liquid fraction (fl may be
+// NULL: every cell active); bit 8: a diagonal shift that is not finite and
+// > 0 on an active cell (shift NULL: no shift).
 __global__ void k_check_fields(const double* __restrict__ coeff, const int* __restrict__ neigh,
                                int n_faces, const double* __restrict__ fl, int n_cells,
-                               int* __restrict__ flag) {
+                               int* __restrict__ flag, const double* __restrict__ shift) {
   int i = blockIdx.x * kBlock + threadIdx.x;
   if (i < n_faces && neigh[i] >= 0) {
     double c = coeff[i];
     if (!(c > 0.0) || !(c <= 1.7976931348623157e308)) atomicOr(flag, 1);
   }
   if (i < n_cells) {
-    double v = fl[i];
+    const double v = fl ? fl[i] : 1.0;
     if (!(v >= 0.0 && v <= 1.0)) atomicOr(flag, 2);
+    if (shift && v > 0.0) {
+      const double d = shift[i];
+      if (!(d > 0.0) || !(d <= 1.7976931348623157e308)) atomicOr(flag, 8);
+    }
   }
 }
 
@@ -95,7 +102,7 @@ __global__ void k_active(const double* __restrict__ fl, int n, int* __restrict__
                          int* __restrict__ parent) {
   int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  active[i] = fl[i] > 0.0 ? 1 : 0;
+  active[i] = (!fl || fl[i] > 0.0) ? 1 : 0;
   parent[i] = i;
 }
 
@@ -174,12 +181,14 @@ __global__ void k_union(const int* __restrict__ owner, const int* __restrict__ n
   }
 }
 
+// comp[i] = the pin (smallest cell) of i's component, -1 on removed cells;
+// without pins (a shifted system) every active cell gets -2.
 __global__ void k_components(const int* __restrict__ active, int n, int* parent,
-                             int* __restrict__ comp, int* __restrict__ is_pin) {
+                             int* __restrict__ comp, int* __restrict__ is_pin, int pins) {
   int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  if (!active[i]) {
-    comp[i] = -1;
+  if (!active[i] || !pins) {
+    comp[i] = active[i] ? -2 : -1;
     is_pin[i] = 0;
     return;
   }
@@ -218,12 +227,13 @@ __global__ void k_fill_rows(const int* __restrict__ perm, int n_active,
                             const double* __restrict__ coeff, const int* __restrict__ rowptr,
                             int* __restrict__ col, double* __restrict__ val,
                             double* __restrict__ diag, int W, int* __restrict__ ell_col,
-                            double* __restrict__ ell_val, double* __restrict__ B) {
+                            double* __restrict__ ell_val, double* __restrict__ B,
+                            const double* __restrict__ shift) {
   int r = blockIdx.x * kBlock + threadIdx.x;
   if (r >= n_active) return;
   int c = perm[r];
   const bool pin = is_pin[c] != 0;
-  double d = 0.0;
+  double d = shift ? shift[c] : 0.0;
   for (int k = adj_ptr[c]; k < adj_ptr[c + 1]; ++k) {
     int j = adj_nbr[k];
     if (active[j]) d = d + coeff[adj_face[k]];
@@ -408,7 +418,7 @@ bool same_system(ppe_solver* s, const double* coeff, const double* fl) {
   fill_int(s, flag, 0, 1);
   const int g = grid_for(nf > nc ? nf : nc);
   hipLaunchKernelGGL(k_check_fields, dim3(g), dim3(kBlock), 0, s->stream, coeff, s->neigh.as<int>(),
-                     nf, fl, nc, flag);
+                     nf, fl, nc, flag, static_cast<const double*>(nullptr));
   PPE_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_same_system, dim3(g), dim3(kBlock), 0, s->stream, coeff,
                      s->prev_coeff.as<double>(), s->neigh.as<int>(), nf, fl, s->active.as<int>(), nc,
@@ -420,13 +430,14 @@ bool same_system(ppe_solver* s, const double* coeff, const double* fl) {
   return !(bad & 4);
 }
 
-void assemble_fine(ppe_solver* s, const double* coeff, const double* fl) {
+void assemble_fine(ppe_solver* s, const double* coeff, const double* fl, const double* shift) {
   const int nc = s->n_cells, nf = s->n_faces, ns = s->n_seg;
+  s->shifted = shift != nullptr;
   int* flag = s->flag.get<int>(1);
   fill_int(s, flag, 0, 1);
   int g = grid_for(nf > nc ? nf : nc);
   hipLaunchKernelGGL(k_check_fields, dim3(g), dim3(kBlock), 0, s->stream, coeff, s->neigh.as<int>(),
-                     nf, fl, nc, flag);
+                     nf, fl, nc, flag, shift);
   PPE_LAUNCH_CHECK();
 
   int* active = s->active.get<int>(nc);
@@ -454,7 +465,9 @@ void assemble_fine(ppe_solver* s, const double* coeff, const double* fl) {
 
   int* comp = s->comp_full.get<int>(nc);
   int* is_pin = s->tmp_i[2].get<int>(nc);
-  if (nf) {
+  // a shifted system is non-singular on every component: no pins, so no
+  // component search either
+  if (nf && !shift) {
     int* forest = s->tmp_i[3].get<int>(nc + 1);
     hipLaunchKernelGGL(k_cc_init, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc,
                        s->adj_ptr.as<int>(), s->adj_nbr.as<int>(), active, forest);
@@ -467,7 +480,7 @@ void assemble_fine(ppe_solver* s, const double* coeff, const double* fl) {
     PPE_LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(k_components, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, active, nc,
-                     parent, comp, is_pin);
+                     parent, comp, is_pin, shift ? 0 : 1);
   PPE_LAUNCH_CHECK();
   const long long* d_ncomp =
       exclusive_scan_async(s, is_pin, s->tmp_i[3].get<int>(nc + 1), nc, 1);
@@ -492,6 +505,7 @@ void assemble_fine(ppe_solver* s, const double* coeff, const double* fl) {
                 ReadItem{d_ncomp, sizeof(long long), &tot[1]}});
   require(!(bad & 1), PPE_ERR_ARG, "face coefficient must be finite and > 0 on interior faces");
   require(!(bad & 2), PPE_ERR_ARG, "liquid fraction must be finite and in [0, 1]");
+  require(!(bad & 8), PPE_ERR_ARG, "diagonal shift must be finite and > 0 on every active cell");
   const int na = s->seg_row_off[ns];
   s->n_active = na;
   s->n_comp = (int)tot[1];
@@ -512,7 +526,7 @@ void assemble_fine(ppe_solver* s, const double* coeff, const double* fl) {
   double* B = L.B.get<double>(na);
   hipLaunchKernelGGL(k_fill_rows, dim3(grid_for(na)), dim3(kBlock), 0, s->stream, perm, na,
                      s->adj_ptr.as<int>(), s->adj_nbr.as<int>(), s->adj_face.as<int>(), active,
-                     is_pin, cid, coeff, rowptr, col, val, diag, L.W, ecol, evl, B);
+                     is_pin, cid, coeff, rowptr, col, val, diag, L.W, ecol, evl, B, shift);
   PPE_LAUNCH_CHECK();
 }
 

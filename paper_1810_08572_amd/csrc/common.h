@@ -195,6 +195,7 @@ struct ppe_solver {
   // reuse of an unchanged system: the coefficients of the last successful
   // assembly (its mask is `active`)
   bool have_prev = false;
+  bool shifted = false;  // the last assembly carried a diagonal shift (no pins)
   ppe::DevBuf prev_coeff;
   // autotuner choices per (level, FP32, quarter-octave bins of rows and of
   // entries): {lpr_a, fuse0, lpr_r, lpr_p}
@@ -430,7 +431,10 @@ void fill_double(ppe_solver* s, double* p, double v, int64_t n);
 // assemble.hip
 void build_topology(ppe_solver* s, const int32_t* owner, const int32_t* neigh);
 void check_segments(ppe_solver* s, const std::vector<int>& off);
-void assemble_fine(ppe_solver* s, const double* coeff, const double* fl);
+// shift NULL: the pinned pressure system of fl's mask.  shift[n_cells]
+// (> 0 on active cells): diag(shift) + L without pins; fl may then be NULL
+// (every cell active).
+void assemble_fine(ppe_solver* s, const double* coeff, const double* fl, const double* shift);
 // Checks the fields (raising PPE_ERR_ARG as the assembly does) and returns
 // whether the coefficients and the mask equal those of the last assembly.
 bool same_system(ppe_solver* s, const double* coeff, const double* fl);

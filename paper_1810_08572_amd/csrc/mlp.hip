@@ -603,7 +603,7 @@ ppe_status ppe_warm_start_features(ppe_solver* s, const double* dp_prev, const d
   if (!s || !dp_prev || !rhs || !face_coeff || !fl || !cell_volume || !mu || !sigma || !features ||
       !dp_scale)
     return PPE_ERR_ARG;
-  if (!s->assembled) return PPE_ERR_STATE;
+  if (!s->assembled || s->shifted) return PPE_ERR_STATE;  // needs a pinned pressure system
   try {
     const int na = s->n_active;
     if (na == 0) {
@@ -636,7 +636,7 @@ ppe_status ppe_warm_start_features(ppe_solver* s, const double* dp_prev, const d
 ppe_status ppe_warm_start_apply(ppe_solver* s, const double* p_prev, const float* y,
                                 double dp_scale, double* x0) {
   if (!s || !p_prev || !x0 || (s->n_active > 0 && !y)) return PPE_ERR_ARG;
-  if (!s->assembled) return PPE_ERR_STATE;
+  if (!s->assembled || s->shifted) return PPE_ERR_STATE;  // needs a pinned pressure system
   try {
     hipLaunchKernelGGL(k_ws_apply, dim3(grid_for(s->n_cells)), dim3(kBlock), 0, s->stream,
                        s->n_cells, s->cid.as<int>(), s->comp_full.as<int>(), p_prev, y, dp_scale,
@@ -653,7 +653,7 @@ ppe_status ppe_warm_start_apply(ppe_solver* s, const double* p_prev, const float
 ppe_status ppe_warm_start_targets(ppe_solver* s, const double* p_new, const double* p_prev,
                                   double dp_scale, float* targets) {
   if (!s || !p_new || !p_prev || (s->n_active > 0 && !targets)) return PPE_ERR_ARG;
-  if (!s->assembled) return PPE_ERR_STATE;
+  if (!s->assembled || s->shifted) return PPE_ERR_STATE;  // needs a pinned pressure system
   try {
     if (s->n_active) {
       hipLaunchKernelGGL(k_ws_targets, dim3(grid_for(s->n_active)), dim3(kBlock), 0, s->stream,

@@ -1,5 +1,6 @@
 """CPU checks of the C-ABI boundary: the library is built, loads, and
-exports every function include/ppe.h declares; the binding mirrors them."""
+exports every function the headers under include/ declare; the binding
+mirrors them."""
 import ctypes
 import os
 import re
@@ -8,13 +9,17 @@ import pytest
 
 import paper_1810_08572_amd as ppe
 
-HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "ppe.h")
+INCLUDE = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include")
 
 
 def _declared():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(ppe_[a-z_0-9]+)\s*\(", text)))
+    names = set()
+    for h in sorted(os.listdir(INCLUDE)):
+        if h.endswith(".h"):
+            text = open(os.path.join(INCLUDE, h)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(ppe_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_binding():
@@ -37,6 +42,17 @@ def test_host_only_calls():
     # NULL solver handles are rejected without touching a device
     assert lib.ppe_assemble(None, None, None) == ppe.PPE_ERR_ARG
     assert lib.ppe_solve(None, None, None, 0, None) == ppe.PPE_ERR_ARG
+    assert lib.ppe_assemble_shifted(None, None, None, None) == ppe.PPE_ERR_ARG
+    # time-step driver: NULL handles and bad creation values
+    assert lib.ppe_flow_step(None, None, None, None, None, None, None, None, None, None,
+                             None) == ppe.PPE_ERR_ARG
+    assert lib.ppe_flow_set_mesh(None, 1, 0, None, None, 1, None, None, None, None, None, None,
+                                 None) == ppe.PPE_ERR_ARG
+    h = ctypes.c_void_p()
+    assert lib.ppe_flow_create(None, 1e-12, ctypes.byref(h)) == ppe.PPE_ERR_ARG
+    assert lib.ppe_flow_create(ctypes.byref(o), 0.0, ctypes.byref(h)) == ppe.PPE_ERR_ARG
+    assert lib.ppe_flow_last_error(None) == b""
+    lib.ppe_flow_destroy(None)
     st = ppe.ppe_stats()
     assert lib.ppe_get_stats(None, ctypes.byref(st)) == ppe.PPE_ERR_ARG
     lib.ppe_destroy(None)
@@ -51,19 +67,22 @@ def test_struct_layouts_match_header(tmp_path):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler")
+    structs = (("ppe_options", ppe.ppe_options), ("ppe_stats", ppe.ppe_stats),
+               ("ppe_project_stats", ppe.ppe_project_stats), ("ppe_alloy", ppe.ppe_alloy),
+               ("ppe_step_params", ppe.ppe_step_params), ("ppe_flow_stats", ppe.ppe_flow_stats))
     lines = []
-    for cname, cls in (("ppe_options", ppe.ppe_options), ("ppe_stats", ppe.ppe_stats)):
+    for cname, cls in structs:
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
         for f, _ in cls._fields_:
             lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
     src = tmp_path / "layout.c"
-    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ppe.h"\nint main(void){'
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ppe_flow.h"\nint main(void){'
                    + "".join(lines) + "return 0;}\n")
     exe = tmp_path / "layout"
-    subprocess.run([cc, "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    subprocess.run([cc, "-I", INCLUDE, str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
     got = dict(line.rsplit(" ", 1) for line in out if line)
-    for cname, cls in (("ppe_options", ppe.ppe_options), ("ppe_stats", ppe.ppe_stats)):
+    for cname, cls in structs:
         assert int(got[f"{cname} size"]) == ctypes.sizeof(cls)
         for f, _ in cls._fields_:
             assert int(got[f"{cname}.{f}"]) == getattr(cls, f).offset, (cname, f)
