@@ -87,6 +87,13 @@ typedef struct {
                          successful assembly's, and keeps the masked system, the
                          AMG hierarchy and captured graphs when both are
                          unchanged.  Default 0: every assembly rebuilds. */
+  int project_krylov; /* outer iteration of ppe_project for the non-symmetric
+                         system (L - X) p = b' with the cross term implicit:
+                         0 (default) deferred correction, each pass an AMG-PCG
+                         solve of L; 1 BiCGSTAB preconditioned by one V-cycle of
+                         L's hierarchy per application (section 2.5 names
+                         BiCGSTAB as the paper's Krylov method for systems PCG
+                         cannot take).  Both stop on the same true residual. */
 } ppe_options;
 
 typedef struct {

@@ -124,6 +124,12 @@ ppe_status ppe_flow_step(ppe_flow* f, const ppe_alloy* alloy, const ppe_step_par
                          double* u, double* T, double* fs, double* flux, double* p,
                          double* conv_u, double* conv_T, ppe_flow_stats* stats);
 
+/* fs[n] = f_s(T[n]) of Eq. 21 (device arrays): the solid fraction that goes
+ * with a given temperature, for an initial state.  PPE_ERR_ARG on NULL
+ * arrays with n > 0, n < 0, T_eps <= 0, T_f = T_liq or k_p = 1. */
+ppe_status ppe_flow_solid_fraction(ppe_flow* f, const ppe_alloy* alloy, int64_t n, const double* T,
+                                   double* fs);
+
 /* Detail of the last failure ("" if none). */
 const char* ppe_flow_last_error(const ppe_flow* f);
 

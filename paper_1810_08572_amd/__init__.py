@@ -44,6 +44,7 @@ class ppe_options(ctypes.Structure):
         ("use_graph", ctypes.c_int),
         ("autotune", ctypes.c_int),
         ("reuse_unchanged", ctypes.c_int),
+        ("project_krylov", ctypes.c_int),
     ]
 
 
@@ -171,6 +172,8 @@ _SIGS = {
                                      ctypes.POINTER(ppe_step_params), _P, _P, _P, _P, _P, _P, _P,
                                      ctypes.POINTER(ppe_flow_stats)]),
     "ppe_flow_last_error": (ctypes.c_char_p, [_P]),
+    "ppe_flow_solid_fraction": (ctypes.c_int, [_P, ctypes.POINTER(ppe_alloy), ctypes.c_int64, _P,
+                                               _P]),
     "ppe_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "ppe_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double),
@@ -278,11 +281,13 @@ class Solver:
 
     def __init__(self, precision="fp64", rtol=1e-10, max_iter=500, cheb_degree=2,
                  cheb_ratio=30.0, coarse_max=128, max_levels=10, theta=0.08, stream=None,
-                 use_graph=True, check_every=2, autotune=False, reuse_unchanged=False):
+                 use_graph=True, check_every=2, autotune=False, reuse_unchanged=False,
+                 krylov="deferred"):
         import torch
 
         lib = load_library()
         o = ppe_default_options()
+        o.project_krylov = {"deferred": 0, "bicgstab": 1}[krylov]
         o.precision = {"fp64": PPE_FP64, "mixed": PPE_MIXED}[precision]
         o.rtol, o.max_iter, o.cheb_degree, o.cheb_ratio = rtol, max_iter, cheb_degree, cheb_ratio
         o.coarse_max, o.max_levels, o.theta = coarse_max, max_levels, theta
@@ -625,11 +630,12 @@ class Flow:
     FP64 to transport_rtol."""
 
     def __init__(self, precision="fp64", rtol=1e-10, transport_rtol=1e-12, stream=None,
-                 use_graph=True, autotune=False):
+                 use_graph=True, autotune=False, krylov="deferred"):
         import torch
 
         self._lib = load_library()
         o = ppe_default_options()
+        o.project_krylov = {"deferred": 0, "bicgstab": 1}[krylov]
         o.precision = {"fp64": PPE_FP64, "mixed": PPE_MIXED}[precision]
         o.rtol = rtol
         o.use_graph = int(bool(use_graph))
@@ -675,11 +681,25 @@ class Flow:
             _dev_ptr(cell_volume, torch.float64, nc, "cell_volume")))
         self.n_cells, self.n_faces = int(nc), int(nf)
 
-    def new_state(self, T, fs, u=None):
-        """State at rest (or with velocity u), no convection history."""
+    def solid_fraction(self, props, T):
+        """f_s(T) of Eq. 21 on the device."""
+        import torch
+
+        fs = torch.empty_like(T)
+        a = _alloy(props)
+        self._chk(self._lib.ppe_flow_solid_fraction(
+            self._h, ctypes.byref(a), int(T.numel()), _dev_ptr(T, torch.float64, None, "T"),
+            ctypes.c_void_p(fs.data_ptr())))
+        return fs
+
+    def new_state(self, T, fs=None, u=None, props=None):
+        """State at rest (or with velocity u), no convection history; fs None:
+        f_s(T) of Eq. 21 for the given props."""
         import torch
 
         dev = T.device
+        if fs is None:
+            fs = self.solid_fraction(props, T)
         n, nf = self.n_cells, self.n_faces
         z = lambda *shape: torch.zeros(*shape, dtype=torch.float64, device=dev)
         u = z(n, 3) if u is None else u.clone()

@@ -99,6 +99,7 @@ void ppe_default_options(ppe_options* o) {
   o->use_graph = 1;
   o->autotune = 0;
   o->reuse_unchanged = 0;
+  o->project_krylov = 0;
 }
 
 ppe_status ppe_create(const ppe_options* opt, ppe_solver** out) {
@@ -113,6 +114,8 @@ ppe_status ppe_create(const ppe_options* opt, ppe_solver** out) {
     ppe::require(o.max_iter >= 1, PPE_ERR_ARG, "max_iter must be >= 1");
     ppe::require(o.cheb_degree >= 1 && o.cheb_degree <= 8, PPE_ERR_ARG, "cheb_degree in [1, 8]");
     ppe::require(o.cheb_ratio > 1, PPE_ERR_ARG, "cheb_ratio must be > 1");
+    ppe::require(o.project_krylov == 0 || o.project_krylov == 1, PPE_ERR_ARG,
+                 "project_krylov must be 0 or 1");
     ppe::require(o.coarse_max >= 1, PPE_ERR_ARG, "coarse_max must be >= 1");
     ppe::require(o.max_levels >= 1 && o.max_levels <= 32, PPE_ERR_ARG, "max_levels in [1, 32]");
     ppe::require(o.theta >= 0 && o.theta < 1, PPE_ERR_ARG, "theta in [0, 1)");

@@ -214,6 +214,7 @@ struct ppe_solver {
   ppe::DevBuf g_nodes, g_cc, g_S, g_fnodes, g_vptr, g_vcell;
   ppe::DevBuf g_inv;  // J^-1 per face, nine arrays of n_faces
   ppe::DevBuf pj_fs, pj_b, pj_r, pj_d, pj_grad, pj_xf, pj_part, pj_t, pj_vm;  // projection workspace
+  ppe::DevBuf pj_k;  // BiCGSTAB vectors, partials and scalars
 
   // dominant-kernel measurement (event pairs around fine-level smoothing steps)
   bool prof = false;

@@ -342,6 +342,15 @@ __global__ void k_finish_faces(int nf, const int* __restrict__ owner, const int*
   flux[f] = open ? F_new[f] : 0.0;
 }
 
+__global__ void k_solid_fraction(int n, const double* __restrict__ T, Alloy a,
+                                 double* __restrict__ fs) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= n) return;
+  double f, slope;
+  solid_fraction(a, T[c], f, slope);
+  fs[c] = f;
+}
+
 __global__ void k_count_fluid(int nc, const double* __restrict__ fs, int* __restrict__ n) {
   const int c = blockIdx.x * kBlock + threadIdx.x;
   if (c < nc && fs[c] < 1.0) atomicAdd(n, 1);
@@ -443,6 +452,24 @@ void ppe_flow_destroy(ppe_flow* f) {
 }
 
 const char* ppe_flow_last_error(const ppe_flow* f) { return f ? f->err.c_str() : ""; }
+
+ppe_status ppe_flow_solid_fraction(ppe_flow* f, const ppe_alloy* al, int64_t n, const double* T,
+                                   double* fs) {
+  if (!f) return PPE_ERR_ARG;
+  return flow_guarded(f, [&]() -> ppe_status {
+    require(al && n >= 0 && (n == 0 || (T && fs)), PPE_ERR_ARG, "NULL argument or n < 0");
+    require(al->T_eps > 0.0 && al->T_f != al->T_liq && al->k_p > 0.0 && al->k_p != 1.0,
+            PPE_ERR_ARG, "T_eps <= 0, T_f = T_liq or k_p not in (0, 1) u (1, inf)");
+    require(n <= INT32_MAX, PPE_ERR_ARG, "n too large");
+    if (n == 0) return PPE_OK;
+    const Alloy a = make_alloy(al);
+    hipLaunchKernelGGL(k_solid_fraction, dim3(grid_for(n)), dim3(kBlock), 0, f->stream, (int)n, T,
+                       a, fs);
+    PPE_LAUNCH_CHECK();
+    PPE_HIP(hipStreamSynchronize(f->stream));
+    return PPE_OK;
+  });
+}
 
 ppe_status ppe_flow_set_mesh(ppe_flow* f, int32_t n_cells, int32_t n_faces, const int32_t* owner,
                              const int32_t* neigh, int32_t n_nodes, const double* nodes,

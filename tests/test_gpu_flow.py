@@ -76,12 +76,12 @@ def test_shifted_assembly_matches_direct(masked):
                   2400.0, 1e-3)
 
 
-def _flow(m):
+def _flow(m, krylov="deferred"):
     import torch
 
     import paper_1810_08572_amd as ppe
 
-    fw = ppe.Flow()
+    fw = ppe.Flow(krylov=krylov)
     fw.set_mesh(to_dev(m.owner, torch.int32), to_dev(m.neigh, torch.int32),
                 to_dev(m.nodes, torch.float64), to_dev(m.extra["face_nodes"], torch.int32),
                 to_dev(m.extra["cell_nodes"], torch.int32), to_dev(m.cell_centre, torch.float64),
@@ -111,15 +111,16 @@ def _cases():
 CASES = list(_cases())
 
 
+@pytest.mark.parametrize("krylov", ["deferred", "bicgstab"])
 @pytest.mark.parametrize("name,m,props,T0,dt,steps", CASES, ids=[c[0] for c in CASES])
-def test_steps_match_oracle(name, m, props, T0, dt, steps):
+def test_steps_match_oracle(name, m, props, T0, dt, steps, krylov):
     import torch
 
     geo = flow.Geometry(m)
     a = flow.Props.of(props)
     rng = np.random.default_rng(3)
     st = flow.initial_state(m, a, T0=T0, u0=2e-3 * rng.normal(size=(m.n_cells, 3)))
-    fw = _flow(m)
+    fw = _flow(m, krylov)
     gs = fw.new_state(to_dev(st.T, torch.float64), to_dev(st.fs, torch.float64),
                       to_dev(st.u, torch.float64))
     for k in range(steps):
@@ -198,3 +199,18 @@ def test_invariants_at_64cube_insulated():
         assert np.abs(div[ok]).max() <= 1e-8 * np.abs(F).max()
         solid_prev = solid
         print(f"  picard {stats['picard']} fluid {stats['n_fluid']} ms {stats['ms']:.1f}", flush=True)
+
+
+def test_solid_fraction_matches_oracle():
+    import torch
+
+    props = al_si_alloy()
+    a = flow.Props.of(props)
+    fw = _flow(box_mesh((3, 3, 2), jitter=0.0, mode=None))
+    kinks = [a.T_liq, a.T_sol - a.T_eps, a.T_sol + a.T_eps, a.T_sol]
+    T = np.concatenate([np.linspace(800.0, 900.0, 4099), kinks,
+                        np.nextafter(kinks, np.inf), np.nextafter(kinks, -np.inf)])
+    fs = fw.solid_fraction(props, to_dev(T, torch.float64)).cpu().numpy()
+    ref = flow.solid_fraction(T, a)
+    assert np.array_equal(fs == 1.0, ref == 1.0) and np.array_equal(fs == 0.0, ref == 0.0)
+    assert np.abs(fs - ref).max() <= 4e-16
