@@ -215,6 +215,7 @@ struct ppe_solver {
   ppe::DevBuf g_inv;  // J^-1 per face, nine arrays of n_faces
   ppe::DevBuf pj_fs, pj_b, pj_r, pj_d, pj_grad, pj_xf, pj_part, pj_t, pj_vm;  // projection workspace
   ppe::DevBuf pj_k;  // BiCGSTAB vectors, partials and scalars
+  ppe::DevBuf pj_ax, pj_kind, pj_list, pj_cnt, pj_cells;  // cross weights, face kinds, case-2 faces
 
   // dominant-kernel measurement (event pairs around fine-level smoothing steps)
   bool prof = false;

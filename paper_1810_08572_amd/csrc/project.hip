@@ -311,6 +311,183 @@ __global__ void k_face_grad(int n_faces, const int* __restrict__ owner,
   xf[f] = x;
 }
 
+// ---- cross flux inside a projection: the mask is fixed, and every field
+// passed is zero on removed cells ----
+enum FaceKind : unsigned char { FK_CLOSED = 0, FK_OPEN = 1, FK_SMEAR = 2 };
+
+// w_V = share of solid cells at vertex V (the mask's part of the means)
+__global__ void k_vertex_solid(int n_nodes, const int* __restrict__ vptr,
+                               const int* __restrict__ vcell, const int* __restrict__ active,
+                               double* __restrict__ w) {
+  const int v = blockIdx.x * kBlock + threadIdx.x;
+  if (v >= n_nodes) return;
+  const int a = vptr[v], e = vptr[v + 1];
+  int solid = 0;
+  for (int k = a; k < e; ++k) solid += active[vcell[k]] ? 0 : 1;
+  w[v] = e > a ? (double)solid / (double)(e - a) : 0.0;
+}
+
+// closed (case 3 or wall), open with no solid neighbour (case 1), open with
+// solid neighbours (case 2); the cross weights t_f . g_k of open faces
+__global__ void k_face_kind(int n_faces, const int* __restrict__ owner,
+                            const int* __restrict__ neigh, const int* __restrict__ active,
+                            const int* __restrict__ face_nodes, const double* __restrict__ w,
+                            const double* __restrict__ gi, const double* __restrict__ t,
+                            unsigned char* __restrict__ kind, double* __restrict__ ax) {
+  const int f = blockIdx.x * kBlock + threadIdx.x;
+  if (f >= n_faces) return;
+  const int o = owner[f], n = neigh[f];
+  unsigned char k = FK_CLOSED;
+  double a[3] = {0.0, 0.0, 0.0};
+  if (open_face(active, o, n)) {
+    bool sm = false;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sm = sm || w[face_nodes[4 * (size_t)f + q]] != 0.0;
+    k = sm ? FK_SMEAR : FK_OPEN;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        a[c] += t[(size_t)d * n_faces + f] * gi[(size_t)(3 * c + d) * n_faces + f];
+  }
+  kind[f] = k;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) ax[(size_t)c * n_faces + f] = a[c];
+}
+
+// pbar_V = (sum of p over the vertex's cells) / n_V; p is zero on removed
+// cells, so this is the active-cell sum of the masked means
+__global__ void k_vertex_sum(int n_nodes, const int* __restrict__ vptr,
+                             const int* __restrict__ vcell, const double* __restrict__ p,
+                             double* __restrict__ pbar) {
+  const int v = blockIdx.x * kBlock + threadIdx.x;
+  if (v >= n_nodes) return;
+  const int a = vptr[v], e = vptr[v + 1];
+  double s = 0.0;
+  for (int k = a; k < e; ++k) s += p[vcell[k]];
+  pbar[v] = e > a ? s / (double)(e - a) : 0.0;
+}
+
+// x_f = t_f . grad(p)_f = sum_k a_k(f) d_k on open faces without solid
+// neighbours (case 1), 0 on closed faces; case-2 faces are left to
+// k_face_cross_smear, so that these waves stay uniform.
+__global__ void k_face_cross(int n_faces, const int* __restrict__ owner,
+                             const int* __restrict__ neigh, const int* __restrict__ face_nodes,
+                             const unsigned char* __restrict__ kind, const double* __restrict__ ax,
+                             const double* __restrict__ pbar, const double* __restrict__ p,
+                             double* __restrict__ xf) {
+  const int f = blockIdx.x * kBlock + threadIdx.x;
+  if (f >= n_faces) return;
+  const unsigned char k = kind[f];
+  if (k == FK_SMEAR) return;
+  double x = 0.0;
+  if (k == FK_OPEN) {
+    const int o = owner[f], n = neigh[f];
+    const int4 vv = *reinterpret_cast<const int4*>(face_nodes + 4 * (size_t)f);
+    x = ax[f] * (p[n] - p[o]) + ax[(size_t)n_faces + f] * (pbar[vv.z] - pbar[vv.x]) +
+        ax[2 * (size_t)n_faces + f] * (pbar[vv.w] - pbar[vv.y]);
+  }
+  xf[f] = x;
+}
+
+// Distinct active cells among the four vertex lists of face f (the cells
+// whose mean replaces the solid ones, Eq. 15-16), in ascending order: the
+// count (cells == nullptr) or the cells themselves.
+__device__ __forceinline__ int smear_cells(int f, const int* __restrict__ active,
+                                           const int* __restrict__ face_nodes,
+                                           const int* __restrict__ vptr,
+                                           const int* __restrict__ vcell, int* __restrict__ cells) {
+  int pos[4], end[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int v = face_nodes[4 * (size_t)f + q];
+    pos[q] = vptr[v];
+    end[q] = vptr[v + 1];
+  }
+  int n_act = 0;
+  for (;;) {
+    int c = INT32_MAX;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (pos[q] < end[q]) c = min(c, vcell[pos[q]]);
+    if (c == INT32_MAX) break;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (pos[q] < end[q] && vcell[pos[q]] == c) ++pos[q];
+    if (active[c]) {
+      if (cells) cells[n_act] = c;
+      ++n_act;
+    }
+  }
+  return n_act;
+}
+
+// once per projection: count[f] = that number on case-2 faces, 0 elsewhere
+__global__ void k_smear_count(int n_faces, const unsigned char* __restrict__ kind,
+                              const int* __restrict__ active, const int* __restrict__ face_nodes,
+                              const int* __restrict__ vptr, const int* __restrict__ vcell,
+                              int* __restrict__ count) {
+  const int f = blockIdx.x * kBlock + threadIdx.x;
+  if (f >= n_faces) return;
+  count[f] = kind[f] == FK_SMEAR ? smear_cells(f, active, face_nodes, vptr, vcell, nullptr) : 0;
+}
+
+__global__ void k_smear_fill(const long long* __restrict__ n_list, const int* __restrict__ list,
+                             const int* __restrict__ active, const int* __restrict__ face_nodes,
+                             const int* __restrict__ vptr, const int* __restrict__ vcell,
+                             const int* __restrict__ off, int* __restrict__ cells) {
+  const long long nl = *n_list;
+  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < nl;
+       i += (long long)gridDim.x * kBlock) {
+    const int f = list[i];
+    smear_cells(f, active, face_nodes, vptr, vcell, cells + off[f]);
+  }
+}
+
+// Case-2 faces (listed, *n_list of them): the solid cells of the four vertex
+// means take the mean m of the face's remaining neighbour cells, whose
+// ascending list cells[off[f]..off[f+1]) was built for this mask.
+__global__ void k_face_cross_smear(const long long* __restrict__ n_list,
+                                   const int* __restrict__ list, int n_faces,
+                                   const int* __restrict__ owner, const int* __restrict__ neigh,
+                                   const int* __restrict__ face_nodes,
+                                   const int* __restrict__ off, const int* __restrict__ cells,
+                                   const double* __restrict__ ax, const double* __restrict__ pbar,
+                                   const double* __restrict__ w, const double* __restrict__ p,
+                                   double* __restrict__ xf) {
+  const long long nl = *n_list;
+  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < nl;
+       i += (long long)gridDim.x * kBlock) {
+    const int f = list[i];
+    const int o = owner[f], n = neigh[f];
+    const int a = off[f], e = off[f + 1];
+    double psum = 0.0;
+    for (int k = a; k < e; ++k) psum += p[cells[k]];
+    const double m = psum / (double)(e - a);  // the owners are active: e - a >= 2
+    const int4 vv = *reinterpret_cast<const int4*>(face_nodes + 4 * (size_t)f);
+    const double pb0 = pbar[vv.x] + w[vv.x] * m, pb1 = pbar[vv.y] + w[vv.y] * m;
+    const double pb2 = pbar[vv.z] + w[vv.z] * m, pb3 = pbar[vv.w] + w[vv.w] * m;
+    xf[f] = ax[f] * (p[n] - p[o]) + ax[(size_t)n_faces + f] * (pb2 - pb0) +
+            ax[2 * (size_t)n_faces + f] * (pb3 - pb1);
+  }
+}
+
+__global__ void k_smear_flags(int n_faces, const unsigned char* __restrict__ kind,
+                              int* __restrict__ flag) {
+  const int f = blockIdx.x * kBlock + threadIdx.x;
+  if (f < n_faces) flag[f] = kind[f] == FK_SMEAR ? 1 : 0;
+}
+
+__global__ void k_set_last(const long long* __restrict__ v, int* __restrict__ dst) {
+  *dst = (int)*v;
+}
+
+__global__ void k_smear_list(int n_faces, const unsigned char* __restrict__ kind,
+                             const int* __restrict__ pos, int* __restrict__ list) {
+  const int f = blockIdx.x * kBlock + threadIdx.x;
+  if (f < n_faces && kind[f] == FK_SMEAR) list[pos[f]] = f;
+}
+
 // r = b + X p - L p on non-pinned active cells (0 elsewhere), with block
 // partials of r.r
 __global__ void __launch_bounds__(kBlock) k_full_residual(
@@ -623,6 +800,97 @@ void face_gradient(ppe_solver* s, const double* p, const double* t, double* grad
   PPE_LAUNCH_CHECK();
 }
 
+namespace {
+
+// Mask-dependent face data of one projection: solid shares, face kinds and
+// the cross weights of the cross vectors t.
+struct CrossData {
+  unsigned char* kind;
+  double* ax;
+  double* w;
+  double* pbar;
+  int* list;               // case-2 faces
+  const long long* count;  // their number (device)
+  int* off;                // their remaining cells: cells[off[f]..off[f+1])
+  int* cells;
+};
+
+CrossData prepare_cross(ppe_solver* s, const double* t) {
+  const int nf = s->n_faces, nn = s->n_nodes;
+  CrossData cd{};
+  cd.w = s->pj_vm.get<double>(2 * (size_t)nn);
+  cd.pbar = cd.w + nn;
+  cd.ax = s->pj_ax.get<double>(3 * (size_t)(nf > 0 ? nf : 1));
+  cd.kind = s->pj_kind.get<unsigned char>(nf > 0 ? nf : 1);
+  hipLaunchKernelGGL(k_vertex_solid, dim3(grid_for(nn)), dim3(kBlock), 0, s->stream, nn,
+                     s->g_vptr.as<int>(), s->g_vcell.as<int>(), s->active.as<int>(), cd.w);
+  PPE_LAUNCH_CHECK();
+  if (nf == 0) return cd;
+  const int* active = s->active.as<int>();
+  const int* fnodes = s->g_fnodes.as<int>();
+  const int* vptr = s->g_vptr.as<int>();
+  const int* vcell = s->g_vcell.as<int>();
+  hipLaunchKernelGGL(k_face_kind, dim3(grid_for(nf)), dim3(kBlock), 0, s->stream, nf,
+                     s->owner.as<int>(), s->neigh.as<int>(), active, fnodes, cd.w,
+                     s->g_inv.as<double>(), t, cd.kind, cd.ax);
+  PPE_LAUNCH_CHECK();
+  // the case-2 faces: a list, and for each the ascending list of its
+  // remaining neighbour cells
+  int* buf = s->pj_list.get<int>(4 * (size_t)nf + 4);
+  int* flag = buf;
+  int* pos = flag + nf + 1;
+  int* cnt = pos + nf + 1;
+  cd.off = cnt + nf + 1;
+  hipLaunchKernelGGL(k_smear_flags, dim3(grid_for(nf)), dim3(kBlock), 0, s->stream, nf, cd.kind,
+                     flag);
+  PPE_LAUNCH_CHECK();
+  const long long* total = exclusive_scan_async(s, flag, pos, nf, 0);
+  long long* counts = s->pj_cnt.get<long long>(2);
+  // the scan totals sit in shared slots: keep copies of our own
+  PPE_HIP(hipMemcpyAsync(counts, total, sizeof(long long), hipMemcpyDeviceToDevice, s->stream));
+  cd.count = counts;
+  cd.list = flag;  // the flags are consumed by the scan; the list reuses them
+  hipLaunchKernelGGL(k_smear_list, dim3(grid_for(nf)), dim3(kBlock), 0, s->stream, nf, cd.kind,
+                     pos, cd.list);
+  PPE_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_smear_count, dim3(grid_for(nf)), dim3(kBlock), 0, s->stream, nf, cd.kind,
+                     active, fnodes, vptr, vcell, cnt);
+  PPE_LAUNCH_CHECK();
+  const long long* nnz_d = exclusive_scan_async(s, cnt, cd.off, nf, 1);
+  long long nnz = 0;
+  read_back(s, {ReadItem{nnz_d, sizeof(long long), &nnz}});
+  // off[nf] = nnz closes the last row
+  PPE_HIP(hipMemcpyAsync(counts + 1, nnz_d, sizeof(long long), hipMemcpyDeviceToDevice, s->stream));
+  hipLaunchKernelGGL(k_set_last, dim3(1), dim3(1), 0, s->stream, counts + 1, cd.off + nf);
+  PPE_LAUNCH_CHECK();
+  cd.cells = s->pj_cells.get<int>(nnz > 0 ? (size_t)nnz : 1);
+  const int gs = grid_for(nf) < 512 ? grid_for(nf) : 512;
+  hipLaunchKernelGGL(k_smear_fill, dim3(gs), dim3(kBlock), 0, s->stream, cd.count, cd.list, active,
+                     fnodes, vptr, vcell, cd.off, cd.cells);
+  PPE_LAUNCH_CHECK();
+  return cd;
+}
+
+// xf = t_f . grad(p)_f for a field p that is zero on removed cells
+void cross_flux(ppe_solver* s, const CrossData& cd, const double* p, double* xf) {
+  const int nf = s->n_faces, nn = s->n_nodes;
+  if (nf == 0) return;
+  hipLaunchKernelGGL(k_vertex_sum, dim3(grid_for(nn)), dim3(kBlock), 0, s->stream, nn,
+                     s->g_vptr.as<int>(), s->g_vcell.as<int>(), p, cd.pbar);
+  PPE_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_face_cross, dim3(grid_for(nf)), dim3(kBlock), 0, s->stream, nf,
+                     s->owner.as<int>(), s->neigh.as<int>(), s->g_fnodes.as<int>(), cd.kind,
+                     cd.ax, cd.pbar, p, xf);
+  PPE_LAUNCH_CHECK();
+  const int gs = grid_for(nf) < 512 ? grid_for(nf) : 512;
+  hipLaunchKernelGGL(k_face_cross_smear, dim3(gs), dim3(kBlock), 0, s->stream, cd.count, cd.list,
+                     nf, s->owner.as<int>(), s->neigh.as<int>(), s->g_fnodes.as<int>(), cd.off,
+                     cd.cells, cd.ax, cd.pbar, cd.w, p, xf);
+  PPE_LAUNCH_CHECK();
+}
+
+}  // namespace
+
 ppe_status project(ppe_solver* s, const double* coeff, const double* ustar, double rho, double dt,
                    double* p, double* flux, double* u, ppe_project_stats* out) {
   const int nc = s->n_cells, nf = s->n_faces;
@@ -652,11 +920,12 @@ ppe_status project(ppe_solver* s, const double* coeff, const double* ustar, doub
   PPE_LAUNCH_CHECK();
   double* t = s->pj_t.get<double>(3 * (size_t)(nf > 0 ? nf : 1));
   cross_vectors(s, coeff, rho, t);
+  const CrossData cd = prepare_cross(s, t);
   fill_double(s, p, 0.0, nc);
   // r = b + X p - L p at p = 0 is b on the non-pinned active cells: its norm
   // is the reference ||b'||
   auto residual = [&](int slot) {
-    face_gradient(s, p, t, nullptr, xf);
+    cross_flux(s, cd, p, xf);
     hipLaunchKernelGGL(k_full_residual, dim3(gc), dim3(kBlock), 0, s->stream, nc, aptr, anbr, aface,
                        owner, active, s->comp_full.as<int>(), coeff, b, xf, p, r, part);
     PPE_LAUNCH_CHECK();
@@ -705,7 +974,7 @@ ppe_status project(ppe_solver* s, const double* coeff, const double* ustar, doub
       PPE_LAUNCH_CHECK();
     };
     auto apply = [&](const double* in, const double* w, double* outv, bool two) {
-      face_gradient(s, in, t, nullptr, xf);
+      cross_flux(s, cd, in, xf);
       if (two)
         hipLaunchKernelGGL(k_apply_full<true>, dim3(gc), dim3(kBlock), 0, s->stream, nc, aptr, anbr,
                            aface, owner, active, comp, coeff, xf, in, w, outv, bpart);

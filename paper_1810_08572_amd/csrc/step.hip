@@ -317,19 +317,23 @@ __global__ void k_max3(int g, const double* __restrict__ part, double* __restric
     for (int k = 0; k < 3; ++k) out[k] = m[k];
 }
 
-// Outputs of the step: solid cells (f_s = 1) lose their velocity; count them.
-__global__ void k_finish_cells(int nc, const double* __restrict__ u_new,
-                               const double* __restrict__ Tm, const double* __restrict__ fm,
-                               double* __restrict__ u, double* __restrict__ T,
-                               double* __restrict__ fs, int* __restrict__ n_solid) {
+// Outputs of the step: solid cells (f_s = 1) lose their velocity; count them
+// (one atomic per workgroup).
+__global__ void __launch_bounds__(kBlock) k_finish_cells(
+    int nc, const double* __restrict__ u_new, const double* __restrict__ Tm,
+    const double* __restrict__ fm, double* __restrict__ u, double* __restrict__ T,
+    double* __restrict__ fs, int* __restrict__ n_solid) {
   const int c = blockIdx.x * kBlock + threadIdx.x;
-  if (c >= nc) return;
-  const bool solid = !(fm[c] < 1.0);
+  int solid = 0;
+  if (c < nc) {
+    solid = fm[c] < 1.0 ? 0 : 1;
 #pragma unroll
-  for (int q = 0; q < 3; ++q) u[3 * (size_t)c + q] = solid ? 0.0 : u_new[3 * (size_t)c + q];
-  T[c] = Tm[c];
-  fs[c] = fm[c];
-  if (solid) atomicAdd(n_solid, 1);
+    for (int q = 0; q < 3; ++q) u[3 * (size_t)c + q] = solid ? 0.0 : u_new[3 * (size_t)c + q];
+    T[c] = Tm[c];
+    fs[c] = fm[c];
+  }
+  solid = block_sum<kBlock>(solid);
+  if (threadIdx.x == 0 && solid) atomicAdd(n_solid, solid);
 }
 
 __global__ void k_finish_faces(int nf, const int* __restrict__ owner, const int* __restrict__ neigh,
@@ -351,9 +355,12 @@ __global__ void k_solid_fraction(int n, const double* __restrict__ T, Alloy a,
   fs[c] = f;
 }
 
-__global__ void k_count_fluid(int nc, const double* __restrict__ fs, int* __restrict__ n) {
+__global__ void __launch_bounds__(kBlock) k_count_fluid(int nc, const double* __restrict__ fs,
+                                                        int* __restrict__ n) {
   const int c = blockIdx.x * kBlock + threadIdx.x;
-  if (c < nc && fs[c] < 1.0) atomicAdd(n, 1);
+  int fluid = (c < nc && fs[c] < 1.0) ? 1 : 0;
+  fluid = block_sum<kBlock>(fluid);
+  if (threadIdx.x == 0 && fluid) atomicAdd(n, fluid);
 }
 
 void check(ppe_flow* fl, ppe_solver* s, ppe_status st, const char* what, ppe_status& worst) {
