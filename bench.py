@@ -285,7 +285,7 @@ def train_network(ppe, torch, wl, d_in, n_adam=400, batch=8192):
                                 loss_last=float(np.mean(losses[-10:])))
 
 
-def projection_leg(ppe, torch, wl, d_in, steps, warm, dev, base, krylov="deferred"):
+def projection_leg(ppe, torch, wl, d_in, steps, warm, dev, base, krylov="bicgstab"):
     """The whole pressure-correction step on the same 64^3 timesteps: a smooth
     synthetic u* per step, masked assembly, then ppe_project (cross diffusion
     by deferred correction around the AMG-PCG solve, consistent face fluxes
@@ -705,8 +705,8 @@ def main():
         out["variants"] = {
             "projection_cross_diffusion": projection_leg(ppe, torch, wl, d_in, steps, warm, dev,
                                                          base),
-            "projection_cross_diffusion_bicgstab": projection_leg(ppe, torch, wl, d_in, steps,
-                                                                  warm, dev, base, "bicgstab")}
+            "projection_cross_diffusion_deferred": projection_leg(ppe, torch, wl, d_in, steps,
+                                                                  warm, dev, base, "deferred")}
         print(json.dumps(out), flush=True)
         return
     if not args.no_variants:
@@ -730,8 +730,8 @@ def main():
         if not args.no_projection:
             variants["projection_cross_diffusion"] = projection_leg(ppe, torch, wl, d_in, steps,
                                                                     warm, dev, base)
-            variants["projection_cross_diffusion_bicgstab"] = projection_leg(
-                ppe, torch, wl, d_in, steps, warm, dev, base, "bicgstab")
+            variants["projection_cross_diffusion_deferred"] = projection_leg(
+                ppe, torch, wl, d_in, steps, warm, dev, base, "deferred")
             note("projection legs done")
         if not args.no_flow:
             variants["fractional_step"] = fractional_step_leg(ppe, torch, dev, K, W)

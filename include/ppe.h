@@ -89,11 +89,12 @@ typedef struct {
                          unchanged.  Default 0: every assembly rebuilds. */
   int project_krylov; /* outer iteration of ppe_project for the non-symmetric
                          system (L - X) p = b' with the cross term implicit:
-                         0 (default) deferred correction, each pass an AMG-PCG
-                         solve of L; 1 BiCGSTAB preconditioned by one V-cycle of
+                         1 (default) BiCGSTAB preconditioned by one V-cycle of
                          L's hierarchy per application (section 2.5 names
                          BiCGSTAB as the paper's Krylov method for systems PCG
-                         cannot take).  Both stop on the same true residual. */
+                         cannot take), falling back to deferred correction on
+                         breakdown; 0 deferred correction, each pass an AMG-PCG
+                         solve of L.  Both stop on the same true residual. */
 } ppe_options;
 
 typedef struct {

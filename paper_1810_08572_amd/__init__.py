@@ -282,7 +282,7 @@ class Solver:
     def __init__(self, precision="fp64", rtol=1e-10, max_iter=500, cheb_degree=2,
                  cheb_ratio=30.0, coarse_max=128, max_levels=10, theta=0.08, stream=None,
                  use_graph=True, check_every=2, autotune=False, reuse_unchanged=False,
-                 krylov="deferred"):
+                 krylov="bicgstab"):
         import torch
 
         lib = load_library()
@@ -630,7 +630,7 @@ class Flow:
     FP64 to transport_rtol."""
 
     def __init__(self, precision="fp64", rtol=1e-10, transport_rtol=1e-12, stream=None,
-                 use_graph=True, autotune=False, krylov="deferred"):
+                 use_graph=True, autotune=False, krylov="bicgstab"):
         import torch
 
         self._lib = load_library()

@@ -99,7 +99,7 @@ void ppe_default_options(ppe_options* o) {
   o->use_graph = 1;
   o->autotune = 0;
   o->reuse_unchanged = 0;
-  o->project_krylov = 0;
+  o->project_krylov = 1;
 }
 
 ppe_status ppe_create(const ppe_options* opt, ppe_solver** out) {

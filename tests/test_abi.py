@@ -37,6 +37,7 @@ def test_host_only_calls():
     o = ppe.ppe_default_options()
     assert o.rtol == 1e-10 and o.max_iter == 500 and o.cheb_degree == 2
     assert o.coarse_max == 128 and o.theta == 0.08
+    assert o.project_krylov == 1 and o.reuse_unchanged == 0
     assert ppe.ppe_status_string(ppe.PPE_ERR_STATE) == "call out of order"
     assert ppe.ppe_status_string(ppe.PPE_NOT_CONVERGED) == "not converged"
     # NULL solver handles are rejected without touching a device
