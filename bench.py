@@ -396,7 +396,8 @@ def fractional_step_leg(ppe, torch, dev, K, W, krylov="bicgstab"):
                     f"500 K from a {FLOW_LAYER * 1e3:.1f} mm boundary layer, dt {FLOW_DT:g} s, "
                     "natural convection; momentum predictor (3 AMG-PCG solves of a shifted "
                     f"system) + masked cross-diffusion projection ({krylov}) + energy Picard loop "
-                    "(one shifted AMG setup and solve per pass), FP64",
+                    "(shifted AMG setup on the first pass, finest-level refresh on the later "
+                    "ones, one solve per pass), FP64",
         "steps_per_s": K / el,
         "ms_per_step": 1e3 * el / K,
         "cells": m.n_cells,

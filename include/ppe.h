@@ -152,6 +152,20 @@ ppe_status ppe_assemble(ppe_solver* s, const double* face_coeff,
 ppe_status ppe_assemble_shifted(ppe_solver* s, const double* face_coeff,
                                 const double* liquid_fraction, const double* diag_shift);
 
+/* A new diagonal shift for the system of the last ppe_assemble_shifted, with
+ * the same face_coeff and mask (the caller guarantees both): the finest
+ * level's diagonal, its spectral bound and Chebyshev coefficients are
+ * recomputed; the coarser levels of the hierarchy are kept as they are.  The
+ * V-cycle stays a symmetric positive-definite preconditioner and ppe_solve
+ * solves the new system to rtol; only its iteration count may differ from a
+ * fresh assembly's.  For repeated solves whose matrices differ only on the
+ * diagonal (the latent-heat Picard passes of the energy step).  Launch
+ * choices return to the fixed rules.  Errors: PPE_ERR_STATE unless the last
+ * assembly was shifted; PPE_ERR_ARG on NULL arrays or a shift that is not
+ * finite and > 0 on a kept cell (the system must then be assembled again:
+ * ppe_solve returns PPE_ERR_STATE until it is). */
+ppe_status ppe_refresh_shift(ppe_solver* s, const double* face_coeff, const double* diag_shift);
+
 /* Solve A p = b' (Eq. 9 as modified in section 2.4.2) by conjugate gradients
  * preconditioned with one V-cycle per iteration (section 2.5), until the
  * recomputed true residual meets rtol ||b'||.  With PPE_MIXED the V-cycle

@@ -5,7 +5,8 @@
  *
  * Every linear system is solved by the AMG-PCG of ppe.h: the momentum and
  * energy matrices (diagonal + Crank-Nicolson half of the direct diffusion
- * term) through ppe_assemble_shifted, the pressure through ppe_assemble and
+ * term) through ppe_assemble_shifted (the energy step's later Picard passes
+ * through ppe_refresh_shift), the pressure through ppe_assemble and
  * ppe_project.  All arrays are DEVICE pointers owned by the caller unless
  * stated otherwise; calls run on the stream of the options given at
  * creation and return after the stream has finished the step.

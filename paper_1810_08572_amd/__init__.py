@@ -117,6 +117,7 @@ _SIGS = {
     "ppe_set_mesh": (ctypes.c_int, [_P, _I32, _I32, _P, _P]),
     "ppe_assemble": (ctypes.c_int, [_P, _P, _P]),
     "ppe_assemble_shifted": (ctypes.c_int, [_P, _P, _P, _P]),
+    "ppe_refresh_shift": (ctypes.c_int, [_P, _P, _P]),
     "ppe_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.POINTER(ppe_stats)]),
     "ppe_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(ppe_stats)]),
     "ppe_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -361,6 +362,14 @@ class Solver:
         self._chk(self._lib.ppe_assemble_shifted(
             self._h, _dev_ptr(face_coeff, torch.float64, nf, "face_coeff"), fl,
             _dev_ptr(diag_shift, torch.float64, nc, "diag_shift")))
+
+    def refresh_shift(self, face_coeff, diag_shift):
+        """New diagonal shift, same coefficients and mask: finest level only."""
+        import torch
+
+        self._chk(self._lib.ppe_refresh_shift(
+            self._h, _dev_ptr(face_coeff, torch.float64, self.n_faces, "face_coeff"),
+            _dev_ptr(diag_shift, torch.float64, self.n_cells, "diag_shift")))
 
     def solve(self, rhs, x0=None, out=None, allow_not_converged=False):
         import torch
@@ -621,6 +630,31 @@ class FlowState:
     conv_u: "object"   # [n, 3]
     conv_T: "object"   # [n]
     have_history: bool = False
+    step: int = 0      # steps taken since the state was created
+    time: float = 0.0  # simulated time
+
+    _FIELDS = ("u", "T", "fs", "flux", "p", "conv_u", "conv_T")
+
+    def save(self, path):
+        """Snapshot to an .npz file (host copies; a restart needs all of it,
+        the convection history included)."""
+        import numpy as np
+
+        arrays = {k: getattr(self, k).detach().cpu().numpy() for k in self._FIELDS}
+        np.savez(path, have_history=np.array(bool(self.have_history)),
+                 step=np.array(int(self.step)), time=np.array(float(self.time)), **arrays)
+
+    @classmethod
+    def load(cls, path, device):
+        """State saved by save(), on `device`."""
+        import numpy as np
+        import torch
+
+        with np.load(path, allow_pickle=False) as z:
+            t = {k: torch.as_tensor(z[k], dtype=torch.float64, device=device).contiguous()
+                 for k in cls._FIELDS}
+            return cls(**t, have_history=bool(z["have_history"]), step=int(z["step"]),
+                       time=float(z["time"]))
 
 
 class Flow:
@@ -727,7 +761,21 @@ class Flow:
             _dev_ptr(state.conv_T, torch.float64, n, "conv_T"), ctypes.byref(st))
         self._chk(status, allow)
         state.have_history = True
+        state.step += 1
+        state.time += float(dt)
         return status, st.as_dict()
+
+    def run(self, props, state: FlowState, dt, n_steps, snapshot_every=0, snapshot=None,
+            **step_kw):
+        """n_steps steps; every snapshot_every steps (0: never) calls
+        snapshot(state) (e.g. lambda st: st.save(f"snap_{st.step:06d}.npz")).
+        Returns the per-step statistics."""
+        out = []
+        for _ in range(int(n_steps)):
+            out.append(self.step(props, state, dt, **step_kw)[1])
+            if snapshot_every and snapshot is not None and state.step % snapshot_every == 0:
+                snapshot(state)
+        return out
 
 
 class PolynomialChaos:

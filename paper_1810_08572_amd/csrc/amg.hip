@@ -1071,6 +1071,12 @@ void ensure_side_stream(ppe_solver* s) {
 
 }  // namespace
 
+const double* level0_bound_async(ppe_solver* s) {
+  double* out = s->setup_out.get<double>((size_t)std::max(1, s->opt.max_levels) + 1);
+  spectral_bound(s, s->levels[0], 0, out);
+  return out;
+}
+
 void build_hierarchy(ppe_solver* s) {
   const double theta2 = s->opt.theta * s->opt.theta;
   const int maxlev = std::max(1, s->opt.max_levels);

@@ -268,6 +268,30 @@ ppe_status ppe_assemble(ppe_solver* s, const double* face_coeff, const double* f
   return assemble_impl(s, face_coeff, fl, nullptr);
 }
 
+ppe_status ppe_refresh_shift(ppe_solver* s, const double* face_coeff, const double* diag_shift) {
+  if (!s) return PPE_ERR_ARG;
+  return guarded(s, [&]() -> ppe_status {
+    DeviceGuard g(s->device);
+    ppe::require(s->assembled && s->shifted, PPE_ERR_STATE,
+                 "ppe_refresh_shift needs a shifted system (ppe_assemble_shifted)");
+    ppe::require(diag_shift && (face_coeff || s->n_faces == 0), PPE_ERR_ARG, "NULL input array");
+    PPE_HIP(hipEventRecord(s->ev0, s->stream));
+    ppe::drop_graph(s);
+    try {
+      ppe::refresh_fine_shift(s, face_coeff, diag_shift);
+    } catch (...) {
+      s->assembled = false;  // the finest level may be half rewritten
+      throw;
+    }
+    ppe::prepare_solve_levels(s);
+    if (s->opt.precision == PPE_MIXED) ppe::make_fp32_hierarchy(s);
+    PPE_HIP(hipEventRecord(s->ev1, s->stream));
+    PPE_HIP(hipEventSynchronize(s->ev1));
+    s->stats.setup_ms = elapsed_ms(s->ev0, s->ev1);
+    return PPE_OK;
+  });
+}
+
 ppe_status ppe_assemble_shifted(ppe_solver* s, const double* face_coeff, const double* fl,
                                 const double* diag_shift) {
   if (s && !diag_shift) {

@@ -274,6 +274,29 @@ __global__ void k_fill_rows(const int* __restrict__ perm, int n_active,
   }
 }
 
+// A new diagonal for the finest level of a shifted system: the same sum as
+// k_fill_rows (shift, then the open faces in ascending neighbour order),
+// into diag and into the CSR row's diagonal entry.  Bit 8: a bad shift.
+__global__ void k_refresh_diag(const int* __restrict__ perm, int n_active,
+                               const int* __restrict__ adj_ptr, const int* __restrict__ adj_nbr,
+                               const int* __restrict__ adj_face, const int* __restrict__ active,
+                               const double* __restrict__ coeff, const double* __restrict__ shift,
+                               const int* __restrict__ rowptr, const int* __restrict__ col,
+                               double* __restrict__ val, double* __restrict__ diag,
+                               int* __restrict__ flag) {
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  if (r >= n_active) return;
+  const int c = perm[r];
+  const double sh = shift[c];
+  if (!(sh > 0.0) || !(sh <= 1.7976931348623157e308)) atomicOr(flag, 8);
+  double d = sh;
+  for (int k = adj_ptr[c]; k < adj_ptr[c + 1]; ++k)
+    if (active[adj_nbr[k]]) d = d + coeff[adj_face[k]];
+  diag[r] = d;
+  for (int p = rowptr[r]; p < rowptr[r + 1]; ++p)
+    if (col[p] == r) val[p] = d;
+}
+
 __global__ void k_gather_int(int n, const int* __restrict__ idx, const int* __restrict__ src,
                              int* __restrict__ dst) {
   int i = blockIdx.x * kBlock + threadIdx.x;
@@ -528,6 +551,25 @@ void assemble_fine(ppe_solver* s, const double* coeff, const double* fl, const d
                      s->adj_ptr.as<int>(), s->adj_nbr.as<int>(), s->adj_face.as<int>(), active,
                      is_pin, cid, coeff, rowptr, col, val, diag, L.W, ecol, evl, B, shift);
   PPE_LAUNCH_CHECK();
+}
+
+void refresh_fine_shift(ppe_solver* s, const double* coeff, const double* shift) {
+  Level& L = s->levels[0];
+  const int na = s->n_active;
+  if (na == 0) return;
+  int* flag = s->flag.get<int>(1);
+  fill_int(s, flag, 0, 1);
+  hipLaunchKernelGGL(k_refresh_diag, dim3(grid_for(na)), dim3(kBlock), 0, s->stream,
+                     s->perm.as<int>(), na, s->adj_ptr.as<int>(), s->adj_nbr.as<int>(),
+                     s->adj_face.as<int>(), s->active.as<int>(), coeff, shift, L.A.rp(), L.A.ci(),
+                     L.A.val.as<double>(), L.diag.as<double>(), flag);
+  PPE_LAUNCH_CHECK();
+  double rho = 0.0;
+  const double* rho_dev = level0_bound_async(s);
+  int bad = 0;
+  read_back(s, {ReadItem{flag, sizeof(int), &bad}, ReadItem{rho_dev, sizeof(double), &rho}});
+  require(!(bad & 8), PPE_ERR_ARG, "diagonal shift must be finite and > 0 on every active cell");
+  if (s->nlev > 1 || L.rho > 0.0) L.rho = rho;  // a level solved directly keeps rho = 0
 }
 
 }  // namespace ppe

@@ -437,6 +437,13 @@ void check_segments(ppe_solver* s, const std::vector<int>& off);
 // (> 0 on active cells): diag(shift) + L without pins; fl may then be NULL
 // (every cell active).
 void assemble_fine(ppe_solver* s, const double* coeff, const double* fl, const double* shift);
+// A shifted system's new shift with the same face coefficients and mask: the
+// finest level's diagonal and spectral bound are recomputed; the coarse
+// levels stay (the V-cycle stays symmetric positive definite).
+void refresh_fine_shift(ppe_solver* s, const double* coeff, const double* shift);
+// The finest level's spectral bound, queued into the setup output slot
+// (device address returned).
+const double* level0_bound_async(ppe_solver* s);
 // Checks the fields (raising PPE_ERR_ARG as the assembly does) and returns
 // whether the coefficients and the mask equal those of the last assembly.
 bool same_system(ppe_solver* s, const double* coeff, const double* fl);

@@ -675,7 +675,13 @@ ppe_status ppe_flow_step(ppe_flow* f, const ppe_alloy* al, const ppe_step_params
                          f->vol.as<double>(), f->wsum.as<double>(), base, Tm, fm, fs_n, a, dt,
                          shift, erhs, Tnew);
       PPE_LAUNCH_CHECK();
-      check(f, f->ene, ppe_assemble_shifted(f->ene, ce, nullptr, shift), "energy assembly", worst);
+      // the passes differ only in the latent term's diagonal: the first one
+      // builds the hierarchy, the later ones refresh the finest level
+      if (it == 1)
+        check(f, f->ene, ppe_assemble_shifted(f->ene, ce, nullptr, shift), "energy assembly",
+              worst);
+      else
+        check(f, f->ene, ppe_refresh_shift(f->ene, ce, shift), "energy refresh", worst);
       ppe_stats es{};
       check(f, f->ene, ppe_solve(f->ene, erhs, Tnew, 1, &es), "energy solve", worst);
       st.energy_iterations += es.iterations;

@@ -214,3 +214,48 @@ def test_solid_fraction_matches_oracle():
     ref = flow.solid_fraction(T, a)
     assert np.array_equal(fs == 1.0, ref == 1.0) and np.array_equal(fs == 0.0, ref == 0.0)
     assert np.abs(fs - ref).max() <= 4e-16
+
+
+def test_refresh_shift_solves_the_new_system():
+    import torch
+
+    import paper_1810_08572_amd as ppe
+
+    m = box_mesh((24, 20, 16), jitter=0.1, seed=4)
+    c = face_coeff(m, 2400.0)
+    rng = np.random.default_rng(8)
+    # weak shifts: a multi-level hierarchy, kept by the refresh
+    s1 = (0.5 + rng.random(m.n_cells)) * 0.05 * c.max()
+    s2 = s1 * (1.0 + 3.0 * rng.random(m.n_cells))
+    b = rng.normal(size=m.n_cells)
+    A2 = (sp.diags(s2) + _lap(m, c, np.ones(m.n_cells, dtype=bool))).tocsc()
+    ref = spla.spsolve(A2, b)
+    s = ppe.Solver(rtol=1e-12)
+    s.set_mesh(m.n_cells, to_dev(m.owner, torch.int32), to_dev(m.neigh, torch.int32))
+    s.assemble_shifted(to_dev(c, torch.float64), to_dev(s1, torch.float64))
+    levels = s.stats()["levels"]
+    assert levels >= 2
+    s.refresh_shift(to_dev(c, torch.float64), to_dev(s2, torch.float64))
+    r = s.solve(to_dev(b, torch.float64))
+    x = r.p.cpu().numpy()
+    assert s.stats()["levels"] == levels
+    assert np.linalg.norm(x - ref) <= 1e-10 * np.linalg.norm(ref)
+    fresh = ppe.Solver(rtol=1e-12)
+    fresh.set_mesh(m.n_cells, to_dev(m.owner, torch.int32), to_dev(m.neigh, torch.int32))
+    fresh.assemble_shifted(to_dev(c, torch.float64), to_dev(s2, torch.float64))
+    rf = fresh.solve(to_dev(b, torch.float64))
+    print(f"refresh: {r.stats['iterations']} iterations, fresh: {rf.stats['iterations']}")
+    assert r.stats["iterations"] <= 2 * rf.stats["iterations"] + 2
+    # errors: a bad shift, and a pressure system
+    bad = s2.copy()
+    bad[5] = -1.0
+    with pytest.raises(ppe.PpeError) as e:
+        s.refresh_shift(to_dev(c, torch.float64), to_dev(bad, torch.float64))
+    assert e.value.status == ppe.PPE_ERR_ARG
+    with pytest.raises(ppe.PpeError) as e:
+        s.solve(to_dev(b, torch.float64))
+    assert e.value.status == ppe.PPE_ERR_STATE
+    s.assemble(to_dev(c, torch.float64), to_dev(np.ones(m.n_cells), torch.float64))
+    with pytest.raises(ppe.PpeError) as e:
+        s.refresh_shift(to_dev(c, torch.float64), to_dev(s2, torch.float64))
+    assert e.value.status == ppe.PPE_ERR_STATE
