@@ -83,9 +83,13 @@ typedef struct {
 
 /* Create a driver.  opt configures the pressure solver (stream, precision,
  * rtol and the rest, as ppe_create); the momentum and energy solvers use
- * the same options with FP64 arithmetic, no reuse, and relative residual
- * transport_rtol (> 0, e.g. 1e-12).  PPE_ERR_ARG on NULL out or bad
- * values; the errors of ppe_create. */
+ * the same options with FP64 arithmetic and relative residual
+ * transport_rtol (> 0, e.g. 1e-12).  With opt->reuse_unchanged the pressure
+ * system and its hierarchy are kept while the mask is unchanged (they depend
+ * on nothing else), and the momentum system then only refreshes its
+ * diagonal (ppe_refresh_shift); the energy system, which keeps every cell,
+ * refreshes its diagonal whenever k is unchanged.  PPE_ERR_ARG on NULL out or
+ * bad values; the errors of ppe_create. */
 ppe_status ppe_flow_create(const ppe_options* opt, double transport_rtol, ppe_flow** out);
 
 /* Destroy a driver and its three solvers.  NULL is accepted. */

@@ -664,12 +664,13 @@ class Flow:
     FP64 to transport_rtol."""
 
     def __init__(self, precision="fp64", rtol=1e-10, transport_rtol=1e-12, stream=None,
-                 use_graph=True, autotune=False, krylov="bicgstab"):
+                 use_graph=True, autotune=False, krylov="bicgstab", reuse_unchanged=True):
         import torch
 
         self._lib = load_library()
         o = ppe_default_options()
         o.project_krylov = {"deferred": 0, "bicgstab": 1}[krylov]
+        o.reuse_unchanged = int(bool(reuse_unchanged))
         o.precision = {"fp64": PPE_FP64, "mixed": PPE_MIXED}[precision]
         o.rtol = rtol
         o.use_graph = int(bool(use_graph))

@@ -24,6 +24,10 @@ struct ppe_flow {
   ppe_solver* ene = nullptr;  // shifted systems of the energy step
   int nc = 0, nf = 0, nn = 0;
   bool have_mesh = false;
+  // the momentum and energy systems' coefficient arrays depend on mu, k and
+  // rho only: while they and the mask stay, a new diagonal is a refresh
+  bool mom_built = false, ene_built = false;
+  double mom_mu = 0.0, ene_k = 0.0, pre_rho = 0.0;
   std::string err;
   // geometry
   ppe::DevBuf vol, cgeo, wgeo, ax, wall_ptr, wall_face, wsum;
@@ -486,6 +490,7 @@ ppe_status ppe_flow_set_mesh(ppe_flow* f, int32_t n_cells, int32_t n_faces, cons
   if (!f) return PPE_ERR_ARG;
   return flow_guarded(f, [&]() -> ppe_status {
     f->have_mesh = false;
+    f->mom_built = f->ene_built = false;
     require(face_centre && cell_volume && (n_faces == 0 || (owner && neigh)), PPE_ERR_ARG,
             "NULL mesh array");
     ppe_status worst = PPE_OK;
@@ -628,7 +633,23 @@ ppe_status ppe_flow_step(ppe_flow* f, const ppe_alloy* al, const ppe_step_params
                        f->vol.as<double>(), xf, nf, flux, u_n, T_n, fs_n, a, dt, conv_u, hist,
                        cu_new, fl, shift, rhs, us);
     PPE_LAUNCH_CHECK();
-    check(f, f->mom, ppe_assemble_shifted(f->mom, cm, fl, shift), "momentum assembly", worst);
+    // the pressure system first: its comparison with the last assembly (when
+    // the pressure solver keeps unchanged systems) tells whether the mask
+    // moved, and the momentum system then only needs its new diagonal
+    const auto t_pre0 = std::chrono::steady_clock::now();
+    const int reused_before = s->stats.reused_setup;
+    check(f, s, ppe_assemble(s, cpr, fl), "pressure assembly", worst);
+    const bool mask_same = s->stats.reused_setup > reused_before && f->pre_rho == a.rho;
+    f->pre_rho = a.rho;
+    const double pre_setup_ms = elapsed(t_pre0);
+    const bool mom_refresh = mask_same && f->mom_built && f->mom_mu == a.mu;
+    f->mom_built = false;  // until the call below succeeds
+    if (mom_refresh)
+      check(f, f->mom, ppe_refresh_shift(f->mom, cm, shift), "momentum refresh", worst);
+    else
+      check(f, f->mom, ppe_assemble_shifted(f->mom, cm, fl, shift), "momentum assembly", worst);
+    f->mom_built = true;
+    f->mom_mu = a.mu;
     for (int q = 0; q < 3; ++q) {
       ppe_stats ps{};
       check(f, f->mom, ppe_solve(f->mom, rhs + (size_t)q * nc, us + (size_t)q * nc, 1, &ps),
@@ -638,18 +659,17 @@ ppe_status ppe_flow_step(ppe_flow* f, const ppe_alloy* al, const ppe_step_params
     double* ustar = f->ustar.get<double>(3 * (size_t)nc);
     hipLaunchKernelGGL(k_interleave3, dim3(gc), dim3(kBlock), 0, f->stream, nc, us, ustar);
     PPE_LAUNCH_CHECK();
-    st.momentum_ms = elapsed(t_mom);
+    st.momentum_ms = elapsed(t_mom) - pre_setup_ms;
 
     // steps 2-3: pressure, fluxes, velocity correction
     const auto t_pre = std::chrono::steady_clock::now();
     double* u_new = f->u_new.get<double>(3 * (size_t)nc);
     double* F_new = f->F_new.get<double>(nf > 0 ? nf : 1);
-    check(f, s, ppe_assemble(s, cpr, fl), "pressure assembly", worst);
     ppe_project_stats pst{};
     check(f, s, ppe_project(s, cpr, ustar, a.rho, dt, p, F_new, u_new, &pst), "projection", worst);
     st.pressure_outer = pst.outer;
     st.pressure_iterations = pst.pcg_iterations;
-    st.pressure_ms = elapsed(t_pre);
+    st.pressure_ms = elapsed(t_pre) + pre_setup_ms;
 
     // step 4: energy with the Picard loop
     const auto t_ene = std::chrono::steady_clock::now();
@@ -675,13 +695,18 @@ ppe_status ppe_flow_step(ppe_flow* f, const ppe_alloy* al, const ppe_step_params
                          f->vol.as<double>(), f->wsum.as<double>(), base, Tm, fm, fs_n, a, dt,
                          shift, erhs, Tnew);
       PPE_LAUNCH_CHECK();
-      // the passes differ only in the latent term's diagonal: the first one
-      // builds the hierarchy, the later ones refresh the finest level
-      if (it == 1)
+      // every cell is kept and the coefficients depend on k only: once the
+      // hierarchy is built, every pass (and every later step) only has a new
+      // diagonal, the latent term's
+      const bool ene_refresh = f->ene_built && f->ene_k == a.k;
+      f->ene_built = false;  // until the call below succeeds
+      if (ene_refresh)
+        check(f, f->ene, ppe_refresh_shift(f->ene, ce, shift), "energy refresh", worst);
+      else
         check(f, f->ene, ppe_assemble_shifted(f->ene, ce, nullptr, shift), "energy assembly",
               worst);
-      else
-        check(f, f->ene, ppe_refresh_shift(f->ene, ce, shift), "energy refresh", worst);
+      f->ene_built = true;
+      f->ene_k = a.k;
       ppe_stats es{};
       check(f, f->ene, ppe_solve(f->ene, erhs, Tnew, 1, &es), "energy solve", worst);
       st.energy_iterations += es.iterations;
