@@ -257,6 +257,14 @@ typedef struct {
 ppe_status ppe_project(ppe_solver* s, const double* face_coeff, const double* ustar, double rho,
                        double dt, double* p, double* flux, double* u, ppe_project_stats* stats);
 
+/* ppe_project from an initial guess: p[n_cells] in is the starting pressure
+ * (e.g. the previous time step's; its values on removed cells and pins are
+ * ignored), out the pressure.  Same arguments, exit test (relative to
+ * ||b'||, not to the starting residual) and errors as ppe_project. */
+ppe_status ppe_project_warm(ppe_solver* s, const double* face_coeff, const double* ustar,
+                            double rho, double dt, double* p, double* flux, double* u,
+                            ppe_project_stats* stats);
+
 /* grad[3 n_faces] = masked face gradient of p[n_cells] (0 on blocked and
  * wall faces) and cross[n_faces] = t_f . grad_f, as ppe_project uses them.
  * Errors: PPE_ERR_STATE before ppe_assemble and ppe_set_geometry. */

@@ -118,7 +118,9 @@ ppe_status ppe_flow_set_mesh(ppe_flow* f, int32_t n_cells, int32_t n_faces, cons
  *   conv_u[3 n_cells], conv_T[n_cells]  convection terms of the previous
  *                     step (read when have_history), replaced by this
  *                     step's C(u^n) and C^T;
- * out: p[n_cells] pressure (0 on removed cells and pins).
+ *   p[n_cells]        in: the previous step's pressure, the projection's
+ *                     starting guess when have_history; out: the pressure
+ *                     (0 on removed cells and pins).
  * stats (host, nullable).  Returns PPE_OK; PPE_NOT_CONVERGED when the
  * Picard loop or an inner solve did not converge (the state then holds the
  * last iterates); PPE_ERR_STATE before ppe_flow_set_mesh; PPE_ERR_ARG on

@@ -154,6 +154,8 @@ _SIGS = {
     "ppe_set_geometry": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P]),
     "ppe_project": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_double, _P, _P, _P,
                                    ctypes.POINTER(ppe_project_stats)]),
+    "ppe_project_warm": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_double, _P, _P,
+                                        _P, ctypes.POINTER(ppe_project_stats)]),
     "ppe_face_gradient": (ctypes.c_int, [_P, _P, ctypes.c_double, _P, _P, _P]),
     "ppe_pce_create": (ctypes.c_int, [_I32, ctypes.POINTER(_I32), _I32, _P, ctypes.POINTER(_P)]),
     "ppe_pce_destroy": (None, [_P]),
@@ -407,17 +409,23 @@ class Solver:
             _dev_ptr(cell_centre, torch.float64, 3 * self.n_cells, "cell_centre"),
             _dev_ptr(face_area, torch.float64, 3 * self.n_faces, "face_area")))
 
-    def project(self, face_coeff, ustar, rho, dt, allow_not_converged=False):
-        """One pressure-correction step; returns (p, flux, u, stats)."""
+    def project(self, face_coeff, ustar, rho, dt, allow_not_converged=False, p0=None):
+        """One pressure-correction step; returns (p, flux, u, stats).  p0: a
+        starting pressure (ppe_project_warm), else zero."""
         import torch
 
         dev = ustar.device
-        p = torch.empty(self.n_cells, dtype=torch.float64, device=dev)
+        if p0 is not None:
+            _dev_ptr(p0, torch.float64, self.n_cells, "p0")  # type, device and size checks
+            p = p0.clone()
+        else:
+            p = torch.empty(self.n_cells, dtype=torch.float64, device=dev)
         flux = torch.empty(max(self.n_faces, 1), dtype=torch.float64, device=dev)
         u = torch.empty((self.n_cells, 3), dtype=torch.float64, device=dev)
         st = ppe_project_stats()
         allow = (PPE_OK, PPE_NOT_CONVERGED) if allow_not_converged else (PPE_OK,)
-        status = self._lib.ppe_project(
+        fn = self._lib.ppe_project if p0 is None else self._lib.ppe_project_warm
+        status = fn(
             self._h, _dev_ptr(face_coeff, torch.float64, self.n_faces, "face_coeff"),
             _dev_ptr(ustar, torch.float64, 3 * self.n_cells, "ustar"), float(rho), float(dt),
             ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(flux.data_ptr()),

@@ -334,8 +334,11 @@ ppe_status ppe_set_geometry(ppe_solver* s, int32_t n_nodes, const double* nodes,
   });
 }
 
-ppe_status ppe_project(ppe_solver* s, const double* face_coeff, const double* ustar, double rho,
-                       double dt, double* p, double* flux, double* u, ppe_project_stats* stats) {
+namespace {
+
+ppe_status project_impl(ppe_solver* s, const double* face_coeff, const double* ustar, double rho,
+                        double dt, double* p, double* flux, double* u, ppe_project_stats* stats,
+                        bool use_x0) {
   if (!s) return PPE_ERR_ARG;
   return guarded(s, [&]() -> ppe_status {
     DeviceGuard g(s->device);
@@ -349,13 +352,26 @@ ppe_status ppe_project(ppe_solver* s, const double* face_coeff, const double* us
                  "rho and dt must be finite and > 0");
     PPE_HIP(hipEventRecord(s->ev0, s->stream));
     ppe_project_stats st{};
-    const ppe_status r = ppe::project(s, face_coeff, ustar, rho, dt, p, flux, u, &st);
+    const ppe_status r = ppe::project(s, face_coeff, ustar, rho, dt, p, flux, u, &st, use_x0);
     PPE_HIP(hipEventRecord(s->ev1, s->stream));
     PPE_HIP(hipEventSynchronize(s->ev1));
     st.ms = elapsed_ms(s->ev0, s->ev1);
     if (stats) *stats = st;
     return r;
   });
+}
+
+}  // namespace
+
+ppe_status ppe_project(ppe_solver* s, const double* face_coeff, const double* ustar, double rho,
+                       double dt, double* p, double* flux, double* u, ppe_project_stats* stats) {
+  return project_impl(s, face_coeff, ustar, rho, dt, p, flux, u, stats, false);
+}
+
+ppe_status ppe_project_warm(ppe_solver* s, const double* face_coeff, const double* ustar,
+                            double rho, double dt, double* p, double* flux, double* u,
+                            ppe_project_stats* stats) {
+  return project_impl(s, face_coeff, ustar, rho, dt, p, flux, u, stats, true);
 }
 
 ppe_status ppe_face_gradient(ppe_solver* s, const double* face_coeff, double rho, const double* p,

@@ -479,7 +479,7 @@ void cross_vectors(ppe_solver* s, const double* coeff, double rho, double* t);
 // p[n_cells]; grad[3 n_faces] receives the gradients unless NULL
 void face_gradient(ppe_solver* s, const double* p, const double* t, double* grad, double* xf);
 ppe_status project(ppe_solver* s, const double* coeff, const double* ustar, double rho, double dt,
-                   double* p, double* flux, double* u, ppe_project_stats* out);
+                   double* p, double* flux, double* u, ppe_project_stats* out, bool use_x0);
 void profile_harvest(ppe_solver* s);
 void drop_graph(ppe_solver* s);
 void profile_enable(ppe_solver* s, bool on);

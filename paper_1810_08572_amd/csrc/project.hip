@@ -525,6 +525,24 @@ __global__ void __launch_bounds__(kBlock) k_sum_partials(const double* __restric
   if (threadIdx.x == 0) *out = s;
 }
 
+// warm start: p = 0 on removed cells and pins (kept elsewhere); block
+// partials of b.b over the non-pinned active cells
+__global__ void __launch_bounds__(kBlock) k_clean_start(int n, const int* __restrict__ active,
+                                                        const int* __restrict__ comp,
+                                                        const double* __restrict__ b,
+                                                        double* __restrict__ p,
+                                                        double* __restrict__ part) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  double v = 0.0;
+  if (c < n) {
+    const bool free = active[c] && comp[c] != c;
+    if (!free) p[c] = 0.0;
+    v = free ? b[c] * b[c] : 0.0;
+  }
+  v = block_sum<kBlock>(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
 __global__ void k_add_cells(int n, const double* __restrict__ d, double* __restrict__ p) {
   const int c = blockIdx.x * kBlock + threadIdx.x;
   if (c < n) p[c] += d[c];
@@ -892,7 +910,7 @@ void cross_flux(ppe_solver* s, const CrossData& cd, const double* p, double* xf)
 }  // namespace
 
 ppe_status project(ppe_solver* s, const double* coeff, const double* ustar, double rho, double dt,
-                   double* p, double* flux, double* u, ppe_project_stats* out) {
+                   double* p, double* flux, double* u, ppe_project_stats* out, bool use_x0) {
   const int nc = s->n_cells, nf = s->n_faces;
   ppe_project_stats st{};
   const int* owner = s->owner.as<int>();
@@ -908,8 +926,8 @@ ppe_status project(ppe_solver* s, const double* coeff, const double* ustar, doub
   double* grad = s->pj_grad.get<double>(3 * (size_t)(nf > 0 ? nf : 1));
   double* xf = s->pj_xf.get<double>(nf > 0 ? nf : 1);
   const int gc = grid_for(nc);
-  double* part = s->pj_part.get<double>(gc + 2);
-  double* sums = part + gc;  // [0] b.b, [1] r.r
+  double* part = s->pj_part.get<double>(gc + 3);
+  double* sums = part + gc;  // [0] r.r at the start, [1] r.r, [2] b.b (warm start)
   if (nf) {
     hipLaunchKernelGGL(k_star_flux, dim3(grid_for(nf)), dim3(kBlock), 0, s->stream, nf, owner,
                        neigh, active, ustar, s->g_S.as<double>(), Fs);
@@ -921,9 +939,23 @@ ppe_status project(ppe_solver* s, const double* coeff, const double* ustar, doub
   double* t = s->pj_t.get<double>(3 * (size_t)(nf > 0 ? nf : 1));
   cross_vectors(s, coeff, rho, t);
   const CrossData cd = prepare_cross(s, t);
-  fill_double(s, p, 0.0, nc);
-  // r = b + X p - L p at p = 0 is b on the non-pinned active cells: its norm
-  // is the reference ||b'||
+  double bn_warm = 0.0;
+  if (use_x0) {
+    // the given pressure, zero on removed cells and pins, and the reference
+    // ||b'|| of the pinned right-hand side
+    hipLaunchKernelGGL(k_clean_start, dim3(gc), dim3(kBlock), 0, s->stream, nc, active,
+                       s->comp_full.as<int>(), b, p, part);
+    PPE_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s->stream, part, gc, sums + 2);
+    PPE_LAUNCH_CHECK();
+    read_back(s, {ReadItem{sums + 2, sizeof(double), &bn_warm}});
+    bn_warm = std::sqrt(bn_warm);
+    if (!(bn_warm > 0.0)) fill_double(s, p, 0.0, nc);  // b' = 0: p = 0 solves it
+  } else {
+    fill_double(s, p, 0.0, nc);
+  }
+  // r = b + X p - L p; at p = 0 it is b on the non-pinned active cells, whose
+  // norm is the reference ||b'||
   auto residual = [&](int slot) {
     cross_flux(s, cd, p, xf);
     hipLaunchKernelGGL(k_full_residual, dim3(gc), dim3(kBlock), 0, s->stream, nc, aptr, anbr, aface,
@@ -935,8 +967,8 @@ ppe_status project(ppe_solver* s, const double* coeff, const double* ustar, doub
     read_back(s, {ReadItem{sums + slot, sizeof(double), &v}});
     return std::sqrt(v);
   };
-  const double bn = residual(0);
-  double rn = bn;
+  double rn = residual(0);
+  const double bn = use_x0 ? bn_warm : rn;
   // one decade below rtol: loose inner solves leave the last residual in
   // smooth modes, which the condition number amplifies in the pressure; the
   // margin keeps p near the exact solution of the full system at the price

@@ -666,7 +666,14 @@ ppe_status ppe_flow_step(ppe_flow* f, const ppe_alloy* al, const ppe_step_params
     double* u_new = f->u_new.get<double>(3 * (size_t)nc);
     double* F_new = f->F_new.get<double>(nf > 0 ? nf : 1);
     ppe_project_stats pst{};
-    check(f, s, ppe_project(s, cpr, ustar, a.rho, dt, p, F_new, u_new, &pst), "projection", worst);
+    // the previous step's pressure starts the projection (the exit test is
+    // relative to ||b'||, so the bar is the same)
+    if (hist)
+      check(f, s, ppe_project_warm(s, cpr, ustar, a.rho, dt, p, F_new, u_new, &pst), "projection",
+            worst);
+    else
+      check(f, s, ppe_project(s, cpr, ustar, a.rho, dt, p, F_new, u_new, &pst), "projection",
+            worst);
     st.pressure_outer = pst.outer;
     st.pressure_iterations = pst.pcg_iterations;
     st.pressure_ms = elapsed(t_pre) + pre_setup_ms;
