@@ -259,3 +259,63 @@ def test_refresh_shift_solves_the_new_system():
     with pytest.raises(ppe.PpeError) as e:
         s.refresh_shift(to_dev(c, torch.float64), to_dev(s2, torch.float64))
     assert e.value.status == ppe.PPE_ERR_STATE
+
+
+def test_flow_edge_cases_and_errors():
+    """All cells solid: nothing moves, p = 0, fluxes 0, the energy step still
+    conducts (walls at 500 K cool the block).  A uniform melt at T_ref at
+    rest with insulated walls is a fixed point.  Argument and state errors
+    are reported without touching the state."""
+    import torch
+
+    import paper_1810_08572_amd as ppe
+
+    m = box_mesh((6, 5, 4), lengths=(6e-3, 5e-3, 4e-3), jitter=0.1, seed=2)
+    props = al_si_alloy()
+    a = flow.Props.of(props)
+    fw = ppe.Flow()
+    # a step before the mesh
+    gs = ppe.FlowState(*(to_dev(np.zeros(sh), torch.float64) for sh in
+                         ((m.n_cells, 3), m.n_cells, m.n_cells, m.n_faces, m.n_cells,
+                          (m.n_cells, 3), m.n_cells)))
+    fw.n_cells, fw.n_faces = m.n_cells, m.n_faces
+    with pytest.raises(ppe.PpeError) as e:
+        fw.step(props, gs, 1e-3)
+    assert e.value.status == ppe.PPE_ERR_STATE
+    fw = _flow(m)
+    # all solid
+    T0 = np.full(m.n_cells, 700.0)
+    gs = fw.new_state(to_dev(T0, torch.float64), props=props)
+    assert float(gs.fs.min()) == 1.0
+    geo = flow.Geometry(m)
+    st = flow.initial_state(m, a, T0=T0)
+    for _ in range(2):
+        status, stats = fw.step(props, gs, 1e-3)
+        st, info = flow.step(geo, a, st, 1e-3)
+        assert stats["n_fluid"] == 0 and stats["n_solid"] == m.n_cells
+        assert float(gs.u.abs().max()) == 0 and float(gs.p.abs().max()) == 0
+        assert float(gs.flux.abs().max()) == 0
+        T = gs.T.cpu().numpy()
+        assert np.abs(T - st.T).max() <= 1e-9 * np.abs(st.T).max()
+    assert T.max() < 700.0
+    # a uniform melt at T_ref, at rest, insulated: nothing changes
+    ins = al_si_alloy(T_wall=None)
+    gs = fw.new_state(to_dev(np.full(m.n_cells, ins["T_ref"]), torch.float64), props=ins)
+    status, stats = fw.step(ins, gs, 1e-3)
+    assert float(gs.u.abs().max()) == 0 and float(gs.flux.abs().max()) == 0
+    assert np.all(gs.T.cpu().numpy() == ins["T_ref"]) and float(gs.fs.abs().max()) == 0
+    assert stats["picard"] == 1
+    # bad arguments leave the state alone
+    before = gs.T.clone()
+    for bad in (dict(mu=0.0), dict(k=-1.0), dict(k_p=1.0), dict(T_eps=0.0)):
+        with pytest.raises(ppe.PpeError) as e:
+            fw.step(dict(ins, **bad), gs, 1e-3)
+        assert e.value.status == ppe.PPE_ERR_ARG
+    for kw in (dict(relax=0.0), dict(relax=1.5), dict(max_picard=0)):
+        with pytest.raises(ppe.PpeError) as e:
+            fw.step(ins, gs, 1e-3, **kw)
+        assert e.value.status == ppe.PPE_ERR_ARG
+    with pytest.raises(ppe.PpeError) as e:
+        fw.step(ins, gs, 0.0)
+    assert e.value.status == ppe.PPE_ERR_ARG
+    assert torch.equal(gs.T, before)
