@@ -367,10 +367,11 @@ __global__ void __launch_bounds__(kBlock) k_count_fluid(int nc, const double* __
   if (threadIdx.x == 0 && fluid) atomicAdd(n, fluid);
 }
 
-void check(ppe_flow* fl, ppe_solver* s, ppe_status st, const char* what, ppe_status& worst) {
+// An inner call's status: failures throw with the inner solver's detail;
+// PPE_NOT_CONVERGED is remembered for the step's own status.
+void check(ppe_solver* s, ppe_status st, const char* what, ppe_status& worst) {
   if (st < 0) throw Error(st, std::string(what) + ": " + s->err);
   if (st == PPE_NOT_CONVERGED) worst = PPE_NOT_CONVERGED;
-  (void)fl;
 }
 
 Alloy make_alloy(const ppe_alloy* al) {
@@ -494,10 +495,10 @@ ppe_status ppe_flow_set_mesh(ppe_flow* f, int32_t n_cells, int32_t n_faces, cons
     require(face_centre && cell_volume && (n_faces == 0 || (owner && neigh)), PPE_ERR_ARG,
             "NULL mesh array");
     ppe_status worst = PPE_OK;
-    check(f, f->pre, ppe_set_mesh(f->pre, n_cells, n_faces, owner, neigh), "pressure mesh", worst);
-    check(f, f->mom, ppe_set_mesh(f->mom, n_cells, n_faces, owner, neigh), "momentum mesh", worst);
-    check(f, f->ene, ppe_set_mesh(f->ene, n_cells, n_faces, owner, neigh), "energy mesh", worst);
-    check(f, f->pre,
+    check(f->pre, ppe_set_mesh(f->pre, n_cells, n_faces, owner, neigh), "pressure mesh", worst);
+    check(f->mom, ppe_set_mesh(f->mom, n_cells, n_faces, owner, neigh), "momentum mesh", worst);
+    check(f->ene, ppe_set_mesh(f->ene, n_cells, n_faces, owner, neigh), "energy mesh", worst);
+    check(f->pre,
           ppe_set_geometry(f->pre, n_nodes, nodes, face_nodes, cell_nodes, cell_centre, face_area),
           "geometry", worst);
     ppe_solver* s = f->pre;
@@ -638,21 +639,21 @@ ppe_status ppe_flow_step(ppe_flow* f, const ppe_alloy* al, const ppe_step_params
     // moved, and the momentum system then only needs its new diagonal
     const auto t_pre0 = std::chrono::steady_clock::now();
     const int reused_before = s->stats.reused_setup;
-    check(f, s, ppe_assemble(s, cpr, fl), "pressure assembly", worst);
+    check(s, ppe_assemble(s, cpr, fl), "pressure assembly", worst);
     const bool mask_same = s->stats.reused_setup > reused_before && f->pre_rho == a.rho;
     f->pre_rho = a.rho;
     const double pre_setup_ms = elapsed(t_pre0);
     const bool mom_refresh = mask_same && f->mom_built && f->mom_mu == a.mu;
     f->mom_built = false;  // until the call below succeeds
     if (mom_refresh)
-      check(f, f->mom, ppe_refresh_shift(f->mom, cm, shift), "momentum refresh", worst);
+      check(f->mom, ppe_refresh_shift(f->mom, cm, shift), "momentum refresh", worst);
     else
-      check(f, f->mom, ppe_assemble_shifted(f->mom, cm, fl, shift), "momentum assembly", worst);
+      check(f->mom, ppe_assemble_shifted(f->mom, cm, fl, shift), "momentum assembly", worst);
     f->mom_built = true;
     f->mom_mu = a.mu;
     for (int q = 0; q < 3; ++q) {
       ppe_stats ps{};
-      check(f, f->mom, ppe_solve(f->mom, rhs + (size_t)q * nc, us + (size_t)q * nc, 1, &ps),
+      check(f->mom, ppe_solve(f->mom, rhs + (size_t)q * nc, us + (size_t)q * nc, 1, &ps),
             "momentum solve", worst);
       st.momentum_iterations += ps.iterations;
     }
@@ -669,10 +670,10 @@ ppe_status ppe_flow_step(ppe_flow* f, const ppe_alloy* al, const ppe_step_params
     // the previous step's pressure starts the projection (the exit test is
     // relative to ||b'||, so the bar is the same)
     if (hist)
-      check(f, s, ppe_project_warm(s, cpr, ustar, a.rho, dt, p, F_new, u_new, &pst), "projection",
+      check(s, ppe_project_warm(s, cpr, ustar, a.rho, dt, p, F_new, u_new, &pst), "projection",
             worst);
     else
-      check(f, s, ppe_project(s, cpr, ustar, a.rho, dt, p, F_new, u_new, &pst), "projection",
+      check(s, ppe_project(s, cpr, ustar, a.rho, dt, p, F_new, u_new, &pst), "projection",
             worst);
     st.pressure_outer = pst.outer;
     st.pressure_iterations = pst.pcg_iterations;
@@ -708,14 +709,14 @@ ppe_status ppe_flow_step(ppe_flow* f, const ppe_alloy* al, const ppe_step_params
       const bool ene_refresh = f->ene_built && f->ene_k == a.k;
       f->ene_built = false;  // until the call below succeeds
       if (ene_refresh)
-        check(f, f->ene, ppe_refresh_shift(f->ene, ce, shift), "energy refresh", worst);
+        check(f->ene, ppe_refresh_shift(f->ene, ce, shift), "energy refresh", worst);
       else
-        check(f, f->ene, ppe_assemble_shifted(f->ene, ce, nullptr, shift), "energy assembly",
+        check(f->ene, ppe_assemble_shifted(f->ene, ce, nullptr, shift), "energy assembly",
               worst);
       f->ene_built = true;
       f->ene_k = a.k;
       ppe_stats es{};
-      check(f, f->ene, ppe_solve(f->ene, erhs, Tnew, 1, &es), "energy solve", worst);
+      check(f->ene, ppe_solve(f->ene, erhs, Tnew, 1, &es), "energy solve", worst);
       st.energy_iterations += es.iterations;
       hipLaunchKernelGGL(k_picard, dim3(gp), dim3(kBlock), 0, f->stream, nc, Tnew, Tm, fm, a,
                          prm->relax, part);

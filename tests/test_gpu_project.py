@@ -184,7 +184,8 @@ def test_projection_degenerate_masks(krylov):
     assert np.array_equal(u[act], us[act]) and np.all(u[~act] == 0)
 
 
-def test_warm_started_projection():
+@pytest.mark.parametrize("krylov", KRYLOV)
+def test_warm_started_projection(krylov):
     """ppe_project_warm: from the exact solution no pass is needed; from a
     perturbed one (with junk on removed cells and pins, which is ignored) it
     meets the same bars as a cold start, in fewer iterations."""
@@ -195,7 +196,7 @@ def test_warm_started_projection():
     c = face_coeff(m, RHO)
     us = ustar_smooth_series(m.cell_centre, 0.05, seed=11)
     ref = pj.project(m, c, f, us, RHO, DT)
-    s = _solver(m, c, f)
+    s = _solver(m, c, f, krylov=krylov)
     cold = s.project(to_dev(c, torch.float64), to_dev(us, torch.float64), RHO, DT)[3]
     p, F, u, st = s.project(to_dev(c, torch.float64), to_dev(us, torch.float64), RHO, DT,
                             p0=to_dev(ref.p, torch.float64))
@@ -211,5 +212,30 @@ def test_warm_started_projection():
     assert np.all(p[~sy.active] == 0) and np.all(p[sy.pins] == 0)
     assert st["rel_residual"] <= 1e-10
     assert np.linalg.norm(p - ref.p) <= 1e-9 * np.linalg.norm(ref.p)
-    print(f"warm: {st['outer']} iterations, cold: {cold['outer']}")
+    print(f"warm ({krylov}): {st['outer']} iterations, cold: {cold['outer']}")
     assert st["outer"] < cold["outer"]
+
+
+@pytest.mark.parametrize("krylov", KRYLOV)
+def test_projection_mixed_precision(krylov):
+    """FP32 hierarchy under either outer iteration: the outer iteration and
+    the exit test stay FP64, so the full-system residual bar holds; the
+    pressure error is held to the mixed-precision solves' 1e-8."""
+    import torch
+
+    m = box_mesh((14, 12, 10), jitter=0.1, seed=3)
+    f = fl_planar_front(m.cell_centre, seed=2)
+    c = face_coeff(m, RHO)
+    us = ustar_smooth_series(m.cell_centre, 0.05, seed=11)
+    ref = pj.project(m, c, f, us, RHO, DT)
+    s = _solver(m, c, f, precision="mixed", krylov=krylov)
+    p, F, u, st = s.project(to_dev(c, torch.float64), to_dev(us, torch.float64), RHO, DT)
+    p = p.cpu().numpy()
+    sy = ref.system
+    bp = ref.b[sy.perm].copy()
+    bp[sy.pinned] = 0.0
+    rr = np.linalg.norm(bp - ref.full @ p[sy.perm]) / np.linalg.norm(bp)
+    err = np.linalg.norm(p - ref.p) / np.linalg.norm(ref.p)
+    print(f"mixed {krylov}: outer {st['outer']}, residual {rr:.2e}, L2 error {err:.2e}")
+    assert st["rel_residual"] <= 1e-10 and rr <= 1.5e-10
+    assert err <= 1e-8
