@@ -230,8 +230,11 @@ ppe_status ppe_set_geometry(ppe_solver* s, int32_t n_nodes, const double* nodes,
                             const double* cell_centre, const double* face_area);
 
 typedef struct {
-  int outer;             /* deferred-correction passes (one AMG-PCG solve each) */
-  int pcg_iterations;    /* PCG iterations summed over the passes */
+  int outer;             /* deferred correction: passes (one AMG-PCG solve
+                            each); BiCGSTAB: iterations */
+  int pcg_iterations;    /* deferred correction: PCG iterations summed over
+                            the passes; BiCGSTAB: V-cycles applied (two per
+                            iteration) */
   double rel_residual;   /* ||b' + X p - L p|| / ||b'|| at exit, FP64 */
   double ms;             /* wall time of the call */
 } ppe_project_stats;

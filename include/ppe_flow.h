@@ -73,8 +73,8 @@ typedef struct {
 typedef struct {
   int picard;               /* Picard passes of the energy step */
   int momentum_iterations;  /* PCG iterations summed over the three components */
-  int pressure_outer;       /* deferred-correction passes of the projection */
-  int pressure_iterations;  /* PCG iterations summed over those passes */
+  int pressure_outer;       /* the projection's outer count (ppe_project_stats.outer) */
+  int pressure_iterations;  /* its inner count (ppe_project_stats.pcg_iterations) */
   int energy_iterations;    /* PCG iterations summed over the Picard passes */
   int n_fluid;              /* cells with f_s < 1 at the start of the step */
   int n_solid;              /* cells with f_s = 1 at the end of the step */
