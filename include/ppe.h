@@ -315,11 +315,13 @@ ppe_status ppe_apply_vcycle(ppe_solver* s, const double* r, double* z);
 
 /* Launch choices of level l's solve kernels, choice[4] (host): lanes per row
  * of the coarse smoother, of the restriction and of the prolongation (0 = the
- * fixed rule, else 4, 8, 16, 32 or 64), and 1 if the first two smoothing
- * steps from a zero guess run fused, 0 if split.  The autotuner sets them at
- * assembly; setting them by hand (until the next assembly) lets a test run
- * every variant.  They never affect the hierarchy, only the solve's order of
- * summation.  PPE_ERR_ARG for a value outside those sets. */
+ * fixed rule, else 4, 8, 16, 32 or 64; on the coarse levels of the FP64
+ * V-cycle the prolongation runs in one pass with the first post-smoothing
+ * step, reading the Galerkin product's A P), and 1 if the first two
+ * smoothing steps from a zero guess run fused, 0 if split.  The autotuner
+ * sets them at assembly; setting them by hand (until the next assembly) lets
+ * a test run every variant.  They never affect the hierarchy, only the
+ * solve's order of summation.  PPE_ERR_ARG for a value outside those sets. */
 ppe_status ppe_get_level_launch(const ppe_solver* s, int level, int32_t* choice);
 ppe_status ppe_set_level_launch(ppe_solver* s, int level, const int32_t* choice);
 

@@ -1091,6 +1091,7 @@ void build_hierarchy(ppe_solver* s) {
     // iteration's sums, and with it the spectral bound
     L.lpr_a = L.lpr_r = L.lpr_p = 0;
     L.fuse0 = true;
+    L.ap_ok = false;
     if (lvl > 0 && n > 0) {
       PPE_ROWS(lanes_for(L.A), k_diag, n, n, L.A.rp(), L.A.ci(), L.A.v(), L.diag.get<double>(n),
                err);  // sets SE_DIAG
@@ -1226,6 +1227,7 @@ void build_hierarchy(ppe_solver* s) {
         std::swap(P.col, L0.Q.col);
         transpose(s, P, L0.R);
         spgemm(s, L0.A, P, L0.AP, s->rmax.as<int>(), &L0.R.maxrow);
+        L0.ap_ok = true;
         spgemm(s, L0.R, L0.AP, C.A, nullptr, nullptr);
         C.n = na;
         s->nlev = lvl + 2;

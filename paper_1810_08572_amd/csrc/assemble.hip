@@ -555,6 +555,7 @@ void assemble_fine(ppe_solver* s, const double* coeff, const double* fl, const d
 
 void refresh_fine_shift(ppe_solver* s, const double* coeff, const double* shift) {
   Level& L = s->levels[0];
+  L.ap_ok = false;  // the kept A P no longer matches the new diagonal
   const int na = s->n_active;
   if (na == 0) return;
   int* flag = s->flag.get<int>(1);

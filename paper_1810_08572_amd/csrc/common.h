@@ -111,7 +111,10 @@ struct Level {
   std::vector<double> c1, c2;  // Chebyshev steps 2..degree
   int mis_rounds = 0;
   int mis_batch = 6;     // MIS-2 rounds before the first check (last assembly's count)
-  Csr Pt, Q, AP;         // setup scratch: tentative P, A*P_tent, A*P
+  Csr Pt, Q;             // setup scratch: tentative P, A*P_tent
+  Csr AP;                // A*P: built for the Galerkin product, then read by
+                         // the prolongation fused with post-smoothing
+  bool ap_ok = false;    // AP equals A*P for the level's current A
   DevBuf strong, state, state2, m1, mis_root, agg1, agg_ptr, agg_mem, pt;
   // coarsest level
   bool dense = false;

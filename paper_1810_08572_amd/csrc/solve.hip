@@ -181,6 +181,101 @@ __global__ void __launch_bounds__(kBlock) k_csr_rect(int n, const int* __restric
   if (g < n && lane == 0) y[g] = ADD ? y[g] + s : s;
 }
 
+// ---- prolongation fused with the first post-smoothing step
+// After the coarse correction e the V-cycle forms x = x1 + P e and takes a
+// Chebyshev step from it (c1 = 0: r = (b - A x)/diag, d = c2 r, y = x + d).
+// Row i needs x at its neighbours, so one pass uses the product AP = A P
+// kept from the Galerkin product: (A x)_i = (A x1)_i + (AP e)_i, exact up to
+// the order of the sums.  That saves the separate prolongation pass and its
+// write and re-read of x.
+constexpr int kFuseU = 4;  // CSR entries per lane requested before any is used
+
+// Entries k0 + lane + u LPR (u < U) of a CSR row ending at k1: columns (-1
+// past the end) and values.
+template <int LPR, int U, class T>
+__device__ __forceinline__ void chunk_load(int k0, int k1, int lane, const int* __restrict__ ci,
+                                           const T* __restrict__ v, int (&c)[U], T (&w)[U]) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = k0 + lane + u * LPR;
+    c[u] = k < k1 ? ci[k] : -1;
+    w[u] = k < k1 ? v[k] : T(0);
+  }
+}
+
+// s + sum of w[u] x[c[u]] over the loaded entries, every gather requested
+// before the first product.
+template <int U, class T>
+__device__ __forceinline__ T chunk_sum(T s, const int (&c)[U], const T (&w)[U],
+                                       const T* __restrict__ x) {
+  T g[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) g[u] = c[u] >= 0 ? x[c[u]] : T(0);
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (c[u] >= 0) s = s + w[u] * g[u];
+  return s;
+}
+
+// The lane's entries of a row past its first chunk (rows longer than LPR U).
+template <int LPR, int U, class T>
+__device__ __forceinline__ T row_rest(T s, int k0, int k1, int lane, const int* __restrict__ ci,
+                                      const T* __restrict__ v, const T* __restrict__ x) {
+  for (int k = k0 + lane + LPR * U; k < k1; k += LPR) s = s + v[k] * x[ci[k]];
+  return s;
+}
+
+// Sums of the LPR lanes of a row group, left in lane 0.
+template <int LPR, class T>
+__device__ __forceinline__ void group_sum2(T& a, T& b) {
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) {
+    a += __shfl_down(a, o, LPR);
+    b += __shfl_down(b, o, LPR);
+  }
+}
+
+// A, P and AP all CSR (A's rows hold the diagonal); LPR lanes per row.
+template <class T, int LPR>
+__global__ void __launch_bounds__(kBlock) k_csr_prolong_cheb(
+    int n, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ v,
+    const T* __restrict__ diag, const int* __restrict__ prp, const int* __restrict__ pci,
+    const T* __restrict__ pv, const int* __restrict__ arp, const int* __restrict__ aci,
+    const T* __restrict__ av, const T* __restrict__ e, const T* __restrict__ x1,
+    const T* __restrict__ b, T* __restrict__ d, T c2, T* __restrict__ y) {
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / LPR;
+  const int lane = threadIdx.x % LPR;
+  T ax = T(0), pe = T(0), bi = T(0), di = T(1), xi = T(0);
+  if (i < n) {
+    if (lane == 0) {
+      bi = b[i];
+      di = diag[i];
+      xi = x1[i];
+    }
+    const int r0 = rp[i], r1 = rp[i + 1], p0 = prp[i], p1 = prp[i + 1], a0 = arp[i],
+              a1 = arp[i + 1];
+    int cc[kFuseU], pc[kFuseU], ac[kFuseU];
+    T cw[kFuseU], pw[kFuseU], aw[kFuseU];
+    chunk_load<LPR, kFuseU, T>(r0, r1, lane, ci, v, cc, cw);
+    chunk_load<LPR, kFuseU, T>(p0, p1, lane, pci, pv, pc, pw);
+    chunk_load<LPR, kFuseU, T>(a0, a1, lane, aci, av, ac, aw);
+    ax = chunk_sum<kFuseU, T>(ax, cc, cw, x1);
+    ax = chunk_sum<kFuseU, T>(ax, ac, aw, e);
+    pe = chunk_sum<kFuseU, T>(pe, pc, pw, e);
+    ax = row_rest<LPR, kFuseU, T>(ax, r0, r1, lane, ci, v, x1);
+    ax = row_rest<LPR, kFuseU, T>(ax, a0, a1, lane, aci, av, e);
+    pe = row_rest<LPR, kFuseU, T>(pe, p0, p1, lane, pci, pv, e);
+  }
+  group_sum2<LPR, T>(ax, pe);
+  if (i < n && lane == 0) {
+    const T r = (bi - ax) / di;
+    const T dn = c2 * r;
+    d[i] = dn;
+    y[i] = (xi + pe) + dn;
+  }
+}
+// ---- end of the fused prolongation
+
 // First Chebyshev step from a zero guess: d = b / (theta diag); x = d.
 template <class T>
 __global__ void k_cheb_first(int n, const T* __restrict__ b, const T* __restrict__ diag,
@@ -659,6 +754,56 @@ void apply_rect(ppe_solver* s, const Csr& M, const T* x, T* y, int lpr_choice = 
   PPE_LAUNCH_CHECK();
 }
 
+// Whether level L's prolongation runs fused with its first post-smoothing
+// step in value type T: on the coarse levels of the FP64 V-cycle, while AP
+// still equals A P, when the smoother takes at least two steps.
+//  - The finest level keeps its separate passes: there the fused pass, with
+//    CSR rows of P and AP gathered beside the ELL rows of A, took as long as
+//    the prolongation and the ELL step together, while on the coarse levels
+//    it saves a dispatch each.
+//  - The FP32 V-cycle keeps them too: A x1 and (AP) e are each of the size
+//    of the right-hand side, so forming their sum in FP32 leaves a rounding
+//    error of that size in a residual the coarse correction has made much
+//    smaller.
+template <class T>
+bool prolong_fusable(const ppe_solver* s, const Level& L) {
+  return std::is_same<T, double>::value && &L != &s->levels[0] && L.ap_ok && !L.c1.empty();
+}
+
+// Lanes per row of the fused pass: the launch choice if set, else the fewest
+// whose first chunks cover the longest row of A, P and AP.
+int prolong_lanes(const Level& L) {
+  if (L.lpr_p > 0) return L.lpr_p;
+  const int need = std::max(std::max(L.P.maxrow, L.AP.maxrow), L.A.maxrow);
+  int lpr = 4;
+  while (lpr < 64 && lpr * kFuseU < need) lpr *= 2;
+  return lpr;
+}
+
+// y = (x1 + P e) + d with d = c2 D^-1 (b - A (x1 + P e)): the prolongation
+// and the first post-smoothing step in one pass (prolong_fusable must hold).
+template <class T>
+void prolong_cheb(ppe_solver* s, Level& L, const T* e, const T* x1, const T* b, T* d, T* y) {
+  const int n = L.n;
+  const int lpr = prolong_lanes(L);
+  const int g = grid_for((int64_t)n * lpr);
+  const T c2 = (T)L.inv_theta;
+#define PPE_PC_CSR(LL)                                                                         \
+  hipLaunchKernelGGL((k_csr_prolong_cheb<T, LL>), dim3(g), dim3(kBlock), 0, s->stream, n,       \
+                     L.A.rp(), L.A.ci(), LevelData<T>::val(L.A), LevelData<T>::diag(L), L.P.rp(), \
+                     L.P.ci(), LevelData<T>::val(L.P), L.AP.rp(), L.AP.ci(),                    \
+                     LevelData<T>::val(L.AP), e, x1, b, d, c2, y)
+  switch (lpr) {
+    case 4: PPE_PC_CSR(4); break;
+    case 8: PPE_PC_CSR(8); break;
+    case 16: PPE_PC_CSR(16); break;
+    case 32: PPE_PC_CSR(32); break;
+    default: PPE_PC_CSR(64); break;
+  }
+#undef PPE_PC_CSR
+  PPE_LAUNCH_CHECK();
+}
+
 // PCG dots fused into the last level-0 step of the V-cycle: tile partials of
 // r.z and (flexible) z.q into part (2 x n_tiles).
 struct PcgDot {
@@ -673,6 +818,10 @@ struct PcgDot {
 // xa/xb are ping-pong buffers distinct from x_in and x_out.  With dot (FP64,
 // level 0 only) the last step also produces the PCG dots; returns whether it
 // did.
+template <class T>
+bool smooth_steps(ppe_solver* s, Level& L, const T* b, const T* cur, int step, T* x_out, T* xa,
+                  T* xb, const PcgDot* dot);
+
 template <class T>
 bool smooth(ppe_solver* s, Level& L, const T* b, const T* x_in, T* x_out, T* xa, T* xb,
             const PcgDot* dot = nullptr) {
@@ -698,6 +847,18 @@ bool smooth(ppe_solver* s, Level& L, const T* b, const T* x_in, T* x_out, T* xa,
       step = 2;
     }
   }
+  return smooth_steps<T>(s, L, b, cur, step, x_out, xa, xb, dot);
+}
+
+// Chebyshev steps step..degree from the iterate cur (with the level's d
+// holding the previous step's update when step > 1); the rest as smooth.
+template <class T>
+bool smooth_steps(ppe_solver* s, Level& L, const T* b, const T* cur, int step, T* x_out, T* xa,
+                  T* xb, const PcgDot* dot) {
+  const int n = L.n;
+  const int deg = 1 + (int)L.c1.size();
+  T* d = L.d.as<T>();
+  auto dst_of = [&](int k) { return k == deg ? x_out : ((k % 2) ? xa : xb); };
   bool dotted = false;
   for (; step <= deg; ++step) {
     T* dst = dst_of(step);
@@ -750,6 +911,13 @@ bool vcycle_t(ppe_solver* s, int l, const T* b, T* x, const PcgDot* dot = nullpt
   apply_op<E_RESID, T>(s, L, x1, b, nullptr, 0.0, 0.0, r, nullptr);
   apply_rect<false, T>(s, L.R, r, C.b.as<T>(), L.lpr_r);
   vcycle_t<T>(s, l + 1, C.b.as<T>(), C.x.as<T>());
+  if constexpr (std::is_same<T, double>::value) {
+    if (prolong_fusable<T>(s, L)) {
+      // the first post-smoothing step writes xa (it is not the last step)
+      prolong_cheb<T>(s, L, C.x.as<T>(), x1, b, L.d.as<T>(), xa);
+      return smooth_steps<T>(s, L, b, xa, 2, x, xa, xb, dot);
+    }
+  }
   apply_rect<true, T>(s, L.P, C.x.as<T>(), x1, L.lpr_p);
   return smooth<T>(s, L, b, x1, x, xa, xb, dot);
 }
@@ -1182,11 +1350,10 @@ float time_launches(ppe_solver* s, F&& launch, int reps = 3) {
 
 constexpr int kLprs[] = {4, 8, 16, 32, 64};
 
-// The fastest lanes-per-row choice for a CSR operator of mean row length
-// mean (candidates from a quarter of the rule's choice up to 64).
+// The fastest lanes-per-row choice, candidates from a quarter of the fixed
+// rule's choice up to 64.
 template <class F>
-int best_lpr(ppe_solver* s, const Csr& M, F&& run) {
-  const int rule = lanes_for(M);
+int best_lpr(ppe_solver* s, int rule, F&& run) {
   int best = rule;
   float tbest = 1e30f;
   for (int c : kLprs) {
@@ -1210,7 +1377,7 @@ void tune_level(ppe_solver* s, int l) {
   T* y = L.x2.as<T>();
   const double c1 = L.c1.empty() ? 0.0 : L.c1[0], c2 = L.c1.empty() ? L.inv_theta : L.c2[0];
   if (l > 0)
-    L.lpr_a = best_lpr(s, L.A, [&](int c) {
+    L.lpr_a = best_lpr(s, lanes_for(L.A), [&](int c) {
       L.lpr_a = c;
       apply_op<E_CHEB, T>(s, L, x, b, d, c1, c2, y, nullptr);
     });
@@ -1227,10 +1394,20 @@ void tune_level(ppe_solver* s, int l) {
   }
   if (coarsest) return;
   Level& C = s->levels[l + 1];
-  L.lpr_r = best_lpr(s, L.R, [&](int c) {
+  L.lpr_r = best_lpr(s, lanes_for(L.R), [&](int c) {
     apply_rect<false, T>(s, L.R, L.r.as<T>(), C.b.as<T>(), c);
   });
-  L.lpr_p = best_lpr(s, L.P, [&](int c) {
+  if constexpr (std::is_same<T, double>::value) {
+    if (prolong_fusable<T>(s, L)) {
+      L.lpr_p = 0;
+      L.lpr_p = best_lpr(s, prolong_lanes(L), [&](int c) {
+        L.lpr_p = c;
+        prolong_cheb<T>(s, L, C.x.as<T>(), L.t.as<T>(), b, d, y);
+      });
+      return;
+    }
+  }
+  L.lpr_p = best_lpr(s, lanes_for(L.P), [&](int c) {
     apply_rect<true, T>(s, L.P, C.x.as<T>(), L.t.as<T>(), c);
   });
 }

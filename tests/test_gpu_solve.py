@@ -185,3 +185,29 @@ def test_reuse_of_an_unchanged_system():
     with pytest.raises(ppe.PpeError) as e:
         s.assemble(to_dev(c4, torch.float64), to_dev(bad, torch.float64))
     assert e.value.status == ppe.PPE_ERR_ARG
+
+
+def test_profile_times_the_finest_chebyshev_step():
+    """With profiling on, the finest level's first post-smoothing step (the
+    ELL Chebyshev step from x = x1 + P e) is timed once per V-cycle, and
+    each launch is credited with its algorithmic bytes: the stored
+    off-diagonal entries of A (8-byte value + 4-byte column) and five
+    vectors (diagonal, iterate in and out, right-hand side, step update)."""
+    import torch
+
+    m, f, c, b = case(shape=(24, 24, 24), fl="front", fl_seed=2, seed=2)
+    s = gpu_solver(m, f, c)
+    i0 = s.level_info(0)
+    n = i0["n"]
+    s.profile(True)
+    res = s.solve(to_dev(b, torch.float64))
+    prof = s.profile_read()
+    s.profile(False)
+    assert res.status == 0
+    assert prof["launches"] >= res.stats["iterations"] >= 1
+    assert prof["kernel_ms"] > 0.0
+    expect = 12.0 * (i0["nnz"] - n) + 5 * 8.0 * n
+    assert prof["bytes"] == expect * prof["launches"]
+    # profiling off: the totals stay as they were
+    s.solve(to_dev(b, torch.float64))
+    assert s.profile_read()["launches"] == prof["launches"]
