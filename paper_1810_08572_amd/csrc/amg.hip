@@ -573,6 +573,104 @@ __global__ void __launch_bounds__(kBlock) k_spgemm_compact(int n, const int* __r
 }
 
 // ------------------------------------------------------------------ transpose
+// A narrow matrix (at most kNarrowCols columns, such as the prolongator onto
+// the coarsest level) is transposed without atomics on its few column
+// counters and without sorting: a one-workgroup count, then one workgroup
+// per column that collects the column's entries in storage order.
+constexpr int kNarrowCols = 1024;
+constexpr int kNarrowU = 8;  // entries per lane whose loads are issued together
+
+// Column counts in LDS, then T's row pointers trp[0..m] (exclusive scan over
+// the columns) and its longest row *rmax.  One workgroup of 1024 threads.
+__global__ void __launch_bounds__(1024) k_narrow_count(int64_t nnz, int m,
+                                                       const int* __restrict__ ci,
+                                                       int* __restrict__ trp,
+                                                       int* __restrict__ rmax) {
+  __shared__ int h[kNarrowCols];
+  __shared__ int wsum[1024 / kWave];
+  __shared__ int hmax;
+  const int t = threadIdx.x, lane = t % kWave, w = t / kWave;
+  h[t] = 0;
+  if (t == 0) hmax = 0;
+  __syncthreads();
+  for (int64_t k = t; k < nnz; k += 1024) atomicAdd(&h[ci[k]], 1);
+  __syncthreads();
+  const int v = t < m ? h[t] : 0;
+  atomicMax(&hmax, v);
+  int inc = v;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int u = __shfl_up(inc, o, kWave);
+    if (lane >= o) inc += u;
+  }
+  if (lane == kWave - 1) wsum[w] = inc;
+  __syncthreads();
+  int before = 0;
+  for (int q = 0; q < w; ++q) before += wsum[q];
+  if (t < m) trp[t] = before + inc - v;
+  if (t == m - 1) trp[m] = before + inc;
+  if (t == 0) *rmax = hmax;
+}
+
+// rowid[k] = the row of entry k.
+__global__ void k_row_ids(int n, const int* __restrict__ rp, int* __restrict__ rowid) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n)
+    for (int k = rp[i]; k < rp[i + 1]; ++k) rowid[k] = i;
+}
+
+// Row J = blockIdx.x of T: wave w of the workgroup takes the w-th run of A's
+// entries in storage order, counts those in column J (ballots), and after
+// the counts of the earlier runs writes them in order.  Storage order is
+// ascending row, so T's rows come out sorted.
+__global__ void __launch_bounds__(1024) k_narrow_fill(int64_t nnz, const int* __restrict__ ci,
+                                                      const double* __restrict__ v,
+                                                      const int* __restrict__ rowid,
+                                                      const int* __restrict__ trp,
+                                                      int* __restrict__ tci,
+                                                      double* __restrict__ tv) {
+  __shared__ int wcnt[1024 / kWave];
+  const int J = blockIdx.x;
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  constexpr int nw = 1024 / kWave, step = kWave * kNarrowU;
+  const int64_t chunk = (nnz + nw - 1) / nw;
+  const int64_t k0 = min(nnz, (int64_t)w * chunk), k1 = min(nnz, k0 + chunk);
+  const unsigned long long below = (1ull << lane) - 1ull;
+  int c = 0;
+  for (int64_t base = k0; base < k1; base += step) {
+    bool hit[kNarrowU];
+#pragma unroll
+    for (int u = 0; u < kNarrowU; ++u) {
+      const int64_t k = base + (int64_t)u * kWave + lane;
+      hit[u] = k < k1 && ci[k] == J;
+    }
+#pragma unroll
+    for (int u = 0; u < kNarrowU; ++u) c += __popcll(__ballot(hit[u]));
+  }
+  if (lane == 0) wcnt[w] = c;
+  __syncthreads();
+  int pos = trp[J];
+  for (int q = 0; q < w; ++q) pos += wcnt[q];
+  for (int64_t base = k0; base < k1; base += step) {
+    bool hit[kNarrowU];
+#pragma unroll
+    for (int u = 0; u < kNarrowU; ++u) {
+      const int64_t k = base + (int64_t)u * kWave + lane;
+      hit[u] = k < k1 && ci[k] == J;
+    }
+#pragma unroll
+    for (int u = 0; u < kNarrowU; ++u) {
+      const unsigned long long mask = __ballot(hit[u]);
+      if (hit[u]) {
+        const int64_t k = base + (int64_t)u * kWave + lane;
+        const int p = pos + __popcll(mask & below);
+        tci[p] = rowid[k];
+        tv[p] = v[k];
+      }
+      pos += __popcll(mask);
+    }
+  }
+}
+
 __global__ void k_col_count(int64_t nnz, const int* __restrict__ ci, int* __restrict__ cnt) {
   int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (k < nnz) atomicAdd(&cnt[ci[k]], 1);
@@ -831,12 +929,13 @@ __global__ void __launch_bounds__(1024) k_dense_inverse_blk(int n, const double*
       if (i0 + r < n && j0 + c < n) Ainv[(size_t)(i0 + r) * n + j0 + c] = a[r][c];
 }
 
+// G = [A | I] (n x 2n, row-major, zeroed before): one wavefront per row.
 __global__ void k_densify(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                           const double* __restrict__ v, double* __restrict__ G) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
   if (i >= n) return;
-  for (int k = rp[i]; k < rp[i + 1]; ++k) G[(size_t)i * 2 * n + ci[k]] = v[k];
-  G[(size_t)i * 2 * n + n + i] = 1.0;
+  for (int k = rp[i] + lane; k < rp[i + 1]; k += kWave) G[(size_t)i * 2 * n + ci[k]] = v[k];
+  if (lane == 0) G[(size_t)i * 2 * n + n + i] = 1.0;
 }
 
 // ------------------------------------------------------------------ host helpers
@@ -1003,6 +1102,20 @@ void transpose(ppe_solver* s, const Csr& A, Csr& T) {
   T.m = A.n;
   T.nnz = A.nnz;
   T.maxrow = 0;
+  if (T.n > 0 && T.n <= kNarrowCols && A.nnz > 0) {
+    int* trp = T.rowptr.get<int>(T.n + 1);
+    hipLaunchKernelGGL(k_narrow_count, dim3(1), dim3(1024), 0, s->stream, A.nnz, T.n, A.ci(), trp,
+                       s->rmax.get<int>(1));
+    PPE_LAUNCH_CHECK();
+    int* rowid = s->tmp_i[2].get<int>(A.nnz);
+    hipLaunchKernelGGL(k_row_ids, dim3(grid_for(A.n)), dim3(kBlock), 0, s->stream, A.n, A.rp(),
+                       rowid);
+    PPE_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_narrow_fill, dim3(T.n), dim3(1024), 0, s->stream, A.nnz, A.ci(), A.v(),
+                       rowid, trp, T.col.get<int>(T.nnz), T.val.get<double>(T.nnz));
+    PPE_LAUNCH_CHECK();
+    return;
+  }
   int* cnt = s->tmp_i[0].get<int>(T.n + 1);
   fill_int(s, cnt, 0, T.n + 1);
   if (A.nnz) {
@@ -1241,8 +1354,8 @@ void build_hierarchy(ppe_solver* s) {
       double* Ainv = L.Ainv.get<double>((size_t)n * n);
       double* G = s->tmp_d[1].get<double>((size_t)2 * n * n);
       fill_double(s, G, 0.0, (int64_t)2 * n * n);
-      hipLaunchKernelGGL(k_densify, dim3(grid_for(n)), dim3(kBlock), 0, s->stream, n, L.A.rp(),
-                         L.A.ci(), L.A.v(), G);
+      hipLaunchKernelGGL(k_densify, dim3(grid_for((int64_t)n * kWave)), dim3(kBlock), 0,
+                         s->stream, n, L.A.rp(), L.A.ci(), L.A.v(), G);
       PPE_LAUNCH_CHECK();
       if (n <= 128) {
         hipLaunchKernelGGL(k_dense_inverse_blk, dim3(1), dim3(1024), 0, s->stream, n, G, Ainv, err);
