@@ -835,92 +835,120 @@ __global__ void __launch_bounds__(1024) k_dense_inverse_reg(int n, const double*
   }
 }
 
-// The same elimination for n <= 128 with a 2-D ownership: thread t owns the
-// 4 x 4 block of rows 4 (t / 32) .. +3 and columns 4 (t mod 32) .. +3 (the
-// 128 x 128 cover; entries past n are carried as throw-away values).  Per
-// step a thread reads four pivot-column and four pivot-row values from LDS
-// (double-buffered as above) and updates its block with 16 multiply-adds.
+// The same elimination for n <= 128 by 4 x 4 blocks: thread t owns the block
+// of rows 4 (t / 32) .. +3 and columns 4 (t mod 32) .. +3 of the 128 x 128
+// cover, padded with the identity past n (the padding stays decoupled).
+// Block step K (pivots 4K .. 4K+3) is the block form of the steps above: with
+// D = A_KK, C_I = A_IK and R_J = A_KJ,
+//   A_KK <- D^-1,  A_KJ <- D^-1 R_J,  A_IK <- -C_I D^-1,
+//   A_IJ <- A_IJ - C_I (D^-1 R_J).
+// The owner of A_KK inverts it in registers by the scalar steps (its four
+// pivots are the elimination's pivots 4K .. 4K+3, each checked > 0).  D^-1,
+// the old block column and the new block row pass through LDS,
+// double-buffered, so a block step takes two barriers instead of the four
+// of four scalar steps.
 __global__ void __launch_bounds__(1024) k_dense_inverse_blk(int n, const double* __restrict__ Gm,
                                                             double* __restrict__ Ainv,
                                                             int* __restrict__ flag) {
   constexpr int B = 4;
-  __shared__ double colk[2][32 * B];
-  __shared__ double rowk[2][32 * B];
+  __shared__ double dinv[2][B][B];
+  __shared__ double cpan[2][32 * B][B];
+  __shared__ double rpan[2][B][32 * B];
   const int t = threadIdx.x;
-  const int i0 = (t / 32) * B, j0 = (t % 32) * B;
+  const int I = t / 32, J = t % 32, i0 = I * B, j0 = J * B;
   double a[B][B];
 #pragma unroll
   for (int r = 0; r < B; ++r)
 #pragma unroll
-    for (int c = 0; c < B; ++c)
-      a[r][c] = (i0 + r < n && j0 + c < n) ? Gm[(size_t)(i0 + r) * 2 * n + j0 + c] : 0.0;
-  // publish column 0 and row 0
-  if (j0 == 0) {
-#pragma unroll
-    for (int r = 0; r < B; ++r) colk[0][i0 + r] = a[r][0];
-  }
-  if (i0 == 0) {
-#pragma unroll
-    for (int c = 0; c < B; ++c) rowk[0][j0 + c] = a[0][c];
-  }
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    const int cb = k & 1, nb = cb ^ 1;
-    double piv = colk[cb][k];
-    if (!(piv > 0.0)) {
-      if (t == 0) atomicOr(flag, SE_DENSE);
-      piv = 1.0;
+    for (int c = 0; c < B; ++c) {
+      const int i = i0 + r, j = j0 + c;
+      a[r][c] = (i < n && j < n) ? Gm[(size_t)i * 2 * n + j] : (i == j ? 1.0 : 0.0);
     }
-    const double inv = 1.0 / piv;
-    double f[B], rk[B];
+  const int nb = (n + B - 1) / B;
+  for (int K = 0; K < nb; ++K) {
+    const int bf = K & 1;
+    if (I == K && J == K) {
 #pragma unroll
-    for (int r = 0; r < B; ++r) f[r] = colk[cb][i0 + r];
+      for (int k = 0; k < B; ++k) {
+        double piv = a[k][k];
+        if (!(piv > 0.0)) {
+          atomicOr(flag, SE_DENSE);
+          piv = 1.0;
+        }
+        const double inv = 1.0 / piv;
+        double rk[B];
 #pragma unroll
-    for (int c = 0; c < B; ++c) rk[c] = (j0 + c == k ? 1.0 : rowk[cb][j0 + c]) * inv;
-    if (j0 <= k && k < j0 + B) {  // a_ik is replaced by 0 before the update
-      const int ck = k - j0;
-#pragma unroll
-      for (int r = 0; r < B; ++r)
-#pragma unroll
-        for (int c = 0; c < B; ++c)
-          if (c == ck) a[r][c] = 0.0;
-    }
-#pragma unroll
-    for (int r = 0; r < B; ++r)
-#pragma unroll
-      for (int c = 0; c < B; ++c) a[r][c] = fma(-f[r], rk[c], a[r][c]);
-    if (i0 <= k && k < i0 + B) {  // the pivot row becomes the scaled row
-      const int rk_ = k - i0;
-#pragma unroll
-      for (int r = 0; r < B; ++r)
-#pragma unroll
-        for (int c = 0; c < B; ++c)
-          if (r == rk_) a[r][c] = rk[c];
-    }
-    if (k + 1 < n) {
-      const int k1 = k + 1;
-      if (j0 <= k1 && k1 < j0 + B) {
-        const int c1 = k1 - j0;
+        for (int c = 0; c < B; ++c) rk[c] = (c == k ? 1.0 : a[k][c]) * inv;
 #pragma unroll
         for (int r = 0; r < B; ++r) {
-          double v = a[r][0];
+          if (r == k) continue;
+          const double f = a[r][k];
 #pragma unroll
-          for (int c = 1; c < B; ++c) v = c == c1 ? a[r][c] : v;
-          colk[nb][i0 + r] = v;
+          for (int c = 0; c < B; ++c) a[r][c] = (c == k ? 0.0 : a[r][c]) - f * rk[c];
         }
-      }
-      if (i0 <= k1 && k1 < i0 + B) {
-        const int r1 = k1 - i0;
 #pragma unroll
-        for (int c = 0; c < B; ++c) {
-          double v = a[0][c];
-#pragma unroll
-          for (int r = 1; r < B; ++r) v = r == r1 ? a[r][c] : v;
-          rowk[nb][j0 + c] = v;
-        }
+        for (int c = 0; c < B; ++c) a[k][c] = rk[c];
       }
+#pragma unroll
+      for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int c = 0; c < B; ++c) dinv[bf][r][c] = a[r][c];
+    }
+    if (J == K && I != K) {
+#pragma unroll
+      for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int c = 0; c < B; ++c) cpan[bf][i0 + r][c] = a[r][c];
     }
     __syncthreads();
+    if (I == K && J != K) {  // the block row: D^-1 R_J
+      double nr[B][B];
+#pragma unroll
+      for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int c = 0; c < B; ++c) {
+          double s = 0.0;
+#pragma unroll
+          for (int m = 0; m < B; ++m) s = fma(dinv[bf][r][m], a[m][c], s);
+          nr[r][c] = s;
+        }
+#pragma unroll
+      for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int c = 0; c < B; ++c) {
+          a[r][c] = nr[r][c];
+          rpan[bf][r][j0 + c] = nr[r][c];
+        }
+    }
+    __syncthreads();
+    if (I != K) {
+      double f[B][B];
+#pragma unroll
+      for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int m = 0; m < B; ++m) f[r][m] = cpan[bf][i0 + r][m];
+      if (J == K) {  // the block column: -C_I D^-1
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+          for (int c = 0; c < B; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int m = 0; m < B; ++m) s = fma(f[r][m], dinv[bf][m][c], s);
+            a[r][c] = -s;
+          }
+      } else {
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+          for (int c = 0; c < B; ++c) {
+            double s = a[r][c];
+#pragma unroll
+            for (int m = 0; m < B; ++m) s = fma(-f[r][m], rpan[bf][m][j0 + c], s);
+            a[r][c] = s;
+          }
+      }
+    }
   }
 #pragma unroll
   for (int r = 0; r < B; ++r)
