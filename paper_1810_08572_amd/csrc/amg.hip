@@ -375,7 +375,7 @@ __global__ void __launch_bounds__(kBlock) k_spgemm_bound(int n, const int* __res
   if (i < n && lane == 0) prod[i] = s > (1 << 30) ? (1 << 30) : (int)s;
 }
 
-enum SpMode { SP_COUNT = 0, SP_FILL = 1, SP_DENSE = 2 };
+enum SpMode { SP_COUNT = 0, SP_FILL = 1, SP_DENSE = 2, SP_BITS = 3 };
 constexpr int kSpBatch = 4;        // entries of A whose loads are issued together
 constexpr int kSpDenseWidth = 512; // widest C accumulated with one slot per column
 
@@ -393,7 +393,9 @@ constexpr int kSpDenseWidth = 512; // widest C accumulated with one slot per col
 //   SP_FILL   the same hash; the row is written to C at off[i], sorted by
 //             column (rank among the row's columns);
 //   SP_DENSE  slot = column (H >= width); the row is written in column order
-//             to the scratch row at off[i]; counts[i] = entries written.
+//             to the scratch row at off[i]; counts[i] = entries written;
+//   SP_BITS   a bit per column of C in H 32-bit words (no probing); counts[i]
+//             = bits set, the row's distinct columns as with SP_COUNT.
 // The block holds blockDim / (LPR W) rows; LDS is sized by the host.
 template <int LPR, int MODE>
 __global__ void __launch_bounds__(1024) k_spgemm_rows(
@@ -407,7 +409,7 @@ __global__ void __launch_bounds__(1024) k_spgemm_rows(
   const int rl = threadIdx.x / per_row, tr = threadIdx.x % per_row;
   const int w = tr / LPR, lane = tr % LPR;
   const int i = blockIdx.x * rpb + rl;
-  const bool numeric = MODE != SP_COUNT;
+  const bool numeric = MODE == SP_FILL || MODE == SP_DENSE;
   double* vals = smem + (size_t)rl * W * H;  // [W][H] of this row
   int* ibase = reinterpret_cast<int*>(smem + (numeric ? (size_t)rpb * W * H : 0));
   int* keys = ibase + (size_t)rl * H;
@@ -416,7 +418,7 @@ __global__ void __launch_bounds__(1024) k_spgemm_rows(
   int* ckey = list + H / 2;
   int* cnt = ibase + (size_t)(MODE == SP_FILL ? 2 : 1) * rpb * H;
   for (int q = tr; q < H; q += per_row) {
-    keys[q] = -1;
+    keys[q] = MODE == SP_BITS ? 0 : -1;
     if (numeric)
       for (int v = 0; v < W; ++v) vals[(size_t)v * H + q] = 0.0;
   }
@@ -430,6 +432,10 @@ __global__ void __launch_bounds__(1024) k_spgemm_rows(
   bool overflow = false;
   auto insert = [&](int key, double y) {
     int q;
+    if (MODE == SP_BITS) {
+      atomicOr(reinterpret_cast<unsigned*>(keys) + (key >> 5), 1u << (key & 31));
+      return;
+    }
     if (MODE == SP_DENSE) {
       q = key;
       keys[q] = key;
@@ -487,6 +493,14 @@ __global__ void __launch_bounds__(1024) k_spgemm_rows(
   if (overflow) atomicOr(flag, 1);
   __syncthreads();
 
+  if (MODE == SP_BITS) {
+    int c = 0;
+    for (int q = tr; q < H; q += per_row) c += __popc((unsigned)keys[q]);
+    atomicAdd(&cnt[rl], c);
+    __syncthreads();
+    if (i < n && tr == 0) counts[i] = cnt[rl];
+    return;
+  }
   if (MODE == SP_COUNT) {
     if (i < n && tr == 0) counts[i] = cnt[rl];
     return;
@@ -989,7 +1003,7 @@ struct SpConfig {
 
 static size_t spgemm_lds(int mode, int rpb, int W, int H, int per_row) {
   const size_t r = (size_t)rpb, h = (size_t)H;
-  if (mode == SP_COUNT) return r * h * 4 + r * 4;
+  if (mode == SP_COUNT || mode == SP_BITS) return r * h * 4 + r * 4;
   if (mode == SP_FILL) return r * W * h * 8 + 2 * r * h * 4 + r * 4;
   return r * W * h * 8 + r * h * 4 + r * (per_row / kWave + 1) * 4;
 }
@@ -1021,8 +1035,9 @@ template <int MODE>
 static void spgemm_launch(ppe_solver* s, const SpConfig& c, const Csr& A, const Csr& B,
                           const int* off, int* counts, int* cci, double* cv, int* flag) {
   const int g = (A.n + c.rpb - 1) / c.rpb;
-  const double* av = MODE == SP_COUNT ? nullptr : A.v();
-  const double* bv = MODE == SP_COUNT ? nullptr : B.v();
+  const bool numeric = MODE == SP_FILL || MODE == SP_DENSE;
+  const double* av = numeric ? A.v() : nullptr;
+  const double* bv = numeric ? B.v() : nullptr;
 #define PPE_SPR(L_)                                                                            \
   hipLaunchKernelGGL((k_spgemm_rows<L_, MODE>), dim3(g), dim3(c.threads), c.lds, s->stream, A.n, \
                      c.W, c.H, A.rp(), A.ci(), av, B.rp(), B.ci(), bv, off, counts, cci, cv, flag)
@@ -1041,7 +1056,8 @@ static void spgemm_launch(ppe_solver* s, const SpConfig& c, const Csr& A, const 
 // to fill a quarter of them) take one pass with a slot per column into
 // fixed-stride scratch rows and a compaction;
 // wider ones count each row's distinct columns with a hash sized from the
-// product bound, then fill C with a hash sized from the largest count.  The
+// product bound (or a bit per column of C when that is smaller), then fill
+// C with a hash sized from the largest count.  The
 // product bound is maxrow(A) maxrow(B) when both are known on the host, else
 // a bound pass reads it back.  C.maxrow is set to C's longest row.  extra: a
 // device int read back in the same round trip as C's size (extra_host).
@@ -1113,8 +1129,15 @@ void spgemm(ppe_solver* s, const Csr& A, const Csr& B, Csr& C, const int* extra,
   }
   int Hc = 32;
   while (Hc < 2 * ub && Hc < 8192) Hc *= 2;
-  const SpConfig cc = spgemm_config(s, A, B, SP_COUNT, Hc);
-  spgemm_launch<SP_COUNT>(s, cc, A, B, nullptr, counts, nullptr, nullptr, flag);
+  // count with a bit per column of C when that takes less LDS than the hash
+  const int words = (C.m + 31) / 32;
+  if (words < Hc) {
+    const SpConfig cb = spgemm_config(s, A, B, SP_BITS, words);
+    spgemm_launch<SP_BITS>(s, cb, A, B, nullptr, counts, nullptr, nullptr, flag);
+  } else {
+    const SpConfig cc = spgemm_config(s, A, B, SP_COUNT, Hc);
+    spgemm_launch<SP_COUNT>(s, cc, A, B, nullptr, counts, nullptr, nullptr, flag);
+  }
   fetch_scan(true);
   int H = 16;  // at least twice the longest row: list and ckey hold H / 2
   while (H < 2 * fm[1]) H *= 2;
