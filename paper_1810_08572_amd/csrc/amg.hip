@@ -607,7 +607,17 @@ __global__ void __launch_bounds__(1024) k_narrow_count(int64_t nnz, int m,
   h[t] = 0;
   if (t == 0) hmax = 0;
   __syncthreads();
-  for (int64_t k = t; k < nnz; k += 1024) atomicAdd(&h[ci[k]], 1);
+  for (int64_t k0 = t; k0 < nnz; k0 += 1024 * kNarrowU) {
+    int c[kNarrowU];
+#pragma unroll
+    for (int u = 0; u < kNarrowU; ++u) {
+      const int64_t k = k0 + (int64_t)u * 1024;
+      c[u] = k < nnz ? ci[k] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kNarrowU; ++u)
+      if (c[u] >= 0) atomicAdd(&h[c[u]], 1);
+  }
   __syncthreads();
   const int v = t < m ? h[t] : 0;
   atomicMax(&hmax, v);
