@@ -324,6 +324,44 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ partia
   return r;
 }
 
+// The sums of NV partial arrays at once (each added in the order of
+// sum_partials, so each result is bitwise the same): one pass over the
+// partials and one exchange through LDS instead of NV; broadcast to every
+// thread.
+template <int BS, int NV>
+__device__ __forceinline__ void sum_partials_n(const double* const (&parts)[NV], int G,
+                                               double (&out)[NV]) {
+  __shared__ double sh[NV][BS / kWave];
+  __shared__ double bc[NV];
+  double a[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) a[k] = 0.0;
+  for (int b = threadIdx.x; b < G; b += BS) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) a[k] += parts[k][b];
+  }
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    a[k] = wave_sum(a[k]);
+    if (lane == 0) sh[k][w] = a[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double t = 0;
+#pragma unroll
+      for (int i = 0; i < BS / kWave; ++i) t += sh[k][i];
+      bc[k] = t;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) out[k] = bc[k];
+  __syncthreads();
+}
+
 inline int red_grid(int64_t work_items, int bs = kBlock) {
   int64_t g = (work_items + bs - 1) / bs;
   if (g < 1) g = 1;

@@ -514,8 +514,18 @@ __global__ void __launch_bounds__(kBlock) k_update_xr_t(Tiles T, const int* __re
   if (t == 0 && threadIdx.x == 0) *active = 0;  // counted again by k_update_p_t
   double acc = 0.0;
   if (!done[q]) {
-    const double pq = seg_sum(part_pq, T, q);
-    const double num = flexible ? seg_sum(part_pq + nt, T, q) : rz[q];
+    double pq, num;
+    if (flexible) {
+      const int g0 = T.tp[q];
+      const double* parts[2] = {part_pq + g0, part_pq + nt + g0};
+      double sums[2];
+      sum_partials_n<kBlock, 2>(parts, T.tp[q + 1] - g0, sums);
+      pq = sums[0];
+      num = sums[1];
+    } else {
+      pq = seg_sum(part_pq, T, q);
+      num = rz[q];
+    }
     if (!(pq > 0.0) || !(num > 0.0)) {
       if (threadIdx.x == 0) atomicOr(err, 1);
     } else {
@@ -550,8 +560,22 @@ __global__ void __launch_bounds__(kBlock) k_update_p_t(
   const int t = blockIdx.x, q = T.seg[t];
   if (done[q]) return;
   const bool lead = t == T.tp[q] && threadIdx.x == 0;
+  // every sum this block may need, in one pass over the segment's partials:
+  // r.r, r.z and (flexible) z.q and p.q
+  const int g0 = T.tp[q], G = T.tp[q + 1] - g0;
+  double sums[4] = {0.0, 0.0, 0.0, 0.0};
+  if (flexible) {
+    const double* parts[4] = {part_rr + g0, part_rz + g0, part_rz + nt + g0, part_pq + g0};
+    sum_partials_n<kBlock, 4>(parts, G, sums);
+  } else {
+    const double* parts[2] = {part_rr + g0, part_rz + g0};
+    double two[2];
+    sum_partials_n<kBlock, 2>(parts, G, two);
+    sums[0] = two[0];
+    sums[1] = two[1];
+  }
   if (test) {
-    const double rr = seg_sum(part_rr, T, q);
+    const double rr = sums[0];
     const bool bad = !(rr == rr) || rr > 1.7976931348623157e308;
     const bool conv = bad || rr <= sc[SS_TOL2 * ns + q];
     if (lead) {
@@ -563,11 +587,11 @@ __global__ void __launch_bounds__(kBlock) k_update_p_t(
     }
     if (conv) return;
   }
-  const double rzn = seg_sum(part_rz, T, q);
+  const double rzn = sums[1];
   double beta = 0.0;
   if (!(!test && restart[q])) {
     if (flexible)
-      beta = -seg_sum(part_rz + nt, T, q) / seg_sum(part_pq, T, q);
+      beta = -sums[2] / sums[3];
     else
       beta = rzn / rz_prev[q];
   }
