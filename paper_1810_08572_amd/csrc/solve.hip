@@ -132,6 +132,33 @@ __global__ void __launch_bounds__(kBlock) k_ell(int n, int W, const int* __restr
 
 // ---- CSR, LPR lanes per row; every lane runs the same trip count so the
 // group shuffles always see all lanes.
+
+// s + the sum over the entries k0 + lane, k0 + lane + LPR, ... (< k1) of a
+// CSR row of v[k] op(ci[k]), added in that order; the loads of U entries are
+// requested before the first is used (the order of the sum is that of the
+// plain loop).
+template <int LPR, int U, class T, class Op>
+__device__ __forceinline__ T row_sum(T s, int k0, int k1, int lane, const int* __restrict__ ci,
+                                     const T* __restrict__ v, Op op) {
+  for (int k = k0 + lane; k < k1; k += LPR * U) {
+    int c[U];
+    T w[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int kk = k + u * LPR;
+      c[u] = kk < k1 ? ci[kk] : -1;
+      w[u] = kk < k1 ? v[kk] : T(0);
+    }
+    T g[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) g[u] = c[u] >= 0 ? op(c[u]) : T(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (c[u] >= 0) s = s + w[u] * g[u];
+  }
+  return s;
+}
+constexpr int kRowU = 4;
 template <int EPI, int LPR, class T>
 __global__ void __launch_bounds__(kBlock) k_csr(int n, const int* __restrict__ rp,
                                                 const int* __restrict__ ci,
@@ -150,10 +177,9 @@ __global__ void __launch_bounds__(kBlock) k_csr(int n, const int* __restrict__ r
   for (int t = 0; t < trips; ++t) {
     const int g = t * groups + my;
     T s = T(0);
-    if (g < n) {
-      for (int k = rp[g] + lane; k < rp[g + 1]; k += LPR)
-        s = s + v[k] * operand<EPI, T>(ci[k], x, b, diag, c0);
-    }
+    if (g < n)
+      s = row_sum<LPR, kRowU, T>(s, rp[g], rp[g + 1], lane, ci, v,
+                                 [&](int j) { return operand<EPI, T>(j, x, b, diag, c0); });
 #pragma unroll
     for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_down(s, o, LPR);
     if (g < n && lane == 0) dot += epilogue<EPI, T>(g, s, x, b, diag, d, c1, c2, scale, y, c0);
@@ -173,9 +199,8 @@ __global__ void __launch_bounds__(kBlock) k_csr_rect(int n, const int* __restric
   const int g = (blockIdx.x * kBlock + threadIdx.x) / LPR;
   const int lane = threadIdx.x % LPR;
   T s = T(0);
-  if (g < n) {
-    for (int k = rp[g] + lane; k < rp[g + 1]; k += LPR) s = s + v[k] * x[ci[k]];
-  }
+  if (g < n)
+    s = row_sum<LPR, kRowU, T>(s, rp[g], rp[g + 1], lane, ci, v, [&](int j) { return x[j]; });
 #pragma unroll
   for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_down(s, o, LPR);
   if (g < n && lane == 0) y[g] = ADD ? y[g] + s : s;
