@@ -159,6 +159,71 @@ __device__ __forceinline__ T row_sum(T s, int k0, int k1, int lane, const int* _
   return s;
 }
 constexpr int kRowU = 4;
+
+// A row's own values that the epilogue reads, loaded by the row's first lane
+// before the row's entries (so they are not a dependent load after the
+// group's shuffles), and the epilogue on them: the same arithmetic as
+// epilogue().
+template <class T>
+struct RowOwn {
+  T x, b, diag, d;
+};
+
+template <int EPI, class T>
+__device__ __forceinline__ RowOwn<T> row_own(int i, const T* __restrict__ x,
+                                             const T* __restrict__ b, const T* __restrict__ diag,
+                                             const T* __restrict__ d, T c1) {
+  RowOwn<T> o{T(0), T(0), T(1), T(0)};
+  if (EPI == E_CHEB0) {
+    o.b = b[i];
+    o.diag = diag[i];
+  } else if (EPI == E_RESID) {
+    o.b = b[i];
+  } else if (EPI == E_CHEB) {
+    o.b = b[i];
+    o.diag = diag[i];
+    o.x = x[i];
+    if (c1 != T(0)) o.d = d[i];
+  } else if (EPI == E_DOT) {
+    o.x = x[i];
+  } else if (EPI == E_POWER) {
+    o.diag = diag[i];
+  }
+  return o;
+}
+
+template <int EPI, class T>
+__device__ __forceinline__ double epilogue_own(int i, T ax, const RowOwn<T>& o,
+                                               T* __restrict__ d, T c1, T c2, T scale,
+                                               T* __restrict__ y, T c0) {
+  if (EPI == E_CHEB0) {
+    const T x1 = c0 * (o.b / o.diag);
+    const T r = (o.b - ax) / o.diag;
+    const T dn = c1 * x1 + c2 * r;
+    d[i] = dn;
+    y[i] = x1 + dn;
+    return 0.0;
+  } else if (EPI == E_SPMV) {
+    y[i] = ax;
+    return 0.0;
+  } else if (EPI == E_RESID) {
+    y[i] = o.b - ax;
+    return 0.0;
+  } else if (EPI == E_CHEB) {
+    const T r = (o.b - ax) / o.diag;
+    const T dn = (c1 == T(0) ? T(0) : c1 * o.d) + c2 * r;
+    d[i] = dn;
+    y[i] = o.x + dn;
+    return 0.0;
+  } else if (EPI == E_DOT) {
+    y[i] = ax;
+    return (double)o.x * (double)ax;
+  } else {
+    const T v = (ax / o.diag) * scale;
+    y[i] = v;
+    return (double)v * (double)v;
+  }
+}
 template <int EPI, int LPR, class T>
 __global__ void __launch_bounds__(kBlock) k_csr(int n, const int* __restrict__ rp,
                                                 const int* __restrict__ ci,
@@ -177,12 +242,15 @@ __global__ void __launch_bounds__(kBlock) k_csr(int n, const int* __restrict__ r
   for (int t = 0; t < trips; ++t) {
     const int g = t * groups + my;
     T s = T(0);
-    if (g < n)
+    RowOwn<T> own{T(0), T(0), T(1), T(0)};
+    if (g < n) {
+      if (lane == 0) own = row_own<EPI, T>(g, x, b, diag, d, c1);
       s = row_sum<LPR, kRowU, T>(s, rp[g], rp[g + 1], lane, ci, v,
                                  [&](int j) { return operand<EPI, T>(j, x, b, diag, c0); });
+    }
 #pragma unroll
     for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_down(s, o, LPR);
-    if (g < n && lane == 0) dot += epilogue<EPI, T>(g, s, x, b, diag, d, c1, c2, scale, y, c0);
+    if (g < n && lane == 0) dot += epilogue_own<EPI, T>(g, s, own, d, c1, c2, scale, y, c0);
   }
   if (EPI == E_DOT || EPI == E_POWER) {
     double vv[1] = {dot};
@@ -198,12 +266,14 @@ __global__ void __launch_bounds__(kBlock) k_csr_rect(int n, const int* __restric
                                                      const T* __restrict__ x, T* __restrict__ y) {
   const int g = (blockIdx.x * kBlock + threadIdx.x) / LPR;
   const int lane = threadIdx.x % LPR;
-  T s = T(0);
-  if (g < n)
+  T s = T(0), y0 = T(0);
+  if (g < n) {
+    if (ADD && lane == 0) y0 = y[g];  // requested before the row's entries
     s = row_sum<LPR, kRowU, T>(s, rp[g], rp[g + 1], lane, ci, v, [&](int j) { return x[j]; });
+  }
 #pragma unroll
   for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_down(s, o, LPR);
-  if (g < n && lane == 0) y[g] = ADD ? y[g] + s : s;
+  if (g < n && lane == 0) y[g] = ADD ? y0 + s : s;
 }
 
 // ---- prolongation fused with the first post-smoothing step
