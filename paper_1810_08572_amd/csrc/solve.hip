@@ -607,6 +607,15 @@ __global__ void __launch_bounds__(kBlock) k_update_xr_t(Tiles T, const int* __re
                                                         int flexible) {
   const int t = blockIdx.x, q = T.seg[t];
   if (t == 0 && threadIdx.x == 0) *active = 0;  // counted again by k_update_p_t
+  // the thread's first row, requested before the segment's sums
+  const int i0 = T.r0[t] + threadIdx.x, i1 = T.r1[t];
+  double x0 = 0.0, p0 = 0.0, r0 = 0.0, q0 = 0.0;
+  if (i0 < i1) {
+    x0 = x[i0];
+    p0 = p[i0];
+    r0 = r[i0];
+    q0 = qv[i0];
+  }
   double acc = 0.0;
   if (!done[q]) {
     double pq, num;
@@ -625,9 +634,10 @@ __global__ void __launch_bounds__(kBlock) k_update_xr_t(Tiles T, const int* __re
       if (threadIdx.x == 0) atomicOr(err, 1);
     } else {
       const double alpha = num / pq;
-      for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) {
-        x[i] = x[i] + alpha * p[i];
-        const double v = r[i] - alpha * qv[i];
+      for (int i = i0; i < i1; i += kBlock) {
+        const bool first = i == i0;
+        x[i] = (first ? x0 : x[i]) + alpha * (first ? p0 : p[i]);
+        const double v = (first ? r0 : r[i]) - alpha * (first ? q0 : qv[i]);
         r[i] = v;
         acc += v * v;
       }
@@ -653,6 +663,13 @@ __global__ void __launch_bounds__(kBlock) k_update_p_t(
     double* __restrict__ rz_next,
     const double* __restrict__ z, double* __restrict__ p, int* __restrict__ err) {
   const int t = blockIdx.x, q = T.seg[t];
+  // the thread's first row, requested before the segment's sums
+  const int i0 = T.r0[t] + threadIdx.x, i1 = T.r1[t];
+  double z0 = 0.0, p0 = 0.0;
+  if (i0 < i1) {
+    z0 = z[i0];
+    p0 = p[i0];
+  }
   if (done[q]) return;
   const bool lead = t == T.tp[q] && threadIdx.x == 0;
   // every sum this block may need, in one pass over the segment's partials:
@@ -694,7 +711,10 @@ __global__ void __launch_bounds__(kBlock) k_update_p_t(
     rz_next[q] = rzn;
     if (!(rzn > 0.0)) atomicOr(err, 4);
   }
-  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) p[i] = z[i] + beta * p[i];
+  for (int i = i0; i < i1; i += kBlock) {
+    const bool first = i == i0;
+    p[i] = (first ? z0 : z[i]) + beta * (first ? p0 : p[i]);
+  }
 }
 
 // After the recurred residuals all met the tolerance: per segment (one
