@@ -816,6 +816,22 @@ template <> struct LevelData<float> {
   static const float* ainv(const Level& L) { return L.Ainvf.as<float>(); }
 };
 
+// Lanes per row of the solve's CSR kernels by default in value type T.  FP64:
+// the fewest (a power of two, 4 to 64) that reach half the mean row length,
+// each lane then taking about two entries whose loads are requested
+// together.  The FP32 V-cycle of the mixed mode keeps lanes_for (one entry
+// per lane): its order of summation under the other rule left a 32^3 mixed
+// solve at the residual bar with the error past its bar, as the FP32 fusion
+// did.
+template <class T>
+int solve_lanes(const Csr& M) {
+  if (!std::is_same<T, double>::value) return lanes_for(M);
+  const double mean = M.n ? (double)M.nnz / M.n : 1.0;
+  int lpr = 4;
+  while (lpr < 64 && 2 * lpr < mean) lpr *= 2;
+  return lpr;
+}
+
 // Apply the level operator with epilogue EPI in value type T.  Dot/power
 // epilogues run on a capped grid and write partials to `partials`; returns
 // that grid size.
@@ -856,7 +872,11 @@ int apply_op(ppe_solver* s, const Level& L, const T* x, const T* b, T* d, double
     }
     return g;
   }
-  const int lpr = L.lpr_a > 0 ? L.lpr_a : lanes_for(L.A);
+  // the setup's power steps keep the one-entry rule: the spectral bounds,
+  // and with them the hierarchy, stay what they were
+  const int lpr = L.lpr_a > 0     ? L.lpr_a
+                  : EPI == E_POWER ? lanes_for(L.A)
+                                   : solve_lanes<T>(L.A);
   const int g = reduce ? red_grid((int64_t)n * lpr) : grid_for((int64_t)n * lpr);
 #define PPE_CSR(LL)                                                                            \
   hipLaunchKernelGGL((k_csr<EPI, LL, T>), dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(),    \
@@ -877,7 +897,7 @@ int apply_op(ppe_solver* s, const Level& L, const T* x, const T* b, T* d, double
 template <bool ADD, class T>
 void apply_rect(ppe_solver* s, const Csr& M, const T* x, T* y, int lpr_choice = 0) {
   if (M.n == 0) return;
-  const int lpr = lpr_choice > 0 ? lpr_choice : lanes_for(M);
+  const int lpr = lpr_choice > 0 ? lpr_choice : solve_lanes<T>(M);
   const int g = grid_for((int64_t)M.n * lpr);
 #define PPE_RECT(LL)                                                                           \
   hipLaunchKernelGGL((k_csr_rect<LL, ADD, T>), dim3(g), dim3(kBlock), 0, s->stream, M.n, M.rp(), \
@@ -1516,7 +1536,7 @@ void tune_level(ppe_solver* s, int l) {
   T* y = L.x2.as<T>();
   const double c1 = L.c1.empty() ? 0.0 : L.c1[0], c2 = L.c1.empty() ? L.inv_theta : L.c2[0];
   if (l > 0)
-    L.lpr_a = best_lpr(s, lanes_for(L.A), [&](int c) {
+    L.lpr_a = best_lpr(s, solve_lanes<T>(L.A), [&](int c) {
       L.lpr_a = c;
       apply_op<E_CHEB, T>(s, L, x, b, d, c1, c2, y, nullptr);
     });
@@ -1533,7 +1553,7 @@ void tune_level(ppe_solver* s, int l) {
   }
   if (coarsest) return;
   Level& C = s->levels[l + 1];
-  L.lpr_r = best_lpr(s, lanes_for(L.R), [&](int c) {
+  L.lpr_r = best_lpr(s, solve_lanes<T>(L.R), [&](int c) {
     apply_rect<false, T>(s, L.R, L.r.as<T>(), C.b.as<T>(), c);
   });
   if constexpr (std::is_same<T, double>::value) {
@@ -1546,7 +1566,7 @@ void tune_level(ppe_solver* s, int l) {
       return;
     }
   }
-  L.lpr_p = best_lpr(s, lanes_for(L.P), [&](int c) {
+  L.lpr_p = best_lpr(s, solve_lanes<T>(L.P), [&](int c) {
     apply_rect<true, T>(s, L.P, C.x.as<T>(), L.t.as<T>(), c);
   });
 }
