@@ -65,3 +65,42 @@ def test_adam_closed_form_and_descent():
         th, m, v = mlp.adam_step(th, gr, m, v, t, lr=3e-3)
     l1, _ = mlp.loss_and_grad(th, shapes, X, T)
     assert l1 < 0.1 * l0
+
+
+def test_warm_start_features_by_hand():
+    """Eight cells, one removed (4), two pockets {0,1,2,3,5} (pin 0) and
+    {6,7} (pin 6).  Every feature below is worked out by hand from the
+    definitions: the previous increment re-referenced to the cell's own
+    pocket pin over its RMS, the RHS over its RMS, f_l, the volume over the
+    mean volume (RMS and mean over the seven active cells), and the open-face
+    coefficients of the cell, largest first, over their sum.  Cell 1's open
+    faces come in the face list with coefficients 1, 3, 2 and cell 3's with
+    2, 7, so a missing sort or an ascending one shows; the blocked face
+    (1, 4) and the wall face must not count."""
+    owner = np.array([1, 1, 3, 1, 5, 3, 7])
+    neigh = np.array([0, 2, 1, 4, -1, 5, 6])
+    coeff = np.array([1.0, 3.0, 2.0, 5.0, 8.0, 7.0, 4.0])
+    fl = np.array([1.0, 0.5, 1.0, 0.75, 0.0, 1.0, 1.0, 1.0])
+    vol = np.array([1.0, 1.0, 2.0, 2.0, 9.0, 3.0, 4.0, 1.0])
+    dp = np.array([2.0, 5.0, -1.0, 4.0, 99.0, 3.0, 10.0, 13.0])
+    rhs = np.array([1.0, 2.0, -2.0, 0.0, 50.0, -1.0, 3.0, -3.0])
+    pin_of = np.array([0, 0, 0, 0, -1, 0, 6, 6])
+    F, s_dp = mlp.warm_start_features(8, owner, neigh, coeff, fl, vol, dp, rhs, pin_of)
+    # re-referenced increments 0, 3, -3, 2, 1 | 0, 3: sum of squares 32 over 7 cells
+    s = np.sqrt(32.0 / 7.0)
+    assert s_dp == pytest.approx(s, rel=1e-15)
+    expect = np.zeros((7, 10))
+    expect[:, 0] = np.array([0.0, 3.0, -3.0, 2.0, 1.0, 0.0, 3.0]) / s
+    # RHS over the active cells: 1, 2, -2, 0, -1, 3, -3 -> RMS sqrt(28 / 7) = 2
+    expect[:, 1] = [0.5, 1.0, -1.0, 0.0, -0.5, 1.5, -1.5]
+    expect[:, 2] = [1.0, 0.5, 1.0, 0.75, 1.0, 1.0, 1.0]
+    # mean active volume 14 / 7 = 2
+    expect[:, 3] = [0.5, 0.5, 1.0, 1.0, 1.5, 2.0, 0.5]
+    expect[0, 4] = 1.0                              # cell 0: face to 1 only
+    expect[1, 4:7] = [3.0 / 6.0, 2.0 / 6.0, 1.0 / 6.0]  # cell 1: 3, 2, 1
+    expect[2, 4] = 1.0                              # cell 2: face to 1
+    expect[3, 4:6] = [7.0 / 9.0, 2.0 / 9.0]         # cell 3: 7, 2
+    expect[4, 4] = 1.0                              # cell 5: face to 3 (wall ignored)
+    expect[5, 4] = 1.0                              # cell 6: face to 7
+    expect[6, 4] = 1.0                              # cell 7: face to 6
+    assert np.allclose(F, expect, rtol=1e-15, atol=1e-15), F - expect
