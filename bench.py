@@ -213,7 +213,7 @@ def counter_traffic(workload):
         region = text[text.index(begin):text.index(end)]
         if hashlib.sha256(region.encode()).hexdigest() != data["source_sha256"]:
             return None
-        return data[workload]["bytes_per_launch"]
+        return data["workloads"][workload]["bytes_per_launch"]
     except (OSError, KeyError, ValueError):
         return None
 

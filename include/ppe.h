@@ -59,7 +59,8 @@ typedef enum {
 typedef enum { PPE_FP64 = 0, PPE_MIXED = 1 } ppe_precision;
 
 typedef struct {
-  int precision;      /* ppe_precision; PPE_MIXED = FP32 hierarchy + FP64 outer PCG */
+  int precision;      /* ppe_precision; PPE_MIXED = FP32-stored hierarchy, FP64
+                         arithmetic and outer PCG (see ppe_solve) */
   double rtol;        /* relative residual target, default 1e-10 */
   int max_iter;       /* PCG iteration cap, default 500 */
   int cheb_degree;    /* Chebyshev smoother degree per application, default 2 */
@@ -169,8 +170,10 @@ ppe_status ppe_refresh_shift(ppe_solver* s, const double* face_coeff, const doub
 /* Solve A p = b' (Eq. 9 as modified in section 2.4.2) by conjugate gradients
  * preconditioned with one V-cycle per iteration (section 2.5), until the
  * recomputed true residual meets rtol ||b'||.  With PPE_MIXED the V-cycle
- * runs on the FP32 hierarchy and the iteration is flexible CG with one stored
- * direction (alpha = r.p / p.Ap, beta = -z.Ap / p.Ap), all in FP64.
+ * reads FP32 copies of the hierarchy's values (level operators, diagonals,
+ * P, R; the coarsest dense inverse stays FP64) and computes in FP64 on FP64
+ * vectors, so it is one fixed symmetric positive definite preconditioner and
+ * plain CG applies; the outer residual, dots and updates are FP64.
  * rhs[n_cells]: entries of removed cells are ignored, pins are replaced by 0.
  * p[n_cells]: in: initial guess if use_x0 != 0; out: pressure, exactly 0 on
  * removed cells and pins.  stats: host pointer, may be NULL.

@@ -49,8 +49,11 @@ float elapsed_ms(hipEvent_t a, hipEvent_t b) {
 double bytes_per_iteration(const ppe_solver* s) {
   // Algorithmic bytes of one PCG iteration: every matrix entry read once
   // (value + column index), every vector an operator touches read or written
-  // once.  v = 8 bytes per value.
+  // once.  v = 8 bytes per vector value and per value of the outer operator;
+  // vm = bytes per value of the V-cycle's matrices (4 for the FP32 copies of
+  // the mixed mode; the coarsest dense inverse stays FP64).
   const double v = 8.0;
+  const double vm = s->opt.precision == PPE_MIXED ? 4.0 : 8.0;
   double total = 0.0;
   const ppe::Level& L0 = s->levels[0];
   const double n0 = L0.n, off0 = (double)(L0.A.nnz - L0.n);
@@ -60,20 +63,20 @@ double bytes_per_iteration(const ppe_solver* s) {
   for (int l = 0; l < s->nlev; ++l) {
     const ppe::Level& L = s->levels[l];
     const double n = L.n;
-    const double mat = (l == 0) ? off0 * (v + 4) + v * n : (double)L.A.nnz * (v + 4) + 4 * n;
+    const double mat = (l == 0) ? off0 * (vm + 4) + vm * n : (double)L.A.nnz * (vm + 4) + 4 * n;
     if (l == s->nlev - 1) {
-      total += L.dense ? n * n * v + 2 * n * v : 2 * deg * (mat + 6 * v * n);
+      total += L.dense ? n * n * v + 2 * n * v : 2 * deg * (mat + 5 * v * n);
       continue;
     }
     // pre: first step elementwise (b, diag -> d, x) + (deg-1) fused steps;
     // residual; restriction; prolongation; post: deg fused steps
     const double fused = mat + 5 * v * n;  // x_in, b, d -> d, x_out (+diag in mat)
-    total += 4 * v * n + (deg - 1) * fused;
+    total += 3 * v * n + vm * n + (deg - 1) * fused;
     total += mat + 3 * v * n;
     const ppe::Csr& R = L.R;
     const ppe::Csr& P = L.P;
-    total += (double)R.nnz * (v + 4) + 4.0 * R.n + v * n + v * R.n;
-    total += (double)P.nnz * (v + 4) + 4.0 * P.n + v * R.n + 2 * v * n;
+    total += (double)R.nnz * (vm + 4) + 4.0 * R.n + v * n + v * R.n;
+    total += (double)P.nnz * (vm + 4) + 4.0 * P.n + v * R.n + 2 * v * n;
     total += deg * fused;
   }
   return total;

@@ -118,10 +118,9 @@ struct Level {
   DevBuf strong, state, state2, m1, mis_root, agg1, agg_ptr, agg_mem, pt;
   // coarsest level
   bool dense = false;
-  DevBuf Ainv, Ainvf;
-  // V-cycle work vectors (FP64 and FP32 variants)
+  DevBuf Ainv;           // dense inverse, FP64 in both precisions
+  // V-cycle work vectors (FP64 in both precisions)
   DevBuf x, b, r, d, x2, d2, t;
-  DevBuf xf, bf, rf, df, x2f, d2f;
 };
 
 // Device-resident PCG scalars.

@@ -35,24 +35,31 @@ enum Slot : int { P_POW = 0 /* 0, 1 */, P_NSLOTS = 2 };
 // device scalars in s->scal
 enum Scal : int { S_POW = 0, S_N = 2 };
 
+// Matrix values come in type M (FP64, or the FP32 copy of the mixed mode);
+// vectors and all arithmetic are FP64 in both modes, so the V-cycle is one
+// fixed linear operator of the (rounded) hierarchy either way.
+
 // Operand of the matrix product: x_j, or for E_CHEB0 the first Chebyshev
 // iterate c0 b_j / diag_j (the same expression the unfused first step stores).
-template <int EPI, class T>
-__device__ __forceinline__ T operand(int j, const T* __restrict__ x, const T* __restrict__ b,
-                                     const T* __restrict__ diag, T c0) {
-  if (EPI == E_CHEB0) return c0 * (b[j] / diag[j]);
+template <int EPI, class M>
+__device__ __forceinline__ double operand(int j, const double* __restrict__ x,
+                                          const double* __restrict__ b,
+                                          const M* __restrict__ diag, double c0) {
+  if (EPI == E_CHEB0) return c0 * (b[j] / (double)diag[j]);
   return x[j];
 }
 
-template <int EPI, class T>
-__device__ __forceinline__ double epilogue(int i, T ax, const T* __restrict__ x,
-                                           const T* __restrict__ b, const T* __restrict__ diag,
-                                           T* __restrict__ d, T c1, T c2, T scale,
-                                           T* __restrict__ y, T c0 = T(0)) {
+template <int EPI, class M>
+__device__ __forceinline__ double epilogue(int i, double ax, const double* __restrict__ x,
+                                           const double* __restrict__ b,
+                                           const M* __restrict__ diag, double* __restrict__ d,
+                                           double c1, double c2, double scale,
+                                           double* __restrict__ y, double c0 = 0.0) {
   if (EPI == E_CHEB0) {
-    const T x1 = c0 * (b[i] / diag[i]);
-    const T r = (b[i] - ax) / diag[i];
-    const T dn = c1 * x1 + c2 * r;
+    const double di = (double)diag[i];
+    const double x1 = c0 * (b[i] / di);
+    const double r = (b[i] - ax) / di;
+    const double dn = c1 * x1 + c2 * r;
     d[i] = dn;
     y[i] = x1 + dn;
     return 0.0;
@@ -63,18 +70,18 @@ __device__ __forceinline__ double epilogue(int i, T ax, const T* __restrict__ x,
     y[i] = b[i] - ax;
     return 0.0;
   } else if (EPI == E_CHEB) {
-    const T r = (b[i] - ax) / diag[i];
-    const T dn = (c1 == T(0) ? T(0) : c1 * d[i]) + c2 * r;
+    const double r = (b[i] - ax) / (double)diag[i];
+    const double dn = (c1 == 0.0 ? 0.0 : c1 * d[i]) + c2 * r;
     d[i] = dn;
     y[i] = x[i] + dn;
     return 0.0;
   } else if (EPI == E_DOT) {
     y[i] = ax;
-    return (double)x[i] * (double)ax;
+    return x[i] * ax;
   } else {
-    const T v = (ax / diag[i]) * scale;
+    const double v = (ax / (double)diag[i]) * scale;
     y[i] = v;
-    return (double)v * (double)v;
+    return v * v;
   }
 }
 
@@ -82,47 +89,52 @@ __device__ __forceinline__ double epilogue(int i, T ax, const T* __restrict__ x,
 // s in slot order.  With WM > 0 (W <= WM) the slot loop is unrolled, so every
 // column index, and then every gathered operand, is requested before the
 // first one is used.
-template <int EPI, int WM, class T>
-__device__ __forceinline__ T ell_row(T s, int i, int n, int W, const int* __restrict__ ecol,
-                                     const T* __restrict__ eval, const T* __restrict__ x,
-                                     const T* __restrict__ b, const T* __restrict__ diag, T c0) {
+template <int EPI, int WM, class M>
+__device__ __forceinline__ double ell_row(double s, int i, int n, int W,
+                                          const int* __restrict__ ecol,
+                                          const M* __restrict__ eval,
+                                          const double* __restrict__ x,
+                                          const double* __restrict__ b,
+                                          const M* __restrict__ diag, double c0) {
   if (WM > 0) {
     int col[WM > 0 ? WM : 1];
-    T v[WM > 0 ? WM : 1];
+    M v[WM > 0 ? WM : 1];
 #pragma unroll
     for (int k = 0; k < WM; ++k) {
       const size_t e = (size_t)k * n + i;
       col[k] = k < W ? ecol[e] : i;
-      v[k] = k < W ? eval[e] : T(0);
+      v[k] = k < W ? eval[e] : M(0);
     }
-    T g[WM > 0 ? WM : 1];
+    double g[WM > 0 ? WM : 1];
 #pragma unroll
-    for (int k = 0; k < WM; ++k) g[k] = operand<EPI, T>(col[k], x, b, diag, c0);
+    for (int k = 0; k < WM; ++k) g[k] = operand<EPI, M>(col[k], x, b, diag, c0);
 #pragma unroll
     for (int k = 0; k < WM; ++k)
-      if (k < W) s = s + v[k] * g[k];
+      if (k < W) s = s + (double)v[k] * g[k];
     return s;
   }
   for (int k = 0; k < W; ++k) {
     const size_t e = (size_t)k * n + i;
-    s = s + eval[e] * operand<EPI, T>(ecol[e], x, b, diag, c0);
+    s = s + (double)eval[e] * operand<EPI, M>(ecol[e], x, b, diag, c0);
   }
   return s;
 }
 
 // ---- finest level: ELL, one thread per row (grid-stride)
-template <int EPI, class T, int WM>
+template <int EPI, class M, int WM>
 __global__ void __launch_bounds__(kBlock) k_ell(int n, int W, const int* __restrict__ ecol,
-                                                const T* __restrict__ eval,
-                                                const T* __restrict__ diag, const T* __restrict__ x,
-                                                const T* __restrict__ b, T* __restrict__ d, T c1,
-                                                T c2, T* __restrict__ y,
-                                                double* __restrict__ partials, T c0) {
+                                                const M* __restrict__ eval,
+                                                const M* __restrict__ diag,
+                                                const double* __restrict__ x,
+                                                const double* __restrict__ b,
+                                                double* __restrict__ d, double c1, double c2,
+                                                double* __restrict__ y,
+                                                double* __restrict__ partials, double c0) {
   double dot = 0.0;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    T s = diag[i] * operand<EPI, T>(i, x, b, diag, c0);
-    s = ell_row<EPI, WM, T>(s, i, n, W, ecol, eval, x, b, diag, c0);
-    dot += epilogue<EPI, T>(i, s, x, b, diag, d, c1, c2, T(1), y, c0);
+    double s = (double)diag[i] * operand<EPI, M>(i, x, b, diag, c0);
+    s = ell_row<EPI, WM, M>(s, i, n, W, ecol, eval, x, b, diag, c0);
+    dot += epilogue<EPI, M>(i, s, x, b, diag, d, c1, c2, 1.0, y, c0);
   }
   if (EPI == E_DOT) {
     double v[1] = {dot};
@@ -137,24 +149,25 @@ __global__ void __launch_bounds__(kBlock) k_ell(int n, int W, const int* __restr
 // CSR row of v[k] op(ci[k]), added in that order; the loads of U entries are
 // requested before the first is used (the order of the sum is that of the
 // plain loop).
-template <int LPR, int U, class T, class Op>
-__device__ __forceinline__ T row_sum(T s, int k0, int k1, int lane, const int* __restrict__ ci,
-                                     const T* __restrict__ v, Op op) {
+template <int LPR, int U, class M, class Op>
+__device__ __forceinline__ double row_sum(double s, int k0, int k1, int lane,
+                                          const int* __restrict__ ci, const M* __restrict__ v,
+                                          Op op) {
   for (int k = k0 + lane; k < k1; k += LPR * U) {
     int c[U];
-    T w[U];
+    M w[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int kk = k + u * LPR;
       c[u] = kk < k1 ? ci[kk] : -1;
-      w[u] = kk < k1 ? v[kk] : T(0);
+      w[u] = kk < k1 ? v[kk] : M(0);
     }
-    T g[U];
+    double g[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) g[u] = c[u] >= 0 ? op(c[u]) : T(0);
+    for (int u = 0; u < U; ++u) g[u] = c[u] >= 0 ? op(c[u]) : 0.0;
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (c[u] >= 0) s = s + w[u] * g[u];
+      if (c[u] >= 0) s = s + (double)w[u] * g[u];
   }
   return s;
 }
@@ -164,42 +177,42 @@ constexpr int kRowU = 4;
 // before the row's entries (so they are not a dependent load after the
 // group's shuffles), and the epilogue on them: the same arithmetic as
 // epilogue().
-template <class T>
 struct RowOwn {
-  T x, b, diag, d;
+  double x, b, diag, d;
 };
 
-template <int EPI, class T>
-__device__ __forceinline__ RowOwn<T> row_own(int i, const T* __restrict__ x,
-                                             const T* __restrict__ b, const T* __restrict__ diag,
-                                             const T* __restrict__ d, T c1) {
-  RowOwn<T> o{T(0), T(0), T(1), T(0)};
+template <int EPI, class M>
+__device__ __forceinline__ RowOwn row_own(int i, const double* __restrict__ x,
+                                          const double* __restrict__ b,
+                                          const M* __restrict__ diag,
+                                          const double* __restrict__ d, double c1) {
+  RowOwn o{0.0, 0.0, 1.0, 0.0};
   if (EPI == E_CHEB0) {
     o.b = b[i];
-    o.diag = diag[i];
+    o.diag = (double)diag[i];
   } else if (EPI == E_RESID) {
     o.b = b[i];
   } else if (EPI == E_CHEB) {
     o.b = b[i];
-    o.diag = diag[i];
+    o.diag = (double)diag[i];
     o.x = x[i];
-    if (c1 != T(0)) o.d = d[i];
+    if (c1 != 0.0) o.d = d[i];
   } else if (EPI == E_DOT) {
     o.x = x[i];
   } else if (EPI == E_POWER) {
-    o.diag = diag[i];
+    o.diag = (double)diag[i];
   }
   return o;
 }
 
-template <int EPI, class T>
-__device__ __forceinline__ double epilogue_own(int i, T ax, const RowOwn<T>& o,
-                                               T* __restrict__ d, T c1, T c2, T scale,
-                                               T* __restrict__ y, T c0) {
+template <int EPI>
+__device__ __forceinline__ double epilogue_own(int i, double ax, const RowOwn& o,
+                                               double* __restrict__ d, double c1, double c2,
+                                               double scale, double* __restrict__ y, double c0) {
   if (EPI == E_CHEB0) {
-    const T x1 = c0 * (o.b / o.diag);
-    const T r = (o.b - ax) / o.diag;
-    const T dn = c1 * x1 + c2 * r;
+    const double x1 = c0 * (o.b / o.diag);
+    const double r = (o.b - ax) / o.diag;
+    const double dn = c1 * x1 + c2 * r;
     d[i] = dn;
     y[i] = x1 + dn;
     return 0.0;
@@ -210,30 +223,32 @@ __device__ __forceinline__ double epilogue_own(int i, T ax, const RowOwn<T>& o,
     y[i] = o.b - ax;
     return 0.0;
   } else if (EPI == E_CHEB) {
-    const T r = (o.b - ax) / o.diag;
-    const T dn = (c1 == T(0) ? T(0) : c1 * o.d) + c2 * r;
+    const double r = (o.b - ax) / o.diag;
+    const double dn = (c1 == 0.0 ? 0.0 : c1 * o.d) + c2 * r;
     d[i] = dn;
     y[i] = o.x + dn;
     return 0.0;
   } else if (EPI == E_DOT) {
     y[i] = ax;
-    return (double)o.x * (double)ax;
+    return o.x * ax;
   } else {
-    const T v = (ax / o.diag) * scale;
+    const double v = (ax / o.diag) * scale;
     y[i] = v;
-    return (double)v * (double)v;
+    return v * v;
   }
 }
-template <int EPI, int LPR, class T>
+template <int EPI, int LPR, class M>
 __global__ void __launch_bounds__(kBlock) k_csr(int n, const int* __restrict__ rp,
                                                 const int* __restrict__ ci,
-                                                const T* __restrict__ v, const T* __restrict__ diag,
-                                                const T* __restrict__ x, const T* __restrict__ b,
-                                                T* __restrict__ d, T c1, T c2, T* __restrict__ y,
+                                                const M* __restrict__ v, const M* __restrict__ diag,
+                                                const double* __restrict__ x,
+                                                const double* __restrict__ b,
+                                                double* __restrict__ d, double c1, double c2,
+                                                double* __restrict__ y,
                                                 const double* __restrict__ prevp, int gprev,
-                                                double* __restrict__ partials, T c0) {
-  T scale = T(1);
-  if (EPI == E_POWER) scale = T(1.0 / sqrt(sum_partials<kBlock>(prevp, gprev)));
+                                                double* __restrict__ partials, double c0) {
+  double scale = 1.0;
+  if (EPI == E_POWER) scale = 1.0 / sqrt(sum_partials<kBlock>(prevp, gprev));
   const int lane = threadIdx.x % LPR;
   const int groups = gridDim.x * (kBlock / LPR);
   const int my = (blockIdx.x * kBlock + threadIdx.x) / LPR;
@@ -241,16 +256,16 @@ __global__ void __launch_bounds__(kBlock) k_csr(int n, const int* __restrict__ r
   double dot = 0.0;
   for (int t = 0; t < trips; ++t) {
     const int g = t * groups + my;
-    T s = T(0);
-    RowOwn<T> own{T(0), T(0), T(1), T(0)};
+    double s = 0.0;
+    RowOwn own{0.0, 0.0, 1.0, 0.0};
     if (g < n) {
-      if (lane == 0) own = row_own<EPI, T>(g, x, b, diag, d, c1);
-      s = row_sum<LPR, kRowU, T>(s, rp[g], rp[g + 1], lane, ci, v,
-                                 [&](int j) { return operand<EPI, T>(j, x, b, diag, c0); });
+      if (lane == 0) own = row_own<EPI, M>(g, x, b, diag, d, c1);
+      s = row_sum<LPR, kRowU, M>(s, rp[g], rp[g + 1], lane, ci, v,
+                                 [&](int j) { return operand<EPI, M>(j, x, b, diag, c0); });
     }
 #pragma unroll
     for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_down(s, o, LPR);
-    if (g < n && lane == 0) dot += epilogue_own<EPI, T>(g, s, own, d, c1, c2, scale, y, c0);
+    if (g < n && lane == 0) dot += epilogue_own<EPI>(g, s, own, d, c1, c2, scale, y, c0);
   }
   if (EPI == E_DOT || EPI == E_POWER) {
     double vv[1] = {dot};
@@ -258,18 +273,19 @@ __global__ void __launch_bounds__(kBlock) k_csr(int n, const int* __restrict__ r
   }
 }
 
-// y (+)= M x for a rectangular CSR (prolongation adds into y).
-template <int LPR, bool ADD, class T>
+// y (+)= P x for a rectangular CSR (prolongation adds into y).
+template <int LPR, bool ADD, class M>
 __global__ void __launch_bounds__(kBlock) k_csr_rect(int n, const int* __restrict__ rp,
                                                      const int* __restrict__ ci,
-                                                     const T* __restrict__ v,
-                                                     const T* __restrict__ x, T* __restrict__ y) {
+                                                     const M* __restrict__ v,
+                                                     const double* __restrict__ x,
+                                                     double* __restrict__ y) {
   const int g = (blockIdx.x * kBlock + threadIdx.x) / LPR;
   const int lane = threadIdx.x % LPR;
-  T s = T(0), y0 = T(0);
+  double s = 0.0, y0 = 0.0;
   if (g < n) {
     if (ADD && lane == 0) y0 = y[g];  // requested before the row's entries
-    s = row_sum<LPR, kRowU, T>(s, rp[g], rp[g + 1], lane, ci, v, [&](int j) { return x[j]; });
+    s = row_sum<LPR, kRowU, M>(s, rp[g], rp[g + 1], lane, ci, v, [&](int j) { return x[j]; });
   }
 #pragma unroll
   for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_down(s, o, LPR);
@@ -287,42 +303,43 @@ constexpr int kFuseU = 4;  // CSR entries per lane requested before any is used
 
 // Entries k0 + lane + u LPR (u < U) of a CSR row ending at k1: columns (-1
 // past the end) and values.
-template <int LPR, int U, class T>
+template <int LPR, int U, class M>
 __device__ __forceinline__ void chunk_load(int k0, int k1, int lane, const int* __restrict__ ci,
-                                           const T* __restrict__ v, int (&c)[U], T (&w)[U]) {
+                                           const M* __restrict__ v, int (&c)[U], M (&w)[U]) {
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int k = k0 + lane + u * LPR;
     c[u] = k < k1 ? ci[k] : -1;
-    w[u] = k < k1 ? v[k] : T(0);
+    w[u] = k < k1 ? v[k] : M(0);
   }
 }
 
 // s + sum of w[u] x[c[u]] over the loaded entries, every gather requested
 // before the first product.
-template <int U, class T>
-__device__ __forceinline__ T chunk_sum(T s, const int (&c)[U], const T (&w)[U],
-                                       const T* __restrict__ x) {
-  T g[U];
+template <int U, class M>
+__device__ __forceinline__ double chunk_sum(double s, const int (&c)[U], const M (&w)[U],
+                                            const double* __restrict__ x) {
+  double g[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) g[u] = c[u] >= 0 ? x[c[u]] : T(0);
+  for (int u = 0; u < U; ++u) g[u] = c[u] >= 0 ? x[c[u]] : 0.0;
 #pragma unroll
   for (int u = 0; u < U; ++u)
-    if (c[u] >= 0) s = s + w[u] * g[u];
+    if (c[u] >= 0) s = s + (double)w[u] * g[u];
   return s;
 }
 
 // The lane's entries of a row past its first chunk (rows longer than LPR U).
-template <int LPR, int U, class T>
-__device__ __forceinline__ T row_rest(T s, int k0, int k1, int lane, const int* __restrict__ ci,
-                                      const T* __restrict__ v, const T* __restrict__ x) {
-  for (int k = k0 + lane + LPR * U; k < k1; k += LPR) s = s + v[k] * x[ci[k]];
+template <int LPR, int U, class M>
+__device__ __forceinline__ double row_rest(double s, int k0, int k1, int lane,
+                                           const int* __restrict__ ci, const M* __restrict__ v,
+                                           const double* __restrict__ x) {
+  for (int k = k0 + lane + LPR * U; k < k1; k += LPR) s = s + (double)v[k] * x[ci[k]];
   return s;
 }
 
 // Sums of the LPR lanes of a row group, left in lane 0.
-template <int LPR, class T>
-__device__ __forceinline__ void group_sum2(T& a, T& b) {
+template <int LPR>
+__device__ __forceinline__ void group_sum2(double& a, double& b) {
 #pragma unroll
   for (int o = LPR / 2; o > 0; o >>= 1) {
     a += __shfl_down(a, o, LPR);
@@ -331,40 +348,40 @@ __device__ __forceinline__ void group_sum2(T& a, T& b) {
 }
 
 // A, P and AP all CSR (A's rows hold the diagonal); LPR lanes per row.
-template <class T, int LPR>
+template <class M, int LPR>
 __global__ void __launch_bounds__(kBlock) k_csr_prolong_cheb(
-    int n, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ v,
-    const T* __restrict__ diag, const int* __restrict__ prp, const int* __restrict__ pci,
-    const T* __restrict__ pv, const int* __restrict__ arp, const int* __restrict__ aci,
-    const T* __restrict__ av, const T* __restrict__ e, const T* __restrict__ x1,
-    const T* __restrict__ b, T* __restrict__ d, T c2, T* __restrict__ y) {
+    int n, const int* __restrict__ rp, const int* __restrict__ ci, const M* __restrict__ v,
+    const M* __restrict__ diag, const int* __restrict__ prp, const int* __restrict__ pci,
+    const M* __restrict__ pv, const int* __restrict__ arp, const int* __restrict__ aci,
+    const M* __restrict__ av, const double* __restrict__ e, const double* __restrict__ x1,
+    const double* __restrict__ b, double* __restrict__ d, double c2, double* __restrict__ y) {
   const int i = (blockIdx.x * kBlock + threadIdx.x) / LPR;
   const int lane = threadIdx.x % LPR;
-  T ax = T(0), pe = T(0), bi = T(0), di = T(1), xi = T(0);
+  double ax = 0.0, pe = 0.0, bi = 0.0, di = 1.0, xi = 0.0;
   if (i < n) {
     if (lane == 0) {
       bi = b[i];
-      di = diag[i];
+      di = (double)diag[i];
       xi = x1[i];
     }
     const int r0 = rp[i], r1 = rp[i + 1], p0 = prp[i], p1 = prp[i + 1], a0 = arp[i],
               a1 = arp[i + 1];
     int cc[kFuseU], pc[kFuseU], ac[kFuseU];
-    T cw[kFuseU], pw[kFuseU], aw[kFuseU];
-    chunk_load<LPR, kFuseU, T>(r0, r1, lane, ci, v, cc, cw);
-    chunk_load<LPR, kFuseU, T>(p0, p1, lane, pci, pv, pc, pw);
-    chunk_load<LPR, kFuseU, T>(a0, a1, lane, aci, av, ac, aw);
-    ax = chunk_sum<kFuseU, T>(ax, cc, cw, x1);
-    ax = chunk_sum<kFuseU, T>(ax, ac, aw, e);
-    pe = chunk_sum<kFuseU, T>(pe, pc, pw, e);
-    ax = row_rest<LPR, kFuseU, T>(ax, r0, r1, lane, ci, v, x1);
-    ax = row_rest<LPR, kFuseU, T>(ax, a0, a1, lane, aci, av, e);
-    pe = row_rest<LPR, kFuseU, T>(pe, p0, p1, lane, pci, pv, e);
+    M cw[kFuseU], pw[kFuseU], aw[kFuseU];
+    chunk_load<LPR, kFuseU, M>(r0, r1, lane, ci, v, cc, cw);
+    chunk_load<LPR, kFuseU, M>(p0, p1, lane, pci, pv, pc, pw);
+    chunk_load<LPR, kFuseU, M>(a0, a1, lane, aci, av, ac, aw);
+    ax = chunk_sum<kFuseU, M>(ax, cc, cw, x1);
+    ax = chunk_sum<kFuseU, M>(ax, ac, aw, e);
+    pe = chunk_sum<kFuseU, M>(pe, pc, pw, e);
+    ax = row_rest<LPR, kFuseU, M>(ax, r0, r1, lane, ci, v, x1);
+    ax = row_rest<LPR, kFuseU, M>(ax, a0, a1, lane, aci, av, e);
+    pe = row_rest<LPR, kFuseU, M>(pe, p0, p1, lane, pci, pv, e);
   }
-  group_sum2<LPR, T>(ax, pe);
+  group_sum2<LPR>(ax, pe);
   if (i < n && lane == 0) {
-    const T r = (bi - ax) / di;
-    const T dn = c2 * r;
+    const double r = (bi - ax) / di;
+    const double dn = c2 * r;
     d[i] = dn;
     y[i] = (xi + pe) + dn;
   }
@@ -372,24 +389,24 @@ __global__ void __launch_bounds__(kBlock) k_csr_prolong_cheb(
 // ---- end of the fused prolongation
 
 // First Chebyshev step from a zero guess: d = b / (theta diag); x = d.
-template <class T>
-__global__ void k_cheb_first(int n, const T* __restrict__ b, const T* __restrict__ diag,
-                             T inv_theta, T* __restrict__ d, T* __restrict__ x) {
+template <class M>
+__global__ void k_cheb_first(int n, const double* __restrict__ b, const M* __restrict__ diag,
+                             double inv_theta, double* __restrict__ d, double* __restrict__ x) {
   int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  T v = inv_theta * (b[i] / diag[i]);
+  double v = inv_theta * (b[i] / (double)diag[i]);
   d[i] = v;
   x[i] = v;
 }
 
-// Dense coarsest solve x = Ainv b: one wave per row, lanes over columns.
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_dense_gemv(int n, const T* __restrict__ Ainv,
-                                                       const T* __restrict__ b,
-                                                       T* __restrict__ x) {
+// Dense coarsest solve x = Ainv b (FP64 in both modes): one wave per row,
+// lanes over columns.
+__global__ void __launch_bounds__(kBlock) k_dense_gemv(int n, const double* __restrict__ Ainv,
+                                                       const double* __restrict__ b,
+                                                       double* __restrict__ x) {
   const int i = (blockIdx.x * kBlock + threadIdx.x) / kWave;
   const int lane = threadIdx.x % kWave;
-  T s = T(0);
+  double s = 0.0;
   if (i < n)
     for (int j = lane; j < n; j += kWave) s = s + Ainv[(size_t)i * n + j] * b[j];
   s = wave_sum(s);
@@ -426,8 +443,7 @@ __device__ __forceinline__ double seg_sum(const double* __restrict__ part, const
 // per-segment scalar arrays (each n_seg doubles) in s->seg_sc
 enum SegScal : int { SS_BB = 0, SS_TOL2 = 1, SS_RZ0 = 2, SS_RZ1 = 3, SS_RES = 4, SS_N = 5 };
 // tile-partial arrays (each n_tiles doubles) in s->tpart
-// (pairs written by one kernel are adjacent: T_PQ/T_RP and T_RZ/T_ZQ)
-enum TilePart : int { T_BB = 0, T_RR = 1, T_PQ = 2, T_RP = 3, T_RZ = 4, T_ZQ = 5, T_RT = 6, T_N = 7 };
+enum TilePart : int { T_BB = 0, T_RR = 1, T_PQ = 2, T_RZ = 3, T_RT = 4, T_N = 5 };
 
 __global__ void __launch_bounds__(kBlock) k_gather_rhs_t(Tiles T, const int* __restrict__ perm,
                                                          const int* __restrict__ comp,
@@ -455,68 +471,48 @@ __global__ void __launch_bounds__(kBlock) k_norm2_t(Tiles T, const double* __res
   write_partials<kBlock, 1>(sv, part);
 }
 
-// tile partials of r.z and (flexible) z.q
-__global__ void __launch_bounds__(kBlock) k_dot2_t(Tiles T, const double* __restrict__ r,
-                                                   const double* __restrict__ z,
-                                                   const double* __restrict__ q,
-                                                   double* __restrict__ part) {
+// tile partials of r.z
+__global__ void __launch_bounds__(kBlock) k_dot_t(Tiles T, const double* __restrict__ r,
+                                                  const double* __restrict__ z,
+                                                  double* __restrict__ part) {
   const int t = blockIdx.x;
-  double sv[2] = {0.0, 0.0};
-  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) {
-    sv[0] += r[i] * z[i];
-    if (q) sv[1] += z[i] * q[i];
-  }
-  write_partials<kBlock, 2>(sv, part);
+  double acc = 0.0;
+  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) acc += r[i] * z[i];
+  double sv[1] = {acc};
+  write_partials<kBlock, 1>(sv, part);
 }
 
-// The last smoothing step of a level-0 V-cycle fused with the PCG dots that
-// follow it: the E_CHEB step y = x + d over the tile's rows, then tile
-// partials of b.y and (flexible) y.q, where b is the PCG residual the V-cycle
-// was applied to and y the preconditioned residual.  Same arithmetic and
-// order as the separate kernels.
-template <int WM>
+// The last smoothing step of a level-0 V-cycle fused with the PCG dot that
+// follows it: the E_CHEB step y = x + d over the tile's rows, then tile
+// partials of b.y, where b is the PCG residual the V-cycle was applied to and
+// y the preconditioned residual.  Same arithmetic and order as the separate
+// kernels.
+template <int WM, class M>
 __global__ void __launch_bounds__(kBlock) k_ell_cheb_dot_t(
-    Tiles T, int n, int W, const int* __restrict__ ecol, const double* __restrict__ eval,
-    const double* __restrict__ diag, const double* __restrict__ x, const double* __restrict__ b,
+    Tiles T, int n, int W, const int* __restrict__ ecol, const M* __restrict__ eval,
+    const M* __restrict__ diag, const double* __restrict__ x, const double* __restrict__ b,
     double* __restrict__ d, double c1, double c2, double* __restrict__ y,
-    const double* __restrict__ qv, double* __restrict__ part) {
+    double* __restrict__ part) {
   const int t = blockIdx.x;
-  double sv[2] = {0.0, 0.0};
+  double acc = 0.0;
   for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) {
-    double s = diag[i] * x[i];
-    s = ell_row<E_CHEB, WM, double>(s, i, n, W, ecol, eval, x, b, diag, 0.0);
-    const double r = (b[i] - s) / diag[i];
+    const double di = (double)diag[i];
+    double s = di * x[i];
+    s = ell_row<E_CHEB, WM, M>(s, i, n, W, ecol, eval, x, b, diag, 0.0);
+    const double r = (b[i] - s) / di;
     const double dn = (c1 == 0.0 ? 0.0 : c1 * d[i]) + c2 * r;
     d[i] = dn;
     const double yi = x[i] + dn;
     y[i] = yi;
-    sv[0] += b[i] * yi;
-    if (qv) sv[1] += yi * qv[i];
+    acc += b[i] * yi;
   }
-  write_partials<kBlock, 2>(sv, part);
+  double sv[1] = {acc};
+  write_partials<kBlock, 1>(sv, part);
 }
 
-// Mixed precision: z = (double) z32 over the tile's rows with the PCG dots
-// r.z and (flexible) z.q as tile partials.
-__global__ void __launch_bounds__(kBlock) k_cast_dot_t(Tiles T, const float* __restrict__ zf,
-                                                       const double* __restrict__ r,
-                                                       const double* __restrict__ qv,
-                                                       double* __restrict__ z,
-                                                       double* __restrict__ part) {
-  const int t = blockIdx.x;
-  double sv[2] = {0.0, 0.0};
-  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) {
-    const double v = (double)zf[i];
-    z[i] = v;
-    sv[0] += r[i] * v;
-    if (qv) sv[1] += v * qv[i];
-  }
-  write_partials<kBlock, 2>(sv, part);
-}
-
-// q = A p on the finest (ELL) level over the tile's rows; tile partials of
-// p.q and (RP: flexible iteration) r.p
-template <int WM, bool RP>
+// q = A p on the finest (ELL) level over the tile's rows (the outer operator,
+// FP64 in both modes); tile partials of p.q
+template <int WM>
 __global__ void __launch_bounds__(kBlock) k_ell_dot_t(Tiles T, int n, int W,
                                                       const int* __restrict__ ecol,
                                                       const double* __restrict__ eval,
@@ -524,26 +520,19 @@ __global__ void __launch_bounds__(kBlock) k_ell_dot_t(Tiles T, int n, int W,
                                                       const int* __restrict__ done,
                                                       const double* __restrict__ p,
                                                       double* __restrict__ q,
-                                                      const double* __restrict__ r,
                                                       double* __restrict__ part) {
   const int t = blockIdx.x;
-  double acc = 0.0, arp = 0.0;
+  double acc = 0.0;
   if (!done[T.seg[t]]) {
     for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) {
       double s = diag[i] * p[i];
       s = ell_row<E_SPMV, WM, double>(s, i, n, W, ecol, eval, p, nullptr, diag, 0.0);
       q[i] = s;
       acc += p[i] * s;
-      if (RP) arp += r[i] * p[i];
     }
   }
-  if (RP) {
-    double sv[2] = {acc, arp};
-    write_partials<kBlock, 2>(sv, part);
-  } else {
-    double sv[1] = {acc};
-    write_partials<kBlock, 1>(sv, part);
-  }
+  double sv[1] = {acc};
+  write_partials<kBlock, 1>(sv, part);
 }
 
 // Per segment (one block each): bb, tolerance, initial convergence; counts
@@ -591,9 +580,7 @@ __global__ void __launch_bounds__(kBlock) k_init_p_t(Tiles T, int ns, const int*
   for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) p[i] = z[i];
 }
 
-// alpha_q = rz_q / (p.q)_q, or (flexible) (r.p)_q / (p.q)_q, the exact line
-// search whatever the preconditioner; x += alpha p; r -= alpha q; tile
-// partial of r.r
+// alpha_q = rz_q / (p.q)_q; x += alpha p; r -= alpha q; tile partial of r.r
 __global__ void __launch_bounds__(kBlock) k_update_xr_t(Tiles T, const int* __restrict__ done,
                                                         const double* __restrict__ rz,
                                                         const double* __restrict__ part_pq,
@@ -603,8 +590,7 @@ __global__ void __launch_bounds__(kBlock) k_update_xr_t(Tiles T, const int* __re
                                                         double* __restrict__ r,
                                                         double* __restrict__ part,
                                                         int* __restrict__ active,
-                                                        int* __restrict__ err, int nt,
-                                                        int flexible) {
+                                                        int* __restrict__ err) {
   const int t = blockIdx.x, q = T.seg[t];
   if (t == 0 && threadIdx.x == 0) *active = 0;  // counted again by k_update_p_t
   // the thread's first row, requested before the segment's sums
@@ -618,18 +604,8 @@ __global__ void __launch_bounds__(kBlock) k_update_xr_t(Tiles T, const int* __re
   }
   double acc = 0.0;
   if (!done[q]) {
-    double pq, num;
-    if (flexible) {
-      const int g0 = T.tp[q];
-      const double* parts[2] = {part_pq + g0, part_pq + nt + g0};
-      double sums[2];
-      sum_partials_n<kBlock, 2>(parts, T.tp[q + 1] - g0, sums);
-      pq = sums[0];
-      num = sums[1];
-    } else {
-      pq = seg_sum(part_pq, T, q);
-      num = rz[q];
-    }
+    const double pq = seg_sum(part_pq, T, q);
+    const double num = rz[q];
     if (!(pq > 0.0) || !(num > 0.0)) {
       if (threadIdx.x == 0) atomicOr(err, 1);
     } else {
@@ -652,15 +628,13 @@ __global__ void __launch_bounds__(kBlock) k_update_xr_t(Tiles T, const int* __re
 // of a segment adds the same partials in the same order, so all of them take
 // the same decision, and a segment that converged (or broke down) keeps its
 // p.  Otherwise (first direction after a restart) restart[q] forces beta 0.
-// Then beta_q = r.z / rz_prev, or (flexible) -(z.q) / (p.q), which makes the
-// new direction A-orthogonal to the previous one whatever the preconditioner;
-// p = z + beta p; counts the segments still running.
+// Then beta_q = r.z / rz_prev; p = z + beta p; counts the segments still
+// running.
 __global__ void __launch_bounds__(kBlock) k_update_p_t(
-    Tiles T, int nt, int ns, int test, int* __restrict__ done, int* __restrict__ restart,
+    Tiles T, int ns, int test, int* __restrict__ done, int* __restrict__ restart,
     const double* __restrict__ part_rr, const double* __restrict__ sc, int* __restrict__ iters,
     int* __restrict__ active, const double* __restrict__ part_rz,
-    const double* __restrict__ part_pq, int flexible, const double* __restrict__ rz_prev,
-    double* __restrict__ rz_next,
+    const double* __restrict__ rz_prev, double* __restrict__ rz_next,
     const double* __restrict__ z, double* __restrict__ p, int* __restrict__ err) {
   const int t = blockIdx.x, q = T.seg[t];
   // the thread's first row, requested before the segment's sums
@@ -672,20 +646,12 @@ __global__ void __launch_bounds__(kBlock) k_update_p_t(
   }
   if (done[q]) return;
   const bool lead = t == T.tp[q] && threadIdx.x == 0;
-  // every sum this block may need, in one pass over the segment's partials:
-  // r.r, r.z and (flexible) z.q and p.q
+  // both sums this block may need, r.r and r.z, in one pass over the
+  // segment's partials
   const int g0 = T.tp[q], G = T.tp[q + 1] - g0;
-  double sums[4] = {0.0, 0.0, 0.0, 0.0};
-  if (flexible) {
-    const double* parts[4] = {part_rr + g0, part_rz + g0, part_rz + nt + g0, part_pq + g0};
-    sum_partials_n<kBlock, 4>(parts, G, sums);
-  } else {
-    const double* parts[2] = {part_rr + g0, part_rz + g0};
-    double two[2];
-    sum_partials_n<kBlock, 2>(parts, G, two);
-    sums[0] = two[0];
-    sums[1] = two[1];
-  }
+  double sums[2];
+  const double* parts[2] = {part_rr + g0, part_rz + g0};
+  sum_partials_n<kBlock, 2>(parts, G, sums);
   if (test) {
     const double rr = sums[0];
     const bool bad = !(rr == rr) || rr > 1.7976931348623157e308;
@@ -701,12 +667,7 @@ __global__ void __launch_bounds__(kBlock) k_update_p_t(
   }
   const double rzn = sums[1];
   double beta = 0.0;
-  if (!(!test && restart[q])) {
-    if (flexible)
-      beta = -sums[2] / sums[3];
-    else
-      beta = rzn / rz_prev[q];
-  }
+  if (!(!test && restart[q])) beta = rzn / rz_prev[q];
   if (lead) {
     rz_next[q] = rzn;
     if (!(rzn > 0.0)) atomicOr(err, 4);
@@ -800,45 +761,37 @@ constexpr size_t kProfPairs = 256;
     else { LAUNCH(0); }                          \
   } while (0)
 
-// Matrix and diagonal arrays of a level in value type T (FP32 copies exist
-// when the solver runs the mixed-precision V-cycle).
-template <class T> struct LevelData;
+// Matrix and diagonal arrays of a level in value type M (the FP32 copies
+// exist when the solver runs the mixed-precision V-cycle).
+template <class M> struct LevelData;
 template <> struct LevelData<double> {
   static const double* ell(const Level& L) { return L.ell_val.as<double>(); }
   static const double* diag(const Level& L) { return L.diag.as<double>(); }
   static const double* val(const Csr& A) { return A.v(); }
-  static const double* ainv(const Level& L) { return L.Ainv.as<double>(); }
 };
 template <> struct LevelData<float> {
   static const float* ell(const Level& L) { return L.ell_valf.as<float>(); }
   static const float* diag(const Level& L) { return L.diagf.as<float>(); }
   static const float* val(const Csr& A) { return A.vf(); }
-  static const float* ainv(const Level& L) { return L.Ainvf.as<float>(); }
 };
 
-// Lanes per row of the solve's CSR kernels by default in value type T.  FP64:
-// the fewest (a power of two, 4 to 64) that reach half the mean row length,
-// each lane then taking about two entries whose loads are requested
-// together.  The FP32 V-cycle of the mixed mode keeps lanes_for (one entry
-// per lane): its order of summation under the other rule left a 32^3 mixed
-// solve at the residual bar with the error past its bar, as the FP32 fusion
-// did.
-template <class T>
+// Lanes per row of the solve's CSR kernels by default: the fewest (a power of
+// two, 4 to 64) that reach half the mean row length, each lane then taking
+// about two entries whose loads are requested together.
 int solve_lanes(const Csr& M) {
-  if (!std::is_same<T, double>::value) return lanes_for(M);
   const double mean = M.n ? (double)M.nnz / M.n : 1.0;
   int lpr = 4;
   while (lpr < 64 && 2 * lpr < mean) lpr *= 2;
   return lpr;
 }
 
-// Apply the level operator with epilogue EPI in value type T.  Dot/power
-// epilogues run on a capped grid and write partials to `partials`; returns
-// that grid size.
-template <int EPI, class T = double>
-int apply_op(ppe_solver* s, const Level& L, const T* x, const T* b, T* d, double c1, double c2,
-             T* y, double* partials, const double* prevp = nullptr, int gprev = 0,
-             double c0 = 0.0) {
+// Apply the level operator with epilogue EPI, matrix values in type M.
+// Dot/power epilogues run on a capped grid and write partials to `partials`;
+// returns that grid size.
+template <int EPI, class M = double>
+int apply_op(ppe_solver* s, const Level& L, const double* x, const double* b, double* d,
+             double c1, double c2, double* y, double* partials, const double* prevp = nullptr,
+             int gprev = 0, double c0 = 0.0) {
   const int n = L.n;
   if (n == 0) return 1;
   const bool reduce = EPI == E_DOT || EPI == E_POWER;
@@ -850,25 +803,28 @@ int apply_op(ppe_solver* s, const Level& L, const T* x, const T* b, T* d, double
       if (s->prof_pending.size() == kProfPairs) profile_harvest(s);
       const size_t k = s->prof_pending.size();
 #define PPE_ELL_PROF(WM_)                                                                     \
-  hipExtLaunchKernelGGL((k_ell<EPI, T, WM_>), dim3(g), dim3(kBlock), 0, s->stream,             \
+  hipExtLaunchKernelGGL((k_ell<EPI, M, WM_>), dim3(g), dim3(kBlock), 0, s->stream,             \
                         s->prof_ev[2 * k], s->prof_ev[2 * k + 1], 0, n, L.W,                   \
-                        L.ell_col.as<int>(), LevelData<T>::ell(L), LevelData<T>::diag(L), x, b, \
-                        d, (T)c1, (T)c2, y, partials, (T)c0)
+                        L.ell_col.as<int>(), LevelData<M>::ell(L), LevelData<M>::diag(L), x, b, \
+                        d, c1, c2, y, partials, c0)
       PPE_ELL_WIDTH(L.W, PPE_ELL_PROF);
 #undef PPE_ELL_PROF
     } else {
 #define PPE_ELL(WM_)                                                                           \
-  hipLaunchKernelGGL((k_ell<EPI, T, WM_>), dim3(g), dim3(kBlock), 0, s->stream, n, L.W,         \
-                     L.ell_col.as<int>(), LevelData<T>::ell(L), LevelData<T>::diag(L), x, b, d,  \
-                     (T)c1, (T)c2, y, partials, (T)c0)
+  hipLaunchKernelGGL((k_ell<EPI, M, WM_>), dim3(g), dim3(kBlock), 0, s->stream, n, L.W,         \
+                     L.ell_col.as<int>(), LevelData<M>::ell(L), LevelData<M>::diag(L), x, b, d,  \
+                     c1, c2, y, partials, c0)
       PPE_ELL_WIDTH(L.W, PPE_ELL);
 #undef PPE_ELL
     }
     PPE_LAUNCH_CHECK();
     if (prof) {
+      // off-diagonal entries, the diagonal, and the vectors x in, b, x out,
+      // d out (+ d in after the first step)
       const double off = (double)(L.A.nnz - n);
-      const double vecs = (c1 != 0.0) ? 6.0 : 5.0;  // diag, x_in, b, x_out, d out (+ d in)
-      s->prof_pending.push_back(off * (sizeof(T) + 4.0) + vecs * sizeof(T) * n);
+      const double vecs = (c1 != 0.0) ? 5.0 : 4.0;
+      s->prof_pending.push_back(off * (sizeof(M) + 4.0) + (double)n * sizeof(M) +
+                                vecs * sizeof(double) * n);
     }
     return g;
   }
@@ -876,12 +832,12 @@ int apply_op(ppe_solver* s, const Level& L, const T* x, const T* b, T* d, double
   // and with them the hierarchy, stay what they were
   const int lpr = L.lpr_a > 0     ? L.lpr_a
                   : EPI == E_POWER ? lanes_for(L.A)
-                                   : solve_lanes<T>(L.A);
+                                   : solve_lanes(L.A);
   const int g = reduce ? red_grid((int64_t)n * lpr) : grid_for((int64_t)n * lpr);
 #define PPE_CSR(LL)                                                                            \
-  hipLaunchKernelGGL((k_csr<EPI, LL, T>), dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(),    \
-                     L.A.ci(), LevelData<T>::val(L.A), LevelData<T>::diag(L), x, b, d, (T)c1,   \
-                     (T)c2, y, prevp, gprev, partials, (T)c0)
+  hipLaunchKernelGGL((k_csr<EPI, LL, M>), dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(),    \
+                     L.A.ci(), LevelData<M>::val(L.A), LevelData<M>::diag(L), x, b, d, c1, c2,  \
+                     y, prevp, gprev, partials, c0)
   switch (lpr) {
     case 4: PPE_CSR(4); break;
     case 8: PPE_CSR(8); break;
@@ -894,14 +850,14 @@ int apply_op(ppe_solver* s, const Level& L, const T* x, const T* b, T* d, double
   return g;
 }
 
-template <bool ADD, class T>
-void apply_rect(ppe_solver* s, const Csr& M, const T* x, T* y, int lpr_choice = 0) {
-  if (M.n == 0) return;
-  const int lpr = lpr_choice > 0 ? lpr_choice : solve_lanes<T>(M);
-  const int g = grid_for((int64_t)M.n * lpr);
+template <bool ADD, class M>
+void apply_rect(ppe_solver* s, const Csr& P, const double* x, double* y, int lpr_choice = 0) {
+  if (P.n == 0) return;
+  const int lpr = lpr_choice > 0 ? lpr_choice : solve_lanes(P);
+  const int g = grid_for((int64_t)P.n * lpr);
 #define PPE_RECT(LL)                                                                           \
-  hipLaunchKernelGGL((k_csr_rect<LL, ADD, T>), dim3(g), dim3(kBlock), 0, s->stream, M.n, M.rp(), \
-                     M.ci(), LevelData<T>::val(M), x, y)
+  hipLaunchKernelGGL((k_csr_rect<LL, ADD, M>), dim3(g), dim3(kBlock), 0, s->stream, P.n, P.rp(), \
+                     P.ci(), LevelData<M>::val(P), x, y)
   switch (lpr) {
     case 4: PPE_RECT(4); break;
     case 8: PPE_RECT(8); break;
@@ -914,19 +870,17 @@ void apply_rect(ppe_solver* s, const Csr& M, const T* x, T* y, int lpr_choice = 
 }
 
 // Whether level L's prolongation runs fused with its first post-smoothing
-// step in value type T: on the coarse levels of the FP64 V-cycle, while AP
-// still equals A P, when the smoother takes at least two steps.
+// step: on the coarse levels of the FP64 V-cycle, while AP still equals A P,
+// when the smoother takes at least two steps.
 //  - The finest level keeps its separate passes: there the fused pass, with
 //    CSR rows of P and AP gathered beside the ELL rows of A, took as long as
 //    the prolongation and the ELL step together, while on the coarse levels
 //    it saves a dispatch each.
-//  - The FP32 V-cycle keeps them too: A x1 and (AP) e are each of the size
-//    of the right-hand side, so forming their sum in FP32 leaves a rounding
-//    error of that size in a residual the coarse correction has made much
-//    smaller.
-template <class T>
+//  - The mixed V-cycle keeps them too: rounded to FP32 separately, the
+//    stored AP is no longer the product of the stored A and P, and the
+//    V-cycle would stop being symmetric at the level of that rounding.
 bool prolong_fusable(const ppe_solver* s, const Level& L) {
-  return std::is_same<T, double>::value && &L != &s->levels[0] && L.ap_ok && !L.c1.empty();
+  return s->opt.precision != PPE_MIXED && &L != &s->levels[0] && L.ap_ok && !L.c1.empty();
 }
 
 // Lanes per row of the fused pass: the launch choice if set, else the fewest
@@ -941,17 +895,18 @@ int prolong_lanes(const Level& L) {
 
 // y = (x1 + P e) + d with d = c2 D^-1 (b - A (x1 + P e)): the prolongation
 // and the first post-smoothing step in one pass (prolong_fusable must hold).
-template <class T>
-void prolong_cheb(ppe_solver* s, Level& L, const T* e, const T* x1, const T* b, T* d, T* y) {
+template <class M>
+void prolong_cheb(ppe_solver* s, Level& L, const double* e, const double* x1, const double* b,
+                  double* d, double* y) {
   const int n = L.n;
   const int lpr = prolong_lanes(L);
   const int g = grid_for((int64_t)n * lpr);
-  const T c2 = (T)L.inv_theta;
+  const double c2 = L.inv_theta;
 #define PPE_PC_CSR(LL)                                                                         \
-  hipLaunchKernelGGL((k_csr_prolong_cheb<T, LL>), dim3(g), dim3(kBlock), 0, s->stream, n,       \
-                     L.A.rp(), L.A.ci(), LevelData<T>::val(L.A), LevelData<T>::diag(L), L.P.rp(), \
-                     L.P.ci(), LevelData<T>::val(L.P), L.AP.rp(), L.AP.ci(),                    \
-                     LevelData<T>::val(L.AP), e, x1, b, d, c2, y)
+  hipLaunchKernelGGL((k_csr_prolong_cheb<M, LL>), dim3(g), dim3(kBlock), 0, s->stream, n,       \
+                     L.A.rp(), L.A.ci(), LevelData<M>::val(L.A), LevelData<M>::diag(L), L.P.rp(), \
+                     L.P.ci(), LevelData<M>::val(L.P), L.AP.rp(), L.AP.ci(),                    \
+                     LevelData<M>::val(L.AP), e, x1, b, d, c2, y)
   switch (lpr) {
     case 4: PPE_PC_CSR(4); break;
     case 8: PPE_PC_CSR(8); break;
@@ -963,122 +918,117 @@ void prolong_cheb(ppe_solver* s, Level& L, const T* e, const T* x1, const T* b, 
   PPE_LAUNCH_CHECK();
 }
 
-// PCG dots fused into the last level-0 step of the V-cycle: tile partials of
-// r.z and (flexible) z.q into part (2 x n_tiles).
+// PCG dot fused into the last level-0 step of the V-cycle: tile partials of
+// r.z into part (n_tiles).
 struct PcgDot {
   Tiles T;
   int nt;
-  const double* q;  // flexible: also z.q (q = A p of the iteration)
   double* part;
 };
 
 // Chebyshev smoothing of A x = b.  x_in == nullptr: zero initial guess, and
 // the first two steps run as one pass.  The result is written to x_out;
-// xa/xb are ping-pong buffers distinct from x_in and x_out.  With dot (FP64,
-// level 0 only) the last step also produces the PCG dots; returns whether it
-// did.
-template <class T>
-bool smooth_steps(ppe_solver* s, Level& L, const T* b, const T* cur, int step, T* x_out, T* xa,
-                  T* xb, const PcgDot* dot);
+// xa/xb are ping-pong buffers distinct from x_in and x_out.  With dot (level
+// 0 only) the last step also produces the PCG dot; returns whether it did.
+template <class M>
+bool smooth_steps(ppe_solver* s, Level& L, const double* b, const double* cur, int step,
+                  double* x_out, double* xa, double* xb, const PcgDot* dot);
 
-template <class T>
-bool smooth(ppe_solver* s, Level& L, const T* b, const T* x_in, T* x_out, T* xa, T* xb,
-            const PcgDot* dot = nullptr) {
+template <class M>
+bool smooth(ppe_solver* s, Level& L, const double* b, const double* x_in, double* x_out,
+            double* xa, double* xb, const PcgDot* dot = nullptr) {
   const int n = L.n;
   const int deg = 1 + (int)L.c1.size();
-  T* d = L.d.as<T>();
+  double* d = L.d.as<double>();
   auto dst_of = [&](int k) { return k == deg ? x_out : ((k % 2) ? xa : xb); };
-  const T* cur = x_in;
+  const double* cur = x_in;
   int step = 1;
   if (cur == nullptr) {
     if (deg >= 2 && L.fuse0) {
-      T* dst = dst_of(2);
-      apply_op<E_CHEB0, T>(s, L, nullptr, b, d, L.c1[0], L.c2[0], dst, nullptr, nullptr, 0,
+      double* dst = dst_of(2);
+      apply_op<E_CHEB0, M>(s, L, nullptr, b, d, L.c1[0], L.c2[0], dst, nullptr, nullptr, 0,
                            L.inv_theta);
       cur = dst;
       step = 3;
     } else {
-      T* dst = dst_of(1);
-      hipLaunchKernelGGL(k_cheb_first<T>, dim3(grid_for(n)), dim3(kBlock), 0, s->stream, n, b,
-                         LevelData<T>::diag(L), (T)L.inv_theta, d, dst);
+      double* dst = dst_of(1);
+      hipLaunchKernelGGL(k_cheb_first<M>, dim3(grid_for(n)), dim3(kBlock), 0, s->stream, n, b,
+                         LevelData<M>::diag(L), L.inv_theta, d, dst);
       PPE_LAUNCH_CHECK();
       cur = dst;
       step = 2;
     }
   }
-  return smooth_steps<T>(s, L, b, cur, step, x_out, xa, xb, dot);
+  return smooth_steps<M>(s, L, b, cur, step, x_out, xa, xb, dot);
 }
 
 // Chebyshev steps step..degree from the iterate cur (with the level's d
 // holding the previous step's update when step > 1); the rest as smooth.
-template <class T>
-bool smooth_steps(ppe_solver* s, Level& L, const T* b, const T* cur, int step, T* x_out, T* xa,
-                  T* xb, const PcgDot* dot) {
+template <class M>
+bool smooth_steps(ppe_solver* s, Level& L, const double* b, const double* cur, int step,
+                  double* x_out, double* xa, double* xb, const PcgDot* dot) {
   const int n = L.n;
   const int deg = 1 + (int)L.c1.size();
-  T* d = L.d.as<T>();
+  double* d = L.d.as<double>();
   auto dst_of = [&](int k) { return k == deg ? x_out : ((k % 2) ? xa : xb); };
   bool dotted = false;
   for (; step <= deg; ++step) {
-    T* dst = dst_of(step);
+    double* dst = dst_of(step);
     const double c1 = step == 1 ? 0.0 : L.c1[step - 2];
     const double c2 = step == 1 ? L.inv_theta : L.c2[step - 2];
-    if constexpr (std::is_same<T, double>::value) {
-      if (dot && step == deg && &L == &s->levels[0]) {
+    if (dot && step == deg && &L == &s->levels[0]) {
 #define PPE_CHEB_DOT(WM_)                                                                     \
-  hipLaunchKernelGGL(k_ell_cheb_dot_t<WM_>, dim3(dot->nt), dim3(kBlock), 0, s->stream, dot->T, n, \
-                     L.W, L.ell_col.as<int>(), L.ell_val.as<double>(), L.diag.as<double>(), cur, \
-                     b, d, c1, c2, dst, dot->q, dot->part)
-        PPE_ELL_WIDTH(L.W, PPE_CHEB_DOT);
+  hipLaunchKernelGGL((k_ell_cheb_dot_t<WM_, M>), dim3(dot->nt), dim3(kBlock), 0, s->stream,     \
+                     dot->T, n, L.W, L.ell_col.as<int>(), LevelData<M>::ell(L),                 \
+                     LevelData<M>::diag(L), cur, b, d, c1, c2, dst, dot->part)
+      PPE_ELL_WIDTH(L.W, PPE_CHEB_DOT);
 #undef PPE_CHEB_DOT
-        PPE_LAUNCH_CHECK();
-        dotted = true;
-        cur = dst;
-        continue;
-      }
+      PPE_LAUNCH_CHECK();
+      dotted = true;
+      cur = dst;
+      continue;
     }
-    apply_op<E_CHEB, T>(s, L, cur, b, d, c1, c2, dst, nullptr);
+    apply_op<E_CHEB, M>(s, L, cur, b, d, c1, c2, dst, nullptr);
     cur = dst;
   }
   return dotted;
 }
 
-// One V-cycle with zero initial guess, x = M b on level l, in value type T.
-// dot: see smooth (consumed by the last level-0 smoothing step, if any).
-template <class T>
-bool vcycle_t(ppe_solver* s, int l, const T* b, T* x, const PcgDot* dot = nullptr) {
+// One V-cycle with zero initial guess, x = M b on level l, matrix values in
+// type M (vectors FP64).  dot: see smooth (consumed by the last level-0
+// smoothing step, if any).
+template <class M>
+bool vcycle_t(ppe_solver* s, int l, const double* b, double* x, const PcgDot* dot = nullptr) {
   Level& L = s->levels[l];
   const int n = L.n;
   if (n == 0) return false;
-  T* xa = L.x2.as<T>();
-  T* xb = L.d2.as<T>();
+  double* xa = L.x2.as<double>();
+  double* xb = L.d2.as<double>();
   if (l == s->nlev - 1) {
     if (L.dense) {
-      hipLaunchKernelGGL(k_dense_gemv<T>, dim3(grid_for((int64_t)n * kWave)), dim3(kBlock), 0,
-                         s->stream, n, LevelData<T>::ainv(L), b, x);
+      hipLaunchKernelGGL(k_dense_gemv, dim3(grid_for((int64_t)n * kWave)), dim3(kBlock), 0,
+                         s->stream, n, L.Ainv.as<double>(), b, x);
       PPE_LAUNCH_CHECK();
       return false;
     }
-    T* t = L.r.as<T>();
-    smooth<T>(s, L, b, nullptr, t, xa, xb);
-    return smooth<T>(s, L, b, t, x, xa, xb, dot);
+    double* t = L.r.as<double>();
+    smooth<M>(s, L, b, nullptr, t, xa, xb);
+    return smooth<M>(s, L, b, t, x, xa, xb, dot);
   }
   Level& C = s->levels[l + 1];
-  T* x1 = L.t.as<T>();  // pre-smoothed iterate, corrected in place
-  T* r = L.r.as<T>();
-  smooth<T>(s, L, b, nullptr, x1, xa, xb);
-  apply_op<E_RESID, T>(s, L, x1, b, nullptr, 0.0, 0.0, r, nullptr);
-  apply_rect<false, T>(s, L.R, r, C.b.as<T>(), L.lpr_r);
-  vcycle_t<T>(s, l + 1, C.b.as<T>(), C.x.as<T>());
-  if constexpr (std::is_same<T, double>::value) {
-    if (prolong_fusable<T>(s, L)) {
-      // the first post-smoothing step writes xa (it is not the last step)
-      prolong_cheb<T>(s, L, C.x.as<T>(), x1, b, L.d.as<T>(), xa);
-      return smooth_steps<T>(s, L, b, xa, 2, x, xa, xb, dot);
-    }
+  double* x1 = L.t.as<double>();  // pre-smoothed iterate, corrected in place
+  double* r = L.r.as<double>();
+  smooth<M>(s, L, b, nullptr, x1, xa, xb);
+  apply_op<E_RESID, M>(s, L, x1, b, nullptr, 0.0, 0.0, r, nullptr);
+  apply_rect<false, M>(s, L.R, r, C.b.as<double>(), L.lpr_r);
+  vcycle_t<M>(s, l + 1, C.b.as<double>(), C.x.as<double>());
+  if (prolong_fusable(s, L)) {
+    // the first post-smoothing step writes xa (it is not the last step)
+    prolong_cheb<M>(s, L, C.x.as<double>(), x1, b, L.d.as<double>(), xa);
+    return smooth_steps<M>(s, L, b, xa, 2, x, xa, xb, dot);
   }
-  apply_rect<true, T>(s, L.P, C.x.as<T>(), x1, L.lpr_p);
-  return smooth<T>(s, L, b, x1, x, xa, xb, dot);
+  apply_rect<true, M>(s, L.P, C.x.as<double>(), x1, L.lpr_p);
+  return smooth<M>(s, L, b, x1, x, xa, xb, dot);
 }
 
 template <class S, class D>
@@ -1181,43 +1131,33 @@ void prepare_solve_levels(ppe_solver* s) {
   }
 }
 
-// z = M r with the V-cycle in the solver's precision: FP64 throughout, or
-// (mixed) r rounded to FP32 on entry, an FP32 V-cycle, z widened on exit.
+// z = M r with the V-cycle in the solver's precision: the hierarchy's values
+// in FP64, or (mixed) their FP32 copies; vectors and arithmetic FP64 either
+// way.
 void vcycle(ppe_solver* s, int l, const double* b, double* x) {
-  if (s->opt.precision != PPE_MIXED) {
+  if (s->opt.precision == PPE_MIXED)
+    vcycle_t<float>(s, l, b, x);
+  else
     vcycle_t<double>(s, l, b, x);
-    return;
-  }
-  Level& L = s->levels[l];
-  cast<double, float>(s, b, L.b.as<float>(), L.n);
-  vcycle_t<float>(s, l, L.b.as<float>(), L.x.as<float>());
-  cast<float, double>(s, L.x.as<float>(), x, L.n);
 }
 
-// z = M r for PCG, with the dots r.z and (flexible) z.q left as tile
-// partials: fused into the last level-0 smoothing step (FP64) or into the
-// cast back to FP64 (mixed), else a separate pass.
+// z = M r for PCG, with the dot r.z left as tile partials: fused into the
+// last level-0 smoothing step, else a separate pass.
 static void vcycle_pcg(ppe_solver* s, const double* r, double* z, const PcgDot& dot) {
-  bool dotted;
-  if (s->opt.precision != PPE_MIXED) {
-    dotted = vcycle_t<double>(s, 0, r, z, &dot);
-  } else {
-    Level& L = s->levels[0];
-    cast<double, float>(s, r, L.b.as<float>(), L.n);
-    vcycle_t<float>(s, 0, L.b.as<float>(), L.x.as<float>());
-    hipLaunchKernelGGL(k_cast_dot_t, dim3(dot.nt), dim3(kBlock), 0, s->stream, dot.T,
-                       L.x.as<float>(), r, dot.q, z, dot.part);
-    PPE_LAUNCH_CHECK();
-    dotted = true;
-  }
+  const bool dotted = s->opt.precision == PPE_MIXED ? vcycle_t<float>(s, 0, r, z, &dot)
+                                                    : vcycle_t<double>(s, 0, r, z, &dot);
   if (!dotted) {
-    hipLaunchKernelGGL(k_dot2_t, dim3(dot.nt), dim3(kBlock), 0, s->stream, dot.T, r, z, dot.q,
-                       dot.part);
+    hipLaunchKernelGGL(k_dot_t, dim3(dot.nt), dim3(kBlock), 0, s->stream, dot.T, r, z, dot.part);
     PPE_LAUNCH_CHECK();
   }
 }
 
-// FP32 copies of the hierarchy for the mixed-precision V-cycle.
+// FP32 copies of the hierarchy's values for the mixed-precision V-cycle:
+// diagonals, level operators, P and R.  Rounding each stored
+// value keeps R = P^T and every level operator symmetric, so the V-cycle
+// stays one symmetric operator.  The coarsest dense inverse stays FP64: its
+// entries are dominated by the smoothest mode, and rounding them would
+// perturb the other modes by the level's condition number times 6e-8.
 void make_fp32_hierarchy(ppe_solver* s) {
   for (int l = 0; l < s->nlev; ++l) {
     Level& L = s->levels[l];
@@ -1226,15 +1166,11 @@ void make_fp32_hierarchy(ppe_solver* s) {
     if (l == 0) {
       const int64_t e = (int64_t)(L.W > 0 ? L.W : 1) * L.n;
       cast<double, float>(s, L.ell_val.as<double>(), L.ell_valf.get<float>(e), e);
-    } else {
-      cast<double, float>(s, L.A.v(), L.A.valf.get<float>(L.A.nnz), L.A.nnz);
     }
+    if (L.A.nnz > 0) cast<double, float>(s, L.A.v(), L.A.valf.get<float>(L.A.nnz), L.A.nnz);
     if (l < s->nlev - 1) {
       cast<double, float>(s, L.P.v(), L.P.valf.get<float>(L.P.nnz), L.P.nnz);
       cast<double, float>(s, L.R.v(), L.R.valf.get<float>(L.R.nnz), L.R.nnz);
-    } else if (L.dense) {
-      const int64_t nn = (int64_t)L.n * L.n;
-      cast<double, float>(s, L.Ainv.as<double>(), L.Ainvf.get<float>(nn), nn);
     }
   }
 }
@@ -1285,7 +1221,6 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
   double* p = s->vp.get<double>(na);
   double* q = s->vq.get<double>(na);
   double* b = s->vb.get<double>(na);
-  const bool flexible = s->opt.precision == PPE_MIXED;
   double* tp = s->tpart.get<double>((size_t)T_N * nt);
   double* sc = s->seg_sc.get<double>((size_t)SS_N * ns);
   int* done = s->seg_done.get<int>(3 * (size_t)ns);
@@ -1374,10 +1309,8 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
 
   // Samples converged from the start (zero right-hand side, exact guess) are
   // left alone by every iteration, so the first check below finds them.
-  auto precondition = [&](int sl, bool with_q) {
-    vcycle_pcg(s, r, zb[sl], PcgDot{T, nt, flexible && with_q ? q : nullptr, tpart(T_RZ)});
-  };
-  precondition(1, false);
+  auto precondition = [&](int sl) { vcycle_pcg(s, r, zb[sl], PcgDot{T, nt, tpart(T_RZ)}); };
+  precondition(1);
   hipLaunchKernelGGL(k_init_p_t, dim3(nt), dim3(kBlock), 0, s->stream, T, ns, done, tpart(T_RZ),
                      zb[1], p, rz[0]);
   PPE_LAUNCH_CHECK();
@@ -1386,24 +1319,19 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
   // left untouched by every kernel, so extra iterations change nothing.
   auto body = [&](int sl) {
 #define PPE_ELL_DOT(WM_)                                                                      \
-  if (flexible)                                                                                 \
-    hipLaunchKernelGGL((k_ell_dot_t<WM_, true>), dim3(nt), dim3(kBlock), 0, s->stream, T, na,     \
-                       L0.W, L0.ell_col.as<int>(), L0.ell_val.as<double>(), L0.diag.as<double>(), \
-                       done, p, q, r, tpart(T_PQ));                                             \
-  else                                                                                          \
-    hipLaunchKernelGGL((k_ell_dot_t<WM_, false>), dim3(nt), dim3(kBlock), 0, s->stream, T, na,    \
-                       L0.W, L0.ell_col.as<int>(), L0.ell_val.as<double>(), L0.diag.as<double>(), \
-                       done, p, q, nullptr, tpart(T_PQ))
+  hipLaunchKernelGGL((k_ell_dot_t<WM_>), dim3(nt), dim3(kBlock), 0, s->stream, T, na, L0.W,     \
+                     L0.ell_col.as<int>(), L0.ell_val.as<double>(), L0.diag.as<double>(), done, \
+                     p, q, tpart(T_PQ))
     PPE_ELL_WIDTH(L0.W, PPE_ELL_DOT);
 #undef PPE_ELL_DOT
     PPE_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_update_xr_t, dim3(nt), dim3(kBlock), 0, s->stream, T, done, rz[sl],
-                       tpart(T_PQ), p, q, x, r, tpart(T_RR), cnt, cnt + 1, nt, flexible ? 1 : 0);
+                       tpart(T_PQ), p, q, x, r, tpart(T_RR), cnt, cnt + 1);
     PPE_LAUNCH_CHECK();
-    precondition(sl, true);
-    hipLaunchKernelGGL(k_update_p_t, dim3(nt), dim3(kBlock), 0, s->stream, T, nt, ns, 1, done,
-                       restart, tpart(T_RR), sc, iters, cnt, tpart(T_RZ), tpart(T_PQ),
-                       flexible ? 1 : 0, rz[sl], rz[1 - sl], zb[sl], p, cnt + 1);
+    precondition(sl);
+    hipLaunchKernelGGL(k_update_p_t, dim3(nt), dim3(kBlock), 0, s->stream, T, ns, 1, done,
+                       restart, tpart(T_RR), sc, iters, cnt, tpart(T_RZ), rz[sl], rz[1 - sl],
+                       zb[sl], p, cnt + 1);
     PPE_LAUNCH_CHECK();
   };
   // Two iterations (both rz slots) captured into a HIP graph on the second
@@ -1467,10 +1395,10 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
       it = c.it;
       if (check_true() == 0) return finish(PPE_OK);
       // restarted samples: z = M r_true, p = z (beta is 0 after a restart)
-      precondition(slot, false);  // beta is 0: z.q is not needed
-      hipLaunchKernelGGL(k_update_p_t, dim3(nt), dim3(kBlock), 0, s->stream, T, nt, ns, 0, done,
-                         restart, tpart(T_RR), sc, iters, cnt, tpart(T_RZ), tpart(T_PQ),
-                         flexible ? 1 : 0, rz[slot], rz[1 - slot], zb[slot], p, cnt + 1);
+      precondition(slot);
+      hipLaunchKernelGGL(k_update_p_t, dim3(nt), dim3(kBlock), 0, s->stream, T, ns, 0, done,
+                         restart, tpart(T_RR), sc, iters, cnt, tpart(T_RZ), rz[slot],
+                         rz[1 - slot], zb[slot], p, cnt + 1);
       PPE_LAUNCH_CHECK();
       slot = 1 - slot;
     }
@@ -1523,51 +1451,50 @@ int best_lpr(ppe_solver* s, int rule, F&& run) {
   return best;
 }
 
-// Tune one level's choices in value type T (the V-cycle's type).  Operands
-// are the level's work vectors; their contents do not affect the timings.
-template <class T>
+// Tune one level's choices with matrix values in type M (the V-cycle's).
+// Operands are the level's work vectors; their contents do not affect the
+// timings.
+template <class M>
 void tune_level(ppe_solver* s, int l) {
   Level& L = s->levels[l];
   const bool coarsest = l == s->nlev - 1;
   if (L.n == 0 || (coarsest && L.dense)) return;
-  T* x = L.x.as<T>();
-  T* b = L.b.as<T>();
-  T* d = L.d.as<T>();
-  T* y = L.x2.as<T>();
+  double* x = L.x.as<double>();
+  double* b = L.b.as<double>();
+  double* d = L.d.as<double>();
+  double* y = L.x2.as<double>();
   const double c1 = L.c1.empty() ? 0.0 : L.c1[0], c2 = L.c1.empty() ? L.inv_theta : L.c2[0];
   if (l > 0)
-    L.lpr_a = best_lpr(s, solve_lanes<T>(L.A), [&](int c) {
+    L.lpr_a = best_lpr(s, solve_lanes(L.A), [&](int c) {
       L.lpr_a = c;
-      apply_op<E_CHEB, T>(s, L, x, b, d, c1, c2, y, nullptr);
+      apply_op<E_CHEB, M>(s, L, x, b, d, c1, c2, y, nullptr);
     });
   if (!L.c1.empty()) {
     const float fused = time_launches(s, [&]() {
-      apply_op<E_CHEB0, T>(s, L, nullptr, b, d, c1, c2, y, nullptr, nullptr, 0, L.inv_theta);
+      apply_op<E_CHEB0, M>(s, L, nullptr, b, d, c1, c2, y, nullptr, nullptr, 0, L.inv_theta);
     });
     const float split = time_launches(s, [&]() {
-      hipLaunchKernelGGL(k_cheb_first<T>, dim3(grid_for(L.n)), dim3(kBlock), 0, s->stream, L.n, b,
-                         LevelData<T>::diag(L), (T)L.inv_theta, d, x);
-      apply_op<E_CHEB, T>(s, L, x, b, d, c1, c2, y, nullptr);
+      hipLaunchKernelGGL(k_cheb_first<M>, dim3(grid_for(L.n)), dim3(kBlock), 0, s->stream, L.n, b,
+                         LevelData<M>::diag(L), L.inv_theta, d, x);
+      apply_op<E_CHEB, M>(s, L, x, b, d, c1, c2, y, nullptr);
     });
     L.fuse0 = fused <= split;
   }
   if (coarsest) return;
   Level& C = s->levels[l + 1];
-  L.lpr_r = best_lpr(s, solve_lanes<T>(L.R), [&](int c) {
-    apply_rect<false, T>(s, L.R, L.r.as<T>(), C.b.as<T>(), c);
+  L.lpr_r = best_lpr(s, solve_lanes(L.R), [&](int c) {
+    apply_rect<false, M>(s, L.R, L.r.as<double>(), C.b.as<double>(), c);
   });
-  if constexpr (std::is_same<T, double>::value) {
-    if (prolong_fusable<T>(s, L)) {
-      L.lpr_p = 0;
-      L.lpr_p = best_lpr(s, prolong_lanes(L), [&](int c) {
-        L.lpr_p = c;
-        prolong_cheb<T>(s, L, C.x.as<T>(), L.t.as<T>(), b, d, y);
-      });
-      return;
-    }
+  if (prolong_fusable(s, L)) {
+    L.lpr_p = 0;
+    L.lpr_p = best_lpr(s, prolong_lanes(L), [&](int c) {
+      L.lpr_p = c;
+      prolong_cheb<M>(s, L, C.x.as<double>(), L.t.as<double>(), b, d, y);
+    });
+    return;
   }
-  L.lpr_p = best_lpr(s, solve_lanes<T>(L.P), [&](int c) {
-    apply_rect<true, T>(s, L.P, C.x.as<T>(), L.t.as<T>(), c);
+  L.lpr_p = best_lpr(s, solve_lanes(L.P), [&](int c) {
+    apply_rect<true, M>(s, L.P, C.x.as<double>(), L.t.as<double>(), c);
   });
 }
 

@@ -1,8 +1,9 @@
-"""Mixed precision (FP32 hierarchy and smoother, FP64 outer PCG with the
-flexible beta): the final pressure meets the same FP64 bars as the FP64
-path - relative residual <= 1e-10 recomputed by the oracle and relative L2
-error <= 1e-9 against an exact reference - and one FP32 V-cycle differs from
-the oracle's FP64 V-cycle only by FP32 rounding."""
+"""Mixed precision (the V-cycle reads FP32 copies of the hierarchy's values
+and computes in FP64; FP64 outer PCG): the final pressure meets the same
+FP64 bars as the FP64 path - relative residual <= 1e-10 recomputed by the
+oracle and relative L2 error <= 1e-9 against an exact reference - with the
+FP64 path's iteration count, and one mixed V-cycle differs from the oracle's
+FP64 V-cycle only by the rounding of the stored values."""
 import numpy as np
 import pytest
 
@@ -11,11 +12,13 @@ from tests.gpu_util import case, gpu_solver, to_dev
 
 pytestmark = pytest.mark.gpu
 
-# One V-cycle is a fixed linear map built from about 10 kernels per level,
-# each rounding to FP32 (unit roundoff 2^-24 = 6e-8) once per entry; with
-# 3-4 levels and the Chebyshev recurrences amplifying by at most a few, the
-# relative difference to the FP64 V-cycle stays below ~1e-5.
-VCYCLE_FP32_RTOL = 2e-5
+# One V-cycle is a fixed linear map whose matrices' values are rounded to
+# FP32 (unit roundoff 2^-24 = 6e-8 per value); the smoothing polynomials and
+# the restriction and prolongation of 3-4 levels combine a few dozen such
+# values per output, so the relative difference to the FP64 V-cycle stays
+# well below 1e-6 (a CPU emulation of exactly that rounding at 24^3 gives
+# 9.9e-8).
+VCYCLE_FP32_RTOL = 1e-6
 
 
 @pytest.mark.parametrize("shape,fl", [((16, 16, 16), "linear"), ((32, 32, 32), "front"),
@@ -34,7 +37,7 @@ def test_mixed_solve_meets_fp64_bars(shape, fl):
     assert res.status == 0
     assert assembly.relative_residual(sy, b, p) <= 1e-10
     assert np.linalg.norm(p - pref) <= 1e-9 * np.linalg.norm(pref)
-    assert res.stats["iterations"] <= it64 + 3
+    assert abs(res.stats["iterations"] - it64) <= 1
 
 
 def test_fp32_vcycle_close_to_fp64_oracle():
@@ -49,4 +52,22 @@ def test_fp32_vcycle_close_to_fp64_oracle():
     zr = amg.vcycle(H, r)
     rel = np.linalg.norm(z - zr) / np.linalg.norm(zr)
     assert rel <= VCYCLE_FP32_RTOL, rel
-    assert rel > 1e-12   # it really ran in FP32
+    assert rel > 1e-12   # it really read the FP32 copies
+    # the oracle's V-cycle on the same FP32-rounded values, computed in FP64:
+    # equal up to FP64 summation order
+    zq = amg.vcycle(_rounded(H), r)
+    assert np.linalg.norm(z - zq) <= 1e-12 * np.linalg.norm(zq)
+
+
+def _rounded(H):
+    """A copy of the oracle's hierarchy with every stored level operator,
+    diagonal, P and R value rounded to FP32 (the coarsest inverse kept)."""
+    import copy
+
+    G = copy.deepcopy(H)
+    q = lambda a: a.astype(np.float32).astype(np.float64)
+    for lev in G.levels:
+        lev.A, lev.diag = q(lev.A), q(lev.diag)
+        if lev.P is not None:
+            lev.P, lev.R = q(lev.P), q(lev.R)
+    return G

@@ -218,9 +218,9 @@ def test_warm_started_projection(krylov):
 
 @pytest.mark.parametrize("krylov", KRYLOV)
 def test_projection_mixed_precision(krylov):
-    """FP32 hierarchy under either outer iteration: the outer iteration and
-    the exit test stay FP64, so the full-system residual bar holds; the
-    pressure error is held to the mixed-precision solves' 1e-8."""
+    """FP32-stored hierarchy under either outer iteration: the outer
+    iteration and the exit test stay FP64, so the full-system residual bar
+    holds and the pressure meets the FP64 error bar of 1e-9."""
     import torch
 
     m = box_mesh((14, 12, 10), jitter=0.1, seed=3)
@@ -238,4 +238,4 @@ def test_projection_mixed_precision(krylov):
     err = np.linalg.norm(p - ref.p) / np.linalg.norm(ref.p)
     print(f"mixed {krylov}: outer {st['outer']}, residual {rr:.2e}, L2 error {err:.2e}")
     assert st["rel_residual"] <= 1e-10 and rr <= 1.5e-10
-    assert err <= 1e-8
+    assert err <= 1e-9

@@ -101,10 +101,7 @@ def test_autotuned_solver_meets_bars(precision):
     res = s.solve(to_dev(b, torch.float64))
     p = res.p.cpu().numpy()
     assert assembly.relative_residual(sy, b, p) <= 1e-10
-    # FP64 bar 1e-9; the mixed path's stated bound is 1e-8 (its rounding, and
-    # with it the error left in the smoothest modes, follows the tuned choices)
-    bar = 1e-9 if precision == "fp64" else 1e-8
-    assert np.linalg.norm(p - pref) <= bar * np.linalg.norm(pref)
+    assert np.linalg.norm(p - pref) <= 1e-9 * np.linalg.norm(pref)
     s.assemble(to_dev(c, torch.float64), to_dev(f, torch.float64))
     again = s.solve(to_dev(b, torch.float64)).p.cpu().numpy()
     assert np.array_equal(p, again)
