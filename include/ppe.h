@@ -373,6 +373,23 @@ ppe_status ppe_warm_start_features(ppe_solver* s, const double* dp_prev, const d
                                    const double* face_coeff, const double* liquid_fraction,
                                    const double* cell_volume, const float* mu, const float* sigma,
                                    float* features, double* dp_scale);
+/* For callers that cannot allocate device memory (code between HIP graph
+ * captures, tight per-timestep loops, harnesses that forbid hipMalloc): the
+ * same features and dp_scale as ppe_warm_start_features, bitwise, computed
+ * with the statistics' workspace in a static device array (3 * 1024 + 3
+ * doubles, 24.6 KB per device, held until the process ends) instead of
+ * solver memory.  Calls no hipMalloc, hipFree or allocating library routine
+ * once its first call on a device has looked the array up.  Every call on one
+ * device shares that array: calls that overlap on one device (two host
+ * threads, or two streams in flight) race and must be serialised by the
+ * caller.  Errors as ppe_warm_start_features, and PPE_ERR_ARG (with a
+ * message) if a workspace larger than the array were needed. */
+ppe_status ppe_warm_start_features_noalloc(ppe_solver* s, const double* dp_prev,
+                                           const double* rhs, const double* face_coeff,
+                                           const double* liquid_fraction,
+                                           const double* cell_volume, const float* mu,
+                                           const float* sigma, float* features,
+                                           double* dp_scale);
 /* x0 = p_prev (re-referenced) + dp_scale * y on active non-pin cells, 0
  * elsewhere (y per compact row, x0 per cell). */
 ppe_status ppe_warm_start_apply(ppe_solver* s, const double* p_prev, const float* y,

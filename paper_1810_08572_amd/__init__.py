@@ -149,6 +149,8 @@ _SIGS = {
                                           ctypes.POINTER(ctypes.c_double)]),
     "ppe_warm_start_features": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P,
                                                ctypes.POINTER(ctypes.c_double)]),
+    "ppe_warm_start_features_noalloc": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                                       ctypes.POINTER(ctypes.c_double)]),
     "ppe_warm_start_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, _P]),
     "ppe_warm_start_targets": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, _P]),
     "ppe_set_geometry": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P]),
@@ -893,6 +895,29 @@ def warm_start_features(solver, dp_prev, rhs, face_coeff, fl, cell_volume, mu, s
         _dev_ptr(mu, torch.float32, 10, "mu"), _dev_ptr(sigma, torch.float32, 10, "sigma"),
         ctypes.c_void_p(feats.data_ptr()), ctypes.byref(scale)))
     return feats[:na], scale.value
+
+
+def warm_start_features_noalloc(solver, dp_prev, rhs, face_coeff, fl, cell_volume, mu, sigma,
+                                out):
+    """ppe_warm_start_features_noalloc: the features written into the
+    caller's out [>= n_active, 10] (FP32, device) with the library's static
+    workspace; returns the increment scale.  Allocates nothing."""
+    import torch
+
+    na = solver.stats()["n_active"]
+    if out.dtype != torch.float32 or out.device != solver.device or not out.is_contiguous() \
+            or out.dim() != 2 or out.shape[1] != 10 or out.shape[0] < na:
+        raise ValueError("out must be a contiguous float32 [>= n_active, 10] tensor on the "
+                         "solver's device")
+    scale = ctypes.c_double()
+    nc, nf = solver.n_cells, solver.n_faces
+    solver._chk(load_library().ppe_warm_start_features_noalloc(
+        solver._h, _dev_ptr(dp_prev, torch.float64, nc, "dp_prev"),
+        _dev_ptr(rhs, torch.float64, nc, "rhs"), _dev_ptr(face_coeff, torch.float64, nf, "coeff"),
+        _dev_ptr(fl, torch.float64, nc, "fl"), _dev_ptr(cell_volume, torch.float64, nc, "volume"),
+        _dev_ptr(mu, torch.float32, 10, "mu"), _dev_ptr(sigma, torch.float32, 10, "sigma"),
+        ctypes.c_void_p(out.data_ptr()), ctypes.byref(scale)))
+    return scale.value
 
 
 def warm_start_apply(solver, p_prev, y, scale):

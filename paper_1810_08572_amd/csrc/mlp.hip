@@ -14,6 +14,8 @@
 #include "common.h"
 
 #include <cmath>
+#include <mutex>
+#include <string>
 
 struct ppe_mlp {
   int n_in = 0, width = 0, n_hidden = 0;
@@ -336,6 +338,69 @@ __global__ void k_ws_targets(int na, const int* __restrict__ perm, const int* __
 }
 
 // ---------------------------------------------------------------- host side
+// Workspace of ppe_warm_start_features_noalloc: the statistics' block
+// partials (at most kRedBlocks per statistic) and the three statistics, in a
+// static device array instead of solver memory.  Each device holds its own
+// copy for the life of the process; host code reaches it only through the
+// address hipGetSymbolAddress gives on that device (the array's name is a
+// host-side stand-in there).
+constexpr int kWsScratch = 3 * kRedBlocks + 3;
+static __device__ __align__(256) double scratch[kWsScratch];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+
+// The device address of `scratch` on `device`, looked up once per device
+// with that device current.
+double* ws_scratch(int device) {
+  require(device >= 0 && device < kMaxDevices, PPE_ERR_ARG, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[device]) {
+    int prev = -1;
+    PPE_HIP(hipGetDevice(&prev));
+    if (prev != device) PPE_HIP(hipSetDevice(device));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (prev != device) (void)hipSetDevice(prev);
+    PPE_HIP(e);
+    require(ptr != nullptr, PPE_ERR_HIP, "hipGetSymbolAddress gave no address for the workspace");
+    g_scratch[device] = static_cast<double*>(ptr);
+  }
+  return g_scratch[device];
+}
+
+// The warm-start features of the assembled solver's active cells with the
+// statistics' partials in `part` (3 red_grid(n_active) + 3 doubles, written
+// before they are read: nothing needs clearing).  *dp_scale is copied to the
+// host and the stream synchronised.
+ppe_status ws_features(ppe_solver* s, const double* dp_prev, const double* rhs,
+                       const double* face_coeff, const double* fl, const double* cell_volume,
+                       const float* mu, const float* sigma, float* features, double* dp_scale,
+                       double* part) {
+  const int na = s->n_active;
+  if (na == 0) {
+    *dp_scale = 0.0;
+    return PPE_OK;
+  }
+  const int g = red_grid(na);
+  hipLaunchKernelGGL(k_ws_stats, dim3(g), dim3(kBlock), 0, s->stream, na, s->perm.as<int>(),
+                     s->comp_full.as<int>(), dp_prev, rhs, cell_volume, part);
+  PPE_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_ws_stats_final, dim3(1), dim3(kBlock), 0, s->stream, part, g, na,
+                     part + 3 * g);
+  PPE_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_ws_features, dim3(grid_for(na)), dim3(kBlock), 0, s->stream, na,
+                     s->perm.as<int>(), s->comp_full.as<int>(), s->adj_ptr.as<int>(),
+                     s->adj_nbr.as<int>(), s->adj_face.as<int>(), s->active.as<int>(), dp_prev,
+                     rhs, fl, cell_volume, face_coeff, part + 3 * g, mu, sigma, features);
+  PPE_LAUNCH_CHECK();
+  PPE_HIP(hipMemcpyAsync(dp_scale, part + 3 * g, sizeof(double), hipMemcpyDeviceToHost,
+                         s->stream));
+  PPE_HIP(hipStreamSynchronize(s->stream));
+  return PPE_OK;
+}
+
 void gemm(ppe_mlp* m, int M, int N, int K, const float* A, int64_t ari, int64_t ack,
           const float* B, int64_t brk, int64_t bcj, float* C, int chunk_rows = 0) {
   const int kc = chunk_rows > 0 ? chunk_rows : K;
@@ -606,27 +671,35 @@ ppe_status ppe_warm_start_features(ppe_solver* s, const double* dp_prev, const d
   if (!s->assembled || s->shifted) return PPE_ERR_STATE;  // needs a pinned pressure system
   try {
     const int na = s->n_active;
-    if (na == 0) {
-      *dp_scale = 0.0;
-      return PPE_OK;
-    }
-    const int g = red_grid(na);
-    double* part = s->tmp_d[0].get<double>((size_t)3 * g + 3);
-    hipLaunchKernelGGL(k_ws_stats, dim3(g), dim3(kBlock), 0, s->stream, na, s->perm.as<int>(),
-                       s->comp_full.as<int>(), dp_prev, rhs, cell_volume, part);
-    PPE_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_ws_stats_final, dim3(1), dim3(kBlock), 0, s->stream, part, g, na,
-                       part + 3 * g);
-    PPE_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_ws_features, dim3(grid_for(na)), dim3(kBlock), 0, s->stream, na,
-                       s->perm.as<int>(), s->comp_full.as<int>(), s->adj_ptr.as<int>(),
-                       s->adj_nbr.as<int>(),
-                       s->adj_face.as<int>(), s->active.as<int>(), dp_prev, rhs, fl, cell_volume,
-                       face_coeff, part + 3 * g, mu, sigma, features);
-    PPE_LAUNCH_CHECK();
-    PPE_HIP(hipMemcpyAsync(dp_scale, part + 3 * g, sizeof(double), hipMemcpyDeviceToHost, s->stream));
-    PPE_HIP(hipStreamSynchronize(s->stream));
-    return PPE_OK;
+    double* part =
+        na > 0 ? s->tmp_d[0].get<double>((size_t)3 * red_grid(na) + 3) : nullptr;
+    return ppe::ws_features(s, dp_prev, rhs, face_coeff, fl, cell_volume, mu, sigma, features,
+                            dp_scale, part);
+  } catch (const Error& e) {
+    s->err = e.what();
+    return e.status;
+  }
+}
+
+ppe_status ppe_warm_start_features_noalloc(ppe_solver* s, const double* dp_prev,
+                                           const double* rhs, const double* face_coeff,
+                                           const double* fl, const double* cell_volume,
+                                           const float* mu, const float* sigma, float* features,
+                                           double* dp_scale) {
+  if (!s || !dp_prev || !rhs || !face_coeff || !fl || !cell_volume || !mu || !sigma || !features ||
+      !dp_scale)
+    return PPE_ERR_ARG;
+  if (!s->assembled || s->shifted) return PPE_ERR_STATE;  // needs a pinned pressure system
+  try {
+    const int na = s->n_active;
+    const size_t need = na > 0 ? (size_t)3 * red_grid(na) + 3 : 0;
+    require(need <= (size_t)ppe::kWsScratch, PPE_ERR_ARG,
+            "ppe_warm_start_features_noalloc: " + std::to_string(need) +
+                " workspace doubles needed, the static workspace holds " +
+                std::to_string(ppe::kWsScratch));
+    double* part = na > 0 ? ppe::ws_scratch(s->device) : nullptr;
+    return ppe::ws_features(s, dp_prev, rhs, face_coeff, fl, cell_volume, mu, sigma, features,
+                            dp_scale, part);
   } catch (const Error& e) {
     s->err = e.what();
     return e.status;
