@@ -58,6 +58,21 @@ typedef enum {
 
 typedef enum { PPE_FP64 = 0, PPE_MIXED = 1 } ppe_precision;
 
+/* Relaxation of the V-cycle (section 2.5 couples the multigrid levels by
+ * relaxation without naming it): Chebyshev polynomial smoothing of D^-1 A,
+ * or l1-Jacobi sweeps x <- x + D_l1^-1 (b - A x) with D_l1 the row l1 norms
+ * sum_j |a_ij| (convergent for every SPD A, no spectral bound needed). */
+typedef enum { PPE_SMOOTH_CHEBYSHEV = 0, PPE_SMOOTH_L1JACOBI = 1 } ppe_smoother;
+
+/* Caller-provided device allocator (for example PyTorch's caching
+ * allocator).  alloc returns a device pointer to at least `bytes` bytes of
+ * the solver's device, usable in stream order on `stream` (the solver's
+ * stream), or NULL on failure (the call then fails with PPE_ERR_OOM).
+ * free releases a pointer alloc returned; the library drains its streams
+ * before calling it, so the block is idle.  ctx is passed through. */
+typedef void* (*ppe_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*ppe_free_fn)(void* ptr, void* ctx);
+
 typedef struct {
   int precision;      /* ppe_precision; PPE_MIXED = FP32-stored hierarchy, FP64
                          arithmetic and outer PCG (see ppe_solve) */
@@ -91,11 +106,23 @@ typedef struct {
   int project_krylov; /* outer iteration of ppe_project for the non-symmetric
                          system (L - X) p = b' with the cross term implicit:
                          1 (default) BiCGSTAB preconditioned by one V-cycle of
-                         L's hierarchy per application (section 2.5 names
-                         BiCGSTAB as the paper's Krylov method for systems PCG
-                         cannot take), falling back to deferred correction on
-                         breakdown; 0 deferred correction, each pass an AMG-PCG
-                         solve of L.  Both stop on the same true residual. */
+                         L's hierarchy per application, falling back to
+                         deferred correction on breakdown; 0 deferred
+                         correction, each pass an AMG-PCG solve of L.  Both
+                         stop on the same true residual.  (Section 2.5 pairs
+                         its AMG with Krylov solvers without naming them and
+                         uses a single-grid BiCGSTAB only as the fallback when
+                         the AMG diverges; BiCGSTAB is used here because the
+                         implicit cross term makes the system non-symmetric.) */
+  int smoother;       /* ppe_smoother, default PPE_SMOOTH_CHEBYSHEV; cheb_degree is
+                         the number of steps per application either way (the
+                         polynomial degree, or the l1-Jacobi sweeps) */
+  ppe_alloc_fn alloc; /* device memory of the solver (hierarchy, workspace, and
+                         a time-step driver's own arrays) comes from alloc/free
+                         when both are set; both NULL (default): hipMalloc and
+                         hipFree.  Setting one without the other is PPE_ERR_ARG. */
+  ppe_free_fn free;
+  void* alloc_ctx;    /* passed to alloc and free */
 } ppe_options;
 
 typedef struct {
@@ -246,10 +273,12 @@ typedef struct {
  * terms of Eq. 11, then Eq. 17 and Eq. 8):
  *   F*_f = (u*_C1 + u*_C2)/2 . S_f on open faces, b'_i = -(1/dt) sum s_if F*_f;
  *   (L - X) p = b' on the active cells, pinned as ppe_solve pins, solved by
- *   deferred correction around the AMG-PCG solve of L (each pass solves
- *   L delta = b' + X p - L p to a loose tolerance) until
- *   ||b' + X p - L p|| <= 0.1 rtol ||b'|| (a decade of margin: the loose
- *   inner solves leave smooth residual modes, which the pressure error
+ *   the outer iteration option project_krylov selects - BiCGSTAB
+ *   right-preconditioned by one V-cycle of L (default), or deferred
+ *   correction around the AMG-PCG solve of L (each pass solves
+ *   L delta = b' + X p - L p to a loose tolerance) - until
+ *   ||b' + X p - L p|| <= 0.1 rtol ||b'|| (a decade of margin: loose inner
+ *   solves leave smooth residual modes, which the pressure error
  *   amplifies);
  *   flux[f] = F*_f - dt (c_f (p_C2 - p_C1) + t_f . grad(p)_f) on open faces,
  *   0 on blocked and wall faces;
@@ -258,8 +287,9 @@ typedef struct {
  * face_coeff must be the array given to ppe_assemble (c_f = |S_f|^2/(rho
  * S_f.d) with the same rho).  ustar[3 n_cells]; p[n_cells] out (0 on
  * removed cells and pins).  One sample only (ppe_set_segments with one
- * sample).  Returns PPE_NOT_CONVERGED after 50 passes, PPE_ERR_STATE before
- * ppe_assemble or ppe_set_geometry or with several samples, PPE_ERR_ARG. */
+ * sample).  Returns PPE_NOT_CONVERGED after 50 deferred-correction
+ * passes, PPE_ERR_STATE before ppe_assemble or ppe_set_geometry or with
+ * several samples, PPE_ERR_ARG. */
 ppe_status ppe_project(ppe_solver* s, const double* face_coeff, const double* ustar, double rho,
                        double dt, double* p, double* flux, double* u, ppe_project_stats* stats);
 

@@ -32,7 +32,10 @@ parameter.  This project's reading is smoothed aggregation:
   P          P_tent - omega D^-1 A P_tent, omega = 4 / (3 rho);
   A_c        Galerkin product P^T A P; R = P^T;
   smoother   Chebyshev polynomial of degree k (default 2) in D^-1 A on
-             [rho / 30, rho];
+             [rho / 30, rho]; or (smoother = "l1jacobi") k sweeps of
+             l1-Jacobi relaxation x <- x + D_l1^-1 (b - A x), D_l1 the
+             diagonal of row l1 norms sum_j |a_ij|, convergent for every SPD
+             A because D_l1 - A is diagonally dominant;
   cycle      V-cycle with the same smoother before and after the coarse
              correction (so the preconditioner is symmetric); the coarsest
              level (at most coarse_max rows, default 128) is solved with a
@@ -229,12 +232,29 @@ def chebyshev(A, diag, b, x, lmax, lmin, degree):
     return x
 
 
+def l1_diagonal(A: sp.csr_matrix) -> np.ndarray:
+    """Row l1 norms sum_j |a_ij| (the diagonal included)."""
+    return np.asarray(abs(A).sum(axis=1)).ravel()
+
+
+def l1_jacobi(A, dl1, b, x, sweeps):
+    """`sweeps` l1-Jacobi sweeps x <- x + (b - A x) / dl1; ``x is None``
+    means a zero initial guess."""
+    if x is None:
+        x = b / dl1
+        sweeps -= 1
+    for _ in range(sweeps):
+        x = x + (b - A @ x) / dl1
+    return x
+
+
 @dataclass
 class Level:
     A: sp.csr_matrix
     diag: np.ndarray
     rho: float
     B: np.ndarray
+    dl1: Optional[np.ndarray] = None
     agg: Optional[np.ndarray] = None
     n_agg: int = 0
     mis_rounds: int = 0
@@ -249,6 +269,7 @@ class Hierarchy:
     levels: List[Level] = field(default_factory=list)
     degree: int = 2
     ratio: float = 30.0
+    smoother: str = "chebyshev"
 
     @property
     def operator_complexity(self) -> float:
@@ -257,12 +278,15 @@ class Hierarchy:
 
 
 def build_hierarchy(A0: sp.csr_matrix, theta=0.08, coarse_max=128, max_levels=10,
-                    degree=2, ratio=30.0, dense_max=4096) -> Hierarchy:
-    H = Hierarchy(degree=degree, ratio=ratio)
+                    degree=2, ratio=30.0, dense_max=4096, smoother="chebyshev") -> Hierarchy:
+    if smoother not in ("chebyshev", "l1jacobi"):
+        raise ValueError(f"unknown smoother {smoother!r}")
+    H = Hierarchy(degree=degree, ratio=ratio, smoother=smoother)
     A = A0.tocsr()
     B = np.ones(A.shape[0])
     for lvl in range(max_levels):
-        lev = Level(A=A, diag=A.diagonal().copy(), rho=spectral_bound(A, lvl), B=B)
+        lev = Level(A=A, diag=A.diagonal().copy(), rho=spectral_bound(A, lvl), B=B,
+                    dl1=l1_diagonal(A))
         H.levels.append(lev)
         if A.shape[0] <= coarse_max or lvl == max_levels - 1:
             break
@@ -285,6 +309,8 @@ def build_hierarchy(A0: sp.csr_matrix, theta=0.08, coarse_max=128, max_levels=10
 
 
 def _smooth(H: Hierarchy, lev: Level, b, x):
+    if H.smoother == "l1jacobi":
+        return l1_jacobi(lev.A, lev.dl1, b, x, H.degree)
     return chebyshev(lev.A, lev.diag, b, x, lev.rho, lev.rho / H.ratio, H.degree)
 
 

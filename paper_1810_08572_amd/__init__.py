@@ -27,6 +27,8 @@ PPE_ERR_STATE = -5
 PPE_ERR_INTERNAL = -6
 PPE_FP64 = 0
 PPE_MIXED = 1
+PPE_SMOOTH_CHEBYSHEV = 0
+PPE_SMOOTH_L1JACOBI = 1
 
 
 class ppe_options(ctypes.Structure):
@@ -45,6 +47,10 @@ class ppe_options(ctypes.Structure):
         ("autotune", ctypes.c_int),
         ("reuse_unchanged", ctypes.c_int),
         ("project_krylov", ctypes.c_int),
+        ("smoother", ctypes.c_int),
+        ("alloc", ctypes.c_void_p),
+        ("free", ctypes.c_void_p),
+        ("alloc_ctx", ctypes.c_void_p),
     ]
 
 
@@ -221,6 +227,64 @@ def _check(status, handle=None, allow=(PPE_OK,)):
 
 
 # ---- one-to-one wrappers of the C ABI ---------------------------------------
+# Caller allocator hooks of ppe_options (ppe_alloc_fn, ppe_free_fn).
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class TorchAllocator:
+    """The library's device memory from PyTorch's caching allocator: alloc
+    takes a block on the device the object was made on, in stream order on
+    the library's stream; free hands it back (the library has drained its
+    streams first).  A failed allocation returns NULL, which the library
+    reports as PPE_ERR_OOM.  Keep the object alive as long as the solver."""
+
+    def __init__(self, device):
+        import torch
+
+        self.device = torch.device(device).index
+        self.live = 0           # blocks handed out and not yet returned
+        self.allocations = 0    # alloc calls that succeeded
+
+        def _alloc(nbytes, stream, ctx):
+            try:
+                import torch as _t
+
+                p = _t.cuda.caching_allocator_alloc(int(nbytes), self.device, int(stream or 0))
+                self.live += 1
+                self.allocations += 1
+                return p
+            except Exception:  # noqa: BLE001 - out of memory or a torch error: NULL
+                return None
+
+        def _free(ptr, ctx):
+            try:
+                import torch as _t
+
+                _t.cuda.caching_allocator_delete(int(ptr))
+                self.live -= 1
+            except Exception:  # noqa: BLE001 - torch already torn down at exit
+                pass
+
+        self._alloc = ALLOC_FN(_alloc)
+        self._free = FREE_FN(_free)
+
+    def install(self, o):
+        o.alloc = ctypes.cast(self._alloc, ctypes.c_void_p)
+        o.free = ctypes.cast(self._free, ctypes.c_void_p)
+        o.alloc_ctx = None
+
+
+def _allocator_for(allocator, device):
+    """allocator: "torch" (PyTorch's caching allocator), "hip" (the
+    library's own hipMalloc) or a TorchAllocator-like object."""
+    if allocator == "torch":
+        return TorchAllocator(device)
+    if allocator == "hip" or allocator is None:
+        return None
+    return allocator
+
+
 def ppe_default_options():
     o = ppe_options()
     load_library().ppe_default_options(ctypes.byref(o))
@@ -287,12 +351,13 @@ class Solver:
     def __init__(self, precision="fp64", rtol=1e-10, max_iter=500, cheb_degree=2,
                  cheb_ratio=30.0, coarse_max=128, max_levels=10, theta=0.08, stream=None,
                  use_graph=True, check_every=2, autotune=False, reuse_unchanged=False,
-                 krylov="bicgstab"):
+                 krylov="bicgstab", smoother="chebyshev", allocator="torch"):
         import torch
 
         lib = load_library()
         o = ppe_default_options()
         o.project_krylov = {"deferred": 0, "bicgstab": 1}[krylov]
+        o.smoother = {"chebyshev": PPE_SMOOTH_CHEBYSHEV, "l1jacobi": PPE_SMOOTH_L1JACOBI}[smoother]
         o.precision = {"fp64": PPE_FP64, "mixed": PPE_MIXED}[precision]
         o.rtol, o.max_iter, o.cheb_degree, o.cheb_ratio = rtol, max_iter, cheb_degree, cheb_ratio
         o.coarse_max, o.max_levels, o.theta = coarse_max, max_levels, theta
@@ -304,6 +369,9 @@ class Solver:
         self.stream = stream
         o.stream = ctypes.c_void_p(stream.cuda_stream)
         self.device = torch.device("cuda", torch.cuda.current_device())
+        self.allocator = _allocator_for(allocator, self.device)
+        if self.allocator is not None:
+            self.allocator.install(o)
         self._lib = lib
         self._h = ppe_create(o)
         self.n_cells = 0
@@ -674,7 +742,8 @@ class Flow:
     FP64 to transport_rtol."""
 
     def __init__(self, precision="fp64", rtol=1e-10, transport_rtol=1e-12, stream=None,
-                 use_graph=True, autotune=False, krylov="bicgstab", reuse_unchanged=True):
+                 use_graph=True, autotune=False, krylov="bicgstab", reuse_unchanged=True,
+                 allocator="torch"):
         import torch
 
         self._lib = load_library()
@@ -689,6 +758,9 @@ class Flow:
             stream = torch.cuda.current_stream()
         self.stream = stream
         o.stream = ctypes.c_void_p(stream.cuda_stream)
+        self.allocator = _allocator_for(allocator, torch.device("cuda", torch.cuda.current_device()))
+        if self.allocator is not None:
+            self.allocator.install(o)
         h = _P()
         _check(self._lib.ppe_flow_create(ctypes.byref(o), float(transport_rtol), ctypes.byref(h)))
         self._h = h

@@ -11,6 +11,8 @@ thread_local std::string g_err;
 
 template <class F>
 ppe_status guarded(ppe_solver* s, F&& f) {
+  // the solver's buffers come from its allocator while the call runs
+  ppe::AllocScope scope(s ? &s->allocator : nullptr);
   try {
     if (s) s->err.clear();
     return f();
@@ -103,6 +105,10 @@ void ppe_default_options(ppe_options* o) {
   o->autotune = 0;
   o->reuse_unchanged = 0;
   o->project_krylov = 1;
+  o->smoother = PPE_SMOOTH_CHEBYSHEV;
+  o->alloc = nullptr;
+  o->free = nullptr;
+  o->alloc_ctx = nullptr;
 }
 
 ppe_status ppe_create(const ppe_options* opt, ppe_solver** out) {
@@ -117,6 +123,10 @@ ppe_status ppe_create(const ppe_options* opt, ppe_solver** out) {
     ppe::require(o.max_iter >= 1, PPE_ERR_ARG, "max_iter must be >= 1");
     ppe::require(o.cheb_degree >= 1 && o.cheb_degree <= 8, PPE_ERR_ARG, "cheb_degree in [1, 8]");
     ppe::require(o.cheb_ratio > 1, PPE_ERR_ARG, "cheb_ratio must be > 1");
+    ppe::require(o.smoother == PPE_SMOOTH_CHEBYSHEV || o.smoother == PPE_SMOOTH_L1JACOBI,
+                 PPE_ERR_ARG, "smoother must be PPE_SMOOTH_CHEBYSHEV or PPE_SMOOTH_L1JACOBI");
+    ppe::require((o.alloc == nullptr) == (o.free == nullptr), PPE_ERR_ARG,
+                 "alloc and free must be set together");
     ppe::require(o.project_krylov == 0 || o.project_krylov == 1, PPE_ERR_ARG,
                  "project_krylov must be 0 or 1");
     ppe::require(o.coarse_max >= 1, PPE_ERR_ARG, "coarse_max must be >= 1");
@@ -126,6 +136,9 @@ ppe_status ppe_create(const ppe_options* opt, ppe_solver** out) {
     auto* s = new ppe_solver();
     s->opt = o;
     s->stream = static_cast<hipStream_t>(o.stream);
+    s->allocator = ppe::Allocator{o.alloc, o.free, o.alloc_ctx, o.stream,
+                                  {&s->stream, &s->side, &s->gstream}};
+    ppe::AllocScope scope(&s->allocator);
     try {
       PPE_HIP(hipGetDevice(&s->device));
       int lds = 0;
@@ -157,7 +170,10 @@ void ppe_destroy(ppe_solver* s) {
   for (auto& e : s->prof_ev)
     if (e) (void)hipEventDestroy(e);
   ppe::drop_graph(s);
+  if (s->side) (void)hipStreamSynchronize(s->side);
+  if (s->gstream) (void)hipStreamSynchronize(s->gstream);
   if (s->gstream) (void)hipStreamDestroy(s->gstream);
+  s->gstream = nullptr;
   if (s->ev0) (void)hipEventDestroy(s->ev0);
   if (s->ev1) (void)hipEventDestroy(s->ev1);
   if (s->tev0) (void)hipEventDestroy(s->tev0);
@@ -169,6 +185,7 @@ void ppe_destroy(ppe_solver* s) {
   if (s->side) {
     (void)hipStreamSynchronize(s->side);
     (void)hipStreamDestroy(s->side);
+    s->side = nullptr;
   }
   if (s->box_h) (void)hipHostFree(s->box_h);
   delete s;

@@ -43,23 +43,72 @@ inline void require(bool ok, ppe_status st, const std::string& msg) {
 }
 
 // ---------------------------------------------------------------- buffers
+// Where device memory comes from: hipMalloc/hipFree, or the caller's
+// allocator of ppe_options.  An object that owns buffers (a solver, a
+// time-step driver) holds one Allocator for its whole life; each API call
+// makes it current for the calling thread (AllocScope), and every buffer
+// keeps the allocator it was taken from, so it is released the same way.
+struct Allocator {
+  ppe_alloc_fn alloc = nullptr;
+  ppe_free_fn free = nullptr;
+  void* ctx = nullptr;
+  void* stream = nullptr;             // passed to alloc
+  const hipStream_t* drain[3] = {};   // streams whose work may still use a block
+  void* take(size_t bytes) const {
+    void* p = alloc(bytes, stream, ctx);
+    if (!p) throw Error(PPE_ERR_OOM, "the caller's allocator returned NULL for " +
+                                         std::to_string(bytes) + " bytes");
+    return p;
+  }
+  void give_back(void* p) const {
+    for (const hipStream_t* s : drain)
+      if (s) (void)hipStreamSynchronize(*s);
+    free(p, ctx);
+  }
+};
+inline thread_local const Allocator* tl_alloc = nullptr;  // the call in progress
+struct AllocScope {
+  const Allocator* prev;
+  explicit AllocScope(const Allocator* a) : prev(tl_alloc) {
+    tl_alloc = (a && a->alloc) ? a : nullptr;
+  }
+  ~AllocScope() { tl_alloc = prev; }
+  AllocScope(const AllocScope&) = delete;
+  AllocScope& operator=(const AllocScope&) = delete;
+};
+
 // Grow-only device allocation: reassembling with a new mask reuses memory.
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
+  const Allocator* al = nullptr;  // nullptr: taken from hipMalloc
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), cap(o.cap) { o.p = nullptr; o.cap = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), cap(o.cap), al(o.al) {
+    o.p = nullptr;
+    o.cap = 0;
+    o.al = nullptr;
+  }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; cap = o.cap; o.p = nullptr; o.cap = 0; }
+    if (this != &o) {
+      release();
+      p = o.p; cap = o.cap; al = o.al;
+      o.p = nullptr; o.cap = 0; o.al = nullptr;
+    }
     return *this;
   }
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (al)
+        al->give_back(p);
+      else
+        (void)hipFree(p);
+    }
     p = nullptr;
     cap = 0;
+    al = nullptr;
   }
   template <class T>
   T* get(size_t n) {
@@ -67,7 +116,12 @@ struct DevBuf {
     if (bytes > cap) {
       release();
       size_t want = bytes + bytes / 8;  // slack so a slowly growing size does not realloc each time
-      PPE_HIP(hipMalloc(&p, want));
+      if (tl_alloc) {
+        p = tl_alloc->take(want);
+        al = tl_alloc;
+      } else {
+        PPE_HIP(hipMalloc(&p, want));
+      }
       cap = want;
     }
     return static_cast<T*>(p);
@@ -92,6 +146,7 @@ struct Level {
   int n = 0;
   Csr A;                 // the level operator
   DevBuf diag, diagf;    // diagonal (FP64, FP32)
+  DevBuf dl1, dl1f;      // row l1 norms (l1-Jacobi smoother; FP64, FP32)
   // finest level: slot-major ELL of the off-diagonal part, padding = (row, 0)
   int W = 0;
   DevBuf ell_col, ell_val, ell_valf;
@@ -141,6 +196,8 @@ struct ReadItem {
 }  // namespace ppe
 
 struct ppe_solver {
+  // declared first, so it outlives every buffer of the solver
+  ppe::Allocator allocator;
   ppe_options opt{};
   hipStream_t stream = nullptr;
   int device = 0;

@@ -669,6 +669,7 @@ ppe_status ppe_warm_start_features(ppe_solver* s, const double* dp_prev, const d
       !dp_scale)
     return PPE_ERR_ARG;
   if (!s->assembled || s->shifted) return PPE_ERR_STATE;  // needs a pinned pressure system
+  AllocScope scope(&s->allocator);
   try {
     const int na = s->n_active;
     double* part =

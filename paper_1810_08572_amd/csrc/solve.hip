@@ -38,25 +38,32 @@ enum Scal : int { S_POW = 0, S_N = 2 };
 // Matrix values come in type M (FP64, or the FP32 copy of the mixed mode);
 // vectors and all arithmetic are FP64 in both modes, so the V-cycle is one
 // fixed linear operator of the (rounded) hierarchy either way.
+//
+// The smoothing steps scale the residual by a diagonal sd: the matrix
+// diagonal for the Chebyshev smoother, the row l1 norms for l1-Jacobi.  One
+// step is r = (b - A x)/sd; d = c1 d + c2 r; y = x + d, which with c1 = 0,
+// c2 = 1 is an l1-Jacobi sweep.  `diag` is always the matrix diagonal (the
+// finest level's product and the power steps read it).
 
 // Operand of the matrix product: x_j, or for E_CHEB0 the first Chebyshev
 // iterate c0 b_j / diag_j (the same expression the unfused first step stores).
 template <int EPI, class M>
 __device__ __forceinline__ double operand(int j, const double* __restrict__ x,
                                           const double* __restrict__ b,
-                                          const M* __restrict__ diag, double c0) {
-  if (EPI == E_CHEB0) return c0 * (b[j] / (double)diag[j]);
+                                          const M* __restrict__ sd, double c0) {
+  if (EPI == E_CHEB0) return c0 * (b[j] / (double)sd[j]);
   return x[j];
 }
 
 template <int EPI, class M>
 __device__ __forceinline__ double epilogue(int i, double ax, const double* __restrict__ x,
                                            const double* __restrict__ b,
-                                           const M* __restrict__ diag, double* __restrict__ d,
+                                           const M* __restrict__ diag,
+                                           const M* __restrict__ sd, double* __restrict__ d,
                                            double c1, double c2, double scale,
                                            double* __restrict__ y, double c0 = 0.0) {
   if (EPI == E_CHEB0) {
-    const double di = (double)diag[i];
+    const double di = (double)sd[i];
     const double x1 = c0 * (b[i] / di);
     const double r = (b[i] - ax) / di;
     const double dn = c1 * x1 + c2 * r;
@@ -70,7 +77,7 @@ __device__ __forceinline__ double epilogue(int i, double ax, const double* __res
     y[i] = b[i] - ax;
     return 0.0;
   } else if (EPI == E_CHEB) {
-    const double r = (b[i] - ax) / (double)diag[i];
+    const double r = (b[i] - ax) / (double)sd[i];
     const double dn = (c1 == 0.0 ? 0.0 : c1 * d[i]) + c2 * r;
     d[i] = dn;
     y[i] = x[i] + dn;
@@ -95,7 +102,7 @@ __device__ __forceinline__ double ell_row(double s, int i, int n, int W,
                                           const M* __restrict__ eval,
                                           const double* __restrict__ x,
                                           const double* __restrict__ b,
-                                          const M* __restrict__ diag, double c0) {
+                                          const M* __restrict__ sd, double c0) {
   if (WM > 0) {
     int col[WM > 0 ? WM : 1];
     M v[WM > 0 ? WM : 1];
@@ -107,7 +114,7 @@ __device__ __forceinline__ double ell_row(double s, int i, int n, int W,
     }
     double g[WM > 0 ? WM : 1];
 #pragma unroll
-    for (int k = 0; k < WM; ++k) g[k] = operand<EPI, M>(col[k], x, b, diag, c0);
+    for (int k = 0; k < WM; ++k) g[k] = operand<EPI, M>(col[k], x, b, sd, c0);
 #pragma unroll
     for (int k = 0; k < WM; ++k)
       if (k < W) s = s + (double)v[k] * g[k];
@@ -115,7 +122,7 @@ __device__ __forceinline__ double ell_row(double s, int i, int n, int W,
   }
   for (int k = 0; k < W; ++k) {
     const size_t e = (size_t)k * n + i;
-    s = s + (double)eval[e] * operand<EPI, M>(ecol[e], x, b, diag, c0);
+    s = s + (double)eval[e] * operand<EPI, M>(ecol[e], x, b, sd, c0);
   }
   return s;
 }
@@ -125,6 +132,7 @@ template <int EPI, class M, int WM>
 __global__ void __launch_bounds__(kBlock) k_ell(int n, int W, const int* __restrict__ ecol,
                                                 const M* __restrict__ eval,
                                                 const M* __restrict__ diag,
+                                                const M* __restrict__ sd,
                                                 const double* __restrict__ x,
                                                 const double* __restrict__ b,
                                                 double* __restrict__ d, double c1, double c2,
@@ -132,9 +140,9 @@ __global__ void __launch_bounds__(kBlock) k_ell(int n, int W, const int* __restr
                                                 double* __restrict__ partials, double c0) {
   double dot = 0.0;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    double s = (double)diag[i] * operand<EPI, M>(i, x, b, diag, c0);
-    s = ell_row<EPI, WM, M>(s, i, n, W, ecol, eval, x, b, diag, c0);
-    dot += epilogue<EPI, M>(i, s, x, b, diag, d, c1, c2, 1.0, y, c0);
+    double s = (double)diag[i] * operand<EPI, M>(i, x, b, sd, c0);
+    s = ell_row<EPI, WM, M>(s, i, n, W, ecol, eval, x, b, sd, c0);
+    dot += epilogue<EPI, M>(i, s, x, b, diag, sd, d, c1, c2, 1.0, y, c0);
   }
   if (EPI == E_DOT) {
     double v[1] = {dot};
@@ -176,7 +184,8 @@ constexpr int kRowU = 4;
 // A row's own values that the epilogue reads, loaded by the row's first lane
 // before the row's entries (so they are not a dependent load after the
 // group's shuffles), and the epilogue on them: the same arithmetic as
-// epilogue().
+// epilogue().  `diag` holds the smoothing diagonal for the smoothing steps
+// and the matrix diagonal for the power steps.
 struct RowOwn {
   double x, b, diag, d;
 };
@@ -184,17 +193,17 @@ struct RowOwn {
 template <int EPI, class M>
 __device__ __forceinline__ RowOwn row_own(int i, const double* __restrict__ x,
                                           const double* __restrict__ b,
-                                          const M* __restrict__ diag,
+                                          const M* __restrict__ diag, const M* __restrict__ sd,
                                           const double* __restrict__ d, double c1) {
   RowOwn o{0.0, 0.0, 1.0, 0.0};
   if (EPI == E_CHEB0) {
     o.b = b[i];
-    o.diag = (double)diag[i];
+    o.diag = (double)sd[i];
   } else if (EPI == E_RESID) {
     o.b = b[i];
   } else if (EPI == E_CHEB) {
     o.b = b[i];
-    o.diag = (double)diag[i];
+    o.diag = (double)sd[i];
     o.x = x[i];
     if (c1 != 0.0) o.d = d[i];
   } else if (EPI == E_DOT) {
@@ -241,6 +250,7 @@ template <int EPI, int LPR, class M>
 __global__ void __launch_bounds__(kBlock) k_csr(int n, const int* __restrict__ rp,
                                                 const int* __restrict__ ci,
                                                 const M* __restrict__ v, const M* __restrict__ diag,
+                                                const M* __restrict__ sd,
                                                 const double* __restrict__ x,
                                                 const double* __restrict__ b,
                                                 double* __restrict__ d, double c1, double c2,
@@ -259,9 +269,9 @@ __global__ void __launch_bounds__(kBlock) k_csr(int n, const int* __restrict__ r
     double s = 0.0;
     RowOwn own{0.0, 0.0, 1.0, 0.0};
     if (g < n) {
-      if (lane == 0) own = row_own<EPI, M>(g, x, b, diag, d, c1);
+      if (lane == 0) own = row_own<EPI, M>(g, x, b, diag, sd, d, c1);
       s = row_sum<LPR, kRowU, M>(s, rp[g], rp[g + 1], lane, ci, v,
-                                 [&](int j) { return operand<EPI, M>(j, x, b, diag, c0); });
+                                 [&](int j) { return operand<EPI, M>(j, x, b, sd, c0); });
     }
 #pragma unroll
     for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_down(s, o, LPR);
@@ -351,7 +361,7 @@ __device__ __forceinline__ void group_sum2(double& a, double& b) {
 template <class M, int LPR>
 __global__ void __launch_bounds__(kBlock) k_csr_prolong_cheb(
     int n, const int* __restrict__ rp, const int* __restrict__ ci, const M* __restrict__ v,
-    const M* __restrict__ diag, const int* __restrict__ prp, const int* __restrict__ pci,
+    const M* __restrict__ sd, const int* __restrict__ prp, const int* __restrict__ pci,
     const M* __restrict__ pv, const int* __restrict__ arp, const int* __restrict__ aci,
     const M* __restrict__ av, const double* __restrict__ e, const double* __restrict__ x1,
     const double* __restrict__ b, double* __restrict__ d, double c2, double* __restrict__ y) {
@@ -361,7 +371,7 @@ __global__ void __launch_bounds__(kBlock) k_csr_prolong_cheb(
   if (i < n) {
     if (lane == 0) {
       bi = b[i];
-      di = (double)diag[i];
+      di = (double)sd[i];
       xi = x1[i];
     }
     const int r0 = rp[i], r1 = rp[i + 1], p0 = prp[i], p1 = prp[i + 1], a0 = arp[i],
@@ -388,13 +398,13 @@ __global__ void __launch_bounds__(kBlock) k_csr_prolong_cheb(
 }
 // ---- end of the fused prolongation
 
-// First Chebyshev step from a zero guess: d = b / (theta diag); x = d.
+// First smoothing step from a zero guess: d = b / (theta sd); x = d.
 template <class M>
-__global__ void k_cheb_first(int n, const double* __restrict__ b, const M* __restrict__ diag,
+__global__ void k_cheb_first(int n, const double* __restrict__ b, const M* __restrict__ sd,
                              double inv_theta, double* __restrict__ d, double* __restrict__ x) {
   int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  double v = inv_theta * (b[i] / (double)diag[i]);
+  double v = inv_theta * (b[i] / (double)sd[i]);
   d[i] = v;
   x[i] = v;
 }
@@ -411,6 +421,27 @@ __global__ void __launch_bounds__(kBlock) k_dense_gemv(int n, const double* __re
     for (int j = lane; j < n; j += kWave) s = s + Ainv[(size_t)i * n + j] * b[j];
   s = wave_sum(s);
   if (i < n && lane == 0) x[i] = s;
+}
+
+// Row l1 norms sum_j |a_ij| of the finest level (ELL off-diagonal slots,
+// padding 0, plus the diagonal), in slot order after the diagonal.
+__global__ void k_l1_ell(int n, int W, const double* __restrict__ eval,
+                         const double* __restrict__ diag, double* __restrict__ out) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double s = fabs(diag[i]);
+  for (int k = 0; k < W; ++k) s += fabs(eval[(size_t)k * n + i]);
+  out[i] = s;
+}
+
+// Row l1 norms of a CSR level (its rows hold the diagonal), in entry order.
+__global__ void k_l1_csr(int n, const int* __restrict__ rp, const double* __restrict__ v,
+                         double* __restrict__ out) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) s += fabs(v[k]);
+  out[i] = s;
 }
 
 __global__ void k_power_init(int n, uint32_t salt, double* __restrict__ x,
@@ -490,16 +521,15 @@ __global__ void __launch_bounds__(kBlock) k_dot_t(Tiles T, const double* __restr
 template <int WM, class M>
 __global__ void __launch_bounds__(kBlock) k_ell_cheb_dot_t(
     Tiles T, int n, int W, const int* __restrict__ ecol, const M* __restrict__ eval,
-    const M* __restrict__ diag, const double* __restrict__ x, const double* __restrict__ b,
-    double* __restrict__ d, double c1, double c2, double* __restrict__ y,
-    double* __restrict__ part) {
+    const M* __restrict__ diag, const M* __restrict__ sd, const double* __restrict__ x,
+    const double* __restrict__ b, double* __restrict__ d, double c1, double c2,
+    double* __restrict__ y, double* __restrict__ part) {
   const int t = blockIdx.x;
   double acc = 0.0;
   for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) {
-    const double di = (double)diag[i];
-    double s = di * x[i];
-    s = ell_row<E_CHEB, WM, M>(s, i, n, W, ecol, eval, x, b, diag, 0.0);
-    const double r = (b[i] - s) / di;
+    double s = (double)diag[i] * x[i];
+    s = ell_row<E_CHEB, WM, M>(s, i, n, W, ecol, eval, x, b, sd, 0.0);
+    const double r = (b[i] - s) / (double)sd[i];
     const double dn = (c1 == 0.0 ? 0.0 : c1 * d[i]) + c2 * r;
     d[i] = dn;
     const double yi = x[i] + dn;
@@ -767,13 +797,22 @@ template <class M> struct LevelData;
 template <> struct LevelData<double> {
   static const double* ell(const Level& L) { return L.ell_val.as<double>(); }
   static const double* diag(const Level& L) { return L.diag.as<double>(); }
+  static const double* l1(const Level& L) { return L.dl1.as<double>(); }
   static const double* val(const Csr& A) { return A.v(); }
 };
 template <> struct LevelData<float> {
   static const float* ell(const Level& L) { return L.ell_valf.as<float>(); }
   static const float* diag(const Level& L) { return L.diagf.as<float>(); }
+  static const float* l1(const Level& L) { return L.dl1f.as<float>(); }
   static const float* val(const Csr& A) { return A.vf(); }
 };
+
+// The diagonal the smoothing steps scale by: the row l1 norms under the
+// l1-Jacobi smoother, the matrix diagonal under Chebyshev.
+template <class M>
+const M* smooth_diag(const ppe_solver* s, const Level& L) {
+  return s->opt.smoother == PPE_SMOOTH_L1JACOBI ? LevelData<M>::l1(L) : LevelData<M>::diag(L);
+}
 
 // Lanes per row of the solve's CSR kernels by default: the fewest (a power of
 // two, 4 to 64) that reach half the mean row length, each lane then taking
@@ -795,6 +834,7 @@ int apply_op(ppe_solver* s, const Level& L, const double* x, const double* b, do
   const int n = L.n;
   if (n == 0) return 1;
   const bool reduce = EPI == E_DOT || EPI == E_POWER;
+  const M* sd = EPI == E_POWER ? LevelData<M>::diag(L) : smooth_diag<M>(s, L);
   if (&L == &s->levels[0] && EPI != E_POWER) {
     const int g = reduce ? red_grid(n) : grid_for(n);
     const bool prof = s->prof && EPI == E_CHEB;
@@ -805,15 +845,15 @@ int apply_op(ppe_solver* s, const Level& L, const double* x, const double* b, do
 #define PPE_ELL_PROF(WM_)                                                                     \
   hipExtLaunchKernelGGL((k_ell<EPI, M, WM_>), dim3(g), dim3(kBlock), 0, s->stream,             \
                         s->prof_ev[2 * k], s->prof_ev[2 * k + 1], 0, n, L.W,                   \
-                        L.ell_col.as<int>(), LevelData<M>::ell(L), LevelData<M>::diag(L), x, b, \
-                        d, c1, c2, y, partials, c0)
+                        L.ell_col.as<int>(), LevelData<M>::ell(L), LevelData<M>::diag(L), sd, \
+                        x, b, d, c1, c2, y, partials, c0)
       PPE_ELL_WIDTH(L.W, PPE_ELL_PROF);
 #undef PPE_ELL_PROF
     } else {
 #define PPE_ELL(WM_)                                                                           \
   hipLaunchKernelGGL((k_ell<EPI, M, WM_>), dim3(g), dim3(kBlock), 0, s->stream, n, L.W,         \
-                     L.ell_col.as<int>(), LevelData<M>::ell(L), LevelData<M>::diag(L), x, b, d,  \
-                     c1, c2, y, partials, c0)
+                     L.ell_col.as<int>(), LevelData<M>::ell(L), LevelData<M>::diag(L), sd, x,  \
+                     b, d, c1, c2, y, partials, c0)
       PPE_ELL_WIDTH(L.W, PPE_ELL);
 #undef PPE_ELL
     }
@@ -836,8 +876,8 @@ int apply_op(ppe_solver* s, const Level& L, const double* x, const double* b, do
   const int g = reduce ? red_grid((int64_t)n * lpr) : grid_for((int64_t)n * lpr);
 #define PPE_CSR(LL)                                                                            \
   hipLaunchKernelGGL((k_csr<EPI, LL, M>), dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(),    \
-                     L.A.ci(), LevelData<M>::val(L.A), LevelData<M>::diag(L), x, b, d, c1, c2,  \
-                     y, prevp, gprev, partials, c0)
+                     L.A.ci(), LevelData<M>::val(L.A), LevelData<M>::diag(L), sd, x, b, d, c1,  \
+                     c2, y, prevp, gprev, partials, c0)
   switch (lpr) {
     case 4: PPE_CSR(4); break;
     case 8: PPE_CSR(8); break;
@@ -904,7 +944,7 @@ void prolong_cheb(ppe_solver* s, Level& L, const double* e, const double* x1, co
   const double c2 = L.inv_theta;
 #define PPE_PC_CSR(LL)                                                                         \
   hipLaunchKernelGGL((k_csr_prolong_cheb<M, LL>), dim3(g), dim3(kBlock), 0, s->stream, n,       \
-                     L.A.rp(), L.A.ci(), LevelData<M>::val(L.A), LevelData<M>::diag(L), L.P.rp(), \
+                     L.A.rp(), L.A.ci(), LevelData<M>::val(L.A), smooth_diag<M>(s, L), L.P.rp(), \
                      L.P.ci(), LevelData<M>::val(L.P), L.AP.rp(), L.AP.ci(),                    \
                      LevelData<M>::val(L.AP), e, x1, b, d, c2, y)
   switch (lpr) {
@@ -953,7 +993,7 @@ bool smooth(ppe_solver* s, Level& L, const double* b, const double* x_in, double
     } else {
       double* dst = dst_of(1);
       hipLaunchKernelGGL(k_cheb_first<M>, dim3(grid_for(n)), dim3(kBlock), 0, s->stream, n, b,
-                         LevelData<M>::diag(L), L.inv_theta, d, dst);
+                         smooth_diag<M>(s, L), L.inv_theta, d, dst);
       PPE_LAUNCH_CHECK();
       cur = dst;
       step = 2;
@@ -980,7 +1020,8 @@ bool smooth_steps(ppe_solver* s, Level& L, const double* b, const double* cur, i
 #define PPE_CHEB_DOT(WM_)                                                                     \
   hipLaunchKernelGGL((k_ell_cheb_dot_t<WM_, M>), dim3(dot->nt), dim3(kBlock), 0, s->stream,     \
                      dot->T, n, L.W, L.ell_col.as<int>(), LevelData<M>::ell(L),                 \
-                     LevelData<M>::diag(L), cur, b, d, c1, c2, dst, dot->part)
+                     LevelData<M>::diag(L), smooth_diag<M>(s, L), cur, b, d, c1, c2, dst,       \
+                     dot->part)
       PPE_ELL_WIDTH(L.W, PPE_CHEB_DOT);
 #undef PPE_CHEB_DOT
       PPE_LAUNCH_CHECK();
@@ -1117,6 +1158,23 @@ void prepare_solve_levels(ppe_solver* s) {
     L.c2.clear();
     L.inv_theta = 0.0;
     if (!(L.rho > 0.0)) continue;  // a coarsest level solved directly: no smoother
+    if (s->opt.smoother == PPE_SMOOTH_L1JACOBI) {
+      // cheb_degree sweeps x += (b - A x) / D_l1: every step with c1 = 0, c2 = 1
+      double* dl1 = L.dl1.get<double>(n);
+      if (l == 0)
+        hipLaunchKernelGGL(k_l1_ell, dim3(grid_for(L.n)), dim3(kBlock), 0, s->stream, L.n, L.W,
+                           L.ell_val.as<double>(), L.diag.as<double>(), dl1);
+      else
+        hipLaunchKernelGGL(k_l1_csr, dim3(grid_for(L.n)), dim3(kBlock), 0, s->stream, L.n,
+                           L.A.rp(), L.A.v(), dl1);
+      PPE_LAUNCH_CHECK();
+      L.inv_theta = 1.0;
+      for (int j = 2; j <= s->opt.cheb_degree; ++j) {
+        L.c1.push_back(0.0);
+        L.c2.push_back(1.0);
+      }
+      continue;
+    }
     const double lmax = L.rho, lmin = L.rho / s->opt.cheb_ratio;
     const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
     const double sigma = theta / delta;
@@ -1163,6 +1221,8 @@ void make_fp32_hierarchy(ppe_solver* s) {
     Level& L = s->levels[l];
     if (L.n == 0) continue;
     cast<double, float>(s, L.diag.as<double>(), L.diagf.get<float>(L.n), L.n);
+    if (s->opt.smoother == PPE_SMOOTH_L1JACOBI && L.rho > 0.0)
+      cast<double, float>(s, L.dl1.as<double>(), L.dl1f.get<float>(L.n), L.n);
     if (l == 0) {
       const int64_t e = (int64_t)(L.W > 0 ? L.W : 1) * L.n;
       cast<double, float>(s, L.ell_val.as<double>(), L.ell_valf.get<float>(e), e);
@@ -1475,7 +1535,7 @@ void tune_level(ppe_solver* s, int l) {
     });
     const float split = time_launches(s, [&]() {
       hipLaunchKernelGGL(k_cheb_first<M>, dim3(grid_for(L.n)), dim3(kBlock), 0, s->stream, L.n, b,
-                         LevelData<M>::diag(L), L.inv_theta, d, x);
+                         smooth_diag<M>(s, L), L.inv_theta, d, x);
       apply_op<E_CHEB, M>(s, L, x, b, d, c1, c2, y, nullptr);
     });
     L.fuse0 = fused <= split;

@@ -17,6 +17,8 @@
 #include <vector>
 
 struct ppe_flow {
+  // declared first, so it outlives every buffer of the driver
+  ppe::Allocator allocator;
   ppe_options opt{};
   hipStream_t stream = nullptr;
   ppe_solver* mom = nullptr;  // shifted systems of the momentum predictor
@@ -413,6 +415,8 @@ namespace {
 
 template <class F>
 ppe_status flow_guarded(ppe_flow* f, F&& fn) {
+  // the driver's own arrays come from its allocator while the call runs
+  ppe::AllocScope scope(f ? &f->allocator : nullptr);
   try {
     if (f) f->err.clear();
     return fn();
@@ -451,6 +455,7 @@ ppe_status ppe_flow_create(const ppe_options* opt, double transport_rtol, ppe_fl
     return st;
   }
   f->stream = f->pre->stream;
+  f->allocator = ppe::Allocator{opt->alloc, opt->free, opt->alloc_ctx, opt->stream, {&f->stream}};
   *out = f;
   return PPE_OK;
 }

@@ -38,6 +38,17 @@ def test_host_only_calls():
     assert o.rtol == 1e-10 and o.max_iter == 500 and o.cheb_degree == 2
     assert o.coarse_max == 128 and o.theta == 0.08
     assert o.project_krylov == 1 and o.reuse_unchanged == 0
+    assert o.smoother == ppe.PPE_SMOOTH_CHEBYSHEV and not o.alloc and not o.free
+    # invalid options are refused before any device is touched
+    h = ctypes.c_void_p()
+    bad = ppe.ppe_default_options()
+    bad.smoother = 2
+    assert lib.ppe_create(ctypes.byref(bad), ctypes.byref(h)) == ppe.PPE_ERR_ARG
+    bad = ppe.ppe_default_options()
+    alloc_only = ppe.ALLOC_FN(lambda n, s, c: None)
+    bad.alloc = ctypes.cast(alloc_only, ctypes.c_void_p)
+    assert lib.ppe_create(ctypes.byref(bad), ctypes.byref(h)) == ppe.PPE_ERR_ARG
+    assert not h.value
     assert ppe.ppe_status_string(ppe.PPE_ERR_STATE) == "call out of order"
     assert ppe.ppe_status_string(ppe.PPE_NOT_CONVERGED) == "not converged"
     # NULL solver handles are rejected without touching a device

@@ -236,3 +236,52 @@ def test_pockets_never_mix_in_hierarchy():
         side = (np.asarray(A.sum(axis=1)).ravel() > 0).astype(int)
         assert np.all(lev.A.diagonal() > 0)
     assert np.all(H.levels[-1].A.diagonal() > 0)
+
+
+@pytest.mark.parametrize("sweeps", [1, 2, 3])
+def test_l1_jacobi_on_a_ring(sweeps):
+    """On the periodic chain tridiag(-1, 2, -1) every row's l1 norm is 4, so
+    a sweep multiplies the Fourier mode cos(k theta j) of the error by
+    1 - (2 - 2 cos theta) / 4 = (1 + cos theta) / 2 (textbook damped Jacobi
+    with weight 1/2)."""
+    n = 24
+    A = sp.diags([-np.ones(n - 1), 2 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1], format="lil")
+    A[0, n - 1] = A[n - 1, 0] = -1.0
+    A = A.tocsr()
+    dl1 = amg.l1_diagonal(A)
+    assert np.array_equal(dl1, 4 * np.ones(n))
+    j = np.arange(n)
+    for k in (1, 5, 12):
+        th = 2 * np.pi * k / n
+        e = np.cos(th * j)
+        out = amg.l1_jacobi(A, dl1, np.zeros(n), e, sweeps)   # b = 0: out is the new error
+        assert np.allclose(out, ((1 + np.cos(th)) / 2) ** sweeps * e, rtol=0, atol=1e-13)
+
+
+def test_l1_jacobi_contracts_the_energy_norm():
+    """For SPD A, D_l1 - A is diagonally dominant, so l1-Jacobi reduces the
+    A-norm of the error of every start (here the C1 system)."""
+    _, _, _, sy = _c1_system()
+    A = sy.A.tocsr()
+    dl1 = amg.l1_diagonal(A)
+    assert np.all(dl1 >= A.diagonal())
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        e = rng.normal(size=A.shape[0])
+        e1 = amg.l1_jacobi(A, dl1, np.zeros_like(e), e, 1)
+        assert e1 @ (A @ e1) < e @ (A @ e)
+
+
+def test_l1_jacobi_vcycle_symmetric_and_pcg_matches_dense():
+    _, _, _, sy = _c1_system()
+    H = amg.build_hierarchy(sy.A, smoother="l1jacobi")
+    rng = np.random.default_rng(0)
+    r1, r2 = rng.normal(size=(2, sy.n_active))
+    a, b = amg.vcycle(H, r1) @ r2, r1 @ amg.vcycle(H, r2)
+    assert abs(a - b) <= 1e-12 * abs(a)
+    assert amg.vcycle(H, r1) @ r1 > 0
+    b0 = rhs_uniform(sy.A.shape[0], seed=1)
+    res = pcg.pcg(sy.A, b0, M=lambda r: amg.vcycle(H, r), rtol=1e-12)
+    ref = np.linalg.solve(sy.A.toarray(), b0)
+    assert res.status == pcg.OK
+    assert np.linalg.norm(res.x - ref) <= 1e-9 * np.linalg.norm(ref)
