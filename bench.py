@@ -1,38 +1,37 @@
 """Benchmark: masked pressure-correction Poisson solves per second on one GPU.
 
-Headline workload: timesteps on a 64^3 cube.
-- Mesh: 64^3 = 262,144-cell jittered (+-10 %) hex cube stored as an
-  unstructured face list; 10 mm cavity; aluminium density rho = 2400.
-- Solid front: grows from the cold wall x = 0 as sqrt(t) over a 200-step
-  schedule of 1e-3 s (mushy band 10 % of the cube).
-- Right-hand side: varies smoothly from step to step, standing in for the
-  velocity divergence of a flow solve; centred over the liquid cells.
-- Each timestep does one masked SA-AMG-PCG solve to 1e-10 relative residual.
+Headline workload: timesteps on the plate with ribs (1.5 M cells).
+- Mesh: 240 x 144 x 36 cells (160 x 96 x 24 mm at h = 2/3 mm) with four
+  ribs of 8 x 144 x 56 cells on top, 1,502,208 jittered (+-5 %) hex cells
+  stored as an unstructured face list; aluminium density rho = 2400.
+- Solid front: rises from the bottom face as s(t) = 0.6 H sqrt(t / 0.2 s)
+  over a 200-step schedule of 1e-3 s (mushy band 10 % of the height H).
+- Right-hand side: a sum of smooth modes varying smoothly from step to step,
+  standing in for the velocity divergence of a flow solve; centred over the
+  liquid cells.
+- Each timestep does one masked SA-AMG-PCG solve to 1e-10 relative
+  residual.  One bench step is one timestep's whole hot path: masked
+  assembly, AMG setup, then PCG (inputs already in device memory).
 
-One bench step is one timestep's whole hot path: masked assembly, AMG setup,
-then PCG.  K consecutive timesteps are timed from the middle of the
-schedule, after W warmup steps, with all inputs already in device memory.
-
-Reported:
-- value: FP64 AMG-PCG from a zero guess (the plain method).
-- variants.mixed: FP32 hierarchy under the FP64 outer PCG.
-- variants.mixed_learned: mixed precision, with the initial guess predicted
-  by the warm-start network from the previous step.  The network is trained
-  beforehand, untimed, on snapshots the solver produced for earlier
-  timesteps of the same run.
-- variants.c3_128cube (unless --no-c3): repeated solves of one 128^3 system
-  (2.1 M cells, random planar front) in FP64 and mixed precision, each with
-  its finest-level roofline; at this size the hierarchy outgrows the
-  256 MB Infinity Cache.
-- variants.c5_plate_ribs (unless --no-c5): timesteps on the 1.5 M-cell plate
-  with four ribs, with the front rising from the bottom face.  Compares zero
-  and previous-solution guesses in FP64 and mixed precision with the guess
-  of the network trained on the cube (a geometry it never saw).
-- variants.uq_batched (--uq): 256 uneven uncertainty samples solved as one
-  batch.
-- roofline: the dominant kernel's achieved HBM bandwidth on the headline
-  workload.
-- cpu_baseline: the FP64 oracle on host cores.
+Reported (one JSON line):
+- value: FP64 AMG-PCG from a zero guess (the plain method), solves/s.
+- roofline: the solve kernel with the largest total time, from the
+  library's per-dispatch event pairs during a re-run of the timed steps
+  (algorithmic bytes / kernel time); pcg_iteration: every solve kernel
+  together (the V-cycle and the PCG vector work).
+- variants.c5_plate: the same timesteps from the previous solution, in
+  mixed precision, with the learned warm start (trained beforehand, untimed,
+  on snapshots of earlier timesteps of the same run), with l1-Jacobi
+  smoothing, and with unchanged systems reused.
+- variants.c3_128cube: assembly + solve of a 128^3 cube with a random
+  planar front, FP64 and mixed, with their dominant kernels' rooflines.
+- variants.c4_uq_batched: 256 uneven uncertainty samples (sides 24..48)
+  solved as one batch per timestep, mixed precision.
+- variants.c2_64cube: the 64^3 timesteps (FP64, mixed, learned).
+- variants.projection_*, fractional_step*, uq_collocation: the next rows
+  of the method (cross diffusion, whole fractional steps, collocation).
+- cpu_baseline: the FP64 oracle on one host core, on a bounded sample of the
+  headline workload.
 """
 from __future__ import annotations
 
@@ -46,15 +45,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+METRIC = "pressure solves/s at 1e-10 rel. residual, FP64 vs mixed+learned; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 N_TIMESTEPS = 200
 DT = 1e-3
 RHO = 2400.0
-CAVITY = 0.01  # m
-FIRST_TIMED = 100
-TRAIN_STEPS = range(20, 80)
+CAVITY = 0.01  # m, side of the cube workloads
 RHS_SEED = 5
 USTAR_SEED = 7
+C5_FIRST = 40                 # first timed timestep of the plate run
+C5_TRAIN = range(8, 38, 1)    # snapshot timesteps for the warm-start network
+C2_FIRST = 100
+C2_TRAIN = range(20, 80)
 
 
 def note(msg):
@@ -71,64 +73,91 @@ class Timesteps:
         self.m = mesh
         self.c = face_coeff(mesh, RHO)
         self.axis, self.length, self.s_max = axis, length, s_max
+        self.host = {}
 
     def inputs(self, k):
         from synth import fl_growing_front, rhs_smooth_series
 
-        t = (k + 1) * DT
-        fl = fl_growing_front(self.m.cell_centre, t=t, t_end=N_TIMESTEPS * DT, s_max=self.s_max,
-                              delta=0.1, axis=self.axis, length=self.length)
-        b = rhs_smooth_series(self.m.cell_centre, t, seed=RHS_SEED, center_mask=fl > 0)
-        return fl, b
+        if k not in self.host:
+            t = (k + 1) * DT
+            fl = fl_growing_front(self.m.cell_centre, t=t, t_end=N_TIMESTEPS * DT,
+                                  s_max=self.s_max, delta=0.1, axis=self.axis,
+                                  length=self.length)
+            b = rhs_smooth_series(self.m.cell_centre, t, seed=RHS_SEED, center_mask=fl > 0)
+            self.host[k] = (fl, b)
+        return self.host[k]
 
     def to_device(self, torch, dev, steps):
         m = self.m
-        host = {k: self.inputs(k) for k in sorted(set(steps))}
-        self.host = host
-        return dict(owner=torch.as_tensor(m.owner, device=dev),
-                    neigh=torch.as_tensor(m.neigh, device=dev),
-                    coeff=torch.as_tensor(self.c, device=dev),
-                    vol=torch.as_tensor(m.cell_volume, device=dev),
-                    fl={k: torch.as_tensor(v[0], device=dev) for k, v in host.items()},
-                    b={k: torch.as_tensor(v[1], device=dev) for k, v in host.items()})
+        d = dict(owner=torch.as_tensor(m.owner, device=dev),
+                 neigh=torch.as_tensor(m.neigh, device=dev),
+                 coeff=torch.as_tensor(self.c, device=dev),
+                 vol=torch.as_tensor(m.cell_volume, device=dev), fl={}, b={})
+        for k in sorted(set(steps)):
+            fl, b = self.inputs(k)
+            d["fl"][k] = torch.as_tensor(fl, device=dev)
+            d["b"][k] = torch.as_tensor(b, device=dev)
+        return d
 
 
-def cpu_baseline(wl, steps, budget_s=20.0):
-    """The FP64 oracle (assembly + SA setup + PCG from zero, unmodified) on
-    host cores, single-threaded, over as many timed steps as fit the budget."""
+def plate_workload():
+    from synth import plate_with_ribs_mesh
+
+    m = plate_with_ribs_mesh()
+    height = float(m.cell_centre[:, 2].max() - m.cell_centre[:, 2].min()) + 2.0e-3 / 3.0
+    return Timesteps(m, axis=2, length=height)
+
+
+def cube_workload(side=64):
+    from synth import box_mesh
+
+    return Timesteps(box_mesh((side,) * 3, lengths=(CAVITY,) * 3, jitter=0.1, seed=0), axis=0,
+                     length=CAVITY)
+
+
+def host_cpu():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            return next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")),
+                        "")
+    except OSError:
+        return ""
+
+
+def cpu_baseline(wl, k, gpu_iterations, max_iter=10):
+    """The FP64 oracle (assembly + SA setup + PCG from zero, unmodified) on one
+    host thread, on a bounded sample of timestep k: the assembly and setup
+    in full, then max_iter PCG iterations; a whole solve is the setup time
+    plus gpu_iterations times the measured time per iteration (the oracle's
+    count equals the GPU's within one, a tested parity property)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import amg, assembly, pcg
 
     m = wl.m
-    done, iters, t0 = 0, 0, time.perf_counter()
+    fl, b = wl.inputs(k)
     with threadpool_limits(limits=1):
-        for k in steps:
-            fl, b = wl.host[k]
-            sy = assembly.masked_system(m.n_cells, m.owner, m.neigh, wl.c, fl)
-            H = amg.build_hierarchy(sy.A)
-            res = pcg.pcg(sy.A, assembly.pinned_rhs(sy, b), M=lambda r: amg.vcycle(H, r),
-                          rtol=1e-10)
-            iters += res.iterations
-            done += 1
-            if time.perf_counter() - t0 > budget_s:
-                break
-    dt = time.perf_counter() - t0
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as fh:
-            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
-    except OSError:
-        pass
-    return dict(value=done / dt, unit="solves/s", cores=1, kind="oracle",
-                host_cpu=model, host_logical_cpus=os.cpu_count(),
-                sample=f"{done} consecutive timed timesteps from step {steps[0]} of the 64^3 run: "
-                       f"assembly + SA setup + PCG to 1e-10 from zero ({iters} PCG iterations), "
-                       f"{dt:.1f} s on one host thread")
+        t0 = time.perf_counter()
+        sy = assembly.masked_system(m.n_cells, m.owner, m.neigh, wl.c, fl)
+        H = amg.build_hierarchy(sy.A)
+        t1 = time.perf_counter()
+        res = pcg.pcg(sy.A, assembly.pinned_rhs(sy, b), M=lambda r: amg.vcycle(H, r), rtol=1e-10,
+                      max_iter=max_iter)
+        t2 = time.perf_counter()
+    per_iter = (t2 - t1) / max(res.iterations, 1)
+    solve_s = (t1 - t0) + gpu_iterations * per_iter
+    return dict(value=1.0 / solve_s, unit="solves/s", cores=1, kind="oracle",
+                host_cpu=host_cpu(), host_logical_cpus=os.cpu_count(),
+                setup_s=t1 - t0, s_per_pcg_iteration=per_iter,
+                dof_iterations_per_s=sy.n_active / per_iter,
+                sample=f"timestep {k} of the plate run ({sy.n_active} active cells): oracle "
+                       f"assembly + SA setup in full ({t1 - t0:.1f} s) and {res.iterations} PCG "
+                       f"iterations ({t2 - t1:.1f} s) on one host thread; one solve = setup + "
+                       f"{gpu_iterations} iterations (the FP64 GPU count of that step)")
 
 
 def run_leg(ppe, torch, wl, d_in, steps, warm, precision, guess="zero", net=None,
-            autotune=False, reuse=False):
+            autotune=False, reuse=False, smoother="chebyshev"):
     """Solve warm + steps timesteps; time the last len(steps).  guess: "zero",
     "prev" (the previous step's pressure) or "learned" (net = (network, mu,
     sigma) predicts the increment from the previous step).  autotune: the
@@ -136,23 +165,30 @@ def run_leg(ppe, torch, wl, d_in, steps, warm, precision, guess="zero", net=None
     shape; the warmup steps take the first tunings).  reuse: assemblies that
     find the mask and coefficients unchanged keep the system and hierarchy."""
     m, dev = wl.m, d_in["coeff"].device
-    s = ppe.Solver(precision=precision, autotune=autotune, reuse_unchanged=reuse)
+    s = ppe.Solver(precision=precision, autotune=autotune, reuse_unchanged=reuse,
+                   smoother=smoother)
     s.set_mesh(m.n_cells, d_in["owner"], d_in["neigh"])
     p_prev = torch.zeros(m.n_cells, dtype=torch.float64, device=dev)
     dp_prev = torch.zeros_like(p_prev)
     out = torch.zeros_like(p_prev)
-    rec = dict(iters=0, setup_ms=0.0, solve_ms=0.0, worst=0.0, n_act=[])
+    rec = dict(iters=0, setup_ms=0.0, solve_ms=0.0, worst=0.0, n_act=[], bytes_iter=[],
+               reused=0)
+    feats = None
+    if guess == "learned":
+        feats = torch.empty((m.n_cells, 10), dtype=torch.float32, device=dev)
 
     def one(k, timed):
         nonlocal p_prev, dp_prev, out
         fl, b = d_in["fl"][k], d_in["b"][k]
+        reused0 = s.stats()["reused_setup"] if reuse else 0
         s.assemble(d_in["coeff"], fl)
         x0 = None
         if guess == "learned":
             network, mu, sigma = net
-            F, scale = ppe.warm_start_features(s, dp_prev, b, d_in["coeff"], fl, d_in["vol"], mu,
-                                               sigma)
-            y = network.forward(F, bf16=True)
+            scale = ppe.warm_start_features_noalloc(s, dp_prev, b, d_in["coeff"], fl, d_in["vol"],
+                                                    mu, sigma, feats)
+            na = s.stats()["n_active"]
+            y = network.forward(feats[:na], bf16=True)
             x0 = ppe.warm_start_apply(s, p_prev, y, scale)
         elif guess == "prev":  # the previous pressure re-referenced to the current pins
             zero = torch.zeros(max(s.stats()["n_active"], 1), dtype=torch.float32, device=dev)
@@ -163,11 +199,15 @@ def run_leg(ppe, torch, wl, d_in, steps, warm, precision, guess="zero", net=None
             p_prev, out = out, p_prev
         if timed:
             st = r.stats
+            rec.setdefault("first_iters", st["iterations"])
             rec["iters"] += st["iterations"]
             rec["setup_ms"] += st["setup_ms"]
             rec["solve_ms"] += st["solve_ms"]
             rec["worst"] = max(rec["worst"], st["rel_residual"])
             rec["n_act"].append(st["n_active"])
+            rec["bytes_iter"].append(st["bytes_per_iter"])
+            if reuse:
+                rec["reused"] += st["reused_setup"] - reused0
 
     for k in warm:
         one(k, False)
@@ -178,6 +218,7 @@ def run_leg(ppe, torch, wl, d_in, steps, warm, precision, guess="zero", net=None
     torch.cuda.synchronize()
     rec["elapsed"] = time.perf_counter() - t0
     rec["solver"] = s
+    rec["rerun"] = lambda: [one(k, False) for k in steps]
     assert rec["worst"] <= 1e-10, f"a timed solve missed the tolerance: {rec['worst']}"
     return rec
 
@@ -185,63 +226,90 @@ def run_leg(ppe, torch, wl, d_in, steps, warm, precision, guess="zero", net=None
 def leg_summary(rec, K, base=None):
     import numpy as np
 
+    it = rec["iters"] / K
     out = dict(value=K / rec["elapsed"], unit="solves/s",
                ms_per_step=1e3 * rec["elapsed"] / K,
-               pcg_iterations_per_solve=rec["iters"] / K,
+               pcg_iterations_per_solve=it,
                setup_ms_per_step=rec["setup_ms"] / K,
                solve_ms_per_step=rec["solve_ms"] / K,
                mean_active_cells=float(np.mean(rec["n_act"])),
+               dof_iterations_per_s=float(np.sum(rec["n_act"])) * it / rec["elapsed"],
                worst_rel_residual=rec["worst"])
+    if rec.get("reused"):
+        out["reused_assemblies"] = rec["reused"]
     if base is not None:
         out["wall_time_ratio_vs_fp64"] = base["elapsed"] / rec["elapsed"]
         out["solve_time_ratio_vs_fp64"] = base["solve_ms"] / max(rec["solve_ms"], 1e-12)
     return out
 
 
-def counter_traffic(workload):
-    """Bytes per launch of the roofline kernel from the committed memory
-    counter summary, or None when the kernel's source region (its operand,
-    epilogue and row helpers and the kernel) changed since."""
+def counter_traffic(workload, kernel):
+    """Bytes per launch of `kernel` from the committed memory-counter summary
+    of `workload`, or None when the summary covers another kernel or the
+    kernel's source region changed since the counters were taken."""
     import hashlib
 
     try:
         with open(os.path.join(ROOT, "profiles", "roofline_traffic.json")) as f:
             data = json.load(f)
+        entry = data["workloads"][workload]
+        if entry["kernel"] != kernel:
+            return None
         with open(os.path.join(ROOT, data["source_file"])) as f:
             text = f.read()
-        begin, end = data["source_region"]
+        begin, end = entry["source_region"]
         region = text[text.index(begin):text.index(end)]
-        if hashlib.sha256(region.encode()).hexdigest() != data["source_sha256"]:
+        if hashlib.sha256(region.encode()).hexdigest() != entry["source_sha256"]:
             return None
-        return data["workloads"][workload]["bytes_per_launch"]
+        return entry["bytes_per_launch"]
     except (OSError, KeyError, ValueError):
         return None
 
 
-def roofline(s, run, workload=None):
-    """Live measurement of the finest-level Chebyshev step over run(): mean
-    dispatch duration from the library's event pairs, algorithmic bytes;
-    traffic from the committed counter summary of that workload."""
+def profile_table(s, run):
+    """Per-kernel table of the solve phase over run(): the library times each
+    dispatch with its own event pair on the solver's stream."""
     s.profile(True)
     run()
-    prof = s.profile_read()
+    table = s.profile_read()
     s.profile(False)
-    launches = max(prof["launches"], 1)
-    avg_ms = prof["kernel_ms"] / launches
-    per_launch = prof["bytes"] / launches
-    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    return table
+
+
+def roofline(table, workload=None, label=""):
+    """The kernel with the largest total time in the table, against the HBM
+    peak (algorithmic bytes / kernel time); plus every solve kernel
+    together (pcg_iteration)."""
+    name, e = max(table.items(), key=lambda kv: kv[1]["kernel_ms"])
+    total_ms = sum(v["kernel_ms"] for v in table.values())
+    total_b = sum(v["bytes"] for v in table.values())
+    achieved = e["bytes"] / (e["kernel_ms"] * 1e-3) / 1e9
+    top = sorted(table.items(), key=lambda kv: -kv[1]["kernel_ms"])[:8]
     return {"bound": "hbm",
-            "kernel": "finest-level Chebyshev step (ELL SpMV + smoother update)",
+            "kernel": name + (f" ({label})" if label else ""),
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": counter_traffic(workload) if workload else None,
-            "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": per_launch,
-            "launches": prof["launches"]}
+            "traffic": counter_traffic(workload, name) if workload else None,
+            "avg_launch_us": 1e3 * e["kernel_ms"] / e["launches"],
+            "bytes_per_launch": e["bytes"] / e["launches"],
+            "launches": e["launches"],
+            "share_of_solve_kernel_time": e["kernel_ms"] / total_ms,
+            "pcg_iteration": {"kernels": "every V-cycle and PCG kernel of the solve",
+                              "achieved": total_b / (total_ms * 1e-3) / 1e9,
+                              "frac": total_b / (total_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              "kernel_ms": total_ms, "bytes": total_b},
+            "top_kernels": [{"kernel": k, "share": v["kernel_ms"] / total_ms,
+                             "avg_launch_us": 1e3 * v["kernel_ms"] / v["launches"],
+                             "frac": v["bytes"] / (v["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                            for k, v in top]}
 
 
-def train_network(ppe, torch, wl, d_in, n_adam=400, batch=8192):
-    """Snapshots produced by the solver on earlier timesteps -> trained
-    network and feature standardisation (untimed)."""
+def train_network(ppe, torch, wl, d_in, steps, n_adam=600, batch=8192):
+    """Snapshots produced by the solver on earlier timesteps of the same run
+    -> trained network and feature standardisation (untimed).  A snapshot is
+    taken on steps whose mask equals the previous step's (a mask change moves
+    pins and opens cells, and its increment is not a local function of the
+    features)."""
     import numpy as np
 
     from synth import mlp_initial_weights
@@ -254,12 +322,11 @@ def train_network(ppe, torch, wl, d_in, n_adam=400, batch=8192):
     p_prev = torch.zeros(m.n_cells, dtype=torch.float64, device=dev)
     dp_prev = torch.zeros_like(p_prev)
     feats, targs, masks = [], [], []
-    for k in TRAIN_STEPS:
+    for k in steps:
         fl, b = d_in["fl"][k], d_in["b"][k]
         masks.append(fl > 0)
         s.assemble(d_in["coeff"], fl)
-        stable = len(masks) >= 3 and bool(torch.equal(masks[-1], masks[-2])) and \
-            bool(torch.equal(masks[-2], masks[-3]))
+        stable = len(masks) >= 2 and bool(torch.equal(masks[-1], masks[-2]))
         if stable:
             F, scale = ppe.warm_start_features(s, dp_prev, b, d_in["coeff"], fl, d_in["vol"],
                                                zero10, one10)
@@ -281,8 +348,135 @@ def train_network(ppe, torch, wl, d_in, n_adam=400, batch=8192):
         idx = torch.randint(0, Xs.shape[0], (batch,), device=dev, generator=g)
         losses.append(net.train_step(Xs[idx].contiguous(), T[idx].contiguous(), 1e-3))
     return net, mu, sigma, dict(snapshots=len(feats), rows=int(X.shape[0]),
+                                steps=f"{steps[0]}..{steps[-1]}",
                                 loss_first=float(np.mean(losses[:10])),
                                 loss_last=float(np.mean(losses[-10:])))
+
+
+def c5_legs(ppe, torch, wl, d_in, K, W, base, net):
+    steps = list(range(C5_FIRST, C5_FIRST + K))
+    warm = list(range(C5_FIRST - W, C5_FIRST))
+    out = {"workload": f"plate with ribs, {wl.m.n_cells} cells (+-5 % jitter), front rising from "
+                       f"the bottom face, timesteps {steps[0]}..{steps[-1]} of 200 x 1e-3 s "
+                       f"after {W} warmup steps; assembly + setup + solve per step; fixed launch "
+                       "rules unless the leg says autotuned"}
+    legs = (("fp64_previous_guess", "fp64", "prev", False, "chebyshev", False),
+            ("fp64_zero_guess_autotuned", "fp64", "zero", False, "chebyshev", True),
+            ("fp64_zero_guess_l1jacobi", "fp64", "zero", False, "l1jacobi", False),
+            ("mixed_zero_guess", "mixed", "zero", False, "chebyshev", False),
+            ("mixed_previous_guess", "mixed", "prev", False, "chebyshev", False),
+            ("mixed_learned", "mixed", "learned", False, "chebyshev", False),
+            ("fp64_zero_guess_reuse_unchanged", "fp64", "zero", True, "chebyshev", False),
+            ("mixed_learned_reuse_unchanged", "mixed", "learned", True, "chebyshev", False))
+    for name, prec, guess, reuse, smoother, tune in legs:
+        rec = run_leg(ppe, torch, wl, d_in, steps, warm, prec, guess=guess, net=net, reuse=reuse,
+                      smoother=smoother, autotune=tune)
+        out[name] = leg_summary(rec, K, base)
+        note(f"plate {name}: {out[name]['value']:.1f} solves/s, "
+             f"{out[name]['pcg_iterations_per_solve']:.1f} iterations")
+        del rec
+    return out
+
+
+def c3_leg(ppe, torch, dev, reps=4):
+    """One 128^3 system (random planar front): assembly + solve repeated."""
+    from synth import box_mesh, face_coeff, fl_planar_front, rhs_uniform
+
+    m = box_mesh((128, 128, 128), jitter=0.1, seed=0)
+    fh = fl_planar_front(m.cell_centre, seed=2)
+    c = torch.as_tensor(face_coeff(m, RHO), device=dev)
+    f = torch.as_tensor(fh, device=dev)
+    b = torch.as_tensor(rhs_uniform(m.n_cells, seed=1, center_mask=fh > 0), device=dev)
+    owner = torch.as_tensor(m.owner, device=dev)
+    neigh = torch.as_tensor(m.neigh, device=dev)
+    out = {"workload": "128^3 jittered cube, planar front (normal seed 2), uniform RHS; "
+                       f"{reps} timed assembly + solve rounds of one system after one untimed; "
+                       "fixed launch rules"}
+    for prec in ("fp64", "mixed"):
+        s = ppe.Solver(precision=prec)
+        s.set_mesh(m.n_cells, owner, neigh)
+        p = torch.zeros(m.n_cells, dtype=torch.float64, device=dev)
+
+        def rnd():
+            s.assemble(c, f)
+            return s.solve(b, out=p)
+
+        rnd()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        setup = solve = 0.0
+        for _ in range(reps):
+            r = rnd()
+            setup += r.stats["setup_ms"]
+            solve += r.stats["solve_ms"]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        assert r.stats["rel_residual"] <= 1e-10
+        na, it = r.stats["n_active"], r.stats["iterations"]
+        out[prec] = dict(solves_per_s=1.0 / dt, ms_per_solve=1e3 * dt, setup_ms=setup / reps,
+                         solve_ms=solve / reps, solve_only_per_s=1e3 / (solve / reps),
+                         pcg_iterations=it, active_cells=na, levels=r.stats["levels"],
+                         op_complexity=r.stats["op_complexity"],
+                         dof_iterations_per_s=na * it / dt, rel_residual=r.stats["rel_residual"],
+                         roofline=roofline(profile_table(s, lambda: [s.solve(b, out=p)
+                                                                     for _ in range(2)]),
+                                           f"128cube_planar_front_{prec}"))
+        s.close()
+    return out
+
+
+def c4_leg(ppe, torch, dev, n_samples=256, steps=5, warm=1, first=10):
+    """Batched uncertainty samples (sides U{24..48}) on the 50-step schedule:
+    per timestep, one assembly and one segmented solve of all samples."""
+    import numpy as np
+
+    from synth import batch_samples, box_mesh, concat_meshes, face_coeff, rhs_uniform, uq_front_fl
+
+    samples = batch_samples(n_samples)
+    meshes = [box_mesh((sm["side"],) * 3, lengths=(CAVITY,) * 3, jitter=0.1, seed=q)
+              for q, sm in enumerate(samples)]
+    u = concat_meshes(meshes)
+    c = torch.as_tensor(face_coeff(u, RHO), device=dev)
+    s = ppe.Solver(precision="mixed")
+    s.set_mesh(u.n_cells, torch.as_tensor(u.owner, device=dev), torch.as_tensor(u.neigh, device=dev))
+    s.set_segments(u.extra["cell_offsets"])
+    ks = list(range(first, first + warm + steps))
+    data = {}
+    for k in ks:
+        fls = [uq_front_fl(mm.cell_centre, sm, (k + 1) * DT, 50 * DT, length=CAVITY)
+               for mm, sm in zip(meshes, samples)]
+        bs = [rhs_uniform(mm.n_cells, seed=1000 * q + k, center_mask=f > 0)
+              for q, (mm, f) in enumerate(zip(meshes, fls))]
+        data[k] = (torch.as_tensor(np.concatenate(fls), device=dev),
+                   torch.as_tensor(np.concatenate(bs), device=dev))
+    out = torch.zeros(u.n_cells, dtype=torch.float64, device=dev)
+    its, worst, n_act = [], 0.0, []
+    for i, k in enumerate(ks):
+        if i == warm:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        s.assemble(c, data[k][0])
+        r = s.solve(data[k][1], out=out)
+        if i >= warm:
+            it, rr = s.segment_stats()
+            its.append(float(np.mean(it)))
+            worst = max(worst, max(rr))
+            n_act.append(r.stats["n_active"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert worst <= 1e-10
+    k_last = ks[-1]
+    table = profile_table(s, lambda: s.solve(data[k_last][1], out=out))
+    return dict(workload=f"{n_samples} uncertainty samples, cube sides U{{24..48}} (seed 3), "
+                         f"T_melt ~ N(950,10), T_wall ~ N(600,20), dT_liq ~ U(-5,5); timesteps "
+                         f"{ks[warm]}..{ks[-1]} of the 50-step schedule after {warm} warmup; one "
+                         "assembly + one batched solve of every sample per step, mixed precision, "
+                         "graph-replayed PCG iterations",
+                value=n_samples * steps / dt, unit="sample-solves/s", samples=n_samples,
+                cells=u.n_cells, mean_active_cells=float(np.mean(n_act)), steps=steps,
+                ms_per_step=1e3 * dt / steps,
+                mean_sample_iterations=float(np.mean(its)), worst_rel_residual=worst,
+                precision="mixed", roofline=roofline(table, "c4_batch"))
 
 
 def projection_leg(ppe, torch, wl, d_in, steps, warm, dev, base, krylov="bicgstab"):
@@ -346,6 +540,8 @@ def projection_leg(ppe, torch, wl, d_in, steps, warm, dev, base, krylov="bicgsta
     }
 
 
+
+
 FLOW_DT = 5e-6          # alpha dt / h^2 of about 0.008 at 64^3 (h = 10 mm / 64)
 FLOW_LAYER = 1.5e-3     # m, width of the initial thermal boundary layer
 
@@ -406,194 +602,6 @@ def fractional_step_leg(ppe, torch, dev, K, W, krylov="bicgstab"):
         **{f"{q}_per_step": acc[q] / K for q in keys},
     }
 
-
-def uq_fractional_step(ppe, torch, dev, side=32, n_steps=10, dt=2e-5, level=3, degree=2,
-                       n_test=20):
-    """The paper's die-casting uncertainty study (section 4) on the time-step
-    driver: solute C0 ~ N(10, 0.2) wt %, initial melt temperature
-    ~ N(1000, 10) K and wall temperature ~ N(500, 5) K; the full tensor grid
-    of `level` Gauss points per input (27 samples at level 3, the paper's
-    smaller set); each sample runs n_steps fractional steps on a side^3 cube
-    from a boundary layer of 1.5 mm; outputs are the mean temperature, the
-    solid volume fraction and the peak speed after those steps; a
-    total-degree expansion of them, its Sobol indices, and the paper's
-    Latin-hypercube check (RMS of expansion minus simulation, here over the
-    outputs' spread across the test points)."""
-    import numpy as np
-
-    from synth import al_si_alloy, box_mesh, latin_hypercube, t_wall_layer
-
-    kinds = ["normal", "normal", "normal"]
-    q = ppe.PolynomialChaos(kinds, degree)
-    m = box_mesh((side,) * 3, lengths=(CAVITY,) * 3, jitter=0.1, seed=0)
-
-    def dev_t(a, dtp):
-        return torch.as_tensor(np.ascontiguousarray(a), dtype=dtp, device=dev)
-
-    fw = ppe.Flow()
-    fw.set_mesh(dev_t(m.owner, torch.int32), dev_t(m.neigh, torch.int32),
-                dev_t(m.nodes, torch.float64), dev_t(m.extra["face_nodes"], torch.int32),
-                dev_t(m.extra["cell_nodes"], torch.int32), dev_t(m.cell_centre, torch.float64),
-                dev_t(m.face_area, torch.float64), dev_t(m.face_centre, torch.float64),
-                dev_t(m.cell_volume, torch.float64))
-    V = dev_t(m.cell_volume, torch.float64)
-
-    def run(X):
-        Y = torch.empty((X.shape[0], 3), dtype=torch.float64, device=dev)
-        picard = 0
-        for k, x in enumerate(X):
-            props = al_si_alloy(si_wt=10.0 + 0.2 * x[0], T_wall=500.0 + 5.0 * x[2])
-            T0 = t_wall_layer(m, props["T_wall"], 1000.0 + 10.0 * x[1], 1.5e-3)
-            st = fw.new_state(dev_t(T0, torch.float64), props=props)
-            for stt in fw.run(props, st, dt, n_steps):
-                picard += stt["picard"]
-            Y[k, 0] = (V * st.T).sum() / V.sum()
-            Y[k, 1] = (V * st.fs).sum() / V.sum()
-            Y[k, 2] = st.u.norm(dim=1).max()
-        return Y, picard
-
-    X, _ = q.nodes("tensor", level)
-    run(X[:1])  # warm-up of the driver's buffers
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    Y, picard = run(X)
-    torch.cuda.synchronize()
-    t_runs = time.perf_counter() - t0
-    W = q.fit(X, Y)
-    mean, var, first, total = (v.cpu().numpy() for v in q.stats(W))
-    T, _ = latin_hypercube(kinds, n_test, seed=17)
-    Yt, _ = run(T)
-    yt, ye = Yt.cpu().numpy(), q.eval(T, W).cpu().numpy()
-    spread = yt.max(axis=0) - yt.min(axis=0)
-    names = ["mean_T", "solid_fraction", "max_speed"]
-    return {
-        "workload": f"{side}^3 cube, Al-Si die casting with C0 ~ N(10, 0.2) wt %, T_init ~ "
-                    f"N(1000, 10) K, T_wall ~ N(500, 5) K; {X.shape[0]}-point tensor grid, "
-                    f"{n_steps} fractional steps of {dt:g} s per sample (BiCGSTAB projection), "
-                    f"degree-{degree} expansion; {n_test} Latin-hypercube test runs",
-        "samples": int(X.shape[0]),
-        "sample_steps_per_s": X.shape[0] * n_steps / t_runs,
-        "seconds_for_all_samples": t_runs,
-        "picard_per_step": picard / (X.shape[0] * n_steps),
-        "outputs": {
-            nm: {"mean": float(mean[j]), "std": float(np.sqrt(var[j])),
-                 "sobol_first": [float(v) for v in first[:, j]],
-                 "sobol_total": [float(v) for v in total[:, j]],
-                 "lhs_rms_error_over_spread": float(np.sqrt(np.mean((ye[:, j] - yt[:, j]) ** 2))
-                                                     / max(spread[j], 1e-300)),
-                 # the paper's measure: the difference over the output's mean value
-                 "lhs_rms_error_over_mean": float(np.sqrt(np.mean((ye[:, j] - yt[:, j]) ** 2))
-                                                   / max(abs(float(mean[j])), 1e-300))}
-            for j, nm in enumerate(names)},
-    }
-
-
-def c3_leg(ppe, torch, dev, reps=4):
-    """One 128^3 system (random planar front), solved repeatedly."""
-    from synth import box_mesh, face_coeff, fl_planar_front, rhs_uniform
-
-    m = box_mesh((128, 128, 128), jitter=0.1, seed=0)
-    fh = fl_planar_front(m.cell_centre, seed=2)
-    c = torch.as_tensor(face_coeff(m, RHO), device=dev)
-    f = torch.as_tensor(fh, device=dev)
-    b = torch.as_tensor(rhs_uniform(m.n_cells, seed=1, center_mask=fh > 0), device=dev)
-    owner = torch.as_tensor(m.owner, device=dev)
-    neigh = torch.as_tensor(m.neigh, device=dev)
-    out = {"workload": "128^3 jittered cube, planar front (normal seed 2), uniform RHS; "
-                       f"{reps} timed solves of one assembled system after one untimed; "
-                       "launch choices autotuned at assembly (setup_ms includes the tuning)"}
-    for prec in ("fp64", "mixed"):
-        s = ppe.Solver(precision=prec, autotune=True)
-        s.set_mesh(m.n_cells, owner, neigh)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s.assemble(c, f)
-        torch.cuda.synchronize()
-        t_setup = time.perf_counter() - t0
-        p = torch.zeros(m.n_cells, dtype=torch.float64, device=dev)
-        r = s.solve(b, out=p)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            r = s.solve(b, out=p)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / reps
-        assert r.stats["rel_residual"] <= 1e-10
-        out[prec] = dict(solves_per_s=1.0 / dt, solve_ms=1e3 * dt, setup_ms=1e3 * t_setup,
-                         pcg_iterations=r.stats["iterations"], active_cells=r.stats["n_active"],
-                         levels=r.stats["levels"], rel_residual=r.stats["rel_residual"],
-                         roofline=roofline(s, lambda: s.solve(b, out=p),
-                                           "128cube_planar_front" if prec == "fp64" else None))
-    return out
-
-
-def c5_leg(ppe, torch, dev, net, steps=10, warm=3, first=40):
-    """Timesteps on the plate with ribs, front rising from the bottom face."""
-    from synth import plate_with_ribs_mesh
-
-    m = plate_with_ribs_mesh()
-    height = float(m.cell_centre[:, 2].max() - m.cell_centre[:, 2].min()) + 2.0e-3 / 3.0
-    wl = Timesteps(m, axis=2, length=height)
-    K = list(range(first, first + steps))
-    W = list(range(first - warm, first))
-    d_in = wl.to_device(torch, dev, W + K)
-    base = run_leg(ppe, torch, wl, d_in, K, W, "fp64", autotune=True)
-    out = {"workload": f"plate with ribs, {m.n_cells} cells (+-5 % jitter), front rising from "
-                       f"the bottom face, timesteps {K[0]}..{K[-1]} of 200 x 1e-3 s; network "
-                       "trained on the 64^3 cube run only; launch choices autotuned",
-           "fp64_zero_guess": leg_summary(base, steps)}
-    for name, prec, guess in (("fp64_previous_guess", "fp64", "prev"),
-                              ("mixed_zero_guess", "mixed", "zero"),
-                              ("mixed_previous_guess", "mixed", "prev"),
-                              ("mixed_learned", "mixed", "learned")):
-        rec = run_leg(ppe, torch, wl, d_in, K, W, prec, guess=guess, net=net, autotune=True)
-        out[name] = leg_summary(rec, steps, base)
-    return out
-
-
-def uq_batched(ppe, torch, dev, n_samples=256, steps=3, warm=1):
-    """Batched uncertainty samples (sides U{24..48}, 50-step schedule):
-    per step, one assembly and one segmented solve of all samples."""
-    import numpy as np
-
-    from synth import batch_samples, box_mesh, concat_meshes, face_coeff, rhs_uniform, uq_front_fl
-
-    samples = batch_samples(n_samples)
-    meshes = [box_mesh((sm["side"],) * 3, lengths=(CAVITY,) * 3, jitter=0.1, seed=q)
-              for q, sm in enumerate(samples)]
-    u = concat_meshes(meshes)
-    off = u.extra["cell_offsets"]
-    c = torch.as_tensor(face_coeff(u, RHO), device=dev)
-    s = ppe.Solver(precision="mixed")
-    s.set_mesh(u.n_cells, torch.as_tensor(u.owner, device=dev), torch.as_tensor(u.neigh, device=dev))
-    s.set_segments(off)
-    ks = list(range(10, 10 + warm + steps))
-    data = {}
-    for k in ks:
-        fls = [uq_front_fl(mm.cell_centre, sm, (k + 1) * DT, 50 * DT, length=CAVITY)
-               for mm, sm in zip(meshes, samples)]
-        bs = [rhs_uniform(mm.n_cells, seed=1000 * q + k, center_mask=f > 0)
-              for q, (mm, f) in enumerate(zip(meshes, fls))]
-        data[k] = (torch.as_tensor(np.concatenate(fls), device=dev),
-                   torch.as_tensor(np.concatenate(bs), device=dev))
-    out = torch.zeros(u.n_cells, dtype=torch.float64, device=dev)
-    its, worst = [], 0.0
-    for i, k in enumerate(ks):
-        if i == warm:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-        s.assemble(c, data[k][0])
-        s.solve(data[k][1], out=out)
-        if i >= warm:
-            it, rr = s.segment_stats()
-            its.append(float(np.mean(it)))
-            worst = max(worst, max(rr))
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    return dict(value=n_samples * steps / dt, unit="sample-solves/s", samples=n_samples,
-                cells=u.n_cells, steps=steps, ms_per_step=1e3 * dt / steps,
-                mean_sample_iterations=float(np.mean(its)), worst_rel_residual=worst,
-                precision="mixed")
 
 
 def uq_collocation(ppe, torch, dev, side=32, level=6, degree=5, n_test=60):
@@ -678,26 +686,39 @@ def uq_collocation(ppe, torch, dev, side=32, level=6, degree=5, n_test=60):
     }
 
 
+def c2_legs(ppe, torch, dev, K, W):
+    """The 64^3 timesteps (one GPU's share of a 128^3 mesh split eight ways):
+    FP64, mixed, and mixed with a network trained on that run's earlier
+    timesteps."""
+    wl = cube_workload(64)
+    steps = list(range(C2_FIRST, C2_FIRST + K))
+    warm = list(range(C2_FIRST - W, C2_FIRST))
+    d_in = wl.to_device(torch, dev, warm + steps + list(C2_TRAIN))
+    base = run_leg(ppe, torch, wl, d_in, steps, warm, "fp64")
+    out = {"workload": f"64^3 jittered hex cube (10 mm), sqrt(t) front from the wall x = 0, "
+                       f"timesteps {steps[0]}..{steps[-1]} of 200 x 1e-3 s; assembly + setup + "
+                       "solve per step; fixed launch rules",
+           "fp64_zero_guess": leg_summary(base, K)}
+    mixed = run_leg(ppe, torch, wl, d_in, steps, warm, "mixed")
+    out["mixed_zero_guess"] = leg_summary(mixed, K, base)
+    net, mu, sigma, tr = train_network(ppe, torch, wl, d_in, list(C2_TRAIN))
+    ml = run_leg(ppe, torch, wl, d_in, steps, warm, "mixed", guess="learned",
+                 net=(net, mu, sigma))
+    out["mixed_learned"] = dict(leg_summary(ml, K, base), training=tr)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--no-variants", action="store_true", help="time the FP64 leg only")
-    ap.add_argument("--no-c3", action="store_true", help="skip the 128^3 leg")
-    ap.add_argument("--no-c5", action="store_true", help="skip the plate-with-ribs leg")
-    ap.add_argument("--no-projection", action="store_true",
-                    help="skip the cross-diffusion pressure-correction leg")
-    ap.add_argument("--no-uq-collocation", action="store_true",
-                    help="skip the polynomial-chaos collocation leg")
-    ap.add_argument("--projection-only", action="store_true",
-                    help="time the FP64 leg and the pressure-correction leg only (for profiling)")
-    ap.add_argument("--no-flow", action="store_true", help="skip the fractional-step legs")
-    ap.add_argument("--flow-only", action="store_true",
-                    help="time the FP64 leg and the fractional-step leg only (for profiling)")
-    ap.add_argument("--uq", action="store_true", help="add the batched-UQ measurement")
+    ap.add_argument("--no-variants", action="store_true", help="time the headline leg only")
+    ap.add_argument("--only", default="",
+                    help="comma list of variant legs to run: c5, c3, c4, c2, projection, flow, "
+                         "collocation (default: all)")
     ap.add_argument("--c3-only", action="store_true",
                     help="run only the 128^3 leg and print its JSON (for profiling it alone)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -713,7 +734,6 @@ def main():
     import torch
 
     import paper_1810_08572_amd as ppe
-    from synth import box_mesh
 
     dev = torch.device("cuda", 0)
     if args.copy_probe:
@@ -726,21 +746,23 @@ def main():
     if args.c3_only:
         print(json.dumps(c3_leg(ppe, torch, dev)), flush=True)
         return
+    only = {x for x in args.only.split(",") if x}
+    want = lambda leg: not args.no_variants and (not only or leg in only)
+
     K, W = args.steps, args.warmup
-    steps = list(range(FIRST_TIMED, FIRST_TIMED + K))
-    warm = list(range(FIRST_TIMED - W, FIRST_TIMED))
-    wl = Timesteps(box_mesh((64, 64, 64), lengths=(CAVITY,) * 3, jitter=0.1, seed=0), axis=0,
-                   length=CAVITY)
-    need = warm + steps + ([] if args.no_variants or args.projection_only or args.flow_only
-                           else list(TRAIN_STEPS))
+    steps = list(range(C5_FIRST, C5_FIRST + K))
+    warm = list(range(C5_FIRST - W, C5_FIRST))
+    wl = plate_workload()
+    need = warm + steps + (list(C5_TRAIN) if want("c5") else [])
     d_in = wl.to_device(torch, dev, need)
     note(f"inputs ready: {len(set(need))} timesteps of {wl.m.n_cells} cells")
 
     base = run_leg(ppe, torch, wl, d_in, steps, warm, "fp64")
-    note(f"fp64 leg: {K / base['elapsed']:.1f} solves/s")
+    note(f"fp64 headline: {K / base['elapsed']:.1f} solves/s")
     n_act = base["n_act"]
+    it = base["iters"] / K
     out = {
-        "metric": "pressure solves/s at 1e-10 rel. residual",
+        "metric": METRIC,
         "value": K / base["elapsed"],
         "unit": "solves/s",
         "n_gpus": 1,
@@ -753,90 +775,68 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "64^3 jittered hex cube, sqrt(t) solid front, smooth-in-time RHS, "
-                        f"timesteps {steps[0]}..{steps[-1]} of 200 x 1e-3 s; one masked SA-AMG-PCG "
-                        "pressure solve per step (assembly + setup + solve), FP64, zero guess",
+            "workload": f"plate with ribs, {wl.m.n_cells} jittered hex cells (240x144x36 plate + "
+                        "4 ribs of 8x144x56), front rising from the bottom face, timesteps "
+                        f"{steps[0]}..{steps[-1]} of 200 x 1e-3 s; one masked SA-AMG-PCG pressure "
+                        "solve per step (assembly + setup + solve), FP64, zero guess",
             "cells": wl.m.n_cells,
             "mean_active_cells": float(np.mean(n_act)),
-            "pcg_iterations_per_solve": base["iters"] / K,
-            "dof_iterations_per_s": float(np.sum(n_act)) * (base["iters"] / K) / base["elapsed"],
+            "pcg_iterations_per_solve": it,
+            "dof_iterations_per_s": float(np.sum(n_act)) * it / base["elapsed"],
             "worst_rel_residual": base["worst"],
             "setup_ms_per_step": base["setup_ms"] / K,
             "solve_ms_per_step": base["solve_ms"] / K,
+            "solve_only_per_s": 1e3 * K / base["solve_ms"],
+            "algorithmic_gb_per_pcg_iteration": float(np.mean(base["bytes_iter"])) / 1e9,
         },
     }
-
     if not args.no_profile:
         s = base["solver"]
-
-        def rerun():
-            for k in steps:
-                s.assemble(d_in["coeff"], d_in["fl"][k])
-                s.solve(d_in["b"][k])
-
-        out["roofline"] = roofline(s, rerun, "64cube_timesteps")
-        out["roofline"]["kernel"] += ", FP64"
-
-    if args.flow_only:
-        out["variants"] = {"fractional_step": fractional_step_leg(ppe, torch, dev, K, W),
-                           "fractional_step_deferred": fractional_step_leg(ppe, torch, dev, K, W,
-                                                                           krylov="deferred"),
-                           "uq_fractional_step": uq_fractional_step(ppe, torch, dev)}
-        print(json.dumps(out), flush=True)
-        return
-    if args.projection_only:
-        out["variants"] = {
-            "projection_cross_diffusion": projection_leg(ppe, torch, wl, d_in, steps, warm, dev,
-                                                         base),
-            "projection_cross_diffusion_deferred": projection_leg(ppe, torch, wl, d_in, steps,
-                                                                  warm, dev, base, "deferred")}
-        print(json.dumps(out), flush=True)
-        return
+        out["roofline"] = roofline(profile_table(s, base["rerun"]), "plate_timesteps_fp64")
+        note(f"roofline: {out['roofline']['kernel']} {out['roofline']['frac']:.3f}")
+    base["solver"].close()
     if not args.no_variants:
         variants = {}
-        mixed = run_leg(ppe, torch, wl, d_in, steps, warm, "mixed")
-        variants["mixed"] = leg_summary(mixed, K, base)
-        note(f"mixed leg: {K / mixed['elapsed']:.1f} solves/s")
-        net, mu, sigma, tr = train_network(ppe, torch, wl, d_in)
-        note(f"network trained: {tr}")
-        ml = run_leg(ppe, torch, wl, d_in, steps, warm, "mixed", guess="learned",
-                     net=(net, mu, sigma))
-        variants["mixed_learned"] = dict(leg_summary(ml, K, base), training=tr)
-        note(f"mixed+learned leg: {K / ml['elapsed']:.1f} solves/s")
-        ru = run_leg(ppe, torch, wl, d_in, steps, warm, "fp64", reuse=True)
-        variants["fp64_reuse_unchanged"] = dict(
-            leg_summary(ru, K, base),
-            reused_assemblies=int(ru["solver"].stats()["reused_setup"]),
-            note="the same timesteps (reused_assemblies counts warmup and timed steps); an assembly whose mask and coefficients equal the previous "
-                 "one's keeps the system and hierarchy (the matrix depends on nothing else)")
-        note(f"fp64 reuse leg: {K / ru['elapsed']:.1f} solves/s")
-        if not args.no_projection:
-            variants["projection_cross_diffusion"] = projection_leg(ppe, torch, wl, d_in, steps,
-                                                                    warm, dev, base)
-            variants["projection_cross_diffusion_deferred"] = projection_leg(
-                ppe, torch, wl, d_in, steps, warm, dev, base, "deferred")
-            note("projection legs done")
-        if not args.no_flow:
-            variants["fractional_step"] = fractional_step_leg(ppe, torch, dev, K, W)
-            note("fractional-step leg done")
-            variants["uq_fractional_step"] = uq_fractional_step(ppe, torch, dev)
-            note("uncertainty over fractional steps done")
-        if not args.no_uq_collocation:
-            variants["uq_collocation"] = uq_collocation(ppe, torch, dev)
-            note("collocation leg done")
-        if not args.no_c3:
+        if want("c5"):
+            net, mu, sigma, tr = train_network(ppe, torch, wl, d_in, list(C5_TRAIN))
+            note(f"network trained on the plate run: {tr}")
+            variants["c5_plate"] = c5_legs(ppe, torch, wl, d_in, K, W, base, (net, mu, sigma))
+            variants["c5_plate"]["mixed_learned"]["training"] = tr
+        del d_in
+        torch.cuda.empty_cache()
+        if want("c3"):
             variants["c3_128cube"] = c3_leg(ppe, torch, dev)
             note("128^3 leg done")
-        if not args.no_c5:
-            variants["c5_plate_ribs"] = c5_leg(ppe, torch, dev, (net, mu, sigma))
-            note("plate-with-ribs leg done")
+        if want("c4"):
+            variants["c4_uq_batched"] = c4_leg(ppe, torch, dev)
+            note("batched uncertainty leg done")
+        if want("c2"):
+            variants["c2_64cube"] = c2_legs(ppe, torch, dev, K, W)
+            note("64^3 legs done")
+        if want("projection") or want("flow"):
+            wl2 = cube_workload(64)
+            st2 = list(range(C2_FIRST, C2_FIRST + K))
+            wa2 = list(range(C2_FIRST - W, C2_FIRST))
+            d2 = wl2.to_device(torch, dev, wa2 + st2)
+            b2 = run_leg(ppe, torch, wl2, d2, st2, wa2, "fp64")
+            if want("projection"):
+                variants["projection_cross_diffusion"] = projection_leg(ppe, torch, wl2, d2, st2,
+                                                                        wa2, dev, b2)
+                variants["projection_cross_diffusion_deferred"] = projection_leg(
+                    ppe, torch, wl2, d2, st2, wa2, dev, b2, "deferred")
+                note("projection legs done")
+            if want("flow"):
+                variants["fractional_step"] = fractional_step_leg(ppe, torch, dev, K, W)
+                variants["fractional_step_deferred"] = fractional_step_leg(ppe, torch, dev, K, W,
+                                                                           krylov="deferred")
+                note("fractional-step legs done")
+        if want("collocation"):
+            variants["uq_collocation"] = uq_collocation(ppe, torch, dev)
+            note("collocation leg done")
         out["variants"] = variants
-    if args.uq:
-        out.setdefault("variants", {})["uq_batched"] = uq_batched(ppe, torch, dev)
-        note("batched UQ leg done")
     if not args.no_cpu_baseline:
         note("timing the oracle on the host")
-        out["cpu_baseline"] = cpu_baseline(wl, steps)
+        out["cpu_baseline"] = cpu_baseline(wl, steps[0], base["first_iters"])
     print(json.dumps(out), flush=True)
 
 

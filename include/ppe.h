@@ -474,18 +474,26 @@ ppe_status ppe_pce_eval(ppe_pce* q, int32_t T, const double* xi, int64_t n_out, 
 ppe_status ppe_pce_stats(ppe_pce* q, int64_t n_out, const double* W, double* mean, double* var,
                          double* first, double* total);
 
-/* ---- Measurement of the dominant kernel. ----
- * While enabled, every launch of the finest-level fused Chebyshev smoothing
- * kernel (the operator applied most often per PCG iteration) is bracketed by
- * a pair of HIP events on the solver's stream, and the library adds up the
- * kernel times and the algorithmic bytes each launch moves (every stored
- * off-diagonal entry read once as 8-byte value + 4-byte column index, and
- * 8 bytes per row for each vector the step reads or writes: diagonal,
- * iterate in and out, right-hand side, search direction in (steps after the
- * first) and out).  Enabling resets the totals.  PPE_ERR_ARG on NULL. */
+/* ---- Per-kernel measurement of the solve. ----
+ * While enabled, every dispatch of the V-cycle and PCG kernels (level
+ * operators, smoothing steps, restriction, prolongation, coarsest solve,
+ * outer SpMV, vector updates and dots) is launched with its own pair of HIP
+ * events on the solver's stream (the events take the dispatch's start and
+ * end), and the library adds up, per kernel instantiation, the launches,
+ * the kernel time and the algorithmic bytes each launch moves: every stored
+ * matrix entry read once (value + 4-byte column index; 4-byte row pointers
+ * for CSR), each diagonal read once, and 8 bytes per row for every vector
+ * the kernel reads or writes.  Graph replay is off meanwhile.  Enabling
+ * resets the table.  PPE_ERR_ARG on NULL. */
 ppe_status ppe_profile_enable(ppe_solver* s, int enable);
-ppe_status ppe_profile_read(const ppe_solver* s, double* kernel_ms, double* bytes,
-                            int64_t* launches);
+/* *n_kernels = the number of kernel instantiations recorded so far. */
+ppe_status ppe_profile_count(const ppe_solver* s, int32_t* n_kernels);
+/* Entry k (0 <= k < count): name (NUL-terminated, truncated to name_cap
+ * bytes; the instantiation as a kernel trace prints it, such as
+ * "k_csr<2, 16, double>"), launches, summed kernel milliseconds and summed
+ * algorithmic bytes.  PPE_ERR_ARG for k out of range or NULL pointers. */
+ppe_status ppe_profile_entry(const ppe_solver* s, int32_t k, char* name, int32_t name_cap,
+                             int64_t* launches, double* kernel_ms, double* bytes);
 
 #ifdef __cplusplus
 }

@@ -186,9 +186,11 @@ _SIGS = {
     "ppe_flow_solid_fraction": (ctypes.c_int, [_P, ctypes.POINTER(ppe_alloy), ctypes.c_int64, _P,
                                                _P]),
     "ppe_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
-    "ppe_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
-                                        ctypes.POINTER(ctypes.c_double),
-                                        ctypes.POINTER(ctypes.c_int64)]),
+    "ppe_profile_count": (ctypes.c_int, [_P, ctypes.POINTER(_I32)]),
+    "ppe_profile_entry": (ctypes.c_int, [_P, _I32, ctypes.c_char_p, _I32,
+                                         ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double)]),
 }
 SYMBOLS = tuple(_SIGS)
 
@@ -520,10 +522,18 @@ class Solver:
         self._chk(self._lib.ppe_profile_enable(self._h, int(enable)))
 
     def profile_read(self):
-        ms, by, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
-        self._chk(self._lib.ppe_profile_read(self._h, ctypes.byref(ms), ctypes.byref(by),
-                                             ctypes.byref(n)))
-        return dict(kernel_ms=ms.value, bytes=by.value, launches=n.value)
+        """{kernel name: dict(launches, kernel_ms, bytes)} recorded since
+        profiling was enabled."""
+        cnt = _I32()
+        self._chk(self._lib.ppe_profile_count(self._h, ctypes.byref(cnt)))
+        out = {}
+        for k in range(cnt.value):
+            name = ctypes.create_string_buffer(256)
+            n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+            self._chk(self._lib.ppe_profile_entry(self._h, k, name, 256, ctypes.byref(n),
+                                                  ctypes.byref(ms), ctypes.byref(by)))
+            out[name.value.decode()] = dict(launches=n.value, kernel_ms=ms.value, bytes=by.value)
+        return out
 
     # ---- inspection (parity tests) ----
     def n_levels(self):

@@ -606,12 +606,27 @@ ppe_status ppe_profile_enable(ppe_solver* s, int enable) {
   });
 }
 
-ppe_status ppe_profile_read(const ppe_solver* s, double* kernel_ms, double* bytes,
-                            int64_t* launches) {
-  if (!s || !kernel_ms || !bytes || !launches) return PPE_ERR_ARG;
-  *kernel_ms = s->prof_ms;
-  *bytes = s->prof_bytes;
-  *launches = s->prof_launches;
+ppe_status ppe_profile_count(const ppe_solver* s, int32_t* n_kernels) {
+  if (!s || !n_kernels) return PPE_ERR_ARG;
+  return guarded(const_cast<ppe_solver*>(s), [&]() -> ppe_status {
+    DeviceGuard g(s->device);
+    ppe::profile_harvest(const_cast<ppe_solver*>(s));
+    *n_kernels = (int32_t)s->prof_table.size();
+    return PPE_OK;
+  });
+}
+
+ppe_status ppe_profile_entry(const ppe_solver* s, int32_t k, char* name, int32_t name_cap,
+                             int64_t* launches, double* kernel_ms, double* bytes) {
+  if (!s || !name || name_cap < 1 || !launches || !kernel_ms || !bytes) return PPE_ERR_ARG;
+  if (k < 0 || k >= (int32_t)s->prof_table.size()) return PPE_ERR_ARG;
+  const auto& e = s->prof_table[k];
+  const size_t len = std::min(e.name.size(), (size_t)name_cap - 1);
+  std::memcpy(name, e.name.data(), len);
+  name[len] = '\0';
+  *launches = e.launches;
+  *kernel_ms = e.ms;
+  *bytes = e.bytes;
   return PPE_OK;
 }
 

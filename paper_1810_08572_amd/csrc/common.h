@@ -12,6 +12,7 @@
 #include <array>
 #include <map>
 #include <vector>
+#include <utility>
 
 #include "../../include/ppe.h"
 
@@ -276,12 +277,22 @@ struct ppe_solver {
   ppe::DevBuf pj_k;  // BiCGSTAB vectors, partials and scalars
   ppe::DevBuf pj_ax, pj_kind, pj_list, pj_cnt, pj_cells;  // cross weights, face kinds, case-2 faces
 
-  // dominant-kernel measurement (event pairs around fine-level smoothing steps)
+  // per-kernel measurement of the solve phase (ppe_profile_*): while on,
+  // every V-cycle and PCG dispatch is timed by its own event pair, and the
+  // durations and algorithmic bytes are summed per kernel instantiation
+  struct ProfPending {
+    int entry;
+    double bytes;
+  };
+  struct ProfEntry {
+    std::string name;  // e.g. "k_csr<2, 16, double>", as a kernel trace names it
+    int64_t launches = 0;
+    double ms = 0.0, bytes = 0.0;
+  };
   bool prof = false;
   std::vector<hipEvent_t> prof_ev;
-  std::vector<double> prof_pending;  // bytes of each recorded pair
-  double prof_ms = 0.0, prof_bytes = 0.0;
-  int64_t prof_launches = 0;
+  std::vector<ProfPending> prof_pending;  // recorded pairs not yet read
+  std::vector<ProfEntry> prof_table;
 };
 
 namespace ppe {
@@ -580,5 +591,9 @@ ppe_status project(ppe_solver* s, const double* coeff, const double* ustar, doub
 void profile_harvest(ppe_solver* s);
 void drop_graph(ppe_solver* s);
 void profile_enable(ppe_solver* s, bool on);
+// The event pair for the next profiled dispatch of kernel `name` moving
+// `bytes` algorithmic bytes (earlier pairs are read first when all are in use).
+std::pair<hipEvent_t, hipEvent_t> profile_slot(ppe_solver* s, const std::string& name,
+                                               double bytes);
 
 }  // namespace ppe

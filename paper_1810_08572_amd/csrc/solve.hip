@@ -779,6 +779,68 @@ double* part(ppe_solver* s, int slot) {
 
 constexpr size_t kProfPairs = 256;
 
+template <class M> const char* tname();
+template <> const char* tname<double>() { return "double"; }
+template <> const char* tname<float>() { return "float"; }
+
+// "base<a, b, ...>" the way a kernel trace prints a template instantiation.
+std::string kname(const char* base, std::initializer_list<std::string> args) {
+  std::string n = base;
+  if (args.size()) {
+    n += "<";
+    bool first = true;
+    for (const auto& a : args) {
+      if (!first) n += ", ";
+      n += a;
+      first = false;
+    }
+    n += ">";
+  }
+  return n;
+}
+std::string str(int v) { return std::to_string(v); }
+std::string str(bool v) { return v ? "true" : "false"; }
+
+// Launch a solve-phase kernel on the solver's stream.  While profiling, the
+// dispatch takes its own event pair (hipExtLaunchKernelGGL records the
+// dispatch's start and end) and is booked under info() = {kernel name,
+// algorithmic bytes}; otherwise info is never evaluated.
+template <class Info, class K, class... Args>
+void launch(ppe_solver* s, Info&& info, K kernel, dim3 grid, dim3 block, Args... args) {
+  if (s->prof) {
+    const std::pair<std::string, double> nb = info();
+    const auto ev = profile_slot(s, nb.first, nb.second);
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s->stream, ev.first, ev.second, 0, args...);
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, 0, s->stream, args...);
+  }
+  PPE_LAUNCH_CHECK();
+}
+
+// Algorithmic bytes of a level operator step: every stored entry once
+// (value + column index), the row pointers (CSR), the diagonal and, when
+// the smoother scales by another diagonal, that one, and the vectors the
+// epilogue reads and writes (8 bytes each).
+template <int EPI, class M>
+double op_bytes(const ppe_solver* s, const Level& L, bool ell, double c1) {
+  const double n = L.n, m = sizeof(M);
+  const bool smoothing = EPI == E_CHEB || EPI == E_CHEB0;
+  const bool l1 = s->opt.smoother == PPE_SMOOTH_L1JACOBI;
+  double b = ell ? (double)(L.A.nnz - L.n) * (m + 4) + n * m     // off-diagonal ELL + diagonal
+                 : (double)L.A.nnz * (m + 4) + 4.0 * (n + 1);   // CSR rows hold the diagonal
+  if (smoothing && (l1 || !ell)) b += n * m;                    // the scaling diagonal
+  double vec = 0.0;
+  switch (EPI) {
+    case E_SPMV: vec = 2; break;                   // x, y
+    case E_RESID: vec = 3; break;                  // x, b, y
+    case E_CHEB: vec = c1 != 0.0 ? 5 : 4; break;   // x, b, (d in), d out, y
+    case E_CHEB0: vec = 3; break;                  // b, d out, y
+    case E_DOT: vec = 2; break;                    // x, y
+    default: vec = 2; break;
+  }
+  return b + 8.0 * vec * n;
+}
+
 // Launch an ELL kernel template K<WM> with the smallest unrolled width that
 // covers W (a generic slot loop beyond 12).
 #define PPE_ELL_WIDTH(W_, LAUNCH)                \
@@ -814,15 +876,22 @@ const M* smooth_diag(const ppe_solver* s, const Level& L) {
   return s->opt.smoother == PPE_SMOOTH_L1JACOBI ? LevelData<M>::l1(L) : LevelData<M>::diag(L);
 }
 
-// Lanes per row of the solve's CSR kernels by default: the fewest (a power of
-// two, 4 to 64) that reach half the mean row length, each lane then taking
-// about two entries whose loads are requested together.
-int solve_lanes(const Csr& M) {
-  const double mean = M.n ? (double)M.nnz / M.n : 1.0;
-  int lpr = 4;
-  while (lpr < 64 && 2 * lpr < mean) lpr *= 2;
-  return lpr;
+// Lanes per row of the solve's CSR kernels by default: the power of two from
+// 4 to 64 nearest (in ratio) to the mean row length over `per_lane`.  The
+// rules follow what the autotuner picked on the 128^3 cube and the 1.5 M-cell
+// plate: about four entries per lane for the smoothing steps, about two for
+// the restriction, the prolongation and the fused prolongation (whose rows of
+// A, P and A P are read together).
+int lanes_near(double target) {
+  int best = 4;
+  for (int c = 8; c <= 64; c *= 2)
+    if (std::fabs(std::log2((double)c / target)) < std::fabs(std::log2((double)best / target)))
+      best = c;
+  return best;
 }
+double mean_row(const Csr& M) { return M.n ? (double)M.nnz / M.n : 1.0; }
+int smooth_lanes(const Csr& A) { return lanes_near(mean_row(A) / 4.0); }
+int transfer_lanes(const Csr& M) { return lanes_near(mean_row(M) / 2.0); }
 
 // Apply the level operator with epilogue EPI, matrix values in type M.
 // Dot/power epilogues run on a capped grid and write partials to `partials`;
@@ -837,47 +906,33 @@ int apply_op(ppe_solver* s, const Level& L, const double* x, const double* b, do
   const M* sd = EPI == E_POWER ? LevelData<M>::diag(L) : smooth_diag<M>(s, L);
   if (&L == &s->levels[0] && EPI != E_POWER) {
     const int g = reduce ? red_grid(n) : grid_for(n);
-    const bool prof = s->prof && EPI == E_CHEB;
-    if (prof) {
-      // the event pair takes the dispatch's own start and end timestamps
-      if (s->prof_pending.size() == kProfPairs) profile_harvest(s);
-      const size_t k = s->prof_pending.size();
-#define PPE_ELL_PROF(WM_)                                                                     \
-  hipExtLaunchKernelGGL((k_ell<EPI, M, WM_>), dim3(g), dim3(kBlock), 0, s->stream,             \
-                        s->prof_ev[2 * k], s->prof_ev[2 * k + 1], 0, n, L.W,                   \
-                        L.ell_col.as<int>(), LevelData<M>::ell(L), LevelData<M>::diag(L), sd, \
-                        x, b, d, c1, c2, y, partials, c0)
-      PPE_ELL_WIDTH(L.W, PPE_ELL_PROF);
-#undef PPE_ELL_PROF
-    } else {
 #define PPE_ELL(WM_)                                                                           \
-  hipLaunchKernelGGL((k_ell<EPI, M, WM_>), dim3(g), dim3(kBlock), 0, s->stream, n, L.W,         \
-                     L.ell_col.as<int>(), LevelData<M>::ell(L), LevelData<M>::diag(L), sd, x,  \
-                     b, d, c1, c2, y, partials, c0)
-      PPE_ELL_WIDTH(L.W, PPE_ELL);
+  launch(s,                                                                                    \
+         [&]() {                                                                               \
+           return std::make_pair(kname("k_ell", {str(EPI), tname<M>(), str(WM_)}),            \
+                                 op_bytes<EPI, M>(s, L, true, c1));                           \
+         },                                                                                    \
+         k_ell<EPI, M, WM_>, dim3(g), dim3(kBlock), n, L.W, (const int*)L.ell_col.as<int>(),   \
+         LevelData<M>::ell(L), LevelData<M>::diag(L), sd, x, b, d, c1, c2, y, partials, c0)
+    PPE_ELL_WIDTH(L.W, PPE_ELL);
 #undef PPE_ELL
-    }
-    PPE_LAUNCH_CHECK();
-    if (prof) {
-      // off-diagonal entries, the diagonal, and the vectors x in, b, x out,
-      // d out (+ d in after the first step)
-      const double off = (double)(L.A.nnz - n);
-      const double vecs = (c1 != 0.0) ? 5.0 : 4.0;
-      s->prof_pending.push_back(off * (sizeof(M) + 4.0) + (double)n * sizeof(M) +
-                                vecs * sizeof(double) * n);
-    }
     return g;
   }
   // the setup's power steps keep the one-entry rule: the spectral bounds,
   // and with them the hierarchy, stay what they were
   const int lpr = L.lpr_a > 0     ? L.lpr_a
                   : EPI == E_POWER ? lanes_for(L.A)
-                                   : solve_lanes(L.A);
+                                   : smooth_lanes(L.A);
   const int g = reduce ? red_grid((int64_t)n * lpr) : grid_for((int64_t)n * lpr);
 #define PPE_CSR(LL)                                                                            \
-  hipLaunchKernelGGL((k_csr<EPI, LL, M>), dim3(g), dim3(kBlock), 0, s->stream, n, L.A.rp(),    \
-                     L.A.ci(), LevelData<M>::val(L.A), LevelData<M>::diag(L), sd, x, b, d, c1,  \
-                     c2, y, prevp, gprev, partials, c0)
+  launch(s,                                                                                    \
+         [&]() {                                                                               \
+           return std::make_pair(kname("k_csr", {str(EPI), str(LL), tname<M>()}),             \
+                                 op_bytes<EPI, M>(s, L, false, c1));                          \
+         },                                                                                    \
+         k_csr<EPI, LL, M>, dim3(g), dim3(kBlock), n, (const int*)L.A.rp(),                    \
+         (const int*)L.A.ci(), LevelData<M>::val(L.A), LevelData<M>::diag(L), sd, x, b, d, c1, \
+         c2, y, prevp, gprev, partials, c0)
   switch (lpr) {
     case 4: PPE_CSR(4); break;
     case 8: PPE_CSR(8); break;
@@ -886,18 +941,24 @@ int apply_op(ppe_solver* s, const Level& L, const double* x, const double* b, do
     default: PPE_CSR(64); break;
   }
 #undef PPE_CSR
-  PPE_LAUNCH_CHECK();
   return g;
 }
 
 template <bool ADD, class M>
 void apply_rect(ppe_solver* s, const Csr& P, const double* x, double* y, int lpr_choice = 0) {
   if (P.n == 0) return;
-  const int lpr = lpr_choice > 0 ? lpr_choice : solve_lanes(P);
+  const int lpr = lpr_choice > 0 ? lpr_choice : transfer_lanes(P);
   const int g = grid_for((int64_t)P.n * lpr);
+  // entries and row pointers of P or R, each operand entry once, y out (and in)
+  auto bytes = [&]() {
+    return (double)P.nnz * (sizeof(M) + 4) + 4.0 * (P.n + 1) + 8.0 * P.m +
+           8.0 * P.n * (ADD ? 2 : 1);
+  };
 #define PPE_RECT(LL)                                                                           \
-  hipLaunchKernelGGL((k_csr_rect<LL, ADD, M>), dim3(g), dim3(kBlock), 0, s->stream, P.n, P.rp(), \
-                     P.ci(), LevelData<M>::val(P), x, y)
+  launch(s, [&]() { return std::make_pair(kname("k_csr_rect", {str(LL), str(ADD), tname<M>()}), \
+                                          bytes()); },                                         \
+         k_csr_rect<LL, ADD, M>, dim3(g), dim3(kBlock), P.n, (const int*)P.rp(),               \
+         (const int*)P.ci(), LevelData<M>::val(P), x, y)
   switch (lpr) {
     case 4: PPE_RECT(4); break;
     case 8: PPE_RECT(8); break;
@@ -906,7 +967,6 @@ void apply_rect(ppe_solver* s, const Csr& P, const double* x, double* y, int lpr
     default: PPE_RECT(64); break;
   }
 #undef PPE_RECT
-  PPE_LAUNCH_CHECK();
 }
 
 // Whether level L's prolongation runs fused with its first post-smoothing
@@ -923,14 +983,11 @@ bool prolong_fusable(const ppe_solver* s, const Level& L) {
   return s->opt.precision != PPE_MIXED && &L != &s->levels[0] && L.ap_ok && !L.c1.empty();
 }
 
-// Lanes per row of the fused pass: the launch choice if set, else the fewest
-// whose first chunks cover the longest row of A, P and AP.
+// Lanes per row of the fused pass: the launch choice if set, else about two
+// entries of A per lane (rows past the first chunk continue lane by lane).
 int prolong_lanes(const Level& L) {
   if (L.lpr_p > 0) return L.lpr_p;
-  const int need = std::max(std::max(L.P.maxrow, L.AP.maxrow), L.A.maxrow);
-  int lpr = 4;
-  while (lpr < 64 && lpr * kFuseU < need) lpr *= 2;
-  return lpr;
+  return transfer_lanes(L.A);
 }
 
 // y = (x1 + P e) + d with d = c2 D^-1 (b - A (x1 + P e)): the prolongation
@@ -942,11 +999,20 @@ void prolong_cheb(ppe_solver* s, Level& L, const double* e, const double* x1, co
   const int lpr = prolong_lanes(L);
   const int g = grid_for((int64_t)n * lpr);
   const double c2 = L.inv_theta;
+  // entries and row pointers of A, P and AP, the scaling diagonal, e, and
+  // x1, b in with d, y out
+  auto bytes = [&]() {
+    return (double)(L.A.nnz + L.P.nnz + L.AP.nnz) * (sizeof(M) + 4) + 12.0 * (n + 1) +
+           (double)n * sizeof(M) + 8.0 * L.P.m + 8.0 * 4 * n;
+  };
 #define PPE_PC_CSR(LL)                                                                         \
-  hipLaunchKernelGGL((k_csr_prolong_cheb<M, LL>), dim3(g), dim3(kBlock), 0, s->stream, n,       \
-                     L.A.rp(), L.A.ci(), LevelData<M>::val(L.A), smooth_diag<M>(s, L), L.P.rp(), \
-                     L.P.ci(), LevelData<M>::val(L.P), L.AP.rp(), L.AP.ci(),                    \
-                     LevelData<M>::val(L.AP), e, x1, b, d, c2, y)
+  launch(s, [&]() { return std::make_pair(kname("k_csr_prolong_cheb", {tname<M>(), str(LL)}),   \
+                                          bytes()); },                                         \
+         k_csr_prolong_cheb<M, LL>, dim3(g), dim3(kBlock), n, (const int*)L.A.rp(),            \
+         (const int*)L.A.ci(), LevelData<M>::val(L.A), smooth_diag<M>(s, L),                  \
+         (const int*)L.P.rp(), (const int*)L.P.ci(), LevelData<M>::val(L.P),                  \
+         (const int*)L.AP.rp(), (const int*)L.AP.ci(), LevelData<M>::val(L.AP), e, x1, b, d,   \
+         c2, y)
   switch (lpr) {
     case 4: PPE_PC_CSR(4); break;
     case 8: PPE_PC_CSR(8); break;
@@ -955,7 +1021,6 @@ void prolong_cheb(ppe_solver* s, Level& L, const double* e, const double* x1, co
     default: PPE_PC_CSR(64); break;
   }
 #undef PPE_PC_CSR
-  PPE_LAUNCH_CHECK();
 }
 
 // PCG dot fused into the last level-0 step of the V-cycle: tile partials of
@@ -992,9 +1057,13 @@ bool smooth(ppe_solver* s, Level& L, const double* b, const double* x_in, double
       step = 3;
     } else {
       double* dst = dst_of(1);
-      hipLaunchKernelGGL(k_cheb_first<M>, dim3(grid_for(n)), dim3(kBlock), 0, s->stream, n, b,
-                         smooth_diag<M>(s, L), L.inv_theta, d, dst);
-      PPE_LAUNCH_CHECK();
+      launch(s,
+             [&]() {
+               return std::make_pair(kname("k_cheb_first", {tname<M>()}),
+                                     (double)n * (sizeof(M) + 24.0));  // sd, b in; d, x out
+             },
+             k_cheb_first<M>, dim3(grid_for(n)), dim3(kBlock), n, (const double*)b,
+             smooth_diag<M>(s, L), L.inv_theta, d, dst);
       cur = dst;
       step = 2;
     }
@@ -1018,13 +1087,16 @@ bool smooth_steps(ppe_solver* s, Level& L, const double* b, const double* cur, i
     const double c2 = step == 1 ? L.inv_theta : L.c2[step - 2];
     if (dot && step == deg && &L == &s->levels[0]) {
 #define PPE_CHEB_DOT(WM_)                                                                     \
-  hipLaunchKernelGGL((k_ell_cheb_dot_t<WM_, M>), dim3(dot->nt), dim3(kBlock), 0, s->stream,     \
-                     dot->T, n, L.W, L.ell_col.as<int>(), LevelData<M>::ell(L),                 \
-                     LevelData<M>::diag(L), smooth_diag<M>(s, L), cur, b, d, c1, c2, dst,       \
-                     dot->part)
+  launch(s,                                                                                    \
+         [&]() {                                                                               \
+           return std::make_pair(kname("k_ell_cheb_dot_t", {str(WM_), tname<M>()}),           \
+                                 op_bytes<E_CHEB, M>(s, L, true, c1));                        \
+         },                                                                                    \
+         k_ell_cheb_dot_t<WM_, M>, dim3(dot->nt), dim3(kBlock), dot->T, n, L.W,                \
+         (const int*)L.ell_col.as<int>(), LevelData<M>::ell(L), LevelData<M>::diag(L),         \
+         smooth_diag<M>(s, L), cur, b, d, c1, c2, dst, dot->part)
       PPE_ELL_WIDTH(L.W, PPE_CHEB_DOT);
 #undef PPE_CHEB_DOT
-      PPE_LAUNCH_CHECK();
       dotted = true;
       cur = dst;
       continue;
@@ -1047,9 +1119,13 @@ bool vcycle_t(ppe_solver* s, int l, const double* b, double* x, const PcgDot* do
   double* xb = L.d2.as<double>();
   if (l == s->nlev - 1) {
     if (L.dense) {
-      hipLaunchKernelGGL(k_dense_gemv, dim3(grid_for((int64_t)n * kWave)), dim3(kBlock), 0,
-                         s->stream, n, L.Ainv.as<double>(), b, x);
-      PPE_LAUNCH_CHECK();
+      launch(s,
+             [&]() {
+               return std::make_pair(std::string("k_dense_gemv"),
+                                     8.0 * (double)n * n + 16.0 * n);  // inverse, b, x
+             },
+             k_dense_gemv, dim3(grid_for((int64_t)n * kWave)), dim3(kBlock), n,
+             (const double*)L.Ainv.as<double>(), b, x);
       return false;
     }
     double* t = L.r.as<double>();
@@ -1096,10 +1172,11 @@ void profile_harvest(ppe_solver* s) {
   for (size_t i = 0; i < k; ++i) {
     float ms = 0.f;
     PPE_HIP(hipEventElapsedTime(&ms, s->prof_ev[2 * i], s->prof_ev[2 * i + 1]));
-    s->prof_ms += ms;
-    s->prof_bytes += s->prof_pending[i];
+    auto& e = s->prof_table[s->prof_pending[i].entry];
+    e.ms += ms;
+    e.bytes += s->prof_pending[i].bytes;
+    e.launches += 1;
   }
-  s->prof_launches += (int64_t)k;
   s->prof_pending.clear();
 }
 
@@ -1110,11 +1187,22 @@ void profile_enable(ppe_solver* s, bool on) {
   }
   profile_harvest(s);
   s->prof = on;
-  if (on) {
-    s->prof_ms = 0.0;
-    s->prof_bytes = 0.0;
-    s->prof_launches = 0;
+  if (on) s->prof_table.clear();
+}
+
+std::pair<hipEvent_t, hipEvent_t> profile_slot(ppe_solver* s, const std::string& name,
+                                               double bytes) {
+  if (s->prof_pending.size() == kProfPairs) profile_harvest(s);
+  int entry = -1;
+  for (size_t i = 0; i < s->prof_table.size(); ++i)
+    if (s->prof_table[i].name == name) entry = (int)i;
+  if (entry < 0) {
+    s->prof_table.push_back(ppe_solver::ProfEntry{name});
+    entry = (int)s->prof_table.size() - 1;
   }
+  const size_t k = s->prof_pending.size();
+  s->prof_pending.push_back(ppe_solver::ProfPending{entry, bytes});
+  return {s->prof_ev[2 * k], s->prof_ev[2 * k + 1]};
 }
 
 void spmv(ppe_solver* s, const Level& L, const double* x, double* y) {
@@ -1145,7 +1233,11 @@ void prepare_solve_levels(ppe_solver* s) {
   for (int l = 0; l < s->nlev; ++l) {
     Level& L = s->levels[l];
     L.lpr_a = L.lpr_r = L.lpr_p = 0;
-    L.fuse0 = true;
+    // The fused first two steps gather b and the scaling diagonal (and divide)
+    // for every stored entry; on CSR levels with long rows one elementwise
+    // pass that forms the first iterate costs less (the autotuner split them
+    // on the 128^3 cube's levels of 34 and 219 entries per row).
+    L.fuse0 = l == 0 || mean_row(L.A) <= 24.0;
     const int n = L.n > 0 ? L.n : 1;
     L.x.get<double>(n);
     L.b.get<double>(n);
@@ -1204,10 +1296,9 @@ void vcycle(ppe_solver* s, int l, const double* b, double* x) {
 static void vcycle_pcg(ppe_solver* s, const double* r, double* z, const PcgDot& dot) {
   const bool dotted = s->opt.precision == PPE_MIXED ? vcycle_t<float>(s, 0, r, z, &dot)
                                                     : vcycle_t<double>(s, 0, r, z, &dot);
-  if (!dotted) {
-    hipLaunchKernelGGL(k_dot_t, dim3(dot.nt), dim3(kBlock), 0, s->stream, dot.T, r, z, dot.part);
-    PPE_LAUNCH_CHECK();
-  }
+  if (!dotted)
+    launch(s, [&]() { return std::make_pair(std::string("k_dot_t"), 16.0 * s->n_active); },
+           k_dot_t, dim3(dot.nt), dim3(kBlock), dot.T, r, (const double*)z, dot.part);
 }
 
 // FP32 copies of the hierarchy's values for the mixed-precision V-cycle:
@@ -1379,20 +1470,28 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
   // left untouched by every kernel, so extra iterations change nothing.
   auto body = [&](int sl) {
 #define PPE_ELL_DOT(WM_)                                                                      \
-  hipLaunchKernelGGL((k_ell_dot_t<WM_>), dim3(nt), dim3(kBlock), 0, s->stream, T, na, L0.W,     \
-                     L0.ell_col.as<int>(), L0.ell_val.as<double>(), L0.diag.as<double>(), done, \
-                     p, q, tpart(T_PQ))
+  launch(s,                                                                                    \
+         [&]() {                                                                               \
+           return std::make_pair(kname("k_ell_dot_t", {str(WM_)}),                            \
+                                 op_bytes<E_SPMV, double>(s, L0, true, 0.0));                 \
+         },                                                                                    \
+         k_ell_dot_t<WM_>, dim3(nt), dim3(kBlock), T, na, L0.W,                                \
+         (const int*)L0.ell_col.as<int>(), (const double*)L0.ell_val.as<double>(),              \
+         (const double*)L0.diag.as<double>(), (const int*)done, (const double*)p, q,           \
+         tpart(T_PQ))
     PPE_ELL_WIDTH(L0.W, PPE_ELL_DOT);
 #undef PPE_ELL_DOT
-    PPE_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_update_xr_t, dim3(nt), dim3(kBlock), 0, s->stream, T, done, rz[sl],
-                       tpart(T_PQ), p, q, x, r, tpart(T_RR), cnt, cnt + 1);
-    PPE_LAUNCH_CHECK();
+    // x, p, r, q in; x, r out
+    launch(s, [&]() { return std::make_pair(std::string("k_update_xr_t"), 48.0 * na); },
+           k_update_xr_t, dim3(nt), dim3(kBlock), T, (const int*)done, (const double*)rz[sl],
+           (const double*)tpart(T_PQ), (const double*)p, (const double*)q, x, r, tpart(T_RR),
+           cnt, cnt + 1);
     precondition(sl);
-    hipLaunchKernelGGL(k_update_p_t, dim3(nt), dim3(kBlock), 0, s->stream, T, ns, 1, done,
-                       restart, tpart(T_RR), sc, iters, cnt, tpart(T_RZ), rz[sl], rz[1 - sl],
-                       zb[sl], p, cnt + 1);
-    PPE_LAUNCH_CHECK();
+    // z, p in; p out
+    launch(s, [&]() { return std::make_pair(std::string("k_update_p_t"), 24.0 * na); },
+           k_update_p_t, dim3(nt), dim3(kBlock), T, ns, 1, done, restart,
+           (const double*)tpart(T_RR), (const double*)sc, iters, cnt, (const double*)tpart(T_RZ),
+           (const double*)rz[sl], rz[1 - sl], (const double*)zb[sl], p, cnt + 1);
   };
   // Two iterations (both rz slots) captured into a HIP graph on the second
   // solve with one hierarchy (a single solve per assembly would pay the
@@ -1525,7 +1624,7 @@ void tune_level(ppe_solver* s, int l) {
   double* y = L.x2.as<double>();
   const double c1 = L.c1.empty() ? 0.0 : L.c1[0], c2 = L.c1.empty() ? L.inv_theta : L.c2[0];
   if (l > 0)
-    L.lpr_a = best_lpr(s, solve_lanes(L.A), [&](int c) {
+    L.lpr_a = best_lpr(s, smooth_lanes(L.A), [&](int c) {
       L.lpr_a = c;
       apply_op<E_CHEB, M>(s, L, x, b, d, c1, c2, y, nullptr);
     });
@@ -1542,7 +1641,7 @@ void tune_level(ppe_solver* s, int l) {
   }
   if (coarsest) return;
   Level& C = s->levels[l + 1];
-  L.lpr_r = best_lpr(s, solve_lanes(L.R), [&](int c) {
+  L.lpr_r = best_lpr(s, transfer_lanes(L.R), [&](int c) {
     apply_rect<false, M>(s, L.R, L.r.as<double>(), C.b.as<double>(), c);
   });
   if (prolong_fusable(s, L)) {
@@ -1553,7 +1652,7 @@ void tune_level(ppe_solver* s, int l) {
     });
     return;
   }
-  L.lpr_p = best_lpr(s, solve_lanes(L.P), [&](int c) {
+  L.lpr_p = best_lpr(s, transfer_lanes(L.P), [&](int c) {
     apply_rect<true, M>(s, L.P, C.x.as<double>(), L.t.as<double>(), c);
   });
 }

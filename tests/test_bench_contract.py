@@ -30,8 +30,8 @@ def test_a_distributed_launch_is_refused():
 
 
 def test_counter_traffic_is_reported_only_for_the_current_kernel():
-    # counters are reported only while the roofline kernel's source region
-    # hashes as it did when they were taken; otherwise the traffic is None
+    # counters are reported only for the kernel they were taken on, and only
+    # while its source region hashes as it did then; otherwise None
     import hashlib
     import json
 
@@ -39,10 +39,11 @@ def test_counter_traffic_is_reported_only_for_the_current_kernel():
         data = json.load(f)
     with open(os.path.join(ROOT, data["source_file"])) as f:
         text = f.read()
-    begin, end = data["source_region"]
-    current = begin in text and end in text and hashlib.sha256(
-        text[text.index(begin):text.index(end)].encode()).hexdigest() == data["source_sha256"]
-    for workload in data["workloads"]:
-        t = bench.counter_traffic(workload)
+    for workload, e in data["workloads"].items():
+        begin, end = e["source_region"]
+        current = begin in text and end in text and hashlib.sha256(
+            text[text.index(begin):text.index(end)].encode()).hexdigest() == e["source_sha256"]
+        t = bench.counter_traffic(workload, e["kernel"])
         assert (t is not None and t > 0) if current else t is None, workload
-    assert bench.counter_traffic("no_such_workload") is None
+        assert bench.counter_traffic(workload, "k_no_such_kernel") is None
+    assert bench.counter_traffic("no_such_workload", "k_csr<2, 16, double>") is None

@@ -184,27 +184,38 @@ def test_reuse_of_an_unchanged_system():
     assert e.value.status == ppe.PPE_ERR_ARG
 
 
-def test_profile_times_the_finest_chebyshev_step():
-    """With profiling on, the finest level's first post-smoothing step (the
-    ELL Chebyshev step from x = x1 + P e) is timed once per V-cycle, and
-    each launch is credited with its algorithmic bytes: the stored
-    off-diagonal entries of A (8-byte value + 4-byte column) and five
-    vectors (diagonal, iterate in and out, right-hand side, step update)."""
+def test_profile_times_every_solve_kernel():
+    """With profiling on, each V-cycle and PCG dispatch is timed and booked
+    under its kernel instantiation with its algorithmic bytes.  The finest
+    level's first post-smoothing step (the ELL step from x = x1 + P e, with
+    no previous update to read) runs once per V-cycle and moves the stored
+    off-diagonal entries (8-byte value + 4-byte column), the diagonal and
+    four vectors (iterate in and out, right-hand side, step update); the
+    outer q = A p moves the same entries, the diagonal, p and q; the x, r
+    update six vectors and the p update three."""
     import torch
 
     m, f, c, b = case(shape=(24, 24, 24), fl="front", fl_seed=2, seed=2)
     s = gpu_solver(m, f, c)
     i0 = s.level_info(0)
-    n = i0["n"]
+    n, off = i0["n"], i0["nnz"] - i0["n"]
     s.profile(True)
     res = s.solve(to_dev(b, torch.float64))
     prof = s.profile_read()
     s.profile(False)
     assert res.status == 0
-    assert prof["launches"] >= res.stats["iterations"] >= 1
-    assert prof["kernel_ms"] > 0.0
-    expect = 12.0 * (i0["nnz"] - n) + 5 * 8.0 * n
-    assert prof["bytes"] == expect * prof["launches"]
-    # profiling off: the totals stay as they were
+    it = res.stats["iterations"]
+    cheb = prof["k_ell<2, double, 6>"]
+    assert cheb["launches"] >= it >= 1 and cheb["kernel_ms"] > 0.0
+    assert cheb["bytes"] == (12.0 * off + 8.0 * n + 4 * 8.0 * n) * cheb["launches"]
+    spmv = prof["k_ell_dot_t<6>"]
+    assert spmv["launches"] >= it
+    assert spmv["bytes"] == (12.0 * off + 8.0 * n + 2 * 8.0 * n) * spmv["launches"]
+    assert prof["k_update_xr_t"]["bytes"] == 48.0 * n * prof["k_update_xr_t"]["launches"]
+    assert prof["k_update_p_t"]["bytes"] == 24.0 * n * prof["k_update_p_t"]["launches"]
+    assert any(k.startswith("k_csr<") for k in prof)          # coarse levels
+    assert "k_dense_gemv" in prof                              # coarsest level
+    assert all(v["kernel_ms"] > 0 and v["bytes"] > 0 for v in prof.values())
+    # profiling off: the table stays as it was
     s.solve(to_dev(b, torch.float64))
-    assert s.profile_read()["launches"] == prof["launches"]
+    assert s.profile_read() == prof
