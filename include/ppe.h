@@ -123,6 +123,18 @@ typedef struct {
                          hipFree.  Setting one without the other is PPE_ERR_ARG. */
   ppe_free_fn free;
   void* alloc_ctx;    /* passed to alloc and free */
+  int coarse_reuse;   /* > 0: after a full setup, up to this many later pressure
+                         assemblies whose active set differs from that build's
+                         in at most 10% of its cells keep its coarse levels and
+                         rebuild only the finest one: the new masked operator,
+                         its diagonal and Gershgorin bound, and a prolongator
+                         made of the earlier finest prolongator's rows of the
+                         same cells (empty for pins and for cells that build
+                         did not have), R = P^T.  The V-cycle stays a symmetric
+                         positive definite preconditioner of the new system, so
+                         the solve meets the same tolerance; only its
+                         iteration count may differ from a fresh setup's.
+                         Default 0: every changed mask gets a full setup. */
 } ppe_options;
 
 typedef struct {
@@ -136,6 +148,8 @@ typedef struct {
   double op_complexity;  /* sum of level nnz / finest nnz */
   double bytes_per_iter; /* algorithmic bytes one PCG iteration moves */
   int reused_setup;      /* assemblies that kept an unchanged system (reuse_unchanged) */
+  int coarse_reused;     /* assemblies that kept the coarse levels of an earlier
+                            build across a changed mask (coarse_reuse) */
 } ppe_stats;
 
 /* Fill *opt with the defaults listed above. */
@@ -333,7 +347,9 @@ ppe_status ppe_copy_level_matrix(const ppe_solver* s, int level, int32_t* row_pt
 ppe_status ppe_copy_prolongator(const ppe_solver* s, int level, int32_t* row_ptr,
                                 int32_t* col, double* val);
 
-/* Copy the aggregate id of every row of level l (-1: not aggregated). */
+/* Copy the aggregate id of every row of level l (-1: not aggregated).
+ * PPE_ERR_STATE for level 0 after an assembly that kept the coarse levels
+ * of an earlier build (coarse_reuse): that finest level has no aggregates. */
 ppe_status ppe_copy_aggregates(const ppe_solver* s, int level, int32_t* agg);
 
 /* Masking outputs on the finest level: compact id per cell (-1 removed) and

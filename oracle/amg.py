@@ -39,7 +39,11 @@ parameter.  This project's reading is smoothed aggregation:
   cycle      V-cycle with the same smoother before and after the coarse
              correction (so the preconditioner is symmetric); the coarsest
              level (at most coarse_max rows, default 128) is solved with a
-             dense inverse.
+             dense inverse;
+  reuse      (optional) after a mask change, keep the coarse levels of an
+             earlier hierarchy and rebuild only the finest one, its
+             prolongator's rows re-indexed to the new active cells
+             (reuse_coarse_levels).
 """
 from __future__ import annotations
 
@@ -306,6 +310,39 @@ def build_hierarchy(A0: sp.csr_matrix, theta=0.08, coarse_max=128, max_levels=10
         c = sla.cho_factor(last.A.toarray(), lower=True)
         last.Ainv = sla.cho_solve(c, np.eye(last.A.shape[0]))
     return H
+
+
+def reuse_coarse_levels(H: Hierarchy, A_new: sp.csr_matrix, base_row, pinned) -> Hierarchy:
+    """A hierarchy for a new masked operator that keeps the coarse levels of H.
+
+    Level 0 becomes A_new, with its own diagonal, Gershgorin bound and row l1
+    norms.  Its prolongator takes, for every row i of A_new, row base_row[i]
+    of H's finest prolongator (the same cell in H's numbering); rows of pinned
+    cells and of cells H did not have (base_row < 0) are empty.  R = P^T.
+    Every coarser level is H's own.  The V-cycle stays symmetric with SPD
+    coarse operators, so it is still an SPD preconditioner of A_new, and
+    nothing of the aggregation or the Galerkin products is recomputed."""
+    A_new = A_new.tocsr()
+    base_row = np.asarray(base_row)
+    pinned = np.asarray(pinned, dtype=bool)
+    P0 = H.levels[0].P.tocsr()
+    keep = (base_row >= 0) & ~pinned
+    rows = np.nonzero(keep)[0]
+    lengths = np.zeros(A_new.shape[0], dtype=np.int64)
+    lengths[rows] = np.diff(P0.indptr)[base_row[rows]]
+    indptr = np.concatenate([[0], np.cumsum(lengths)])
+    cols = np.concatenate([P0.indices[P0.indptr[o]:P0.indptr[o + 1]] for o in base_row[rows]]) \
+        if rows.size else np.zeros(0, dtype=np.int64)
+    vals = np.concatenate([P0.data[P0.indptr[o]:P0.indptr[o + 1]] for o in base_row[rows]]) \
+        if rows.size else np.zeros(0)
+    P = sp.csr_matrix((vals, cols, indptr), shape=(A_new.shape[0], P0.shape[1]))
+    lev0 = Level(A=A_new, diag=A_new.diagonal().copy(), rho=spectral_bound(A_new, 0),
+                 B=np.ones(A_new.shape[0]), dl1=l1_diagonal(A_new))
+    lev0.P, lev0.R = P, P.T.tocsr()
+    lev0.agg, lev0.n_agg = None, P0.shape[1]
+    G = Hierarchy(degree=H.degree, ratio=H.ratio, smoother=H.smoother)
+    G.levels = [lev0] + list(H.levels[1:])
+    return G
 
 
 def _smooth(H: Hierarchy, lev: Level, b, x):

@@ -44,10 +44,15 @@ What one step computes, and where the paper defines it:
       S_c = (rho L_f V/dt) (f_s^m - f_s^n - f_s'(T^m) T^m)
   (reading: Eq. 18 is the latent term integrated over the cell and the
   step; divided by the step it carries rho/dt, as Eq. 4 does), with
-  C^T = rho c_p sum s_if F^(n+1)_f (T^n_C1 + T^n_C2)/2, then
-  f_s^(m+1) = (1 - lambda) f_s^m + lambda f_s(T^(m+1)) (lambda = 1 by
+  C^T = rho c_p sum s_if F^(n+1)_f (T^n_C1 + T^n_C2)/2.  The solved
+  temperature T* becomes T^(m+1) except where it lies beyond a kink of
+  Eq. 21 seen from T^m: there the cell stops at the first kink it crosses
+  (reading: Eq. 19-20 are Newton's linearisation of a piecewise-smooth
+  relation, which cycles when a cell jumps across a kink in one pass; the
+  limit changes the path only, since at convergence no cell crosses a kink).
+  Then f_s^(m+1) = (1 - lambda) f_s^m + lambda f_s(T^(m+1)) (lambda = 1 by
   default, as the paper finds for its aluminium alloy), until
-  max|T^(m+1) - T^m| <= tol max|T^(m+1)| and max|f_s^(m+1) - f_s^m| <= tol.
+  max|T* - T^m| <= tol max|T^(m+1)| and max|f_s^(m+1) - f_s^m| <= tol.
   Walls are held at T_wall, or insulated (T_wall None).
 * Mask evolution: cells with f_s^(n+1) = 1 get u = 0, faces no longer open
   under the new mask get F = 0 (reading: they are blocked from now on).
@@ -277,10 +282,41 @@ def momentum_predictor(geo: Geometry, a, st: State, dt):
 
 
 # ------------------------------------------------ step 4 (Eq. 4, 18-21)
+def branch_limited(T_prev, T_solved, a):
+    """The next Picard iterate: T_solved, except that a cell whose solved
+    temperature lies beyond a kink of Eq. 21 (T_liq, T_sol + T_eps,
+    T_sol - T_eps) as seen from T_prev stops at the first kink it crosses.
+    A cell already on a kink moves freely; the kink belongs to the branch
+    below it (Eq. 21's liquid branch is T > T_liq, its band is closed), so
+    the next pass linearises with the slope of the branch the cell entered.
+    At convergence no cell crosses a kink, so the fixed point is the plain
+    iteration's."""
+    a = Props.of(a)
+    out = np.array(T_solved, dtype=np.float64, copy=True)
+    lo = np.minimum(T_prev, T_solved)
+    hi = np.maximum(T_prev, T_solved)
+    down = T_solved < T_prev
+    done = np.zeros(out.shape, dtype=bool)
+    kinks = (a.T_liq, a.T_sol + a.T_eps, a.T_sol - a.T_eps)
+    # cooling cells stop at the highest kink strictly between, heating ones at the lowest
+    for K in kinks:
+        hit = down & ~done & (lo < K) & (K < hi)
+        out[hit] = K
+        done |= hit
+    done[:] = False
+    for K in reversed(kinks):
+        hit = ~down & ~done & (lo < K) & (K < hi)
+        out[hit] = K
+        done |= hit
+    return out
+
+
 def energy(geo: Geometry, a, st: State, F_new, dt, tol=1e-10, max_picard=50, relax=1.0):
     """T^(n+1), f_s^(n+1), C^T (for the next step) and the Picard count
     (negative when max_picard passes did not converge).  relax is the
-    under-relaxation lambda of the f_s update (0 < lambda <= 1)."""
+    under-relaxation lambda of the f_s update (0 < lambda <= 1).  Each
+    pass's new iterate is branch_limited: Newton's linearisation of Eq. 19
+    is kept, and a cell does not jump over a kink of Eq. 21 in one pass."""
     a = Props.of(a)
     rcv = a.rho * a.cp * geo.V / dt
     rlv = a.rho * a.Lf * geo.V / dt
@@ -298,9 +334,10 @@ def energy(geo: Geometry, a, st: State, F_new, dt, tol=1e-10, max_picard=50, rel
         Sp = rlv * slope
         Sc = rlv * (fm - st.fs - slope * Tm)
         A = (sp.diags(rcv - Sp + 0.5 * a.k * Wk) + L).tocsc()
-        Tn = spla.spsolve(A, base + Sc)
+        Ts = spla.spsolve(A, base + Sc)
+        Tn = branch_limited(Tm, Ts, a)
         fn = (1.0 - relax) * fm + relax * solid_fraction(Tn, a)
-        dT = np.abs(Tn - Tm).max()
+        dT = np.abs(Ts - Tm).max()
         df = np.abs(fn - fm).max()
         Tm, fm = Tn, fn
         if dT <= tol * np.abs(Tn).max() and df <= tol:

@@ -51,6 +51,7 @@ class ppe_options(ctypes.Structure):
         ("alloc", ctypes.c_void_p),
         ("free", ctypes.c_void_p),
         ("alloc_ctx", ctypes.c_void_p),
+        ("coarse_reuse", ctypes.c_int),
     ]
 
 
@@ -66,6 +67,7 @@ class ppe_stats(ctypes.Structure):
         ("op_complexity", ctypes.c_double),
         ("bytes_per_iter", ctypes.c_double),
         ("reused_setup", ctypes.c_int),
+        ("coarse_reused", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -353,7 +355,7 @@ class Solver:
     def __init__(self, precision="fp64", rtol=1e-10, max_iter=500, cheb_degree=2,
                  cheb_ratio=30.0, coarse_max=128, max_levels=10, theta=0.08, stream=None,
                  use_graph=True, check_every=2, autotune=False, reuse_unchanged=False,
-                 krylov="bicgstab", smoother="chebyshev", allocator="torch"):
+                 krylov="bicgstab", smoother="chebyshev", allocator="torch", coarse_reuse=0):
         import torch
 
         lib = load_library()
@@ -366,6 +368,7 @@ class Solver:
         o.use_graph, o.check_every = int(bool(use_graph)), int(check_every)
         o.autotune = int(bool(autotune))
         o.reuse_unchanged = int(bool(reuse_unchanged))
+        o.coarse_reuse = int(coarse_reuse)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

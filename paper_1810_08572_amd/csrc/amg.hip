@@ -1245,6 +1245,113 @@ void ensure_side_stream(ppe_solver* s) {
 
 }  // namespace
 
+// ---- coarse levels kept across a changed mask
+namespace {
+
+// Row i of the re-indexed finest prolongator: the base build's row of the
+// same cell, or empty for a pin or a cell that build did not have.  cnt[i]
+// is its length; matched[i] = 1 if the cell had a row in the base build.
+__global__ void k_reuse_rows(int na, const int* __restrict__ perm, const int* __restrict__ comp,
+                             const int* __restrict__ base_cid, const int* __restrict__ base_rp,
+                             int* __restrict__ cnt, int* __restrict__ matched) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= na) return;
+  const int c = perm[i];
+  const int o = base_cid[c];
+  cnt[i] = (o >= 0 && comp[c] != c) ? base_rp[o + 1] - base_rp[o] : 0;
+  matched[i] = o >= 0 ? 1 : 0;
+}
+
+__global__ void k_reuse_fill(int na, const int* __restrict__ perm, const int* __restrict__ comp,
+                             const int* __restrict__ base_cid, const int* __restrict__ base_rp,
+                             const int* __restrict__ base_ci, const double* __restrict__ base_v,
+                             const int* __restrict__ rp, int* __restrict__ ci,
+                             double* __restrict__ v) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= na) return;
+  const int c = perm[i];
+  const int o = base_cid[c];
+  if (o < 0 || comp[c] == c) return;
+  const int src = base_rp[o], len = base_rp[o + 1] - src, dst = rp[i];
+  for (int k = 0; k < len; ++k) {
+    ci[dst + k] = base_ci[src + k];
+    v[dst + k] = base_v[src + k];
+  }
+}
+
+}  // namespace
+
+void keep_base(ppe_solver* s) {
+  s->have_base = false;
+  if (s->opt.coarse_reuse <= 0 || s->shifted || s->nlev < 2) return;
+  const int nc = s->n_cells;
+  const Csr& P = s->levels[0].P;
+  Csr& B = s->base_P0;
+  B.n = P.n;
+  B.m = P.m;
+  B.nnz = P.nnz;
+  B.maxrow = P.maxrow;
+  PPE_HIP(hipMemcpyAsync(s->base_cid.get<int>(nc + 1), s->cid.as<int>(), sizeof(int) * (nc + 1),
+                         hipMemcpyDeviceToDevice, s->stream));
+  PPE_HIP(hipMemcpyAsync(B.rowptr.get<int>(P.n + 1), P.rp(), sizeof(int) * (P.n + 1),
+                         hipMemcpyDeviceToDevice, s->stream));
+  if (P.nnz) {
+    PPE_HIP(hipMemcpyAsync(B.col.get<int>(P.nnz), P.ci(), sizeof(int) * P.nnz,
+                           hipMemcpyDeviceToDevice, s->stream));
+    PPE_HIP(hipMemcpyAsync(B.val.get<double>(P.nnz), P.v(), sizeof(double) * P.nnz,
+                           hipMemcpyDeviceToDevice, s->stream));
+  }
+  s->base_na = s->n_active;
+  s->base_nlev = s->nlev;
+  s->base_uses = 0;
+  s->have_base = true;
+}
+
+bool reuse_coarse_levels(ppe_solver* s) {
+  if (!s->have_base || s->shifted || s->base_uses >= s->opt.coarse_reuse) return false;
+  const int na = s->n_active;
+  if (na == 0) return false;
+  Level& L0 = s->levels[0];
+  const Csr& B = s->base_P0;
+  const int* perm = s->perm.as<int>();
+  const int* comp = s->comp_full.as<int>();
+  const int* bcid = s->base_cid.as<int>();
+  int* cnt = s->tmp_i[0].get<int>(na + 1);
+  int* matched = s->tmp_i[1].get<int>(na + 1);
+  hipLaunchKernelGGL(k_reuse_rows, dim3(grid_for(na)), dim3(kBlock), 0, s->stream, na, perm, comp,
+                     bcid, B.rp(), cnt, matched);
+  PPE_LAUNCH_CHECK();
+  int* rp = L0.P.rowptr.get<int>(na + 1);
+  const long long* d_nnz = exclusive_scan_async(s, cnt, rp, na, 0);
+  const long long* d_matched = exclusive_scan_async(s, matched, s->tmp_i[2].get<int>(na + 1), na, 1);
+  const double* d_rho = level0_bound_async(s);
+  long long nnz = 0, kept = 0;
+  double rho = 0.0;
+  read_back(s, {ReadItem{d_nnz, sizeof(long long), &nnz},
+                ReadItem{d_matched, sizeof(long long), &kept},
+                ReadItem{d_rho, sizeof(double), &rho}});
+  // cells removed since the base build plus cells it did not have
+  const long long moved = (s->base_na - kept) + (na - kept);
+  if (10 * moved > (long long)s->base_na) return false;
+  Csr& P = L0.P;
+  P.n = na;
+  P.m = B.m;
+  P.nnz = nnz;
+  P.maxrow = B.maxrow;
+  hipLaunchKernelGGL(k_reuse_fill, dim3(grid_for(na)), dim3(kBlock), 0, s->stream, na, perm, comp,
+                     bcid, B.rp(), B.ci(), B.v(), rp, P.col.get<int>(nnz > 0 ? nnz : 1),
+                     P.val.get<double>(nnz > 0 ? nnz : 1));
+  PPE_LAUNCH_CHECK();
+  transpose(s, P, L0.R);
+  L0.n_agg = B.m;
+  L0.rho = rho;
+  L0.ap_ok = false;
+  L0.dense = false;
+  s->nlev = s->base_nlev;
+  s->base_uses += 1;
+  return true;
+}
+
 const double* level0_bound_async(ppe_solver* s) {
   double* out = s->setup_out.get<double>((size_t)std::max(1, s->opt.max_levels) + 1);
   spectral_bound(s, s->levels[0], 0, out);

@@ -109,6 +109,7 @@ void ppe_default_options(ppe_options* o) {
   o->alloc = nullptr;
   o->free = nullptr;
   o->alloc_ctx = nullptr;
+  o->coarse_reuse = 0;
 }
 
 ppe_status ppe_create(const ppe_options* opt, ppe_solver** out) {
@@ -132,6 +133,7 @@ ppe_status ppe_create(const ppe_options* opt, ppe_solver** out) {
     ppe::require(o.coarse_max >= 1, PPE_ERR_ARG, "coarse_max must be >= 1");
     ppe::require(o.max_levels >= 1 && o.max_levels <= 32, PPE_ERR_ARG, "max_levels in [1, 32]");
     ppe::require(o.theta >= 0 && o.theta < 1, PPE_ERR_ARG, "theta in [0, 1)");
+    ppe::require(o.coarse_reuse >= 0, PPE_ERR_ARG, "coarse_reuse must be >= 0");
     if (o.check_every < 1) o.check_every = 1;
     auto* s = new ppe_solver();
     s->opt = o;
@@ -242,7 +244,14 @@ ppe_status assemble_impl(ppe_solver* s, const double* face_coeff, const double* 
     ppe::drop_graph(s);
     ppe::assemble_fine(s, face_coeff, fl, shift);
     if (s->n_active > 0) {
-      ppe::build_hierarchy(s);
+      s->fine_reindexed = false;
+      if (!shift && s->opt.coarse_reuse > 0 && ppe::reuse_coarse_levels(s)) {
+        s->stats.coarse_reused += 1;
+        s->fine_reindexed = true;
+      } else {
+        ppe::build_hierarchy(s);
+        ppe::keep_base(s);
+      }
       ppe::prepare_solve_levels(s);
       if (s->opt.precision == PPE_MIXED) ppe::make_fp32_hierarchy(s);
       if (s->opt.autotune) {
@@ -546,6 +555,9 @@ ppe_status ppe_copy_aggregates(const ppe_solver* s, int level, int32_t* agg) {
   ppe_status st = check_level(s, level);
   if (st != PPE_OK) return st;
   if (level == s->nlev - 1 || !agg) return PPE_ERR_ARG;
+  // a finest level re-indexed onto kept coarse levels has no aggregates of
+  // its own (its prolongator rows come from the earlier build)
+  if (level == 0 && s->fine_reindexed) return PPE_ERR_STATE;
   ppe_solver* m = const_cast<ppe_solver*>(s);
   return guarded(m, [&]() -> ppe_status {
     DeviceGuard g(s->device);

@@ -255,6 +255,13 @@ struct ppe_solver {
   // reuse of an unchanged system: the coefficients of the last successful
   // assembly (its mask is `active`)
   bool have_prev = false;
+  // reuse of the coarse levels across a changed mask (option coarse_reuse):
+  // the compact numbering and finest prolongator of the last full build
+  bool have_base = false;
+  bool fine_reindexed = false;  // the last assembly kept the coarse levels
+  int base_na = 0, base_nlev = 0, base_uses = 0;
+  ppe::DevBuf base_cid;  // int[n_cells + 1]: cell -> compact row of that build, or -1
+  ppe::Csr base_P0;
   bool shifted = false;  // the last assembly carried a diagonal shift (no pins)
   ppe::DevBuf prev_coeff;
   // autotuner choices per (level, FP32, quarter-octave bins of rows and of
@@ -558,6 +565,12 @@ bool same_system(ppe_solver* s, const double* coeff, const double* fl);
 
 // amg.hip
 void build_hierarchy(ppe_solver* s);
+// Keep the coarse levels of the last full build for the newly assembled
+// finest level (option coarse_reuse); false (nothing changed) when the
+// active set moved too far, and a full build must follow.
+bool reuse_coarse_levels(ppe_solver* s);
+// Record the finest level's numbering and prolongator after a full build.
+void keep_base(ppe_solver* s);
 
 // solve.hip
 void spmv(ppe_solver* s, const Level& L, const double* x, double* y);

@@ -69,6 +69,27 @@ __device__ __forceinline__ void solid_fraction(const Alloy& a, double T, double&
   }
 }
 
+// The next Picard iterate from the previous one (tp) and the pass's solved
+// temperature (ts): ts, except that a cell does not jump over a kink of
+// Eq. 21 in one pass.  Cooling stops at the highest kink strictly between,
+// heating at the lowest; a cell on a kink moves freely, and the kink belongs
+// to the branch below it, so the next pass linearises with the slope of the
+// branch the cell entered.  At convergence no cell crosses a kink, so the
+// fixed point is that of the plain iteration.
+__device__ __forceinline__ double branch_limited(const Alloy& a, double tp, double ts) {
+  const double k1 = a.T_liq, k2 = a.T_sol + a.T_eps, k3 = a.T_sol - a.T_eps;
+  if (ts < tp) {
+    if (ts < k1 && k1 < tp) return k1;
+    if (ts < k2 && k2 < tp) return k2;
+    if (ts < k3 && k3 < tp) return k3;
+  } else if (ts > tp) {
+    if (tp < k3 && k3 < ts) return k3;
+    if (tp < k2 && k2 < ts) return k2;
+    if (tp < k1 && k1 < ts) return k1;
+  }
+  return ts;
+}
+
 __device__ __forceinline__ double darcy(const Alloy& a, double fs, double cap) {
   if (!(fs > 0.0 && fs < 1.0)) return 0.0;
   const double q = 1.0 - fs;
@@ -283,19 +304,20 @@ __global__ void k_energy_sys(int nc, const double* __restrict__ vol, const doubl
   Tnew[c] = Tm[c];
 }
 
-// f^(m+1) = (1 - lambda) f^m + lambda f_s(T^(m+1)); T^m <- T^(m+1); block
-// maxima of |dT|, |df|, |T|.
+// T^(m+1) = the branch-limited solved temperature; f^(m+1) = (1 - lambda)
+// f^m + lambda f_s(T^(m+1)); block maxima of |T_solved - T^m|, |df|, |T^(m+1)|.
 __global__ void k_picard(int nc, const double* __restrict__ Tnew, double* __restrict__ Tm,
                          double* __restrict__ fm, Alloy a, double relax,
                          double* __restrict__ part) {
   const int c = blockIdx.x * kBlock + threadIdx.x;
   double m0 = 0.0, m1 = 0.0, m2 = 0.0;
   if (c < nc) {
-    const double t = Tnew[c];
+    const double ts = Tnew[c], tp = Tm[c];
+    const double t = branch_limited(a, tp, ts);
     double f, slope;
     solid_fraction(a, t, f, slope);
     const double fn = (1.0 - relax) * fm[c] + relax * f;
-    m0 = fabs(t - Tm[c]);
+    m0 = fabs(ts - tp);
     m1 = fabs(fn - fm[c]);
     m2 = fabs(t);
     Tm[c] = t;

@@ -6,7 +6,7 @@ velocities and material properties.  It holds
 none of the solver's arithmetic (no masking, assembly, aggregation or Krylov
 step); those live separately in the oracle and in the HIP library.
 """
-from .alloy import al_si_alloy
+from .alloy import al_alloy, al_si_alloy
 from .mesh import HexMesh, box_mesh, plate_with_ribs_mesh, concat_meshes, face_coeff
 from .fields import (
     fl_linear_x,
@@ -23,6 +23,7 @@ from .fields import (
 )
 
 __all__ = [
+    "al_alloy",
     "al_si_alloy",
     "HexMesh",
     "box_mesh",

@@ -41,3 +41,18 @@ def al_si_alloy(si_wt=10.0, T_wall=500.0, T_ref=1000.0, gravity=(0.0, 0.0, -9.81
         g=tuple(float(v) for v in gravity),
         T_wall=None if T_wall is None else float(T_wall),
     )
+
+
+def al_alloy(T_liq=913.0, T_sol=833.0, k=150.0, cp=900.0, Lf=3.9e5, T_wall=600.0, T_ref=950.0,
+             gravity=(0.0, 0.0, -9.81)):
+    """Property set of an aluminium alloy given by its liquidus and solidus:
+    rho 2400 kg/m^3, k 150 W/(m K), c_p 900 J/(kg K), latent heat 3.9e5 J/kg,
+    liquidus 913 K, solidus 833 K by default.  The Scheil partition
+    coefficient follows from straight liquidus and solidus lines through the
+    melting point of pure Al: k_p = (T_f - T_liq) / (T_f - T_sol).  The
+    viscosity, expansion coefficient and dendrite arm spacing are those of
+    al_si_alloy."""
+    base = al_si_alloy(T_wall=T_wall, T_ref=T_ref, gravity=gravity)
+    base.update(k=float(k), cp=float(cp), Lf=float(Lf), T_liq=float(T_liq), T_sol=float(T_sol),
+                k_p=(T_FREEZE - T_liq) / (T_FREEZE - T_sol))
+    return base

@@ -23,7 +23,7 @@ import scipy.sparse.linalg as spla
 
 from oracle import flow
 from oracle import projection as pj
-from synth import al_si_alloy, box_mesh, face_coeff, fl_planar_front, t_wall_layer
+from synth import al_alloy, al_si_alloy, box_mesh, face_coeff, fl_planar_front, t_wall_layer
 from tests.gpu_util import to_dev
 
 pytestmark = pytest.mark.gpu
@@ -106,6 +106,13 @@ def _cases():
     # layer has formed, on several reduction tiles with a ragged tail
     m = box_mesh((23, 19, 13), lengths=(2e-2, 1.6e-2, 1.1e-2), jitter=0.12, seed=8)
     yield "die_casting_5681", m, al_si_alloy(), t_wall_layer(m, 500.0, 1000.0, 4e-3), 1e-3, 2
+    # a uniform melt at 950 K against walls at 600 K at the 64^3 cavity's
+    # spacing (10 mm / 64) and time step (1e-3 s): alpha dt / h^2 = 2.8, so
+    # the wall cells cross the whole mushy range in one step and the Picard
+    # passes must not jump over the kinks of Eq. 21
+    h = 1e-2 / 64
+    m = box_mesh((10, 9, 8), lengths=(10 * h, 9 * h, 8 * h), jitter=0.1, seed=2)
+    yield "cavity_dt_1e-3", m, al_alloy(), np.full(m.n_cells, 950.0), 1e-3, 3
 
 
 CASES = list(_cases())

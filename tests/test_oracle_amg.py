@@ -285,3 +285,47 @@ def test_l1_jacobi_vcycle_symmetric_and_pcg_matches_dense():
     ref = np.linalg.solve(sy.A.toarray(), b0)
     assert res.status == pcg.OK
     assert np.linalg.norm(res.x - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def _front_system(x0):
+    m = box_mesh((14, 12, 10), jitter=0.1, seed=5)
+    fl = np.clip((m.cell_centre[:, 0] - x0) / 0.1, 0.0, 1.0)
+    c = face_coeff(m, 2400.0)
+    return m, assembly.masked_system(m.n_cells, m.owner, m.neigh, c, fl)
+
+
+def test_reused_coarse_levels_give_an_spd_preconditioner():
+    """The front moves one layer and leaves dangling mushy cells: the reused
+    hierarchy's V-cycle is symmetric and positive on the new system, its
+    finest prolongator holds exactly the base rows of the kept cells (empty
+    for pins), and PCG with it reaches the dense solution."""
+    m, sy0 = _front_system(0.18)
+    H0 = amg.build_hierarchy(sy0.A)
+    _, sy = _front_system(0.26)
+    assert sy.n_active < sy0.n_active
+    base_of_cell = np.full(m.n_cells, -1)
+    base_of_cell[sy0.perm] = np.arange(sy0.n_active)
+    base_row = base_of_cell[sy.perm]
+    pinned = np.zeros(sy.n_active, dtype=bool)
+    pinned[sy.pinned] = True
+    G = amg.reuse_coarse_levels(H0, sy.A, base_row, pinned)
+    assert G.levels[1] is H0.levels[1]
+    P, P0 = G.levels[0].P, H0.levels[0].P.tocsr()
+    for i in range(sy.n_active):
+        row = P.getrow(i)
+        if pinned[i]:
+            assert row.nnz == 0
+        else:
+            ref = P0.getrow(base_row[i])
+            assert np.array_equal(row.indices, ref.indices) and np.array_equal(row.data, ref.data)
+    assert (G.levels[0].R != P.T).nnz == 0
+    rng = np.random.default_rng(4)
+    r1, r2 = rng.normal(size=(2, sy.n_active))
+    a, b = amg.vcycle(G, r1) @ r2, r1 @ amg.vcycle(G, r2)
+    assert abs(a - b) <= 1e-12 * abs(a)
+    assert amg.vcycle(G, r1) @ r1 > 0
+    b0 = assembly.pinned_rhs(sy, rhs_uniform(m.n_cells, seed=2, center_mask=None))
+    res = pcg.pcg(sy.A, b0, M=lambda r: amg.vcycle(G, r), rtol=1e-12)
+    ref = np.linalg.solve(sy.A.toarray(), b0)
+    assert res.status == pcg.OK
+    assert np.linalg.norm(res.x - ref) <= 1e-9 * np.linalg.norm(ref)

@@ -280,3 +280,37 @@ def test_convection_of_a_linear_field_by_a_uniform_flow():
     assert interior.sum() >= 4
     ref = 2.5 * (U @ G) * geo.V
     assert np.abs(C - ref)[interior].max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_branch_limited_iterate():
+    """Eq. 21's kinks seen from the previous iterate: a cooling cell stops
+    at the highest kink it would cross, a heating one at the lowest; with no
+    kink strictly between (a start on a kink included) the solved value
+    stays."""
+    a = flow.Props.of(_props())
+    k1, k2, k3 = a.T_liq, a.T_sol + a.T_eps, a.T_sol - a.T_eps
+    prev = np.array([k1 + 5, k1 + 5, k2 + 1, k1 - 1, k3 - 5, k3 - 5, k2 + 1, k1, k3, 700.0])
+    solv = np.array([k1 - 1, 700.0, k3 - 3, k1 - 3, 1000.0, k3 + 1, k2 + 2, k1 - 9, k3 + 9, 650.0])
+    # (from k3 heating past k2 the next kink still stops the cell)
+    want = np.array([k1, k1, k2, k1 - 3, k3, k3, k2 + 2, k1 - 9, k2, 650.0])
+    assert np.array_equal(flow.branch_limited(prev, solv, a), want)
+
+
+@pytest.mark.parametrize("T0,fs0", [(840.0, 0.3), (700.0, 0.0), (845.0, 0.9)])
+def test_latent_release_across_kinks_converges(T0, fs0):
+    """A solid block holding far less solid than Eq. 21 gives it releases
+    enough heat to cross one or more kinks upward in one step: the plain
+    Newton passes jump between the solid and liquid branches and never
+    settle, the branch-limited ones reach the bracketed root of the cell's
+    energy balance c_p (T - T0) = L_f (f_s(T) - f_s0)."""
+    a = _props(T_wall=None)
+    m = box_mesh((3, 3, 2), lengths=(1e-2, 1e-2, 8e-3), jitter=0.1, seed=3)
+    geo = flow.Geometry(m)
+    st = flow.initial_state(m, a, T0=np.full(m.n_cells, T0))
+    st.fs[:] = fs0
+    T, fs, _, it = flow.energy(geo, a, st, np.zeros(m.n_faces), DT, max_picard=40)
+    root = brentq(lambda t: a.cp * (t - T0) - a.Lf * (flow.solid_fraction(np.array([t]), a)[0] - fs0),
+                  T0, 2000.0, xtol=1e-13, rtol=1e-15)
+    assert 0 < it <= 40, it
+    assert np.abs(T - root).max() <= 1e-8 * root
+    assert np.abs(fs - flow.solid_fraction(np.array([root]), a)[0]).max() <= 1e-8
