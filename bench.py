@@ -280,6 +280,30 @@ def profile_table(s, run):
     return table
 
 
+COPY = {}
+
+
+def copy_bandwidth(torch, dev, mib=192, reps=20):
+    """Bytes read + written per second by a plain device-to-device copy of
+    `mib` MiB (torch's copy kernel), the practical HBM rate that the
+    kernels' rates are set beside."""
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    COPY.update(gbs=2.0 * n * 8 / (ms * 1e-3) / 1e9, mib=mib)
+    return COPY["gbs"]
+
+
 def roofline(table, workload=None, label=""):
     """The kernel with the largest total time in the table, against the HBM
     peak (algorithmic bytes / kernel time); plus every solve kernel
@@ -305,7 +329,10 @@ def roofline(table, workload=None, label=""):
             "top_kernels": [{"kernel": k, "share": v["kernel_ms"] / total_ms,
                              "avg_launch_us": 1e3 * v["kernel_ms"] / v["launches"],
                              "frac": v["bytes"] / (v["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
-                            for k, v in top]}
+                            for k, v in top],
+            "copy_gbs": COPY.get("gbs"),
+            "copy_note": (f"a plain device copy of {COPY['mib']} MiB (read + write) measured in "
+                          "the same process" if COPY else None)}
 
 
 def train_network(ppe, torch, wl, d_in, steps, n_adam=600, batch=8192):
@@ -759,6 +786,8 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    copy_bandwidth(torch, dev)
+    note(f"plain copy: {COPY['gbs']:.0f} GB/s")
     if args.c3_only:
         print(json.dumps(c3_leg(ppe, torch, dev)), flush=True)
         return

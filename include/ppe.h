@@ -363,11 +363,13 @@ ppe_status ppe_apply_matrix(ppe_solver* s, int level, const double* x, double* y
 ppe_status ppe_apply_vcycle(ppe_solver* s, const double* r, double* z);
 
 /* Launch choices of level l's solve kernels, choice[4] (host): lanes per row
- * of the coarse smoother, of the restriction and of the prolongation (0 = the
- * fixed rule, else 4, 8, 16, 32 or 64; on the coarse levels of the FP64
- * V-cycle the prolongation runs in one pass with the first post-smoothing
- * step, reading the Galerkin product's A P), and 1 if the first two
- * smoothing steps from a zero guess run fused, 0 if split.  The autotuner
+ * of the coarse smoother (0 = the fixed rule, else 4, 8, 16, 32 or 64), of
+ * the restriction and of the prolongation (0, or a power of two from 1 to
+ * 64; on the coarse levels of the FP64 V-cycle the prolongation runs in one
+ * pass with the first post-smoothing step, reading the Galerkin product's
+ * A P, and that pass takes 4 lanes for a choice of 1 or 2), and 1 if the
+ * first two smoothing steps from a zero guess run fused, 0 if split.  The
+ * autotuner
  * sets them at assembly; setting them by hand (until the next assembly) lets
  * a test run every variant.  They never affect the hierarchy, only the
  * solve's order of summation.  PPE_ERR_ARG for a value outside those sets. */

@@ -510,8 +510,11 @@ ppe_status ppe_set_level_launch(ppe_solver* s, int level, const int32_t* choice)
   ppe_status st = check_level(s, level);
   if (st != PPE_OK) return st;
   if (!choice) return PPE_ERR_ARG;
-  auto ok = [](int v) { return v == 0 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64; };
-  if (!ok(choice[0]) || !ok(choice[1]) || !ok(choice[2]) || (choice[3] != 0 && choice[3] != 1))
+  auto ok = [](int v, int lo) {
+    return v == 0 || (v >= lo && v <= 64 && (v & (v - 1)) == 0);
+  };
+  if (!ok(choice[0], 4) || !ok(choice[1], 1) || !ok(choice[2], 1) ||
+      (choice[3] != 0 && choice[3] != 1))
     return PPE_ERR_ARG;
   ppe::Level& L = s->levels[level];
   L.lpr_a = choice[0];

@@ -283,23 +283,39 @@ __global__ void __launch_bounds__(kBlock) k_csr(int n, const int* __restrict__ r
   }
 }
 
-// y (+)= P x for a rectangular CSR (prolongation adds into y).
-template <int LPR, bool ADD, class M>
+// y (+)= P x for a rectangular CSR (prolongation adds into y).  With FIRST
+// (restriction only) the pass also takes the coarse level's first smoothing
+// step from a zero guess on the row it has just formed: d1 = x1 =
+// inv_theta y / sd, the arithmetic of k_cheb_first.
+template <int LPR, bool ADD, class M, bool FIRST>
 __global__ void __launch_bounds__(kBlock) k_csr_rect(int n, const int* __restrict__ rp,
                                                      const int* __restrict__ ci,
                                                      const M* __restrict__ v,
                                                      const double* __restrict__ x,
-                                                     double* __restrict__ y) {
+                                                     double* __restrict__ y,
+                                                     const M* __restrict__ sd, double inv_theta,
+                                                     double* __restrict__ d1,
+                                                     double* __restrict__ x1) {
+  static_assert(!(ADD && FIRST), "the first smoothing step follows a restriction");
   const int g = (blockIdx.x * kBlock + threadIdx.x) / LPR;
   const int lane = threadIdx.x % LPR;
-  double s = 0.0, y0 = 0.0;
+  double s = 0.0, y0 = 0.0, sdi = 1.0;
   if (g < n) {
-    if (ADD && lane == 0) y0 = y[g];  // requested before the row's entries
+    // the row's own operands are requested before its entries
+    if (ADD && lane == 0) y0 = y[g];
+    if (FIRST && lane == 0) sdi = (double)sd[g];
     s = row_sum<LPR, kRowU, M>(s, rp[g], rp[g + 1], lane, ci, v, [&](int j) { return x[j]; });
   }
 #pragma unroll
   for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_down(s, o, LPR);
-  if (g < n && lane == 0) y[g] = ADD ? y0 + s : s;
+  if (g < n && lane == 0) {
+    y[g] = ADD ? y0 + s : s;
+    if (FIRST) {
+      const double w = inv_theta * (s / sdi);
+      d1[g] = w;
+      x1[g] = w;
+    }
+  }
 }
 
 // ---- prolongation fused with the first post-smoothing step
@@ -876,22 +892,26 @@ const M* smooth_diag(const ppe_solver* s, const Level& L) {
   return s->opt.smoother == PPE_SMOOTH_L1JACOBI ? LevelData<M>::l1(L) : LevelData<M>::diag(L);
 }
 
-// Lanes per row of the solve's CSR kernels by default: the power of two from
-// 4 to 64 nearest (in ratio) to the mean row length over `per_lane`.  The
-// rules follow what the autotuner picked on the 128^3 cube and the 1.5 M-cell
-// plate: about four entries per lane for the smoothing steps, about two for
-// the restriction, the prolongation and the fused prolongation (whose rows of
-// A, P and A P are read together).
-int lanes_near(double target) {
-  int best = 4;
-  for (int c = 8; c <= 64; c *= 2)
+// Lanes per row of the solve's CSR kernels by default.  The rules are fits
+// to what the autotuner picked on the 128^3 cube and the 1.5 M-cell plate
+// (FP64 and mixed): about five entries per lane for the smoothing steps,
+// three for the restriction and the plain prolongation, and about
+// 3 sqrt(row length) lanes for the fused prolongation (whose rows of A, P and
+// A P are read together).  The plain transfers go down to one lane per row
+// (the finest prolongation has three to four entries a row); the smoothing
+// and fused kernels keep at least four.  A level too small to give every
+// compute unit a block of 256 threads at that count takes 64 lanes.
+int lanes_near(double target, int lo = 4) {
+  int best = lo;
+  for (int c = 2 * lo; c <= 64; c *= 2)
     if (std::fabs(std::log2((double)c / target)) < std::fabs(std::log2((double)best / target)))
       best = c;
   return best;
 }
+int widen_small(const Csr& M, int lpr) { return (int64_t)M.n * lpr < 65536 ? 64 : lpr; }
 double mean_row(const Csr& M) { return M.n ? (double)M.nnz / M.n : 1.0; }
-int smooth_lanes(const Csr& A) { return lanes_near(mean_row(A) / 4.0); }
-int transfer_lanes(const Csr& M) { return lanes_near(mean_row(M) / 2.0); }
+int smooth_lanes(const Csr& A) { return widen_small(A, lanes_near(mean_row(A) / 5.0)); }
+int transfer_lanes(const Csr& M) { return widen_small(M, lanes_near(mean_row(M) / 3.0, 1)); }
 
 // Apply the level operator with epilogue EPI, matrix values in type M.
 // Dot/power epilogues run on a capped grid and write partials to `partials`;
@@ -944,22 +964,40 @@ int apply_op(ppe_solver* s, const Level& L, const double* x, const double* b, do
   return g;
 }
 
-template <bool ADD, class M>
-void apply_rect(ppe_solver* s, const Csr& P, const double* x, double* y, int lpr_choice = 0) {
+// The coarse level's first smoothing step from a zero guess, taken by the
+// restriction that forms its right-hand side: the level's smoothing
+// diagonal, 1/theta, and where the step's update and iterate go.
+template <class M>
+struct FirstStep {
+  const M* sd;
+  double inv_theta;
+  double* d;
+  double* x;
+};
+
+template <bool ADD, class M, bool FIRST = false>
+void apply_rect(ppe_solver* s, const Csr& P, const double* x, double* y, int lpr_choice = 0,
+                const FirstStep<M>& fs = FirstStep<M>{nullptr, 0.0, nullptr, nullptr}) {
   if (P.n == 0) return;
   const int lpr = lpr_choice > 0 ? lpr_choice : transfer_lanes(P);
   const int g = grid_for((int64_t)P.n * lpr);
-  // entries and row pointers of P or R, each operand entry once, y out (and in)
+  // entries and row pointers of P or R, each operand entry once, y out (and
+  // in); with the first step the diagonal in and its update and iterate out
   auto bytes = [&]() {
     return (double)P.nnz * (sizeof(M) + 4) + 4.0 * (P.n + 1) + 8.0 * P.m +
-           8.0 * P.n * (ADD ? 2 : 1);
+           8.0 * P.n * (ADD ? 2 : 1) + (FIRST ? (sizeof(M) + 16.0) * P.n : 0.0);
   };
 #define PPE_RECT(LL)                                                                           \
-  launch(s, [&]() { return std::make_pair(kname("k_csr_rect", {str(LL), str(ADD), tname<M>()}), \
-                                          bytes()); },                                         \
-         k_csr_rect<LL, ADD, M>, dim3(g), dim3(kBlock), P.n, (const int*)P.rp(),               \
-         (const int*)P.ci(), LevelData<M>::val(P), x, y)
+  launch(s,                                                                                    \
+         [&]() {                                                                               \
+           return std::make_pair(                                                              \
+               kname("k_csr_rect", {str(LL), str(ADD), tname<M>(), str(FIRST)}), bytes());     \
+         },                                                                                    \
+         k_csr_rect<LL, ADD, M, FIRST>, dim3(g), dim3(kBlock), P.n, (const int*)P.rp(),        \
+         (const int*)P.ci(), LevelData<M>::val(P), x, y, fs.sd, fs.inv_theta, fs.d, fs.x)
   switch (lpr) {
+    case 1: PPE_RECT(1); break;
+    case 2: PPE_RECT(2); break;
     case 4: PPE_RECT(4); break;
     case 8: PPE_RECT(8); break;
     case 16: PPE_RECT(16); break;
@@ -983,11 +1021,12 @@ bool prolong_fusable(const ppe_solver* s, const Level& L) {
   return s->opt.precision != PPE_MIXED && &L != &s->levels[0] && L.ap_ok && !L.c1.empty();
 }
 
-// Lanes per row of the fused pass: the launch choice if set, else about two
-// entries of A per lane (rows past the first chunk continue lane by lane).
+// Lanes per row of the fused pass: the launch choice if set (at least
+// four), else the fixed rule (rows past the first chunk continue lane by
+// lane).
 int prolong_lanes(const Level& L) {
-  if (L.lpr_p > 0) return L.lpr_p;
-  return transfer_lanes(L.A);
+  if (L.lpr_p > 0) return std::max(L.lpr_p, 4);
+  return widen_small(L.A, lanes_near(3.0 * std::sqrt(mean_row(L.A))));
 }
 
 // y = (x1 + P e) + d with d = c2 D^-1 (b - A (x1 + P e)): the prolongation
@@ -1041,7 +1080,7 @@ bool smooth_steps(ppe_solver* s, Level& L, const double* b, const double* cur, i
 
 template <class M>
 bool smooth(ppe_solver* s, Level& L, const double* b, const double* x_in, double* x_out,
-            double* xa, double* xb, const PcgDot* dot = nullptr) {
+            double* xa, double* xb, const PcgDot* dot = nullptr, bool first_done = false) {
   const int n = L.n;
   const int deg = 1 + (int)L.c1.size();
   double* d = L.d.as<double>();
@@ -1049,7 +1088,10 @@ bool smooth(ppe_solver* s, Level& L, const double* b, const double* x_in, double
   const double* cur = x_in;
   int step = 1;
   if (cur == nullptr) {
-    if (deg >= 2 && L.fuse0) {
+    if (first_done) {  // the restriction took the first step (restricted_first)
+      cur = dst_of(1);
+      step = 2;
+    } else if (deg >= 2 && L.fuse0) {
       double* dst = dst_of(2);
       apply_op<E_CHEB0, M>(s, L, nullptr, b, d, L.c1[0], L.c2[0], dst, nullptr, nullptr, 0,
                            L.inv_theta);
@@ -1107,11 +1149,31 @@ bool smooth_steps(ppe_solver* s, Level& L, const double* b, const double* cur, i
   return dotted;
 }
 
+// Whether the V-cycle's first smoothing on level l (l > 0, from a zero
+// guess) starts with the plain first step (not the fused first two steps),
+// which the restriction into level l then takes; and where that step's
+// iterate goes: the first smoothing's output x1 (t, or r on the coarsest
+// level) when the smoother has one step, else its ping-pong buffer x2.
+bool restricted_first(const ppe_solver* s, int l) {
+  const Level& C = s->levels[l];
+  if (l == s->nlev - 1 && C.dense) return false;
+  return !(C.c1.size() >= 1 && C.fuse0);
+}
+template <class M>
+FirstStep<M> first_step(ppe_solver* s, int l) {
+  Level& C = s->levels[l];
+  double* out = l == s->nlev - 1 ? C.r.as<double>() : C.t.as<double>();
+  return FirstStep<M>{smooth_diag<M>(s, C), C.inv_theta, C.d.as<double>(),
+                      C.c1.empty() ? out : C.x2.as<double>()};
+}
+
 // One V-cycle with zero initial guess, x = M b on level l, matrix values in
 // type M (vectors FP64).  dot: see smooth (consumed by the last level-0
-// smoothing step, if any).
+// smoothing step, if any).  first_done: the restriction into level l has
+// taken its first smoothing step (restricted_first).
 template <class M>
-bool vcycle_t(ppe_solver* s, int l, const double* b, double* x, const PcgDot* dot = nullptr) {
+bool vcycle_t(ppe_solver* s, int l, const double* b, double* x, const PcgDot* dot = nullptr,
+              bool first_done = false) {
   Level& L = s->levels[l];
   const int n = L.n;
   if (n == 0) return false;
@@ -1129,16 +1191,20 @@ bool vcycle_t(ppe_solver* s, int l, const double* b, double* x, const PcgDot* do
       return false;
     }
     double* t = L.r.as<double>();
-    smooth<M>(s, L, b, nullptr, t, xa, xb);
+    smooth<M>(s, L, b, nullptr, t, xa, xb, nullptr, first_done);
     return smooth<M>(s, L, b, t, x, xa, xb, dot);
   }
   Level& C = s->levels[l + 1];
   double* x1 = L.t.as<double>();  // pre-smoothed iterate, corrected in place
   double* r = L.r.as<double>();
-  smooth<M>(s, L, b, nullptr, x1, xa, xb);
+  smooth<M>(s, L, b, nullptr, x1, xa, xb, nullptr, first_done);
   apply_op<E_RESID, M>(s, L, x1, b, nullptr, 0.0, 0.0, r, nullptr);
-  apply_rect<false, M>(s, L.R, r, C.b.as<double>(), L.lpr_r);
-  vcycle_t<M>(s, l + 1, C.b.as<double>(), C.x.as<double>());
+  const bool first = C.n > 0 && restricted_first(s, l + 1);
+  if (first)
+    apply_rect<false, M, true>(s, L.R, r, C.b.as<double>(), L.lpr_r, first_step<M>(s, l + 1));
+  else
+    apply_rect<false, M>(s, L.R, r, C.b.as<double>(), L.lpr_r);
+  vcycle_t<M>(s, l + 1, C.b.as<double>(), C.x.as<double>(), nullptr, first);
   if (prolong_fusable(s, L)) {
     // the first post-smoothing step writes xa (it is not the last step)
     prolong_cheb<M>(s, L, C.x.as<double>(), x1, b, L.d.as<double>(), xa);
@@ -1234,10 +1300,12 @@ void prepare_solve_levels(ppe_solver* s) {
     Level& L = s->levels[l];
     L.lpr_a = L.lpr_r = L.lpr_p = 0;
     // The fused first two steps gather b and the scaling diagonal (and divide)
-    // for every stored entry; on CSR levels with long rows one elementwise
-    // pass that forms the first iterate costs less (the autotuner split them
-    // on the 128^3 cube's levels of 34 and 219 entries per row).
-    L.fuse0 = l == 0 || mean_row(L.A) <= 24.0;
+    // for every stored entry.  On a coarse level the restriction into it
+    // takes the first step for the cost of two more vectors written, and the
+    // split pair then costs one plain step (the autotuner split every coarse
+    // level of the 128^3 cube and the plate); the finest level has no
+    // restriction before it and keeps the fused pair.
+    L.fuse0 = l == 0;
     const int n = L.n > 0 ? L.n : 1;
     L.x.get<double>(n);
     L.b.get<double>(n);
@@ -1594,16 +1662,16 @@ float time_launches(ppe_solver* s, F&& launch, int reps = 3) {
   return ms / reps;
 }
 
-constexpr int kLprs[] = {4, 8, 16, 32, 64};
+constexpr int kLprs[] = {1, 2, 4, 8, 16, 32, 64};
 
 // The fastest lanes-per-row choice, candidates from a quarter of the fixed
-// rule's choice up to 64.
+// rule's choice (and at least lo) up to 64.
 template <class F>
-int best_lpr(ppe_solver* s, int rule, F&& run) {
+int best_lpr(ppe_solver* s, int rule, int lo, F&& run) {
   int best = rule;
   float tbest = 1e30f;
   for (int c : kLprs) {
-    if (c * 4 < rule) continue;
+    if (c * 4 < rule || c < lo) continue;
     const float t = time_launches(s, [&]() { run(c); });
     if (t < tbest) { tbest = t; best = c; }
   }
@@ -1624,35 +1692,43 @@ void tune_level(ppe_solver* s, int l) {
   double* y = L.x2.as<double>();
   const double c1 = L.c1.empty() ? 0.0 : L.c1[0], c2 = L.c1.empty() ? L.inv_theta : L.c2[0];
   if (l > 0)
-    L.lpr_a = best_lpr(s, smooth_lanes(L.A), [&](int c) {
+    L.lpr_a = best_lpr(s, smooth_lanes(L.A), 4, [&](int c) {
       L.lpr_a = c;
       apply_op<E_CHEB, M>(s, L, x, b, d, c1, c2, y, nullptr);
     });
   if (!L.c1.empty()) {
+    // on a coarse level the split first step rides on the restriction into
+    // the level, so both variants are timed with that restriction
+    Level* F = l > 0 ? &s->levels[l - 1] : nullptr;
     const float fused = time_launches(s, [&]() {
+      if (F) apply_rect<false, M>(s, F->R, F->r.as<double>(), b, F->lpr_r);
       apply_op<E_CHEB0, M>(s, L, nullptr, b, d, c1, c2, y, nullptr, nullptr, 0, L.inv_theta);
     });
     const float split = time_launches(s, [&]() {
-      hipLaunchKernelGGL(k_cheb_first<M>, dim3(grid_for(L.n)), dim3(kBlock), 0, s->stream, L.n, b,
-                         smooth_diag<M>(s, L), L.inv_theta, d, x);
+      if (F)
+        apply_rect<false, M, true>(s, F->R, F->r.as<double>(), b, F->lpr_r,
+                                   FirstStep<M>{smooth_diag<M>(s, L), L.inv_theta, d, x});
+      else
+        hipLaunchKernelGGL(k_cheb_first<M>, dim3(grid_for(L.n)), dim3(kBlock), 0, s->stream,
+                           L.n, b, smooth_diag<M>(s, L), L.inv_theta, d, x);
       apply_op<E_CHEB, M>(s, L, x, b, d, c1, c2, y, nullptr);
     });
     L.fuse0 = fused <= split;
   }
   if (coarsest) return;
   Level& C = s->levels[l + 1];
-  L.lpr_r = best_lpr(s, transfer_lanes(L.R), [&](int c) {
+  L.lpr_r = best_lpr(s, transfer_lanes(L.R), 1, [&](int c) {
     apply_rect<false, M>(s, L.R, L.r.as<double>(), C.b.as<double>(), c);
   });
   if (prolong_fusable(s, L)) {
     L.lpr_p = 0;
-    L.lpr_p = best_lpr(s, prolong_lanes(L), [&](int c) {
+    L.lpr_p = best_lpr(s, prolong_lanes(L), 4, [&](int c) {
       L.lpr_p = c;
       prolong_cheb<M>(s, L, C.x.as<double>(), L.t.as<double>(), b, d, y);
     });
     return;
   }
-  L.lpr_p = best_lpr(s, transfer_lanes(L.P), [&](int c) {
+  L.lpr_p = best_lpr(s, transfer_lanes(L.P), 1, [&](int c) {
     apply_rect<true, M>(s, L.P, C.x.as<double>(), L.t.as<double>(), c);
   });
 }

@@ -111,8 +111,11 @@ def test_every_launch_choice_meets_bars_and_repeats_after_reassembly():
     """Each lane count of each level's smoother, restriction and prolongation,
     and the split first smoothing step, set by hand one at a time: the
     pressure meets the bars, and a re-assembly with the same choice repeats it
-    bitwise (the hierarchy never depends on the choices)."""
+    bitwise (the hierarchy never depends on the choices).  Choices outside
+    the allowed sets are refused."""
     import torch
+
+    import paper_1810_08572_amd as ppe
 
     m, f, c, b = case(shape=(24, 24, 24), fl="front", fl_seed=2, seed=2)
     sy = assembly.masked_system(m.n_cells, m.owner, m.neigh, c, f)
@@ -123,13 +126,18 @@ def test_every_launch_choice_meets_bars_and_repeats_after_reassembly():
     variants = []
     for lvl in range(nlev - 1):
         for k in range(3):
-            for lpr in (4, 8, 16, 32, 64):
+            # the smoother takes 4..64 lanes, the transfers 1..64 (a fused
+            # prolongation runs 1 and 2 as 4)
+            for lpr in (4, 8, 16, 32, 64) if k == 0 else (1, 2, 4, 8, 16, 32, 64):
                 if k == 0 and lvl == 0:
                     continue  # the finest level is ELL: no lanes per row
                 ch = [0, 0, 0, 1]
                 ch[k] = lpr
                 variants.append((lvl, tuple(ch)))
         variants.append((lvl, (0, 0, 0, 0)))
+    for bad in ((2, 0, 0, 1), (0, 3, 0, 1), (0, 0, 128, 1), (0, 0, 0, 2)):
+        with pytest.raises(ppe.PpeError):
+            s.set_level_launch(0, bad)
     for lvl, ch in variants:
         outs = []
         for _ in range(2):
