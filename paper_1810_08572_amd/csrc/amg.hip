@@ -997,6 +997,8 @@ __global__ void k_densify(int n, const int* __restrict__ rp, const int* __restri
     const int lpr_ = (LPR_);                                                                 \
     const int g_ = grid_for((int64_t)(rows) * lpr_);                                         \
     switch (lpr_) {                                                                          \
+      case 1: hipLaunchKernelGGL(K<1>, dim3(g_), dim3(kBlock), 0, s->stream, __VA_ARGS__); break;   \
+      case 2: hipLaunchKernelGGL(K<2>, dim3(g_), dim3(kBlock), 0, s->stream, __VA_ARGS__); break;   \
       case 4: hipLaunchKernelGGL(K<4>, dim3(g_), dim3(kBlock), 0, s->stream, __VA_ARGS__); break;   \
       case 8: hipLaunchKernelGGL(K<8>, dim3(g_), dim3(kBlock), 0, s->stream, __VA_ARGS__); break;   \
       case 16: hipLaunchKernelGGL(K<16>, dim3(g_), dim3(kBlock), 0, s->stream, __VA_ARGS__); break; \
@@ -1005,6 +1007,18 @@ __global__ void k_densify(int n, const int* __restrict__ rp, const int* __restri
     }                                                                                        \
     PPE_LAUNCH_CHECK();                                                                      \
   } while (0)
+// Lanes per row of the aggregation kernels (strength, the MIS-2 rounds and
+// the two joining passes): the power of two from 1 to 64 nearest to half the
+// mean row length.  Their results are maxima and per-entry tests, so they do
+// not depend on it.
+static int agg_lanes(const Csr& A) {
+  const double target = (A.n ? (double)A.nnz / A.n : 1.0) / 2.0;
+  int best = 1;
+  for (int c = 2; c <= 64; c *= 2)
+    if (std::fabs(std::log2(c / target)) < std::fabs(std::log2(best / target))) best = c;
+  return best;
+}
+
 // Launch configuration of k_spgemm_rows for one product.
 struct SpConfig {
   int lpr, W, H, rpb, threads;
@@ -1414,7 +1428,7 @@ void build_hierarchy(ppe_solver* s) {
       unsigned char* st = L.state.get<unsigned char>(n);
       unsigned char* st2 = L.state2.get<unsigned char>(n);
       unsigned long long* m1 = L.m1.get<unsigned long long>(n);
-      const int lpr = lanes_for(L.A);
+      const int lpr = agg_lanes(L.A);
       PPE_ROWS(lpr, k_strength, n, n, L.A.rp(), L.A.ci(), L.A.v(), L.diag.as<double>(), theta2,
                strong, st);
       const uint32_t salt = level_salt(lvl);

@@ -179,7 +179,7 @@ __device__ __forceinline__ double row_sum(double s, int k0, int k1, int lane,
   }
   return s;
 }
-constexpr int kRowU = 4;
+constexpr int kRowU = 8;
 
 // A row's own values that the epilogue reads, loaded by the row's first lane
 // before the row's entries (so they are not a dependent load after the
