@@ -249,23 +249,22 @@ def leg_summary(rec, K, base=None):
 
 def counter_traffic(workload, kernel):
     """Bytes per launch of `kernel` from the committed memory-counter summary
-    of `workload`, or None when the summary covers another kernel or the
-    kernel's source region changed since the counters were taken."""
+    of `workload`, or None when the summary does not cover the kernel or the
+    source region of the solve kernels changed since the counters were
+    taken."""
     import hashlib
 
     try:
         with open(os.path.join(ROOT, "profiles", "roofline_traffic.json")) as f:
             data = json.load(f)
         entry = data["workloads"][workload]
-        if entry["kernel"] != kernel:
-            return None
         with open(os.path.join(ROOT, data["source_file"])) as f:
             text = f.read()
         begin, end = entry["source_region"]
         region = text[text.index(begin):text.index(end)]
         if hashlib.sha256(region.encode()).hexdigest() != entry["source_sha256"]:
             return None
-        return entry["bytes_per_launch"]
+        return entry["kernels"][kernel]["bytes_per_launch"]
     except (OSError, KeyError, ValueError):
         return None
 

@@ -43,7 +43,8 @@ def test_counter_traffic_is_reported_only_for_the_current_kernel():
         begin, end = e["source_region"]
         current = begin in text and end in text and hashlib.sha256(
             text[text.index(begin):text.index(end)].encode()).hexdigest() == e["source_sha256"]
-        t = bench.counter_traffic(workload, e["kernel"])
-        assert (t is not None and t > 0) if current else t is None, workload
+        for kernel in e["kernels"]:
+            t = bench.counter_traffic(workload, kernel)
+            assert (t is not None and t > 0) if current else t is None, (workload, kernel)
         assert bench.counter_traffic(workload, "k_no_such_kernel") is None
     assert bench.counter_traffic("no_such_workload", "k_csr<2, 16, double>") is None
