@@ -376,11 +376,13 @@ __device__ __forceinline__ T block_max(T v) {
 constexpr int kRedBlocks = 1024;
 
 template <int BS, int NV>
-__device__ __forceinline__ void write_partials(const double (&v)[NV], double* partials) {
+__device__ __forceinline__ void write_partials(const double (&v)[NV], double* partials,
+                                               int slot = -1) {
+  const int at = slot < 0 ? (int)blockIdx.x : slot;  // a block that works for another's slot
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     double s = block_sum<BS>(v[k]);
-    if (threadIdx.x == 0) partials[(size_t)k * gridDim.x + blockIdx.x] = s;
+    if (threadIdx.x == 0) partials[(size_t)k * gridDim.x + at] = s;
   }
 }
 
