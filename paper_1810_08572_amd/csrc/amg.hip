@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(kBlock) k_strength(int n, const int* __restric
                                                      const double* __restrict__ diag, double theta2,
                                                      unsigned char* __restrict__ strong,
                                                      unsigned char* __restrict__ state) {
-  const int i = (blockIdx.x * kBlock + threadIdx.x) / LPR, lane = threadIdx.x % LPR;
+  const int i = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / LPR, lane = threadIdx.x % LPR;
   int deg = 0;
   if (i < n) {
     const double di = diag[i];
@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(kBlock) k_mis_max1(int n, const int* __restric
                                                      const unsigned char* __restrict__ state,
                                                      uint32_t salt,
                                                      unsigned long long* __restrict__ m1) {
-  const int i = (blockIdx.x * kBlock + threadIdx.x) / LPR, lane = threadIdx.x % LPR;
+  const int i = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / LPR, lane = threadIdx.x % LPR;
   unsigned long long m = 0;
   if (i < n) {
     for (int k = rp[i] + lane; k < rp[i + 1]; k += LPR) {
@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(kBlock) k_mis_max2(int n, const int* __restric
                                                      const unsigned long long* __restrict__ m1,
                                                      unsigned char* __restrict__ next,
                                                      int* __restrict__ undecided) {
-  const int i = (blockIdx.x * kBlock + threadIdx.x) / LPR, lane = threadIdx.x % LPR;
+  const int i = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / LPR, lane = threadIdx.x % LPR;
   const unsigned char st = i < n ? state[i] : (unsigned char)S_OUT;
   unsigned long long m = 0;
   int und = 0;
@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(kBlock) k_agg_first(int n, const int* __restri
                                                       const unsigned char* __restrict__ state,
                                                       const int* __restrict__ root_id,
                                                       int* __restrict__ agg1) {
-  const int i = (blockIdx.x * kBlock + threadIdx.x) / LPR, lane = threadIdx.x % LPR;
+  const int i = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / LPR, lane = threadIdx.x % LPR;
   int a = -1;
   const bool root = i < n && state[i] == S_IN;
   if (i < n && !root) {
@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(kBlock) k_agg_second(int n, const int* __restr
                                                        const unsigned char* __restrict__ strong,
                                                        const int* __restrict__ agg1,
                                                        int* __restrict__ agg, int* __restrict__ flag) {
-  const int i = (blockIdx.x * kBlock + threadIdx.x) / LPR, lane = threadIdx.x % LPR;
+  const int i = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / LPR, lane = threadIdx.x % LPR;
   const int a1 = i < n ? agg1[i] : 0;
   double best = -1.0;
   int bestj = INT32_MAX;

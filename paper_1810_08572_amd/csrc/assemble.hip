@@ -229,7 +229,7 @@ __global__ void k_fill_rows(const int* __restrict__ perm, int n_active,
                             double* __restrict__ diag, int W, int* __restrict__ ell_col,
                             double* __restrict__ ell_val, double* __restrict__ B,
                             const double* __restrict__ shift) {
-  int r = blockIdx.x * kBlock + threadIdx.x;
+  int r = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (r >= n_active) return;
   int c = perm[r];
   const bool pin = is_pin[c] != 0;

@@ -45,17 +45,6 @@ enum Scal : int { S_POW = 0, S_N = 2 };
 // c2 = 1 is an l1-Jacobi sweep.  `diag` is always the matrix diagonal (the
 // finest level's product and the power steps read it).
 
-// Workgroups are dispatched round-robin over the eight XCDs (block b runs on
-// XCD b mod 8), and each XCD has its own L2.  The finest level's ELL kernels
-// renumber their blocks so that each XCD takes one contiguous run of rows:
-// the rows one plane of cells apart, which gather the same values, then meet
-// in one L2 instead of eight (the 128^3 residual pass: 28.6 -> 21.1 us).  The
-// coarse CSR kernels keep the plain order, which measured faster for them.
-// A bijection of [0, G): XCD x's blocks take the run from x q + min(x, r).
-__device__ __forceinline__ int xcd_block(int b, int G) {
-  const int x = b & 7, k = b >> 3, q = G >> 3, r = G & 7;
-  return x * q + min(x, r) + k;
-}
 
 // Operand of the matrix product: x_j, or for E_CHEB0 the first Chebyshev
 // iterate c0 b_j / diag_j (the same expression the unfused first step stores).
