@@ -362,17 +362,21 @@ ppe_status ppe_apply_matrix(ppe_solver* s, int level, const double* x, double* y
 /* z = M r: one V-cycle from level 0 with a zero initial guess (length n_active). */
 ppe_status ppe_apply_vcycle(ppe_solver* s, const double* r, double* z);
 
-/* Launch choices of level l's solve kernels, choice[4] (host): lanes per row
- * of the coarse smoother (0 = the fixed rule, else 4, 8, 16, 32 or 64), of
- * the restriction and of the prolongation (0, or a power of two from 1 to
- * 64; on the coarse levels of the FP64 V-cycle the prolongation runs in one
- * pass with the first post-smoothing step, reading the Galerkin product's
- * A P, and that pass takes 4 lanes for a choice of 1 or 2), and 1 if the
- * first two smoothing steps from a zero guess run fused, 0 if split.  The
- * autotuner
- * sets them at assembly; setting them by hand (until the next assembly) lets
- * a test run every variant.  They never affect the hierarchy, only the
- * solve's order of summation.  PPE_ERR_ARG for a value outside those sets. */
+/* Launch choices of level l's solve kernels, choice[5] (host):
+ *   [0] lanes per row of the coarse smoother (0 = the fixed rule, else 4, 8,
+ *       16, 32 or 64);
+ *   [1], [2] lanes per row of the restriction and of the prolongation (0, or
+ *       a power of two from 1 to 64; a fused prolongation takes 4 for 1 or 2);
+ *   [3] 1 if the first two smoothing steps from a zero guess run as one
+ *       fused pass, 0 if split (on a coarse level the restriction into it
+ *       then takes the first step);
+ *   [4] 1 if the prolongation runs in one pass with the first
+ *       post-smoothing step, reading the Galerkin product's A P (possible on
+ *       the coarse levels of the FP64 V-cycle), 0 for separate passes.
+ * The fixed rules set them at assembly, or the autotuner when enabled;
+ * setting them by hand (until the next assembly) lets a test run every
+ * variant.  They never affect the hierarchy, only the solve's order of
+ * summation.  PPE_ERR_ARG for a value outside those sets. */
 ppe_status ppe_get_level_launch(const ppe_solver* s, int level, int32_t* choice);
 ppe_status ppe_set_level_launch(ppe_solver* s, int level, const int32_t* choice);
 

@@ -598,13 +598,16 @@ class Solver:
         return y
 
     def level_launch(self, level):
-        """(lanes smoother, lanes restriction, lanes prolongation, fused first step)."""
-        c = (_I32 * 4)()
+        """(lanes smoother, lanes restriction, lanes prolongation, fused first
+        steps, fused prolongation)."""
+        c = (_I32 * 5)()
         self._chk(self._lib.ppe_get_level_launch(self._h, level, c))
         return tuple(c)
 
     def set_level_launch(self, level, choice):
-        c = (_I32 * 4)(*[int(v) for v in choice])
+        if len(choice) != 5:
+            raise ValueError("a launch choice has five entries")
+        c = (_I32 * 5)(*[int(v) for v in choice])
         self._chk(self._lib.ppe_set_level_launch(self._h, level, c))
 
     def apply_vcycle(self, r):

@@ -503,6 +503,7 @@ ppe_status ppe_get_level_launch(const ppe_solver* s, int level, int32_t* choice)
   choice[1] = L.lpr_r;
   choice[2] = L.lpr_p;
   choice[3] = L.fuse0 ? 1 : 0;
+  choice[4] = L.fuse_p ? 1 : 0;
   return PPE_OK;
 }
 
@@ -514,13 +515,14 @@ ppe_status ppe_set_level_launch(ppe_solver* s, int level, const int32_t* choice)
     return v == 0 || (v >= lo && v <= 64 && (v & (v - 1)) == 0);
   };
   if (!ok(choice[0], 4) || !ok(choice[1], 1) || !ok(choice[2], 1) ||
-      (choice[3] != 0 && choice[3] != 1))
+      (choice[3] != 0 && choice[3] != 1) || (choice[4] != 0 && choice[4] != 1))
     return PPE_ERR_ARG;
   ppe::Level& L = s->levels[level];
   L.lpr_a = choice[0];
   L.lpr_r = choice[1];
   L.lpr_p = choice[2];
   L.fuse0 = choice[3] != 0;
+  L.fuse_p = choice[4] != 0;
   ppe::drop_graph(s);  // a captured graph holds the old launches
   return PPE_OK;
 }

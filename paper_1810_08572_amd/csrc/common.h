@@ -157,12 +157,13 @@ struct Level {
   DevBuf agg;            // int[n], aggregate id or -1
   DevBuf B;              // near-null vector
   double rho = 1.0;      // spectral bound of D^-1 A
-  // launch choices of the solve kernels (0 / true: the fixed rules; set by
-  // the autotuner when enabled): lanes per row of the smoother's CSR
-  // kernel, of the restriction and of the prolongation; whether the first
-  // two Chebyshev steps from a zero guess run as one fused pass
+  // launch choices of the solve kernels (0: the fixed rule; set by the
+  // autotuner when enabled): lanes per row of the smoother's CSR kernel, of
+  // the restriction and of the prolongation; whether the first two Chebyshev
+  // steps from a zero guess run as one fused pass; whether the prolongation
+  // runs fused with the first post-smoothing step (where it can)
   int lpr_a = 0, lpr_r = 0, lpr_p = 0;
-  bool fuse0 = true;
+  bool fuse0 = true, fuse_p = true;
   double inv_theta = 0.0;
   std::vector<double> c1, c2;  // Chebyshev steps 2..degree
   int mis_rounds = 0;
@@ -265,8 +266,8 @@ struct ppe_solver {
   bool shifted = false;  // the last assembly carried a diagonal shift (no pins)
   ppe::DevBuf prev_coeff;
   // autotuner choices per (level, FP32, quarter-octave bins of rows and of
-  // entries): {lpr_a, fuse0, lpr_r, lpr_p}
-  std::map<std::array<int, 4>, std::array<int, 4>> tune_cache;
+  // entries): {lpr_a, fuse0, lpr_r, lpr_p, fuse_p}
+  std::map<std::array<int, 4>, std::array<int, 5>> tune_cache;
 
   // HIP graph of two PCG iterations, captured once per hierarchy
   hipStream_t gstream = nullptr;

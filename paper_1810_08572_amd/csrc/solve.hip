@@ -1009,9 +1009,10 @@ void apply_rect(ppe_solver* s, const Csr& P, const double* x, double* y, int lpr
 #undef PPE_RECT
 }
 
-// Whether level L's prolongation runs fused with its first post-smoothing
-// step: on the coarse levels of the FP64 V-cycle, while AP still equals A P,
-// when the smoother takes at least two steps.
+// Whether level L's prolongation can run fused with its first
+// post-smoothing step: on the coarse levels of the FP64 V-cycle, while AP
+// still equals A P, when the smoother takes at least two steps (and whether
+// it does: the level's launch choice as well).
 //  - The finest level keeps its separate passes: there the fused pass, with
 //    CSR rows of P and AP gathered beside the ELL rows of A, took as long as
 //    the prolongation and the ELL step together, while on the coarse levels
@@ -1019,8 +1020,21 @@ void apply_rect(ppe_solver* s, const Csr& P, const double* x, double* y, int lpr
 //  - The mixed V-cycle keeps them too: rounded to FP32 separately, the
 //    stored AP is no longer the product of the stored A and P, and the
 //    V-cycle would stop being symmetric at the level of that rounding.
-bool prolong_fusable(const ppe_solver* s, const Level& L) {
+bool prolong_can_fuse(const ppe_solver* s, const Level& L) {
   return s->opt.precision != PPE_MIXED && &L != &s->levels[0] && L.ap_ok && !L.c1.empty();
+}
+bool prolong_fusable(const ppe_solver* s, const Level& L) {
+  return L.fuse_p && prolong_can_fuse(s, L);
+}
+
+// The fixed rule for fusing: the fused pass reads A P where the separate
+// passes read P and write and re-read x, and saves one dispatch.  Where A P
+// holds more than about 16 MB beyond that (128^3 level 1: 9 M entries), the
+// separate passes move less (182 against about 80 MB there); a level below
+// that is latency-bound and the saved dispatch wins.
+bool fuse_rule(const Level& L) {
+  const double extra = 12.0 * (double)L.AP.nnz - 16.0 * (double)L.n;
+  return extra <= 16.0e6;
 }
 
 // Lanes per row of the fused pass: the launch choice if set (at least
@@ -1308,6 +1322,7 @@ void prepare_solve_levels(ppe_solver* s) {
     // level of the 128^3 cube and the plate); the finest level has no
     // restriction before it and keeps the fused pair.
     L.fuse0 = l == 0;
+    L.fuse_p = fuse_rule(L);
     const int n = L.n > 0 ? L.n : 1;
     L.x.get<double>(n);
     L.b.get<double>(n);
@@ -1667,9 +1682,9 @@ float time_launches(ppe_solver* s, F&& launch, int reps = 3) {
 constexpr int kLprs[] = {1, 2, 4, 8, 16, 32, 64};
 
 // The fastest lanes-per-row choice, candidates from a quarter of the fixed
-// rule's choice (and at least lo) up to 64.
+// rule's choice (and at least lo) up to 64; its time in *t_out if given.
 template <class F>
-int best_lpr(ppe_solver* s, int rule, int lo, F&& run) {
+int best_lpr(ppe_solver* s, int rule, int lo, F&& run, float* t_out = nullptr) {
   int best = rule;
   float tbest = 1e30f;
   for (int c : kLprs) {
@@ -1677,6 +1692,7 @@ int best_lpr(ppe_solver* s, int rule, int lo, F&& run) {
     const float t = time_launches(s, [&]() { run(c); });
     if (t < tbest) { tbest = t; best = c; }
   }
+  if (t_out) *t_out = tbest;
   return best;
 }
 
@@ -1722,17 +1738,31 @@ void tune_level(ppe_solver* s, int l) {
   L.lpr_r = best_lpr(s, transfer_lanes(L.R), 1, [&](int c) {
     apply_rect<false, M>(s, L.R, L.r.as<double>(), C.b.as<double>(), c);
   });
-  if (prolong_fusable(s, L)) {
-    L.lpr_p = 0;
-    L.lpr_p = best_lpr(s, prolong_lanes(L), 4, [&](int c) {
-      L.lpr_p = c;
-      prolong_cheb<M>(s, L, C.x.as<double>(), L.t.as<double>(), b, d, y);
-    });
-    return;
-  }
-  L.lpr_p = best_lpr(s, transfer_lanes(L.P), 1, [&](int c) {
-    apply_rect<true, M>(s, L.P, C.x.as<double>(), L.t.as<double>(), c);
+  // the prolongation alone, then (where it can fuse) the fused pass against
+  // the prolongation followed by the first post-smoothing step
+  float t_rect = 0.f;
+  const int lp_rect = best_lpr(
+      s, transfer_lanes(L.P), 1,
+      [&](int c) { apply_rect<true, M>(s, L.P, C.x.as<double>(), L.t.as<double>(), c); },
+      &t_rect);
+  L.lpr_p = lp_rect;
+  L.fuse_p = false;
+  if (!prolong_can_fuse(s, L)) return;
+  const float t_step = time_launches(s, [&]() {
+    apply_op<E_CHEB, M>(s, L, L.t.as<double>(), b, d, 0.0, L.inv_theta, y, nullptr);
   });
+  float t_fused = 0.f;
+  L.fuse_p = true;
+  L.lpr_p = 0;
+  const int lp_fused = best_lpr(
+      s, prolong_lanes(L), 4,
+      [&](int c) {
+        L.lpr_p = c;
+        prolong_cheb<M>(s, L, C.x.as<double>(), L.t.as<double>(), b, d, y);
+      },
+      &t_fused);
+  L.fuse_p = t_fused <= t_rect + t_step;
+  L.lpr_p = L.fuse_p ? lp_fused : lp_rect;
 }
 
 }  // namespace
@@ -1751,13 +1781,14 @@ void autotune_levels(ppe_solver* s) {
       L.fuse0 = it->second[1] != 0;
       L.lpr_r = it->second[2];
       L.lpr_p = it->second[3];
+      L.fuse_p = it->second[4] != 0;
       continue;
     }
     if (f32)
       tune_level<float>(s, l);
     else
       tune_level<double>(s, l);
-    s->tune_cache[key] = {L.lpr_a, L.fuse0 ? 1 : 0, L.lpr_r, L.lpr_p};
+    s->tune_cache[key] = {L.lpr_a, L.fuse0 ? 1 : 0, L.lpr_r, L.lpr_p, L.fuse_p ? 1 : 0};
   }
 }
 

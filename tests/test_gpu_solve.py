@@ -108,11 +108,12 @@ def test_autotuned_solver_meets_bars(precision):
 
 
 def test_every_launch_choice_meets_bars_and_repeats_after_reassembly():
-    """Each lane count of each level's smoother, restriction and prolongation,
-    and the split first smoothing step, set by hand one at a time: the
-    pressure meets the bars, and a re-assembly with the same choice repeats it
-    bitwise (the hierarchy never depends on the choices).  Choices outside
-    the allowed sets are refused."""
+    """Each lane count of each level's smoother, restriction and prolongation
+    (fused with the first post-smoothing step and separate), and the split
+    first smoothing step, set by hand one at a time: the pressure meets the
+    bars, and a re-assembly with the same choice repeats it bitwise (the
+    hierarchy never depends on the choices).  Choices outside the allowed
+    sets are refused."""
     import torch
 
     import paper_1810_08572_amd as ppe
@@ -131,11 +132,14 @@ def test_every_launch_choice_meets_bars_and_repeats_after_reassembly():
             for lpr in (4, 8, 16, 32, 64) if k == 0 else (1, 2, 4, 8, 16, 32, 64):
                 if k == 0 and lvl == 0:
                     continue  # the finest level is ELL: no lanes per row
-                ch = [0, 0, 0, 1]
-                ch[k] = lpr
-                variants.append((lvl, tuple(ch)))
-        variants.append((lvl, (0, 0, 0, 0)))
-    for bad in ((2, 0, 0, 1), (0, 3, 0, 1), (0, 0, 128, 1), (0, 0, 0, 2)):
+                for fuse_p in ((0, 1) if k == 2 else (1,)):
+                    ch = [0, 0, 0, 1, fuse_p]
+                    ch[k] = lpr
+                    variants.append((lvl, tuple(ch)))
+        variants.append((lvl, (0, 0, 0, 0, 1)))
+        variants.append((lvl, (0, 0, 0, 0, 0)))
+    for bad in ((2, 0, 0, 1, 1), (0, 3, 0, 1, 1), (0, 0, 128, 1, 1), (0, 0, 0, 2, 1),
+                (0, 0, 0, 1, 2)):
         with pytest.raises(ppe.PpeError):
             s.set_level_launch(0, bad)
     for lvl, ch in variants:
