@@ -896,8 +896,9 @@ const M* smooth_diag(const ppe_solver* s, const Level& L) {
 
 // Lanes per row of the solve's CSR kernels by default.  The rules are fits
 // to what the autotuner picked on the 128^3 cube and the 1.5 M-cell plate
-// (FP64 and mixed): about five entries per lane for the smoothing steps,
-// three for the restriction and the plain prolongation, and about
+// (FP64 and mixed): about 1.8 sqrt(row length) lanes for the smoothing steps
+// (8 for rows of 30 entries, 16 for 128, 32 for 219), three entries per lane
+// for the restriction and the plain prolongation, and about
 // 3 sqrt(row length) lanes for the fused prolongation (whose rows of A, P and
 // A P are read together).  The plain transfers go down to one lane per row
 // (the finest prolongation has three to four entries a row); the smoothing
@@ -912,7 +913,9 @@ int lanes_near(double target, int lo = 4) {
 }
 int widen_small(const Csr& M, int lpr) { return (int64_t)M.n * lpr < 65536 ? 64 : lpr; }
 double mean_row(const Csr& M) { return M.n ? (double)M.nnz / M.n : 1.0; }
-int smooth_lanes(const Csr& A) { return widen_small(A, lanes_near(mean_row(A) / 5.0)); }
+int smooth_lanes(const Csr& A) {
+  return widen_small(A, lanes_near(1.8 * std::sqrt(mean_row(A))));
+}
 int transfer_lanes(const Csr& M) { return widen_small(M, lanes_near(mean_row(M) / 3.0, 1)); }
 
 // Apply the level operator with epilogue EPI, matrix values in type M.
