@@ -408,6 +408,7 @@ def c5_legs(ppe, torch, wl, d_in, K, W, base, net):
     # changed masks keep the coarse levels of the last full setup (at most
     # eight assemblies in a row, active set within 10 % of that build's)
     for name, prec, guess in (("fp64_zero_guess_coarse_reuse", "fp64", "zero"),
+                              ("fp64_previous_guess_coarse_reuse", "fp64", "prev"),
                               ("mixed_previous_guess_coarse_reuse", "mixed", "prev"),
                               ("mixed_learned_coarse_reuse", "mixed", "learned")):
         rec = run_leg(ppe, torch, wl, d_in, steps, warm, prec, guess=guess, net=net, reuse=True,
