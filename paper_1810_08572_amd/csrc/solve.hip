@@ -159,6 +159,12 @@ __global__ void __launch_bounds__(kBlock) k_ell(int n, int W, const int* __restr
 // CSR row of v[k] op(ci[k]), added in that order; the loads of U entries are
 // requested before the first is used (the order of the sum is that of the
 // plain loop).
+// FP32 values (the mixed V-cycle) are loaded unconditionally, from the
+// lane's first entry past the row's end: loaded behind a branch, each was
+// converted to double inside it and so waited for one at a time.  Column
+// indices, gathers and FP64 values stay behind the branch, where the loads
+// already issue back to back (loading them unconditionally cost the FP64
+// V-cycle 9%).
 template <int LPR, int U, class M, class Op>
 __device__ __forceinline__ double row_sum(double s, int k0, int k1, int lane,
                                           const int* __restrict__ ci, const M* __restrict__ v,
@@ -170,7 +176,10 @@ __device__ __forceinline__ double row_sum(double s, int k0, int k1, int lane,
     for (int u = 0; u < U; ++u) {
       const int kk = k + u * LPR;
       c[u] = kk < k1 ? ci[kk] : -1;
-      w[u] = kk < k1 ? v[kk] : M(0);
+      if constexpr (sizeof(M) == 4)
+        w[u] = v[kk < k1 ? kk : k];
+      else
+        w[u] = kk < k1 ? v[kk] : M(0);
     }
     double g[U];
 #pragma unroll
@@ -330,7 +339,8 @@ __global__ void __launch_bounds__(kBlock) k_csr_rect(int n, const int* __restric
 constexpr int kFuseU = 4;  // CSR entries per lane requested before any is used
 
 // Entries k0 + lane + u LPR (u < U) of a CSR row ending at k1: columns (-1
-// past the end) and values.
+// past the end) and values (FP32 values loaded unconditionally, as in
+// row_sum; an empty row loads none).
 template <int LPR, int U, class M>
 __device__ __forceinline__ void chunk_load(int k0, int k1, int lane, const int* __restrict__ ci,
                                            const M* __restrict__ v, int (&c)[U], M (&w)[U]) {
@@ -338,7 +348,10 @@ __device__ __forceinline__ void chunk_load(int k0, int k1, int lane, const int* 
   for (int u = 0; u < U; ++u) {
     const int k = k0 + lane + u * LPR;
     c[u] = k < k1 ? ci[k] : -1;
-    w[u] = k < k1 ? v[k] : M(0);
+    if constexpr (sizeof(M) == 4)
+      w[u] = k1 > k0 ? v[k < k1 ? k : k0] : M(0);
+    else
+      w[u] = k < k1 ? v[k] : M(0);
   }
 }
 
