@@ -107,11 +107,22 @@ __device__ __forceinline__ double ell_row(double s, int i, int n, int W,
   if (WM > 0) {
     int col[WM > 0 ? WM : 1];
     M v[WM > 0 ? WM : 1];
+    if (W == WM) {
+      // every slot stored (the hexahedral case): no condition at all, so the
+      // loads issue back to back whatever the value type
 #pragma unroll
-    for (int k = 0; k < WM; ++k) {
-      const size_t e = (size_t)k * n + i;
-      col[k] = k < W ? ecol[e] : i;
-      v[k] = k < W ? eval[e] : M(0);
+      for (int k = 0; k < WM; ++k) {
+        const size_t e = (size_t)k * n + i;
+        col[k] = ecol[e];
+        v[k] = eval[e];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < WM; ++k) {
+        const size_t e = (size_t)k * n + i;
+        col[k] = k < W ? ecol[e] : i;
+        v[k] = k < W ? eval[e] : M(0);
+      }
     }
     double g[WM > 0 ? WM : 1];
 #pragma unroll
