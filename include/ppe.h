@@ -80,7 +80,8 @@ typedef struct {
   int max_iter;       /* PCG iteration cap, default 500 */
   int cheb_degree;    /* Chebyshev smoother degree per application, default 2 */
   double cheb_ratio;  /* smoothing interval [rho/ratio, rho], default 30 */
-  int coarse_max;     /* stop coarsening at <= this many rows, default 128 */
+  int coarse_max;     /* stop coarsening at <= this many rows, default 512 (the
+                         coarsest level, up to 1024 rows, is inverted) */
   int max_levels;     /* hierarchy depth cap, default 10 */
   double theta;       /* strength threshold, default 0.08 */
   int check_every;    /* PCG iterations between host convergence checks when not

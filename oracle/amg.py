@@ -38,7 +38,7 @@ parameter.  This project's reading is smoothed aggregation:
              A because D_l1 - A is diagonally dominant;
   cycle      V-cycle with the same smoother before and after the coarse
              correction (so the preconditioner is symmetric); the coarsest
-             level (at most coarse_max rows, default 128) is solved with a
+             level (at most coarse_max rows, default 512) is solved with a
              dense inverse;
   reuse      (optional) after a mask change, keep the coarse levels of an
              earlier hierarchy and rebuild only the finest one, its
@@ -281,7 +281,7 @@ class Hierarchy:
         return sum(l.A.nnz for l in self.levels) / nnz0 if nnz0 else 1.0
 
 
-def build_hierarchy(A0: sp.csr_matrix, theta=0.08, coarse_max=128, max_levels=10,
+def build_hierarchy(A0: sp.csr_matrix, theta=0.08, coarse_max=512, max_levels=10,
                     degree=2, ratio=30.0, dense_max=4096, smoother="chebyshev") -> Hierarchy:
     if smoother not in ("chebyshev", "l1jacobi"):
         raise ValueError(f"unknown smoother {smoother!r}")

@@ -353,7 +353,7 @@ class Solver:
     """Pressure solver bound to the current device and torch stream."""
 
     def __init__(self, precision="fp64", rtol=1e-10, max_iter=500, cheb_degree=2,
-                 cheb_ratio=30.0, coarse_max=128, max_levels=10, theta=0.08, stream=None,
+                 cheb_ratio=30.0, coarse_max=512, max_levels=10, theta=0.08, stream=None,
                  use_graph=True, check_every=2, autotune=False, reuse_unchanged=False,
                  krylov="bicgstab", smoother="chebyshev", allocator="torch", coarse_reuse=0):
         import torch

@@ -742,124 +742,16 @@ __global__ void __launch_bounds__(kWave) k_rank_rows(const int* __restrict__ rp,
 }
 
 // ------------------------------------------------------------------ dense coarsest
-// Explicit inverse of the SPD matrix in the left half of the n x 2n
-// row-major array G = [A | I] by Gauss-Jordan elimination without pivoting
-// (pivots of an SPD matrix are positive).  One workgroup; at step k only the
-// columns k..n+k can change.  The inverse is left in the right half and
-// copied to Ainv.
-__global__ void __launch_bounds__(1024) k_dense_inverse(int n, double* __restrict__ G,
-                                                        double* __restrict__ Ainv,
-                                                        int* __restrict__ flag) {
-  __shared__ double f[kDenseMax];
-  __shared__ double piv;
-  const int t = threadIdx.x, nt = blockDim.x;
-  const int w = 2 * n;
-  for (int k = 0; k < n; ++k) {
-    if (t == 0) {
-      double d = G[(size_t)k * w + k];
-      if (!(d > 0.0)) { atomicOr(flag, SE_DENSE); d = 1.0; }
-      piv = d;
-    }
-    for (int i = t; i < n; i += nt) f[i] = G[(size_t)i * w + k];
-    __syncthreads();
-    const double inv = 1.0 / piv;
-    const int ncol = n + 1;  // columns k .. n+k
-    for (int j = t; j < ncol; j += nt) G[(size_t)k * w + k + j] *= inv;
-    __syncthreads();
-    for (int64_t p = t; p < (int64_t)n * ncol; p += nt) {
-      const int i = (int)(p / ncol), j = k + (int)(p % ncol);
-      if (i != k) G[(size_t)i * w + j] -= f[i] * G[(size_t)k * w + j];
-    }
-    __syncthreads();
-  }
-  for (int64_t p = t; p < (int64_t)n * n; p += nt) {
-    const int i = (int)(p / n), j = (int)(p % n);
-    Ainv[p] = G[(size_t)i * w + n + j];
-  }
-}
+// Explicit inverse of the SPD coarsest matrix by Gauss-Jordan elimination
+// without pivoting (pivots of an SPD matrix are positive): at step k the
+// pivot row is divided by the pivot with a_kk replaced by 1, and every other
+// row i gets a_ij -= f_i a_kj with a_ik replaced by 0 (f the pivot column),
+// which leaves A^-1 in place of A.  Up to kDenseBlk rows one workgroup does
+// it from the n x 2n row-major array G = [A | I] (k_dense_inverse_blk);
+// larger levels take the blocked form over many workgroups (k_ginv_*).
+constexpr int kDenseBlk = 128;
 
-// The same elimination done in place with the matrix held in registers (the
-// identity half implicit): at step k the pivot row is divided by the pivot
-// with a_kk replaced by 1, and every other row i gets a_ij -= f_i a_kj with
-// a_ik replaced by 0.  With G = ceil(n / E) row groups, thread t < G n owns
-// column j = t mod n and the E consecutive rows g E .. g E + E - 1 (g = t / n)
-// (rows past n are carried as throw-away values).  The pivot column and the (unscaled) pivot row of step k are
-// published in LDS by their owners at the end of step k - 1, into the buffer
-// step k - 1 did not read, so one barrier per step suffices; every thread
-// scales its own entry of the pivot row.  The update of an owned entry is a
-// load from LDS at a fixed offset, a multiply and a subtract; column k and
-// row k are fixed up by their owners only.
-constexpr int kDenseReg = 256;
-template <int E>
-__global__ void __launch_bounds__(1024) k_dense_inverse_reg(int n, const double* __restrict__ Gm,
-                                                            double* __restrict__ Ainv,
-                                                            int* __restrict__ flag) {
-  __shared__ double colk[2][kDenseReg + E];  // + E: the last group's rows past n
-  __shared__ double rowk[2][kDenseReg];
-  const int t = threadIdx.x;
-  const int G = (n + E - 1) / E;  // groups needed (G n <= 1024: the host picks E >= n / (1024 / n))
-  const bool owner = t < G * n;
-  const int j = owner ? t % n : 0, g = owner ? t / n : 0;
-  const int r0 = g * E;  // first owned row; r0 + E <= n - 1 + E
-  double a[E];
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int i = r0 + m;
-    a[m] = (owner && i < n) ? Gm[(size_t)i * 2 * n + j] : 0.0;
-  }
-  // publish column 0 and row 0 (group 0, slot 0)
-  if (owner && j == 0) {
-#pragma unroll
-    for (int m = 0; m < E; ++m) colk[0][r0 + m] = a[m];
-  }
-  if (owner && g == 0) rowk[0][j] = a[0];
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    const int cb = k & 1, nb = cb ^ 1;
-    double piv = colk[cb][k];
-    if (!(piv > 0.0)) {
-      if (t == 0) atomicOr(flag, SE_DENSE);
-      piv = 1.0;
-    }
-    const double inv = 1.0 / piv;
-    const double rk = (j == k ? 1.0 : rowk[cb][j]) * inv;  // scaled pivot row, column j
-    if (j == k) {  // a_ik is replaced by 0 before the update
-#pragma unroll
-      for (int m = 0; m < E; ++m) a[m] = 0.0;
-    }
-    const double* f = &colk[cb][r0];
-#pragma unroll
-    for (int m = 0; m < E; ++m) a[m] = a[m] - f[m] * rk;
-    if (g == k / E) {  // the pivot row becomes the scaled row
-      const int mk = k - r0;
-#pragma unroll
-      for (int m = 0; m < E; ++m) a[m] = m == mk ? rk : a[m];
-    }
-    if (owner && k + 1 < n) {
-      if (j == k + 1) {
-#pragma unroll
-        for (int m = 0; m < E; ++m) colk[nb][r0 + m] = a[m];
-      }
-      if (g == (k + 1) / E) {
-        const int mk = k + 1 - r0;
-        double v = a[0];
-#pragma unroll
-        for (int m = 1; m < E; ++m) v = m == mk ? a[m] : v;
-        rowk[nb][j] = v;
-      }
-    }
-    __syncthreads();
-  }
-  if (owner) {
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const int i = r0 + m;
-      if (i < n) Ainv[(size_t)i * n + j] = a[m];
-    }
-  }
-}
-
-// The same elimination for n <= 128 by 4 x 4 blocks: thread t owns the block
+// The elimination for n <= 128 by 4 x 4 blocks: thread t owns the block
 // of rows 4 (t / 32) .. +3 and columns 4 (t mod 32) .. +3 of the 128 x 128
 // cover, padded with the identity past n (the padding stays decoupled).
 // Block step K (pivots 4K .. 4K+3) is the block form of the steps above: with
@@ -979,6 +871,105 @@ __global__ void __launch_bounds__(1024) k_dense_inverse_blk(int n, const double*
 #pragma unroll
     for (int c = 0; c < B; ++c)
       if (i0 + r < n && j0 + c < n) Ainv[(size_t)(i0 + r) * n + j0 + c] = a[r][c];
+}
+
+// ---- blocked Gauss-Jordan over several workgroups (coarsest levels of 257
+// to 1024 rows).  The SPD matrix is padded with the identity to N = 32 nb
+// rows and eliminated by 32 x 32 blocks: at block step K the diagonal block
+// D = G[K][K] is inverted by the scalar steps (its 32 pivots are the
+// elimination's pivots 32K .. 32K+31, each checked > 0), then every block is
+// rewritten from the old matrix into the other buffer:
+//   G'[K][K] = D^-1,  G'[K][J] = D^-1 G[K][J],  G'[I][K] = -G[I][K] D^-1,
+//   G'[I][J] = G[I][J] - G[I][K] (D^-1 G[K][J]).
+// Reading only the old matrix, the blocks need no ordering among themselves.
+
+// D^-1 of block K of the N x N row-major G into Dinv (32 x 32): one 1024-thread
+// workgroup, one entry per thread, two barriers per scalar step.
+__global__ void __launch_bounds__(1024) k_ginv_diag(int N, const double* __restrict__ G, int K,
+                                                    double* __restrict__ Dinv,
+                                                    int* __restrict__ flag) {
+  __shared__ double D[32][33];
+  __shared__ double rowk[32], colk[32];
+  const int r = threadIdx.x / 32, c = threadIdx.x % 32;
+  D[r][c] = G[(size_t)(K * 32 + r) * N + K * 32 + c];
+  __syncthreads();
+  for (int k = 0; k < 32; ++k) {
+    double p = D[k][k];
+    if (!(p > 0.0)) {
+      if (threadIdx.x == 0) atomicOr(flag, SE_DENSE);
+      p = 1.0;
+    }
+    if (r == 0) {
+      rowk[c] = (c == k ? 1.0 : D[k][c]) / p;
+      colk[c] = D[c][k];
+    }
+    __syncthreads();
+    if (r == k)
+      D[r][c] = rowk[c];
+    else
+      D[r][c] = c == k ? -colk[r] / p : D[r][c] - colk[r] * rowk[c];
+    __syncthreads();
+  }
+  Dinv[r * 32 + c] = D[r][c];
+}
+
+// One block step over all blocks: workgroup (J, I) writes block (I, J) of Gn.
+__global__ void __launch_bounds__(1024) k_ginv_update(int N, const double* __restrict__ G,
+                                                      const double* __restrict__ Dinv, int K,
+                                                      double* __restrict__ Gn) {
+  __shared__ double Ds[32][33], Rs[32][33], Cs[32][33], Ts[32][33];
+  const int I = blockIdx.y, J = blockIdx.x;
+  const int r = threadIdx.x / 32, c = threadIdx.x % 32;
+  const size_t row = (size_t)I * 32 + r, col = (size_t)J * 32 + c;
+  if (I == K && J == K) {
+    Gn[row * N + col] = Dinv[r * 32 + c];
+    return;
+  }
+  Ds[r][c] = Dinv[r * 32 + c];
+  if (J != K) Rs[r][c] = G[((size_t)K * 32 + r) * N + col];
+  if (I != K) Cs[r][c] = G[row * N + (size_t)K * 32 + c];
+  __syncthreads();
+  if (I == K) {
+    double t = 0.0;
+    for (int k = 0; k < 32; ++k) t = t + Ds[r][k] * Rs[k][c];
+    Gn[row * N + col] = t;
+    return;
+  }
+  if (J == K) {
+    double t = 0.0;
+    for (int k = 0; k < 32; ++k) t = t + Cs[r][k] * Ds[k][c];
+    Gn[row * N + col] = -t;
+    return;
+  }
+  double t = 0.0;
+  for (int k = 0; k < 32; ++k) t = t + Ds[r][k] * Rs[k][c];
+  Ts[r][c] = t;
+  __syncthreads();
+  double u = 0.0;
+  for (int k = 0; k < 32; ++k) u = u + Cs[r][k] * Ts[k][c];
+  Gn[row * N + col] = G[row * N + col] - u;
+}
+
+// G = A padded with the identity to N x N (row-major, zeroed before): one
+// wavefront per row.
+__global__ void k_densify_sq(int n, int N, const int* __restrict__ rp, const int* __restrict__ ci,
+                             const double* __restrict__ v, double* __restrict__ G) {
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
+  if (i >= N) return;
+  if (i >= n) {
+    if (lane == 0) G[(size_t)i * N + i] = 1.0;
+    return;
+  }
+  for (int k = rp[i] + lane; k < rp[i + 1]; k += kWave) G[(size_t)i * N + ci[k]] = v[k];
+}
+
+// Ainv (n x n) = the leading block of the N x N G.
+__global__ void k_lead_block(int n, int N, const double* __restrict__ G,
+                             double* __restrict__ Ainv) {
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= (int64_t)n * n) return;
+  const int i = (int)(p / n), j = (int)(p % n);
+  Ainv[p] = G[(size_t)i * N + j];
 }
 
 // G = [A | I] (n x 2n, row-major, zeroed before): one wavefront per row.
@@ -1534,27 +1525,36 @@ void build_hierarchy(ppe_solver* s) {
     s->nlev = lvl + 1;
     if (n > 0 && n <= kDenseMax) {
       double* Ainv = L.Ainv.get<double>((size_t)n * n);
-      double* G = s->tmp_d[1].get<double>((size_t)2 * n * n);
-      fill_double(s, G, 0.0, (int64_t)2 * n * n);
-      hipLaunchKernelGGL(k_densify, dim3(grid_for((int64_t)n * kWave)), dim3(kBlock), 0,
-                         s->stream, n, L.A.rp(), L.A.ci(), L.A.v(), G);
-      PPE_LAUNCH_CHECK();
-      if (n <= 128) {
+      double* G = nullptr;
+      if (n <= kDenseBlk) {  // [A | I] for the one-workgroup elimination
+        G = s->tmp_d[1].get<double>((size_t)2 * n * n);
+        fill_double(s, G, 0.0, (int64_t)2 * n * n);
+        hipLaunchKernelGGL(k_densify, dim3(grid_for((int64_t)n * kWave)), dim3(kBlock), 0,
+                           s->stream, n, L.A.rp(), L.A.ci(), L.A.v(), G);
+        PPE_LAUNCH_CHECK();
+      }
+      if (n <= kDenseBlk) {
         hipLaunchKernelGGL(k_dense_inverse_blk, dim3(1), dim3(1024), 0, s->stream, n, G, Ainv, err);
-      } else if (n <= 256) {
-        // rows one thread owns; every FMA of the elimination stays in registers
-        const int rows_per = (n + (1024 / n) - 1) / (1024 / n);
-#define PPE_DINV(E_)                                                                           \
-  hipLaunchKernelGGL(k_dense_inverse_reg<E_>, dim3(1), dim3(1024), 0, s->stream, n, G, Ainv, err)
-        if (rows_per <= 4) PPE_DINV(4);
-        else if (rows_per <= 8) PPE_DINV(8);
-        else if (rows_per <= 16) PPE_DINV(16);
-        else if (rows_per <= 24) PPE_DINV(24);
-        else if (rows_per <= 40) PPE_DINV(40);
-        else PPE_DINV(64);
-#undef PPE_DINV
       } else {
-        hipLaunchKernelGGL(k_dense_inverse, dim3(1), dim3(1024), 0, s->stream, n, G, Ainv, err);
+        // 129 .. 1024 rows: blocked over nb x nb workgroups per block step
+        const int nb = (n + 31) / 32, N = 32 * nb;
+        double* G0 = s->tmp_d[1].get<double>((size_t)2 * N * N + 1024);
+        double* G1 = G0 + (size_t)N * N;
+        double* Dinv = G1 + (size_t)N * N;
+        fill_double(s, G0, 0.0, (int64_t)N * N);
+        hipLaunchKernelGGL(k_densify_sq, dim3(grid_for((int64_t)N * kWave)), dim3(kBlock), 0,
+                           s->stream, n, N, L.A.rp(), L.A.ci(), L.A.v(), G0);
+        PPE_LAUNCH_CHECK();
+        for (int K = 0; K < nb; ++K) {
+          hipLaunchKernelGGL(k_ginv_diag, dim3(1), dim3(1024), 0, s->stream, N, G0, K, Dinv, err);
+          PPE_LAUNCH_CHECK();
+          hipLaunchKernelGGL(k_ginv_update, dim3(nb, nb), dim3(1024), 0, s->stream, N, G0, Dinv,
+                             K, G1);
+          PPE_LAUNCH_CHECK();
+          std::swap(G0, G1);
+        }
+        hipLaunchKernelGGL(k_lead_block, dim3(grid_for((int64_t)n * n)), dim3(kBlock), 0,
+                           s->stream, n, N, G0, Ainv);
       }
       PPE_LAUNCH_CHECK();
       L.dense = true;

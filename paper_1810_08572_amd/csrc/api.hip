@@ -96,7 +96,7 @@ void ppe_default_options(ppe_options* o) {
   o->max_iter = 500;
   o->cheb_degree = 2;
   o->cheb_ratio = 30.0;
-  o->coarse_max = 128;
+  o->coarse_max = 512;
   o->max_levels = 10;
   o->theta = 0.08;
   o->check_every = 2;

@@ -73,17 +73,22 @@ def test_setup_is_deterministic():
 def _vcycle_case(name):
     if name.startswith("c1"):
         return case()
+    if name == "cube22":
+        m, f, c, _ = case(shape=(22, 22, 22), fl="front", fl_seed=2, seed=2)
+        return m, f, c, None
     if name == "ragged_front":
         m = box_mesh((23, 19, 17), jitter=0.1, seed=4)
         return m, fl_planar_front(m.cell_centre, seed=7), face_coeff(m, 2400.0), None
     raise ValueError(name)
 
 
-# The coarsest operator is inverted by register-resident Gauss-Jordan for
-# n <= 256 (one template per rows-per-thread bound) and by the global-memory
-# variant above; coarse_max picks which one a hierarchy ends in.
+# The coarsest operator is inverted by one workgroup's 4 x 4-blocked
+# Gauss-Jordan up to 128 rows and by the 32 x 32-blocked form over many
+# workgroups above that (ragged last blocks included); coarse_max picks
+# which one a hierarchy ends in.
 @pytest.mark.parametrize("name,coarse_max,n_coarsest", [
-    ("c1", 16, 2), ("c1", 128, 45), ("c1", 400, 279), ("ragged_front", 128, None)])
+    ("c1", 16, 2), ("c1", 128, 45), ("c1", 400, 279), ("ragged_front", 128, 87),
+    ("ragged_front", 512, 466), ("cube22", 1024, 728)])
 def test_coarsest_inverse_variants(name, coarse_max, n_coarsest):
     import torch
 

@@ -163,7 +163,7 @@ def test_chebyshev_error_polynomial(degree):
 
 def test_vcycle_symmetric_positive():
     _, _, _, sy = _c1_system()
-    H = amg.build_hierarchy(sy.A)
+    H = amg.build_hierarchy(sy.A, coarse_max=128)  # three levels: a recursive V-cycle
     assert len(H.levels) >= 3
     rng = np.random.default_rng(0)
     r1, r2 = rng.normal(size=(2, sy.n_active))
