@@ -79,11 +79,12 @@ typedef struct {
   double rtol;        /* relative residual target, default 1e-10 */
   int max_iter;       /* PCG iteration cap, default 500 */
   int cheb_degree;    /* Chebyshev smoother degree per application, default 2 */
-  double cheb_ratio;  /* smoothing interval [rho/ratio, rho], default 30 */
+  double cheb_ratio;  /* smoothing interval [rho/ratio, rho], default 7 */
   int coarse_max;     /* stop coarsening at <= this many rows, default 512 (the
                          coarsest level, up to 1024 rows, is inverted) */
   int max_levels;     /* hierarchy depth cap, default 10 */
-  double theta;       /* strength threshold, default 0.08 */
+  double theta;       /* strength threshold of the finest level, default 0.08;
+                         level l uses theta * theta_decay^l */
   int check_every;    /* PCG iterations between host convergence checks when not
                          replaying graphs (a graph replay of two iterations is
                          followed by one check), default 2; iterations past
@@ -136,6 +137,10 @@ typedef struct {
                          the solve meets the same tolerance; only its
                          iteration count may differ from a fresh setup's.
                          Default 0: every changed mask gets a full setup. */
+  double theta_decay; /* factor of the strength threshold from one level to the
+                         next coarser one, in (0, 1], default 0.5 (the
+                         level-halved threshold of Vanek, Mandel and Brezina's
+                         smoothed aggregation); 1 keeps theta on every level */
 } ppe_options;
 
 typedef struct {

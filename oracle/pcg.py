@@ -6,8 +6,12 @@ The paper pairs its multigrid with a Krylov method (section 2.5) without
 naming it; the pinned pressure matrix is symmetric positive definite and the
 V-cycle preconditioner is symmetric, so conjugate gradients applies.  The
 stopping rule is ||b - A x||_2 <= rtol ||b||_2; when the recurred residual
-meets it the true residual is recomputed, and the iteration goes on from the
-true residual if that one does not.  ``flexible`` selects the flexible form
+meets it the true residual is recomputed, and if that one does not, the
+iteration restarts from it: r = b - A x, and the next direction is M r alone
+(beta = 0).  Carrying the old direction across the replaced residual loses
+conjugacy, and near the attainable accuracy (a tolerance the rounding of A x
+cannot reach) repeated replacements then drive the iterate away instead of
+leaving it where it stagnates.  ``flexible`` selects the flexible form
 for preconditioners that are only approximately fixed (a lower-precision
 V-cycle): alpha = (r.p) / (p.Ap), the exact line search along p, and
 beta = -(z_new.Ap) / (p.Ap), which makes the new direction A-orthogonal to
@@ -52,6 +56,7 @@ def pcg(A, b, M: Optional[Callable] = None, x0=None, rtol=1e-10, max_iter=500,
     rz = float(r @ z)
     if not rz > 0.0:
         return PcgResult(x, 0, BREAKDOWN, rn / bnorm, hist)
+    restart = False
     for k in range(1, max_iter + 1):
         q = A @ p
         pq = float(p @ q)
@@ -69,11 +74,15 @@ def pcg(A, b, M: Optional[Callable] = None, x0=None, rtol=1e-10, max_iter=500,
                 hist[-1] = rtn / bnorm
                 return PcgResult(x, k, OK, rtn / bnorm, hist)
             r = rt
+            restart = True
         z = M(r)
         rz_new = float(r @ z)
         if not rz_new > 0.0:
             return PcgResult(x, k, BREAKDOWN, hist[-1], hist)
-        beta = -float(z @ q) / pq if flexible else rz_new / rz
+        if restart:
+            beta, restart = 0.0, False
+        else:
+            beta = -float(z @ q) / pq if flexible else rz_new / rz
         p = z + beta * p
         rz = rz_new
     rt = b - A @ x

@@ -52,6 +52,7 @@ class ppe_options(ctypes.Structure):
         ("free", ctypes.c_void_p),
         ("alloc_ctx", ctypes.c_void_p),
         ("coarse_reuse", ctypes.c_int),
+        ("theta_decay", ctypes.c_double),
     ]
 
 
@@ -353,9 +354,10 @@ class Solver:
     """Pressure solver bound to the current device and torch stream."""
 
     def __init__(self, precision="fp64", rtol=1e-10, max_iter=500, cheb_degree=2,
-                 cheb_ratio=30.0, coarse_max=512, max_levels=10, theta=0.08, stream=None,
+                 cheb_ratio=7.0, coarse_max=512, max_levels=10, theta=0.08, stream=None,
                  use_graph=True, check_every=2, autotune=False, reuse_unchanged=False,
-                 krylov="bicgstab", smoother="chebyshev", allocator="torch", coarse_reuse=0):
+                 krylov="bicgstab", smoother="chebyshev", allocator="torch", coarse_reuse=0,
+                 theta_decay=0.5):
         import torch
 
         lib = load_library()
@@ -365,6 +367,7 @@ class Solver:
         o.precision = {"fp64": PPE_FP64, "mixed": PPE_MIXED}[precision]
         o.rtol, o.max_iter, o.cheb_degree, o.cheb_ratio = rtol, max_iter, cheb_degree, cheb_ratio
         o.coarse_max, o.max_levels, o.theta = coarse_max, max_levels, theta
+        o.theta_decay = theta_decay
         o.use_graph, o.check_every = int(bool(use_graph)), int(check_every)
         o.autotune = int(bool(autotune))
         o.reuse_unchanged = int(bool(reuse_unchanged))

@@ -2,7 +2,8 @@
 // of the paper, which coarsens the matrix by heuristics without a physical
 // grid; the paper names no variant, this is smoothed aggregation):
 //
-//   strength   j strong for i  iff  a_ij^2 >= theta^2 (a_ii a_jj), j != i
+//   strength   j strong for i  iff  a_ij^2 >= theta_l^2 (a_ii a_jj), j != i,
+//              theta_l = theta theta_decay^l on level l (finest l = 0)
 //   MIS-2      synchronous rounds over keys (state, fmix32(i ^ salt), -i):
 //              an undecided node that holds the maximum key of its
 //              distance-2 neighbourhood joins, one that sees a member there
@@ -1364,7 +1365,6 @@ const double* level0_bound_async(ppe_solver* s) {
 }
 
 void build_hierarchy(ppe_solver* s) {
-  const double theta2 = s->opt.theta * s->opt.theta;
   const int maxlev = std::max(1, s->opt.max_levels);
   double* rho_dev = s->setup_out.get<double>((size_t)maxlev + 1);
   int* err = reinterpret_cast<int*>(rho_dev + maxlev);
@@ -1420,8 +1420,10 @@ void build_hierarchy(ppe_solver* s) {
       unsigned char* st2 = L.state2.get<unsigned char>(n);
       unsigned long long* m1 = L.m1.get<unsigned long long>(n);
       const int lpr = agg_lanes(L.A);
-      PPE_ROWS(lpr, k_strength, n, n, L.A.rp(), L.A.ci(), L.A.v(), L.diag.as<double>(), theta2,
-               strong, st);
+      // the threshold is halved (theta_decay) on each coarser level
+      const double theta_l = s->opt.theta * std::pow(s->opt.theta_decay, lvl);
+      PPE_ROWS(lpr, k_strength, n, n, L.A.rp(), L.A.ci(), L.A.v(), L.diag.as<double>(),
+               theta_l * theta_l, strong, st);
       const uint32_t salt = level_salt(lvl);
       // rounds run in triples between host checks; a round after the set is
       // complete changes nothing, so only the last count is read.  The roots

@@ -95,7 +95,7 @@ void ppe_default_options(ppe_options* o) {
   o->rtol = 1e-10;
   o->max_iter = 500;
   o->cheb_degree = 2;
-  o->cheb_ratio = 30.0;
+  o->cheb_ratio = 7.0;
   o->coarse_max = 512;
   o->max_levels = 10;
   o->theta = 0.08;
@@ -110,6 +110,7 @@ void ppe_default_options(ppe_options* o) {
   o->free = nullptr;
   o->alloc_ctx = nullptr;
   o->coarse_reuse = 0;
+  o->theta_decay = 0.5;
 }
 
 ppe_status ppe_create(const ppe_options* opt, ppe_solver** out) {
@@ -133,6 +134,7 @@ ppe_status ppe_create(const ppe_options* opt, ppe_solver** out) {
     ppe::require(o.coarse_max >= 1, PPE_ERR_ARG, "coarse_max must be >= 1");
     ppe::require(o.max_levels >= 1 && o.max_levels <= 32, PPE_ERR_ARG, "max_levels in [1, 32]");
     ppe::require(o.theta >= 0 && o.theta < 1, PPE_ERR_ARG, "theta in [0, 1)");
+    ppe::require(o.theta_decay > 0 && o.theta_decay <= 1, PPE_ERR_ARG, "theta_decay in (0, 1]");
     ppe::require(o.coarse_reuse >= 0, PPE_ERR_ARG, "coarse_reuse must be >= 0");
     if (o.check_every < 1) o.check_every = 1;
     auto* s = new ppe_solver();

@@ -36,7 +36,7 @@ def test_host_only_calls():
     lib = ppe.load_library()
     o = ppe.ppe_default_options()
     assert o.rtol == 1e-10 and o.max_iter == 500 and o.cheb_degree == 2
-    assert o.coarse_max == 512 and o.theta == 0.08
+    assert o.coarse_max == 512 and o.theta == 0.08 and o.theta_decay == 0.5 and o.cheb_ratio == 7.0
     assert o.project_krylov == 1 and o.reuse_unchanged == 0
     assert o.smoother == ppe.PPE_SMOOTH_CHEBYSHEV and not o.alloc and not o.free
     # invalid options are refused before any device is touched

@@ -85,10 +85,10 @@ def _vcycle_case(name):
 # The coarsest operator is inverted by one workgroup's 4 x 4-blocked
 # Gauss-Jordan up to 128 rows and by the 32 x 32-blocked form over many
 # workgroups above that (ragged last blocks included); coarse_max picks
-# which one a hierarchy ends in.
+# which one a hierarchy ends in, down to a single aggregate of one row.
 @pytest.mark.parametrize("name,coarse_max,n_coarsest", [
-    ("c1", 16, 2), ("c1", 128, 45), ("c1", 400, 279), ("ragged_front", 128, 87),
-    ("ragged_front", 512, 466), ("cube22", 1024, 728)])
+    ("c1", 8, 1), ("cube22", 16, 2), ("c1", 128, 16), ("ragged_front", 128, 25),
+    ("cube22", 128, 40), ("c1", 400, 279), ("ragged_front", 512, 466), ("cube22", 1024, 728)])
 def test_coarsest_inverse_variants(name, coarse_max, n_coarsest):
     import torch
 

@@ -25,7 +25,7 @@ def _cell_bounds(m):
     return lo, hi
 
 
-def _mms_error(n, mode, front):
+def _mms_system(n, mode, front):
     m = box_mesh((n, n, n), jitter=0.1, seed=5, mode=mode)
     lo, hi = _cell_bounds(m)
     # the front is the node plane i = n/4 (it moves with plane jitter)
@@ -39,6 +39,11 @@ def _mms_error(n, mode, front):
     fl = np.where(act, 1.0, 0.0)
     c = face_coeff(m, 1.0)
     sy = assembly.masked_system(m.n_cells, m.owner, m.neigh, c, fl)
+    return m, act, k, x0, b, sy
+
+
+def _mms_error(n, mode, front):
+    m, act, k, x0, b, sy = _mms_system(n, mode, front)
     if sy.n_active <= 20000:
         p = direct.solve_sparse(sy, b)
     else:
@@ -63,3 +68,20 @@ def test_second_order(mode, front):
     # random plane jitter makes single steps fluctuate; the fit is the pin
     assert np.all(orders >= (1.9 if mode is None else 1.7)), (errs, orders)
     assert fit >= 1.9, (errs, fit)
+
+
+def test_pcg_restarts_after_a_missed_true_residual():
+    """At 48^3 with plane jitter the rounding of A x stops the true residual
+    near 1.5e-13, so a tolerance of 1e-13 is never met: the recurred residual
+    meets it, the true one does not, and PCG restarts from the true residual
+    with beta = 0.  The iterate then stays at the attainable accuracy.  Carrying
+    the old direction across the replacement instead loses conjugacy and
+    drives the residual up by orders of magnitude within 60 iterations
+    (6e-11 there, 6e-9 at 100)."""
+    m, act, k, x0, b, sy = _mms_system(48, "plane", False)
+    bp = assembly.pinned_rhs(sy, b)
+    H = amg.build_hierarchy(sy.A)
+    res = pcg.pcg(sy.A, bp, M=lambda r: amg.vcycle(H, r), rtol=1e-13, max_iter=60)
+    assert res.status == pcg.NOT_CONVERGED
+    rr = np.linalg.norm(bp - sy.A @ res.x) / np.linalg.norm(bp)
+    assert rr <= 1e-12, rr
