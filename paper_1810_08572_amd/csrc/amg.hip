@@ -1231,6 +1231,13 @@ void spectral_bound(ppe_solver* s, Level& L, int lvl, double* rho_dev) {
   }
   L.x.get<double>(n);
   L.r.get<double>(n);
+  // setup work: its power steps stay out of the solve's kernel profile
+  struct NoProfile {
+    ppe_solver* s;
+    bool saved;
+    ~NoProfile() { s->prof = saved; }
+  } guard{s, s->prof};
+  s->prof = false;
   power_estimate(s, L, level_salt(lvl), kPowerIters, kPowerSafety, rho_dev);
 }
 
