@@ -161,6 +161,172 @@ __global__ void __launch_bounds__(kBlock) k_mis_max2(int n, const int* __restric
   if (threadIdx.x == 0 && und) *undecided = 1;
 }
 
+// ------------------------------------------------------------------ finest level, ELL
+// The same strength, MIS-2 and joining rules on the finest level's
+// slot-major ELL copy of the off-diagonal part (slot k of row i at
+// k n + i, padding = the row itself): one thread per row, every slot's load
+// issued before its gathers, no row pointers.  The strength pass leaves
+// scol = the column of each strong entry and the row itself elsewhere, so
+// the later passes read one array.  Results are maxima and per-entry tests,
+// as in the CSR kernels, so they are the same bit for bit.
+template <int WM>
+__device__ __forceinline__ void slot_cols(int i, int n, int W, const int* __restrict__ col,
+                                          int (&c)[WM]) {
+#pragma unroll
+  for (int k = 0; k < WM; ++k) c[k] = k < W ? col[(size_t)k * n + i] : i;
+}
+
+// WM: unrolled slot count covering W (0: a plain loop over W slots).
+template <int WM>
+__global__ void __launch_bounds__(kBlock) k_strength_ell(int n, int W, const int* __restrict__ ecol,
+                                                         const double* __restrict__ ev,
+                                                         const double* __restrict__ diag,
+                                                         double theta2, int* __restrict__ scol,
+                                                         unsigned char* __restrict__ state) {
+  const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double di = diag[i];
+  int deg = 0;
+  auto test = [&](int k, int j) {
+    const double a = ev[(size_t)k * n + i];
+    const bool st = (j != i) && (a != 0.0) && (a * a >= theta2 * (di * diag[j]));
+    scol[(size_t)k * n + i] = st ? j : i;
+    deg += st ? 1 : 0;
+  };
+  if constexpr (WM > 0) {
+    int c[WM];
+    slot_cols<WM>(i, n, W, ecol, c);
+#pragma unroll
+    for (int k = 0; k < WM; ++k)
+      if (k < W) test(k, c[k]);
+  } else {
+    for (int k = 0; k < W; ++k) test(k, ecol[(size_t)k * n + i]);
+  }
+  state[i] = deg > 0 ? S_UND : S_OUT;
+}
+
+template <int WM>
+__global__ void __launch_bounds__(kBlock) k_mis_max1_ell(int n, int W, const int* __restrict__ scol,
+                                                         const unsigned char* __restrict__ state,
+                                                         uint32_t salt,
+                                                         unsigned long long* __restrict__ m1) {
+  const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  unsigned long long m = mis_key(state[i], i, salt);
+  auto take = [&](int j) {
+    if (j == i) return;
+    const unsigned long long kj = mis_key(state[j], j, salt);
+    m = kj > m ? kj : m;
+  };
+  if constexpr (WM > 0) {
+    int c[WM];
+    slot_cols<WM>(i, n, W, scol, c);
+#pragma unroll
+    for (int k = 0; k < WM; ++k) take(c[k]);
+  } else {
+    for (int k = 0; k < W; ++k) take(scol[(size_t)k * n + i]);
+  }
+  m1[i] = m;
+}
+
+template <int WM>
+__global__ void __launch_bounds__(kBlock) k_mis_max2_ell(int n, int W, const int* __restrict__ scol,
+                                                         const unsigned char* __restrict__ state,
+                                                         uint32_t salt,
+                                                         const unsigned long long* __restrict__ m1,
+                                                         unsigned char* __restrict__ next,
+                                                         int* __restrict__ undecided) {
+  const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const unsigned char st = i < n ? state[i] : (unsigned char)S_OUT;
+  int und = 0;
+  if (i < n) {
+    unsigned char ns = st;
+    if (st == S_UND) {
+      unsigned long long m = m1[i];
+      auto take = [&](int j) {
+        if (j == i) return;
+        const unsigned long long mj = m1[j];
+        m = mj > m ? mj : m;
+      };
+      if constexpr (WM > 0) {
+        int c[WM];
+        slot_cols<WM>(i, n, W, scol, c);
+#pragma unroll
+        for (int k = 0; k < WM; ++k) take(c[k]);
+      } else {
+        for (int k = 0; k < W; ++k) take(scol[(size_t)k * n + i]);
+      }
+      if (m == mis_key(st, i, salt))
+        ns = S_IN;
+      else if ((m >> 62) == S_IN)
+        ns = S_OUT;
+    }
+    next[i] = ns;
+    und = ns == S_UND ? 1 : 0;
+  }
+  und = block_sum<kBlock>(und);
+  if (threadIdx.x == 0 && und) *undecided = 1;
+}
+
+template <int WM>
+__global__ void __launch_bounds__(kBlock) k_agg_first_ell(int n, int W, const int* __restrict__ scol,
+                                                          const unsigned char* __restrict__ state,
+                                                          const int* __restrict__ root_id,
+                                                          int* __restrict__ agg1) {
+  const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  if (state[i] == S_IN) {
+    agg1[i] = root_id[i];
+    return;
+  }
+  int a = -1;
+  auto take = [&](int j) {
+    if (j != i && state[j] == S_IN) a = max(a, root_id[j]);
+  };
+  if constexpr (WM > 0) {
+    int c[WM];
+    slot_cols<WM>(i, n, W, scol, c);
+#pragma unroll
+    for (int k = 0; k < WM; ++k) take(c[k]);
+  } else {
+    for (int k = 0; k < W; ++k) take(scol[(size_t)k * n + i]);
+  }
+  agg1[i] = a;
+}
+
+template <int WM>
+__global__ void __launch_bounds__(kBlock) k_agg_second_ell(int n, int W, const int* __restrict__ scol,
+                                                           const double* __restrict__ ev,
+                                                           const int* __restrict__ agg1,
+                                                           int* __restrict__ agg,
+                                                           int* __restrict__ flag) {
+  const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int a = agg1[i];
+  if (a < 0) {
+    double best = -1.0;
+    int bestj = INT32_MAX, any = 0;
+    auto take = [&](int k, int j) {
+      if (j == i) return;
+      any = 1;
+      if (agg1[j] < 0) return;
+      const double w = fabs(ev[(size_t)k * n + i]);
+      if (w > best || (w == best && j < bestj)) { best = w; bestj = j; }
+    };
+    if constexpr (WM > 0) {
+      int c[WM];
+      slot_cols<WM>(i, n, W, scol, c);
+#pragma unroll
+      for (int k = 0; k < WM; ++k) take(k, c[k]);
+    } else {
+      for (int k = 0; k < W; ++k) take(k, scol[(size_t)k * n + i]);
+    }
+    if (best >= 0.0) a = agg1[bestj];
+    else if (any) atomicOr(flag, SE_AGG);
+  }
+  agg[i] = a;
+}
+
 // ------------------------------------------------------------------ aggregation
 __global__ void k_is_root(int n, const unsigned char* __restrict__ state, int* __restrict__ root) {
   int i = blockIdx.x * kBlock + threadIdx.x;
@@ -1422,15 +1588,38 @@ void build_hierarchy(ppe_solver* s) {
     }
     if (!last) {
       const int g = grid_for(n);
-      unsigned char* strong = L.strong.get<unsigned char>(L.A.nnz);
+      // the finest level runs these passes on its ELL copy (one thread per
+      // row); coarse levels on CSR with lpr lanes per row
+      const bool ell = lvl == 0 && L.W > 0;
+      const int W = L.W;
+      const int* ecol = L.ell_col.as<int>();
+      const double* ev = L.ell_val.as<double>();
+      unsigned char* strong = ell ? nullptr : L.strong.get<unsigned char>(L.A.nnz);
+      int* scol = ell ? L.scol.get<int>((size_t)W * n) : nullptr;
       unsigned char* st = L.state.get<unsigned char>(n);
       unsigned char* st2 = L.state2.get<unsigned char>(n);
       unsigned long long* m1 = L.m1.get<unsigned long long>(n);
       const int lpr = agg_lanes(L.A);
+#define PPE_SLOTS(LAUNCH)                      \
+  do {                                         \
+    if (W <= 4) { LAUNCH(4); }                 \
+    else if (W <= 6) { LAUNCH(6); }            \
+    else if (W <= 8) { LAUNCH(8); }            \
+    else { LAUNCH(0); }                        \
+    PPE_LAUNCH_CHECK();                        \
+  } while (0)
+#define PPE_ELL_K(K, ...) \
+  hipLaunchKernelGGL(K, dim3(g), dim3(kBlock), 0, s->stream, __VA_ARGS__)
       // the threshold is halved (theta_decay) on each coarser level
       const double theta_l = s->opt.theta * std::pow(s->opt.theta_decay, lvl);
-      PPE_ROWS(lpr, k_strength, n, n, L.A.rp(), L.A.ci(), L.A.v(), L.diag.as<double>(),
-               theta_l * theta_l, strong, st);
+      if (ell) {
+#define PPE_L(WM) PPE_ELL_K(k_strength_ell<WM>, n, W, ecol, ev, L.diag.as<double>(), theta_l * theta_l, scol, st)
+        PPE_SLOTS(PPE_L);
+#undef PPE_L
+      } else {
+        PPE_ROWS(lpr, k_strength, n, n, L.A.rp(), L.A.ci(), L.A.v(), L.diag.as<double>(),
+                 theta_l * theta_l, strong, st);
+      }
       const uint32_t salt = level_salt(lvl);
       // rounds run in triples between host checks; a round after the set is
       // complete changes nothing, so only the last count is read.  The roots
@@ -1444,8 +1633,17 @@ void build_hierarchy(ppe_solver* s) {
       for (int batch = std::max(3, L.mis_batch);; batch = 3) {
         for (int k = 0; k < batch; ++k) {
           if (k == batch - 1) fill_int(s, und, 0, 1);
-          PPE_ROWS(lpr, k_mis_max1, n, n, L.A.rp(), L.A.ci(), strong, st, salt, m1);
-          PPE_ROWS(lpr, k_mis_max2, n, n, L.A.rp(), L.A.ci(), strong, st, salt, m1, st2, und);
+          if (ell) {
+#define PPE_L(WM) PPE_ELL_K(k_mis_max1_ell<WM>, n, W, scol, st, salt, m1)
+            PPE_SLOTS(PPE_L);
+#undef PPE_L
+#define PPE_L(WM) PPE_ELL_K(k_mis_max2_ell<WM>, n, W, scol, st, salt, m1, st2, und)
+            PPE_SLOTS(PPE_L);
+#undef PPE_L
+          } else {
+            PPE_ROWS(lpr, k_mis_max1, n, n, L.A.rp(), L.A.ci(), strong, st, salt, m1);
+            PPE_ROWS(lpr, k_mis_max2, n, n, L.A.rp(), L.A.ci(), strong, st, salt, m1, st2, und);
+          }
           std::swap(st, st2);
           ++L.mis_rounds;
         }
@@ -1463,9 +1661,20 @@ void build_hierarchy(ppe_solver* s) {
       if (na > 0) {
         int* agg1 = L.agg1.get<int>(n);
         int* agg = L.agg.get<int>(n);
-        PPE_ROWS(lpr, k_agg_first, n, n, L.A.rp(), L.A.ci(), strong, st, root_id, agg1);
-        PPE_ROWS(lpr, k_agg_second, n, n, L.A.rp(), L.A.ci(), L.A.v(), strong, agg1, agg,
-                 err);  // sets SE_AGG
+        if (ell) {
+#define PPE_L(WM) PPE_ELL_K(k_agg_first_ell<WM>, n, W, scol, st, root_id, agg1)
+          PPE_SLOTS(PPE_L);
+#undef PPE_L
+#define PPE_L(WM) PPE_ELL_K(k_agg_second_ell<WM>, n, W, scol, ev, agg1, agg, err)
+          PPE_SLOTS(PPE_L);  // sets SE_AGG
+#undef PPE_L
+        } else {
+          PPE_ROWS(lpr, k_agg_first, n, n, L.A.rp(), L.A.ci(), strong, st, root_id, agg1);
+          PPE_ROWS(lpr, k_agg_second, n, n, L.A.rp(), L.A.ci(), L.A.v(), strong, agg1, agg,
+                   err);  // sets SE_AGG
+        }
+#undef PPE_ELL_K
+#undef PPE_SLOTS
         L.n_agg = na;
         // aggregate members, coarse near-null vector, tentative prolongator
         // (nodes with no strong connection stay outside every aggregate, so

@@ -173,6 +173,7 @@ struct Level {
                          // the prolongation fused with post-smoothing
   bool ap_ok = false;    // AP equals A*P for the level's current A
   DevBuf strong, state, state2, m1, mis_root, agg1, agg_ptr, agg_mem, pt;
+  DevBuf scol;           // finest level: ELL strong columns (the row itself elsewhere)
   // coarsest level
   bool dense = false;
   DevBuf Ainv;           // dense inverse, FP64 in both precisions
