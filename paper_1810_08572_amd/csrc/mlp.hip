@@ -26,6 +26,8 @@ struct ppe_mlp {
   ppe::DevBuf params, grad, m, v, bf16;  // bf16: hidden weight matrices in BF16
   ppe::DevBuf act, pre, gbuf, gbuf2, part, lossbuf;
   int64_t adam_t = 0;
+  size_t lds_max = 0;  // LDS one workgroup may use (0: not queried yet)
+  int cus = 0;         // compute units of the device
   std::string err;
 };
 
@@ -249,6 +251,151 @@ __global__ void __launch_bounds__(64 * kWaves) k_mlp_infer_bf16(
     s = s + __shfl_down(s, 32, 64);
     if (half == 0 && c < n) y[c] = s + last[kW];
     __syncthreads();
+  }
+}
+
+// The inference pass used at every timestep.  With out^T = W h^T (features x
+// cells), a lane's accumulators r = 4q .. 4q+3 hold four consecutive
+// features of one cell: the k-quad the next layer's B operand reads.  So
+// activations and weights sit in LDS as quads of BF16 (8 bytes):
+// activation (k, cell) in quad (k/4) 32 + cell of the wave's buffer, weight
+// (f, k) in quad (k/4) 128 + f, and every MFMA operand is one 8-byte LDS
+// read per lane, consecutive across lanes.  The hidden weights are staged
+// once per workgroup; a layer's outputs are computed in registers for all
+// 128 features before they overwrite its inputs (a wave's LDS accesses
+// complete in issue order), so each wave needs one buffer.
+//
+// Roundings are those of the pass above: the first layer is formed to FP32
+// accuracy on the matrix cores from three-way BF16 splits of x and W1
+// (x = x0 + x1 + x2, 8 bits each; the six products x_i w_j with i + j <= 2,
+// exact in the FP32 accumulator; the dropped ones are below 2^-24 of the
+// sum), every hidden activation and the width x width weights are BF16,
+// the output layer is an FP32 dot product with the last BF16 activations.
+// SiLU uses the hardware exp2 and reciprocal (about 1 ulp of FP32 each,
+// far below the BF16 rounding that follows).
+constexpr int kWavesM = 8;  // waves per workgroup
+
+__device__ __forceinline__ float silu_hw(float z) {
+  const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * z);
+  return z * __builtin_amdgcn_rcpf(1.0f + e);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ uint64_t pack4(uint16_t a, uint16_t b, uint16_t c, uint16_t d) {
+  return (uint64_t)a | ((uint64_t)b << 16) | ((uint64_t)c << 32) | ((uint64_t)d << 48);
+}
+
+__global__ void __launch_bounds__(64 * kWavesM) k_mlp_infer_mfma(
+    int n, int n_mid, const float* __restrict__ x, const float* __restrict__ params,
+    const uint16_t* __restrict__ wbf, float* __restrict__ y) {
+  extern __shared__ uint64_t lds_q[];
+  constexpr int kQ = kW * kW / 4;  // quads of one width x width matrix
+  uint64_t* wq = lds_q;                                   // n_mid matrices
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  const int cell = lane % 32, half = lane / 32;
+  uint64_t* act = lds_q + (size_t)n_mid * kQ + (size_t)wv * (kW * 32 / 4);
+  // stage the hidden weights: W_l[f][4kq .. 4kq+3] is 8 contiguous bytes
+  for (int q = threadIdx.x; q < n_mid * kQ; q += blockDim.x) {
+    const int l = q / kQ, rem = q % kQ, kq = rem / kW, f = rem % kW;
+    wq[q] = *reinterpret_cast<const uint64_t*>(wbf + (size_t)l * kW * kW + (size_t)f * kW + 4 * kq);
+  }
+  const float* W1 = params;
+  const float* b1 = W1 + kW * kIn;
+  const int64_t hid = (int64_t)kW * kW + kW;
+  const float* last = b1 + kW + (int64_t)n_mid * hid;  // W_out [kW], then b_out
+  // first-layer A operands in registers, three BF16 parts each:
+  // A[f][k] = W1[mt 32 + cell][8 kt + 4 half + v], zero for k >= n_in
+  short4_t a1[3][4][2];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = kt * 8 + 4 * half + v;
+        float w = k < kIn ? W1[(mt * 32 + cell) * kIn + k] : 0.0f;
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+          const uint16_t h = f2bf(w);
+          a1[p][mt][kt][v] = (short)h;
+          w = w - bf2f(h);
+        }
+      }
+  __syncthreads();
+  const int ntile = (n + 31) / 32;
+  for (int tile = blockIdx.x * kWavesM + wv; tile < ntile; tile += gridDim.x * kWavesM) {
+    const int c = tile * 32 + cell;
+    // layer 1: B[k][cell] = x[c][k] for k = 8 kt + 4 half + v
+    short4_t b1p[3][2];
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = kt * 8 + 4 * half + v;
+        float xv = (c < n && k < kIn) ? x[(size_t)c * kIn + k] : 0.0f;
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+          const uint16_t h = f2bf(xv);
+          b1p[p][kt][v] = (short)h;
+          xv = xv - bf2f(h);
+        }
+      }
+    float16_t acc[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      acc[mt] = float16_t{0};
+#pragma unroll
+      for (int kt = 0; kt < 2; ++kt) {  // smallest products first
+        acc[mt] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[0][mt][kt], b1p[2][kt], acc[mt], 0, 0, 0);
+        acc[mt] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[1][mt][kt], b1p[1][kt], acc[mt], 0, 0, 0);
+        acc[mt] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[2][mt][kt], b1p[0][kt], acc[mt], 0, 0, 0);
+        acc[mt] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[0][mt][kt], b1p[1][kt], acc[mt], 0, 0, 0);
+        acc[mt] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[1][mt][kt], b1p[0][kt], acc[mt], 0, 0, 0);
+        acc[mt] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[0][mt][kt], b1p[0][kt], acc[mt], 0, 0, 0);
+      }
+    }
+    const float* bias = b1;
+    for (int l = 0;; ++l) {
+      // SiLU of the accumulators (bias added), rounded to BF16
+      if (l == n_mid) {  // the last hidden layer feeds the output layer
+        float s = 0.0f;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int f = mt * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+            s = s + last[f] * bf2f(f2bf(silu_hw(acc[mt][r] + bias[f])));
+          }
+        s = s + __shfl_down(s, 32, 64);
+        if (half == 0 && c < n) y[c] = s + last[kW];
+        break;
+      }
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int f0 = mt * 32 + 8 * q + 4 * half;
+          uint16_t h[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) h[j] = f2bf(silu_hw(acc[mt][4 * q + j] + bias[f0 + j]));
+          act[(f0 / 4) * 32 + cell] = pack4(h[0], h[1], h[2], h[3]);
+        }
+      // hidden layer l: out^T = W_l h^T, all four output tiles in registers
+      const uint64_t* W = wq + (size_t)l * kQ;
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) acc[mt] = float16_t{0};
+#pragma unroll 4
+      for (int kt = 0; kt < kW / 8; ++kt) {
+        const short4_t b = __builtin_bit_cast(short4_t, act[(2 * kt + half) * 32 + cell]);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+          const short4_t a = __builtin_bit_cast(short4_t, W[(2 * kt + half) * kW + mt * 32 + cell]);
+          acc[mt] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[mt], 0, 0, 0);
+        }
+      }
+      bias = b1 + kW + (int64_t)l * hid + kW * kW;
+    }
   }
 }
 
@@ -615,10 +762,30 @@ ppe_status ppe_mlp_forward(ppe_mlp* m, int32_t n, const float* x, float* y, int 
       require(m->n_in == kIn && m->width == kW && m->n_hidden >= 2, PPE_ERR_ARG,
               "the BF16 MFMA path needs 10 inputs, width 128 and >= 2 hidden layers");
       const int tiles = (n + 31) / 32;
-      int g = (tiles + kWaves - 1) / kWaves;
-      if (g > 2048) g = 2048;
-      hipLaunchKernelGGL(k_mlp_infer_bf16, dim3(g), dim3(64 * kWaves), 0, m->stream, n,
-                         m->n_hidden, x, m->params.as<float>(), m->bf16.as<uint16_t>(), y);
+      const int n_mid = m->n_hidden - 1;
+      const size_t lds = ((size_t)n_mid * kW * kW / 4 + (size_t)kWavesM * kW * 32 / 4) * 8;
+      if (m->lds_max == 0) {
+        int dev = 0, v = 0;
+        PPE_HIP(hipGetDevice(&dev));
+        PPE_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        int cus = 0;
+        PPE_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        m->lds_max = (size_t)v;
+        m->cus = cus;
+      }
+      if (lds <= m->lds_max) {
+        // one workgroup per compute unit holds the staged weights; waves
+        // stride over the 32-cell tiles
+        int g = (tiles + kWavesM - 1) / kWavesM;
+        if (g > m->cus) g = m->cus;
+        hipLaunchKernelGGL(k_mlp_infer_mfma, dim3(g), dim3(64 * kWavesM), lds, m->stream, n,
+                           n_mid, x, m->params.as<float>(), m->bf16.as<uint16_t>(), y);
+      } else {  // deeper networks than the staged weights fit
+        int g = (tiles + kWaves - 1) / kWaves;
+        if (g > 2048) g = 2048;
+        hipLaunchKernelGGL(k_mlp_infer_bf16, dim3(g), dim3(64 * kWaves), 0, m->stream, n,
+                           m->n_hidden, x, m->params.as<float>(), m->bf16.as<uint16_t>(), y);
+      }
       PPE_LAUNCH_CHECK();
     } else {
       float* yy = forward_fp32(m, n, x);
