@@ -282,8 +282,12 @@ __device__ __forceinline__ float silu_hw(float z) {
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-__device__ __forceinline__ uint64_t pack4(uint16_t a, uint16_t b, uint16_t c, uint16_t d) {
-  return (uint64_t)a | ((uint64_t)b << 16) | ((uint64_t)c << 32) | ((uint64_t)d << 48);
+// Two FP32 values rounded to BF16 (nearest, ties to even) in one gfx950
+// conversion (v_cvt_pk_bf16_f32), the first in the low half.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float float2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf16_pair(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(float2_t{a, b}, bf16x2_t));
 }
 
 __global__ void __launch_bounds__(64 * kWavesM) k_mlp_infer_mfma(
@@ -363,9 +367,12 @@ __global__ void __launch_bounds__(64 * kWavesM) k_mlp_infer_mfma(
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
+          for (int r = 0; r < 16; r += 2) {
             const int f = mt * 32 + 8 * (r / 4) + 4 * half + (r % 4);
-            s = s + last[f] * bf2f(f2bf(silu_hw(acc[mt][r] + bias[f])));
+            const uint32_t h = bf16_pair(silu_hw(acc[mt][r] + bias[f]),
+                                         silu_hw(acc[mt][r + 1] + bias[f + 1]));
+            s = s + last[f] * __uint_as_float(h << 16);
+            s = s + last[f + 1] * __uint_as_float(h & 0xFFFF0000u);
           }
         s = s + __shfl_down(s, 32, 64);
         if (half == 0 && c < n) y[c] = s + last[kW];
@@ -376,10 +383,11 @@ __global__ void __launch_bounds__(64 * kWavesM) k_mlp_infer_mfma(
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int f0 = mt * 32 + 8 * q + 4 * half;
-          uint16_t h[4];
+          float h[4];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) h[j] = f2bf(silu_hw(acc[mt][4 * q + j] + bias[f0 + j]));
-          act[(f0 / 4) * 32 + cell] = pack4(h[0], h[1], h[2], h[3]);
+          for (int j = 0; j < 4; ++j) h[j] = silu_hw(acc[mt][4 * q + j] + bias[f0 + j]);
+          act[(f0 / 4) * 32 + cell] =
+              (uint64_t)bf16_pair(h[0], h[1]) | ((uint64_t)bf16_pair(h[2], h[3]) << 32);
         }
       // hidden layer l: out^T = W_l h^T, all four output tiles in registers
       const uint64_t* W = wq + (size_t)l * kQ;
