@@ -969,9 +969,10 @@ int apply_op(ppe_solver* s, const Level& L, const double* x, const double* b, do
   }
   // the setup's power steps keep the one-entry rule: the spectral bounds,
   // and with them the hierarchy, stay what they were
-  const int lpr = L.lpr_a > 0     ? L.lpr_a
-                  : EPI == E_POWER ? lanes_for(L.A)
-                                   : smooth_lanes(L.A);
+  // the power steps (a reduction, so at most kRedBlocks workgroups) take the
+  // smoother's lanes too: with one lane per entry each lane group walked
+  // seven rows of level 1 in turn
+  const int lpr = L.lpr_a > 0 ? L.lpr_a : smooth_lanes(L.A);
   const int g = reduce ? red_grid((int64_t)n * lpr) : grid_for((int64_t)n * lpr);
 #define PPE_CSR(LL)                                                                            \
   launch(s,                                                                                    \
