@@ -408,19 +408,34 @@ __global__ void k_agg_fill(int n, const int* __restrict__ agg, int* __restrict__
 }
 
 // Sort each aggregate's members, then norm_J = sqrt(sum B_i^2) in ascending
-// i.  One wavefront per aggregate: up to 64 members are ranked in registers
-// and their squares summed in rank order by one lane; a larger aggregate is
-// sorted and summed by one lane.
+// i.  One wavefront per aggregate.  Up to 64 members are ranked in
+// registers; up to kAggLds by the whole wave (the members staged in LDS,
+// each lane counts for its own members the smaller keys among all of them,
+// then writes them back in rank order); a larger aggregate is sorted by
+// one lane in place.  The squares are summed
+// in rank order by one lane.
+constexpr int kAggLds = 1024;
 __global__ void __launch_bounds__(kBlock) k_agg_norm(int na, const int* __restrict__ ptr,
                                                      int* __restrict__ mem,
                                                      const double* __restrict__ B,
                                                      double* __restrict__ Bc) {
   __shared__ double sq[kBlock];
+  __shared__ int skey[kBlock / kWave][kAggLds];
   const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int J = blockIdx.x * (kBlock / kWave) + w;
-  const int b = J < na ? ptr[J] : 0, e = J < na ? ptr[J + 1] : 0, m = e - b;
+  if (J >= na) return;  // whole wavefronts: only wave-level ordering below
+  const int b = ptr[J], e = ptr[J + 1], m = e - b;
   double* wsq = sq + w * kWave;
-  if (J < na && m <= kWave) {
+  int* wk = skey[w];
+  // a wavefront's LDS operations complete in issue order; the fences keep
+  // the compiler from moving them across
+  auto wave_sync = []() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  double s = 0.0;
+  if (m <= kWave) {
     const int key = lane < m ? mem[b + lane] : INT32_MAX;
     int rank = 0;
     for (int q = 0; q < m; ++q) rank += __shfl(key, q, kWave) < key ? 1 : 0;
@@ -428,23 +443,52 @@ __global__ void __launch_bounds__(kBlock) k_agg_norm(int na, const int* __restri
       mem[b + rank] = key;
       wsq[rank] = B[key] * B[key];
     }
+    wave_sync();
+    if (lane == 0)
+      for (int q = 0; q < m; ++q) s = s + wsq[q];
+  } else if (m <= kAggLds) {
+    constexpr int T = kAggLds / kWave;  // members per lane
+    int myk[T], myr[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int i = lane + t * kWave;
+      myk[t] = i < m ? mem[b + i] : INT32_MAX;
+      if (i < m) wk[i] = myk[t];
+    }
+    wave_sync();
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      int r = 0;
+      if (lane + t * kWave < m)
+        for (int q = 0; q < m; ++q) r += wk[q] < myk[t] ? 1 : 0;
+      myr[t] = r;
+    }
+    wave_sync();  // every lane has read wk before it is overwritten in rank order
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+      if (lane + t * kWave < m) wk[myr[t]] = myk[t];
+    wave_sync();
+    for (int c = 0; c < m; c += kWave) {
+      const int q = c + lane;
+      if (q < m) {
+        const int key = wk[q];
+        mem[b + q] = key;
+        wsq[lane] = B[key] * B[key];
+      }
+      wave_sync();
+      if (lane == 0)
+        for (int t = 0; t < kWave && c + t < m; ++t) s = s + wsq[t];
+      wave_sync();  // wsq is rewritten for the next chunk
+    }
+  } else if (lane == 0) {
+    for (int i = b + 1; i < e; ++i) {
+      int key = mem[i], j = i - 1;
+      while (j >= b && mem[j] > key) { mem[j + 1] = mem[j]; --j; }
+      mem[j + 1] = key;
+    }
+    for (int i = b; i < e; ++i) s = s + B[mem[i]] * B[mem[i]];
   }
-  __syncthreads();
-  if (J >= na || lane != 0) return;
-  if (m <= kWave) {
-    double s = 0.0;
-    for (int q = 0; q < m; ++q) s = s + wsq[q];
-    Bc[J] = sqrt(s);
-    return;
-  }
-  for (int i = b + 1; i < e; ++i) {
-    int key = mem[i], j = i - 1;
-    while (j >= b && mem[j] > key) { mem[j + 1] = mem[j]; --j; }
-    mem[j + 1] = key;
-  }
-  double s = 0.0;
-  for (int i = b; i < e; ++i) s = s + B[mem[i]] * B[mem[i]];
-  Bc[J] = sqrt(s);
+  if (lane == 0) Bc[J] = sqrt(s);
 }
 
 __global__ void k_tent(int n, const int* __restrict__ agg, const double* __restrict__ B,

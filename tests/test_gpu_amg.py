@@ -16,6 +16,10 @@ def _cases():
     m = box_mesh((23, 19, 17), jitter=0.1, seed=4)
     f = fl_planar_front(m.cell_centre, seed=7)
     yield "ragged_front", (m, f, face_coeff(m, 2400.0), None)
+    # a tall all-liquid box: level 2 holds an aggregate of more than 64
+    # members, which the bookkeeping ranks with the whole wavefront
+    m = box_mesh((32, 32, 96), jitter=0.1, seed=0)
+    yield "tall", (m, np.ones(m.n_cells), face_coeff(m, 2400.0), None)
 
 
 @pytest.mark.parametrize("name,cs", list(_cases()), ids=lambda x: x if isinstance(x, str) else "")
@@ -23,6 +27,8 @@ def test_hierarchy_matches_oracle(name, cs):
     m, f, c, _ = cs
     sy = assembly.masked_system(m.n_cells, m.owner, m.neigh, c, f)
     H = amg.build_hierarchy(sy.A)
+    if name == "tall":
+        assert max(np.bincount(lev.agg[lev.agg >= 0]).max() for lev in H.levels[:-1]) > 64
     s = gpu_solver(m, f, c)
     assert s.n_levels() == len(H.levels)
     for lvl, lev in enumerate(H.levels):
