@@ -327,6 +327,63 @@ __global__ void __launch_bounds__(kBlock) k_agg_second_ell(int n, int W, const i
   agg[i] = a;
 }
 
+// Finest level: Q = A P_tent from the ELL copy, one thread per row.  P_tent
+// has one entry per aggregated node (pt_j in column agg_j), so row i of Q
+// holds, for every aggregate J reached from row i, the sum of a_ij pt_j
+// over that row's entries j in J.  The row's entries are taken in CSR order
+// (ascending column, the diagonal in its place) and each sum starts from 0
+// in that order: bitwise the general product's one-sub-group result.  COUNT:
+// distinct aggregates per row into counts; else the row, sorted by
+// aggregate, at rp[i].
+template <int WM, bool COUNT>
+__global__ void __launch_bounds__(kBlock) k_coarsen_cols_ell(
+    int n, int W, const int* __restrict__ ecol, const double* __restrict__ ev,
+    const double* __restrict__ diag, const int* __restrict__ agg, const double* __restrict__ pt,
+    int* __restrict__ counts, const int* __restrict__ rp, int* __restrict__ ci,
+    double* __restrict__ v) {
+  const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  // fixed register slots: ELL slot k (aggregate Jk[k], -1 for none), and the
+  // diagonal, which comes before slot dpos in CSR order
+  int c[WM];
+  slot_cols<WM>(i, n, W, ecol, c);
+  int Jk[WM];
+  double yk[WM];
+  int dpos = WM;
+#pragma unroll
+  for (int k = WM - 1; k >= 0; --k) {
+    const int j = c[k];
+    const bool real = j != i;  // padding (slots past W included) holds the row
+    if (real && j > i) dpos = k;
+    Jk[k] = real ? agg[j] : -1;
+    if (!COUNT) yk[k] = Jk[k] >= 0 ? ev[(size_t)k * n + i] * pt[j] : 0.0;
+  }
+  const int Jd = agg[i];
+  const double yd = (!COUNT && Jd >= 0) ? diag[i] * pt[i] : 0.0;
+  int out = COUNT ? 0 : rp[i];
+  int last = -1;
+  for (int step = 0; step <= WM; ++step) {
+    int cur = Jd > last ? Jd : INT32_MAX;
+#pragma unroll
+    for (int k = 0; k < WM; ++k)
+      if (Jk[k] > last && Jk[k] < cur) cur = Jk[k];
+    if (cur == INT32_MAX) break;
+    if (!COUNT) {
+      double sum = 0.0;
+#pragma unroll
+      for (int k = 0; k <= WM; ++k) {
+        if (k == dpos && Jd == cur) sum = sum + yd;
+        if (k < WM && Jk[k] == cur) sum = sum + yk[k];
+      }
+      ci[out] = cur;
+      v[out] = sum;
+    }
+    ++out;
+    last = cur;
+  }
+  if (COUNT) counts[i] = out;
+}
+
 // ------------------------------------------------------------------ aggregation
 __global__ void k_is_root(int n, const unsigned char* __restrict__ state, int* __restrict__ root) {
   int i = blockIdx.x * kBlock + threadIdx.x;
@@ -1581,6 +1638,46 @@ const double* level0_bound_async(ppe_solver* s) {
   return out;
 }
 
+// Q = A P_tent on the finest level from its ELL copy (k_coarsen_cols_ell):
+// count, scan with the longest row (one round trip), fill.  Q is what the
+// general product gives, entry for entry.
+static void coarsen_cols_ell(ppe_solver* s, const Level& L, const int* agg, const double* pt,
+                             int na, Csr& Q) {
+  const int n = L.n, W = L.W;
+  Q.n = n;
+  Q.m = na;
+  int* qrp = Q.rowptr.get<int>(n + 1);
+  int* counts = s->sp_cnt.get<int>(n + 1);
+  int* flag = s->flag.get<int>(4);
+  fill_int(s, flag, 0, 2);
+  const int g = grid_for(n);
+  const int* ecol = L.ell_col.as<int>();
+  const double* ev = L.ell_val.as<double>();
+  const double* dg = L.diag.as<double>();
+#define PPE_QC(WM, COUNT, ...)                                                                 \
+  hipLaunchKernelGGL((k_coarsen_cols_ell<WM, COUNT>), dim3(g), dim3(kBlock), 0, s->stream, n, W, \
+                     ecol, ev, dg, agg, pt, __VA_ARGS__)
+  if (W <= 4) PPE_QC(4, true, counts, nullptr, nullptr, nullptr);
+  else if (W <= 6) PPE_QC(6, true, counts, nullptr, nullptr, nullptr);
+  else PPE_QC(8, true, counts, nullptr, nullptr, nullptr);
+  PPE_LAUNCH_CHECK();
+  const long long* dtotal = exclusive_scan_async(s, counts, qrp, n);
+  max_int_async(s, counts, n, flag + 1, false);
+  long long total = 0;
+  int fm[2] = {0, 0};
+  read_back(s, {ReadItem{dtotal, sizeof(long long), &total}, ReadItem{flag, sizeof(int) * 2, fm}});
+  require(total <= INT32_MAX, PPE_ERR_INTERNAL, "sparse product too large for int32 indices");
+  Q.nnz = total;
+  Q.maxrow = fm[1];
+  int* qci = Q.col.get<int>(Q.nnz);
+  double* qv = Q.val.get<double>(Q.nnz);
+  if (W <= 4) PPE_QC(4, false, nullptr, qrp, qci, qv);
+  else if (W <= 6) PPE_QC(6, false, nullptr, qrp, qci, qv);
+  else PPE_QC(8, false, nullptr, qrp, qci, qv);
+#undef PPE_QC
+  PPE_LAUNCH_CHECK();
+}
+
 void build_hierarchy(ppe_solver* s) {
   const int maxlev = std::max(1, s->opt.max_levels);
   double* rho_dev = s->setup_out.get<double>((size_t)maxlev + 1);
@@ -1759,7 +1856,11 @@ void build_hierarchy(ppe_solver* s) {
                            Pt.col.get<int>(Pt.nnz), Pt.val.get<double>(Pt.nnz));
         PPE_LAUNCH_CHECK();
         // smoothed prolongator
-        spgemm(s, L0.A, Pt, L0.Q, nullptr, nullptr);
+        if (lvl == 0 && L0.W > 0 && L0.W <= 8) {
+          coarsen_cols_ell(s, L0, agg, pt, na, L0.Q);
+        } else {
+          spgemm(s, L0.A, Pt, L0.Q, nullptr, nullptr);
+        }
         Csr& P = L0.P;
         P.n = n;
         P.m = na;
