@@ -220,6 +220,12 @@ __global__ void k_row_counts(const int* __restrict__ perm, const int* __restrict
   counts[r] = cnt;
 }
 
+// Row r of the compact system: its CSR entries (the diagonal in its sorted
+// place), its diagonal, its slot-major ELL row and B = 1.  With STAGE the
+// workgroup's rows, which are one contiguous CSR range, are assembled in
+// LDS (W + 1 entries per row at most) and written out together, so the
+// stores of a wavefront are contiguous instead of one row per lane.
+template <bool STAGE>
 __global__ void k_fill_rows(const int* __restrict__ perm, int n_active,
                             const int* __restrict__ adj_ptr, const int* __restrict__ adj_nbr,
                             const int* __restrict__ adj_face, const int* __restrict__ active,
@@ -229,48 +235,65 @@ __global__ void k_fill_rows(const int* __restrict__ perm, int n_active,
                             double* __restrict__ diag, int W, int* __restrict__ ell_col,
                             double* __restrict__ ell_val, double* __restrict__ B,
                             const double* __restrict__ shift) {
-  int r = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  if (r >= n_active) return;
-  int c = perm[r];
-  const bool pin = is_pin[c] != 0;
-  double d = shift ? shift[c] : 0.0;
-  for (int k = adj_ptr[c]; k < adj_ptr[c + 1]; ++k) {
-    int j = adj_nbr[k];
-    if (active[j]) d = d + coeff[adj_face[k]];
-  }
-  if (pin && d == 0.0) d = 1.0;
-  diag[r] = d;
-  B[r] = 1.0;
-  int p = rowptr[r];
-  int slot = 0;
-  bool diag_done = false;
-  if (!pin) {
+  extern __shared__ double stage_v[];  // STAGE: kBlock (W + 1) values, then columns
+  const int r0 = xcd_block(blockIdx.x, gridDim.x) * kBlock;
+  const int r = r0 + threadIdx.x;
+  const int base = STAGE ? rowptr[r0] : 0;
+  int* stage_c = reinterpret_cast<int*>(stage_v + (size_t)kBlock * (W + 1));
+  // where row r's entries go: LDS (offset from the workgroup's first entry) or C
+  int* cdst = STAGE ? stage_c - base : col;
+  double* vdst = STAGE ? stage_v - base : val;
+  if (r < n_active) {
+    int c = perm[r];
+    const bool pin = is_pin[c] != 0;
+    double d = shift ? shift[c] : 0.0;
     for (int k = adj_ptr[c]; k < adj_ptr[c + 1]; ++k) {
       int j = adj_nbr[k];
-      if (!active[j] || is_pin[j]) continue;
-      int cj = cid[j];
-      double v = -coeff[adj_face[k]];
-      if (!diag_done && cj > r) {
-        col[p] = r;
-        val[p] = d;
+      if (active[j]) d = d + coeff[adj_face[k]];
+    }
+    if (pin && d == 0.0) d = 1.0;
+    diag[r] = d;
+    B[r] = 1.0;
+    int p = rowptr[r];
+    int slot = 0;
+    bool diag_done = false;
+    if (!pin) {
+      for (int k = adj_ptr[c]; k < adj_ptr[c + 1]; ++k) {
+        int j = adj_nbr[k];
+        if (!active[j] || is_pin[j]) continue;
+        int cj = cid[j];
+        double v = -coeff[adj_face[k]];
+        if (!diag_done && cj > r) {
+          cdst[p] = r;
+          vdst[p] = d;
+          ++p;
+          diag_done = true;
+        }
+        cdst[p] = cj;
+        vdst[p] = v;
         ++p;
-        diag_done = true;
+        ell_col[(size_t)slot * n_active + r] = cj;
+        ell_val[(size_t)slot * n_active + r] = v;
+        ++slot;
       }
-      col[p] = cj;
-      val[p] = v;
-      ++p;
-      ell_col[(size_t)slot * n_active + r] = cj;
-      ell_val[(size_t)slot * n_active + r] = v;
-      ++slot;
+    }
+    if (!diag_done) {
+      cdst[p] = r;
+      vdst[p] = d;
+    }
+    for (; slot < W; ++slot) {
+      ell_col[(size_t)slot * n_active + r] = r;
+      ell_val[(size_t)slot * n_active + r] = 0.0;
     }
   }
-  if (!diag_done) {
-    col[p] = r;
-    val[p] = d;
-  }
-  for (; slot < W; ++slot) {
-    ell_col[(size_t)slot * n_active + r] = r;
-    ell_val[(size_t)slot * n_active + r] = 0.0;
+  if (STAGE) {
+    __syncthreads();
+    const int r1 = min(r0 + kBlock, n_active);
+    const int cnt = rowptr[r1] - base;
+    for (int q = threadIdx.x; q < cnt; q += kBlock) {
+      col[base + q] = stage_c[q];
+      val[base + q] = stage_v[q];
+    }
   }
 }
 
@@ -547,9 +570,18 @@ void assemble_fine(ppe_solver* s, const double* coeff, const double* fl, const d
   int* ecol = L.ell_col.get<int>((size_t)W * na);
   double* evl = L.ell_val.get<double>((size_t)W * na);
   double* B = L.B.get<double>(na);
-  hipLaunchKernelGGL(k_fill_rows, dim3(grid_for(na)), dim3(kBlock), 0, s->stream, perm, na,
-                     s->adj_ptr.as<int>(), s->adj_nbr.as<int>(), s->adj_face.as<int>(), active,
-                     is_pin, cid, coeff, rowptr, col, val, diag, L.W, ecol, evl, B, shift);
+  // a row holds at most W + 1 entries (its open faces and the diagonal)
+  const size_t stage = (size_t)kBlock * (L.W + 1) * (sizeof(double) + sizeof(int));
+  if (stage <= s->lds_max)
+    hipLaunchKernelGGL(k_fill_rows<true>, dim3(grid_for(na)), dim3(kBlock), stage, s->stream,
+                       perm, na, s->adj_ptr.as<int>(), s->adj_nbr.as<int>(),
+                       s->adj_face.as<int>(), active, is_pin, cid, coeff, rowptr, col, val, diag,
+                       L.W, ecol, evl, B, shift);
+  else
+    hipLaunchKernelGGL(k_fill_rows<false>, dim3(grid_for(na)), dim3(kBlock), 0, s->stream, perm,
+                       na, s->adj_ptr.as<int>(), s->adj_nbr.as<int>(), s->adj_face.as<int>(),
+                       active, is_pin, cid, coeff, rowptr, col, val, diag, L.W, ecol, evl, B,
+                       shift);
   PPE_LAUNCH_CHECK();
 }
 
