@@ -384,6 +384,70 @@ __global__ void __launch_bounds__(kBlock) k_coarsen_cols_ell(
   if (COUNT) counts[i] = out;
 }
 
+// Finest level: AP = A P by rows, one thread per row from the ELL copy:
+// row i of AP merges the sorted rows of P selected by row i of A (its ELL
+// slots and the diagonal, at most WM + 1 of them), column by column.  A
+// column's products are added from 0 in CSR order of A's row, which is the
+// order the general product adds them in (one sub-group walks A's row in
+// order): bitwise its result.  COUNT: entries per row into counts; else the
+// row, sorted, at rp[i].
+template <int WM, bool COUNT>
+__global__ void __launch_bounds__(kBlock) k_ap_merge_ell(
+    int n, int W, const int* __restrict__ ecol, const double* __restrict__ ev,
+    const double* __restrict__ diag, const int* __restrict__ prp, const int* __restrict__ pci,
+    const double* __restrict__ pv, int* __restrict__ counts, const int* __restrict__ rp,
+    int* __restrict__ ci, double* __restrict__ v) {
+  const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int c[WM];
+  slot_cols<WM>(i, n, W, ecol, c);
+  // list k < WM: row c[k] of P (empty for padding); list WM: row i (the
+  // diagonal), which comes before list dpos in CSR order
+  int pos[WM + 1], end[WM + 1], col[WM + 1];
+  double a[WM + 1], pval[WM + 1];
+  int dpos = WM;
+#pragma unroll
+  for (int k = WM; k >= 0; --k) {
+    const int j = k < WM ? c[k] : i;
+    const bool real = k == WM || j != i;
+    if (k < WM && real && j > i) dpos = k;
+    pos[k] = real ? prp[j] : 0;
+    end[k] = real ? prp[j + 1] : 0;
+    if (!COUNT) a[k] = k < WM ? (real ? ev[(size_t)k * n + i] : 0.0) : diag[i];
+  }
+#pragma unroll
+  for (int k = 0; k <= WM; ++k) {
+    col[k] = pos[k] < end[k] ? pci[pos[k]] : INT32_MAX;
+    if (!COUNT) pval[k] = pos[k] < end[k] ? pv[pos[k]] : 0.0;
+  }
+  int out = COUNT ? 0 : rp[i];
+  for (;;) {
+    int cur = col[0];
+#pragma unroll
+    for (int k = 1; k <= WM; ++k) cur = col[k] < cur ? col[k] : cur;
+    if (cur == INT32_MAX) break;
+    if (!COUNT) {
+      double sum = 0.0;
+#pragma unroll
+      for (int k = 0; k <= WM; ++k) {
+        if (k == dpos && col[WM] == cur) sum = sum + a[WM] * pval[WM];
+        if (k < WM && col[k] == cur) sum = sum + a[k] * pval[k];
+      }
+      ci[out] = cur;
+      v[out] = sum;
+    }
+    ++out;
+#pragma unroll
+    for (int k = 0; k <= WM; ++k)
+      if (col[k] == cur) {
+        ++pos[k];
+        col[k] = pos[k] < end[k] ? pci[pos[k]] : INT32_MAX;
+        if (!COUNT) pval[k] = pos[k] < end[k] ? pv[pos[k]] : 0.0;
+      }
+  }
+  if (COUNT) counts[i] = out;
+}
+
 // ------------------------------------------------------------------ aggregation
 __global__ void k_is_root(int n, const unsigned char* __restrict__ state, int* __restrict__ root) {
   int i = blockIdx.x * kBlock + threadIdx.x;
@@ -1678,6 +1742,47 @@ static void coarsen_cols_ell(ppe_solver* s, const Level& L, const int* agg, cons
   PPE_LAUNCH_CHECK();
 }
 
+// AP = A P on the finest level from its ELL copy (k_ap_merge_ell): count,
+// scan with the longest row and the device value extra (one round trip),
+// fill.  AP is what the general product gives, entry for entry.
+static void ap_merge_ell(ppe_solver* s, const Level& L, const Csr& P, Csr& AP, const int* extra,
+                         int* extra_host) {
+  const int n = L.n, W = L.W;
+  AP.n = n;
+  AP.m = P.m;
+  int* crp = AP.rowptr.get<int>(n + 1);
+  int* counts = s->sp_cnt.get<int>(n + 1);
+  int* flag = s->flag.get<int>(4);
+  fill_int(s, flag, 0, 2);
+  const int g = grid_for(n);
+  const int* ecol = L.ell_col.as<int>();
+  const double* ev = L.ell_val.as<double>();
+  const double* dg = L.diag.as<double>();
+#define PPE_AP(WM, COUNT, ...)                                                                 \
+  hipLaunchKernelGGL((k_ap_merge_ell<WM, COUNT>), dim3(g), dim3(kBlock), 0, s->stream, n, W, ecol, \
+                     ev, dg, P.rp(), P.ci(), P.v(), __VA_ARGS__)
+  if (W <= 4) PPE_AP(4, true, counts, nullptr, nullptr, nullptr);
+  else if (W <= 6) PPE_AP(6, true, counts, nullptr, nullptr, nullptr);
+  else PPE_AP(8, true, counts, nullptr, nullptr, nullptr);
+  PPE_LAUNCH_CHECK();
+  const long long* dtotal = exclusive_scan_async(s, counts, crp, n);
+  max_int_async(s, counts, n, flag + 1, false);
+  long long total = 0;
+  int fm[2] = {0, 0};
+  read_back(s, {ReadItem{dtotal, sizeof(long long), &total}, ReadItem{flag, sizeof(int) * 2, fm},
+                ReadItem{extra, sizeof(int), extra_host}});
+  require(total <= INT32_MAX, PPE_ERR_INTERNAL, "sparse product too large for int32 indices");
+  AP.nnz = total;
+  AP.maxrow = fm[1];
+  int* cci = AP.col.get<int>(AP.nnz);
+  double* cv = AP.val.get<double>(AP.nnz);
+  if (W <= 4) PPE_AP(4, false, nullptr, crp, cci, cv);
+  else if (W <= 6) PPE_AP(6, false, nullptr, crp, cci, cv);
+  else PPE_AP(8, false, nullptr, crp, cci, cv);
+#undef PPE_AP
+  PPE_LAUNCH_CHECK();
+}
+
 void build_hierarchy(ppe_solver* s) {
   const int maxlev = std::max(1, s->opt.max_levels);
   double* rho_dev = s->setup_out.get<double>((size_t)maxlev + 1);
@@ -1875,7 +1980,10 @@ void build_hierarchy(ppe_solver* s) {
         std::swap(P.rowptr, L0.Q.rowptr);
         std::swap(P.col, L0.Q.col);
         transpose(s, P, L0.R);
-        spgemm(s, L0.A, P, L0.AP, s->rmax.as<int>(), &L0.R.maxrow);
+        if (lvl == 0 && L0.W > 0 && L0.W <= 8)
+          ap_merge_ell(s, L0, P, L0.AP, s->rmax.as<int>(), &L0.R.maxrow);
+        else
+          spgemm(s, L0.A, P, L0.AP, s->rmax.as<int>(), &L0.R.maxrow);
         L0.ap_ok = true;
         spgemm(s, L0.R, L0.AP, C.A, nullptr, nullptr);
         C.n = na;
