@@ -137,6 +137,7 @@ __global__ void k_dsilu_mul(int64_t len, const float* __restrict__ z, float* __r
 }
 
 // column sums of G [n x w] over rows chunk z: parts[z*w + j]
+constexpr int kColRows = 64, kColChunks = 1024;
 __global__ void k_colsum_chunks(int n, int w, int chunk, const float* __restrict__ G,
                                 float* __restrict__ parts) {
   const int j = blockIdx.x * kBlock + threadIdx.x;
@@ -630,10 +631,13 @@ double loss_grad(ppe_mlp* m, int n, const float* x, const float* t) {
     // dW [out x in] = G^T [out x n] . hin [n x in]   (sum over rows, split-K)
     gemm(m, out, in, n, G, 1, out, hin, in, 1, dP + m->woff[l], kChunkRows);
     // db [out] = column sums of G
-    const int nz = (n + kChunkRows - 1) / kChunkRows;
+    // bias gradient: column sums over chunks of at least kColRows rows (at
+    // most kColChunks chunks), the chunks then added in order
+    const int crow = std::max(kColRows, (n + kColChunks - 1) / kColChunks);
+    const int nz = (n + crow - 1) / crow;
     float* parts = m->part.get<float>((size_t)nz * out);
     hipLaunchKernelGGL(k_colsum_chunks, dim3((out + kBlock - 1) / kBlock, nz), dim3(kBlock), 0,
-                       m->stream, n, out, kChunkRows, G, parts);
+                       m->stream, n, out, crow, G, parts);
     PPE_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_sum_chunks, dim3(grid_for(out)), dim3(kBlock), 0, m->stream, (int64_t)out,
                        nz, parts, dP + m->boff[l]);
