@@ -137,3 +137,47 @@ def test_full_size_64cube_hierarchy():
     r = np.random.default_rng(6).normal(size=sy.n_active)
     z = s.apply_vcycle(to_dev(r, torch.float64)).cpu().numpy()
     assert np.linalg.norm(z - amg.vcycle(H, r)) <= 1e-12 * np.linalg.norm(z)
+
+
+def test_hierarchy_on_a_graph_of_degree_ten():
+    """Extra faces to the in-plane diagonal neighbours give rows of up to ten
+    off-diagonal entries: the finest level's ELL strength, MIS-2 and joining
+    passes take their plain slot loop (more than eight slots) and the finest
+    products the general sparse product.  Aggregates equal the oracle's,
+    operators and prolongators agree to rounding, and so does one V-cycle."""
+    import torch
+
+    import paper_1810_08572_amd as ppe
+
+    m = box_mesh((10, 9, 8), jitter=0.1, seed=3)
+    idx = {tuple(g): c for c, g in enumerate(m.grid_index)}
+    extra = [(c, idx[(i + di, j + dj, k)]) for c, (i, j, k) in enumerate(m.grid_index)
+             for di, dj in ((1, 1), (1, -1)) if (i + di, j + dj, k) in idx]
+    extra = np.array(extra)
+    owner = np.concatenate([m.owner, extra[:, 0]]).astype(np.int32)
+    neigh = np.concatenate([m.neigh, extra[:, 1]]).astype(np.int32)
+    c0 = face_coeff(m, 2400.0)
+    c = np.concatenate([c0, np.full(len(extra), 0.3 * c0[m.neigh >= 0].mean())])
+    f = np.clip((m.cell_centre[:, 0] - 0.2) / 0.5, 0.0, 1.0)
+    inner = neigh >= 0
+    deg = np.bincount(np.concatenate([owner[inner], neigh[inner]]), minlength=m.n_cells)
+    assert deg.max() > 8
+    sy = assembly.masked_system(m.n_cells, owner, neigh, c, f)
+    H = amg.build_hierarchy(sy.A, coarse_max=32)
+    assert len(H.levels) >= 3
+    s = ppe.Solver(coarse_max=32)
+    s.set_mesh(m.n_cells, to_dev(owner, torch.int32), to_dev(neigh, torch.int32))
+    s.assemble(to_dev(c, torch.float64), to_dev(f, torch.float64))
+    assert s.n_levels() == len(H.levels)
+    for lvl, lev in enumerate(H.levels):
+        n = lev.A.shape[0]
+        A = csr(*s.level_matrix(lvl), (n, n))
+        assert A.nnz == lev.A.nnz and rel_max(A, lev.A) <= 1e-13, lvl
+        if lvl < len(H.levels) - 1:
+            assert np.array_equal(s.aggregates(lvl).cpu().numpy(), lev.agg), lvl
+            P = csr(*s.prolongator(lvl), lev.P.shape)
+            assert rel_max(P, lev.P) <= 1e-13, lvl
+    r = np.random.default_rng(11).normal(size=sy.n_active)
+    z = s.apply_vcycle(to_dev(r, torch.float64)).cpu().numpy()
+    assert np.linalg.norm(z - amg.vcycle(H, r)) <= 1e-12 * np.linalg.norm(z)
+    s.close()
