@@ -181,3 +181,32 @@ def test_hierarchy_on_a_graph_of_degree_ten():
     z = s.apply_vcycle(to_dev(r, torch.float64)).cpu().numpy()
     assert np.linalg.norm(z - amg.vcycle(H, r)) <= 1e-12 * np.linalg.norm(z)
     s.close()
+
+
+def test_hierarchy_after_another_mesh_on_the_same_solver():
+    """A chain of 200 cells, then a 40^3 cube, on one solver: the second
+    setup reuses the first one's level buffers, MIS-2 batch counts and
+    launch state, and must still give the oracle's hierarchy exactly."""
+    import torch
+
+    import paper_1810_08572_amd as ppe
+
+    cm = 16
+    s = ppe.Solver(coarse_max=cm)
+    for m in (box_mesh((200, 1, 1), jitter=0.1, seed=1), box_mesh((40, 40, 40), jitter=0.1, seed=0)):
+        f, c = np.ones(m.n_cells), face_coeff(m, 2400.0)
+        sy = assembly.masked_system(m.n_cells, m.owner, m.neigh, c, f)
+        H = amg.build_hierarchy(sy.A, coarse_max=cm)
+        s.set_mesh(m.n_cells, to_dev(m.owner, torch.int32), to_dev(m.neigh, torch.int32))
+        s.assemble(to_dev(c, torch.float64), to_dev(f, torch.float64))
+        assert s.n_levels() == len(H.levels)
+        for lvl, lev in enumerate(H.levels):
+            n = lev.A.shape[0]
+            A = csr(*s.level_matrix(lvl), (n, n))
+            assert A.nnz == lev.A.nnz and rel_max(A, lev.A) <= 1e-13, lvl
+            if lvl < len(H.levels) - 1:
+                assert np.array_equal(s.aggregates(lvl).cpu().numpy(), lev.agg), lvl
+        r = np.random.default_rng(8).normal(size=sy.n_active)
+        z = s.apply_vcycle(to_dev(r, torch.float64)).cpu().numpy()
+        assert np.linalg.norm(z - amg.vcycle(H, r)) <= 1e-12 * np.linalg.norm(z)
+    s.close()
