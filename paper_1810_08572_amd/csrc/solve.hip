@@ -509,8 +509,17 @@ struct Tiles {
   const int* tp;  // segment q owns tiles [tp[q], tp[q+1])
 };
 
+// Workgroup size of the tile and segment kernels.  A tile holds 256 to 4096
+// rows (768 on the 1.5 M-cell plate, 1,536 on the 128^3 cube): 512 threads
+// take one to three rows each, where 256 left up to six in turn (128^3 solve
+// 4.09 -> 4.03 ms).  With 1024 only one workgroup of the ELL tile kernels
+// fits a CU at their register use, and every tile kernel got slower.  All
+// tile and segment kernels share the size, so every consumer adds a
+// segment's tile partials in the same order.
+constexpr int kTileBlock = 512;
+
 __device__ __forceinline__ double seg_sum(const double* __restrict__ part, const Tiles& T, int q) {
-  return sum_partials<kBlock>(part + T.tp[q], T.tp[q + 1] - T.tp[q]);
+  return sum_partials<kTileBlock>(part + T.tp[q], T.tp[q + 1] - T.tp[q]);
 }
 
 // per-segment scalar arrays (each n_seg doubles) in s->seg_sc
@@ -518,41 +527,39 @@ enum SegScal : int { SS_BB = 0, SS_TOL2 = 1, SS_RZ0 = 2, SS_RZ1 = 3, SS_RES = 4,
 // tile-partial arrays (each n_tiles doubles) in s->tpart
 enum TilePart : int { T_BB = 0, T_RR = 1, T_PQ = 2, T_RZ = 3, T_RT = 4, T_N = 5 };
 
-__global__ void __launch_bounds__(kBlock) k_gather_rhs_t(Tiles T, const int* __restrict__ perm,
-                                                         const int* __restrict__ comp,
-                                                         const double* __restrict__ rhs,
-                                                         double* __restrict__ b,
-                                                         double* __restrict__ part) {
+__global__ void __launch_bounds__(kTileBlock)
+k_gather_rhs_t(Tiles T, const int* __restrict__ perm, const int* __restrict__ comp,
+               const double* __restrict__ rhs, double* __restrict__ b, double* __restrict__ part) {
   const int t = blockIdx.x;
   double acc = 0.0;
-  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) {
+  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kTileBlock) {
     const int c = perm[i];
     const double v = comp[c] == c ? 0.0 : rhs[c];
     b[i] = v;
     acc += v * v;
   }
   double sv[1] = {acc};
-  write_partials<kBlock, 1>(sv, part);
+  write_partials<kTileBlock, 1>(sv, part);
 }
 
-__global__ void __launch_bounds__(kBlock) k_norm2_t(Tiles T, const double* __restrict__ a,
-                                                    double* __restrict__ part) {
+__global__ void __launch_bounds__(kTileBlock) k_norm2_t(Tiles T, const double* __restrict__ a,
+                                                        double* __restrict__ part) {
   const int t = blockIdx.x;
   double acc = 0.0;
-  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) acc += a[i] * a[i];
+  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kTileBlock) acc += a[i] * a[i];
   double sv[1] = {acc};
-  write_partials<kBlock, 1>(sv, part);
+  write_partials<kTileBlock, 1>(sv, part);
 }
 
 // tile partials of r.z
-__global__ void __launch_bounds__(kBlock) k_dot_t(Tiles T, const double* __restrict__ r,
-                                                  const double* __restrict__ z,
-                                                  double* __restrict__ part) {
+__global__ void __launch_bounds__(kTileBlock) k_dot_t(Tiles T, const double* __restrict__ r,
+                                                      const double* __restrict__ z,
+                                                      double* __restrict__ part) {
   const int t = blockIdx.x;
   double acc = 0.0;
-  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) acc += r[i] * z[i];
+  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kTileBlock) acc += r[i] * z[i];
   double sv[1] = {acc};
-  write_partials<kBlock, 1>(sv, part);
+  write_partials<kTileBlock, 1>(sv, part);
 }
 
 // The last smoothing step of a level-0 V-cycle fused with the PCG dot that
@@ -561,14 +568,15 @@ __global__ void __launch_bounds__(kBlock) k_dot_t(Tiles T, const double* __restr
 // y the preconditioned residual.  Same arithmetic and order as the separate
 // kernels.
 template <int WM, class M>
-__global__ void __launch_bounds__(kBlock) k_ell_cheb_dot_t(
-    Tiles T, int n, int W, const int* __restrict__ ecol, const M* __restrict__ eval,
-    const M* __restrict__ diag, const M* __restrict__ sd, const double* __restrict__ x,
-    const double* __restrict__ b, double* __restrict__ d, double c1, double c2,
-    double* __restrict__ y, double* __restrict__ part) {
+__global__ void __launch_bounds__(kTileBlock)
+k_ell_cheb_dot_t(Tiles T, int n, int W, const int* __restrict__ ecol, const M* __restrict__ eval,
+                 const M* __restrict__ diag, const M* __restrict__ sd,
+                 const double* __restrict__ x, const double* __restrict__ b,
+                 double* __restrict__ d, double c1, double c2, double* __restrict__ y,
+                 double* __restrict__ part) {
   const int t = xcd_block(blockIdx.x, gridDim.x);  // the tile (its partial's slot)
   double acc = 0.0;
-  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) {
+  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kTileBlock) {
     double s = (double)diag[i] * x[i];
     s = ell_row<E_CHEB, WM, M>(s, i, n, W, ecol, eval, x, b, sd, 0.0);
     const double r = (b[i] - s) / (double)sd[i];
@@ -579,24 +587,24 @@ __global__ void __launch_bounds__(kBlock) k_ell_cheb_dot_t(
     acc += b[i] * yi;
   }
   double sv[1] = {acc};
-  write_partials<kBlock, 1>(sv, part, t);
+  write_partials<kTileBlock, 1>(sv, part, t);
 }
 
 // q = A p on the finest (ELL) level over the tile's rows (the outer operator,
 // FP64 in both modes); tile partials of p.q
 template <int WM>
-__global__ void __launch_bounds__(kBlock) k_ell_dot_t(Tiles T, int n, int W,
-                                                      const int* __restrict__ ecol,
-                                                      const double* __restrict__ eval,
-                                                      const double* __restrict__ diag,
-                                                      const int* __restrict__ done,
-                                                      const double* __restrict__ p,
-                                                      double* __restrict__ q,
-                                                      double* __restrict__ part) {
+__global__ void __launch_bounds__(kTileBlock) k_ell_dot_t(Tiles T, int n, int W,
+                                                          const int* __restrict__ ecol,
+                                                          const double* __restrict__ eval,
+                                                          const double* __restrict__ diag,
+                                                          const int* __restrict__ done,
+                                                          const double* __restrict__ p,
+                                                          double* __restrict__ q,
+                                                          double* __restrict__ part) {
   const int t = xcd_block(blockIdx.x, gridDim.x);  // the tile (its partial's slot)
   double acc = 0.0;
   if (!done[T.seg[t]]) {
-    for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) {
+    for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kTileBlock) {
       double s = diag[i] * p[i];
       s = ell_row<E_SPMV, WM, double>(s, i, n, W, ecol, eval, p, nullptr, diag, 0.0);
       q[i] = s;
@@ -604,18 +612,19 @@ __global__ void __launch_bounds__(kBlock) k_ell_dot_t(Tiles T, int n, int W,
     }
   }
   double sv[1] = {acc};
-  write_partials<kBlock, 1>(sv, part, t);
+  write_partials<kTileBlock, 1>(sv, part, t);
 }
 
 // Per segment (one block each): bb, tolerance, initial convergence; counts
 // active segments.
-__global__ void __launch_bounds__(kBlock) k_seg_init(int ns, Tiles T,
-                                                     const double* __restrict__ part_bb,
-                                                     const double* __restrict__ part_rr,
-                                                     double rtol2, double* __restrict__ sc,
-                                                     int* __restrict__ done, int* __restrict__ iters,
-                                                     int* __restrict__ restart,
-                                                     int* __restrict__ active) {
+__global__ void __launch_bounds__(kTileBlock) k_seg_init(int ns, Tiles T,
+                                                         const double* __restrict__ part_bb,
+                                                         const double* __restrict__ part_rr,
+                                                         double rtol2, double* __restrict__ sc,
+                                                         int* __restrict__ done,
+                                                         int* __restrict__ iters,
+                                                         int* __restrict__ restart,
+                                                         int* __restrict__ active) {
   const int q = blockIdx.x;
   const double bb = seg_sum(part_bb, T, q);
   const double rr = seg_sum(part_rr, T, q);
@@ -631,38 +640,38 @@ __global__ void __launch_bounds__(kBlock) k_seg_init(int ns, Tiles T,
 }
 
 // zero the iterate of segments whose right-hand side is zero
-__global__ void __launch_bounds__(kBlock) k_zero_empty_t(Tiles T, int ns,
-                                                         const double* __restrict__ sc,
-                                                         double* __restrict__ x) {
+__global__ void __launch_bounds__(kTileBlock)
+k_zero_empty_t(Tiles T, int ns, const double* __restrict__ sc, double* __restrict__ x) {
   const int t = blockIdx.x;
   if (sc[SS_BB * ns + T.seg[t]] != 0.0) return;
-  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) x[i] = 0.0;
+  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kTileBlock) x[i] = 0.0;
 }
 
 // p = z on active segments; the first tile of a segment stores its r.z
-__global__ void __launch_bounds__(kBlock) k_init_p_t(Tiles T, int ns, const int* __restrict__ done,
-                                                     const double* __restrict__ part_rz,
-                                                     const double* __restrict__ z,
-                                                     double* __restrict__ p,
-                                                     double* __restrict__ rz_out) {
+__global__ void __launch_bounds__(kTileBlock) k_init_p_t(Tiles T, int ns,
+                                                         const int* __restrict__ done,
+                                                         const double* __restrict__ part_rz,
+                                                         const double* __restrict__ z,
+                                                         double* __restrict__ p,
+                                                         double* __restrict__ rz_out) {
   const int t = blockIdx.x, q = T.seg[t];
   if (done[q]) return;
   const double rz = seg_sum(part_rz, T, q);
   if (t == T.tp[q] && threadIdx.x == 0) rz_out[q] = rz;
-  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) p[i] = z[i];
+  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kTileBlock) p[i] = z[i];
 }
 
 // alpha_q = rz_q / (p.q)_q; x += alpha p; r -= alpha q; tile partial of r.r
-__global__ void __launch_bounds__(kBlock) k_update_xr_t(Tiles T, const int* __restrict__ done,
-                                                        const double* __restrict__ rz,
-                                                        const double* __restrict__ part_pq,
-                                                        const double* __restrict__ p,
-                                                        const double* __restrict__ qv,
-                                                        double* __restrict__ x,
-                                                        double* __restrict__ r,
-                                                        double* __restrict__ part,
-                                                        int* __restrict__ active,
-                                                        int* __restrict__ err) {
+__global__ void __launch_bounds__(kTileBlock) k_update_xr_t(Tiles T, const int* __restrict__ done,
+                                                            const double* __restrict__ rz,
+                                                            const double* __restrict__ part_pq,
+                                                            const double* __restrict__ p,
+                                                            const double* __restrict__ qv,
+                                                            double* __restrict__ x,
+                                                            double* __restrict__ r,
+                                                            double* __restrict__ part,
+                                                            int* __restrict__ active,
+                                                            int* __restrict__ err) {
   const int t = blockIdx.x, q = T.seg[t];
   if (t == 0 && threadIdx.x == 0) *active = 0;  // counted again by k_update_p_t
   // the thread's first row, requested before the segment's sums
@@ -682,7 +691,7 @@ __global__ void __launch_bounds__(kBlock) k_update_xr_t(Tiles T, const int* __re
       if (threadIdx.x == 0) atomicOr(err, 1);
     } else {
       const double alpha = num / pq;
-      for (int i = i0; i < i1; i += kBlock) {
+      for (int i = i0; i < i1; i += kTileBlock) {
         const bool first = i == i0;
         x[i] = (first ? x0 : x[i]) + alpha * (first ? p0 : p[i]);
         const double v = (first ? r0 : r[i]) - alpha * (first ? q0 : qv[i]);
@@ -692,7 +701,7 @@ __global__ void __launch_bounds__(kBlock) k_update_xr_t(Tiles T, const int* __re
     }
   }
   double sv[1] = {acc};
-  write_partials<kBlock, 1>(sv, part);
+  write_partials<kTileBlock, 1>(sv, part);
 }
 
 // With test set (every PCG iteration): count the iteration of each running
@@ -702,12 +711,19 @@ __global__ void __launch_bounds__(kBlock) k_update_xr_t(Tiles T, const int* __re
 // p.  Otherwise (first direction after a restart) restart[q] forces beta 0.
 // Then beta_q = r.z / rz_prev; p = z + beta p; counts the segments still
 // running.
-__global__ void __launch_bounds__(kBlock) k_update_p_t(
-    Tiles T, int ns, int test, int* __restrict__ done, int* __restrict__ restart,
-    const double* __restrict__ part_rr, const double* __restrict__ sc, int* __restrict__ iters,
-    int* __restrict__ active, const double* __restrict__ part_rz,
-    const double* __restrict__ rz_prev, double* __restrict__ rz_next,
-    const double* __restrict__ z, double* __restrict__ p, int* __restrict__ err) {
+__global__ void __launch_bounds__(kTileBlock) k_update_p_t(Tiles T, int ns, int test,
+                                                           int* __restrict__ done,
+                                                           int* __restrict__ restart,
+                                                           const double* __restrict__ part_rr,
+                                                           const double* __restrict__ sc,
+                                                           int* __restrict__ iters,
+                                                           int* __restrict__ active,
+                                                           const double* __restrict__ part_rz,
+                                                           const double* __restrict__ rz_prev,
+                                                           double* __restrict__ rz_next,
+                                                           const double* __restrict__ z,
+                                                           double* __restrict__ p,
+                                                           int* __restrict__ err) {
   const int t = blockIdx.x, q = T.seg[t];
   // the thread's first row, requested before the segment's sums
   const int i0 = T.r0[t] + threadIdx.x, i1 = T.r1[t];
@@ -723,7 +739,7 @@ __global__ void __launch_bounds__(kBlock) k_update_p_t(
   const int g0 = T.tp[q], G = T.tp[q + 1] - g0;
   double sums[2];
   const double* parts[2] = {part_rr + g0, part_rz + g0};
-  sum_partials_n<kBlock, 2>(parts, G, sums);
+  sum_partials_n<kTileBlock, 2>(parts, G, sums);
   if (test) {
     const double rr = sums[0];
     const bool bad = !(rr == rr) || rr > 1.7976931348623157e308;
@@ -744,7 +760,7 @@ __global__ void __launch_bounds__(kBlock) k_update_p_t(
     rz_next[q] = rzn;
     if (!(rzn > 0.0)) atomicOr(err, 4);
   }
-  for (int i = i0; i < i1; i += kBlock) {
+  for (int i = i0; i < i1; i += kTileBlock) {
     const bool first = i == i0;
     p[i] = (first ? z0 : z[i]) + beta * (first ? p0 : p[i]);
   }
@@ -752,12 +768,12 @@ __global__ void __launch_bounds__(kBlock) k_update_p_t(
 
 // After the recurred residuals all met the tolerance: per segment (one
 // block each), the true residual; a segment that misses it restarts.
-__global__ void __launch_bounds__(kBlock) k_seg_check(int ns, Tiles T,
-                                                      const double* __restrict__ part_rt,
-                                                      double* __restrict__ sc,
-                                                      int* __restrict__ done,
-                                                      int* __restrict__ restart,
-                                                      int* __restrict__ active) {
+__global__ void __launch_bounds__(kTileBlock) k_seg_check(int ns, Tiles T,
+                                                          const double* __restrict__ part_rt,
+                                                          double* __restrict__ sc,
+                                                          int* __restrict__ done,
+                                                          int* __restrict__ restart,
+                                                          int* __restrict__ active) {
   const int q = blockIdx.x;
   const double rt = seg_sum(part_rt, T, q);
   if (threadIdx.x != 0) return;
@@ -771,12 +787,12 @@ __global__ void __launch_bounds__(kBlock) k_seg_check(int ns, Tiles T,
 }
 
 // r = r_true on segments that restart
-__global__ void __launch_bounds__(kBlock) k_copy_restart_t(Tiles T, const int* __restrict__ restart,
-                                                           const double* __restrict__ rt,
-                                                           double* __restrict__ r) {
+__global__ void __launch_bounds__(kTileBlock)
+k_copy_restart_t(Tiles T, const int* __restrict__ restart, const double* __restrict__ rt,
+                 double* __restrict__ r) {
   const int t = blockIdx.x;
   if (!restart[T.seg[t]]) return;
-  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kBlock) r[i] = rt[i];
+  for (int i = T.r0[t] + threadIdx.x; i < T.r1[t]; i += kTileBlock) r[i] = rt[i];
 }
 
 __global__ void k_gather_x0(int na, const int* __restrict__ perm, const int* __restrict__ comp,
@@ -1178,7 +1194,7 @@ bool smooth_steps(ppe_solver* s, Level& L, const double* b, const double* cur, i
            return std::make_pair(kname("k_ell_cheb_dot_t", {str(WM_), tname<M>()}),           \
                                  op_bytes<E_CHEB, M>(s, L, true, c1));                        \
          },                                                                                    \
-         k_ell_cheb_dot_t<WM_, M>, dim3(dot->nt), dim3(kBlock), dot->T, n, L.W,                \
+         k_ell_cheb_dot_t<WM_, M>, dim3(dot->nt), dim3(kTileBlock), dot->T, n, L.W,            \
          (const int*)L.ell_col.as<int>(), LevelData<M>::ell(L), LevelData<M>::diag(L),         \
          smooth_diag<M>(s, L), cur, b, d, c1, c2, dst, dot->part)
       PPE_ELL_WIDTH(L.W, PPE_CHEB_DOT);
@@ -1411,7 +1427,7 @@ static void vcycle_pcg(ppe_solver* s, const double* r, double* z, const PcgDot& 
                                                     : vcycle_t<double>(s, 0, r, z, &dot);
   if (!dotted)
     launch(s, [&]() { return std::make_pair(std::string("k_dot_t"), 16.0 * s->n_active); },
-           k_dot_t, dim3(dot.nt), dim3(kBlock), dot.T, r, (const double*)z, dot.part);
+           k_dot_t, dim3(dot.nt), dim3(kTileBlock), dot.T, r, (const double*)z, dot.part);
 }
 
 // FP32 copies of the hierarchy's values for the mixed-precision V-cycle:
@@ -1501,8 +1517,8 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
   // the box holds the final statistics (read_back) beside the two check slots
   ensure_box(s, kBoxRead + 1 + 5 * (size_t)ns);
   std::vector<double> bbh(ns), rth(ns);
-  hipLaunchKernelGGL(k_gather_rhs_t, dim3(nt), dim3(kBlock), 0, s->stream, T, perm, comp, rhs, b,
-                     tpart(T_BB));
+  hipLaunchKernelGGL(k_gather_rhs_t, dim3(nt), dim3(kTileBlock), 0, s->stream, T, perm, comp, rhs,
+                     b, tpart(T_BB));
   PPE_LAUNCH_CHECK();
   if (use_x0) {
     hipLaunchKernelGGL(k_gather_x0, dim3(ge), dim3(kBlock), 0, s->stream, na, perm, comp, p_out, x);
@@ -1513,14 +1529,14 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
     hipLaunchKernelGGL(k_copy, dim3(ge), dim3(kBlock), 0, s->stream, na, b, r);
     PPE_LAUNCH_CHECK();
   }
-  hipLaunchKernelGGL(k_norm2_t, dim3(nt), dim3(kBlock), 0, s->stream, T, r, tpart(T_RR));
+  hipLaunchKernelGGL(k_norm2_t, dim3(nt), dim3(kTileBlock), 0, s->stream, T, r, tpart(T_RR));
   PPE_LAUNCH_CHECK();
   fill_int(s, cnt, 0, 2);
-  hipLaunchKernelGGL(k_seg_init, dim3(ns), dim3(kBlock), 0, s->stream, ns, T, tpart(T_BB),
+  hipLaunchKernelGGL(k_seg_init, dim3(ns), dim3(kTileBlock), 0, s->stream, ns, T, tpart(T_BB),
                      tpart(T_RR), s->opt.rtol * s->opt.rtol, sc, done, iters, restart, cnt);
   PPE_LAUNCH_CHECK();
   if (use_x0) {
-    hipLaunchKernelGGL(k_zero_empty_t, dim3(nt), dim3(kBlock), 0, s->stream, T, ns, sc, x);
+    hipLaunchKernelGGL(k_zero_empty_t, dim3(nt), dim3(kTileBlock), 0, s->stream, T, ns, sc, x);
     PPE_LAUNCH_CHECK();
   }
   // true residual of every segment, then restart those that miss the
@@ -1529,13 +1545,14 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
   bool fetched = false;
   auto check_true = [&]() {
     apply_op<E_RESID, double>(s, L0, x, b, nullptr, 0.0, 0.0, q, nullptr);
-    hipLaunchKernelGGL(k_norm2_t, dim3(nt), dim3(kBlock), 0, s->stream, T, q, tpart(T_RT));
+    hipLaunchKernelGGL(k_norm2_t, dim3(nt), dim3(kTileBlock), 0, s->stream, T, q, tpart(T_RT));
     PPE_LAUNCH_CHECK();
     fill_int(s, cnt, 0, 1);
-    hipLaunchKernelGGL(k_seg_check, dim3(ns), dim3(kBlock), 0, s->stream, ns, T, tpart(T_RT), sc,
-                       done, restart, cnt);
+    hipLaunchKernelGGL(k_seg_check, dim3(ns), dim3(kTileBlock), 0, s->stream, ns, T, tpart(T_RT),
+                       sc, done, restart, cnt);
     PPE_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_copy_restart_t, dim3(nt), dim3(kBlock), 0, s->stream, T, restart, q, r);
+    hipLaunchKernelGGL(k_copy_restart_t, dim3(nt), dim3(kTileBlock), 0, s->stream, T, restart, q,
+                       r);
     PPE_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc,
                        s->cid.as<int>(), comp, x, p_out);
@@ -1575,7 +1592,7 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
   // left alone by every iteration, so the first check below finds them.
   auto precondition = [&](int sl) { vcycle_pcg(s, r, zb[sl], PcgDot{T, nt, tpart(T_RZ)}); };
   precondition(1);
-  hipLaunchKernelGGL(k_init_p_t, dim3(nt), dim3(kBlock), 0, s->stream, T, ns, done, tpart(T_RZ),
+  hipLaunchKernelGGL(k_init_p_t, dim3(nt), dim3(kTileBlock), 0, s->stream, T, ns, done, tpart(T_RZ),
                      zb[1], p, rz[0]);
   PPE_LAUNCH_CHECK();
   // One PCG iteration of every sample still running: q = A p; x, r update;
@@ -1588,7 +1605,7 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
            return std::make_pair(kname("k_ell_dot_t", {str(WM_)}),                            \
                                  op_bytes<E_SPMV, double>(s, L0, true, 0.0));                 \
          },                                                                                    \
-         k_ell_dot_t<WM_>, dim3(nt), dim3(kBlock), T, na, L0.W,                                \
+         k_ell_dot_t<WM_>, dim3(nt), dim3(kTileBlock), T, na, L0.W,                            \
          (const int*)L0.ell_col.as<int>(), (const double*)L0.ell_val.as<double>(),              \
          (const double*)L0.diag.as<double>(), (const int*)done, (const double*)p, q,           \
          tpart(T_PQ))
@@ -1596,13 +1613,13 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
 #undef PPE_ELL_DOT
     // x, p, r, q in; x, r out
     launch(s, [&]() { return std::make_pair(std::string("k_update_xr_t"), 48.0 * na); },
-           k_update_xr_t, dim3(nt), dim3(kBlock), T, (const int*)done, (const double*)rz[sl],
+           k_update_xr_t, dim3(nt), dim3(kTileBlock), T, (const int*)done, (const double*)rz[sl],
            (const double*)tpart(T_PQ), (const double*)p, (const double*)q, x, r, tpart(T_RR),
            cnt, cnt + 1);
     precondition(sl);
     // z, p in; p out
     launch(s, [&]() { return std::make_pair(std::string("k_update_p_t"), 24.0 * na); },
-           k_update_p_t, dim3(nt), dim3(kBlock), T, ns, 1, done, restart,
+           k_update_p_t, dim3(nt), dim3(kTileBlock), T, ns, 1, done, restart,
            (const double*)tpart(T_RR), (const double*)sc, iters, cnt, (const double*)tpart(T_RZ),
            (const double*)rz[sl], rz[1 - sl], (const double*)zb[sl], p, cnt + 1);
   };
@@ -1668,7 +1685,7 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
       if (check_true() == 0) return finish(PPE_OK);
       // restarted samples: z = M r_true, p = z (beta is 0 after a restart)
       precondition(slot);
-      hipLaunchKernelGGL(k_update_p_t, dim3(nt), dim3(kBlock), 0, s->stream, T, ns, 0, done,
+      hipLaunchKernelGGL(k_update_p_t, dim3(nt), dim3(kTileBlock), 0, s->stream, T, ns, 0, done,
                          restart, tpart(T_RR), sc, iters, cnt, tpart(T_RZ), rz[slot],
                          rz[1 - slot], zb[slot], p, cnt + 1);
       PPE_LAUNCH_CHECK();
@@ -1677,11 +1694,11 @@ ppe_status pcg_solve(ppe_solver* s, const double* rhs, double* p_out, int use_x0
   }
   // out of iterations: record the true residuals
   apply_op<E_RESID, double>(s, L0, x, b, nullptr, 0.0, 0.0, q, nullptr);
-  hipLaunchKernelGGL(k_norm2_t, dim3(nt), dim3(kBlock), 0, s->stream, T, q, tpart(T_RT));
+  hipLaunchKernelGGL(k_norm2_t, dim3(nt), dim3(kTileBlock), 0, s->stream, T, q, tpart(T_RT));
   PPE_LAUNCH_CHECK();
   fill_int(s, cnt, 0, 1);
-  hipLaunchKernelGGL(k_seg_check, dim3(ns), dim3(kBlock), 0, s->stream, ns, T, tpart(T_RT), sc, done,
-                     restart, cnt);
+  hipLaunchKernelGGL(k_seg_check, dim3(ns), dim3(kTileBlock), 0, s->stream, ns, T, tpart(T_RT), sc,
+                     done, restart, cnt);
   PPE_LAUNCH_CHECK();
   return finish(PPE_NOT_CONVERGED);
 }
