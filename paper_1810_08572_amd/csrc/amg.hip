@@ -1427,8 +1427,10 @@ void spgemm(ppe_solver* s, const Csr& A, const Csr& B, Csr& C, const int* extra,
   // no fill of its own unless a bound pass used the slot before
   bool max_slot_used = false;
   auto fetch_scan = [&](bool with_max) {
-    const long long* dtotal = exclusive_scan_async(s, counts, crp, C.n);
-    if (with_max) max_int_async(s, counts, C.n, flag + 1, max_slot_used);
+    // a bound pass that used the max slot leaves a larger value there
+    if (with_max && max_slot_used) fill_int(s, flag + 1, INT32_MIN, 1);
+    const long long* dtotal =
+        exclusive_scan_async(s, counts, crp, C.n, 0, with_max ? flag + 1 : nullptr);
     if (extra)
       read_back(s, {ReadItem{dtotal, sizeof(long long), &total},
                     ReadItem{flag, sizeof(int) * 2, fm}, ReadItem{extra, sizeof(int), extra_host}});
@@ -1522,8 +1524,9 @@ void transpose(ppe_solver* s, const Csr& A, Csr& T) {
     PPE_LAUNCH_CHECK();
   }
   int* trp = T.rowptr.get<int>(T.n + 1);
-  max_int_async(s, cnt, T.n, s->rmax.get<int>(1));
-  exclusive_scan_async(s, cnt, trp, T.n);  // the total is A.nnz
+  int* rmax = s->rmax.get<int>(1);
+  fill_int(s, rmax, INT32_MIN, 1);
+  exclusive_scan_async(s, cnt, trp, T.n, 0, rmax);  // the total is A.nnz
   int* cursor = s->tmp_i[1].get<int>(T.n + 1);
   PPE_HIP(hipMemcpyAsync(cursor, trp, sizeof(int) * (T.n + 1), hipMemcpyDeviceToDevice, s->stream));
   int* tci = T.col.get<int>(T.nnz);
@@ -1725,8 +1728,7 @@ static void coarsen_cols_ell(ppe_solver* s, const Level& L, const int* agg, cons
   else if (W <= 6) PPE_QC(6, true, counts, nullptr, nullptr, nullptr);
   else PPE_QC(8, true, counts, nullptr, nullptr, nullptr);
   PPE_LAUNCH_CHECK();
-  const long long* dtotal = exclusive_scan_async(s, counts, qrp, n);
-  max_int_async(s, counts, n, flag + 1, false);
+  const long long* dtotal = exclusive_scan_async(s, counts, qrp, n, 0, flag + 1);
   long long total = 0;
   int fm[2] = {0, 0};
   read_back(s, {ReadItem{dtotal, sizeof(long long), &total}, ReadItem{flag, sizeof(int) * 2, fm}});
@@ -1765,8 +1767,7 @@ static void ap_merge_ell(ppe_solver* s, const Level& L, const Csr& P, Csr& AP, c
   else if (W <= 6) PPE_AP(6, true, counts, nullptr, nullptr, nullptr);
   else PPE_AP(8, true, counts, nullptr, nullptr, nullptr);
   PPE_LAUNCH_CHECK();
-  const long long* dtotal = exclusive_scan_async(s, counts, crp, n);
-  max_int_async(s, counts, n, flag + 1, false);
+  const long long* dtotal = exclusive_scan_async(s, counts, crp, n, 0, flag + 1);
   long long total = 0;
   int fm[2] = {0, 0};
   read_back(s, {ReadItem{dtotal, sizeof(long long), &total}, ReadItem{flag, sizeof(int) * 2, fm},

@@ -515,11 +515,13 @@ inline int grid_for(int64_t n, int bs = kBlock) {
 // Exclusive scan of int32 counts into out[0..n] (out[n] = total).  Returns
 // the total; throws PPE_ERR_INTERNAL if it does not fit int32.
 int64_t exclusive_scan(ppe_solver* s, const int* in, int* out, int n);
-// The same without reading the total back: the total stays at
-// tmp_l[0] + scan_blocks(n) (a long long) for the caller to fetch.
-// Returns the device address of the total (a long long in tmp_l[slot], slot
-// 0 or 1, valid until the next scan through that slot).
-long long* exclusive_scan_async(ppe_solver* s, const int* in, int* out, int n, int slot = 0);
+// The same without reading the total back.  Returns the device address of
+// the total (a long long in tmp_l[slot], slot 0 or 1, valid until the next
+// scan through that slot).  With max_out, the largest count is also max-ed
+// into *max_out, as max_int_async(..., init = false) would do, with no
+// dispatch of its own.
+long long* exclusive_scan_async(ppe_solver* s, const int* in, int* out, int n, int slot = 0,
+                                int* max_out = nullptr);
 int scan_blocks(int n);
 // *out = max of in[0..n) on the device (no host read)
 // init = false: *out already holds a lower bound (e.g. 0 for counts)

@@ -39,21 +39,37 @@ __device__ __forceinline__ long long block_excl_scan(long long v, long long* tot
   return off + inc - v;
 }
 
+// Block sums of the counts and, with bmax, block maxima (the scan then also
+// delivers the largest count, which the callers need beside the total).
 __global__ void __launch_bounds__(kBlock) k_scan_reduce(const int* __restrict__ in, int n,
-                                                        long long* __restrict__ bsum) {
+                                                        long long* __restrict__ bsum,
+                                                        int* __restrict__ bmax) {
   const long long base = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanItems;
   long long s = 0;
+  int m = INT32_MIN;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     long long i = base + k;
-    if (i < n) s += in[i];
+    if (i < n) {
+      const int v = in[i];
+      s += v;
+      m = max(m, v);
+    }
   }
   s = block_sum<kBlock>(s);
   if (threadIdx.x == 0) bsum[blockIdx.x] = s;
+  if (bmax) {
+    m = block_max<kBlock>(m);
+    if (threadIdx.x == 0) bmax[blockIdx.x] = m;
+  }
 }
 
+// Scan of the block sums; with mx, the largest block maximum is max-ed into
+// *mx (as k_max_int does).
 __global__ void __launch_bounds__(kBlock) k_scan_top(long long* __restrict__ bsum, int nb,
-                                                     long long* __restrict__ total) {
+                                                     long long* __restrict__ total,
+                                                     const int* __restrict__ bmax,
+                                                     int* __restrict__ mx) {
   long long carry = 0;
   for (int base = 0; base < nb; base += kBlock) {
     int i = base + threadIdx.x;
@@ -64,6 +80,12 @@ __global__ void __launch_bounds__(kBlock) k_scan_top(long long* __restrict__ bsu
     carry += t;
   }
   if (threadIdx.x == 0) *total = carry;
+  if (mx) {
+    int m = INT32_MIN;
+    for (int i = threadIdx.x; i < nb; i += kBlock) m = max(m, bmax[i]);
+    m = block_max<kBlock>(m);
+    if (threadIdx.x == 0) atomicMax(mx, m);
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_scan_down(const int* __restrict__ in, int n,
@@ -100,10 +122,20 @@ constexpr int kSmallScan = kSmallBlock * kSmallItems;
 
 __global__ void __launch_bounds__(kSmallBlock) k_scan_small(const int* __restrict__ in, int n,
                                                             int* __restrict__ out,
-                                                            long long* __restrict__ total) {
+                                                            long long* __restrict__ total,
+                                                            int* __restrict__ mx) {
   __shared__ int buf[kSmallScan];
   __shared__ long long wsum[kSmallBlock / kWave];
-  for (int i = threadIdx.x; i < n; i += kSmallBlock) buf[i] = in[i];
+  int m = INT32_MIN;
+  for (int i = threadIdx.x; i < n; i += kSmallBlock) {
+    const int v = in[i];
+    buf[i] = v;
+    m = max(m, v);
+  }
+  if (mx) {  // the largest count, max-ed into *mx as k_max_int does
+    m = block_max<kSmallBlock>(m);
+    if (threadIdx.x == 0) atomicMax(mx, m);
+  }
   __syncthreads();
   const int per = (n + kSmallBlock - 1) / kSmallBlock;  // <= kSmallItems
   const int base = threadIdx.x * per;
@@ -187,20 +219,25 @@ int scan_blocks(int n) {
   return nb < 1 ? 1 : nb;
 }
 
-long long* exclusive_scan_async(ppe_solver* s, const int* in, int* out, int n, int slot) {
+long long* exclusive_scan_async(ppe_solver* s, const int* in, int* out, int n, int slot,
+                                int* max_out) {
   if (n < 0) throw Error(PPE_ERR_INTERNAL, "negative scan length");
   if (n <= kSmallScan) {
     long long* total = s->tmp_l[slot].get<long long>(2) + 1;
-    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kSmallBlock), 0, s->stream, in, n, out, total);
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kSmallBlock), 0, s->stream, in, n, out, total,
+                       max_out);
     PPE_LAUNCH_CHECK();
     return total;
   }
   const int nb = scan_blocks(n);
-  long long* bsum = s->tmp_l[slot].get<long long>(nb + 1);
+  // block sums, the total, then (with max_out) the block maxima as ints
+  long long* bsum = s->tmp_l[slot].get<long long>(nb + 1 + (max_out ? (nb + 1) / 2 : 0));
   long long* total = bsum + nb;
-  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s->stream, in, n, bsum);
+  int* bmax = max_out ? reinterpret_cast<int*>(total + 1) : nullptr;
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s->stream, in, n, bsum, bmax);
   PPE_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s->stream, bsum, nb, total);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s->stream, bsum, nb, total,
+                     (const int*)bmax, max_out);
   PPE_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kBlock), 0, s->stream, in, n, bsum, total, out);
   PPE_LAUNCH_CHECK();
