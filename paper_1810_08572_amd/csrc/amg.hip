@@ -1027,20 +1027,63 @@ __global__ void __launch_bounds__(1024) k_narrow_fill(int64_t nnz, const int* __
   }
 }
 
-__global__ void k_col_count(int64_t nnz, const int* __restrict__ ci, int* __restrict__ cnt) {
-  int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (k < nnz) atomicAdd(&cnt[ci[k]], 1);
+// The lanes of a wavefront holding the same key among those with `valid`
+// set: the caller's group as a lane mask (its own lane included), 0 for a
+// lane that is not valid.  Every lane of the wavefront calls it together.
+__device__ __forceinline__ unsigned long long wave_key_group(int key, bool valid) {
+  unsigned long long todo = __ballot(valid);
+  unsigned long long grp = 0;
+  while (todo) {
+    const int k = __shfl(key, __ffsll((long long)todo) - 1, kWave);
+    const bool same = valid && key == k;
+    const unsigned long long m = __ballot(same);
+    if (same) grp = m;
+    todo &= ~m;
+  }
+  return grp;
 }
 
+// Column counts of a CSR.  Consecutive entries belong to neighbouring rows
+// and share columns, so the lanes of a wavefront with one column add their
+// number with one atomic (the device-scope atomics, not the loads, bound
+// the plain one-atomic-per-entry pass).
+__global__ void k_col_count(int64_t nnz, const int* __restrict__ ci, int* __restrict__ cnt) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int lane = threadIdx.x % kWave;
+  const bool valid = k < nnz;
+  const int c = valid ? ci[k] : -1;
+  const unsigned long long grp = wave_key_group(c, valid);
+  if (valid && (grp & ((1ull << lane) - 1ull)) == 0) atomicAdd(&cnt[c], __popcll(grp));
+}
+
+// Each entry (i, c) of row i takes a free slot of row c of the transpose
+// (the order within a row is fixed afterwards by k_rank_rows).  Entry u of
+// every row of a wavefront is placed together: lanes with the same column
+// take consecutive slots from one atomic of their lowest lane.
 __global__ void k_transpose_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                  const double* __restrict__ v, int* __restrict__ cursor,
                                  int* __restrict__ tci, double* __restrict__ tv) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  for (int k = rp[i]; k < rp[i + 1]; ++k) {
-    int p = atomicAdd(&cursor[ci[k]], 1);
-    tci[p] = i;
-    tv[p] = v[k];
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int lane = threadIdx.x % kWave;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  int k0 = 0, k1 = 0;
+  if (i < n) {
+    k0 = rp[i];
+    k1 = rp[i + 1];
+  }
+  for (int u = 0; __ballot(k0 + u < k1) != 0; ++u) {
+    const bool valid = k0 + u < k1;
+    const int c = valid ? ci[k0 + u] : -1;
+    const double w = valid ? v[k0 + u] : 0.0;
+    const unsigned long long grp = wave_key_group(c, valid);
+    int base = 0;
+    if (valid && (grp & below) == 0) base = atomicAdd(&cursor[c], __popcll(grp));
+    base = __shfl(base, valid ? __ffsll((long long)grp) - 1 : lane, kWave);
+    if (valid) {
+      const int p = base + __popcll(grp & below);
+      tci[p] = i;
+      tv[p] = w;
+    }
   }
 }
 
