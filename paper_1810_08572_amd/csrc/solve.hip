@@ -951,12 +951,14 @@ int lanes_near(double target, int lo = 4) {
       best = c;
   return best;
 }
-int widen_small(const Csr& M, int lpr) { return (int64_t)M.n * lpr < 65536 ? 64 : lpr; }
+int widen_small(const Csr& M, int lpr) { return (int64_t)M.n * lpr < 16384 ? 64 : lpr; }
 double mean_row(const Csr& M) { return M.n ? (double)M.nnz / M.n : 1.0; }
 int smooth_lanes(const Csr& A) {
   return widen_small(A, lanes_near(1.8 * std::sqrt(mean_row(A))));
 }
+// lanes per row of a prolongation P and of a restriction R = P^T
 int transfer_lanes(const Csr& M) { return widen_small(M, lanes_near(mean_row(M) / 3.0, 1)); }
+int restrict_lanes(const Csr& R) { return widen_small(R, lanes_near(mean_row(R) / 5.0, 1)); }
 
 // Apply the level operator with epilogue EPI, matrix values in type M.
 // Dot/power epilogues run on a capped grid and write partials to `partials`;
@@ -1025,7 +1027,7 @@ template <bool ADD, class M, bool FIRST = false>
 void apply_rect(ppe_solver* s, const Csr& P, const double* x, double* y, int lpr_choice = 0,
                 const FirstStep<M>& fs = FirstStep<M>{nullptr, 0.0, nullptr, nullptr}) {
   if (P.n == 0) return;
-  const int lpr = lpr_choice > 0 ? lpr_choice : transfer_lanes(P);
+  const int lpr = lpr_choice > 0 ? lpr_choice : (ADD ? transfer_lanes(P) : restrict_lanes(P));
   const int g = grid_for((int64_t)P.n * lpr);
   // entries and row pointers of P or R, each operand entry once, y out (and
   // in); with the first step the diagonal in and its update and iterate out
@@ -1086,7 +1088,7 @@ bool fuse_rule(const Level& L) {
 // lane).
 int prolong_lanes(const Level& L) {
   if (L.lpr_p > 0) return std::max(L.lpr_p, 4);
-  return widen_small(L.A, lanes_near(3.0 * std::sqrt(mean_row(L.A))));
+  return widen_small(L.A, lanes_near(2.0 * std::sqrt(mean_row(L.A))));
 }
 
 // y = (x1 + P e) + d with d = c2 D^-1 (b - A (x1 + P e)): the prolongation
@@ -1780,7 +1782,7 @@ void tune_level(ppe_solver* s, int l) {
   }
   if (coarsest) return;
   Level& C = s->levels[l + 1];
-  L.lpr_r = best_lpr(s, transfer_lanes(L.R), 1, [&](int c) {
+  L.lpr_r = best_lpr(s, restrict_lanes(L.R), 1, [&](int c) {
     apply_rect<false, M>(s, L.R, L.r.as<double>(), C.b.as<double>(), c);
   });
   // the prolongation alone, then (where it can fuse) the fused pass against
