@@ -819,11 +819,23 @@ __global__ void __launch_bounds__(kBlock) k_finalize_norm(const double* __restri
 }
 
 
-template <class S, class D>
-__global__ void k_cast(int64_t n, const S* __restrict__ a, D* __restrict__ b) {
+// Several FP64 -> FP32 casts in one dispatch: segment k is blockIdx.y, its
+// n[k] values cast by a grid-stride loop over blockIdx.x.
+constexpr int kCastSegs = 24;
+struct CastArgs {
+  const double* src[kCastSegs];
+  float* dst[kCastSegs];
+  int64_t n[kCastSegs];
+};
+
+__global__ void __launch_bounds__(kBlock) k_cast_segments(CastArgs a) {
+  const int k = blockIdx.y;
+  const double* __restrict__ src = a.src[k];
+  float* __restrict__ dst = a.dst[k];
+  const int64_t n = a.n[k];
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kBlock)
-    b[i] = (D)a[i];
+    dst[i] = (float)src[i];
 }
 
 __global__ void k_copy(int n, const double* __restrict__ a, double* __restrict__ b) {
@@ -1276,15 +1288,6 @@ bool vcycle_t(ppe_solver* s, int l, const double* b, double* x, const PcgDot* do
   return smooth<M>(s, L, b, x1, x, xa, xb, dot);
 }
 
-template <class S, class D>
-void cast(ppe_solver* s, const S* a, D* b, int64_t n) {
-  if (n <= 0) return;
-  int g = grid_for(n);
-  if (g > 4096) g = 4096;
-  hipLaunchKernelGGL((k_cast<S, D>), dim3(g), dim3(kBlock), 0, s->stream, n, a, b);
-  PPE_LAUNCH_CHECK();
-}
-
 }  // namespace
 
 void drop_graph(ppe_solver* s) {
@@ -1439,22 +1442,45 @@ static void vcycle_pcg(ppe_solver* s, const double* r, double* z, const PcgDot& 
 // entries are dominated by the smoothest mode, and rounding them would
 // perturb the other modes by the level's condition number times 6e-8.
 void make_fp32_hierarchy(ppe_solver* s) {
+  // every copy of every level in one dispatch (per kCastSegs copies)
+  CastArgs a{};
+  int ns = 0;
+  int64_t most = 0;
+  auto flush = [&]() {
+    if (ns == 0) return;
+    int g = grid_for(most);
+    if (g > 1024) g = 1024;
+    hipLaunchKernelGGL(k_cast_segments, dim3(g, ns), dim3(kBlock), 0, s->stream, a);
+    PPE_LAUNCH_CHECK();
+    ns = 0;
+    most = 0;
+  };
+  auto add = [&](const double* src, float* dst, int64_t n) {
+    if (n <= 0) return;
+    if (ns == kCastSegs) flush();
+    a.src[ns] = src;
+    a.dst[ns] = dst;
+    a.n[ns] = n;
+    ++ns;
+    most = std::max(most, n);
+  };
   for (int l = 0; l < s->nlev; ++l) {
     Level& L = s->levels[l];
     if (L.n == 0) continue;
-    cast<double, float>(s, L.diag.as<double>(), L.diagf.get<float>(L.n), L.n);
+    add(L.diag.as<double>(), L.diagf.get<float>(L.n), L.n);
     if (s->opt.smoother == PPE_SMOOTH_L1JACOBI && L.rho > 0.0)
-      cast<double, float>(s, L.dl1.as<double>(), L.dl1f.get<float>(L.n), L.n);
+      add(L.dl1.as<double>(), L.dl1f.get<float>(L.n), L.n);
     if (l == 0) {
       const int64_t e = (int64_t)(L.W > 0 ? L.W : 1) * L.n;
-      cast<double, float>(s, L.ell_val.as<double>(), L.ell_valf.get<float>(e), e);
+      add(L.ell_val.as<double>(), L.ell_valf.get<float>(e), e);
     }
-    if (L.A.nnz > 0) cast<double, float>(s, L.A.v(), L.A.valf.get<float>(L.A.nnz), L.A.nnz);
+    if (L.A.nnz > 0) add(L.A.v(), L.A.valf.get<float>(L.A.nnz), L.A.nnz);
     if (l < s->nlev - 1) {
-      cast<double, float>(s, L.P.v(), L.P.valf.get<float>(L.P.nnz), L.P.nnz);
-      cast<double, float>(s, L.R.v(), L.R.valf.get<float>(L.R.nnz), L.R.nnz);
+      add(L.P.v(), L.P.valf.get<float>(L.P.nnz), L.P.nnz);
+      add(L.R.v(), L.R.valf.get<float>(L.R.nnz), L.R.nnz);
     }
   }
+  flush();
 }
 
 // Record the launches `issue` makes into a HIP graph on the solver's capture
